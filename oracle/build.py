@@ -1,0 +1,26 @@
+"""Build the CPU oracle (test infrastructure only): oracle.c -> liborc.so.
+
+Plain gcc, -O2, no fast-math, no floating-point contraction, OpenMP over
+particles.
+"""
+import os
+import subprocess
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def build(verbose=False):
+    src = os.path.join(_HERE, "oracle.c")
+    out = os.path.join(_HERE, "liborc.so")
+    tmp = out + ".tmp"
+    cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+           "-fno-fast-math", "-Wall", "-Wextra", "-Wno-unused-parameter", "-o", tmp, src, "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+    return out
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))
