@@ -496,7 +496,7 @@ def test_chi2_law_two_channels_share_phase():
     Upsilon_N ~ chi^2_{2N}(rho^2), not chi^2_{4N}."""
     from scipy import stats
 
-    base = D.lisa_small(K=8000, noise=False, snr=8.0)
+    base = D.lisa_small(K=8000, f_min=0.0179, noise=False, snr=8.0)
     vals = []
     for s in range(300):
         n = synth.noise(base.psd, base.grid.df, 30_000 + s)
