@@ -1,0 +1,249 @@
+/*
+ * libscs -- semi-coherent search statistic on MI355X (gfx950).
+ *
+ * C ABI for evaluating the semi-coherent detection statistic Upsilon_N of
+ * Bandopadhyay & Moore (arXiv:2408.13170) for a whole particle swarm at once,
+ * and for the particle-swarm update that drives the search.
+ *
+ * Conventions for every entry point
+ *   - Return 0 on success, a negative SCS_E* code on failure; never throws or
+ *     aborts across the ABI.  scs_last_error() returns a thread-local message
+ *     describing the last failure on the calling thread.
+ *   - "dev" pointers are HIP device pointers (for example torch CUDA tensors);
+ *     "host" pointers are ordinary host memory.  Where an argument accepts
+ *     either, a mem_kind argument says which (SCS_MEM_HOST / SCS_MEM_DEVICE).
+ *   - The caller keeps ownership of every buffer it passes.  With device
+ *     pointers the work is queued on `stream` (a hipStream_t, NULL = the null
+ *     stream) and inputs must stay valid until the stream reaches that point;
+ *     with host pointers the call returns after the results are on the host.
+ *   - A context (one search: one data set, one model) is used by one host
+ *     thread and one stream at a time; different contexts may run
+ *     concurrently on different streams of the same device.
+ *
+ * Parameter vector theta, 7 doubles per particle, in this order:
+ *   Mc      chirp mass [solar masses, detector frame]
+ *   eta     symmetric mass ratio, 0 < eta <= 1/4
+ *   f_low   gravitational-wave frequency at the start of observation [Hz];
+ *           it fixes the coalescence time through t(f_low) = 0
+ *   lambda  ecliptic longitude [rad]
+ *   beta    ecliptic latitude [rad]
+ *   iota    inclination [rad]
+ *   psi     polarisation angle [rad]
+ * (the searched parameters of Table tab:GW150914-like_injection with e0 = 0;
+ * distance and phase are maximised out of the statistic, Sec 4).
+ */
+#ifndef SCS_H
+#define SCS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ---------------------------------------------------- */
+#define SCS_OK 0
+#define SCS_EINVAL (-1)  /* bad argument */
+#define SCS_ENOMEM (-2)  /* device or host allocation failed */
+#define SCS_EDEVICE (-3) /* HIP runtime error, or no usable gfx950 device */
+#define SCS_EBUSY (-4)   /* request exceeds an admitted budget */
+#define SCS_ESTATE (-5)  /* call out of order (e.g. evaluate before load_data) */
+
+/* ---- enumerations ---------------------------------------------------- */
+#define SCS_MEM_HOST 0
+#define SCS_MEM_DEVICE 1
+
+#define SCS_PREC_FP64 0  /* every step in IEEE double */
+#define SCS_PREC_MIXED 1 /* FP64 anchors + FP32 residual, FP32 Kahan sums */
+
+#define SCS_RESP_NONE 0       /* one channel, h = f^-7/6 e^{-i Psi} */
+#define SCS_RESP_LISA_LF_AE 1 /* two channels A, E, low-frequency LISA response */
+
+#define SCS_SUPPORT_FULL 0 /* every bin of the grid */
+#define SCS_SUPPORT_TOBS 1 /* bins with 0 <= t(f_k) < T_obs */
+
+#define SCS_SEG_EQUAL_SNR 0 /* equal [h|h] per segment, per particle (Sec 2.2) */
+#define SCS_SEG_UNIFORM 1   /* equal bin counts inside the support */
+#define SCS_SEG_EXPLICIT 2  /* caller's bin edges, clamped to the support */
+
+typedef struct scs_ctx scs_ctx;
+typedef struct scs_swarm scs_swarm;
+
+/* Waveform and response model (Sec 4).  Zero-initialise, then set fields. */
+typedef struct scs_model {
+    int32_t pn_order;        /* highest PN power of v in the phase, 0..7 (4 = 2PN, 7 = 3.5PN) */
+    int32_t response;        /* SCS_RESP_* ; NONE needs 1 channel, LISA_LF_AE needs 2 */
+    int32_t support;         /* SCS_SUPPORT_* */
+    int32_t block_len;       /* polynomial block length in bins (power of 2, 16..512); 0 = 512 */
+    double t_obs;            /* observation time [s]; 0 = 1/df */
+    double orbit_phase0;     /* orbital angle of the constellation centre at t = 0 [rad] */
+    double cartwheel_phase0; /* in-plane angle of spacecraft 0 at t = 0 [rad] */
+} scs_model;
+
+/* ---- context --------------------------------------------------------- */
+
+/* Create a context on HIP device `device` (a gfx950 GPU).  *out receives the
+ * handle.  Fails with SCS_EDEVICE when the device is missing or not gfx950. */
+int scs_ctx_create(scs_ctx** out, int device);
+
+/* Release the context and every device buffer it owns.  NULL is accepted. */
+int scs_ctx_destroy(scs_ctx* ctx);
+
+/* Load the data stream d_alpha(f_k) and its one-sided PSD S_alpha(f_k)
+ * (eqn:inner_prod) on the grid f_k = f_min + k df, k = 0..K-1.
+ *   n_chan  1 or 2 (A, E)
+ *   d_ri    [n_chan][K][2] real and imaginary parts
+ *   psd     [n_chan][K], every value finite and > 0
+ * f_min / df must be an integer (to 1e-9 relative): f_k are FFT bins and
+ * T_obs = 1/df.  The library copies the arrays (the caller may free them on
+ * return) and precomputes the particle-independent products
+ * f^-7/6 d / S and f^-7/3 / S in FP64 and FP32.  Synchronous. */
+int scs_load_data(scs_ctx* ctx, int32_t n_chan, int64_t K, double f_min, double df, const double* d_ri,
+                  const double* psd, int32_t mem_kind);
+
+/* Set the waveform/response model.  Errors: pn_order outside 0..7, response
+ * not matching the loaded channel count, block_len not a power of 2 in
+ * 16..512, negative t_obs. */
+int scs_set_model(scs_ctx* ctx, const scs_model* model);
+
+/* Define the segmentation used by scs_evaluate (Sec 2.2).
+ *   N      number of segments, >= 1
+ *   mode   SCS_SEG_*; EQUAL_SNR places the edges of every particle so that
+ *          each segment holds the same [h|h], re-evaluated for every theta
+ *   G      node stride of the EQUAL_SNR cumulative (1 = every bin); >= 1
+ *   edges  host [N+1] nondecreasing bin indices for EXPLICIT, else NULL */
+int scs_define_segmentation(scs_ctx* ctx, int32_t N, int32_t mode, int32_t G, const int64_t* edges);
+
+/* Evaluate Upsilon_N (Sec 2.2, the statistic's definition) for P particles.
+ *   theta  [P][7]
+ *   ups    [P] out: Upsilon_N; NaN for invalid theta (Mc <= 0, eta outside
+ *          (0, 1/4], f_low <= 0, non-finite) or a theta the polynomial block
+ *          scheme cannot resolve (counted by scs_ctx_stats); 0 when the
+ *          support is empty
+ *   seg    [P][N][3] out, nullable: (Re Z_n, Im Z_n, H_n) with
+ *          Z_n = sum_{k in n} sum_alpha d conj(h) / S and H_n = sum w(k), so that
+ *          x_n = 4 df |Z_n| and [h|h]_n = 4 df H_n
+ *   prec   SCS_PREC_*
+ * theta, ups and seg are all host or all device pointers (mem_kind). */
+int scs_evaluate(scs_ctx* ctx, int64_t P, const double* theta, int32_t prec, double* ups, double* seg,
+                 int32_t mem_kind, void* stream);
+
+/* Per-particle support [k_lo, k_hi) and segment edges b_0..b_N (int32) from
+ * the last scs_evaluate on this context, copied to host arrays
+ * support [P][2] and bounds [P][N+1] (either may be NULL).  Synchronises the
+ * context's last stream. */
+int scs_last_bounds(scs_ctx* ctx, int64_t P, int32_t* support, int32_t* bounds);
+
+/* Template h_alpha(f_k) for one theta, h_ri [n_chan][K][2], zero outside
+ * the support, with the FP64 kernels (used to synthesise injections). */
+int scs_waveform(scs_ctx* ctx, const double* theta, double* h_ri, int32_t mem_kind, void* stream);
+
+/* Counters accumulated since the last reset: in-support particle-bin
+ * evaluations, full-band particle-bin evaluations, and particles the block
+ * scheme could not resolve.  Synchronises the device. */
+int scs_ctx_stats(scs_ctx* ctx, int64_t* evals_support, int64_t* evals_band, int64_t* unresolved, int32_t reset);
+
+/* Time the dominant (generate-and-reduce) kernel with HIP events on the
+ * stream it is launched on.  enable = 1 starts recording; the query returns
+ * the number of launches and the summed milliseconds since enabling. */
+int scs_ctx_profile(scs_ctx* ctx, int32_t enable, int64_t* launches, double* total_ms);
+
+/* HBM bytes an evaluation of P particles with N segments needs on this
+ * context beyond the loaded data (coefficients, edges, fragments), for
+ * admission control. */
+int scs_footprint(const scs_ctx* ctx, int64_t P, int32_t N, int32_t prec, size_t* bytes);
+
+/* ---- batched evaluation --------------------------------------------- */
+
+/* One swarm of a batched launch.  Segmentation mode and G come from the
+ * item's context, N from the item. */
+typedef struct scs_batch_item {
+    scs_ctx* ctx;
+    int32_t N;
+    int32_t pad;
+    int64_t P;
+    const double* theta; /* dev [P][7] */
+    double* ups;         /* dev [P] */
+    double* seg;         /* dev [P][N][3] or NULL */
+} scs_batch_item;
+
+/* Evaluate several swarms (uneven P and N, possibly different contexts on
+ * one device) in one fused launch sequence: one prologue, one persistent
+ * generate-and-reduce kernel pulling (swarm, particle group, chunk) work
+ * items from a device queue, one finalize.  Results equal scs_evaluate on
+ * each item alone.  Device pointers only. */
+int scs_evaluate_batched(const scs_batch_item* items, int32_t n_items, int32_t prec, void* stream);
+
+/* Capture scs_evaluate_batched for fixed items into a HIP graph; replay it
+ * with scs_graph_launch after updating theta in place. */
+typedef struct scs_graph scs_graph;
+int scs_graph_create(scs_graph** out, const scs_batch_item* items, int32_t n_items, int32_t prec);
+int scs_graph_launch(scs_graph* g, void* stream);
+int scs_graph_destroy(scs_graph* g);
+
+/* Tile-shape autotuner: time the candidate launch shapes (waves per
+ * workgroup, bins per chunk) of the generate-and-reduce kernel on this
+ * context for the P particles theta_dev (device [P][7]) and N segments, and
+ * keep the fastest for later calls with a similar (P, N, prec).  cache_path
+ * (nullable) is a text file of "key waves blocks" lines, read before tuning
+ * (a hit skips the timing) and rewritten after. */
+int scs_autotune(scs_ctx* ctx, int64_t P, const double* theta_dev, int32_t N, int32_t prec, const char* cache_path);
+
+/* ---- particle swarm (Sec 3.1) ---------------------------------------- */
+
+/* Hyper-parameters of one rung (Table tab:PSO_hyperparams). */
+typedef struct scs_pso_params {
+    double omega;  /* inertia */
+    double phi_p;  /* pull to the particle best */
+    double phi_g;  /* pull to the swarm best */
+    double eps[7]; /* minimum speed per dimension (eqn:PSO_min_velocity) */
+} scs_pso_params;
+
+/* Create a swarm of P particles bound to ctx (its data, model and
+ * segmentation), positions uniform in [lo, hi] (host [7] each), zero
+ * velocity.  periodic[d] = 1 wraps dimension d into [lo, hi).  Random numbers
+ * come from Philox4x32-10 with key (seed low word, seed high word + swarm_id)
+ * and counter (iteration, particle, dimension, stream). */
+int scs_swarm_create(scs_ctx* ctx, scs_swarm** out, int64_t P, const double* lo, const double* hi,
+                     const int32_t* periodic, uint64_t seed, uint32_t swarm_id);
+int scs_swarm_destroy(scs_swarm* sw);
+
+/* One iteration: on the first call only evaluate; afterwards move every
+ * particle (eqn:PSO_velocity_rule then eqn:PSO_min_velocity, using the bests
+ * of the previous iteration), evaluate Upsilon_N at the new positions, and
+ * update particle and swarm bests (out-of-box or NaN values count as -inf). */
+int scs_pso_step(scs_swarm* sw, const scs_pso_params* params, int32_t prec, void* stream);
+
+/* Copy the swarm state to host arrays (any may be NULL): theta, vel, pbest
+ * [P][7], pbest_val [P], gbest [7], gbest_val, iteration.  Synchronous. */
+int scs_swarm_read(scs_swarm* sw, double* theta, double* vel, double* pbest, double* pbest_val, double* gbest,
+                   double* gbest_val, uint32_t* iteration);
+
+/* Restore a swarm state from host arrays (checkpoint / resume). */
+int scs_swarm_write(scs_swarm* sw, const double* theta, const double* vel, const double* pbest,
+                    const double* pbest_val, const double* gbest, double gbest_val, uint32_t iteration);
+
+/* Device pointers to the swarm's live arrays (theta [P][7], ups [P]). */
+int scs_swarm_device_ptrs(scs_swarm* sw, double** theta, double** ups);
+
+/* Raw move kernel on caller buffers (dev): theta, vel [P][7] updated in
+ * place from pbest [P][7] and gbest [7]; lo, hi, eps as host [7]. */
+int scs_pso_move(int64_t P, double* theta, double* vel, const double* pbest, const double* gbest,
+                 const scs_pso_params* params, const double* lo, const double* hi, const int32_t* periodic,
+                 uint64_t seed, uint32_t swarm_id, uint32_t iteration, void* stream);
+
+/* Raw best-update kernel on caller buffers (dev): vals [P]; pbest, pbest_val,
+ * gbest [7], gbest_val [1] updated in place. */
+int scs_pso_best(int64_t P, const double* theta, const double* vals, const double* lo, const double* hi,
+                 const int32_t* periodic, double* pbest, double* pbest_val, double* gbest, double* gbest_val,
+                 void* stream);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char* scs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SCS_H */

@@ -1,0 +1,341 @@
+"""ctypes binding of libscs (include/scs.h).  Argument marshalling only: every
+step of the statistic runs in the HIP kernels of libscs.so.
+
+Functions keep the C names.  Pointer arguments accept numpy arrays (host) or
+torch CUDA tensors (device); the binding passes raw pointers and the memory
+kind, and raises ScsError with scs_last_error() on a negative return code.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(_HERE, "libscs.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "scs.h")
+
+SCS_MEM_HOST, SCS_MEM_DEVICE = 0, 1
+SCS_PREC_FP64, SCS_PREC_MIXED = 0, 1
+SCS_RESP_NONE, SCS_RESP_LISA_LF_AE = 0, 1
+SCS_SUPPORT_FULL, SCS_SUPPORT_TOBS = 0, 1
+SCS_SEG_EQUAL_SNR, SCS_SEG_UNIFORM, SCS_SEG_EXPLICIT = 0, 1, 2
+
+
+class ScsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libscs error {code}: {msg}")
+        self.code = code
+
+
+class scs_model(C.Structure):
+    _fields_ = [("pn_order", C.c_int32), ("response", C.c_int32), ("support", C.c_int32),
+                ("block_len", C.c_int32), ("t_obs", C.c_double), ("orbit_phase0", C.c_double),
+                ("cartwheel_phase0", C.c_double)]
+
+
+class scs_batch_item(C.Structure):
+    _fields_ = [("ctx", C.c_void_p), ("N", C.c_int32), ("pad", C.c_int32), ("P", C.c_int64),
+                ("theta", C.c_void_p), ("ups", C.c_void_p), ("seg", C.c_void_p)]
+
+
+class scs_pso_params(C.Structure):
+    _fields_ = [("omega", C.c_double), ("phi_p", C.c_double), ("phi_g", C.c_double),
+                ("eps", C.c_double * 7)]
+
+
+_lib = None
+
+_SIGS = {
+    "scs_ctx_create": [C.POINTER(C.c_void_p), C.c_int],
+    "scs_ctx_destroy": [C.c_void_p],
+    "scs_load_data": [C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_int32],
+    "scs_set_model": [C.c_void_p, C.POINTER(scs_model)],
+    "scs_define_segmentation": [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p],
+    "scs_evaluate": [C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p],
+    "scs_last_bounds": [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p],
+    "scs_waveform": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p],
+    "scs_ctx_stats": [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_int32],
+    "scs_ctx_profile": [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)],
+    "scs_footprint": [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)],
+    "scs_evaluate_batched": [C.POINTER(scs_batch_item), C.c_int32, C.c_int32, C.c_void_p],
+    "scs_graph_create": [C.POINTER(C.c_void_p), C.POINTER(scs_batch_item), C.c_int32, C.c_int32],
+    "scs_graph_launch": [C.c_void_p, C.c_void_p],
+    "scs_graph_destroy": [C.c_void_p],
+    "scs_autotune": [C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_int32, C.c_char_p],
+    "scs_swarm_create": [C.c_void_p, C.POINTER(C.c_void_p), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                         C.c_uint64, C.c_uint32],
+    "scs_swarm_destroy": [C.c_void_p],
+    "scs_pso_step": [C.c_void_p, C.POINTER(scs_pso_params), C.c_int32, C.c_void_p],
+    "scs_swarm_read": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                       C.POINTER(C.c_double), C.POINTER(C.c_uint32)],
+    "scs_swarm_write": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                        C.c_uint32],
+    "scs_swarm_device_ptrs": [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)],
+    "scs_pso_move": [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(scs_pso_params),
+                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint32, C.c_void_p],
+    "scs_pso_best": [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+    "scs_last_error": [],
+}
+
+
+def lib():
+    """Load libscs.so from the package directory (fails loudly if absent)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise ImportError(f"{LIBPATH} is missing: build it with paper_2408_13170_amd/build.py "
+                              "(or __graft_entry__.build())")
+        L = C.CDLL(LIBPATH)
+        for name, args in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_char_p if name == "scs_last_error" else C.c_int
+        _lib = L
+    return _lib
+
+
+def header_symbols():
+    """Names of every function declared in include/scs.h."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(scs_\w+)\s*\(", txt, re.M)))
+
+
+def _check(rc):
+    if rc != 0:
+        msg = lib().scs_last_error()
+        raise ScsError(rc, msg.decode() if msg else "")
+
+
+def _is_torch(x):
+    return type(x).__module__.startswith("torch")
+
+
+def ptr(x):
+    """Raw pointer and memory kind of a numpy array or torch tensor (or None)."""
+    if x is None:
+        return None, None
+    if _is_torch(x):
+        if not x.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return C.c_void_p(x.data_ptr()), (SCS_MEM_DEVICE if x.is_cuda else SCS_MEM_HOST)
+    if isinstance(x, np.ndarray):
+        if not x.flags["C_CONTIGUOUS"]:
+            raise ValueError("array must be C-contiguous")
+        return C.c_void_p(x.ctypes.data), SCS_MEM_HOST
+    raise TypeError(f"unsupported buffer type {type(x)}")
+
+
+def _stream(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def current_stream():
+    import torch
+
+    return torch.cuda.current_stream()
+
+
+# ---------------------------------------------------------------- wrappers
+def scs_ctx_create(device=0):
+    h = C.c_void_p()
+    _check(lib().scs_ctx_create(C.byref(h), device))
+    return h
+
+
+def scs_ctx_destroy(ctx):
+    _check(lib().scs_ctx_destroy(ctx))
+
+
+def scs_load_data(ctx, d_ri, psd, f_min, df):
+    """d_ri [n_chan, K, 2] and psd [n_chan, K] (float64, host or device)."""
+    n_chan, K = psd.shape[0], psd.shape[1]
+    pd, kd = ptr(d_ri)
+    pp, kp = ptr(psd)
+    if kd != kp:
+        raise ValueError("data and psd must live in the same memory")
+    _check(lib().scs_load_data(ctx, n_chan, K, f_min, df, pd, pp, kd))
+
+
+def scs_set_model(ctx, pn_order, response, support, t_obs=0.0, block_len=0, orbit_phase0=0.0,
+                  cartwheel_phase0=0.0):
+    m = scs_model(pn_order, response, support, block_len, t_obs, orbit_phase0, cartwheel_phase0)
+    _check(lib().scs_set_model(ctx, C.byref(m)))
+
+
+def scs_define_segmentation(ctx, N, mode=SCS_SEG_EQUAL_SNR, G=1024, edges=None):
+    e = None
+    if edges is not None:
+        edges = np.ascontiguousarray(edges, dtype=np.int64)
+        e = C.c_void_p(edges.ctypes.data)
+    _check(lib().scs_define_segmentation(ctx, N, mode, G, e))
+
+
+def scs_evaluate(ctx, theta, ups, prec=SCS_PREC_FP64, seg=None, stream=None):
+    """theta [P,7] -> ups [P] (and seg [P,N,3]); all numpy or all CUDA tensors."""
+    P = theta.shape[0]
+    pt, kt = ptr(theta)
+    pu, ku = ptr(ups)
+    ps, ks = ptr(seg)
+    if kt != ku or (seg is not None and ks != kt):
+        raise ValueError("theta, ups and seg must live in the same memory")
+    if kt == SCS_MEM_DEVICE and stream is None:
+        stream = current_stream()
+    _check(lib().scs_evaluate(ctx, P, pt, prec, pu, ps, kt, _stream(stream)))
+
+
+def scs_last_bounds(ctx, P, N):
+    sup = np.empty((P, 2), dtype=np.int32)
+    bnd = np.empty((P, N + 1), dtype=np.int32)
+    _check(lib().scs_last_bounds(ctx, P, C.c_void_p(sup.ctypes.data), C.c_void_p(bnd.ctypes.data)))
+    return sup, bnd
+
+
+def scs_waveform(ctx, theta, h_ri, stream=None):
+    pt, kt = ptr(theta)
+    ph, kh = ptr(h_ri)
+    if kt != kh:
+        raise ValueError("theta and h must live in the same memory")
+    if kt == SCS_MEM_DEVICE and stream is None:
+        stream = current_stream()
+    _check(lib().scs_waveform(ctx, pt, ph, kt, _stream(stream)))
+
+
+def scs_ctx_stats(ctx, reset=False):
+    a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+    _check(lib().scs_ctx_stats(ctx, C.byref(a), C.byref(b), C.byref(c), int(reset)))
+    return a.value, b.value, c.value
+
+
+def scs_ctx_profile(ctx, enable=-1):
+    n, ms = C.c_int64(), C.c_double()
+    _check(lib().scs_ctx_profile(ctx, enable, C.byref(n), C.byref(ms)))
+    return n.value, ms.value
+
+
+def scs_footprint(ctx, P, N, prec=SCS_PREC_FP64):
+    b = C.c_size_t()
+    _check(lib().scs_footprint(ctx, P, N, prec, C.byref(b)))
+    return b.value
+
+
+def _items(items):
+    arr = (scs_batch_item * len(items))()
+    for i, it in enumerate(items):
+        ctx, N, theta, ups = it[:4]
+        seg = it[4] if len(it) > 4 else None
+        arr[i] = scs_batch_item(ctx.value if isinstance(ctx, C.c_void_p) else ctx, N, 0, theta.shape[0],
+                                theta.data_ptr(), ups.data_ptr(), seg.data_ptr() if seg is not None else None)
+    return arr
+
+
+def scs_evaluate_batched(items, prec=SCS_PREC_FP64, stream=None):
+    """items: list of (ctx, N, theta_cuda [P,7], ups_cuda [P][, seg_cuda])."""
+    arr = _items(items)
+    if stream is None:
+        stream = current_stream()
+    _check(lib().scs_evaluate_batched(arr, len(items), prec, _stream(stream)))
+
+
+def scs_graph_create(items, prec=SCS_PREC_FP64):
+    arr = _items(items)
+    h = C.c_void_p()
+    _check(lib().scs_graph_create(C.byref(h), arr, len(items), prec))
+    return h
+
+
+def scs_graph_launch(graph, stream=None):
+    if stream is None:
+        stream = current_stream()
+    _check(lib().scs_graph_launch(graph, _stream(stream)))
+
+
+def scs_graph_destroy(graph):
+    _check(lib().scs_graph_destroy(graph))
+
+
+def scs_autotune(ctx, theta_cuda, N, prec=SCS_PREC_FP64, cache_path=None):
+    _check(lib().scs_autotune(ctx, theta_cuda.shape[0], C.c_void_p(theta_cuda.data_ptr()), N, prec,
+                              cache_path.encode() if cache_path else None))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def scs_swarm_create(ctx, P, lo, hi, periodic=None, seed=0, swarm_id=0):
+    lo, hi = _f64(lo), _f64(hi)
+    per = np.ascontiguousarray(periodic if periodic is not None else np.zeros(7), dtype=np.int32)
+    h = C.c_void_p()
+    _check(lib().scs_swarm_create(ctx, C.byref(h), P, C.c_void_p(lo.ctypes.data), C.c_void_p(hi.ctypes.data),
+                                  C.c_void_p(per.ctypes.data), seed, swarm_id))
+    return h
+
+
+def scs_swarm_destroy(sw):
+    _check(lib().scs_swarm_destroy(sw))
+
+
+def pso_params(omega, phi_p, phi_g, eps):
+    return scs_pso_params(omega, phi_p, phi_g, (C.c_double * 7)(*[float(e) for e in eps]))
+
+
+def scs_pso_step(sw, params, prec=SCS_PREC_FP64, stream=None):
+    if stream is None:
+        stream = current_stream()
+    _check(lib().scs_pso_step(sw, C.byref(params), prec, _stream(stream)))
+
+
+def scs_swarm_read(sw, P):
+    th, v, pb = np.empty((P, 7)), np.empty((P, 7)), np.empty((P, 7))
+    pv, gb = np.empty(P), np.empty(7)
+    gv, it = C.c_double(), C.c_uint32()
+    _check(lib().scs_swarm_read(sw, C.c_void_p(th.ctypes.data), C.c_void_p(v.ctypes.data),
+                                C.c_void_p(pb.ctypes.data), C.c_void_p(pv.ctypes.data),
+                                C.c_void_p(gb.ctypes.data), C.byref(gv), C.byref(it)))
+    return {"theta": th, "vel": v, "pbest": pb, "pbest_val": pv, "gbest": gb, "gbest_val": gv.value,
+            "iteration": it.value}
+
+
+def scs_swarm_write(sw, state):
+    arrs = [_f64(state[k]) for k in ("theta", "vel", "pbest", "pbest_val", "gbest")]
+    _check(lib().scs_swarm_write(sw, *[C.c_void_p(a.ctypes.data) for a in arrs], float(state["gbest_val"]),
+                                 int(state["iteration"])))
+
+
+def scs_swarm_device_ptrs(sw):
+    a, b = C.c_void_p(), C.c_void_p()
+    _check(lib().scs_swarm_device_ptrs(sw, C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
+def scs_pso_move(theta, vel, pbest, gbest, params, lo, hi, periodic, seed, swarm_id, iteration, stream=None):
+    lo, hi = _f64(lo), _f64(hi)
+    per = np.ascontiguousarray(periodic, dtype=np.int32)
+    if stream is None:
+        stream = current_stream()
+    _check(lib().scs_pso_move(theta.shape[0], theta.data_ptr(), vel.data_ptr(), pbest.data_ptr(), gbest.data_ptr(),
+                              C.byref(params), C.c_void_p(lo.ctypes.data), C.c_void_p(hi.ctypes.data),
+                              C.c_void_p(per.ctypes.data), seed, swarm_id, iteration, _stream(stream)))
+
+
+def scs_pso_best(theta, vals, lo, hi, periodic, pbest, pbest_val, gbest, gbest_val, stream=None):
+    lo, hi = _f64(lo), _f64(hi)
+    per = np.ascontiguousarray(periodic, dtype=np.int32)
+    if stream is None:
+        stream = current_stream()
+    _check(lib().scs_pso_best(theta.shape[0], theta.data_ptr(), vals.data_ptr(), C.c_void_p(lo.ctypes.data),
+                              C.c_void_p(hi.ctypes.data), C.c_void_p(per.ctypes.data), pbest.data_ptr(),
+                              pbest_val.data_ptr(), gbest.data_ptr(), gbest_val.data_ptr(), _stream(stream)))
+
+
+def scs_last_error():
+    m = lib().scs_last_error()
+    return m.decode() if m else ""

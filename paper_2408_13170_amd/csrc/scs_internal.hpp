@@ -1,0 +1,141 @@
+// Internal interface between the host runtime (scs_host.hip) and the kernels
+// (scs_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace scs {
+
+constexpr int kNodes = 6;  // degree-5 block polynomials (6 coefficients / Chebyshev nodes)
+constexpr int kGStride = 56;  // doubles per basis-table entry: 8 functions x 6 orders, G00 hi/lo, padding
+constexpr int kGHi = 48;
+constexpr int kGLo = 49;
+constexpr int kMaxLevel = 10;  // sub-block lengths 2^3 .. 2^9
+
+struct GridArgs {
+    int64_t K;
+    double k0;  // f_min / df
+    double df;
+    int nch;
+};
+
+struct ModelArgs {
+    int pn_order;
+    int response;
+    int support;
+    double t_obs;
+    double orb0_cyc;  // orbital phase at t = 0 [cycles]
+    double cart0;     // cartwheel phase at t = 0 [rad]
+};
+
+struct PhysConst {
+    double pitsun_hi, pitsun_lo;  // pi G Msun / c^3 [s], double-double
+    double k3_hi, k3_lo;          // 3 / (256 pi), double-double
+};
+
+struct PrologueArgs {
+    GridArgs g;
+    ModelArgs m;
+    PhysConst c;
+    int64_t P;
+    int64_t stride;  // coefficient buffer stride (particle capacity)
+    const double* theta;
+    double* coef;
+    int32_t* klo;
+    int32_t* khi;
+    int8_t* lg;  // log2 of the polynomial block length; -1 invalid theta, -2 unresolved
+    int lg_max;
+    unsigned long long* evals;
+    unsigned long long* unresolved;
+};
+
+struct BoundArgs {
+    GridArgs g;
+    ModelArgs m;
+    int64_t P;
+    int64_t stride;
+    int N;
+    int mode;
+    int64_t G;
+    const double* coef;
+    const int32_t* klo;
+    const int32_t* khi;
+    const int8_t* lg;
+    const double* b64;
+    const int64_t* edges;  // device, EXPLICIT mode
+    int32_t* bounds;       // [P][N+1]
+};
+
+struct MainArgs {
+    GridArgs g;
+    ModelArgs m;
+    int64_t p0, P_end;     // particle range handled by this launch
+    int64_t stride;
+    int N;
+    int L;                 // LDS block length (bins) = largest polynomial block
+    int CB;                // LDS blocks per chunk
+    int64_t chunk0;        // first chunk index covered by rec
+    int64_t n_groups;      // particle groups (64 * waves particles each)
+    int64_t n_tiles;       // n_chunks * n_groups
+    int64_t rec_stride;    // particle stride in rec
+    const double* coef;
+    const int32_t* klo;
+    const int32_t* khi;
+    const int8_t* lg;
+    const int32_t* bounds;
+    const double* b64;
+    const float* b32;
+    const double* gtab;            // basis tables of every level
+    int64_t gtab_off[kMaxLevel];   // entry offset of level lg
+    double* rec;           // [chunk][7][rec_stride]
+    double* seg;           // [P][N][3] or null
+    double zscale32;       // FP32 tables hold u * sqrt(s), q * s: Z32 * zscale32 = Z, H32 * hscale32 = H
+    double hscale32;
+};
+
+struct FinalArgs {
+    int64_t K;
+    double df;
+    int64_t p0, P_end;
+    int N;
+    int64_t cbins;
+    int64_t chunk0;
+    int64_t rec_stride;
+    const int32_t* klo;
+    const int32_t* khi;
+    const int8_t* lg;
+    const int32_t* bounds;
+    const double* rec;
+    double* ups;  // [P_end - p0]
+    double* seg;
+};
+
+struct PsoBox {
+    double lo[7], hi[7];
+    int periodic[7];
+};
+struct PsoParams {
+    double omega, phi_p, phi_g;
+    double eps[7];
+};
+
+hipError_t upload_cheb(const double* x, const double* m);
+void launch_bins(const GridArgs& g, const double* d_ri, const double* psd, double* b64, float* b32, double su,
+                 double sq, hipStream_t s);
+void launch_prologue(const PrologueArgs& a, hipStream_t s);
+void launch_bounds(const BoundArgs& a, hipStream_t s);
+size_t main_lds_bytes(int nch, int L, bool mixed);
+void launch_main(const MainArgs& a, int waves, bool mixed, hipStream_t s);
+void launch_finalize(const FinalArgs& a, hipStream_t s);
+void launch_waveform(const MainArgs& a, double* h_ri, hipStream_t s);
+void launch_gtab(const GridArgs& g, int lg, int64_t nsub, double* tab, hipStream_t s);
+void launch_pso_init(int64_t P, const PsoBox& box, uint64_t seed, uint32_t swarm, double* theta, hipStream_t s);
+void launch_pso_move(int64_t P, const PsoBox& box, const PsoParams& prm, uint64_t seed, uint32_t swarm, uint32_t it,
+                     double* theta, double* vel, const double* pbest, const double* gbest, hipStream_t s);
+void launch_pso_best(int64_t P, const PsoBox& box, const double* theta, const double* vals, double* pbest,
+                     double* pbest_val, double* gbest, double* gbest_val, hipStream_t s);
+void launch_fill(double* p, int64_t n, double v, hipStream_t s);
+void launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
+
+}  // namespace scs

@@ -1,0 +1,1224 @@
+// Kernels of the semi-coherent statistic Upsilon_N (arXiv:2408.13170, Sec 2.2)
+// for gfx950.  Layering:
+//   k_bins        particle-independent per-bin products u = f^-7/6 d / S, q = f^-7/3 / S
+//   k_prologue    per particle: PN coefficients (double-double where the phase
+//                 is large), coalescence time, support window, response
+//                 trig-polynomial, polynomial block length        (rows a1, a2)
+//   k_bounds_*    per particle segment edges: equal [h|h], uniform, explicit (a3)
+//   k_main        generate-and-reduce over (chunk, particle group) tiles:
+//                 data staged in LDS, one particle per lane, per-lane
+//                 segmented accumulation                          (a4)
+//   k_finalize    combine fragments of segments that straddle chunks,
+//                 term_n = 4 df |Z_n|^2 / H_n, Upsilon = sum_n    (a5)
+//   k_waveform    template on the grid for one theta (injections, parity)
+//   k_pso_*       particle-swarm move and best update              (a6)
+#include "scs_internal.hpp"
+#include "scs_math.hpp"
+
+namespace scs {
+
+// Chebyshev nodes of the degree-5 block interpolant and the matrix taking
+// node values to monomial coefficients in x in [-1, 1].
+__constant__ double c_cheb_x[kNodes];
+__constant__ double c_cheb_m[kNodes * kNodes];
+
+// ============================================================== per-bin data
+// The FP32 copy is scaled (u by su = sqrt(s), q by sq = s, s ~ 1 / median q)
+// so that it stays far from FP32 overflow for strain-sized PSDs; the
+// statistic is invariant under that scaling and Z, H are unscaled on exit.
+__global__ void k_bins(GridArgs g, const double* __restrict__ d_ri, const double* __restrict__ psd,
+                       double* __restrict__ b64, float* __restrict__ b32, double su, double sq)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= g.K) return;
+    const double f = (g.k0 + (double)k) * g.df;
+    const double a76 = pow(f, -7.0 / 6.0);
+    const double a73 = a76 * a76;
+    const int nv = 3 * g.nch;
+    for (int c = 0; c < g.nch; ++c) {
+        const double S = psd[(int64_t)c * g.K + k];
+        const double dr = d_ri[((int64_t)c * g.K + k) * 2];
+        const double di = d_ri[((int64_t)c * g.K + k) * 2 + 1];
+        const double ur = a76 * dr / S, ui = a76 * di / S, q = a73 / S;
+        // per bin: [u0r, u0i, (u1r, u1i,) q0, (q1)]
+        b64[k * nv + 2 * c] = ur;
+        b64[k * nv + 2 * c + 1] = ui;
+        b64[k * nv + 2 * g.nch + c] = q;
+        b32[k * nv + 2 * c] = (float)(ur * su);
+        b32[k * nv + 2 * c + 1] = (float)(ui * su);
+        b32[k * nv + 2 * g.nch + c] = (float)(q * sq);
+    }
+}
+
+// ============================================================== prologue helpers
+struct PN {
+    double piM, pref, psi2, psi3, psi4, a5, psi6c, psi7;
+    int order;
+};
+
+// t(f) - t_c = d/df [PN phase] from the basis coefficients (FP64; used for
+// the support window and the boundary weights, not for the phase itself).
+__device__ inline double dphase_pn(const double* cf, double f)
+{
+    const double u = 1.0 / cbrt(f);  // f^-1/3
+    const double u2 = u * u, u3 = u2 * u, u4 = u2 * u2, u5 = u4 * u, u6 = u3 * u3, u8 = u4 * u4;
+    const double lnf = log(f);
+    double s = -(5.0 / 3.0) * cf[0] * u8;
+    s += -cf[1] * u6;
+    s += -(2.0 / 3.0) * cf[2] * u5;
+    s += -(1.0 / 3.0) * cf[3] * u4;
+    s += cf[4] * u3;
+    s += (1.0 / 3.0) * cf[5] * u2;
+    s += cf[6] * u2 * (lnf * (1.0 / 3.0) + 1.0);
+    s += (2.0 / 3.0) * cf[7] * u;
+    return s;
+}
+
+__global__ void k_prologue(PrologueArgs a)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.P) return;
+    const int64_t S = a.stride;
+    double* cf = a.coef;
+    const double* th = a.theta + kTheta * p;
+    double t[kTheta];
+    bool ok = true;
+    for (int i = 0; i < kTheta; ++i) {
+        t[i] = th[i];
+        ok = ok && isfinite(t[i]);
+    }
+    const double Mc = t[0], eta = t[1], flow = t[2];
+    ok = ok && Mc > 0.0 && eta > 0.0 && eta <= 0.25 && flow > 0.0;
+    if (!ok) {
+        a.klo[p] = 0;
+        a.khi[p] = 0;
+        a.lg[p] = -1;
+        return;
+    }
+    const int J = a.m.pn_order;
+    // ---- PN phase as sum_i b_i g_i(f) (cycles): f^-5/3, f^-1, f^-2/3, f^-1/3,
+    //      ln f, f^1/3, f^1/3 ln f, f^2/3, plus f t_c and a constant.
+    const dd x = dd_mul_d(dd{a.c.pitsun_hi, a.c.pitsun_lo}, Mc);  // pi T_sun Mc [s]
+    const dd c0 = dd_mul(dd{a.c.k3_hi, a.c.k3_lo}, dd_pow_m53(x));  // (3/(256 pi)) (pi T_sun Mc)^-5/3
+    const double piM = x.hi * pow(eta, -0.6);
+    const double mu = cbrt(piM);
+    const double lnmu = log(mu);
+    const double pref = 3.0 / (256.0 * kPi * eta);
+    const double eta2 = eta * eta, eta3 = eta2 * eta;
+    const double psi2 = 3715.0 / 756.0 + 55.0 * eta / 9.0;
+    const double psi3 = -16.0 * kPi;
+    const double psi4 = 15293365.0 / 508032.0 + 27145.0 * eta / 504.0 + 3085.0 * eta2 / 72.0;
+    const double a5 = kPi * (38645.0 / 756.0 - 65.0 * eta / 9.0);
+    const double psi6c = 11583231236531.0 / 4694215680.0 - 640.0 * kPi * kPi / 3.0 - 6848.0 * kEulerGamma / 21.0 +
+                         (-15737765635.0 / 3048192.0 + 2255.0 * kPi * kPi / 12.0) * eta + 76055.0 * eta2 / 1728.0 -
+                         127825.0 * eta3 / 1296.0;
+    const double b6 = -6848.0 / 21.0;
+    const double psi7 = kPi * (77096675.0 / 254016.0 + 378515.0 * eta / 1512.0 - 74045.0 * eta2 / 756.0);
+    double b[8];
+    b[0] = c0.hi;
+    b[1] = J >= 2 ? pref * psi2 / piM : 0.0;
+    b[2] = J >= 3 ? pref * psi3 / (mu * mu) : 0.0;
+    b[3] = J >= 4 ? pref * psi4 / mu : 0.0;
+    b[4] = J >= 5 ? pref * a5 : 0.0;
+    b[5] = J >= 6 ? pref * mu * (psi6c + b6 * (1.3862943611198906188 + lnmu)) : 0.0;
+    b[6] = J >= 6 ? pref * mu * b6 * (1.0 / 3.0) : 0.0;
+    b[7] = J >= 7 ? pref * psi7 * mu * mu : 0.0;
+    double phic = -0.125;
+    if (J >= 5) phic += pref * a5 * (1.0 + 3.0 * lnmu + 1.5 * 1.7917594692280550008);
+    // ---- t_c from t(f_low) = 0: t_c = -dPhi_PN/df(f_low); Newtonian part in double-double
+    const dd five3 = dd_ratio(5.0, 3.0);
+    const dd tN = dd_mul(dd_mul(five3, c0), dd_pow_m83(dd{flow, 0.0}));
+    double cf_rest[8];
+    cf_rest[0] = 0.0;
+    for (int i = 1; i < 8; ++i) cf_rest[i] = b[i];
+    const double trest = -dphase_pn(cf_rest, flow);
+    const dd tc = dd_add(tN, dd{trest, 0.0});
+    const dd tau = dd_mul_d(tc, a.g.df);  // t_c / T, T = 1/df
+    // ---- support window
+    int64_t klo = 0, khi = a.g.K;
+    const double tcs = tc.hi + tc.lo;
+    if (a.m.support == 1) {
+        // first bin with f_k >= f_low, compared exactly: (k0 + k) df as double-double
+        int64_t k = (int64_t)ceil(flow / a.g.df - a.g.k0);
+        k = k < 0 ? 0 : k;
+        for (int it = 0; it < 4; ++it) {
+            if (k > 0) {
+                const dd fm = two_prod(a.g.k0 + (double)(k - 1), a.g.df);
+                if (fm.hi > flow || (fm.hi == flow && fm.lo >= 0.0)) { --k; continue; }
+            }
+            const dd f0 = two_prod(a.g.k0 + (double)k, a.g.df);
+            if (f0.hi < flow || (f0.hi == flow && f0.lo < 0.0)) { ++k; continue; }
+            break;
+        }
+        klo = k > a.g.K ? a.g.K : k;
+        // first bin at or after klo with t(f_k) >= T_obs (t rises with f)
+        int64_t lo = klo, hi = a.g.K;
+        while (lo < hi) {
+            const int64_t mid = lo + (hi - lo) / 2;
+            const double fm = (a.g.k0 + (double)mid) * a.g.df;
+            const double tm = tcs + dphase_pn(b, fm);
+            if (tm >= a.m.t_obs) hi = mid; else lo = mid + 1;
+        }
+        khi = lo;
+    }
+    // ---- polynomial block length: the largest power of two (<= block_len)
+    //      whose Taylor / Chebyshev remainders stay below 1e-12 cycles
+    //      (phase) and 1e-11 relative (response), using the Newtonian scaling
+    //      at the fastest-chirping point of the support, its start.
+    int lg = -2;
+    if (khi > klo) {
+        const double fs = (a.g.k0 + (double)klo) * a.g.df;
+        double taus = -dphase_pn(b, fs);
+        taus = taus > 0.0 ? taus : 0.0;
+        for (int l = a.lg_max; l >= 3; --l) {
+            const double h = (double)(1 << (l - 1));
+            const double r = h * a.g.df / fs;
+            const double r2 = r * r, r6 = r2 * r2 * r2;
+            const double ephi = 2.4 * taus * fs * r6;
+            bool good = ephi <= 1e-12;
+            if (a.m.response == 1) {
+                const double th_h = 4.0 * kTwoPi * kInvYear * (8.0 / 3.0) * (taus / fs) * a.g.df * h;
+                const double t2 = th_h * th_h;
+                good = good && (t2 * t2 * t2 / 11520.0) <= 1e-11;
+            }
+            if (good) { lg = l; break; }
+        }
+        if (lg < 0) atomicAdd(a.unresolved, 1ULL);
+    } else {
+        lg = a.lg_max;  // empty support: nothing to resolve
+    }
+    // ---- response: trig polynomial of degree 4 in the orbital angle, from
+    //      nine samples (exact for degree <= 4)
+    if (a.m.response == 1) {
+        const Pol pol = polarisation(t[3], t[4], t[6]);
+        const double ci = cos(t[5]);
+        const double ap = 0.5 * (1.0 + ci * ci), ax = ci;
+        double acc[36];
+        for (int i = 0; i < 36; ++i) acc[i] = 0.0;
+        for (int sIdx = 0; sIdx < 9; ++sIdx) {
+            const double Phi = kTwoPi * sIdx / 9.0;
+            double F[4];
+            antenna_lf(Phi, a.m.cart0, pol, F);
+            const double R[4] = {ap * F[0], -ax * F[1], ap * F[2], -ax * F[3]};
+            double ch[5], sh[5];
+            double s1, c1;
+            sincos(Phi, &s1, &c1);
+            harmonics(c1, s1, ch, sh);
+            for (int f = 0; f < 4; ++f) {
+                acc[9 * f] += R[f] * (1.0 / 9.0);
+                for (int k = 1; k <= 4; ++k) {
+                    acc[9 * f + k] += R[f] * ch[k] * (2.0 / 9.0);
+                    acc[9 * f + 4 + k] += R[f] * sh[k] * (2.0 / 9.0);
+                }
+            }
+        }
+        for (int i = 0; i < 36; ++i) cf[(C_RESP + i) * S + p] = acc[i];
+        double sl, cl;
+        sincos(t[3], &sl, &cl);
+        const double cb = cos(t[4]);
+        cf[C_DC * S + p] = -kAuOverC * cb * cl;
+        cf[C_DS * S + p] = -kAuOverC * cb * sl;
+    }
+    cf[C_C0H * S + p] = c0.hi;
+    cf[C_C0L * S + p] = c0.lo;
+    for (int i = 1; i < 8; ++i) cf[(C_B1 + i - 1) * S + p] = b[i];
+    cf[C_PHIC * S + p] = phic;
+    cf[C_TAUH * S + p] = tau.hi;
+    cf[C_TAUL * S + p] = tau.lo;
+    cf[C_TC * S + p] = tcs;
+    a.klo[p] = (int32_t)klo;
+    a.khi[p] = (int32_t)khi;
+    a.lg[p] = (int8_t)lg;
+    if (lg >= 0 && khi > klo) atomicAdd(a.evals, (unsigned long long)(khi - klo));
+}
+
+// ============================================================== block polynomials
+// Taylor coefficients in j (bins from a sub-block centre fc = Kc df) of the
+// eight PN basis functions f^-5/3, f^-1, f^-2/3, f^-1/3, ln f, f^1/3,
+// f^1/3 ln f, f^2/3, m = 0..5.  They depend on the grid only, so one table per
+// sub-block length (level lg, Lp = 2^lg) is built once per context; entry
+// [i*6 + m], plus G[0][0] as a double-double ([kGHi] = hi, [kGLo] = lo).
+__global__ void k_gtab(GridArgs g, int lg, int64_t nsub, double* __restrict__ tab)
+{
+    const int64_t sidx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (sidx >= nsub) return;
+    const int64_t Lp = (int64_t)1 << lg;
+    const double Kc = g.k0 + (double)(sidx * Lp + Lp / 2);
+    const dd fc = two_prod(Kc, g.df);
+    const double eps = g.df / fc.hi;
+    const double u = rcbrt(fc.hi);  // f^-1/3
+    const double u2 = u * u;
+    const double lnf = log(fc.hi) + fc.lo / fc.hi;
+    const double pw[6] = {u2 * u2 * u, u2 * u, u2, u, 1.0 / u, 1.0 / u2};
+    const double sig[6] = {-5.0 / 3.0, -1.0, -2.0 / 3.0, -1.0 / 3.0, 1.0 / 3.0, 2.0 / 3.0};
+    const int slot[6] = {0, 1, 2, 3, 5, 7};
+    double epow[kNodes], lnser[kNodes], f13[kNodes];
+    double e = 1.0;
+    for (int m = 0; m < kNodes; ++m) {
+        epow[m] = e;
+        e *= eps;
+    }
+    lnser[0] = lnf;
+    for (int m = 1; m < kNodes; ++m) lnser[m] = ((m & 1) ? 1.0 : -1.0) * epow[m] / m;
+    double* out = tab + sidx * kGStride;
+    for (int i = 0; i < 6; ++i) {
+        double bin = 1.0;
+        for (int m = 0; m < kNodes; ++m) {
+            const double gim = pw[i] * bin * epow[m];
+            out[slot[i] * kNodes + m] = gim;
+            if (i == 4) f13[m] = gim;
+            bin *= (sig[i] - m) / (m + 1.0);
+        }
+    }
+    for (int m = 0; m < kNodes; ++m) out[4 * kNodes + m] = lnser[m];
+    for (int m = 0; m < kNodes; ++m) {
+        double s = 0.0;
+        for (int q = 0; q <= m; ++q) s = __builtin_fma(f13[q], lnser[m - q], s);
+        out[6 * kNodes + m] = s;
+    }
+    const dd g0 = dd_pow_m53(fc);
+    out[kGHi] = g0.hi;
+    out[kGLo] = g0.lo;
+    for (int q = kGLo + 1; q < kGStride; ++q) out[q] = 0.0;
+}
+
+struct PhasePoly {
+    double ph[kNodes];  // phase [cycles] (GW + Doppler), monomials in x = j / h; ph[0] in [-0.5, 0.5)
+};
+struct RespPoly {
+    double r[4][kNodes];  // response R_A re, R_A im, R_E re, R_E im, monomials in x
+};
+
+// Per-lane polynomial set-up for one sub-block of length 2h centred on
+// absolute bin Kc: phase Taylor coefficients from the basis table (wave-
+// uniform, scalar loads), constant term reduced exactly in double-double;
+// for the LISA response, response and Doppler interpolated at the Chebyshev
+// nodes.  Returns the GW phase coefficients a[] (x-space) for node times.
+template <bool RESP>
+__device__ inline void block_setup(const double* __restrict__ cf, int64_t S, int64_t p, double Kc, int lg,
+                                   const double* __restrict__ G, const GridArgs& g, const ModelArgs& m,
+                                   PhasePoly& out, RespPoly& resp)
+{
+    const double h = (double)(1 << (lg - 1));
+    const double c0h = cf[C_C0H * S + p];
+    double ci[8];
+    ci[0] = c0h;
+#pragma unroll
+    for (int i = 1; i < 8; ++i) ci[i] = cf[(C_B1 + i - 1) * S + p];
+    double a[kNodes];
+#pragma unroll
+    for (int mm = 0; mm < kNodes; ++mm) a[mm] = 0.0;
+    // one basis function at a time, so only six table values are live
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        __asm__ volatile("" ::: "memory");
+#pragma unroll
+        for (int mm = 0; mm < kNodes; ++mm)
+            if (!(i == 0 && mm == 0)) a[mm] = __builtin_fma(ci[i], G[i * kNodes + mm], a[mm]);
+    }
+    {
+        // constant term: frac(Kc tau) + frac(c0 f^-5/3) + frac(rest), cycles
+        const double tauh = cf[C_TAUH * S + p], taul = cf[C_TAUL * S + p];
+        dd lin = two_prod(Kc, tauh);
+        lin.lo = __builtin_fma(Kc, taul, lin.lo);
+        const dd n0 = dd_mul(dd{c0h, cf[C_C0L * S + p]}, dd{G[kGHi], G[kGLo]});
+        const double rest = a[0] + cf[C_PHIC * S + p];
+        const double c = dd_frac(lin) + dd_frac(n0) + (rest - rint(rest));
+        a[0] = c - rint(c);
+        a[1] += tauh + taul;
+    }
+    double hp = 1.0;
+#pragma unroll
+    for (int mm = 0; mm < kNodes; ++mm) {
+        a[mm] *= hp;
+        out.ph[mm] = a[mm];
+        hp *= h;
+    }
+    if constexpr (RESP) {
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+#pragma unroll
+            for (int mm = 0; mm < kNodes; ++mm) resp.r[f][mm] = 0.0;
+        const double dcx = cf[C_DC * S + p], dsx = cf[C_DS * S + p];
+        const double inv_hdf = 1.0 / (h * g.df);
+#pragma unroll 1
+        for (int n = 0; n < kNodes; ++n) {
+            __asm__ volatile("" ::: "memory");  // reload coefficients per node instead of pinning 36 registers
+            const double xn = c_cheb_x[n];
+            // t = (dPhi/dj) / df ; dPhi/dj = (1/h) sum m a_m x^(m-1)
+            double d = 5.0 * a[5];
+            d = __builtin_fma(d, xn, 4.0 * a[4]);
+            d = __builtin_fma(d, xn, 3.0 * a[3]);
+            d = __builtin_fma(d, xn, 2.0 * a[2]);
+            d = __builtin_fma(d, xn, a[1]);
+            double orb = m.orb0_cyc + d * inv_hdf * kInvYear;  // orbital angle [cycles]
+            orb -= rint(orb);
+            double s1, c1;
+            sincos2pi(orb, &s1, &c1);
+            double ch[5], sh[5];
+            harmonics(c1, s1, ch, sh);
+            const double fn = (Kc + xn * h) * g.df;
+            const double dop = fn * (dcx * c1 + dsx * s1);
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                __asm__ volatile("" ::: "memory");  // nine coefficients live at a time
+                const double* cc = cf + (C_RESP + 9 * f) * S + p;
+                double rv = cc[0];
+#pragma unroll
+                for (int k = 1; k <= 4; ++k)
+                    rv = __builtin_fma(cc[k * S], ch[k], __builtin_fma(cc[(4 + k) * S], sh[k], rv));
+#pragma unroll
+                for (int mm = 0; mm < kNodes; ++mm)
+                    resp.r[f][mm] = __builtin_fma(c_cheb_m[mm * kNodes + n], rv, resp.r[f][mm]);
+            }
+#pragma unroll
+            for (int mm = 0; mm < kNodes; ++mm) out.ph[mm] = __builtin_fma(c_cheb_m[mm * kNodes + n], dop, out.ph[mm]);
+        }
+        out.ph[0] -= rint(out.ph[0]);
+    }
+}
+
+__device__ __forceinline__ double horner5(const double* c, double x)
+{
+    double v = c[5];
+    v = __builtin_fma(v, x, c[4]);
+    v = __builtin_fma(v, x, c[3]);
+    v = __builtin_fma(v, x, c[2]);
+    v = __builtin_fma(v, x, c[1]);
+    return __builtin_fma(v, x, c[0]);
+}
+__device__ __forceinline__ float horner5f(const float* c, float x)
+{
+    float v = c[5];
+    v = __builtin_fmaf(v, x, c[4]);
+    v = __builtin_fmaf(v, x, c[3]);
+    v = __builtin_fmaf(v, x, c[2]);
+    v = __builtin_fmaf(v, x, c[1]);
+    return __builtin_fmaf(v, x, c[0]);
+}
+
+// ============================================================== boundaries
+__device__ __forceinline__ double wave_incl_scan(double v, int lane)
+{
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const double t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// Dense weight w(k) = sum_alpha q_alpha(k) |R_alpha(t(f_k))|^2.
+template <int NCH>
+__device__ inline double weight_at(const double* __restrict__ cf, int64_t S, int64_t p, int64_t k, const GridArgs& g,
+                                   const ModelArgs& m, const double* __restrict__ b64, const double* bcoef, double tc)
+{
+    if constexpr (NCH == 1) {
+        return b64[k * 3 + 2];
+    } else {
+        const double f = (g.k0 + (double)k) * g.df;
+        const double t = tc + dphase_pn(bcoef, f);
+        double orb = m.orb0_cyc + t * kInvYear;
+        orb -= rint(orb);
+        double s1, c1;
+        sincos2pi(orb, &s1, &c1);
+        double ch[5], sh[5];
+        harmonics(c1, s1, ch, sh);
+        double rv[4];
+        for (int fi = 0; fi < 4; ++fi) {
+            double cc[9];
+            for (int kk = 0; kk < 9; ++kk) cc[kk] = cf[(C_RESP + 9 * fi + kk) * S + p];
+            rv[fi] = trig4(cc, ch, sh);
+        }
+        return b64[k * 6 + 4] * (rv[0] * rv[0] + rv[1] * rv[1]) + b64[k * 6 + 5] * (rv[2] * rv[2] + rv[3] * rv[3]);
+    }
+}
+
+// Equal-[h|h] edges (rule: nodes k_lo + jG and k_hi - 1, W linear between
+// nodes, C(k) = sum_{i<k} W(i), b_n = min{k : C(k) >= (n/N) C(k_hi)}).  One
+// wave per particle; 63 node intervals per round; two passes (total, then
+// edges) so that no per-node scratch is needed.
+template <int NCH>
+__global__ __launch_bounds__(64) void k_bounds_equal(BoundArgs a)
+{
+    const int64_t p = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (p >= a.P) return;
+    const int N = a.N;
+    int32_t* bo = a.bounds + p * (int64_t)(N + 1);
+    const int lgp = a.lg[p];
+    const int64_t klo = a.klo[p], khi = a.khi[p];
+    if (lgp < 0 || khi <= klo) {
+        for (int n = lane; n <= N; n += 64) bo[n] = (int32_t)klo;
+        return;
+    }
+    const int64_t S = a.stride;
+    double bcoef[8];
+    bcoef[0] = a.coef[C_C0H * S + p];
+    for (int i = 1; i < 8; ++i) bcoef[i] = a.coef[(C_B1 + i - 1) * S + p];
+    const double tc = a.coef[C_TC * S + p];
+    const int64_t G = a.G;
+    const int64_t len = khi - klo;
+    const int64_t nreg = (len - 1) / G + 1;
+    const int64_t nn = nreg + ((klo + (nreg - 1) * G != khi - 1) ? 1 : 0);  // nodes
+    // node j position; node nn is khi (end of the final single-bin interval)
+    auto node = [&](int64_t j) -> int64_t { return j >= nn ? khi : (j == nn - 1 ? khi - 1 : klo + j * G); };
+    // interval integral over [node j, node j+1): g w_j + (w_{j+1} - w_j)(g - 1)/2,
+    // the last interval being the single bin khi - 1 (w_{j+1} := w_j).
+    double total = 0.0;
+    for (int pass = 0; pass < 2; ++pass) {
+        double C0 = 0.0;
+        int n_next = 1;
+        for (int64_t j0 = 0; j0 < nn; j0 += 63) {
+            const int64_t j = j0 + lane;
+            double w = 0.0;
+            if (j < nn) w = weight_at<NCH>(a.coef, S, p, node(j), a.g, a.m, a.b64, bcoef, tc);
+            double wn = __shfl_down(w, 1, 64);
+            if (j + 1 >= nn) wn = w;
+            const int64_t xj = node(j), gj = node(j + 1) - xj;
+            double I = 0.0;
+            const bool live = lane < 63 && j < nn;
+            if (live) I = (double)gj * w + (wn - w) * (double)(gj - 1) * 0.5;
+            const double incl = wave_incl_scan(I, lane);
+            const double chunk = __shfl(incl, 62, 64);
+            if (pass == 0) {
+                total += chunk;
+                continue;
+            }
+            const double cend = C0 + incl;     // C(node j+1)
+            const double cbeg = cend - I;      // C(node j)
+            const double chunk_end = C0 + chunk;
+            // targets falling in this round
+            while (n_next < N) {
+                const int n = n_next + lane;
+                const double tgt = ((double)n / (double)N) * total;
+                const bool mine = n < N && (tgt <= chunk_end || j0 + 63 >= nn);
+                // interval: first live lane with C(node j+1) >= tgt
+                int sel = 62;
+                for (int l = 62; l >= 0; --l) {
+                    const double ce = __shfl(cend, l, 64);
+                    const bool lv = (j0 + l) < nn;
+                    if (lv && ce >= tgt) sel = l;
+                }
+                const int64_t last_live = (nn - 1 - j0) < 62 ? (nn - 1 - j0) : 62;
+                if (sel > last_live) sel = (int)last_live;
+                const double cb = __shfl(cbeg, sel, 64);
+                const double ws = __shfl(w, sel, 64);
+                const double wns = __shfl(wn, sel, 64);
+                const int64_t xs = node(j0 + sel);
+                const int64_t gs = node(j0 + sel + 1) - xs;
+                if (mine) {
+                    // min m in [0, g] with cb + S(m) >= tgt, S(m) = m w + (wn - w) m (m-1) / (2 g)
+                    const double dlt = (wns - ws) / (2.0 * (double)gs);
+                    const double D = tgt - cb;
+                    double mst;
+                    const double A = dlt, B = ws - dlt;
+                    if (fabs(A) * (double)gs < 1e-12 * fabs(B) || A == 0.0) mst = D / B;
+                    else {
+                        const double disc = B * B + 4.0 * A * D;
+                        mst = disc > 0.0 ? (2.0 * D) / (B + sqrt(disc)) : (double)gs;
+                    }
+                    int64_t mm = (int64_t)ceil(mst);
+                    mm = mm < 0 ? 0 : (mm > gs ? gs : mm);
+                    auto Sm = [&](int64_t q) {
+                        const double qd = (double)q;
+                        return cb + (qd * ws + (wns - ws) * (qd * (qd - 1.0)) / (2.0 * (double)gs));
+                    };
+                    while (mm > 0 && Sm(mm - 1) >= tgt) --mm;
+                    while (mm < gs && Sm(mm) < tgt) ++mm;
+                    bo[n] = (int32_t)(xs + mm);
+                }
+                const unsigned long long bal = __ballot(mine);
+                const int cnt = __popcll(bal);
+                n_next += cnt;
+                if (cnt < 64) break;
+            }
+            C0 = chunk_end;
+        }
+        if (pass == 1) {
+            for (int n = n_next + lane; n < N; n += 64) bo[n] = (int32_t)khi;
+        }
+    }
+    if (lane == 0) {
+        bo[0] = (int32_t)klo;
+        bo[N] = (int32_t)khi;
+    }
+}
+
+__global__ void k_bounds_simple(BoundArgs a)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int N = a.N;
+    const int64_t p = idx / (N + 1);
+    const int n = (int)(idx % (N + 1));
+    if (p >= a.P) return;
+    const int64_t klo = a.klo[p], khi = a.khi[p];
+    int64_t v;
+    if (a.lg[p] < 0 || khi <= klo) v = klo;
+    else if (a.mode == 1) v = klo + (int64_t)(((__int128)n * (khi - klo)) / N);
+    else {
+        const int64_t e = a.edges[n];
+        v = e < klo ? klo : (e > khi ? khi : e);
+    }
+    a.bounds[p * (int64_t)(N + 1) + n] = (int32_t)v;
+}
+
+// ============================================================== main kernel
+// Work tile = (chunk of CB LDS blocks of L bins, group of 64 W particles).
+// One lane = one particle; all lanes of a workgroup read the same staged bins
+// (LDS broadcast).  Each lane accumulates Z and H of its current segment and
+// closes it at its own edges; a chunk leaves per (particle, chunk) the sum of
+// terms of segments complete inside it and the head / tail pieces of the
+// segments that cross its edges, which k_finalize joins.
+__device__ __forceinline__ int bsearch_seg(const int32_t* __restrict__ bo, int N, int64_t k)
+{
+    // largest n in [0, N-1] with b_n <= k
+    int lo = 0, hi = N - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (bo[mid] <= k) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int NCH, bool MIXED>
+__global__ __launch_bounds__(256) void k_main(MainArgs a, const double* __restrict__ gtab)
+{
+    constexpr int NV = 3 * NCH;  // values per bin
+    constexpr bool RESP = NCH == 2;
+    extern __shared__ __align__(16) unsigned char smem[];
+    // ---- tile decode, XCD-aware: consecutive logical tiles (same chunk,
+    //      neighbouring particle groups) land on the same XCD's L2.
+    const int64_t nwg = a.n_tiles;
+    const int64_t per_xcd = (nwg + 7) / 8;
+    const int64_t bid = blockIdx.x;
+    const int64_t logical = (bid & 7) * per_xcd + (bid >> 3);
+    if (logical >= nwg) return;
+    const int64_t chunk = a.chunk0 + logical / a.n_groups;
+    const int64_t group = logical % a.n_groups;
+    const int tid = threadIdx.x;
+    const int64_t p = a.p0 + group * (int64_t)blockDim.x + tid;
+    const int K = (int)a.g.K;
+    const int cbins = a.L * a.CB;
+    const int Kc = (int)chunk * cbins;
+    const int Ke = (Kc + cbins < K) ? Kc + cbins : K;
+    int lo = 0, hi = 0, lg = -1;
+    if (p < a.P_end) {
+        lg = a.lg[p];
+        if (lg >= 0) {
+            lo = a.klo[p];
+            hi = a.khi[p];
+        }
+    }
+    lo = lo > Kc ? lo : Kc;
+    hi = hi < Ke ? hi : Ke;
+    const bool has = lo < hi;
+    if (!__syncthreads_or(has)) return;
+    const int64_t S = a.stride;
+    const int N = a.N;
+    const int32_t* __restrict__ bo = a.bounds + (p < a.P_end ? p : a.p0) * (int64_t)(N + 1);
+    // wave-uniform polynomial block length: the smallest requested in the wave
+    int lgw = has ? lg : 30;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const int t = __shfl_xor(lgw, o, 64);
+        lgw = t < lgw ? t : lgw;
+    }
+    lgw = __builtin_amdgcn_readfirstlane(lgw);  // uniform: scalar registers and scalar loads downstream
+    int n = 0, nb = 0;
+    bool before = false;
+    if (has) {
+        n = bsearch_seg(bo, N, lo);
+        nb = bo[n + 1];
+        before = bo[n] < Kc;
+    }
+    double zr = 0.0, zi = 0.0, hh = 0.0;
+    float kzr = 0.f, kzi = 0.f, khh = 0.f, czr = 0.f, czi = 0.f, chh = 0.f;  // Kahan sums (mixed)
+    double part = 0.0;
+    double hd0 = 0.0, hd1 = 0.0, hd2 = 0.0, tl0 = 0.0, tl1 = 0.0, tl2 = 0.0;
+    const double four_df = 4.0 * a.g.df;
+    double* const seg = a.seg;
+    // close segment n at bin k (exclusive) and move to the next non-empty one
+    auto flush = [&](int k) {
+        double fzr = zr, fzi = zi, fhh = hh;
+        if constexpr (MIXED) {
+            fzr = ((double)kzr - (double)czr) * a.zscale32;
+            fzi = ((double)kzi - (double)czi) * a.zscale32;
+            fhh = ((double)khh - (double)chh) * a.hscale32;
+            kzr = kzi = khh = czr = czi = chh = 0.f;
+        }
+        if (before) {
+            hd0 = fzr;
+            hd1 = fzi;
+            hd2 = fhh;
+        } else {
+            if (fhh > 0.0) part += four_df * (fzr * fzr + fzi * fzi) / fhh;
+            if (seg) {
+                double* sp = seg + (p * (int64_t)N + n) * 3;
+                sp[0] = fzr;
+                sp[1] = fzi;
+                sp[2] = fhh;
+            }
+        }
+        zr = zi = hh = 0.0;
+        before = false;
+        ++n;
+        nb = (n < N) ? bo[n + 1] : INT32_MAX;
+        while (n < N - 1 && nb == k) {
+            ++n;
+            nb = bo[n + 1];
+        }
+    };
+    const int L = a.L;
+    const int nthreads = blockDim.x;
+    const double* __restrict__ gt = gtab + (lgw < kMaxLevel ? a.gtab_off[lgw] : 0) * kGStride;
+    PhasePoly poly;
+    RespPoly rp;
+    float phf[kNodes], rf[4][kNodes];
+    float a1h = 0.f;
+    for (int b0 = Kc; b0 < Ke; b0 += L) {
+        const int b1 = (b0 + L < Ke) ? b0 + L : Ke;
+        const int nbins = b1 - b0;
+        // ---- stage bins [b0, b1) into LDS
+        __syncthreads();
+        if constexpr (!MIXED && NV % 2 == 0) {
+            const double2* src = reinterpret_cast<const double2*>(a.b64 + (int64_t)b0 * NV);
+            double2* dst = reinterpret_cast<double2*>(smem);
+            const int cnt = nbins * NV / 2;
+            for (int i = tid; i < cnt; i += nthreads) dst[i] = src[i];
+        } else if constexpr (!MIXED) {
+            const double* src = a.b64 + (int64_t)b0 * NV;
+            double* dst = reinterpret_cast<double*>(smem);
+            const int cnt = nbins * NV;
+            for (int i = tid; i < cnt; i += nthreads) dst[i] = src[i];
+        } else {
+            const float* src = a.b32 + (int64_t)b0 * NV;
+            float* dst = reinterpret_cast<float*>(smem);
+            const int cnt = nbins * NV;
+            for (int i = tid; i < cnt; i += nthreads) dst[i] = src[i];
+        }
+        __syncthreads();
+        const int llo = lo > b0 ? lo : b0;
+        const int lhi = hi < b1 ? hi : b1;
+        const bool act = llo < lhi;
+        // wave-uniform bin range
+        int wlo = act ? llo : INT32_MAX, whi = act ? lhi : INT32_MIN;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const int t1 = __shfl_xor(wlo, o, 64);
+            const int t2 = __shfl_xor(whi, o, 64);
+            wlo = t1 < wlo ? t1 : wlo;
+            whi = t2 > whi ? t2 : whi;
+        }
+        wlo = __builtin_amdgcn_readfirstlane(wlo);
+        whi = __builtin_amdgcn_readfirstlane(whi);
+        if (wlo >= whi) continue;
+        const int Lp = 1 << lgw;
+        const int hp = Lp >> 1;
+        const double inv_h = 1.0 / (double)hp;
+#pragma unroll 1
+        for (int sb0 = (wlo >> lgw) << lgw; sb0 < whi; sb0 += Lp) {
+            const int kc = sb0 + hp;
+            const int s_lo = sb0 > wlo ? sb0 : wlo;
+            const int s_hi = (sb0 + Lp < whi) ? sb0 + Lp : whi;
+            const bool sact = act && llo < sb0 + Lp && lhi > sb0;
+            if (sact) {
+                block_setup<RESP>(a.coef, S, p, a.g.k0 + (double)kc, lgw, gt + (int64_t)(sb0 >> lgw) * kGStride, a.g,
+                                  a.m, poly, rp);
+                if constexpr (MIXED) {
+                    // phase = a0 + frac(a1h j) + residual(j): j is an integer and
+                    // a1h keeps 12 significant bits, so a1h j is exact in FP32
+                    double aj[kNodes];
+                    double sc = 1.0;
+#pragma unroll
+                    for (int mm = 0; mm < kNodes; ++mm) {
+                        aj[mm] = poly.ph[mm] * sc;
+                        sc *= inv_h;
+                    }
+                    int ex;
+                    frexp(aj[1], &ex);
+                    const double q = ldexp(1.0, ex - 12);
+                    const double hi1 = rint(aj[1] / q) * q;
+                    a1h = (float)hi1;
+                    phf[0] = (float)aj[0];
+                    phf[1] = (float)(aj[1] - hi1);
+#pragma unroll
+                    for (int mm = 2; mm < kNodes; ++mm) phf[mm] = (float)aj[mm];
+                    if constexpr (RESP) {
+#pragma unroll
+                        for (int f = 0; f < 4; ++f)
+#pragma unroll
+                            for (int mm = 0; mm < kNodes; ++mm) rf[f][mm] = (float)rp.r[f][mm];
+                    }
+                }
+            }
+#pragma unroll 1
+            for (int k = s_lo; k < s_hi; ++k) {
+                if (k >= llo && k < lhi) {
+                    if (k == nb) flush(k);
+                    const int jl = k - b0;
+                    if constexpr (!MIXED) {
+                        const double x = (double)(k - kc) * inv_h;
+                        double ph = horner5(poly.ph, x);
+                        ph -= rint(ph);
+                        double sn, cs;
+                        sincos2pi(ph, &sn, &cs);
+                        const double* bin = reinterpret_cast<const double*>(smem) + jl * NV;
+                        if constexpr (RESP) {
+                            const double2 uA = *reinterpret_cast<const double2*>(bin);
+                            const double2 uE = *reinterpret_cast<const double2*>(bin + 2);
+                            const double2 qq = *reinterpret_cast<const double2*>(bin + 4);
+                            const double rar = horner5(rp.r[0], x), rai = horner5(rp.r[1], x);
+                            const double rer = horner5(rp.r[2], x), rei = horner5(rp.r[3], x);
+                            double sr = uA.x * rar;
+                            sr = __builtin_fma(uA.y, rai, sr);
+                            sr = __builtin_fma(uE.x, rer, sr);
+                            sr = __builtin_fma(uE.y, rei, sr);
+                            double si = uA.y * rar;
+                            si = __builtin_fma(-uA.x, rai, si);
+                            si = __builtin_fma(uE.y, rer, si);
+                            si = __builtin_fma(-uE.x, rei, si);
+                            zr = __builtin_fma(sr, cs, __builtin_fma(-si, sn, zr));
+                            zi = __builtin_fma(sr, sn, __builtin_fma(si, cs, zi));
+                            const double wa = __builtin_fma(rar, rar, rai * rai);
+                            const double we = __builtin_fma(rer, rer, rei * rei);
+                            hh = __builtin_fma(qq.x, wa, __builtin_fma(qq.y, we, hh));
+                        } else {
+                            const double ur = bin[0], ui = bin[1], qq = bin[2];
+                            zr = __builtin_fma(ur, cs, __builtin_fma(-ui, sn, zr));
+                            zi = __builtin_fma(ur, sn, __builtin_fma(ui, cs, zi));
+                            hh += qq;
+                        }
+                    } else {
+                        const float jf = (float)(k - kc);
+                        const float pl = a1h * jf;
+                        const float f1 = pl - rintf(pl);
+                        float r = phf[5];
+                        r = __builtin_fmaf(r, jf, phf[4]);
+                        r = __builtin_fmaf(r, jf, phf[3]);
+                        r = __builtin_fmaf(r, jf, phf[2]);
+                        r = __builtin_fmaf(r, jf, phf[1]);
+                        const float ph = __builtin_fmaf(r, jf, phf[0] + f1);
+                        const float sn = __builtin_amdgcn_sinf(ph);
+                        const float cs = __builtin_amdgcn_cosf(ph);
+                        const float* bin = reinterpret_cast<const float*>(smem) + jl * NV;
+                        float dzr, dzi, dhh;
+                        if constexpr (RESP) {
+                            const float x = jf * (float)inv_h;
+                            const float rar = horner5f(rf[0], x), rai = horner5f(rf[1], x);
+                            const float rer = horner5f(rf[2], x), rei = horner5f(rf[3], x);
+                            const float uar = bin[0], uai = bin[1], uer = bin[2], uei = bin[3];
+                            float sr = uar * rar;
+                            sr = __builtin_fmaf(uai, rai, sr);
+                            sr = __builtin_fmaf(uer, rer, sr);
+                            sr = __builtin_fmaf(uei, rei, sr);
+                            float si = uai * rar;
+                            si = __builtin_fmaf(-uar, rai, si);
+                            si = __builtin_fmaf(uei, rer, si);
+                            si = __builtin_fmaf(-uer, rei, si);
+                            dzr = __builtin_fmaf(sr, cs, -si * sn);
+                            dzi = __builtin_fmaf(sr, sn, si * cs);
+                            const float wa = __builtin_fmaf(rar, rar, rai * rai);
+                            const float we = __builtin_fmaf(rer, rer, rei * rei);
+                            dhh = __builtin_fmaf(bin[4], wa, bin[5] * we);
+                        } else {
+                            const float ur = bin[0], ui = bin[1];
+                            dzr = __builtin_fmaf(ur, cs, -ui * sn);
+                            dzi = __builtin_fmaf(ur, sn, ui * cs);
+                            dhh = bin[2];
+                        }
+                        // Kahan-compensated FP32 sums
+                        {
+                            const float y = dzr - czr, t = kzr + y;
+                            czr = (t - kzr) - y;
+                            kzr = t;
+                        }
+                        {
+                            const float y = dzi - czi, t = kzi + y;
+                            czi = (t - kzi) - y;
+                            kzi = t;
+                        }
+                        {
+                            const float y = dhh - chh, t = khh + y;
+                            chh = (t - khh) - y;
+                            khh = t;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    // ---- close the chunk
+    if (has) {
+        if (nb <= hi) {
+            flush(hi);
+        } else {
+            double fzr = zr, fzi = zi, fhh = hh;
+            if constexpr (MIXED) {
+                fzr = ((double)kzr - (double)czr) * a.zscale32;
+                fzi = ((double)kzi - (double)czi) * a.zscale32;
+                fhh = ((double)khh - (double)chh) * a.hscale32;
+            }
+            if (before) {
+                hd0 = fzr;
+                hd1 = fzi;
+                hd2 = fhh;
+            } else {
+                tl0 = fzr;
+                tl1 = fzi;
+                tl2 = fhh;
+            }
+        }
+        const int64_t RS = a.rec_stride;
+        const int64_t ci = chunk - a.chunk0;
+        double* rec = a.rec + ci * RS * 7 + (p - a.p0);
+        rec[0 * RS] = part;
+        rec[1 * RS] = hd0;
+        rec[2 * RS] = hd1;
+        rec[3 * RS] = hd2;
+        rec[4 * RS] = tl0;
+        rec[5 * RS] = tl1;
+        rec[6 * RS] = tl2;
+    }
+}
+
+// ============================================================== finalize
+__global__ void k_finalize(FinalArgs a)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.P_end) return;
+    const int N = a.N;
+    const int lg = a.lg[p];
+    double* seg = a.seg;
+    if (lg == -1 || lg == -2) {
+        a.ups[p - a.p0] = __longlong_as_double(0x7ff8000000000000LL);  // NaN: invalid / unresolved theta
+        if (seg)
+            for (int n = 0; n < N; ++n)
+                for (int c = 0; c < 3; ++c) seg[(p * (int64_t)N + n) * 3 + c] = __longlong_as_double(0x7ff8000000000000LL);
+        return;
+    }
+    const int64_t klo = a.klo[p], khi = a.khi[p];
+    const int32_t* bo = a.bounds + p * (int64_t)(N + 1);
+    if (seg) {
+        for (int n = 0; n < N; ++n)
+            if (bo[n] == bo[n + 1])
+                for (int c = 0; c < 3; ++c) seg[(p * (int64_t)N + n) * 3 + c] = 0.0;
+    }
+    if (khi <= klo) {
+        a.ups[p - a.p0] = 0.0;
+        return;
+    }
+    const int64_t cb = a.cbins;
+    const int64_t c_first = klo / cb, c_last = (khi - 1) / cb;
+    const int64_t RS = a.rec_stride;
+    const double* rec = a.rec + (p - a.p0);
+    const double four_df = 4.0 * a.df;
+    double sum = 0.0;
+    for (int64_t c = c_first; c <= c_last; ++c) sum += rec[(c - a.chunk0) * RS * 7];
+    double azr = 0.0, azi = 0.0, ahh = 0.0;
+    for (int64_t c = c_first; c <= c_last; ++c) {
+        const double* r = rec + (c - a.chunk0) * RS * 7;
+        const int64_t Kc = c * cb;
+        const int64_t Ke = (Kc + cb < a.K) ? Kc + cb : a.K;
+        if (Kc > klo) {
+            const int n = bsearch_seg(bo, N, Kc);
+            if (bo[n] < Kc) {
+                azr += r[1 * RS];
+                azi += r[2 * RS];
+                ahh += r[3 * RS];
+                if (bo[n + 1] <= Ke) {
+                    if (ahh > 0.0) sum += four_df * (azr * azr + azi * azi) / ahh;
+                    if (seg) {
+                        double* sp = seg + (p * (int64_t)N + n) * 3;
+                        sp[0] = azr; sp[1] = azi; sp[2] = ahh;
+                    }
+                    azr = azi = ahh = 0.0;
+                }
+            }
+        }
+        const int64_t last = ((Ke < khi) ? Ke : khi) - 1;
+        const int n2 = bsearch_seg(bo, N, last);
+        if (bo[n2 + 1] > Ke && bo[n2] >= Kc) {
+            azr = r[4 * RS];
+            azi = r[5 * RS];
+            ahh = r[6 * RS];
+        }
+    }
+    a.ups[p - a.p0] = sum;
+}
+
+// ============================================================== waveform
+__global__ void k_waveform(MainArgs a, double* __restrict__ h_ri)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.g.K) return;
+    const int nch = a.g.nch;
+    for (int c = 0; c < nch; ++c) {
+        h_ri[((int64_t)c * a.g.K + k) * 2] = 0.0;
+        h_ri[((int64_t)c * a.g.K + k) * 2 + 1] = 0.0;
+    }
+    const int lg = a.lg[0];
+    if (lg < 0 || k < a.klo[0] || k >= a.khi[0]) return;
+    const int64_t Lp = (int64_t)1 << lg;
+    const int64_t sb = k >> lg;
+    const int64_t kc = sb * Lp + (Lp >> 1);
+    const double* G = a.gtab + (a.gtab_off[lg] + sb) * kGStride;
+    PhasePoly poly;
+    RespPoly rp;
+    const double x = (double)(k - kc) / (double)(Lp >> 1);
+    const double f = (a.g.k0 + (double)k) * a.g.df;
+    const double amp = pow(f, -7.0 / 6.0);
+    if (nch == 2) {
+        block_setup<true>(a.coef, a.stride, 0, a.g.k0 + (double)kc, lg, G, a.g, a.m, poly, rp);
+        double ph = horner5(poly.ph, x);
+        ph -= rint(ph);
+        double sn, cs;
+        sincos2pi(ph, &sn, &cs);
+        for (int c = 0; c < 2; ++c) {
+            const double rr = horner5(rp.r[2 * c], x), ri = horner5(rp.r[2 * c + 1], x);
+            // h = amp R e^{-i 2 pi ph}
+            h_ri[((int64_t)c * a.g.K + k) * 2] = amp * (rr * cs + ri * sn);
+            h_ri[((int64_t)c * a.g.K + k) * 2 + 1] = amp * (ri * cs - rr * sn);
+        }
+    } else {
+        block_setup<false>(a.coef, a.stride, 0, a.g.k0 + (double)kc, lg, G, a.g, a.m, poly, rp);
+        double ph = horner5(poly.ph, x);
+        ph -= rint(ph);
+        double sn, cs;
+        sincos2pi(ph, &sn, &cs);
+        h_ri[2 * k] = amp * cs;
+        h_ri[2 * k + 1] = -amp * sn;
+    }
+}
+
+// ============================================================== PSO
+// Philox4x32-10 (Salmon et al. 2011): 10 rounds of two 32x32 -> 64-bit
+// multiplies, Weyl key schedule.
+__device__ __forceinline__ void philox10(uint32_t c[4], uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
+        const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+__device__ __forceinline__ double uniform01(uint64_t seed, uint32_t swarm, uint32_t it, uint32_t pp, uint32_t d,
+                                            uint32_t stream)
+{
+    uint32_t c[4] = {it, pp, d, stream};
+    philox10(c, (uint32_t)seed, (uint32_t)(seed >> 32) + swarm);
+    const uint64_t x = ((uint64_t)(c[0] >> 6) << 26) | (uint64_t)(c[1] >> 6);
+    return ((double)x + 0.5) * 0x1p-52;
+}
+
+// Every arithmetic step is a single IEEE operation (no contraction) so the
+// result is reproducible bit for bit on any IEEE machine.
+#pragma clang fp contract(off)
+__global__ void k_pso_init(int64_t P, PsoBox box, uint64_t seed, uint32_t swarm, double* __restrict__ theta)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P * kTheta) return;
+    const int64_t pp = i / kTheta;
+    const int d = (int)(i % kTheta);
+    const double r = uniform01(seed, swarm, 0u, (uint32_t)pp, (uint32_t)d, 3u);
+    const double w = box.hi[d] - box.lo[d];
+    const double x = r * w;
+    theta[i] = box.lo[d] + x;
+}
+
+__global__ void k_pso_move(int64_t P, PsoBox box, PsoParams prm, uint64_t seed, uint32_t swarm, uint32_t it,
+                           double* __restrict__ theta, double* __restrict__ vel, const double* __restrict__ pbest,
+                           const double* __restrict__ gbest)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P * kTheta) return;
+    const int64_t pp = i / kTheta;
+    const int d = (int)(i % kTheta);
+    const double x = theta[i];
+    const double rp = uniform01(seed, swarm, it, (uint32_t)pp, (uint32_t)d, 0u);
+    const double rg = uniform01(seed, swarm, it, (uint32_t)pp, (uint32_t)d, 1u);
+    const double t1 = prm.omega * vel[i];
+    const double ta = prm.phi_p * rp;
+    const double tb = pbest[i] - x;
+    const double t2 = ta * tb;
+    const double tcg = prm.phi_g * rg;
+    const double te = gbest[d] - x;
+    const double t3 = tcg * te;
+    const double s = t1 + t2;
+    const double u = s + t3;
+    const double eps = prm.eps[d];
+    double v;
+    if (fabs(u) >= eps) v = u;
+    else if (u != 0.0) v = copysign(eps, u);
+    else if (eps == 0.0) v = 0.0;
+    else v = uniform01(seed, swarm, it, (uint32_t)pp, (uint32_t)d, 2u) < 0.5 ? -eps : eps;
+    double xn = x + v;
+    if (box.periodic[d]) {
+        const double per = box.hi[d] - box.lo[d];
+        double y = xn - box.lo[d];
+        const double q = floor(y / per);
+        const double z = per * q;
+        y = y - z;
+        xn = box.lo[d] + y;
+    }
+    vel[i] = v;
+    theta[i] = xn;
+}
+#pragma clang fp contract(on)
+
+// Particle bests (one thread per particle), then the swarm best by a
+// single-workgroup arg-max (first index among equal values).
+__global__ void k_pso_pbest(int64_t P, PsoBox box, const double* __restrict__ theta, const double* __restrict__ vals,
+                            double* __restrict__ pbest, double* __restrict__ pbest_val)
+{
+    const int64_t pp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pp >= P) return;
+    double v = vals[pp];
+    bool inbox = true;
+    for (int d = 0; d < kTheta; ++d) {
+        const double x = theta[pp * kTheta + d];
+        if (!box.periodic[d] && !(x >= box.lo[d] && x <= box.hi[d])) inbox = false;
+    }
+    if (!inbox || isnan(v)) v = -INFINITY;
+    if (v > pbest_val[pp]) {
+        pbest_val[pp] = v;
+        for (int d = 0; d < kTheta; ++d) pbest[pp * kTheta + d] = theta[pp * kTheta + d];
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_pso_gbest(int64_t P, const double* __restrict__ pbest,
+                                                     const double* __restrict__ pbest_val, double* __restrict__ gbest,
+                                                     double* __restrict__ gbest_val)
+{
+    __shared__ double sv[1024];
+    __shared__ int64_t si[1024];
+    const int tid = threadIdx.x;
+    double bv = -INFINITY;
+    int64_t bi = -1;
+    for (int64_t i = tid; i < P; i += blockDim.x) {
+        const double v = pbest_val[i];
+        if (v > bv) { bv = v; bi = i; }
+    }
+    sv[tid] = bv;
+    si[tid] = bi;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (tid < s) {
+            const double v2 = sv[tid + s];
+            const int64_t i2 = si[tid + s];
+            if (v2 > sv[tid] || (v2 == sv[tid] && i2 >= 0 && (si[tid] < 0 || i2 < si[tid]))) {
+                sv[tid] = v2;
+                si[tid] = i2;
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        if (si[0] >= 0 && sv[0] > *gbest_val) {
+            *gbest_val = sv[0];
+            for (int d = 0; d < kTheta; ++d) gbest[d] = pbest[si[0] * kTheta + d];
+        }
+    }
+}
+
+__global__ void k_fill_f64(double* p, int64_t n, double v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+__global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ============================================================== launchers
+static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+hipError_t upload_cheb(const double* x, const double* m)
+{
+    hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_cheb_x), x, sizeof(double) * kNodes);
+    if (e != hipSuccess) return e;
+    return hipMemcpyToSymbol(HIP_SYMBOL(c_cheb_m), m, sizeof(double) * kNodes * kNodes);
+}
+
+void launch_bins(const GridArgs& g, const double* d_ri, const double* psd, double* b64, float* b32, double su,
+                 double sq, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bins, dim3(nblk(g.K, 256)), dim3(256), 0, s, g, d_ri, psd, b64, b32, su, sq);
+}
+void launch_prologue(const PrologueArgs& a, hipStream_t s)
+{
+    if (a.P > 0) hipLaunchKernelGGL(k_prologue, dim3(nblk(a.P, 64)), dim3(64), 0, s, a);
+}
+void launch_bounds(const BoundArgs& a, hipStream_t s)
+{
+    if (a.P <= 0) return;
+    if (a.mode == 0) {
+        if (a.g.nch == 2) hipLaunchKernelGGL(k_bounds_equal<2>, dim3((unsigned)a.P), dim3(64), 0, s, a);
+        else hipLaunchKernelGGL(k_bounds_equal<1>, dim3((unsigned)a.P), dim3(64), 0, s, a);
+    } else {
+        hipLaunchKernelGGL(k_bounds_simple, dim3(nblk(a.P * (a.N + 1), 256)), dim3(256), 0, s, a);
+    }
+}
+size_t main_lds_bytes(int nch, int L, bool mixed) { return (size_t)L * 3 * nch * (mixed ? 4 : 8); }
+void launch_main(const MainArgs& a, int waves, bool mixed, hipStream_t s)
+{
+    if (a.n_tiles <= 0) return;
+    const unsigned grid = (unsigned)(((a.n_tiles + 7) / 8) * 8);
+    const size_t lds = main_lds_bytes(a.g.nch, a.L, mixed);
+    const dim3 blk(64 * waves);
+    if (a.g.nch == 2) {
+        if (mixed) hipLaunchKernelGGL((k_main<2, true>), dim3(grid), blk, lds, s, a, a.gtab);
+        else hipLaunchKernelGGL((k_main<2, false>), dim3(grid), blk, lds, s, a, a.gtab);
+    } else {
+        if (mixed) hipLaunchKernelGGL((k_main<1, true>), dim3(grid), blk, lds, s, a, a.gtab);
+        else hipLaunchKernelGGL((k_main<1, false>), dim3(grid), blk, lds, s, a, a.gtab);
+    }
+}
+void launch_finalize(const FinalArgs& a, hipStream_t s)
+{
+    const int64_t n = a.P_end - a.p0;
+    if (n > 0) hipLaunchKernelGGL(k_finalize, dim3(nblk(a.P_end, 128)), dim3(128), 0, s, a);
+}
+void launch_gtab(const GridArgs& g, int lg, int64_t nsub, double* tab, hipStream_t s)
+{
+    if (nsub > 0) hipLaunchKernelGGL(k_gtab, dim3(nblk(nsub, 128)), dim3(128), 0, s, g, lg, nsub, tab);
+}
+void launch_waveform(const MainArgs& a, double* h_ri, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_waveform, dim3(nblk(a.g.K, 128)), dim3(128), 0, s, a, h_ri);
+}
+void launch_pso_init(int64_t P, const PsoBox& box, uint64_t seed, uint32_t swarm, double* theta, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pso_init, dim3(nblk(P * kTheta, 256)), dim3(256), 0, s, P, box, seed, swarm, theta);
+}
+void launch_pso_move(int64_t P, const PsoBox& box, const PsoParams& prm, uint64_t seed, uint32_t swarm, uint32_t it,
+                     double* theta, double* vel, const double* pbest, const double* gbest, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pso_move, dim3(nblk(P * kTheta, 256)), dim3(256), 0, s, P, box, prm, seed, swarm, it, theta,
+                       vel, pbest, gbest);
+}
+void launch_pso_best(int64_t P, const PsoBox& box, const double* theta, const double* vals, double* pbest,
+                     double* pbest_val, double* gbest, double* gbest_val, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pso_pbest, dim3(nblk(P, 256)), dim3(256), 0, s, P, box, theta, vals, pbest, pbest_val);
+    hipLaunchKernelGGL(k_pso_gbest, dim3(1), dim3(1024), 0, s, P, pbest, pbest_val, gbest, gbest_val);
+}
+void launch_fill(double* p, int64_t n, double v, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_fill_f64, dim3(nblk(n, 256)), dim3(256), 0, s, p, n, v);
+}
+void launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_fill_u64, dim3(nblk(n, 256)), dim3(256), 0, s, p, n, v);
+}
+
+}  // namespace scs

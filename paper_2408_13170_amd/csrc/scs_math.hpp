@@ -1,0 +1,231 @@
+// Device arithmetic for the semi-coherent statistic kernels (gfx950).
+//
+// * double-double helpers (Dekker / Knuth error-free transformations) for the
+//   few quantities whose size (~1e6-1e7 cycles of phase) exceeds what one
+//   double resolves at the 1e-12-cycle level;
+// * sin/cos of 2 pi r for a phase already reduced to cycles;
+// * the TaylorF2 phase written as a sum of particle coefficients times
+//   particle-independent basis functions of frequency (Sec 4 waveform);
+// * the low-frequency LISA A/E antenna patterns (Sec 4 response).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace scs {
+
+// ---------------------------------------------------------------- constants
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr double kPi = 3.141592653589793238462643383279503;
+constexpr double kAuOverC = 1.495978707e11 / 299792458.0;  // light travel time of 1 AU [s]
+constexpr double kInvYear = 1.0 / 31557600.0;              // Julian year
+constexpr double kEulerGamma = 0.57721566490153286060651209;
+constexpr int kTheta = 7;
+
+// coefficient-buffer field indices (field-major SoA, stride = particle capacity)
+enum Coef : int {
+    C_C0H = 0, C_C0L,      // Newtonian coefficient of f^-5/3, double-double
+    C_B1, C_B2, C_B3, C_B4, C_B5, C_B6, C_B7,  // coefficients of f^-1, f^-2/3, f^-1/3, ln f, f^1/3, f^1/3 ln f, f^2/3
+    C_PHIC,                // constant phase [cycles]
+    C_TAUH, C_TAUL,        // t_c * df, double-double
+    C_TC,                  // t_c [s]
+    C_DC, C_DS,            // Doppler [cycles/Hz] = dc cos(Phi_orb) + ds sin(Phi_orb)
+    C_RESP,                // 36 response trig-polynomial coefficients: R_A re, R_A im, R_E re, R_E im
+    C_COUNT = C_RESP + 36
+};
+
+// ---------------------------------------------------------------- double-double
+struct dd {
+    double hi, lo;
+};
+
+__device__ __forceinline__ dd two_sum(double a, double b)
+{
+    const double s = a + b;
+    const double bb = s - a;
+    const double e = (a - (s - bb)) + (b - bb);
+    return {s, e};
+}
+__device__ __forceinline__ dd fast_two_sum(double a, double b)
+{
+    const double s = a + b;
+    return {s, b - (s - a)};
+}
+__device__ __forceinline__ dd two_prod(double a, double b)
+{
+    const double p = a * b;
+    return {p, __builtin_fma(a, b, -p)};
+}
+__device__ __forceinline__ dd dd_mul(dd a, dd b)
+{
+    dd p = two_prod(a.hi, b.hi);
+    p.lo = __builtin_fma(a.hi, b.lo, __builtin_fma(a.lo, b.hi, p.lo));
+    return fast_two_sum(p.hi, p.lo);
+}
+__device__ __forceinline__ dd dd_mul_d(dd a, double b)
+{
+    dd p = two_prod(a.hi, b);
+    p.lo = __builtin_fma(a.lo, b, p.lo);
+    return fast_two_sum(p.hi, p.lo);
+}
+__device__ __forceinline__ dd dd_add(dd a, dd b)
+{
+    dd s = two_sum(a.hi, b.hi);
+    s.lo += a.lo + b.lo;
+    return fast_two_sum(s.hi, s.lo);
+}
+// exact rational constant p/q as double-double
+__device__ __forceinline__ dd dd_ratio(double p, double q)
+{
+    const double hi = p / q;
+    const double lo = __builtin_fma(-hi, q, p) / q;
+    return {hi, lo};
+}
+// fractional part of a double-double in [-0.5, 0.5)
+__device__ __forceinline__ double dd_frac(dd a)
+{
+    const double r = a.hi - rint(a.hi);  // exact
+    const double s = r + a.lo;
+    return s - rint(s);
+}
+
+// x^(-5/3) and x^(-8/3) in double-double for double-double x (one Newton
+// step on y^3 x^5 = 1, resp. y^3 x^8 = 1, from the double estimate).
+__device__ inline dd dd_pow_m53(dd x)
+{
+    const double y0 = pow(x.hi, -5.0 / 3.0);
+    const dd x2 = dd_mul(x, x);
+    const dd x5 = dd_mul(dd_mul(x2, x2), x);
+    const dd y3 = dd_mul_d(two_prod(y0, y0), y0);
+    const dd pr = dd_mul(y3, x5);
+    const double r = (pr.hi - 1.0) + pr.lo;
+    return two_sum(y0, -y0 * r * (1.0 / 3.0));
+}
+__device__ inline dd dd_pow_m83(dd x)
+{
+    const double y0 = pow(x.hi, -8.0 / 3.0);
+    const dd x2 = dd_mul(x, x);
+    const dd x4 = dd_mul(x2, x2);
+    const dd x8 = dd_mul(x4, x4);
+    const dd y3 = dd_mul_d(two_prod(y0, y0), y0);
+    const dd pr = dd_mul(y3, x8);
+    const double r = (pr.hi - 1.0) + pr.lo;
+    return two_sum(y0, -y0 * r * (1.0 / 3.0));
+}
+
+// ---------------------------------------------------------------- sin/cos(2 pi r)
+// r in cycles (|r| < 2^40).  Quarter-turn reduction, then Taylor series of
+// sin and cos on |x| <= pi/4 truncated after x^15 and x^16 (remainders below
+// 1e-16); the quadrant swaps and negates the pair.
+__device__ __forceinline__ void sincos2pi(double r, double* s_out, double* c_out)
+{
+    const double q = rint(4.0 * r);
+    const double t = __builtin_fma(q, -0.25, r);
+    const double x = t * kTwoPi;
+    const double x2 = x * x;
+    double ps = -7.6471637318198164759e-13;  // -1/15!
+    ps = __builtin_fma(ps, x2, 1.6059043836821614599e-10);   // 1/13!
+    ps = __builtin_fma(ps, x2, -2.5052108385441718775e-8);   // -1/11!
+    ps = __builtin_fma(ps, x2, 2.7557319223985890653e-6);    // 1/9!
+    ps = __builtin_fma(ps, x2, -1.9841269841269841270e-4);   // -1/7!
+    ps = __builtin_fma(ps, x2, 8.3333333333333333333e-3);    // 1/5!
+    ps = __builtin_fma(ps, x2, -1.6666666666666666667e-1);   // -1/3!
+    const double sn = __builtin_fma(x * x2, ps, x);
+    double pc = 4.7794773323873852974e-14;  // 1/16!
+    pc = __builtin_fma(pc, x2, -1.1470745597729724714e-11);  // -1/14!
+    pc = __builtin_fma(pc, x2, 2.0876756987868098979e-9);    // 1/12!
+    pc = __builtin_fma(pc, x2, -2.7557319223985890653e-7);   // -1/10!
+    pc = __builtin_fma(pc, x2, 2.4801587301587301587e-5);    // 1/8!
+    pc = __builtin_fma(pc, x2, -1.3888888888888888889e-3);   // -1/6!
+    pc = __builtin_fma(pc, x2, 4.1666666666666666667e-2);    // 1/4!
+    pc = __builtin_fma(pc, x2, -0.5);
+    const double cs = __builtin_fma(x2, pc, 1.0);
+    const int iq = ((int)q) & 3;
+    const double s1 = (iq & 1) ? cs : sn;
+    const double c1 = (iq & 1) ? sn : cs;
+    *s_out = (iq & 2) ? -s1 : s1;
+    *c_out = ((iq + 1) & 2) ? -c1 : c1;
+}
+
+// ---------------------------------------------------------------- response
+// Polarisation vectors for sky direction (lambda, beta) and angle psi.
+struct Pol {
+    double P[3], Q[3];
+};
+__device__ inline Pol polarisation(double lam, double bet, double psi)
+{
+    double sl, cl, sb, cb, sp, cp;
+    sincos(lam, &sl, &cl);
+    sincos(bet, &sb, &cb);
+    sincos(psi, &sp, &cp);
+    const double u[3] = {sb * cl, sb * sl, -cb};
+    const double v[3] = {sl, -cl, 0.0};
+    Pol o;
+    for (int i = 0; i < 3; ++i) {
+        o.P[i] = cp * u[i] + sp * v[i];
+        o.Q[i] = -sp * u[i] + cp * v[i];
+    }
+    return o;
+}
+
+// Antenna patterns at constellation orbital angle Phi.  For an arm with unit
+// vector n, n.e+.n = (n.P)^2 - (n.Q)^2 and n.ex.n = 2 (n.P)(n.Q).  With
+// q_ab the arm forms, F_X = (q01 - q02)/2 (and cyclic), hence
+// F_A = (2 q02 - q01 - q12) / (2 sqrt2) and F_E = 3 (q01 - q12) / (2 sqrt6).
+// out[0] = F+_A, out[1] = Fx_A, out[2] = F+_E, out[3] = Fx_E.
+__device__ inline void antenna_lf(double Phi, double cart0, const Pol& pol, double out[4])
+{
+    double sP, cP;
+    sincos(Phi, &sP, &cP);
+    const double h3 = 0.86602540378443864676;  // sqrt(3)/2
+    // in-plane orthonormal pair: e1 = -r/2 - (sqrt3/2) z, e2 = phi-hat
+    const double e1[3] = {-0.5 * cP, -0.5 * sP, -h3};
+    const double e2[3] = {-sP, cP, 0.0};
+    double s[3][3];
+    for (int a = 0; a < 3; ++a) {
+        double st, ct;
+        sincos(cart0 - Phi + kTwoPi * a / 3.0, &st, &ct);
+        for (int i = 0; i < 3; ++i) s[a][i] = ct * e1[i] + st * e2[i];
+    }
+    const double inv_r3 = 0.57735026918962576451;  // 1/sqrt(3): chord between craft
+    double qp[3], qx[3];                             // arms 01, 02, 12
+    const int A0[3] = {0, 0, 1}, A1[3] = {1, 2, 2};
+    for (int k = 0; k < 3; ++k) {
+        double n[3];
+        for (int i = 0; i < 3; ++i) n[i] = (s[A1[k]][i] - s[A0[k]][i]) * inv_r3;
+        const double a = n[0] * pol.P[0] + n[1] * pol.P[1] + n[2] * pol.P[2];
+        const double b = n[0] * pol.Q[0] + n[1] * pol.Q[1] + n[2] * pol.Q[2];
+        qp[k] = a * a - b * b;
+        qx[k] = 2.0 * a * b;
+    }
+    const double ka = 0.35355339059327376220;  // 1/(2 sqrt2)
+    const double ke = 0.61237243569579452455;  // 3/(2 sqrt6)
+    out[0] = ka * (2.0 * qp[1] - qp[0] - qp[2]);
+    out[1] = ka * (2.0 * qx[1] - qx[0] - qx[2]);
+    out[2] = ke * (qp[0] - qp[2]);
+    out[3] = ke * (qx[0] - qx[2]);
+}
+
+// Evaluate a degree-4 trigonometric polynomial c[0] + sum_k c[k] cos kPhi + c[4+k] sin kPhi
+// given the harmonics (ch[k], sh[k]) = (cos kPhi, sin kPhi), k = 1..4.
+__device__ __forceinline__ double trig4(const double* c, const double* ch, const double* sh)
+{
+    double v = c[0];
+#pragma unroll
+    for (int k = 1; k <= 4; ++k) v = __builtin_fma(c[k], ch[k], __builtin_fma(c[4 + k], sh[k], v));
+    return v;
+}
+
+__device__ __forceinline__ void harmonics(double c1, double s1, double* ch, double* sh)
+{
+    ch[1] = c1;
+    sh[1] = s1;
+    ch[2] = c1 * c1 - s1 * s1;
+    sh[2] = 2.0 * c1 * s1;
+    ch[3] = ch[2] * c1 - sh[2] * s1;
+    sh[3] = sh[2] * c1 + ch[2] * s1;
+    ch[4] = ch[2] * ch[2] - sh[2] * sh[2];
+    sh[4] = 2.0 * ch[2] * sh[2];
+}
+
+}  // namespace scs

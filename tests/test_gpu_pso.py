@@ -1,0 +1,106 @@
+"""PSO kernels (move, best update, whole step) against the oracle, bit for bit."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from tests import datasets as D
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2408_13170_amd import B  # noqa: E402
+
+LO, HI, PER = synth.GW150914_PRIOR_LO, synth.GW150914_PRIOR_HI, synth.PERIODIC
+
+
+def _t(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def test_pso_move_bitwise():
+    rng = np.random.default_rng(0)
+    P = 1000
+    th = O.pso_init(P, LO, HI, 5, 2)
+    v = rng.normal(size=(P, 7)) * (HI - LO) * 0.05
+    v[:10] = 0.0  # zero velocities with zero pulls exercise the random-sign branch
+    pb = O.pso_init(P, LO, HI, 6, 2)
+    pb[:10] = th[:10]
+    gb = th[10].copy()
+    eps = np.array([0.01, 0.05, 1e-8, 0.01, 0.01, 0.2, 0.1])
+    prm = B.pso_params(0.5, 0.2, 0.4, eps)
+    tt, vt, pt, gt = _t(th), _t(v), _t(pb), _t(gb)
+    B.scs_pso_move(tt, vt, pt, gt, prm, LO, HI, PER, 5, 2, 9)
+    torch.cuda.synchronize()
+    O.pso_move(th, v, pb, gb, 0.5, 0.2, 0.4, eps, LO, HI, PER, 5, 2, 9)
+    assert np.array_equal(tt.cpu().numpy(), th)
+    assert np.array_equal(vt.cpu().numpy(), v)
+
+
+def test_pso_best_bitwise():
+    rng = np.random.default_rng(1)
+    P = 3000
+    th = O.pso_init(P, LO, HI, 7, 0)
+    th[:20, 0] = 31.0  # out of the box: never a best
+    vals = rng.normal(size=P) * 10 + 50
+    vals[5] = np.nan
+    vals[100] = vals[200] = vals.max() + 1  # tie: the lower index wins
+    pbv = rng.normal(size=P) * 10 + 45
+    pb = O.pso_init(P, LO, HI, 8, 0)
+    gb = pb[0].copy()
+    gv = 40.0
+    tt, vv, pbt, pvt, gbt = _t(th), _t(vals), _t(pb), _t(pbv), _t(gb)
+    gvt = _t(np.array([gv]))
+    B.scs_pso_best(tt, vv, LO, HI, PER, pbt, pvt, gbt, gvt)
+    torch.cuda.synchronize()
+    gv2 = O.pso_best(th, vals, LO, HI, PER, pb, pbv, gb, gv)
+    assert np.array_equal(pbt.cpu().numpy(), pb)
+    assert np.array_equal(pvt.cpu().numpy(), pbv)
+    assert np.array_equal(gbt.cpu().numpy(), gb) and gvt.cpu().numpy()[0] == gv2
+
+
+def test_swarm_steps_and_checkpoint_resume():
+    """Initial positions equal the oracle's Philox draw; a resumed swarm
+    continues bit for bit like an uninterrupted one."""
+    ds = D.lisa_small(seed=6)
+    g = ds.grid
+    P = 256
+    h = B.scs_ctx_create(0)
+    try:
+        B.scs_load_data(h, np.ascontiguousarray(ds.d_ri), np.ascontiguousarray(ds.psd), g.k0 * g.df, g.df)
+        B.scs_set_model(h, 7, 1, 1, ds.model.t_obs)
+        B.scs_define_segmentation(h, 8, B.SCS_SEG_EQUAL_SNR, 16)
+        sw = B.scs_swarm_create(h, P, LO, HI, PER, seed=11, swarm_id=3)
+        st0 = B.scs_swarm_read(sw, P)
+        assert np.array_equal(st0["theta"], O.pso_init(P, LO, HI, 11, 3))
+        prm = B.pso_params(0.5, 0.2, 0.3, [0.1, 0.05, 5e-8, 0.1, 0.1, 0.2, 0.1])
+        for _ in range(3):
+            B.scs_pso_step(sw, prm)
+        mid = B.scs_swarm_read(sw, P)
+        for _ in range(3):
+            B.scs_pso_step(sw, prm)
+        end = B.scs_swarm_read(sw, P)
+        sw2 = B.scs_swarm_create(h, P, LO, HI, PER, seed=11, swarm_id=3)
+        B.scs_swarm_write(sw2, mid)
+        for _ in range(3):
+            B.scs_pso_step(sw2, prm)
+        end2 = B.scs_swarm_read(sw2, P)
+        for k in ("theta", "vel", "pbest", "pbest_val", "gbest"):
+            assert np.array_equal(end[k], end2[k]), k
+        assert end["gbest_val"] == end2["gbest_val"] and end["iteration"] == 6
+        assert end["gbest_val"] >= mid["gbest_val"]
+        # one move reproduced by the oracle from the read-back state
+        th, v, pb = mid["theta"].copy(), mid["vel"].copy(), mid["pbest"].copy()
+        O.pso_move(th, v, pb, mid["gbest"], 0.5, 0.2, 0.3, [0.1, 0.05, 5e-8, 0.1, 0.1, 0.2, 0.1], LO, HI, PER,
+                   11, 3, 3)
+        st = B.scs_swarm_read(sw, P)
+        B.scs_swarm_destroy(sw)
+        B.scs_swarm_destroy(sw2)
+        sw3 = B.scs_swarm_create(h, P, LO, HI, PER, seed=11, swarm_id=3)
+        B.scs_swarm_write(sw3, mid)
+        B.scs_pso_step(sw3, prm)
+        st3 = B.scs_swarm_read(sw3, P)
+        assert np.array_equal(st3["theta"], th) and np.array_equal(st3["vel"], v)
+        B.scs_swarm_destroy(sw3)
+    finally:
+        B.scs_ctx_destroy(h)
