@@ -1,0 +1,216 @@
+"""Benchmark: particle x frequency-bin evaluations of the semi-coherent
+statistic per second on one MI355X.
+
+A step is one iteration of the search's hot path over the whole swarm: the
+PSO move of 10^4 particles, the per-particle prologue (coefficients, support
+window, equal-[h|h] edges), the generate-and-reduce over the data, the
+finalize to Upsilon_N, and the best update.  Workload: 2^20 bins over
+[0.016, 0.032) Hz (T_obs ~ 2.08 yr), A+E channels, two-component instrument
+PSD, synthetic Gaussian noise plus a GW150914-like 3.5PN inspiral with the
+low-frequency response at SNR 17, N = 1024 equal-[h|h] segments (node
+stride 1024), particles uniform in the GW150914-like prior box.
+
+Prints one JSON line.  value = in-support particle-bin evaluations per second
+in FP64 (mixed precision reported beside it).
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+# FP64 operations per in-support particle-bin of the generate-and-reduce
+# kernel, two channels, from its per-bin op list (a fused multiply-add counts
+# 2, any other arithmetic op 1; roundings and conversions 0): bin coordinate
+# 1 mul; phase polynomial 5 FMA; reduction to [-1/2, 1/2] 1 add; sin/cos of
+# 2 pi r: scale 1, table offset 1 FMA, to radians 1 mul, x^2 1 mul, sine 2
+# FMA + 1 mul, cosine 3 FMA, angle sum 2 FMA + 2 mul; response polynomials
+# 20 FMA; data x conj(response) 6 FMA + 2 mul; Z rotation-accumulate 4 FMA;
+# H 4 FMA + 2 mul.  Total 42 FMA + 12 other = 96 + 10 = 106 (the FP64 flop
+# counter of rocprofv3 reads 108 per in-support evaluation, the excess being
+# lanes idle at support edges and the per-sub-block set-up).
+FLOP_PER_EVAL_FP64 = 106
+PEAK_FP64_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 64 lanes x 2
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (counter calibration) and exit")
+    args = ap.parse_args()
+    if args.copy_probe_mib:
+        import torch
+
+        src = torch.ones(args.copy_probe_mib << 17, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_each_way": src.numel() * 8, "copies": 3}))
+        return
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); every GPU box here has one GPU and the "
+              "multi-GPU path (particle sharding) is a design, not a build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2408_13170_amd import B
+
+    dev = torch.device("cuda:0")
+    w = synth.workload("lisa1m")
+    K, df, f_min = w.grid.K, w.grid.df, w.grid.f_min
+    psd = synth.psd_arrays(w)
+    noise = synth.noise(psd, df, w.seed)
+    # --- data: noise + injection made with the library's own FP64 template
+    ctx = B.scs_ctx_create(0)
+    zeros = np.zeros((2, K, 2))
+    B.scs_load_data(ctx, zeros, psd, f_min, df)
+    B.scs_set_model(ctx, w.pn_order, B.SCS_RESP_LISA_LF_AE, B.SCS_SUPPORT_TOBS, w.grid.t_obs)
+    h = torch.empty((2, K, 2), dtype=torch.float64, device=dev)
+    B.scs_waveform(ctx, torch.tensor(w.injection, device=dev), h)
+    torch.cuda.synchronize()
+    hc = torch.complex(h[..., 0], h[..., 1])
+    S = torch.tensor(psd, device=dev)
+    hh = float(4 * df * torch.sum(hc.abs() ** 2 / S))
+    d = torch.tensor(noise, device=dev) + hc * (w.snr / math.sqrt(hh))
+    d_ri = torch.stack([d.real, d.imag], -1).contiguous()
+    B.scs_load_data(ctx, d_ri, S.contiguous(), f_min, df)
+    B.scs_set_model(ctx, w.pn_order, B.SCS_RESP_LISA_LF_AE, B.SCS_SUPPORT_TOBS, w.grid.t_obs)
+    B.scs_define_segmentation(ctx, w.N, B.SCS_SEG_EQUAL_SNR, w.G)
+    del h, hc, d
+    # --- swarm of 10^4 particles, first rung of the ladder (Table tab:PSO_hyperparams, N = 100 row)
+    eps = [0.1, 0.05, 5e-8, 0.1, 0.1, 0.2, 0.1]  # Mc, eta, f_low, lambda, beta, iota, psi
+    prm = B.pso_params(0.5, 0.2, 0.3, eps)
+    stream = torch.cuda.current_stream()
+
+    def run(prec, steps, warmup, swarm_seed):
+        sw = B.scs_swarm_create(ctx, w.P, w.prior_lo, w.prior_hi, synth.PERIODIC, seed=swarm_seed, swarm_id=0)
+        for _ in range(warmup):
+            B.scs_pso_step(sw, prm, prec, stream)
+        torch.cuda.synchronize()
+        B.scs_ctx_stats(ctx, reset=True)
+        B.scs_ctx_profile(ctx, 1)
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        evs[0].record(stream)
+        for i in range(steps):
+            B.scs_pso_step(sw, prm, prec, stream)
+            evs[i + 1].record(stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        n_launch, main_ms = B.scs_ctx_profile(ctx, 0)
+        ev_support, ev_band, unresolved = B.scs_ctx_stats(ctx, reset=True)
+        step_ms = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(steps)])
+        st = B.scs_swarm_read(sw, w.P)
+        B.scs_swarm_destroy(sw)
+        return {"wall_s": t1 - t0, "evals": ev_support, "unresolved": unresolved, "step_ms": step_ms,
+                "main_ms": main_ms, "main_launches": n_launch, "gbest": st["gbest_val"]}
+
+    r64 = run(B.SCS_PREC_FP64, args.steps, args.warmup, 101)
+    log(f"fp64: {r64['evals'] / r64['wall_s']:.4g} evals/s, step p50 {np.median(r64['step_ms']):.3f} ms, "
+        f"main kernel {r64['main_ms'] / max(r64['main_launches'], 1):.3f} ms/launch, best {r64['gbest']:.2f}")
+    rmx = None
+    if not args.no_mixed:
+        rmx = run(B.SCS_PREC_MIXED, args.steps, args.warmup, 101)
+        log(f"mixed: {rmx['evals'] / rmx['wall_s']:.4g} evals/s, step p50 {np.median(rmx['step_ms']):.3f} ms")
+    # --- mixed vs FP64 on one fixed swarm position
+    th = torch.tensor(synth.workload_particles(w, seed=w.seed + 7), device=dev)
+    u64 = torch.empty(w.P, dtype=torch.float64, device=dev)
+    u32 = torch.empty(w.P, dtype=torch.float64, device=dev)
+    B.scs_evaluate(ctx, th, u64, B.SCS_PREC_FP64)
+    B.scs_evaluate(ctx, th, u32, B.SCS_PREC_MIXED)
+    torch.cuda.synchronize()
+    a, b = u64.cpu().numpy(), u32.cpu().numpy()
+    ok = np.isfinite(a)
+    err = np.abs(b[ok] - a[ok]) / np.maximum(np.abs(a[ok]), 2.0 * w.N)
+
+    value = r64["evals"] / r64["wall_s"]
+    ms_step = 1e3 * r64["wall_s"] / args.steps
+    avg_main_ms = r64["main_ms"] / max(r64["main_launches"], 1)
+    evals_per_launch = r64["evals"] / max(r64["main_launches"], 1)
+    achieved = evals_per_launch * FLOP_PER_EVAL_FP64 / (avg_main_ms * 1e-3) / 1e12
+    out = {
+        "metric": "particle x freq-bin statistic evals/s (in-support), FP64; p50/p99 step latency; mixed vs FP64",
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic: seeded Gaussian noise from the two-component LISA PSD + GW150914-like 3.5PN injection",
+        "config": {"workload": "A+E, 2^20 bins over [0.016,0.032) Hz, T_obs 2.08 yr, N_seg 1024 (equal [h|h], "
+                               "node stride 1024), 10^4 PSO particles in the GW150914-like prior box, one PSO "
+                               "iteration per step", "particles": w.P, "bins": K, "N_seg": w.N},
+        "latency_ms": {"p50": float(np.median(r64["step_ms"])), "p99": float(np.quantile(r64["step_ms"], 0.99))},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "kernel": "k_main<2,false> (FP64 generate-and-reduce)",
+                     "avg_launch_ms": avg_main_ms, "flop_per_eval": FLOP_PER_EVAL_FP64,
+                     "evals_per_launch": evals_per_launch},
+        "unresolved_particles": r64["unresolved"],
+    }
+    if rmx is not None:
+        out["mixed"] = {"value": rmx["evals"] / rmx["wall_s"], "unit": "evals/s",
+                        "ms_per_step": 1e3 * rmx["wall_s"] / args.steps,
+                        "latency_ms": {"p50": float(np.median(rmx["step_ms"])),
+                                       "p99": float(np.quantile(rmx["step_ms"], 0.99))},
+                        "avg_main_launch_ms": rmx["main_ms"] / max(rmx["main_launches"], 1),
+                        "speedup_vs_fp64": (rmx["evals"] / rmx["wall_s"]) / value,
+                        "err_vs_fp64": {"median": float(np.median(err)), "p99": float(np.quantile(err, 0.99)),
+                                        "max": float(err.max()),
+                                        "measure": "|U_mixed - U_fp64| / max(U_fp64, 2N)"}}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, psd, d_ri.cpu().numpy(), args.cpu_seconds)
+    B.scs_ctx_destroy(ctx)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(w, psd, d_ri, seconds):
+    """The CPU oracle, as it stands, on a bounded sample of the same workload:
+    particles from the same prior box, evaluated in batches on every host
+    thread until about `seconds` of wall time."""
+    import oracle as O
+
+    g = O.Grid(w.grid.K, w.grid.k0, w.grid.df, 2)
+    m = O.Model(pn_order=w.pn_order, response=O.RESP_LISA_LF_AE, support=O.SUPPORT_TOBS, t_obs=w.grid.t_obs)
+    th_all = synth.workload_particles(w, seed=w.seed + 11)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    evals, used, t = 0, 0, 0.0
+    batch = max(threads, 8)
+    while t < seconds and used + batch <= th_all.shape[0] and used < 512:
+        th = th_all[used:used + batch]
+        t0 = time.perf_counter()
+        out = O.evaluate(g, m, d_ri, psd, th, w.N, O.SEG_EQUAL_SNR, w.G, n_threads=threads)
+        t += time.perf_counter() - t0
+        evals += int((out["support"][:, 1] - out["support"][:, 0]).sum())
+        used += batch
+    return {"value": evals / t, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{used} particles of the same workload (full 2^20-bin grid, N_seg 1024), {t:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

@@ -92,6 +92,13 @@ static int device_setup(int device)
     double x[kNodes], m[kNodes * kNodes];
     cheb_matrix(x, m);
     HIP_TRY(upload_cheb(x, m));
+    std::vector<double> trig(2 * kTrig);
+    for (int i = 0; i < kTrig; ++i) {
+        const long double a = 2.0L * 3.141592653589793238462643383279502884L * i / kTrig;
+        trig[2 * i] = (double)cosl(a);
+        trig[2 * i + 1] = (double)sinl(a);
+    }
+    HIP_TRY(upload_trig(trig.data()));
     g_dev_ready[device] = true;
     return SCS_OK;
 }
@@ -127,6 +134,13 @@ struct Workspace {
     double* stage = nullptr;
     int64_t P_last = 0;
     int N_last = 0;
+    // support-order permutation (radix sort of (k_hi, k_lo))
+    int64_t capSort = 0;
+    uint64_t* keys = nullptr;  // [2P]
+    int32_t* idx = nullptr;    // [P]
+    int32_t* perm = nullptr;   // [P]
+    int64_t capTemp = 0;
+    unsigned char* temp = nullptr;
 };
 
 struct TuneChoice {
@@ -208,6 +222,10 @@ static void free_ws(Workspace& w)
     hipFree(w.bounds);
     hipFree(w.rec);
     hipFree(w.stage);
+    hipFree(w.keys);
+    hipFree(w.idx);
+    hipFree(w.perm);
+    hipFree(w.temp);
     w = Workspace();
 }
 
@@ -434,11 +452,14 @@ static Plan make_plan(const scs_ctx* c, int64_t P, const TuneChoice& t)
 
 static int64_t pad64(int64_t v) { return (v + 63) / 64 * 64; }
 
+// Swarms of at least this many particles are evaluated in support order.
+static constexpr int64_t kSortMin = 128;
+
 static size_t ws_bytes(const scs_ctx* c, int64_t P, int N, const Plan& pl)
 {
     const int64_t Pp = pad64(std::max<int64_t>(P, 1));
     size_t b = 0;
-    b += sizeof(double) * (size_t)C_COUNT * Pp;
+    b += sizeof(double) * (size_t)kCoefStride * Pp;
     b += (sizeof(int32_t) * 2 + 1) * (size_t)Pp;
     b += sizeof(int32_t) * (size_t)P * (N + 1);
     b += sizeof(double) * (size_t)pl.n_chunks * 7 * Pp;
@@ -457,7 +478,7 @@ static int ensure_ws(scs_ctx* c, Workspace& w, int64_t P, int N, const Plan& pl)
         w.coef = nullptr;
         w.klo = w.khi = nullptr;
         w.lg = nullptr;
-        if (hipMalloc((void**)&w.coef, sizeof(double) * C_COUNT * Pp) != hipSuccess ||
+        if (hipMalloc((void**)&w.coef, sizeof(double) * kCoefStride * Pp) != hipSuccess ||
             hipMalloc((void**)&w.klo, sizeof(int32_t) * Pp) != hipSuccess ||
             hipMalloc((void**)&w.khi, sizeof(int32_t) * Pp) != hipSuccess ||
             hipMalloc((void**)&w.lg, Pp) != hipSuccess) {
@@ -468,6 +489,19 @@ static int ensure_ws(scs_ctx* c, Workspace& w, int64_t P, int N, const Plan& pl)
     }
     if ((rc = grow(&w.bounds, &w.capBounds, P * (int64_t)(N + 1)))) return rc;
     if ((rc = grow(&w.rec, &w.capRec, pl.n_chunks * 7 * w.capP))) return rc;
+    if (P >= kSortMin && P > w.capSort) {
+        int64_t c1 = 0, c2 = 0, c3 = 0;
+        hipFree(w.keys);
+        hipFree(w.idx);
+        hipFree(w.perm);
+        w.keys = nullptr;
+        w.idx = w.perm = nullptr;
+        w.capSort = 0;
+        if ((rc = grow(&w.keys, &c1, 2 * w.capP)) || (rc = grow(&w.idx, &c2, w.capP)) || (rc = grow(&w.perm, &c3, w.capP)))
+            return rc;
+        w.capSort = w.capP;
+        if ((rc = grow(&w.temp, &w.capTemp, (int64_t)sort_temp_bytes(w.capP)))) return rc;
+    }
     return SCS_OK;
 }
 
@@ -497,6 +531,14 @@ static int run_eval(scs_ctx* c, Workspace& w, int64_t P, int N, const double* th
     pa.evals = c->counters;
     pa.unresolved = c->counters + 2;
     launch_prologue(pa, s);
+    const int32_t* perm = nullptr;
+    if (P >= kSortMin && w.perm) {
+        int kb = 32;
+        while (kb < 64 && ((int64_t)1 << (kb - 32)) <= c->g.K) ++kb;
+        hipError_t e = launch_sort_perm(P, w.klo, w.khi, w.keys, w.idx, w.perm, w.temp, (size_t)w.capTemp, kb, s);
+        if (e != hipSuccess) return fail(SCS_EDEVICE, "support sort failed: %s", hipGetErrorString(e));
+        perm = w.perm;
+    }
     BoundArgs ba{};
     ba.g = c->g;
     ba.m = c->m;
@@ -536,6 +578,7 @@ static int run_eval(scs_ctx* c, Workspace& w, int64_t P, int N, const double* th
     ma.b32 = c->b32;
     ma.gtab = c->gtab;
     for (int l = 0; l < kMaxLevel; ++l) ma.gtab_off[l] = c->gtab_off[l];
+    ma.perm = perm;
     ma.rec = w.rec;
     ma.seg = seg;
     ma.zscale32 = c->zscale32;
@@ -564,6 +607,7 @@ static int run_eval(scs_ctx* c, Workspace& w, int64_t P, int N, const double* th
     fa.khi = w.khi;
     fa.lg = w.lg;
     fa.bounds = w.bounds;
+    fa.perm = perm;
     fa.rec = w.rec;
     fa.ups = ups;
     fa.seg = seg;

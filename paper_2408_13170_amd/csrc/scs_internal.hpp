@@ -12,6 +12,8 @@ constexpr int kGStride = 56;  // doubles per basis-table entry: 8 functions x 6 
 constexpr int kGHi = 48;
 constexpr int kGLo = 49;
 constexpr int kMaxLevel = 10;  // sub-block lengths 2^3 .. 2^9
+constexpr int kTrig = 256;        // entries of the (cos, sin)(2 pi i / kTrig) table
+constexpr int kCoefStride = 56;  // doubles per particle record of the coefficient buffer
 
 struct GridArgs {
     int64_t K;
@@ -88,7 +90,8 @@ struct MainArgs {
     const float* b32;
     const double* gtab;            // basis tables of every level
     int64_t gtab_off[kMaxLevel];   // entry offset of level lg
-    double* rec;           // [chunk][7][rec_stride]
+    const int32_t* perm;   // slot -> particle (relative to p0), or null for identity
+    double* rec;           // [chunk][7][rec_stride], indexed by slot
     double* seg;           // [P][N][3] or null
     double zscale32;       // FP32 tables hold u * sqrt(s), q * s: Z32 * zscale32 = Z, H32 * hscale32 = H
     double hscale32;
@@ -106,6 +109,7 @@ struct FinalArgs {
     const int32_t* khi;
     const int8_t* lg;
     const int32_t* bounds;
+    const int32_t* perm;  // as in MainArgs
     const double* rec;
     double* ups;  // [P_end - p0]
     double* seg;
@@ -121,6 +125,7 @@ struct PsoParams {
 };
 
 hipError_t upload_cheb(const double* x, const double* m);
+hipError_t upload_trig(const double* cs);
 void launch_bins(const GridArgs& g, const double* d_ri, const double* psd, double* b64, float* b32, double su,
                  double sq, hipStream_t s);
 void launch_prologue(const PrologueArgs& a, hipStream_t s);
@@ -135,6 +140,9 @@ void launch_pso_move(int64_t P, const PsoBox& box, const PsoParams& prm, uint64_
                      double* theta, double* vel, const double* pbest, const double* gbest, hipStream_t s);
 void launch_pso_best(int64_t P, const PsoBox& box, const double* theta, const double* vals, double* pbest,
                      double* pbest_val, double* gbest, double* gbest_val, hipStream_t s);
+size_t sort_temp_bytes(int64_t P);
+hipError_t launch_sort_perm(int64_t P, const int32_t* klo, const int32_t* khi, uint64_t* keys, int32_t* idx,
+                            int32_t* perm, void* temp, size_t temp_bytes, int key_bits, hipStream_t s);
 void launch_fill(double* p, int64_t n, double v, hipStream_t s);
 void launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
 

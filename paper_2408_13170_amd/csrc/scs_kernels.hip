@@ -12,6 +12,8 @@
 //                 term_n = 4 df |Z_n|^2 / H_n, Upsilon = sum_n    (a5)
 //   k_waveform    template on the grid for one theta (injections, parity)
 //   k_pso_*       particle-swarm move and best update              (a6)
+#include <hipcub/hipcub.hpp>
+
 #include "scs_internal.hpp"
 #include "scs_math.hpp"
 
@@ -21,6 +23,28 @@ namespace scs {
 // node values to monomial coefficients in x in [-1, 1].
 __constant__ double c_cheb_x[kNodes];
 __constant__ double c_cheb_m[kNodes * kNodes];
+// (cos, sin) of 2 pi i / kTrig, i = 0..kTrig-1, rounded from extended precision
+__device__ double2 g_trig[kTrig];
+
+// sin and cos of 2 pi r for |r| <= 1/2 (cycles) with the LDS table tab:
+// r = q / kTrig + s, |s| <= 1 / (2 kTrig); short Taylor polynomials in
+// x = 2 pi s (|x| <= pi / 256: remainders below 1e-17) and the angle sum.
+__device__ __forceinline__ void sincos2pi_tab(double r, const double2* tab, double* s_out, double* c_out)
+{
+    const double q = rint(r * (double)kTrig);
+    const int iq = ((int)q) & (kTrig - 1);
+    const double s = __builtin_fma(q, -1.0 / kTrig, r);
+    const double x = s * kTwoPi;
+    const double x2 = x * x;
+    const double sp = __builtin_fma(x2, 1.0 / 120.0, -1.0 / 6.0);
+    const double sn = __builtin_fma(x * x2, sp, x);
+    double cp = __builtin_fma(x2, -1.0 / 720.0, 1.0 / 24.0);
+    cp = __builtin_fma(x2, cp, -0.5);
+    const double cs = __builtin_fma(x2, cp, 1.0);
+    const double2 t = tab[iq];
+    *s_out = __builtin_fma(t.y, cs, t.x * sn);
+    *c_out = __builtin_fma(t.x, cs, -(t.y * sn));
+}
 
 // ============================================================== per-bin data
 // The FP32 copy is scaled (u by su = sqrt(s), q by sq = s, s ~ 1 / median q)
@@ -212,20 +236,20 @@ __global__ void k_prologue(PrologueArgs a)
                 }
             }
         }
-        for (int i = 0; i < 36; ++i) cf[(C_RESP + i) * S + p] = acc[i];
+        for (int i = 0; i < 36; ++i) cf[p * kCoefStride + (C_RESP + i)] = acc[i];
         double sl, cl;
         sincos(t[3], &sl, &cl);
         const double cb = cos(t[4]);
-        cf[C_DC * S + p] = -kAuOverC * cb * cl;
-        cf[C_DS * S + p] = -kAuOverC * cb * sl;
+        cf[p * kCoefStride + C_DC] = -kAuOverC * cb * cl;
+        cf[p * kCoefStride + C_DS] = -kAuOverC * cb * sl;
     }
-    cf[C_C0H * S + p] = c0.hi;
-    cf[C_C0L * S + p] = c0.lo;
-    for (int i = 1; i < 8; ++i) cf[(C_B1 + i - 1) * S + p] = b[i];
-    cf[C_PHIC * S + p] = phic;
-    cf[C_TAUH * S + p] = tau.hi;
-    cf[C_TAUL * S + p] = tau.lo;
-    cf[C_TC * S + p] = tcs;
+    cf[p * kCoefStride + C_C0H] = c0.hi;
+    cf[p * kCoefStride + C_C0L] = c0.lo;
+    for (int i = 1; i < 8; ++i) cf[p * kCoefStride + (C_B1 + i - 1)] = b[i];
+    cf[p * kCoefStride + C_PHIC] = phic;
+    cf[p * kCoefStride + C_TAUH] = tau.hi;
+    cf[p * kCoefStride + C_TAUL] = tau.lo;
+    cf[p * kCoefStride + C_TC] = tcs;
     a.klo[p] = (int32_t)klo;
     a.khi[p] = (int32_t)khi;
     a.lg[p] = (int8_t)lg;
@@ -300,11 +324,11 @@ __device__ inline void block_setup(const double* __restrict__ cf, int64_t S, int
                                    PhasePoly& out, RespPoly& resp)
 {
     const double h = (double)(1 << (lg - 1));
-    const double c0h = cf[C_C0H * S + p];
+    const double c0h = cf[p * kCoefStride + C_C0H];
     double ci[8];
     ci[0] = c0h;
 #pragma unroll
-    for (int i = 1; i < 8; ++i) ci[i] = cf[(C_B1 + i - 1) * S + p];
+    for (int i = 1; i < 8; ++i) ci[i] = cf[p * kCoefStride + (C_B1 + i - 1)];
     double a[kNodes];
 #pragma unroll
     for (int mm = 0; mm < kNodes; ++mm) a[mm] = 0.0;
@@ -318,11 +342,11 @@ __device__ inline void block_setup(const double* __restrict__ cf, int64_t S, int
     }
     {
         // constant term: frac(Kc tau) + frac(c0 f^-5/3) + frac(rest), cycles
-        const double tauh = cf[C_TAUH * S + p], taul = cf[C_TAUL * S + p];
+        const double tauh = cf[p * kCoefStride + C_TAUH], taul = cf[p * kCoefStride + C_TAUL];
         dd lin = two_prod(Kc, tauh);
         lin.lo = __builtin_fma(Kc, taul, lin.lo);
-        const dd n0 = dd_mul(dd{c0h, cf[C_C0L * S + p]}, dd{G[kGHi], G[kGLo]});
-        const double rest = a[0] + cf[C_PHIC * S + p];
+        const dd n0 = dd_mul(dd{c0h, cf[p * kCoefStride + C_C0L]}, dd{G[kGHi], G[kGLo]});
+        const double rest = a[0] + cf[p * kCoefStride + C_PHIC];
         const double c = dd_frac(lin) + dd_frac(n0) + (rest - rint(rest));
         a[0] = c - rint(c);
         a[1] += tauh + taul;
@@ -339,7 +363,7 @@ __device__ inline void block_setup(const double* __restrict__ cf, int64_t S, int
         for (int f = 0; f < 4; ++f)
 #pragma unroll
             for (int mm = 0; mm < kNodes; ++mm) resp.r[f][mm] = 0.0;
-        const double dcx = cf[C_DC * S + p], dsx = cf[C_DS * S + p];
+        const double dcx = cf[p * kCoefStride + C_DC], dsx = cf[p * kCoefStride + C_DS];
         const double inv_hdf = 1.0 / (h * g.df);
 #pragma unroll 1
         for (int n = 0; n < kNodes; ++n) {
@@ -362,11 +386,11 @@ __device__ inline void block_setup(const double* __restrict__ cf, int64_t S, int
 #pragma unroll
             for (int f = 0; f < 4; ++f) {
                 __asm__ volatile("" ::: "memory");  // nine coefficients live at a time
-                const double* cc = cf + (C_RESP + 9 * f) * S + p;
+                const double* cc = cf + p * kCoefStride + (C_RESP + 9 * f);
                 double rv = cc[0];
 #pragma unroll
                 for (int k = 1; k <= 4; ++k)
-                    rv = __builtin_fma(cc[k * S], ch[k], __builtin_fma(cc[(4 + k) * S], sh[k], rv));
+                    rv = __builtin_fma(cc[k], ch[k], __builtin_fma(cc[4 + k], sh[k], rv));
 #pragma unroll
                 for (int mm = 0; mm < kNodes; ++mm)
                     resp.r[f][mm] = __builtin_fma(c_cheb_m[mm * kNodes + n], rv, resp.r[f][mm]);
@@ -427,7 +451,7 @@ __device__ inline double weight_at(const double* __restrict__ cf, int64_t S, int
         double rv[4];
         for (int fi = 0; fi < 4; ++fi) {
             double cc[9];
-            for (int kk = 0; kk < 9; ++kk) cc[kk] = cf[(C_RESP + 9 * fi + kk) * S + p];
+            for (int kk = 0; kk < 9; ++kk) cc[kk] = cf[p * kCoefStride + (C_RESP + 9 * fi + kk)];
             rv[fi] = trig4(cc, ch, sh);
         }
         return b64[k * 6 + 4] * (rv[0] * rv[0] + rv[1] * rv[1]) + b64[k * 6 + 5] * (rv[2] * rv[2] + rv[3] * rv[3]);
@@ -454,9 +478,9 @@ __global__ __launch_bounds__(64) void k_bounds_equal(BoundArgs a)
     }
     const int64_t S = a.stride;
     double bcoef[8];
-    bcoef[0] = a.coef[C_C0H * S + p];
-    for (int i = 1; i < 8; ++i) bcoef[i] = a.coef[(C_B1 + i - 1) * S + p];
-    const double tc = a.coef[C_TC * S + p];
+    bcoef[0] = a.coef[p * kCoefStride + C_C0H];
+    for (int i = 1; i < 8; ++i) bcoef[i] = a.coef[p * kCoefStride + (C_B1 + i - 1)];
+    const double tc = a.coef[p * kCoefStride + C_TC];
     const int64_t G = a.G;
     const int64_t len = khi - klo;
     const int64_t nreg = (len - 1) / G + 1;
@@ -581,12 +605,25 @@ __device__ __forceinline__ int bsearch_seg(const int32_t* __restrict__ bo, int N
     return lo;
 }
 
+// Occupancy target: the per-sub-block set-up needs more registers than the
+// bin loop; capping the allocation lets four waves share a SIMD, the set-up
+// spilling to scratch while the bin loop stays in registers.
+// Measured on MI355X: three waves for the FP64 kernel, four for mixed.
+#ifndef SCS_WAVES_FP64
+#define SCS_WAVES_FP64 3
+#endif
+#ifndef SCS_WAVES_MIXED
+#define SCS_WAVES_MIXED 4
+#endif
 template <int NCH, bool MIXED>
-__global__ __launch_bounds__(256) void k_main(MainArgs a, const double* __restrict__ gtab)
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(MIXED ? SCS_WAVES_MIXED : SCS_WAVES_FP64))) void k_main(
+    MainArgs a, const double* __restrict__ gtab)
 {
     constexpr int NV = 3 * NCH;  // values per bin
     constexpr bool RESP = NCH == 2;
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double2 s_trig[MIXED ? 1 : kTrig];
     // ---- tile decode, XCD-aware: consecutive logical tiles (same chunk,
     //      neighbouring particle groups) land on the same XCD's L2.
     const int64_t nwg = a.n_tiles;
@@ -597,7 +634,9 @@ __global__ __launch_bounds__(256) void k_main(MainArgs a, const double* __restri
     const int64_t chunk = a.chunk0 + logical / a.n_groups;
     const int64_t group = logical % a.n_groups;
     const int tid = threadIdx.x;
-    const int64_t p = a.p0 + group * (int64_t)blockDim.x + tid;
+    // slot s in the support-sorted order; particle p = perm[s]
+    const int64_t s_idx = a.p0 + group * (int64_t)blockDim.x + tid;
+    const int64_t p = (a.perm && s_idx < a.P_end) ? a.p0 + a.perm[s_idx - a.p0] : s_idx;
     const int K = (int)a.g.K;
     const int cbins = a.L * a.CB;
     const int Kc = (int)chunk * cbins;
@@ -614,6 +653,10 @@ __global__ __launch_bounds__(256) void k_main(MainArgs a, const double* __restri
     hi = hi < Ke ? hi : Ke;
     const bool has = lo < hi;
     if (!__syncthreads_or(has)) return;
+    if constexpr (!MIXED) {
+        for (int i = tid; i < kTrig; i += blockDim.x) s_trig[i] = g_trig[i];
+        // made visible by the barrier before the first staged block
+    }
     const int64_t S = a.stride;
     const int N = a.N;
     const int32_t* __restrict__ bo = a.bounds + (p < a.P_end ? p : a.p0) * (int64_t)(N + 1);
@@ -635,7 +678,9 @@ __global__ __launch_bounds__(256) void k_main(MainArgs a, const double* __restri
     double zr = 0.0, zi = 0.0, hh = 0.0;
     float kzr = 0.f, kzi = 0.f, khh = 0.f, czr = 0.f, czi = 0.f, chh = 0.f;  // Kahan sums (mixed)
     double part = 0.0;
-    double hd0 = 0.0, hd1 = 0.0, hd2 = 0.0, tl0 = 0.0, tl1 = 0.0, tl2 = 0.0;
+    bool head_done = false;
+    const int64_t RS = a.rec_stride;
+    double* const recp = a.rec + (chunk - a.chunk0) * RS * 7 + (s_idx < a.P_end ? s_idx - a.p0 : 0);
     const double four_df = 4.0 * a.g.df;
     double* const seg = a.seg;
     // close segment n at bin k (exclusive) and move to the next non-empty one
@@ -648,9 +693,11 @@ __global__ __launch_bounds__(256) void k_main(MainArgs a, const double* __restri
             kzr = kzi = khh = czr = czi = chh = 0.f;
         }
         if (before) {
-            hd0 = fzr;
-            hd1 = fzi;
-            hd2 = fhh;
+            // head piece of a segment that started in an earlier chunk
+            recp[1 * RS] = fzr;
+            recp[2 * RS] = fzi;
+            recp[3 * RS] = fhh;
+            head_done = true;
         } else {
             if (fhh > 0.0) part += four_df * (fzr * fzr + fzi * fzi) / fhh;
             if (seg) {
@@ -762,7 +809,7 @@ __global__ __launch_bounds__(256) void k_main(MainArgs a, const double* __restri
                         double ph = horner5(poly.ph, x);
                         ph -= rint(ph);
                         double sn, cs;
-                        sincos2pi(ph, &sn, &cs);
+                        sincos2pi_tab(ph, s_trig, &sn, &cs);
                         const double* bin = reinterpret_cast<const double*>(smem) + jl * NV;
                         if constexpr (RESP) {
                             const double2 uA = *reinterpret_cast<const double2*>(bin);
@@ -850,6 +897,7 @@ __global__ __launch_bounds__(256) void k_main(MainArgs a, const double* __restri
     }
     // ---- close the chunk
     if (has) {
+        double tl0 = 0.0, tl1 = 0.0, tl2 = 0.0;
         if (nb <= hi) {
             flush(hi);
         } else {
@@ -860,33 +908,34 @@ __global__ __launch_bounds__(256) void k_main(MainArgs a, const double* __restri
                 fhh = ((double)khh - (double)chh) * a.hscale32;
             }
             if (before) {
-                hd0 = fzr;
-                hd1 = fzi;
-                hd2 = fhh;
+                recp[1 * RS] = fzr;  // middle piece: the segment spans the whole chunk
+                recp[2 * RS] = fzi;
+                recp[3 * RS] = fhh;
+                head_done = true;
             } else {
                 tl0 = fzr;
                 tl1 = fzi;
                 tl2 = fhh;
             }
         }
-        const int64_t RS = a.rec_stride;
-        const int64_t ci = chunk - a.chunk0;
-        double* rec = a.rec + ci * RS * 7 + (p - a.p0);
-        rec[0 * RS] = part;
-        rec[1 * RS] = hd0;
-        rec[2 * RS] = hd1;
-        rec[3 * RS] = hd2;
-        rec[4 * RS] = tl0;
-        rec[5 * RS] = tl1;
-        rec[6 * RS] = tl2;
+        if (!head_done) {
+            recp[1 * RS] = 0.0;
+            recp[2 * RS] = 0.0;
+            recp[3 * RS] = 0.0;
+        }
+        recp[0] = part;
+        recp[4 * RS] = tl0;
+        recp[5 * RS] = tl1;
+        recp[6 * RS] = tl2;
     }
 }
 
 // ============================================================== finalize
 __global__ void k_finalize(FinalArgs a)
 {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= a.P_end) return;
+    const int64_t s_idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + a.p0;  // slot of the main kernel
+    if (s_idx >= a.P_end) return;
+    const int64_t p = a.perm ? a.p0 + a.perm[s_idx - a.p0] : s_idx;
     const int N = a.N;
     const int lg = a.lg[p];
     double* seg = a.seg;
@@ -911,7 +960,7 @@ __global__ void k_finalize(FinalArgs a)
     const int64_t cb = a.cbins;
     const int64_t c_first = klo / cb, c_last = (khi - 1) / cb;
     const int64_t RS = a.rec_stride;
-    const double* rec = a.rec + (p - a.p0);
+    const double* rec = a.rec + (s_idx - a.p0);
     const double four_df = 4.0 * a.df;
     double sum = 0.0;
     for (int64_t c = c_first; c <= c_last; ++c) sum += rec[(c - a.chunk0) * RS * 7];
@@ -1148,6 +1197,10 @@ hipError_t upload_cheb(const double* x, const double* m)
     if (e != hipSuccess) return e;
     return hipMemcpyToSymbol(HIP_SYMBOL(c_cheb_m), m, sizeof(double) * kNodes * kNodes);
 }
+hipError_t upload_trig(const double* cs)
+{
+    return hipMemcpyToSymbol(HIP_SYMBOL(g_trig), cs, sizeof(double) * 2 * kTrig);
+}
 
 void launch_bins(const GridArgs& g, const double* d_ri, const double* psd, double* b64, float* b32, double su,
                  double sq, hipStream_t s)
@@ -1186,7 +1239,35 @@ void launch_main(const MainArgs& a, int waves, bool mixed, hipStream_t s)
 void launch_finalize(const FinalArgs& a, hipStream_t s)
 {
     const int64_t n = a.P_end - a.p0;
-    if (n > 0) hipLaunchKernelGGL(k_finalize, dim3(nblk(a.P_end, 128)), dim3(128), 0, s, a);
+    if (n > 0) hipLaunchKernelGGL(k_finalize, dim3(nblk(n, 128)), dim3(128), 0, s, a);
+}
+
+// Order particles by the end, then the start, of their support window so
+// that the 64 lanes of a wave cover nearly the same bins.
+__global__ void k_sort_keys(int64_t P, const int32_t* __restrict__ klo, const int32_t* __restrict__ khi,
+                            uint64_t* __restrict__ keys, int32_t* __restrict__ idx)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P) return;
+    keys[i] = ((uint64_t)(uint32_t)khi[i] << 32) | (uint64_t)(uint32_t)klo[i];
+    idx[i] = (int32_t)i;
+}
+
+size_t sort_temp_bytes(int64_t P)
+{
+    size_t bytes = 0;
+    hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const uint64_t*)nullptr, (uint64_t*)nullptr,
+                                       (const int32_t*)nullptr, (int32_t*)nullptr, (int)P, 0, 64);
+    return bytes;
+}
+
+hipError_t launch_sort_perm(int64_t P, const int32_t* klo, const int32_t* khi, uint64_t* keys, int32_t* idx,
+                            int32_t* perm, void* temp, size_t temp_bytes, int key_bits, hipStream_t s)
+{
+    if (P <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sort_keys, dim3(nblk(P, 256)), dim3(256), 0, s, P, klo, khi, keys, idx);
+    // keys[0..P) are sorted in place into keys[P..2P)
+    return hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys, keys + P, idx, perm, (int)P, 0, key_bits, s);
 }
 void launch_gtab(const GridArgs& g, int lg, int64_t nsub, double* tab, hipStream_t s)
 {
