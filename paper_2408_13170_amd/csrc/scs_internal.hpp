@@ -12,7 +12,7 @@ constexpr int kGStride = 56;  // doubles per basis-table entry: 8 functions x 6 
 constexpr int kGHi = 48;
 constexpr int kGLo = 49;
 constexpr int kMaxLevel = 10;  // sub-block lengths 2^3 .. 2^9
-constexpr int kTrig = 256;        // entries of the (cos, sin)(2 pi i / kTrig) table
+constexpr int kTrig = 1024;       // entries of the (cos, sin)(2 pi i / kTrig) table
 constexpr int kCoefStride = 56;  // doubles per particle record of the coefficient buffer
 
 struct GridArgs {

@@ -26,26 +26,6 @@ __constant__ double c_cheb_m[kNodes * kNodes];
 // (cos, sin) of 2 pi i / kTrig, i = 0..kTrig-1, rounded from extended precision
 __device__ double2 g_trig[kTrig];
 
-// sin and cos of 2 pi r for |r| <= 1/2 (cycles) with the LDS table tab:
-// r = q / kTrig + s, |s| <= 1 / (2 kTrig); short Taylor polynomials in
-// x = 2 pi s (|x| <= pi / 256: remainders below 1e-17) and the angle sum.
-__device__ __forceinline__ void sincos2pi_tab(double r, const double2* tab, double* s_out, double* c_out)
-{
-    const double q = rint(r * (double)kTrig);
-    const int iq = ((int)q) & (kTrig - 1);
-    const double s = __builtin_fma(q, -1.0 / kTrig, r);
-    const double x = s * kTwoPi;
-    const double x2 = x * x;
-    const double sp = __builtin_fma(x2, 1.0 / 120.0, -1.0 / 6.0);
-    const double sn = __builtin_fma(x * x2, sp, x);
-    double cp = __builtin_fma(x2, -1.0 / 720.0, 1.0 / 24.0);
-    cp = __builtin_fma(x2, cp, -0.5);
-    const double cs = __builtin_fma(x2, cp, 1.0);
-    const double2 t = tab[iq];
-    *s_out = __builtin_fma(t.y, cs, t.x * sn);
-    *c_out = __builtin_fma(t.x, cs, -(t.y * sn));
-}
-
 // ============================================================== per-bin data
 // The FP32 copy is scaled (u by su = sqrt(s), q by sq = s, s ~ 1 / median q)
 // so that it stays far from FP32 overflow for strain-sized PSDs; the
@@ -594,6 +574,14 @@ __global__ void k_bounds_simple(BoundArgs a)
 // closes it at its own edges; a chunk leaves per (particle, chunk) the sum of
 // terms of segments complete inside it and the head / tail pieces of the
 // segments that cross its edges, which k_finalize joins.
+//
+// The bin loop carries no per-lane test.  Each lane keeps the bin of its next
+// event: the start of its support (clear the sums, which may hold terms of
+// earlier bins of the same polynomial block), a segment edge (close the
+// segment), the end of its support (zero its polynomials, so that later bins
+// add exact zeros).  The wave runs straight through the bins up to the
+// smallest pending event, lets the lanes whose event is due handle it, and
+// goes on.
 __device__ __forceinline__ int bsearch_seg(const int32_t* __restrict__ bo, int N, int64_t k)
 {
     // largest n in [0, N-1] with b_n <= k
@@ -605,16 +593,140 @@ __device__ __forceinline__ int bsearch_seg(const int32_t* __restrict__ bo, int N
     return lo;
 }
 
+// Minimum over the 64 lanes of a wave; every lane must be active.  Prefix
+// minimum inside each row of 16 lanes by DPP row shifts (lanes shifted in
+// from outside the row read INT32_MAX), then the four row minima through
+// scalar registers.
+__device__ __forceinline__ int wave_min_i32(int v)
+{
+    v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x111, 0xf, 0xf, false));  // row_shr:1
+    v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x112, 0xf, 0xf, false));  // row_shr:2
+    v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x114, 0xf, 0xf, false));  // row_shr:4
+    v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x118, 0xf, 0xf, false));  // row_shr:8
+    const int r0 = __builtin_amdgcn_readlane(v, 15), r1 = __builtin_amdgcn_readlane(v, 31);
+    const int r2 = __builtin_amdgcn_readlane(v, 47), r3 = __builtin_amdgcn_readlane(v, 63);
+    const int m01 = r0 < r1 ? r0 : r1, m23 = r2 < r3 ? r2 : r3;
+    return m01 < m23 ? m01 : m23;
+}
+
+// sin and cos of 2 pi s / kTrig for |s| <= 1/2: Taylor polynomials in
+// z = s^2 with the powers of 2 pi / kTrig folded in; remainders below 1e-18.
+constexpr double kArg = kTwoPi / kTrig;
+constexpr double kSin1 = kArg;
+constexpr double kSin3 = -(kArg * kArg * kArg) / 6.0;
+constexpr double kSin5 = (kArg * kArg * kArg * kArg * kArg) / 120.0;
+constexpr double kCos2 = -(kArg * kArg) / 2.0;
+constexpr double kCos4 = (kArg * kArg * kArg * kArg) / 24.0;
+// Adding 1.5 * 2^52 to a double of magnitude below 2^51 rounds it to the
+// nearest integer, which then sits in the low mantissa bits.
+constexpr double kRoundShift = 0x1.8p52;
+
+// One bin of the FP64 path: template phase at bin offset j from the block
+// centre, in units of 1/kTrig cycle (the block polynomial carries that
+// power-of-two scale); e^{2 pi i phase} from the table entry of the nearest
+// unit and the polynomials for the remainder; then
+// Z += (sum_alpha u_alpha conj(R_alpha)) e^{2 pi i phase},
+// H += sum_alpha q_alpha |R_alpha|^2.  bin = [uA re, uA im, uE re, uE im, qA, qE]
+// (two channels) or [u re, u im, q]; amp scales the one-channel terms (0 or 1).
+template <bool RESP>
+__device__ __forceinline__ void bin_fp64(double j, const double* __restrict__ bin, const double2* __restrict__ tab,
+                                         const PhasePoly& poly, const RespPoly& rp, int tmask, int toff, double amp,
+                                         double& zr, double& zi, double& hh)
+{
+    const double pc = horner5(poly.ph, j);
+    const double t = pc + kRoundShift;
+    const double q = t - kRoundShift;  // rint(pc)
+    const int iq = ((int)(uint32_t)__double_as_longlong(t) & tmask) | toff;
+    const double s = pc - q;  // exact, |s| <= 1/2
+    const double z = s * s;
+    const double sn = s * __builtin_fma(z, __builtin_fma(z, kSin5, kSin3), kSin1);
+    const double cn = __builtin_fma(z, __builtin_fma(z, kCos4, kCos2), 1.0);
+    const double2 tt = tab[iq];
+    const double sv = __builtin_fma(tt.y, cn, tt.x * sn);
+    const double cv = __builtin_fma(tt.x, cn, -(tt.y * sn));
+    if constexpr (RESP) {
+        const double2 uA = *reinterpret_cast<const double2*>(bin);
+        const double2 uE = *reinterpret_cast<const double2*>(bin + 2);
+        const double2 qq = *reinterpret_cast<const double2*>(bin + 4);
+        const double rar = horner5(rp.r[0], j), rai = horner5(rp.r[1], j);
+        const double rer = horner5(rp.r[2], j), rei = horner5(rp.r[3], j);
+        double sr = uA.x * rar;
+        sr = __builtin_fma(uA.y, rai, sr);
+        sr = __builtin_fma(uE.x, rer, sr);
+        sr = __builtin_fma(uE.y, rei, sr);
+        double si = uA.y * rar;
+        si = __builtin_fma(-uA.x, rai, si);
+        si = __builtin_fma(uE.y, rer, si);
+        si = __builtin_fma(-uE.x, rei, si);
+        zr = __builtin_fma(sr, cv, __builtin_fma(-si, sv, zr));
+        zi = __builtin_fma(sr, sv, __builtin_fma(si, cv, zi));
+        const double wa = __builtin_fma(rar, rar, rai * rai);
+        const double we = __builtin_fma(rer, rer, rei * rei);
+        hh = __builtin_fma(qq.x, wa, __builtin_fma(qq.y, we, hh));
+    } else {
+        const double ur = bin[0], ui = bin[1], qq = bin[2];
+        zr = __builtin_fma(ur, cv, __builtin_fma(-ui, sv, zr));
+        zi = __builtin_fma(ur, sv, __builtin_fma(ui, cv, zi));
+        hh = __builtin_fma(qq, amp, hh);
+    }
+}
+
+// One bin of the mixed path: FP32 phase a0 + frac(a1h j) + residual(j)
+// (a1h j exact, see the block set-up), hardware sin / cos of cycles, FP32
+// response; plain FP32 partial sums over at most kMixedRun bins, which then
+// enter the FP32 segment sums through Kahan-compensated additions.
+template <bool RESP>
+__device__ __forceinline__ void bin_mixed(float jf, const float* __restrict__ bin, const float* phf, float a1h,
+                                          const float (*rf)[kNodes], float amp, float& pzr, float& pzi, float& phh)
+{
+    const float pl = a1h * jf;
+    const float f1 = pl - rintf(pl);
+    float r = phf[5];
+    r = __builtin_fmaf(r, jf, phf[4]);
+    r = __builtin_fmaf(r, jf, phf[3]);
+    r = __builtin_fmaf(r, jf, phf[2]);
+    r = __builtin_fmaf(r, jf, phf[1]);
+    const float ph = __builtin_fmaf(r, jf, phf[0] + f1);
+    const float sn = __builtin_amdgcn_sinf(ph);
+    const float cs = __builtin_amdgcn_cosf(ph);
+    if constexpr (RESP) {
+        const float rar = horner5f(rf[0], jf), rai = horner5f(rf[1], jf);
+        const float rer = horner5f(rf[2], jf), rei = horner5f(rf[3], jf);
+        const float4 u = *reinterpret_cast<const float4*>(bin);
+        const float2 qq = *reinterpret_cast<const float2*>(bin + 4);
+        float sr = u.x * rar;
+        sr = __builtin_fmaf(u.y, rai, sr);
+        sr = __builtin_fmaf(u.z, rer, sr);
+        sr = __builtin_fmaf(u.w, rei, sr);
+        float si = u.y * rar;
+        si = __builtin_fmaf(-u.x, rai, si);
+        si = __builtin_fmaf(u.w, rer, si);
+        si = __builtin_fmaf(-u.z, rei, si);
+        pzr = __builtin_fmaf(sr, cs, __builtin_fmaf(-si, sn, pzr));
+        pzi = __builtin_fmaf(sr, sn, __builtin_fmaf(si, cs, pzi));
+        const float wa = __builtin_fmaf(rar, rar, rai * rai);
+        const float we = __builtin_fmaf(rer, rer, rei * rei);
+        phh = __builtin_fmaf(qq.x, wa, __builtin_fmaf(qq.y, we, phh));
+    } else {
+        const float ur = bin[0] * amp, ui = bin[1] * amp;
+        pzr = __builtin_fmaf(ur, cs, __builtin_fmaf(-ui, sn, pzr));
+        pzi = __builtin_fmaf(ur, sn, __builtin_fmaf(ui, cs, pzi));
+        phh = __builtin_fmaf(bin[2], amp, phh);
+    }
+}
+
 // Occupancy target: the per-sub-block set-up needs more registers than the
-// bin loop; capping the allocation lets four waves share a SIMD, the set-up
+// bin loop; capping the allocation lets more waves share a SIMD, the set-up
 // spilling to scratch while the bin loop stays in registers.
-// Measured on MI355X: three waves for the FP64 kernel, four for mixed.
 #ifndef SCS_WAVES_FP64
 #define SCS_WAVES_FP64 3
 #endif
 #ifndef SCS_WAVES_MIXED
 #define SCS_WAVES_MIXED 4
 #endif
+// Bins in one plain FP32 partial sum before its compensated addition (mixed).
+constexpr int kMixedRun = 32;
+
 template <int NCH, bool MIXED>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(MIXED ? SCS_WAVES_MIXED : SCS_WAVES_FP64))) void k_main(
@@ -623,7 +735,8 @@ __attribute__((amdgpu_waves_per_eu(MIXED ? SCS_WAVES_MIXED : SCS_WAVES_FP64))) v
     constexpr int NV = 3 * NCH;  // values per bin
     constexpr bool RESP = NCH == 2;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double2 s_trig[MIXED ? 1 : kTrig];
+    // (cos, sin)(2 pi i / kTrig) and one zero entry for idle lanes (one channel)
+    __shared__ double2 s_trig[MIXED ? 1 : kTrig + 1];
     // ---- tile decode, XCD-aware: consecutive logical tiles (same chunk,
     //      neighbouring particle groups) land on the same XCD's L2.
     const int64_t nwg = a.n_tiles;
@@ -655,6 +768,7 @@ __attribute__((amdgpu_waves_per_eu(MIXED ? SCS_WAVES_MIXED : SCS_WAVES_FP64))) v
     if (!__syncthreads_or(has)) return;
     if constexpr (!MIXED) {
         for (int i = tid; i < kTrig; i += blockDim.x) s_trig[i] = g_trig[i];
+        if (tid == 0) s_trig[kTrig] = make_double2(0.0, 0.0);
         // made visible by the barrier before the first staged block
     }
     const int64_t S = a.stride;
@@ -668,15 +782,32 @@ __attribute__((amdgpu_waves_per_eu(MIXED ? SCS_WAVES_MIXED : SCS_WAVES_FP64))) v
         lgw = t < lgw ? t : lgw;
     }
     lgw = __builtin_amdgcn_readfirstlane(lgw);  // uniform: scalar registers and scalar loads downstream
-    int n = 0, nb = 0;
+    // segment state: current segment n, its end nb = b_{n+1}, and b_{n+2}
+    // loaded ahead so that closing a segment does not wait for memory
+    int n = 0, nb = INT32_MAX, nb2 = INT32_MAX;
     bool before = false;
     if (has) {
         n = bsearch_seg(bo, N, lo);
         nb = bo[n + 1];
+        nb2 = (n + 2 <= N) ? bo[n + 2] : INT32_MAX;
         before = bo[n] < Kc;
     }
-    double zr = 0.0, zi = 0.0, hh = 0.0;
-    float kzr = 0.f, kzi = 0.f, khh = 0.f, czr = 0.f, czi = 0.f, chh = 0.f;  // Kahan sums (mixed)
+    // event state: 0 before the support, 1 inside, 2 after (or no support)
+    int stage = has ? 0 : 2;
+    int nxt = has ? lo : INT32_MAX;
+    double zr = 0.0, zi = 0.0, hh = 0.0;  // FP64 sums
+    // mixed: FP32 running sums with Kahan compensation (value = sum - comp)
+    float kzr = 0.f, kzi = 0.f, khh = 0.f, czr = 0.f, czi = 0.f, chh = 0.f;
+    auto kahan = [](float& sum, float& comp, float x) {
+        const float y = x - comp;
+        const float t = sum + y;
+        comp = (t - sum) - y;
+        sum = t;
+    };
+    auto clear_sums = [&]() {
+        zr = zi = hh = 0.0;
+        kzr = kzi = khh = czr = czi = chh = 0.f;
+    };
     double part = 0.0;
     bool head_done = false;
     const int64_t RS = a.rec_stride;
@@ -690,7 +821,6 @@ __attribute__((amdgpu_waves_per_eu(MIXED ? SCS_WAVES_MIXED : SCS_WAVES_FP64))) v
             fzr = ((double)kzr - (double)czr) * a.zscale32;
             fzi = ((double)kzi - (double)czi) * a.zscale32;
             fhh = ((double)khh - (double)chh) * a.hscale32;
-            kzr = kzi = khh = czr = czi = chh = 0.f;
         }
         if (before) {
             // head piece of a segment that started in an earlier chunk
@@ -707,13 +837,15 @@ __attribute__((amdgpu_waves_per_eu(MIXED ? SCS_WAVES_MIXED : SCS_WAVES_FP64))) v
                 sp[2] = fhh;
             }
         }
-        zr = zi = hh = 0.0;
+        clear_sums();
         before = false;
         ++n;
-        nb = (n < N) ? bo[n + 1] : INT32_MAX;
-        while (n < N - 1 && nb == k) {
+        nb = (n < N) ? nb2 : INT32_MAX;
+        nb2 = (n + 2 <= N) ? bo[n + 2] : INT32_MAX;
+        while (n < N - 1 && nb == k) {  // empty segments
             ++n;
             nb = bo[n + 1];
+            nb2 = (n + 2 <= N) ? bo[n + 2] : INT32_MAX;
         }
     };
     const int L = a.L;
@@ -723,6 +855,50 @@ __attribute__((amdgpu_waves_per_eu(MIXED ? SCS_WAVES_MIXED : SCS_WAVES_FP64))) v
     RespPoly rp;
     float phf[kNodes], rf[4][kNodes];
     float a1h = 0.f;
+    // one-channel idle lanes: table index of the zero entry, zero weight
+    int tmask = 0, toff = kTrig;
+    double amp = 0.0;
+    auto zero_polys = [&]() {
+        if constexpr (MIXED) {
+            a1h = 0.f;
+#pragma unroll
+            for (int mm = 0; mm < kNodes; ++mm) phf[mm] = 0.f;
+            if constexpr (RESP) {
+#pragma unroll
+                for (int f = 0; f < 4; ++f)
+#pragma unroll
+                    for (int mm = 0; mm < kNodes; ++mm) rf[f][mm] = 0.f;
+            }
+        } else {
+#pragma unroll
+            for (int mm = 0; mm < kNodes; ++mm) poly.ph[mm] = 0.0;
+            if constexpr (RESP) {
+#pragma unroll
+                for (int f = 0; f < 4; ++f)
+#pragma unroll
+                    for (int mm = 0; mm < kNodes; ++mm) rp.r[f][mm] = 0.0;
+            }
+        }
+        tmask = 0;
+        toff = kTrig;
+        amp = 0.0;
+    };
+    // lanes whose event is due at bin k (nxt <= k)
+    auto handle = [&](int k) {
+        if (stage == 0) {
+            clear_sums();
+            stage = 1;
+        }
+        if (stage == 1) {
+            if (nb == k && k < hi) flush(k);
+            if (hi <= k) {
+                stage = 2;
+                zero_polys();
+            }
+        }
+        nxt = (stage == 1) ? (nb < hi ? nb : hi) : INT32_MAX;
+        if (nxt <= k) nxt = INT32_MAX;  // not reached; keeps the wave loop finite
+    };
     for (int b0 = Kc; b0 < Ke; b0 += L) {
         const int b1 = (b0 + L < Ke) ? b0 + L : Ke;
         const int nbins = b1 - b0;
@@ -748,7 +924,7 @@ __attribute__((amdgpu_waves_per_eu(MIXED ? SCS_WAVES_MIXED : SCS_WAVES_FP64))) v
         const int llo = lo > b0 ? lo : b0;
         const int lhi = hi < b1 ? hi : b1;
         const bool act = llo < lhi;
-        // wave-uniform bin range
+        // wave-uniform bin range: the union of the lanes' ranges
         int wlo = act ? llo : INT32_MAX, whi = act ? lhi : INT32_MIN;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
@@ -772,25 +948,35 @@ __attribute__((amdgpu_waves_per_eu(MIXED ? SCS_WAVES_MIXED : SCS_WAVES_FP64))) v
             if (sact) {
                 block_setup<RESP>(a.coef, S, p, a.g.k0 + (double)kc, lgw, gt + (int64_t)(sb0 >> lgw) * kGStride, a.g,
                                   a.m, poly, rp);
-                if constexpr (MIXED) {
-                    // phase = a0 + frac(a1h j) + residual(j): j is an integer and
-                    // a1h keeps 12 significant bits, so a1h j is exact in FP32
-                    double aj[kNodes];
+                // monomials in j = x h (h a power of two: exact rescaling); the
+                // FP64 phase also in units of 1/kTrig cycle
+                {
                     double sc = 1.0;
 #pragma unroll
                     for (int mm = 0; mm < kNodes; ++mm) {
-                        aj[mm] = poly.ph[mm] * sc;
+                        poly.ph[mm] *= MIXED ? sc : sc * kTrig;
+                        if constexpr (RESP) {
+#pragma unroll
+                            for (int f = 0; f < 4; ++f) rp.r[f][mm] *= sc;
+                        }
                         sc *= inv_h;
                     }
+                }
+                tmask = kTrig - 1;
+                toff = 0;
+                amp = 1.0;
+                if constexpr (MIXED) {
+                    // phase = a0 + frac(a1h j) + residual(j): j is an integer and
+                    // a1h keeps 12 significant bits, so a1h j is exact in FP32
                     int ex;
-                    frexp(aj[1], &ex);
-                    const double q = ldexp(1.0, ex - 12);
-                    const double hi1 = rint(aj[1] / q) * q;
+                    frexp(poly.ph[1], &ex);
+                    const double qd = ldexp(1.0, ex - 12);
+                    const double hi1 = rint(poly.ph[1] / qd) * qd;
                     a1h = (float)hi1;
-                    phf[0] = (float)aj[0];
-                    phf[1] = (float)(aj[1] - hi1);
+                    phf[0] = (float)poly.ph[0];
+                    phf[1] = (float)(poly.ph[1] - hi1);
 #pragma unroll
-                    for (int mm = 2; mm < kNodes; ++mm) phf[mm] = (float)aj[mm];
+                    for (int mm = 2; mm < kNodes; ++mm) phf[mm] = (float)poly.ph[mm];
                     if constexpr (RESP) {
 #pragma unroll
                         for (int f = 0; f < 4; ++f)
@@ -798,100 +984,56 @@ __attribute__((amdgpu_waves_per_eu(MIXED ? SCS_WAVES_MIXED : SCS_WAVES_FP64))) v
                             for (int mm = 0; mm < kNodes; ++mm) rf[f][mm] = (float)rp.r[f][mm];
                     }
                 }
+            } else {
+                zero_polys();
             }
+            int ev = wave_min_i32(nxt);
+            int k = s_lo;
+            while (true) {
+                const int kend = ev < s_hi ? ev : s_hi;
+                if constexpr (!MIXED) {
+                    double jd = (double)(k - kc);
+                    const double* binp = reinterpret_cast<const double*>(smem) + (k - b0) * NV;
 #pragma unroll 1
-            for (int k = s_lo; k < s_hi; ++k) {
-                if (k >= llo && k < lhi) {
-                    if (k == nb) flush(k);
-                    const int jl = k - b0;
-                    if constexpr (!MIXED) {
-                        const double x = (double)(k - kc) * inv_h;
-                        double ph = horner5(poly.ph, x);
-                        ph -= rint(ph);
-                        double sn, cs;
-                        sincos2pi_tab(ph, s_trig, &sn, &cs);
-                        const double* bin = reinterpret_cast<const double*>(smem) + jl * NV;
-                        if constexpr (RESP) {
-                            const double2 uA = *reinterpret_cast<const double2*>(bin);
-                            const double2 uE = *reinterpret_cast<const double2*>(bin + 2);
-                            const double2 qq = *reinterpret_cast<const double2*>(bin + 4);
-                            const double rar = horner5(rp.r[0], x), rai = horner5(rp.r[1], x);
-                            const double rer = horner5(rp.r[2], x), rei = horner5(rp.r[3], x);
-                            double sr = uA.x * rar;
-                            sr = __builtin_fma(uA.y, rai, sr);
-                            sr = __builtin_fma(uE.x, rer, sr);
-                            sr = __builtin_fma(uE.y, rei, sr);
-                            double si = uA.y * rar;
-                            si = __builtin_fma(-uA.x, rai, si);
-                            si = __builtin_fma(uE.y, rer, si);
-                            si = __builtin_fma(-uE.x, rei, si);
-                            zr = __builtin_fma(sr, cs, __builtin_fma(-si, sn, zr));
-                            zi = __builtin_fma(sr, sn, __builtin_fma(si, cs, zi));
-                            const double wa = __builtin_fma(rar, rar, rai * rai);
-                            const double we = __builtin_fma(rer, rer, rei * rei);
-                            hh = __builtin_fma(qq.x, wa, __builtin_fma(qq.y, we, hh));
-                        } else {
-                            const double ur = bin[0], ui = bin[1], qq = bin[2];
-                            zr = __builtin_fma(ur, cs, __builtin_fma(-ui, sn, zr));
-                            zi = __builtin_fma(ur, sn, __builtin_fma(ui, cs, zi));
-                            hh += qq;
+                    for (; k + 1 < kend; k += 2) {
+                        bin_fp64<RESP>(jd, binp, s_trig, poly, rp, tmask, toff, amp, zr, zi, hh);
+                        bin_fp64<RESP>(jd + 1.0, binp + NV, s_trig, poly, rp, tmask, toff, amp, zr, zi, hh);
+                        jd += 2.0;
+                        binp += 2 * NV;
+                    }
+                    if (k < kend) {
+                        bin_fp64<RESP>(jd, binp, s_trig, poly, rp, tmask, toff, amp, zr, zi, hh);
+                        ++k;
+                    }
+                } else {
+                    const float ampf = (float)amp;
+#pragma unroll 1
+                    while (k < kend) {
+                        const int pe = (kend - k > kMixedRun) ? k + kMixedRun : kend;
+                        float jf = (float)(k - kc);
+                        const float* binp = reinterpret_cast<const float*>(smem) + (k - b0) * NV;
+                        float pzr = 0.f, pzi = 0.f, phh = 0.f;
+#pragma unroll 1
+                        for (; k + 1 < pe; k += 2) {
+                            bin_mixed<RESP>(jf, binp, phf, a1h, rf, ampf, pzr, pzi, phh);
+                            bin_mixed<RESP>(jf + 1.f, binp + NV, phf, a1h, rf, ampf, pzr, pzi, phh);
+                            jf += 2.f;
+                            binp += 2 * NV;
                         }
-                    } else {
-                        const float jf = (float)(k - kc);
-                        const float pl = a1h * jf;
-                        const float f1 = pl - rintf(pl);
-                        float r = phf[5];
-                        r = __builtin_fmaf(r, jf, phf[4]);
-                        r = __builtin_fmaf(r, jf, phf[3]);
-                        r = __builtin_fmaf(r, jf, phf[2]);
-                        r = __builtin_fmaf(r, jf, phf[1]);
-                        const float ph = __builtin_fmaf(r, jf, phf[0] + f1);
-                        const float sn = __builtin_amdgcn_sinf(ph);
-                        const float cs = __builtin_amdgcn_cosf(ph);
-                        const float* bin = reinterpret_cast<const float*>(smem) + jl * NV;
-                        float dzr, dzi, dhh;
-                        if constexpr (RESP) {
-                            const float x = jf * (float)inv_h;
-                            const float rar = horner5f(rf[0], x), rai = horner5f(rf[1], x);
-                            const float rer = horner5f(rf[2], x), rei = horner5f(rf[3], x);
-                            const float uar = bin[0], uai = bin[1], uer = bin[2], uei = bin[3];
-                            float sr = uar * rar;
-                            sr = __builtin_fmaf(uai, rai, sr);
-                            sr = __builtin_fmaf(uer, rer, sr);
-                            sr = __builtin_fmaf(uei, rei, sr);
-                            float si = uai * rar;
-                            si = __builtin_fmaf(-uar, rai, si);
-                            si = __builtin_fmaf(uei, rer, si);
-                            si = __builtin_fmaf(-uer, rei, si);
-                            dzr = __builtin_fmaf(sr, cs, -si * sn);
-                            dzi = __builtin_fmaf(sr, sn, si * cs);
-                            const float wa = __builtin_fmaf(rar, rar, rai * rai);
-                            const float we = __builtin_fmaf(rer, rer, rei * rei);
-                            dhh = __builtin_fmaf(bin[4], wa, bin[5] * we);
-                        } else {
-                            const float ur = bin[0], ui = bin[1];
-                            dzr = __builtin_fmaf(ur, cs, -ui * sn);
-                            dzi = __builtin_fmaf(ur, sn, ui * cs);
-                            dhh = bin[2];
+                        if (k < pe) {
+                            bin_mixed<RESP>(jf, binp, phf, a1h, rf, ampf, pzr, pzi, phh);
+                            ++k;
                         }
-                        // Kahan-compensated FP32 sums
-                        {
-                            const float y = dzr - czr, t = kzr + y;
-                            czr = (t - kzr) - y;
-                            kzr = t;
-                        }
-                        {
-                            const float y = dzi - czi, t = kzi + y;
-                            czi = (t - kzi) - y;
-                            kzi = t;
-                        }
-                        {
-                            const float y = dhh - chh, t = khh + y;
-                            chh = (t - khh) - y;
-                            khh = t;
-                        }
+                        kahan(kzr, czr, pzr);
+                        kahan(kzi, czi, pzi);
+                        kahan(khh, chh, phh);
                     }
                 }
+                k = k > kend ? k : kend;
+                if (k >= s_hi) break;
+                if (nxt <= k) handle(k);
+                ev = wave_min_i32(nxt);
+                ev = ev > k ? ev : k + 1;  // every pass of this loop covers at least one bin
             }
         }
     }
