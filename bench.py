@@ -67,8 +67,8 @@ def main():
         print(json.dumps({"copy_probe_bytes_each_way": src.numel() * 8, "copies": 3}))
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for {args.gpus}); every GPU box here has one GPU and the "
-              "multi-GPU path (particle sharding) is a design, not a build.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the statistic shards by particle with no "
+              "exchange, and that multi-GPU path is a design, not part of this library.", file=sys.stderr)
         sys.exit(2)
 
     import torch

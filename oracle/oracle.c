@@ -25,8 +25,14 @@
  *   response               low-frequency LISA A/E channels               [Sec 4, response paragraph]
  *   PSO update             velocity rule + minimum-velocity clamp       [Sec 3.1, eqn:PSO_velocity_rule,
  *                                                                         eqn:PSO_min_velocity]
- * Readings of points the paper leaves open are listed in the design doc of the
- * repository and restated next to the code that takes them.
+ * Where the paper leaves a point open, the reading taken is stated next to
+ * the code that takes it.
+ *
+ * Parity unpinned: the PN phase coefficients above the Newtonian term (the
+ * paper does not print them; they are the standard TaylorF2 values, checked
+ * only through an extended-precision evaluation of the same formula and the
+ * coalescence times of the injection tables), and the low-frequency response
+ * beyond its invariants (the paper's full response code is not available).
  */
 #include <math.h>
 #include <stdint.h>
