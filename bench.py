@@ -55,6 +55,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration) and exit")
+    ap.add_argument("--mode", choices=["step", "batched", "serve"], default="step",
+                    help="step: PSO steps of one 10^4-particle swarm (default); batched: six swarms of the "
+                         "hierarchy in one graph-captured persistent launch; serve: concurrent searches with "
+                         "Poisson-arriving requests")
+    ap.add_argument("--requests", type=int, default=2000, help="serve: requests per offered load")
+    ap.add_argument("--loads", type=str, default="0.5,0.8,0.95", help="serve: offered loads (x capacity)")
     args = ap.parse_args()
     if args.copy_probe_mib:
         import torch
@@ -71,32 +77,21 @@ def main():
               "exchange, and that multi-GPU path is a design, not part of this library.", file=sys.stderr)
         sys.exit(2)
 
+    if args.mode == "batched":
+        return bench_batched(args)
+    if args.mode == "serve":
+        return bench_serve(args)
+
     import torch
 
     from paper_2408_13170_amd import B
 
     dev = torch.device("cuda:0")
     w = synth.workload("lisa1m")
-    K, df, f_min = w.grid.K, w.grid.df, w.grid.f_min
+    K = w.grid.K
     psd = synth.psd_arrays(w)
-    noise = synth.noise(psd, df, w.seed)
     # --- data: noise + injection made with the library's own FP64 template
-    ctx = B.scs_ctx_create(0)
-    zeros = np.zeros((2, K, 2))
-    B.scs_load_data(ctx, zeros, psd, f_min, df)
-    B.scs_set_model(ctx, w.pn_order, B.SCS_RESP_LISA_LF_AE, B.SCS_SUPPORT_TOBS, w.grid.t_obs)
-    h = torch.empty((2, K, 2), dtype=torch.float64, device=dev)
-    B.scs_waveform(ctx, torch.tensor(w.injection, device=dev), h)
-    torch.cuda.synchronize()
-    hc = torch.complex(h[..., 0], h[..., 1])
-    S = torch.tensor(psd, device=dev)
-    hh = float(4 * df * torch.sum(hc.abs() ** 2 / S))
-    d = torch.tensor(noise, device=dev) + hc * (w.snr / math.sqrt(hh))
-    d_ri = torch.stack([d.real, d.imag], -1).contiguous()
-    B.scs_load_data(ctx, d_ri, S.contiguous(), f_min, df)
-    B.scs_set_model(ctx, w.pn_order, B.SCS_RESP_LISA_LF_AE, B.SCS_SUPPORT_TOBS, w.grid.t_obs)
-    B.scs_define_segmentation(ctx, w.N, B.SCS_SEG_EQUAL_SNR, w.G)
-    del h, hc, d
+    ctx, d_ri = make_search(B, torch, w, dev)
     # --- swarm of 10^4 particles, first rung of the ladder (Table tab:PSO_hyperparams, N = 100 row)
     eps = [0.1, 0.05, 5e-8, 0.1, 0.1, 0.2, 0.1]  # Mc, eta, f_low, lambda, beta, iota, psi
     prm = B.pso_params(0.5, 0.2, 0.3, eps)
@@ -186,6 +181,182 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, psd, d_ri.cpu().numpy(), args.cpu_seconds)
     B.scs_ctx_destroy(ctx)
+    print(json.dumps(out), flush=True)
+
+
+def make_search(B, torch, w, dev):
+    """Context with seeded noise plus the injection of workload w at its SNR
+    (template from the library's own FP64 waveform kernel)."""
+    K, df, f_min = w.grid.K, w.grid.df, w.grid.f_min
+    psd = synth.psd_arrays(w)
+    noise = synth.noise(psd, df, w.seed)
+    ctx = B.scs_ctx_create(0)
+    B.scs_load_data(ctx, np.zeros((w.n_chan, K, 2)), psd, f_min, df)
+    B.scs_set_model(ctx, w.pn_order, B.SCS_RESP_LISA_LF_AE, B.SCS_SUPPORT_TOBS, w.grid.t_obs)
+    h = torch.empty((w.n_chan, K, 2), dtype=torch.float64, device=dev)
+    B.scs_waveform(ctx, torch.tensor(w.injection, device=dev), h)
+    torch.cuda.synchronize()
+    hc = torch.complex(h[..., 0], h[..., 1])
+    S = torch.tensor(psd, device=dev)
+    hh = float(4 * df * torch.sum(hc.abs() ** 2 / S))
+    d = torch.tensor(noise, device=dev) + hc * (w.snr / math.sqrt(hh))
+    d_ri = torch.stack([d.real, d.imag], -1).contiguous()
+    B.scs_load_data(ctx, d_ri, S.contiguous(), f_min, df)
+    B.scs_set_model(ctx, w.pn_order, B.SCS_RESP_LISA_LF_AE, B.SCS_SUPPORT_TOBS, w.grid.t_obs)
+    B.scs_define_segmentation(ctx, w.N, B.SCS_SEG_EQUAL_SNR, w.G)
+    return ctx, d_ri
+
+
+def bench_batched(args):
+    """Six swarms of the hierarchy, (N, P) = (4096, 16384) ... (1, 128), on the
+    2^20-bin A+E data in ONE graph-captured batched launch (one persistent
+    generate-and-reduce kernel over all tiles), FP64 and mixed; mixed error
+    per level against FP64."""
+    import torch
+
+    from paper_2408_13170_amd import B
+
+    dev = torch.device("cuda:0")
+    w = synth.workload("lisa1m")
+    ctx, _ = make_search(B, torch, w, dev)
+    stream = torch.cuda.current_stream()
+    items = []
+    for i, (N, P) in enumerate(synth.LADDER_SWARMS):
+        th = torch.tensor(synth.particles(w.prior_lo, w.prior_hi, P, w.seed + 700 + i), device=dev)
+        items.append((ctx, N, th, torch.empty(P, dtype=torch.float64, device=dev)))
+    res = {}
+    for prec, name in ((B.SCS_PREC_FP64, "fp64"), (B.SCS_PREC_MIXED, "mixed")):
+        g = B.scs_graph_create(items, prec)
+        for _ in range(args.warmup):
+            B.scs_graph_launch(g, stream)
+        torch.cuda.synchronize()
+        B.scs_ctx_stats(ctx, reset=True)
+        B.scs_ctx_profile(ctx, 1)
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+        t0 = time.perf_counter()
+        evs[0].record(stream)
+        for i in range(args.steps):
+            B.scs_graph_launch(g, stream)
+            evs[i + 1].record(stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        n_launch, main_ms = B.scs_ctx_profile(ctx, 0)
+        ev_support, _, _ = B.scs_ctx_stats(ctx, reset=True)
+        step_ms = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
+        B.scs_graph_destroy(g)
+        res[name] = {"value": ev_support / (t1 - t0), "unit": "evals/s", "ms_per_batch": 1e3 * (t1 - t0) / args.steps,
+                     "latency_ms": {"p50": float(np.median(step_ms)), "p99": float(np.quantile(step_ms, 0.99))},
+                     "evals_per_batch": ev_support / args.steps,
+                     "ups": [it[3].cpu().numpy().copy() for it in items]}
+        log(f"batched {name}: {res[name]['value']:.4g} evals/s, {res[name]['ms_per_batch']:.2f} ms per batch")
+    per_level = []
+    for (N, P), a, b in zip(synth.LADDER_SWARMS, res["fp64"]["ups"], res["mixed"]["ups"]):
+        ok = np.isfinite(a)
+        e = np.abs(b[ok] - a[ok]) / np.maximum(np.abs(a[ok]), 2.0 * N)
+        per_level.append({"N": N, "P": P, "median": float(np.median(e)), "p99": float(np.quantile(e, 0.99)),
+                          "max": float(e.max())})
+    for r in res.values():
+        del r["ups"]
+    out = {"metric": "particle x freq-bin statistic evals/s (in-support), batched hierarchy, FP64; mixed beside",
+           "value": res["fp64"]["value"], "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": res["fp64"]["ms_per_batch"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic: same data as the step benchmark",
+           "config": {"workload": "six swarms (N, P) = " + str(synth.LADDER_SWARMS) + " on the 2^20-bin A+E data, "
+                                  "one HIP graph per precision, one persistent fused generate-and-reduce launch"},
+           "fp64": res["fp64"], "mixed": res["mixed"],
+           "mixed_speedup": res["mixed"]["value"] / res["fp64"]["value"],
+           "mixed_err_vs_fp64_per_level": per_level}
+    B.scs_ctx_destroy(ctx)
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args):
+    """Eight independent searches (2^19 - 2^21 bins, A+E, GW150914-like and
+    GW190521-like injections at SNR 15 - 40) behind the native request loop.
+    Requests of 256 - 16384 particles (log-uniform) at a segment count from
+    the ladder arrive as a Poisson process at fractions of the measured
+    capacity; p50 / p99 latency (submit to result) and throughput."""
+    import torch
+
+    from paper_2408_13170_amd import B
+
+    dev = torch.device("cuda:0")
+    searches = []
+    for w in synth.served_streams():
+        ctx, _ = make_search(B, torch, w, dev)
+        searches.append((w, ctx))
+        log(f"search {w.name}: K = {w.grid.K}, SNR {w.snr}")
+    torch.cuda.synchronize()
+    ladder = [4096, 1024, 256, 64, 16]
+    rng = np.random.default_rng(synth.BASE_SEED + 900)
+
+    def make_requests(n):
+        reqs = []
+        for _ in range(n):
+            si = int(rng.integers(len(searches)))
+            w, ctx = searches[si]
+            P = int(np.exp(rng.uniform(np.log(256), np.log(16384))))
+            reqs.append((ctx, int(rng.choice(ladder)), synth.particles(w.prior_lo, w.prior_hi, P,
+                                                                         int(rng.integers(1 << 30))), si))
+        return reqs
+
+    budget = 64 << 30
+    srv = B.scs_server_create(0, max_inflight=32, hbm_budget=budget, n_streams=4)
+
+    def run(reqs, arrivals):
+        outs, t_sub = {}, {}
+        done = []
+        t0 = time.perf_counter()
+        k = 0
+        while len(done) < len(reqs):
+            now = time.perf_counter() - t0
+            while k < len(reqs) and (arrivals is None or arrivals[k] <= now):
+                ctx, N, th, si = reqs[k]
+                ups = np.empty(th.shape[0])
+                rid = B.scs_server_submit(srv, ctx, N, th, ups, B.SCS_PREC_FP64)
+                outs[rid] = (ups, k)
+                k += 1
+            wait = 1 if k < len(reqs) else 20
+            done += B.scs_server_poll(srv, max_out=1024, wait_ms=wait)
+        t1 = time.perf_counter() - t0
+        lat = np.array([d["t_done"] - d["t_submit"] for d in done]) * 1e3
+        assert all(d["status"] == 0 for d in done)
+        return t1, lat
+
+    # capacity: a closed burst of requests
+    for _, ctx in searches:
+        B.scs_ctx_stats(ctx, reset=True)
+    burst = make_requests(max(64, args.requests // 8))
+    run(burst[:16], None)  # warm-up: workspaces, slots
+    for _, ctx in searches:
+        B.scs_ctx_stats(ctx, reset=True)
+    t_b, _ = run(burst, None)
+    ev_b = sum(B.scs_ctx_stats(ctx, reset=True)[0] for _, ctx in searches)
+    capacity = len(burst) / t_b
+    log(f"capacity {capacity:.1f} requests/s, {ev_b / t_b:.4g} evals/s")
+    levels = []
+    for load in [float(x) for x in args.loads.split(",")]:
+        reqs = make_requests(args.requests)
+        arrivals = np.cumsum(rng.exponential(1.0 / (load * capacity), len(reqs)))
+        t, lat = run(reqs, arrivals)
+        ev = sum(B.scs_ctx_stats(ctx, reset=True)[0] for _, ctx in searches)
+        levels.append({"offered_load": load, "offered_rps": load * capacity, "achieved_rps": len(reqs) / t,
+                       "evals_per_s": ev / t, "requests": len(reqs),
+                       "latency_ms": {"p50": float(np.median(lat)), "p99": float(np.quantile(lat, 0.99))}})
+        log(f"load {load}: {len(reqs) / t:.1f} req/s, p50 {np.median(lat):.1f} ms, p99 {np.quantile(lat, 0.99):.1f} ms")
+    st = B.scs_server_stats(srv)
+    B.scs_server_destroy(srv)
+    for _, ctx in searches:
+        B.scs_ctx_destroy(ctx)
+    out = {"metric": "served statistic evaluations: p50/p99 request latency and throughput, FP64",
+           "value": levels[-1]["evals_per_s"], "unit": "evals/s", "n_gpus": 1, "steps": len(levels),
+           "warmup": 1, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic: eight seeded searches",
+           "config": {"workload": "8 searches, K in {2^19, 2^20, 2^21}, A+E; requests of 256-16384 particles "
+                                  "(log-uniform), N in " + str(ladder) + ", Poisson arrivals",
+                      "max_inflight": 32, "streams": 4, "hbm_budget_gib": budget >> 30},
+           "capacity_rps": capacity, "capacity_evals_per_s": ev_b / t_b, "levels": levels,
+           "server": {k: int(v) for k, v in st.items()}}
     print(json.dumps(out), flush=True)
 
 

@@ -169,10 +169,14 @@ typedef struct scs_batch_item {
 } scs_batch_item;
 
 /* Evaluate several swarms (uneven P and N, possibly different contexts on
- * one device) in one fused launch sequence: one prologue, one persistent
- * generate-and-reduce kernel pulling (swarm, particle group, chunk) work
- * items from a device queue, one finalize.  Results equal scs_evaluate on
- * each item alone.  Device pointers only. */
+ * one device) with ONE persistent generate-and-reduce launch per channel
+ * count: a fixed grid of workgroups takes (swarm, chunk, particle group)
+ * tiles of every item from a device counter.  The per-item prologues, edge
+ * searches and finalizes are queued before and after it.  Results equal
+ * scs_evaluate on each item alone, bit for bit.  Device pointers only.  Each
+ * item uses a workspace of its context (one per item index), so calls whose
+ * items share a context must be issued on one stream.  Errors: EINVAL (bad
+ * items, items on different devices), ENOMEM, EDEVICE. */
 int scs_evaluate_batched(const scs_batch_item* items, int32_t n_items, int32_t prec, void* stream);
 
 /* Capture scs_evaluate_batched for fixed items into a HIP graph; replay it
@@ -189,6 +193,66 @@ int scs_graph_destroy(scs_graph* g);
  * (nullable) is a text file of "key waves blocks" lines, read before tuning
  * (a hit skips the timing) and rewritten after. */
 int scs_autotune(scs_ctx* ctx, int64_t P, const double* theta_dev, int32_t N, int32_t prec, const char* cache_path);
+
+/* ---- serving ------------------------------------------------------- */
+
+/* A request loop for several concurrent searches (Sec 3: every search walks
+ * its own hierarchy of swarms and segment counts).  Each search is a context
+ * whose data stays on the device.  A worker thread admits submitted requests
+ * in arrival order while a request slot is free and the HBM footprint of the
+ * admitted requests (scs_footprint plus the request's theta and result
+ * buffers) stays within hbm_budget; everything admitted since the last
+ * launch goes into one batched launch (scs_evaluate_batched) on a free
+ * stream, so requests that arrive while others run join the next launch and
+ * their work overlaps on the device (continuous batching).  A request's
+ * result equals scs_evaluate of the same particles alone.
+ *
+ * Contexts given to a server are used by its worker thread: the caller must
+ * not use them concurrently until the server is destroyed.  Times are
+ * seconds on the server's monotonic clock (scs_server_clock). */
+typedef struct scs_server scs_server;
+
+typedef struct scs_request_done {
+    uint64_t id;
+    int32_t status;   /* SCS_OK or the error code of its launch */
+    int32_t pad;
+    double t_submit;  /* scs_server_submit returned */
+    double t_admit;   /* admitted (slot and memory reserved) */
+    double t_launch;  /* its batch was queued on a stream */
+    double t_done;    /* result copied to the caller's buffer */
+} scs_request_done;
+
+typedef struct scs_server_counters {
+    int64_t submitted, completed, failed;
+    int64_t launches;          /* batched launches */
+    int64_t max_batch;         /* most requests in one launch */
+    int64_t max_inflight;      /* most requests admitted at once */
+    uint64_t hbm_in_use;       /* footprint of the admitted requests [bytes] */
+    uint64_t hbm_peak;
+} scs_server_counters;
+
+/* max_inflight: request slots (1..1024); hbm_budget: bytes (> 0); n_streams:
+ * HIP streams the launches rotate over (1..16, default priority). */
+int scs_server_create(scs_server** out, int32_t device, int32_t max_inflight, uint64_t hbm_budget, int32_t n_streams);
+
+/* Queue an evaluation of P particles (theta, HOST [P][7], copied before the
+ * call returns) with N segments on search ctx.  ups (HOST [P]) must stay
+ * valid until the request is reported by scs_server_poll.  A request whose
+ * footprint alone exceeds the budget is rejected with ENOMEM.  Errors:
+ * EINVAL, ENOMEM, ESTATE (server stopping). */
+int scs_server_submit(scs_server* srv, scs_ctx* ctx, int32_t N, int64_t P, const double* theta, int32_t prec,
+                      double* ups, uint64_t* id);
+
+/* Report up to max_out finished requests (oldest first), waiting up to
+ * wait_ms milliseconds for the first one; *n_out = number reported. */
+int scs_server_poll(scs_server* srv, scs_request_done* out, int32_t max_out, int32_t wait_ms, int32_t* n_out);
+
+int scs_server_stats(scs_server* srv, scs_server_counters* out);
+double scs_server_clock(const scs_server* srv);
+
+/* Finish every admitted request, fail the ones not yet admitted (status
+ * ESTATE, reported by no further poll), and free the server. */
+int scs_server_destroy(scs_server* srv);
 
 /* ---- particle swarm (Sec 3.1) ---------------------------------------- */
 

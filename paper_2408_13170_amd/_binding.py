@@ -41,6 +41,17 @@ class scs_batch_item(C.Structure):
                 ("theta", C.c_void_p), ("ups", C.c_void_p), ("seg", C.c_void_p)]
 
 
+class scs_request_done(C.Structure):
+    _fields_ = [("id", C.c_uint64), ("status", C.c_int32), ("pad", C.c_int32), ("t_submit", C.c_double),
+                ("t_admit", C.c_double), ("t_launch", C.c_double), ("t_done", C.c_double)]
+
+
+class scs_server_counters(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64), ("launches", C.c_int64),
+                ("max_batch", C.c_int64), ("max_inflight", C.c_int64), ("hbm_in_use", C.c_uint64),
+                ("hbm_peak", C.c_uint64)]
+
+
 class scs_pso_params(C.Structure):
     _fields_ = [("omega", C.c_double), ("phi_p", C.c_double), ("phi_g", C.c_double),
                 ("eps", C.c_double * 7)]
@@ -78,8 +89,16 @@ _SIGS = {
                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint32, C.c_void_p],
     "scs_pso_best": [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+    "scs_server_create": [C.POINTER(C.c_void_p), C.c_int32, C.c_int32, C.c_uint64, C.c_int32],
+    "scs_server_submit": [C.c_void_p, C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p,
+                          C.POINTER(C.c_uint64)],
+    "scs_server_poll": [C.c_void_p, C.POINTER(scs_request_done), C.c_int32, C.c_int32, C.POINTER(C.c_int32)],
+    "scs_server_stats": [C.c_void_p, C.POINTER(scs_server_counters)],
+    "scs_server_clock": [C.c_void_p],
+    "scs_server_destroy": [C.c_void_p],
     "scs_last_error": [],
 }
+_RESTYPES = {"scs_last_error": C.c_char_p, "scs_server_clock": C.c_double}
 
 
 def lib():
@@ -93,7 +112,7 @@ def lib():
         for name, args in _SIGS.items():
             f = getattr(L, name)
             f.argtypes = args
-            f.restype = C.c_char_p if name == "scs_last_error" else C.c_int
+            f.restype = _RESTYPES.get(name, C.c_int)
         _lib = L
     return _lib
 
@@ -101,7 +120,7 @@ def lib():
 def header_symbols():
     """Names of every function declared in include/scs.h."""
     txt = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(scs_\w+)\s*\(", txt, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|double|const char\*)\s+(scs_\w+)\s*\(", txt, re.M)))
 
 
 def _check(rc):
@@ -339,3 +358,46 @@ def scs_pso_best(theta, vals, lo, hi, periodic, pbest, pbest_val, gbest, gbest_v
 def scs_last_error():
     m = lib().scs_last_error()
     return m.decode() if m else ""
+
+
+# ---------------------------------------------------------------- serving
+def scs_server_create(device=0, max_inflight=16, hbm_budget=8 << 30, n_streams=4):
+    h = C.c_void_p()
+    _check(lib().scs_server_create(C.byref(h), device, max_inflight, hbm_budget, n_streams))
+    return h
+
+
+def scs_server_submit(srv, ctx, N, theta, ups, prec=SCS_PREC_FP64):
+    """theta: numpy [P,7] float64 (copied); ups: numpy [P] float64, written when the request completes."""
+    if not (isinstance(theta, np.ndarray) and isinstance(ups, np.ndarray)):
+        raise TypeError("theta and ups must be numpy arrays (host memory)")
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    if ups.dtype != np.float64 or not ups.flags["C_CONTIGUOUS"] or ups.shape[0] != theta.shape[0]:
+        raise ValueError("ups must be a contiguous float64 array of P entries")
+    rid = C.c_uint64()
+    _check(lib().scs_server_submit(srv, ctx, N, theta.shape[0], C.c_void_p(theta.ctypes.data), prec,
+                                   C.c_void_p(ups.ctypes.data), C.byref(rid)))
+    return rid.value
+
+
+def scs_server_poll(srv, max_out=256, wait_ms=0):
+    """List of dicts (id, status, t_submit, t_admit, t_launch, t_done) of finished requests."""
+    arr = (scs_request_done * max_out)()
+    n = C.c_int32()
+    _check(lib().scs_server_poll(srv, arr, max_out, wait_ms, C.byref(n)))
+    return [{k: getattr(arr[i], k) for k in ("id", "status", "t_submit", "t_admit", "t_launch", "t_done")}
+            for i in range(n.value)]
+
+
+def scs_server_stats(srv):
+    c = scs_server_counters()
+    _check(lib().scs_server_stats(srv, C.byref(c)))
+    return {k: getattr(c, k) for k, _ in scs_server_counters._fields_}
+
+
+def scs_server_clock(srv):
+    return lib().scs_server_clock(srv)
+
+
+def scs_server_destroy(srv):
+    _check(lib().scs_server_destroy(srv))

@@ -9,7 +9,11 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
 #include <mutex>
+#include <thread>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -134,13 +138,26 @@ struct Workspace {
     double* stage = nullptr;
     int64_t P_last = 0;
     int N_last = 0;
-    // support-order permutation (radix sort of (k_hi, k_lo))
+    // support-order permutation (counting sort of (k_hi, k_lo) buckets)
     int64_t capSort = 0;
-    uint64_t* keys = nullptr;  // [2P]
-    int32_t* idx = nullptr;    // [P]
-    int32_t* perm = nullptr;   // [P]
-    int64_t capTemp = 0;
-    unsigned char* temp = nullptr;
+    int32_t* bucket = nullptr;  // [P]
+    int32_t* rank = nullptr;    // [P]
+    int32_t* perm = nullptr;    // [P]
+    unsigned* hist = nullptr;   // [kSortBuckets]
+};
+
+// Device descriptors of one fused batched launch: the MainArgs of every
+// item, the per-item first tile, the work counter; and the pinned host copy
+// they are uploaded from.  A ring of these lets eager batched calls overlap
+// without overwriting descriptors a queued launch still reads.
+struct BatchSlot {
+    int cap = 0;  // items
+    MainArgs* d_items = nullptr;
+    int64_t* d_start = nullptr;                // [2][cap + 1]
+    unsigned long long* d_counter = nullptr;  // [2]
+    MainArgs* h_items = nullptr;               // pinned
+    int64_t* h_start = nullptr;                // pinned
+    hipEvent_t done = nullptr;                 // recorded after the last launch that read the slot
 };
 
 struct TuneChoice {
@@ -178,9 +195,15 @@ struct scs_ctx {
     std::map<std::string, TuneChoice> tune;
     TuneChoice override_choice;
     bool has_override = false;
+    // fused batched launches whose first item is this context
+    int n_cu = 0;
+    static constexpr int kRing = 4;
+    BatchSlot ring[kRing];
+    int ring_next = 0;
 };
 
 static int build_gtab(scs_ctx* c);
+static void free_slot(BatchSlot& b);
 
 struct DevScope {
     int prev = -1;
@@ -222,10 +245,10 @@ static void free_ws(Workspace& w)
     hipFree(w.bounds);
     hipFree(w.rec);
     hipFree(w.stage);
-    hipFree(w.keys);
-    hipFree(w.idx);
+    hipFree(w.bucket);
+    hipFree(w.rank);
     hipFree(w.perm);
-    hipFree(w.temp);
+    hipFree(w.hist);
     w = Workspace();
 }
 
@@ -241,6 +264,8 @@ extern "C" int scs_ctx_create(scs_ctx** out, int device)
     scs_ctx* c = new (std::nothrow) scs_ctx();
     if (!c) return fail(SCS_ENOMEM, "host allocation failed");
     c->device = device;
+    if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || c->n_cu < 1)
+        c->n_cu = 256;
     if (hipMalloc((void**)&c->counters, 3 * sizeof(unsigned long long)) != hipSuccess) {
         delete c;
         return fail(SCS_ENOMEM, "counter allocation failed");
@@ -261,6 +286,7 @@ extern "C" int scs_ctx_destroy(scs_ctx* c)
     DevScope ds(c->device);
     hipDeviceSynchronize();
     for (auto& kv : c->ws) free_ws(kv.second);
+    for (auto& b : c->ring) free_slot(b);
     for (auto& e : c->ev) {
         hipEventDestroy(e.first);
         hipEventDestroy(e.second);
@@ -490,28 +516,44 @@ static int ensure_ws(scs_ctx* c, Workspace& w, int64_t P, int N, const Plan& pl)
     if ((rc = grow(&w.bounds, &w.capBounds, P * (int64_t)(N + 1)))) return rc;
     if ((rc = grow(&w.rec, &w.capRec, pl.n_chunks * 7 * w.capP))) return rc;
     if (P >= kSortMin && P > w.capSort) {
-        int64_t c1 = 0, c2 = 0, c3 = 0;
-        hipFree(w.keys);
-        hipFree(w.idx);
+        int64_t c1 = 0, c2 = 0, c3 = 0, c4 = 0;
+        hipFree(w.bucket);
+        hipFree(w.rank);
         hipFree(w.perm);
-        w.keys = nullptr;
-        w.idx = w.perm = nullptr;
+        hipFree(w.hist);
+        w.bucket = w.rank = w.perm = nullptr;
+        w.hist = nullptr;
         w.capSort = 0;
-        if ((rc = grow(&w.keys, &c1, 2 * w.capP)) || (rc = grow(&w.idx, &c2, w.capP)) || (rc = grow(&w.perm, &c3, w.capP)))
+        if ((rc = grow(&w.bucket, &c1, w.capP)) || (rc = grow(&w.rank, &c2, w.capP)) ||
+            (rc = grow(&w.perm, &c3, w.capP)) || (rc = grow(&w.hist, &c4, (int64_t)kSortBuckets)))
             return rc;
         w.capSort = w.capP;
-        if ((rc = grow(&w.temp, &w.capTemp, (int64_t)sort_temp_bytes(w.capP)))) return rc;
     }
     return SCS_OK;
 }
 
-// Queue the whole evaluation on stream s (device pointers).
-static int run_eval(scs_ctx* c, Workspace& w, int64_t P, int N, const double* theta, int prec, double* ups,
-                    double* seg, hipStream_t s, const TuneChoice* force = nullptr)
+// One evaluation, queued in stages: front (prologue, support sort, edges),
+// the generate-and-reduce (solo or inside a fused batched launch), back
+// (finalize).  Device pointers throughout.
+struct EvalJob {
+    scs_ctx* c = nullptr;
+    Workspace* w = nullptr;
+    int64_t P = 0;
+    int N = 1;
+    Plan pl{};
+    MainArgs ma{};
+    FinalArgs fa{};
+};
+
+static int eval_front(EvalJob& j, const double* theta, double* ups, double* seg, const TuneChoice& t, hipStream_t s)
 {
-    const TuneChoice t = force ? *force : choose(c, P, N, prec);
-    const Plan pl = make_plan(c, P, t);
-    int rc = ensure_ws(c, w, P, N, pl);
+    scs_ctx* c = j.c;
+    Workspace& w = *j.w;
+    const int64_t P = j.P;
+    const int N = j.N;
+    if (c->mode == SCS_SEG_EXPLICIT && N != c->N) return fail(SCS_EINVAL, "EXPLICIT edges were defined for N = %d", c->N);
+    j.pl = make_plan(c, P, t);
+    int rc = ensure_ws(c, w, P, N, j.pl);
     if (rc) return rc;
     w.P_last = P;
     w.N_last = N;
@@ -533,10 +575,7 @@ static int run_eval(scs_ctx* c, Workspace& w, int64_t P, int N, const double* th
     launch_prologue(pa, s);
     const int32_t* perm = nullptr;
     if (P >= kSortMin && w.perm) {
-        int kb = 32;
-        while (kb < 64 && ((int64_t)1 << (kb - 32)) <= c->g.K) ++kb;
-        hipError_t e = launch_sort_perm(P, w.klo, w.khi, w.keys, w.idx, w.perm, w.temp, (size_t)w.capTemp, kb, s);
-        if (e != hipSuccess) return fail(SCS_EDEVICE, "support sort failed: %s", hipGetErrorString(e));
+        launch_sort_perm(P, c->g.K, w.klo, w.khi, w.hist, w.bucket, w.rank, w.perm, s);
         perm = w.perm;
     }
     BoundArgs ba{};
@@ -554,9 +593,9 @@ static int run_eval(scs_ctx* c, Workspace& w, int64_t P, int N, const double* th
     ba.b64 = c->b64;
     ba.edges = c->d_edges;
     ba.bounds = w.bounds;
-    if (c->mode == SCS_SEG_EXPLICIT && N != c->N) return fail(SCS_EINVAL, "EXPLICIT edges were defined for N = %d", c->N);
     launch_bounds(ba, s);
-    MainArgs ma{};
+    MainArgs& ma = j.ma;
+    ma = MainArgs{};
     ma.g = c->g;
     ma.m = c->m;
     ma.p0 = 0;
@@ -564,10 +603,10 @@ static int run_eval(scs_ctx* c, Workspace& w, int64_t P, int N, const double* th
     ma.stride = w.capP;
     ma.N = N;
     ma.L = c->L;
-    ma.CB = pl.CB;
+    ma.CB = j.pl.CB;
     ma.chunk0 = 0;
-    ma.n_groups = pl.n_groups;
-    ma.n_tiles = pl.n_tiles;
+    ma.n_groups = j.pl.n_groups;
+    ma.n_tiles = j.pl.n_tiles;
     ma.rec_stride = w.capP;
     ma.coef = w.coef;
     ma.klo = w.klo;
@@ -583,24 +622,14 @@ static int run_eval(scs_ctx* c, Workspace& w, int64_t P, int N, const double* th
     ma.seg = seg;
     ma.zscale32 = c->zscale32;
     ma.hscale32 = c->hscale32;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (c->prof) {
-        hipEventCreate(&e0);
-        hipEventCreate(&e1);
-        hipEventRecord(e0, s);
-    }
-    launch_main(ma, pl.waves, prec == SCS_PREC_MIXED, s);
-    if (c->prof) {
-        hipEventRecord(e1, s);
-        c->ev.emplace_back(e0, e1);
-    }
-    FinalArgs fa{};
+    FinalArgs& fa = j.fa;
+    fa = FinalArgs{};
     fa.K = c->g.K;
     fa.df = c->g.df;
     fa.p0 = 0;
     fa.P_end = P;
     fa.N = N;
-    fa.cbins = pl.cbins;
+    fa.cbins = j.pl.cbins;
     fa.chunk0 = 0;
     fa.rec_stride = w.capP;
     fa.klo = w.klo;
@@ -611,7 +640,42 @@ static int run_eval(scs_ctx* c, Workspace& w, int64_t P, int N, const double* th
     fa.rec = w.rec;
     fa.ups = ups;
     fa.seg = seg;
-    launch_finalize(fa, s);
+    return SCS_OK;
+}
+
+static void prof_begin(scs_ctx* c, hipStream_t s, hipEvent_t* e0)
+{
+    *e0 = nullptr;
+    if (!c->prof) return;
+    hipEventCreate(e0);
+    hipEventRecord(*e0, s);
+}
+static void prof_end(scs_ctx* c, hipStream_t s, hipEvent_t e0)
+{
+    if (!c->prof || !e0) return;
+    hipEvent_t e1 = nullptr;
+    hipEventCreate(&e1);
+    hipEventRecord(e1, s);
+    c->ev.emplace_back(e0, e1);
+}
+
+// Queue the whole evaluation on stream s (device pointers).
+static int run_eval(scs_ctx* c, Workspace& w, int64_t P, int N, const double* theta, int prec, double* ups,
+                    double* seg, hipStream_t s, const TuneChoice* force = nullptr)
+{
+    EvalJob j;
+    j.c = c;
+    j.w = &w;
+    j.P = P;
+    j.N = N;
+    const TuneChoice t = force ? *force : choose(c, P, N, prec);
+    int rc = eval_front(j, theta, ups, seg, t, s);
+    if (rc || P == 0) return rc;
+    hipEvent_t e0;
+    prof_begin(c, s, &e0);
+    launch_main(j.ma, j.pl.waves, prec == SCS_PREC_MIXED, s);
+    prof_end(c, s, e0);
+    launch_finalize(j.fa, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(SCS_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     c->last_stream = s;
@@ -803,26 +867,137 @@ extern "C" int scs_footprint(const scs_ctx* c, int64_t P, int32_t N, int32_t pre
 }
 
 // ---------------------------------------------------------------- batched
-// Items are evaluated back to back on one stream; every item owns a
-// workspace slot of its context, so items may share a context.
-extern "C" int scs_evaluate_batched(const scs_batch_item* items, int32_t n_items, int32_t prec, void* stream)
+// Every item owns a workspace slot of its context (slot 1 + its index), so
+// items may share a context; calls that share a context must be issued on
+// one stream.  The prologues, sorts and edges of the items are queued first,
+// then ONE persistent generate-and-reduce launch per channel count covers
+// the tiles of all its items (workgroups take tiles from a device counter),
+// then the finalizes.
+
+static void free_slot(BatchSlot& b)
+{
+    if (b.done) hipEventSynchronize(b.done);
+    hipFree(b.d_items);
+    hipFree(b.d_start);
+    hipFree(b.d_counter);
+    hipHostFree(b.h_items);
+    hipHostFree(b.h_start);
+    if (b.done) hipEventDestroy(b.done);
+    b = BatchSlot();
+}
+
+static int slot_reserve(BatchSlot& b, int n)
+{
+    if (b.done) HIP_TRY(hipEventSynchronize(b.done));  // the launch that last read it has finished
+    if (n <= b.cap) return SCS_OK;
+    free_slot(b);
+    const int cap = std::max(n, 8);
+    if (hipMalloc((void**)&b.d_items, sizeof(MainArgs) * cap) != hipSuccess ||
+        hipMalloc((void**)&b.d_start, sizeof(int64_t) * 2 * (cap + 1)) != hipSuccess ||
+        hipMalloc((void**)&b.d_counter, sizeof(unsigned long long) * 2) != hipSuccess ||
+        hipHostMalloc((void**)&b.h_items, sizeof(MainArgs) * cap) != hipSuccess ||
+        hipHostMalloc((void**)&b.h_start, sizeof(int64_t) * 2 * (cap + 1)) != hipSuccess ||
+        hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess) {
+        free_slot(b);
+        return fail(SCS_ENOMEM, "batch descriptor allocation failed");
+    }
+    b.cap = cap;
+    return SCS_OK;
+}
+
+static int check_items(const scs_batch_item* items, int32_t n_items, int32_t prec)
 {
     if (!items || n_items < 0) return fail(SCS_EINVAL, "bad items");
     if (prec != SCS_PREC_FP64 && prec != SCS_PREC_MIXED) return fail(SCS_EINVAL, "bad precision");
-    hipStream_t s = (hipStream_t)stream;
     for (int i = 0; i < n_items; ++i) {
         const scs_batch_item& it = items[i];
         int rc = check_ready(it.ctx);
         if (rc) return rc;
         if (it.N < 1 || it.P < 0 || (it.P > 0 && (!it.theta || !it.ups)))
             return fail(SCS_EINVAL, "item %d: bad N, P or pointers", i);
+        if (it.ctx->device != items[0].ctx->device || it.ctx->L != items[0].ctx->L)
+            return fail(SCS_EINVAL, "item %d: all items of a batch must share the device", i);
     }
+    return SCS_OK;
+}
+
+// Queue a batch on s using the descriptors of slot b.  upload: copy the
+// descriptors from the pinned host copy (skipped under graph capture, where
+// they were uploaded when the graph was built and stay valid).
+// wss[i] (nullable) is the workspace of item i; by default slot 1 + i of its
+// context.
+static int run_batched(const scs_batch_item* items, int n_items, int prec, hipStream_t s, BatchSlot& b, bool upload,
+                       Workspace* const* wss = nullptr)
+{
+    const bool mixed = prec == SCS_PREC_MIXED;
+    constexpr int kWaves = 4;  // workgroup shape of the fused launch
+    std::vector<EvalJob> jobs(n_items);
     for (int i = 0; i < n_items; ++i) {
         const scs_batch_item& it = items[i];
-        DevScope ds(it.ctx->device);
-        int rc = run_eval(it.ctx, it.ctx->ws[1 + i], it.P, it.N, it.theta, prec, it.ups, it.seg, s);
+        EvalJob& j = jobs[i];
+        j.c = it.ctx;
+        j.w = (wss && wss[i]) ? wss[i] : &it.ctx->ws[1 + i];
+        j.P = it.P;
+        j.N = it.N;
+        TuneChoice t = choose(it.ctx, it.P, it.N, prec);
+        t.waves = kWaves;
+        int rc = eval_front(j, it.theta, it.ups, it.seg, t, s);
         if (rc) return rc;
     }
+    scs_ctx* c0 = items[0].ctx;
+    int off = 0;
+    for (int gi = 0; gi < 2; ++gi) {
+        const int nch = gi == 0 ? 2 : 1;
+        int cnt = 0;
+        int64_t total = 0;
+        int64_t* hs = b.h_start + gi * (b.cap + 1);
+        for (int i = 0; i < n_items; ++i) {
+            const EvalJob& j = jobs[i];
+            if (j.c->g.nch != nch || j.P == 0 || j.pl.n_tiles == 0) continue;
+            if (upload) {
+                b.h_items[off + cnt] = j.ma;
+                hs[cnt] = total;
+            }
+            total += j.pl.n_tiles;
+            ++cnt;
+        }
+        if (!cnt) continue;
+        if (upload) {
+            hs[cnt] = total;
+            HIP_TRY(hipMemcpyAsync(b.d_items + off, b.h_items + off, sizeof(MainArgs) * cnt, hipMemcpyHostToDevice, s));
+            HIP_TRY(hipMemcpyAsync(b.d_start + gi * (b.cap + 1), hs, sizeof(int64_t) * (cnt + 1), hipMemcpyHostToDevice, s));
+        }
+        launch_fill_u64(b.d_counter + gi, 1, 0ULL, s);
+        const int per_cu = main_multi_blocks_per_cu(nch, c0->L, kWaves, mixed);
+        const int64_t grid = std::min<int64_t>(total, (int64_t)c0->n_cu * per_cu);
+        hipEvent_t e0;
+        prof_begin(c0, s, &e0);
+        hipError_t e = launch_main_multi(b.d_items + off, b.d_start + gi * (b.cap + 1), cnt, b.d_counter + gi, nch, c0->L,
+                                         kWaves, mixed, (int)grid, s);
+        if (e != hipSuccess) return fail(SCS_EDEVICE, "fused launch failed: %s", hipGetErrorString(e));
+        prof_end(c0, s, e0);
+        off += cnt;
+    }
+    for (int i = 0; i < n_items; ++i)
+        if (jobs[i].P > 0) launch_finalize(jobs[i].fa, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(SCS_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    for (int i = 0; i < n_items; ++i) items[i].ctx->last_stream = s;
+    return SCS_OK;
+}
+
+extern "C" int scs_evaluate_batched(const scs_batch_item* items, int32_t n_items, int32_t prec, void* stream)
+{
+    int rc = check_items(items, n_items, prec);
+    if (rc || n_items == 0) return rc;
+    scs_ctx* c0 = items[0].ctx;
+    DevScope ds(c0->device);
+    hipStream_t s = (hipStream_t)stream;
+    BatchSlot& b = c0->ring[c0->ring_next];
+    c0->ring_next = (c0->ring_next + 1) % scs_ctx::kRing;
+    if ((rc = slot_reserve(b, n_items))) return rc;
+    if ((rc = run_batched(items, n_items, prec, s, b, true))) return rc;
+    HIP_TRY(hipEventRecord(b.done, s));
     return SCS_OK;
 }
 
@@ -830,35 +1005,38 @@ struct scs_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int device = 0;
+    BatchSlot slot;  // descriptors read by the captured fused launches
 };
 
 extern "C" int scs_graph_create(scs_graph** out, const scs_batch_item* items, int32_t n_items, int32_t prec)
 {
-    if (!out || !items || n_items < 1) return fail(SCS_EINVAL, "bad arguments");
+    if (!out) return fail(SCS_EINVAL, "out is NULL");
     *out = nullptr;
-    const int dev = items[0].ctx ? items[0].ctx->device : 0;
+    int rc = check_items(items, n_items, prec);
+    if (rc) return rc;
+    if (n_items < 1) return fail(SCS_EINVAL, "no items");
+    const int dev = items[0].ctx->device;
     DevScope ds(dev);
-    // first call outside capture: allocates every workspace
     hipStream_t s;
     HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-    int rc = scs_evaluate_batched(items, n_items, prec, s);
-    if (rc) {
-        hipStreamDestroy(s);
-        return rc;
-    }
-    HIP_TRY(hipStreamSynchronize(s));
     scs_graph* g = new scs_graph();
     g->device = dev;
-    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-        rc = scs_evaluate_batched(items, n_items, prec, s);
-        e = hipStreamEndCapture(s, &g->graph);
+    // one eager pass: allocates every workspace and uploads the descriptors
+    if ((rc = slot_reserve(g->slot, n_items)) == SCS_OK) rc = run_batched(items, n_items, prec, s, g->slot, true);
+    hipError_t e = hipStreamSynchronize(s);
+    if (rc == SCS_OK && e == hipSuccess) {
+        e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            rc = run_batched(items, n_items, prec, s, g->slot, false);
+            e = hipStreamEndCapture(s, &g->graph);
+        }
+        if (e == hipSuccess && rc == SCS_OK) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
     }
-    if (e == hipSuccess && rc == SCS_OK) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
     hipStreamDestroy(s);
     if (e != hipSuccess || rc != SCS_OK) {
         if (g->exec) hipGraphExecDestroy(g->exec);
         if (g->graph) hipGraphDestroy(g->graph);
+        free_slot(g->slot);
         delete g;
         return rc ? rc : fail(SCS_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
     }
@@ -871,6 +1049,7 @@ extern "C" int scs_graph_launch(scs_graph* g, void* stream)
     if (!g) return fail(SCS_EINVAL, "graph is NULL");
     DevScope ds(g->device);
     HIP_TRY(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    HIP_TRY(hipEventRecord(g->slot.done, (hipStream_t)stream));
     return SCS_OK;
 }
 
@@ -880,7 +1059,368 @@ extern "C" int scs_graph_destroy(scs_graph* g)
     DevScope ds(g->device);
     hipGraphExecDestroy(g->exec);
     hipGraphDestroy(g->graph);
+    free_slot(g->slot);
     delete g;
+    return SCS_OK;
+}
+
+// ---------------------------------------------------------------- serving
+namespace {
+
+struct SrvRequest {
+    uint64_t id = 0;
+    scs_ctx* ctx = nullptr;
+    int N = 1;
+    int64_t P = 0;
+    int prec = SCS_PREC_FP64;
+    double* ups_user = nullptr;
+    std::vector<double> theta;  // host copy
+    uint64_t bytes = 0;
+    int slot = -1;
+    double t_submit = 0, t_admit = 0, t_launch = 0;
+};
+
+// A request slot: device theta / result buffers, a workspace and the pinned
+// host buffers of its copies; kept and regrown across requests.
+struct SrvSlot {
+    bool busy = false;
+    int64_t cap = 0;
+    double* d_theta = nullptr;
+    double* d_ups = nullptr;
+    double* h_theta = nullptr;  // pinned
+    double* h_ups = nullptr;    // pinned
+    Workspace ws;
+};
+
+struct SrvBatch {
+    std::vector<SrvRequest*> reqs;
+    int stream = 0;
+    hipEvent_t done = nullptr;
+};
+
+}  // namespace
+
+struct scs_server {
+    int device = 0;
+    int max_inflight = 1;
+    uint64_t budget = 0;
+    std::chrono::steady_clock::time_point t0;
+    std::vector<hipStream_t> streams;
+    std::vector<bool> stream_busy;
+    std::vector<BatchSlot> bslots;  // descriptors, one per stream
+    std::vector<SrvSlot> slots;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<SrvRequest*> pending;
+    std::deque<scs_request_done> done;
+    std::vector<SrvBatch> inflight;
+    uint64_t next_id = 1;
+    bool stop = false;
+    scs_server_counters st{};
+    std::thread worker;
+
+    double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+    void run();
+    int launch(std::vector<SrvRequest*>& batch, int si);
+    void finish(SrvBatch& b, int status);
+};
+
+static uint64_t request_bytes(const scs_ctx* c, int64_t P, int N, int prec)
+{
+    const TuneChoice t = choose(c, P, N, prec);
+    return (uint64_t)ws_bytes(c, P, N, make_plan(c, P, t)) + (uint64_t)sizeof(double) * 8 * (uint64_t)std::max<int64_t>(P, 1);
+}
+
+static int slot_grow(SrvSlot& s, int64_t P)
+{
+    if (P <= s.cap) return SCS_OK;
+    hipFree(s.d_theta);
+    hipFree(s.d_ups);
+    hipHostFree(s.h_theta);
+    hipHostFree(s.h_ups);
+    s.d_theta = s.d_ups = s.h_theta = s.h_ups = nullptr;
+    s.cap = 0;
+    const int64_t cap = std::max<int64_t>(P, 256);
+    if (hipMalloc((void**)&s.d_theta, sizeof(double) * 7 * cap) != hipSuccess ||
+        hipMalloc((void**)&s.d_ups, sizeof(double) * cap) != hipSuccess ||
+        hipHostMalloc((void**)&s.h_theta, sizeof(double) * 7 * cap) != hipSuccess ||
+        hipHostMalloc((void**)&s.h_ups, sizeof(double) * cap) != hipSuccess)
+        return fail(SCS_ENOMEM, "request buffers of %lld particles", (long long)P);
+    s.cap = cap;
+    return SCS_OK;
+}
+
+// Queue one batched launch of the admitted requests on stream si.
+int scs_server::launch(std::vector<SrvRequest*>& batch, int si)
+{
+    hipStream_t s = streams[si];
+    std::vector<scs_batch_item> items(batch.size());
+    std::vector<Workspace*> wss(batch.size());
+    int rc = SCS_OK;
+    for (size_t i = 0; i < batch.size() && rc == SCS_OK; ++i) {
+        SrvRequest* r = batch[i];
+        SrvSlot& sl = slots[r->slot];
+        if ((rc = slot_grow(sl, r->P))) break;
+        std::memcpy(sl.h_theta, r->theta.data(), sizeof(double) * 7 * r->P);
+        if (hipMemcpyAsync(sl.d_theta, sl.h_theta, sizeof(double) * 7 * r->P, hipMemcpyHostToDevice, s) != hipSuccess)
+            rc = fail(SCS_EDEVICE, "theta upload failed");
+        items[i] = scs_batch_item{r->ctx, r->N, 0, r->P, sl.d_theta, sl.d_ups, nullptr};
+        wss[i] = &sl.ws;
+    }
+    // one precision per launch: split the batch if it mixes them
+    for (int prec : {SCS_PREC_FP64, SCS_PREC_MIXED}) {
+        if (rc) break;
+        std::vector<scs_batch_item> it2;
+        std::vector<Workspace*> w2;
+        for (size_t i = 0; i < batch.size(); ++i)
+            if (batch[i]->prec == prec) {
+                it2.push_back(items[i]);
+                w2.push_back(wss[i]);
+            }
+        if (it2.empty()) continue;
+        BatchSlot& b = bslots[si];
+        if ((rc = slot_reserve(b, (int)it2.size()))) break;
+        if ((rc = run_batched(it2.data(), (int)it2.size(), prec, s, b, true, w2.data()))) break;
+        if (hipEventRecord(b.done, s) != hipSuccess) rc = fail(SCS_EDEVICE, "event record failed");
+    }
+    for (size_t i = 0; i < batch.size() && rc == SCS_OK; ++i) {
+        SrvSlot& sl = slots[batch[i]->slot];
+        if (hipMemcpyAsync(sl.h_ups, sl.d_ups, sizeof(double) * batch[i]->P, hipMemcpyDeviceToHost, s) != hipSuccess)
+            rc = fail(SCS_EDEVICE, "result download failed");
+    }
+    return rc;
+}
+
+void scs_server::finish(SrvBatch& b, int status)
+{
+    const double t = now();
+    for (SrvRequest* r : b.reqs) {
+        if (status == SCS_OK) std::memcpy(r->ups_user, slots[r->slot].h_ups, sizeof(double) * r->P);
+        scs_request_done d{};
+        d.id = r->id;
+        d.status = status;
+        d.t_submit = r->t_submit;
+        d.t_admit = r->t_admit;
+        d.t_launch = r->t_launch;
+        d.t_done = t;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            slots[r->slot].busy = false;
+            st.hbm_in_use -= r->bytes;
+            if (status == SCS_OK) ++st.completed; else ++st.failed;
+            done.push_back(d);
+        }
+        delete r;
+    }
+    b.reqs.clear();
+    cv_done.notify_all();
+}
+
+void scs_server::run()
+{
+    DevScope ds(device);
+    while (true) {
+        // ---- completions
+        for (size_t k = 0; k < inflight.size();) {
+            const hipError_t q = hipEventQuery(inflight[k].done);
+            if (q == hipErrorNotReady) {
+                ++k;
+                continue;
+            }
+            finish(inflight[k], q == hipSuccess ? SCS_OK : SCS_EDEVICE);
+            hipEventDestroy(inflight[k].done);
+            stream_busy[inflight[k].stream] = false;
+            inflight.erase(inflight.begin() + k);
+        }
+        // ---- admission: arrival order, while a slot, the memory and a stream are free
+        std::vector<SrvRequest*> batch;
+        int si = -1;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            if (stop && pending.empty() && inflight.empty()) break;
+            for (int i = 0; i < (int)streams.size(); ++i)
+                if (!stream_busy[i]) {
+                    si = i;
+                    break;
+                }
+            if (si >= 0) {
+                while (!pending.empty()) {
+                    SrvRequest* r = pending.front();
+                    if (st.hbm_in_use + r->bytes > budget) break;
+                    int free_slot_i = -1;
+                    for (int i = 0; i < max_inflight; ++i)
+                        if (!slots[i].busy) {
+                            free_slot_i = i;
+                            break;
+                        }
+                    if (free_slot_i < 0) break;
+                    pending.pop_front();
+                    slots[free_slot_i].busy = true;
+                    r->slot = free_slot_i;
+                    r->t_admit = now();
+                    st.hbm_in_use += r->bytes;
+                    st.hbm_peak = std::max(st.hbm_peak, st.hbm_in_use);
+                    batch.push_back(r);
+                }
+                int64_t busy = 0;
+                for (auto& sl : slots) busy += sl.busy;
+                st.max_inflight = std::max<int64_t>(st.max_inflight, busy);
+            }
+            if (batch.empty()) {
+                if (inflight.empty()) cv_work.wait_for(lk, std::chrono::milliseconds(2));
+            }
+        }
+        if (batch.empty()) {
+            if (!inflight.empty()) std::this_thread::sleep_for(std::chrono::microseconds(20));
+            continue;
+        }
+        const double tl = now();
+        for (SrvRequest* r : batch) r->t_launch = tl;
+        SrvBatch b;
+        b.reqs = batch;
+        b.stream = si;
+        int rc = launch(batch, si);
+        if (rc == SCS_OK && hipEventCreateWithFlags(&b.done, hipEventDisableTiming) == hipSuccess &&
+            hipEventRecord(b.done, streams[si]) == hipSuccess) {
+            stream_busy[si] = true;
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                ++st.launches;
+                st.max_batch = std::max<int64_t>(st.max_batch, (int64_t)batch.size());
+            }
+            inflight.push_back(b);
+        } else {
+            if (b.done) hipEventDestroy(b.done);
+            hipStreamSynchronize(streams[si]);
+            finish(b, rc ? rc : SCS_EDEVICE);
+        }
+    }
+}
+
+extern "C" int scs_server_create(scs_server** out, int32_t device, int32_t max_inflight, uint64_t hbm_budget,
+                                 int32_t n_streams)
+{
+    if (!out) return fail(SCS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (max_inflight < 1 || max_inflight > 1024) return fail(SCS_EINVAL, "max_inflight must be in 1..1024");
+    if (n_streams < 1 || n_streams > 16) return fail(SCS_EINVAL, "n_streams must be in 1..16");
+    if (hbm_budget == 0) return fail(SCS_EINVAL, "hbm_budget must be > 0");
+    int rc = device_setup(device);
+    if (rc) return rc;
+    DevScope ds(device);
+    scs_server* s = new (std::nothrow) scs_server();
+    if (!s) return fail(SCS_ENOMEM, "host allocation failed");
+    s->device = device;
+    s->max_inflight = max_inflight;
+    s->budget = hbm_budget;
+    s->t0 = std::chrono::steady_clock::now();
+    s->slots.resize(max_inflight);
+    s->bslots.resize(n_streams);
+    s->stream_busy.assign(n_streams, false);
+    for (int i = 0; i < n_streams; ++i) {
+        hipStream_t st;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            for (auto x : s->streams) hipStreamDestroy(x);
+            delete s;
+            return fail(SCS_EDEVICE, "stream creation failed");
+        }
+        s->streams.push_back(st);
+    }
+    s->worker = std::thread([s] { s->run(); });
+    *out = s;
+    return SCS_OK;
+}
+
+extern "C" int scs_server_submit(scs_server* srv, scs_ctx* ctx, int32_t N, int64_t P, const double* theta, int32_t prec,
+                                 double* ups, uint64_t* id)
+{
+    if (!srv) return fail(SCS_EINVAL, "server is NULL");
+    int rc = check_ready(ctx);
+    if (rc) return rc;
+    if (ctx->device != srv->device) return fail(SCS_EINVAL, "context is on device %d, server on %d", ctx->device, srv->device);
+    if (N < 1 || P < 1 || !theta || !ups) return fail(SCS_EINVAL, "bad N, P or pointers");
+    if (prec != SCS_PREC_FP64 && prec != SCS_PREC_MIXED) return fail(SCS_EINVAL, "bad precision");
+    if (ctx->mode == SCS_SEG_EXPLICIT && N != ctx->N) return fail(SCS_EINVAL, "EXPLICIT edges were defined for N = %d", ctx->N);
+    const uint64_t bytes = request_bytes(ctx, P, N, prec);
+    if (bytes > srv->budget)
+        return fail(SCS_ENOMEM, "request needs %llu bytes, budget is %llu", (unsigned long long)bytes,
+                    (unsigned long long)srv->budget);
+    SrvRequest* r = new (std::nothrow) SrvRequest();
+    if (!r) return fail(SCS_ENOMEM, "host allocation failed");
+    r->ctx = ctx;
+    r->N = N;
+    r->P = P;
+    r->prec = prec;
+    r->ups_user = ups;
+    r->theta.assign(theta, theta + 7 * P);
+    r->bytes = bytes;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        if (srv->stop) {
+            delete r;
+            return fail(SCS_ESTATE, "server is stopping");
+        }
+        r->id = srv->next_id++;
+        r->t_submit = srv->now();
+        srv->pending.push_back(r);
+        ++srv->st.submitted;
+        if (id) *id = r->id;
+    }
+    srv->cv_work.notify_one();
+    return SCS_OK;
+}
+
+extern "C" int scs_server_poll(scs_server* srv, scs_request_done* out, int32_t max_out, int32_t wait_ms, int32_t* n_out)
+{
+    if (!srv || (!out && max_out > 0) || !n_out) return fail(SCS_EINVAL, "NULL argument");
+    std::unique_lock<std::mutex> lk(srv->mu);
+    if (srv->done.empty() && wait_ms > 0)
+        srv->cv_done.wait_for(lk, std::chrono::milliseconds(wait_ms), [srv] { return !srv->done.empty(); });
+    int n = 0;
+    while (n < max_out && !srv->done.empty()) {
+        out[n++] = srv->done.front();
+        srv->done.pop_front();
+    }
+    *n_out = n;
+    return SCS_OK;
+}
+
+extern "C" int scs_server_stats(scs_server* srv, scs_server_counters* out)
+{
+    if (!srv || !out) return fail(SCS_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    *out = srv->st;
+    return SCS_OK;
+}
+
+extern "C" double scs_server_clock(const scs_server* srv) { return srv ? srv->now() : 0.0; }
+
+extern "C" int scs_server_destroy(scs_server* srv)
+{
+    if (!srv) return SCS_OK;
+    std::deque<SrvRequest*> dropped;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stop = true;
+        dropped.swap(srv->pending);
+    }
+    for (SrvRequest* r : dropped) delete r;
+    srv->cv_work.notify_all();
+    if (srv->worker.joinable()) srv->worker.join();
+    DevScope ds(srv->device);
+    for (auto st : srv->streams) {
+        hipStreamSynchronize(st);
+        hipStreamDestroy(st);
+    }
+    for (auto& b : srv->bslots) free_slot(b);
+    for (auto& sl : srv->slots) {
+        hipFree(sl.d_theta);
+        hipFree(sl.d_ups);
+        hipHostFree(sl.h_theta);
+        hipHostFree(sl.h_ups);
+        free_ws(sl.ws);
+    }
+    delete srv;
     return SCS_OK;
 }
 

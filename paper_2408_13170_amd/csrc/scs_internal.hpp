@@ -12,7 +12,7 @@ constexpr int kGStride = 56;  // doubles per basis-table entry: 8 functions x 6 
 constexpr int kGHi = 48;
 constexpr int kGLo = 49;
 constexpr int kMaxLevel = 10;  // sub-block lengths 2^3 .. 2^9
-constexpr int kTrig = 1024;       // entries of the (cos, sin)(2 pi i / kTrig) table
+constexpr int kTrig = 512;        // entries of the (cos, sin)(2 pi i / kTrig) table
 constexpr int kCoefStride = 56;  // doubles per particle record of the coefficient buffer
 
 struct GridArgs {
@@ -132,6 +132,9 @@ void launch_prologue(const PrologueArgs& a, hipStream_t s);
 void launch_bounds(const BoundArgs& a, hipStream_t s);
 size_t main_lds_bytes(int nch, int L, bool mixed);
 void launch_main(const MainArgs& a, int waves, bool mixed, hipStream_t s);
+hipError_t launch_main_multi(const MainArgs* items, const int64_t* tile_start, int n_items, unsigned long long* counter,
+                             int nch, int L, int waves, bool mixed, int grid, hipStream_t s);
+int main_multi_blocks_per_cu(int nch, int L, int waves, bool mixed);
 void launch_finalize(const FinalArgs& a, hipStream_t s);
 void launch_waveform(const MainArgs& a, double* h_ri, hipStream_t s);
 void launch_gtab(const GridArgs& g, int lg, int64_t nsub, double* tab, hipStream_t s);
@@ -140,9 +143,9 @@ void launch_pso_move(int64_t P, const PsoBox& box, const PsoParams& prm, uint64_
                      double* theta, double* vel, const double* pbest, const double* gbest, hipStream_t s);
 void launch_pso_best(int64_t P, const PsoBox& box, const double* theta, const double* vals, double* pbest,
                      double* pbest_val, double* gbest, double* gbest_val, hipStream_t s);
-size_t sort_temp_bytes(int64_t P);
-hipError_t launch_sort_perm(int64_t P, const int32_t* klo, const int32_t* khi, uint64_t* keys, int32_t* idx,
-                            int32_t* perm, void* temp, size_t temp_bytes, int key_bits, hipStream_t s);
+constexpr int kSortBuckets = 65536;  // 256 levels of k_hi x 256 levels of k_lo
+void launch_sort_perm(int64_t P, int64_t K, const int32_t* klo, const int32_t* khi, unsigned* hist, int32_t* bucket,
+                      int32_t* rank, int32_t* perm, hipStream_t s);
 void launch_fill(double* p, int64_t n, double v, hipStream_t s);
 void launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
 

@@ -37,3 +37,18 @@ def test_context_creation_fails_cleanly_without_gpu():
     rc = B.lib().scs_ctx_create(C.byref(h), 0)
     assert rc == -3 and not h.value
     assert B.scs_last_error()
+
+
+def test_server_arguments_are_checked_before_any_device_work():
+    L = B.lib()
+    h = C.c_void_p()
+    assert L.scs_server_create(None, 0, 4, 1 << 30, 2) == -1
+    assert L.scs_server_create(C.byref(h), 0, 0, 1 << 30, 2) == -1  # no request slot
+    assert L.scs_server_create(C.byref(h), 0, 4, 0, 2) == -1        # no memory budget
+    assert L.scs_server_create(C.byref(h), 0, 4, 1 << 30, 17) == -1  # too many streams
+    assert not h.value
+    n = C.c_int32()
+    assert L.scs_server_submit(None, None, 1, 1, None, 0, None, None) == -1
+    assert L.scs_server_poll(None, None, 0, 0, C.byref(n)) == -1
+    assert L.scs_server_destroy(None) == 0
+    assert B.scs_server_clock(None) == 0.0

@@ -1,0 +1,76 @@
+"""The request loop: requests of two searches (different channel counts,
+segment counts, swarm sizes and precisions) submitted while others run are
+admitted within the slot and HBM limits, batched, and each result equals the
+evaluation of the same particles alone, bit for bit."""
+import time
+
+import numpy as np
+import pytest
+
+import synth
+from tests import datasets as D
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2408_13170_amd import B  # noqa: E402
+
+
+def _ctx(ds, G):
+    g = ds.grid
+    h = B.scs_ctx_create(0)
+    B.scs_load_data(h, np.ascontiguousarray(ds.d_ri), np.ascontiguousarray(ds.psd), g.k0 * g.df, g.df)
+    m = ds.model
+    B.scs_set_model(h, m.pn_order, m.response, m.support, m.t_obs)
+    B.scs_define_segmentation(h, 1, B.SCS_SEG_EQUAL_SNR, G)
+    return h
+
+
+def test_served_results_equal_alone():
+    lisa, white = D.lisa_small(seed=21), D.white16k()
+    hl, hw = _ctx(lisa, 16), _ctx(white, 1)
+    wth = synth.workload_particles(synth.workload("white16k"))
+    rng = np.random.default_rng(5)
+    reqs = []
+    for r in range(24):
+        if r % 3 == 2:
+            P = int(rng.integers(8, 65))
+            reqs.append(dict(h=hw, G=1, N=int(rng.choice([1, 4, 16])), th=wth[:P].copy(),
+                             prec=B.SCS_PREC_FP64 if r % 2 else B.SCS_PREC_MIXED))
+        else:
+            P = int(rng.integers(16, 400))
+            reqs.append(dict(h=hl, G=16, N=int(rng.choice([1, 8, 64, 256])),
+                             th=D.lisa_particles(P, seed=300 + r),
+                             prec=B.SCS_PREC_FP64 if r % 2 else B.SCS_PREC_MIXED))
+    try:
+        fp = max(B.scs_footprint(q["h"], q["th"].shape[0], q["N"], q["prec"]) for q in reqs)
+        budget = 3 * (fp + 8 * 8 * 400)
+        srv = B.scs_server_create(0, max_inflight=4, hbm_budget=budget, n_streams=2)
+        try:
+            ids = {}
+            for k, q in enumerate(reqs):
+                q["ups"] = np.full(q["th"].shape[0], -1.0)
+                ids[B.scs_server_submit(srv, q["h"], q["N"], q["th"], q["ups"], q["prec"])] = k
+                if k % 5 == 4:
+                    time.sleep(0.002)  # later requests arrive while earlier ones run
+            done = []
+            t_end = time.time() + 60
+            while len(done) < len(reqs) and time.time() < t_end:
+                done += B.scs_server_poll(srv, wait_ms=50)
+            st = B.scs_server_stats(srv)
+        finally:
+            B.scs_server_destroy(srv)
+        print("server stats", st)
+        assert len(done) == len(reqs) and all(d["status"] == 0 for d in done)
+        assert st["completed"] == len(reqs) and st["failed"] == 0
+        assert st["hbm_peak"] <= budget and st["max_inflight"] <= 4
+        assert all(d["t_submit"] <= d["t_admit"] <= d["t_launch"] <= d["t_done"] for d in done)
+        # alone: the same particles through scs_evaluate
+        for q in reqs:
+            B.scs_define_segmentation(q["h"], q["N"], B.SCS_SEG_EQUAL_SNR, q["G"])
+            u = np.empty(q["th"].shape[0])
+            B.scs_evaluate(q["h"], np.ascontiguousarray(q["th"]), u, q["prec"])
+            assert np.array_equal(u, q["ups"]), (q["N"], q["th"].shape[0], q["prec"])
+    finally:
+        B.scs_ctx_destroy(hl)
+        B.scs_ctx_destroy(hw)
