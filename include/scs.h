@@ -75,7 +75,7 @@ typedef struct scs_model {
     int32_t pn_order;        /* highest PN power of v in the phase, 0..7 (4 = 2PN, 7 = 3.5PN) */
     int32_t response;        /* SCS_RESP_* ; NONE needs 1 channel, LISA_LF_AE needs 2 */
     int32_t support;         /* SCS_SUPPORT_* */
-    int32_t block_len;       /* polynomial block length in bins (power of 2, 16..512); 0 = 512 */
+    int32_t block_len;       /* longest polynomial block in bins (power of 2, 16..2048); 0 = 2048 */
     double t_obs;            /* observation time [s]; 0 = 1/df */
     double orbit_phase0;     /* orbital angle of the constellation centre at t = 0 [rad] */
     double cartwheel_phase0; /* in-plane angle of spacecraft 0 at t = 0 [rad] */
@@ -104,7 +104,7 @@ int scs_load_data(scs_ctx* ctx, int32_t n_chan, int64_t K, double f_min, double 
 
 /* Set the waveform/response model.  Errors: pn_order outside 0..7, response
  * not matching the loaded channel count, block_len not a power of 2 in
- * 16..512, negative t_obs. */
+ * 16..2048, negative t_obs. */
 int scs_set_model(scs_ctx* ctx, const scs_model* model);
 
 /* Define the segmentation used by scs_evaluate (Sec 2.2).

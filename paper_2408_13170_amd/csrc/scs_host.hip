@@ -127,12 +127,14 @@ struct Workspace {
     int64_t capP = 0;
     int64_t capBounds = 0;  // int32 entries
     int64_t capRec = 0;     // doubles
+    int64_t capZs = 0;      // doubles
     double* coef = nullptr;
     int32_t* klo = nullptr;
     int32_t* khi = nullptr;
     int8_t* lg = nullptr;
     int32_t* bounds = nullptr;
     double* rec = nullptr;
+    double* zs = nullptr;  // [P][N][3] per-segment sums (when the caller asks for no segment output)
     // host-pointer staging
     int64_t capStage = 0;
     double* stage = nullptr;
@@ -244,6 +246,7 @@ static void free_ws(Workspace& w)
     hipFree(w.lg);
     hipFree(w.bounds);
     hipFree(w.rec);
+    hipFree(w.zs);
     hipFree(w.stage);
     hipFree(w.bucket);
     hipFree(w.rank);
@@ -393,8 +396,8 @@ extern "C" int scs_set_model(scs_ctx* c, const scs_model* m)
     if ((m->response == SCS_RESP_LISA_LF_AE) != (c->g.nch == 2))
         return fail(SCS_EINVAL, "response %d does not match %d loaded channels", m->response, c->g.nch);
     if (m->support != SCS_SUPPORT_FULL && m->support != SCS_SUPPORT_TOBS) return fail(SCS_EINVAL, "bad support");
-    int L = m->block_len ? m->block_len : 512;
-    if (L < 16 || L > 512 || (L & (L - 1))) return fail(SCS_EINVAL, "block_len must be a power of 2 in 16..512");
+    const int bl = m->block_len ? m->block_len : 2048;
+    if (bl < 16 || bl > 2048 || (bl & (bl - 1))) return fail(SCS_EINVAL, "block_len must be a power of 2 in 16..2048");
     if (m->t_obs < 0.0 || !std::isfinite(m->t_obs)) return fail(SCS_EINVAL, "bad t_obs");
     c->m.pn_order = m->pn_order;
     c->m.response = m->response;
@@ -403,9 +406,9 @@ extern "C" int scs_set_model(scs_ctx* c, const scs_model* m)
     double oc = m->orbit_phase0 / (2.0 * M_PI);
     c->m.orb0_cyc = oc - std::floor(oc);
     c->m.cart0 = m->cartwheel_phase0;
-    c->L = L;
+    c->L = 512;  // bins per LDS-staged block of the generate-and-reduce kernel
     int lg = 0;
-    while ((1 << lg) < L) ++lg;
+    while ((1 << lg) < bl) ++lg;
     c->lg_max = lg;
     c->has_model = true;
     DevScope ds(c->device);
@@ -488,7 +491,8 @@ static size_t ws_bytes(const scs_ctx* c, int64_t P, int N, const Plan& pl)
     b += sizeof(double) * (size_t)kCoefStride * Pp;
     b += (sizeof(int32_t) * 2 + 1) * (size_t)Pp;
     b += sizeof(int32_t) * (size_t)P * (N + 1);
-    b += sizeof(double) * (size_t)pl.n_chunks * 7 * Pp;
+    b += sizeof(double) * (size_t)pl.n_chunks * kRec * Pp;
+    b += sizeof(double) * 3 * (size_t)P * N;
     return b;
 }
 
@@ -514,7 +518,8 @@ static int ensure_ws(scs_ctx* c, Workspace& w, int64_t P, int N, const Plan& pl)
         w.capP = Pp;
     }
     if ((rc = grow(&w.bounds, &w.capBounds, P * (int64_t)(N + 1)))) return rc;
-    if ((rc = grow(&w.rec, &w.capRec, pl.n_chunks * 7 * w.capP))) return rc;
+    if ((rc = grow(&w.rec, &w.capRec, pl.n_chunks * kRec * w.capP))) return rc;
+    if ((rc = grow(&w.zs, &w.capZs, 3 * P * (int64_t)N))) return rc;
     if (P >= kSortMin && P > w.capSort) {
         int64_t c1 = 0, c2 = 0, c3 = 0, c4 = 0;
         hipFree(w.bucket);
@@ -619,7 +624,7 @@ static int eval_front(EvalJob& j, const double* theta, double* ups, double* seg,
     for (int l = 0; l < kMaxLevel; ++l) ma.gtab_off[l] = c->gtab_off[l];
     ma.perm = perm;
     ma.rec = w.rec;
-    ma.seg = seg;
+    ma.zs = seg ? seg : w.zs;
     ma.zscale32 = c->zscale32;
     ma.hscale32 = c->hscale32;
     FinalArgs& fa = j.fa;
@@ -638,6 +643,7 @@ static int eval_front(EvalJob& j, const double* theta, double* ups, double* seg,
     fa.bounds = w.bounds;
     fa.perm = perm;
     fa.rec = w.rec;
+    fa.zs = seg ? seg : w.zs;
     fa.ups = ups;
     fa.seg = seg;
     return SCS_OK;
@@ -659,6 +665,8 @@ static void prof_end(scs_ctx* c, hipStream_t s, hipEvent_t e0)
     c->ev.emplace_back(e0, e1);
 }
 
+static int eval_main(scs_ctx* c, EvalJob& j, int prec, hipStream_t s);
+
 // Queue the whole evaluation on stream s (device pointers).
 static int run_eval(scs_ctx* c, Workspace& w, int64_t P, int N, const double* theta, int prec, double* ups,
                     double* seg, hipStream_t s, const TuneChoice* force = nullptr)
@@ -671,10 +679,7 @@ static int run_eval(scs_ctx* c, Workspace& w, int64_t P, int N, const double* th
     const TuneChoice t = force ? *force : choose(c, P, N, prec);
     int rc = eval_front(j, theta, ups, seg, t, s);
     if (rc || P == 0) return rc;
-    hipEvent_t e0;
-    prof_begin(c, s, &e0);
-    launch_main(j.ma, j.pl.waves, prec == SCS_PREC_MIXED, s);
-    prof_end(c, s, e0);
+    if ((rc = eval_main(c, j, prec, s))) return rc;
     launch_finalize(j.fa, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(SCS_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
@@ -921,30 +926,13 @@ static int check_items(const scs_batch_item* items, int32_t n_items, int32_t pre
     return SCS_OK;
 }
 
-// Queue a batch on s using the descriptors of slot b.  upload: copy the
-// descriptors from the pinned host copy (skipped under graph capture, where
-// they were uploaded when the graph was built and stay valid).
-// wss[i] (nullable) is the workspace of item i; by default slot 1 + i of its
-// context.
-static int run_batched(const scs_batch_item* items, int n_items, int prec, hipStream_t s, BatchSlot& b, bool upload,
-                       Workspace* const* wss = nullptr)
+// The generate-and-reduce of prepared evaluations: one persistent launch per
+// channel count over the tiles of all of them (descriptors in slot b;
+// upload: copy them from the pinned host copy first).
+static int fused_main(std::vector<EvalJob>& jobs, int waves, bool mixed, hipStream_t s, BatchSlot& b, bool upload)
 {
-    const bool mixed = prec == SCS_PREC_MIXED;
-    constexpr int kWaves = 4;  // workgroup shape of the fused launch
-    std::vector<EvalJob> jobs(n_items);
-    for (int i = 0; i < n_items; ++i) {
-        const scs_batch_item& it = items[i];
-        EvalJob& j = jobs[i];
-        j.c = it.ctx;
-        j.w = (wss && wss[i]) ? wss[i] : &it.ctx->ws[1 + i];
-        j.P = it.P;
-        j.N = it.N;
-        TuneChoice t = choose(it.ctx, it.P, it.N, prec);
-        t.waves = kWaves;
-        int rc = eval_front(j, it.theta, it.ups, it.seg, t, s);
-        if (rc) return rc;
-    }
-    scs_ctx* c0 = items[0].ctx;
+    const int n_items = (int)jobs.size();
+    scs_ctx* c0 = jobs[0].c;
     int off = 0;
     for (int gi = 0; gi < 2; ++gi) {
         const int nch = gi == 0 ? 2 : 1;
@@ -968,16 +956,59 @@ static int run_batched(const scs_batch_item* items, int n_items, int prec, hipSt
             HIP_TRY(hipMemcpyAsync(b.d_start + gi * (b.cap + 1), hs, sizeof(int64_t) * (cnt + 1), hipMemcpyHostToDevice, s));
         }
         launch_fill_u64(b.d_counter + gi, 1, 0ULL, s);
-        const int per_cu = main_multi_blocks_per_cu(nch, c0->L, kWaves, mixed);
+        const int per_cu = main_multi_blocks_per_cu(nch, c0->L, waves, mixed);
         const int64_t grid = std::min<int64_t>(total, (int64_t)c0->n_cu * per_cu);
         hipEvent_t e0;
         prof_begin(c0, s, &e0);
         hipError_t e = launch_main_multi(b.d_items + off, b.d_start + gi * (b.cap + 1), cnt, b.d_counter + gi, nch, c0->L,
-                                         kWaves, mixed, (int)grid, s);
-        if (e != hipSuccess) return fail(SCS_EDEVICE, "fused launch failed: %s", hipGetErrorString(e));
+                                         waves, mixed, (int)grid, s);
+        if (e != hipSuccess) return fail(SCS_EDEVICE, "generate-and-reduce launch failed: %s", hipGetErrorString(e));
         prof_end(c0, s, e0);
         off += cnt;
     }
+    return SCS_OK;
+}
+
+// One evaluation's generate-and-reduce, through the same persistent kernel
+// (a device queue spreads its tiles over every XCD), descriptors from the
+// context's ring.
+static int eval_main(scs_ctx* c, EvalJob& j, int prec, hipStream_t s)
+{
+    BatchSlot& b = c->ring[c->ring_next];
+    c->ring_next = (c->ring_next + 1) % scs_ctx::kRing;
+    int rc = slot_reserve(b, 1);
+    if (rc) return rc;
+    std::vector<EvalJob> one(1, j);
+    if ((rc = fused_main(one, j.pl.waves, prec == SCS_PREC_MIXED, s, b, true))) return rc;
+    HIP_TRY(hipEventRecord(b.done, s));
+    return SCS_OK;
+}
+
+// Queue a batch on s using the descriptors of slot b.  upload: copy the
+// descriptors from the pinned host copy (skipped under graph capture, where
+// they were uploaded when the graph was built and stay valid).
+// wss[i] (nullable) is the workspace of item i; by default slot 1 + i of its
+// context.
+static int run_batched(const scs_batch_item* items, int n_items, int prec, hipStream_t s, BatchSlot& b, bool upload,
+                       Workspace* const* wss = nullptr)
+{
+    const bool mixed = prec == SCS_PREC_MIXED;
+    constexpr int kWaves = 4;  // workgroup shape of the fused launch
+    std::vector<EvalJob> jobs(n_items);
+    for (int i = 0; i < n_items; ++i) {
+        const scs_batch_item& it = items[i];
+        EvalJob& j = jobs[i];
+        j.c = it.ctx;
+        j.w = (wss && wss[i]) ? wss[i] : &it.ctx->ws[1 + i];
+        j.P = it.P;
+        j.N = it.N;
+        TuneChoice t = choose(it.ctx, it.P, it.N, prec);
+        t.waves = kWaves;
+        int rc = eval_front(j, it.theta, it.ups, it.seg, t, s);
+        if (rc) return rc;
+    }
+    int rc = fused_main(jobs, kWaves, mixed, s, b, upload);
+    if (rc) return rc;
     for (int i = 0; i < n_items; ++i)
         if (jobs[i].P > 0) launch_finalize(jobs[i].fa, s);
     hipError_t e = hipGetLastError();

@@ -11,9 +11,10 @@ constexpr int kNodes = 6;  // degree-5 block polynomials (6 coefficients / Cheby
 constexpr int kGStride = 56;  // doubles per basis-table entry: 8 functions x 6 orders, G00 hi/lo, padding
 constexpr int kGHi = 48;
 constexpr int kGLo = 49;
-constexpr int kMaxLevel = 10;  // sub-block lengths 2^3 .. 2^9
+constexpr int kMaxLevel = 12;  // sub-block lengths 2^3 .. 2^11
 constexpr int kTrig = 512;        // entries of the (cos, sin)(2 pi i / kTrig) table
 constexpr int kCoefStride = 56;  // doubles per particle record of the coefficient buffer
+constexpr int kRec = 8;          // doubles per (chunk, slot) record: head piece, tail piece, padding
 
 struct GridArgs {
     int64_t K;
@@ -91,8 +92,8 @@ struct MainArgs {
     const double* gtab;            // basis tables of every level
     int64_t gtab_off[kMaxLevel];   // entry offset of level lg
     const int32_t* perm;   // slot -> particle (relative to p0), or null for identity
-    double* rec;           // [chunk][7][rec_stride], indexed by slot
-    double* seg;           // [P][N][3] or null
+    double* rec;           // [chunk][rec_stride][kRec], indexed by slot
+    double* zs;            // [P][N][3]: (Z re, Z im, H) of segments closed inside a chunk
     double zscale32;       // FP32 tables hold u * sqrt(s), q * s: Z32 * zscale32 = Z, H32 * hscale32 = H
     double hscale32;
 };
@@ -111,8 +112,9 @@ struct FinalArgs {
     const int32_t* bounds;
     const int32_t* perm;  // as in MainArgs
     const double* rec;
+    double* zs;   // as in MainArgs
     double* ups;  // [P_end - p0]
-    double* seg;
+    double* seg;  // non-null: zs is the caller's segment output, completed here
 };
 
 struct PsoBox {
@@ -131,7 +133,6 @@ void launch_bins(const GridArgs& g, const double* d_ri, const double* psd, doubl
 void launch_prologue(const PrologueArgs& a, hipStream_t s);
 void launch_bounds(const BoundArgs& a, hipStream_t s);
 size_t main_lds_bytes(int nch, int L, bool mixed);
-void launch_main(const MainArgs& a, int waves, bool mixed, hipStream_t s);
 hipError_t launch_main_multi(const MainArgs* items, const int64_t* tile_start, int n_items, unsigned long long* counter,
                              int nch, int L, int waves, bool mixed, int grid, hipStream_t s);
 int main_multi_blocks_per_cu(int nch, int L, int waves, bool mixed);

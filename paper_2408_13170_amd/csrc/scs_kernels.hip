@@ -3,15 +3,16 @@
 //   k_bins        particle-independent per-bin products u = f^-7/6 d / S, q = f^-7/3 / S
 //   k_prologue    per particle: PN coefficients (double-double where the phase
 //                 is large), coalescence time, support window, response
-//                 trig-polynomial, polynomial block length        (rows a1, a2)
-//   k_bounds_*    per particle segment edges: equal [h|h], uniform, explicit (a3)
-//   k_main        generate-and-reduce over (chunk, particle group) tiles:
+//                 trig-polynomial, polynomial block length          (Sec 4)
+//   k_bounds_*    per particle segment edges: equal [h|h], uniform,
+//                 explicit                                          (Sec 2.2)
+//   k_main_multi  generate-and-reduce over (chunk, particle group) tiles:
 //                 data staged in LDS, one particle per lane, per-lane
-//                 segmented accumulation                          (a4)
-//   k_finalize    combine fragments of segments that straddle chunks,
-//                 term_n = 4 df |Z_n|^2 / H_n, Upsilon = sum_n    (a5)
+//                 segmented accumulation                            (Sec 2.2)
+//   k_finalize    term_n = 4 df |Z_n|^2 / H_n with the pieces of segments
+//                 that straddle chunks joined, Upsilon = sum_n      (Sec 2.2)
 //   k_waveform    template on the grid for one theta (injections, parity)
-//   k_pso_*       particle-swarm move and best update              (a6)
+//   k_pso_*       particle-swarm move and best update               (Sec 3.1)
 #include "scs_internal.hpp"
 #include "scs_math.hpp"
 
@@ -567,16 +568,19 @@ __global__ void k_bounds_simple(BoundArgs a)
 
 // ============================================================== main kernel
 // Work tile = (chunk of CB LDS blocks of L bins, group of 64 W particles).
-// The bins of an LDS block are staged once and shared by the workgroup.
-// Each wave owns 64 particle slots: lane i keeps the segment state of slot i
-// between LDS blocks, and the wave takes its particles one at a time.  For
-// one particle the lanes cover 64 consecutive bins, the block polynomials
-// are wave-uniform (scalar registers) and so are the segment edges: a lane
-// sums the terms of its bins, and the lane sums are combined by a wave
-// reduction only where a segment closes or the wave moves to the next
-// particle.  A chunk leaves per (particle, chunk) the sum of the terms of
-// segments complete inside it and the head / tail pieces of the segments that
-// cross its edges, which k_finalize joins.
+// One lane = one particle; all lanes of a workgroup read the same staged bins
+// (LDS broadcast).  Each lane accumulates Z and H of its current segment and
+// closes it at its own edges; a chunk leaves per (particle, chunk) the sum of
+// terms of segments complete inside it and the head / tail pieces of the
+// segments that cross its edges, which k_finalize joins.
+//
+// The bin loop carries no per-lane test.  Each lane keeps the bin of its next
+// event: the start of its support (clear the sums, which may hold terms of
+// earlier bins of the same polynomial block), a segment edge (close the
+// segment), the end of its support (zero its polynomials, so that later bins
+// add exact zeros).  The wave runs straight through the bins up to the
+// smallest pending event, lets the lanes whose event is due handle it, and
+// goes on.
 __device__ __forceinline__ int bsearch_seg(const int32_t* __restrict__ bo, int N, int64_t k)
 {
     // largest n in [0, N-1] with b_n <= k
@@ -588,146 +592,20 @@ __device__ __forceinline__ int bsearch_seg(const int32_t* __restrict__ bo, int N
     return lo;
 }
 
-// x of lane l (l wave-uniform), and a value known to be wave-uniform, as
-// scalar-register doubles.
-__device__ __forceinline__ double lane_f64(double x, int l)
+// Minimum over the 64 lanes of a wave; every lane must be active.  Prefix
+// minimum inside each row of 16 lanes by DPP row shifts (lanes shifted in
+// from outside the row read INT32_MAX), then the four row minima through
+// scalar registers.
+__device__ __forceinline__ int wave_min_i32(int v)
 {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
-    return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ double uniform_f64(double x)
-{
-    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(x));
-    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(x));
-    return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ float uniform_f32(float x)
-{
-    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
-}
-
-// Sum over the 64 lanes of a wave (every lane active), wave-uniform result:
-// inclusive prefix sums inside each row of 16 lanes by DPP row shifts (lanes
-// shifted in from outside the row read +0.0), then the four row totals.
-template <int CTRL>
-__device__ __forceinline__ double dpp_row_shr_f64(double v)
-{
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
-    return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ void wave_sum3(double& a, double& b, double& c)
-{
-    a += dpp_row_shr_f64<0x111>(a);
-    b += dpp_row_shr_f64<0x111>(b);
-    c += dpp_row_shr_f64<0x111>(c);
-    a += dpp_row_shr_f64<0x112>(a);
-    b += dpp_row_shr_f64<0x112>(b);
-    c += dpp_row_shr_f64<0x112>(c);
-    a += dpp_row_shr_f64<0x114>(a);
-    b += dpp_row_shr_f64<0x114>(b);
-    c += dpp_row_shr_f64<0x114>(c);
-    a += dpp_row_shr_f64<0x118>(a);
-    b += dpp_row_shr_f64<0x118>(b);
-    c += dpp_row_shr_f64<0x118>(c);
-    a = (lane_f64(a, 15) + lane_f64(a, 31)) + (lane_f64(a, 47) + lane_f64(a, 63));
-    b = (lane_f64(b, 15) + lane_f64(b, 31)) + (lane_f64(b, 47) + lane_f64(b, 63));
-    c = (lane_f64(c, 15) + lane_f64(c, 31)) + (lane_f64(c, 47) + lane_f64(c, 63));
-}
-
-// Wave-uniform block polynomials of one sub-block: monomials in the bin
-// offset j from the sub-block centre.  ph: template phase (cycles; the FP64
-// path scales it by kTrig), r: R_A re, R_A im, R_E re, R_E im.
-struct BlockCoef {
-    double ph[kNodes];
-    double r[4][kNodes];
-};
-
-// The set-up of block_setup done by one wave for one (wave-uniform)
-// particle: lanes 0..5 each take one Taylor order of the phase, then one
-// Chebyshev node of the response and Doppler term, then one output order of
-// the node-to-monomial transform.
-template <bool RESP>
-__device__ inline void coop_setup(const double* __restrict__ cf, int64_t p, double Kc, int lg,
-                                  const double* __restrict__ G, const GridArgs& g, const ModelArgs& m, int lane,
-                                  BlockCoef& u)
-{
-    const double* __restrict__ c = cf + p * kCoefStride;
-    const double h = (double)(1 << (lg - 1));
-    const int mo = lane < kNodes ? lane : 0;
-    // ---- phase Taylor coefficient of order mo in j
-    double am = 0.0;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const double ci = (i == 0) ? c[C_C0H] : c[C_B1 + i - 1];
-        const double t = __builtin_fma(ci, G[i * kNodes + mo], am);
-        am = (i == 0 && mo == 0) ? am : t;
-    }
-    if (mo == 0) {
-        // constant term: frac(Kc tau) + frac(c0 f^-5/3) + frac(rest), cycles
-        const double tauh = c[C_TAUH], taul = c[C_TAUL];
-        dd lin = two_prod(Kc, tauh);
-        lin.lo = __builtin_fma(Kc, taul, lin.lo);
-        const dd n0 = dd_mul(dd{c[C_C0H], c[C_C0L]}, dd{G[kGHi], G[kGLo]});
-        const double rest = am + c[C_PHIC];
-        const double cc = dd_frac(lin) + dd_frac(n0) + (rest - rint(rest));
-        am = cc - rint(cc);
-    } else if (mo == 1) {
-        am += c[C_TAUH] + c[C_TAUL];
-    }
-    double a[kNodes];
-#pragma unroll
-    for (int mm = 0; mm < kNodes; ++mm) a[mm] = lane_f64(am, mm);
-    if constexpr (!RESP) {
-#pragma unroll
-        for (int mm = 0; mm < kNodes; ++mm) u.ph[mm] = a[mm];
-        return;
-    } else {
-        // ---- node mo: time, orbital angle, response and Doppler
-        const double jn = c_cheb_x[mo] * h;
-        double d = 5.0 * a[5];
-        d = __builtin_fma(d, jn, 4.0 * a[4]);
-        d = __builtin_fma(d, jn, 3.0 * a[3]);
-        d = __builtin_fma(d, jn, 2.0 * a[2]);
-        d = __builtin_fma(d, jn, a[1]);  // dPhi/dj [cycles per bin] = t(f) df
-        double orb = m.orb0_cyc + (d / g.df) * kInvYear;
-        orb -= rint(orb);
-        double s1, c1;
-        sincos2pi(orb, &s1, &c1);
-        double ch[5], sh[5];
-        harmonics(c1, s1, ch, sh);
-        double val[5];
-#pragma unroll
-        for (int f = 0; f < 4; ++f) {
-            double rv = c[C_RESP + 9 * f];
-#pragma unroll
-            for (int k = 1; k <= 4; ++k)
-                rv = __builtin_fma(c[C_RESP + 9 * f + k], ch[k], __builtin_fma(c[C_RESP + 9 * f + 4 + k], sh[k], rv));
-            val[f] = rv;
-        }
-        val[4] = ((Kc + jn) * g.df) * (c[C_DC] * c1 + c[C_DS] * s1);
-        // ---- order mo of the interpolant of each quantity (in x = j / h)
-        double coef[5];
-#pragma unroll
-        for (int f = 0; f < 5; ++f) coef[f] = 0.0;
-#pragma unroll
-        for (int n = 0; n < kNodes; ++n) {
-            const double w = c_cheb_m[mo * kNodes + n];
-#pragma unroll
-            for (int f = 0; f < 5; ++f) coef[f] = __builtin_fma(w, lane_f64(val[f], n), coef[f]);
-        }
-        // x^mo -> j^mo: divide by h^mo (a power of two, exact)
-#pragma unroll
-        for (int f = 0; f < 5; ++f) coef[f] = ldexp(coef[f], -(lg - 1) * mo);
-#pragma unroll
-        for (int mm = 0; mm < kNodes; ++mm) {
-#pragma unroll
-            for (int f = 0; f < 4; ++f) u.r[f][mm] = lane_f64(coef[f], mm);
-            u.ph[mm] = a[mm] + lane_f64(coef[4], mm);
-        }
-        u.ph[0] -= rint(u.ph[0]);
-    }
+    v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x111, 0xf, 0xf, false));  // row_shr:1
+    v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x112, 0xf, 0xf, false));  // row_shr:2
+    v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x114, 0xf, 0xf, false));  // row_shr:4
+    v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x118, 0xf, 0xf, false));  // row_shr:8
+    const int r0 = __builtin_amdgcn_readlane(v, 15), r1 = __builtin_amdgcn_readlane(v, 31);
+    const int r2 = __builtin_amdgcn_readlane(v, 47), r3 = __builtin_amdgcn_readlane(v, 63);
+    const int m01 = r0 < r1 ? r0 : r1, m23 = r2 < r3 ? r2 : r3;
+    return m01 < m23 ? m01 : m23;
 }
 
 // sin and cos of 2 pi s / kTrig for |s| <= 1/2: Taylor polynomials in
@@ -743,27 +621,22 @@ constexpr double kCos4 = (kArg * kArg * kArg * kArg) / 24.0;
 // nearest integer, which then sits in the low mantissa bits.
 constexpr double kRoundShift = 0x1.8p52;
 
-// LDS layout of one staged block (structure of arrays, so that lanes reading
-// consecutive bins read consecutive addresses):
-//   FP64, two channels: uA[L] (double2), uE[L] (double2), q[L] (double2: qA, qE)
-//   FP64, one channel:  u[L] (double2), q[L] (double)
-//   mixed, two channels: u[L] (float4: uA re, im, uE re, im), q[L] (float2)
-//   mixed, one channel:  u[L] (float2), q[L] (float)
-
-// One bin of the FP64 path.  The phase (units of 1/kTrig cycle) is rounded
-// to the nearest unit with the 1.5*2^52 shift; e^{2 pi i phase} is the table
-// entry of that unit times the remainder polynomials.  Then
-// Z += (sum_alpha u_alpha conj(R_alpha)) e^{2 pi i phase} and
-// H += sum_alpha q_alpha |R_alpha|^2.
+// One bin of the FP64 path: template phase at bin offset j from the block
+// centre, in units of 1/kTrig cycle (the block polynomial carries that
+// power-of-two scale); e^{2 pi i phase} from the table entry of the nearest
+// unit and the polynomials for the remainder; then
+// Z += (sum_alpha u_alpha conj(R_alpha)) e^{2 pi i phase},
+// H += sum_alpha q_alpha |R_alpha|^2.  bin = [uA re, uA im, uE re, uE im, qA, qE]
+// (two channels) or [u re, u im, q]; amp scales the one-channel terms (0 or 1).
 template <bool RESP>
-__device__ __forceinline__ void tbin_fp64(double j, int kl, const unsigned char* __restrict__ sm, int L,
-                                          const double2* __restrict__ tab, const BlockCoef& u, double& zr,
-                                          double& zi, double& hh)
+__device__ __forceinline__ void bin_fp64(double j, const double* __restrict__ bin, const double2* __restrict__ tab,
+                                         const PhasePoly& poly, const RespPoly& rp, int tmask, int toff, double amp,
+                                         double& zr, double& zi, double& hh)
 {
-    const double pc = horner5(u.ph, j);
+    const double pc = horner5(poly.ph, j);
     const double t = pc + kRoundShift;
     const double q = t - kRoundShift;  // rint(pc)
-    const int iq = (int)(uint32_t)__double_as_longlong(t) & (kTrig - 1);
+    const int iq = ((int)(uint32_t)__double_as_longlong(t) & tmask) | toff;
     const double s = pc - q;  // exact, |s| <= 1/2
     const double z = s * s;
     const double sn = s * __builtin_fma(z, __builtin_fma(z, kSin5, kSin3), kSin1);
@@ -772,12 +645,11 @@ __device__ __forceinline__ void tbin_fp64(double j, int kl, const unsigned char*
     const double sv = __builtin_fma(tt.y, cn, tt.x * sn);
     const double cv = __builtin_fma(tt.x, cn, -(tt.y * sn));
     if constexpr (RESP) {
-        const double2* su = reinterpret_cast<const double2*>(sm);
-        const double2 uA = su[kl];
-        const double2 uE = su[L + kl];
-        const double2 qq = su[2 * L + kl];
-        const double rar = horner5(u.r[0], j), rai = horner5(u.r[1], j);
-        const double rer = horner5(u.r[2], j), rei = horner5(u.r[3], j);
+        const double2 uA = *reinterpret_cast<const double2*>(bin);
+        const double2 uE = *reinterpret_cast<const double2*>(bin + 2);
+        const double2 qq = *reinterpret_cast<const double2*>(bin + 4);
+        const double rar = horner5(rp.r[0], j), rai = horner5(rp.r[1], j);
+        const double rer = horner5(rp.r[2], j), rei = horner5(rp.r[3], j);
         double sr = uA.x * rar;
         sr = __builtin_fma(uA.y, rai, sr);
         sr = __builtin_fma(uE.x, rer, sr);
@@ -792,76 +664,74 @@ __device__ __forceinline__ void tbin_fp64(double j, int kl, const unsigned char*
         const double we = __builtin_fma(rer, rer, rei * rei);
         hh = __builtin_fma(qq.x, wa, __builtin_fma(qq.y, we, hh));
     } else {
-        const double2 uu = reinterpret_cast<const double2*>(sm)[kl];
-        const double qq = reinterpret_cast<const double*>(sm + (size_t)L * 16)[kl];
-        zr = __builtin_fma(uu.x, cv, __builtin_fma(-uu.y, sv, zr));
-        zi = __builtin_fma(uu.x, sv, __builtin_fma(uu.y, cv, zi));
-        hh += qq;
+        const double ur = bin[0], ui = bin[1], qq = bin[2];
+        zr = __builtin_fma(ur, cv, __builtin_fma(-ui, sv, zr));
+        zi = __builtin_fma(ur, sv, __builtin_fma(ui, cv, zi));
+        hh = __builtin_fma(qq, amp, hh);
     }
 }
 
-// FP32 block polynomials of the mixed path: phase a0 + frac(a1h j) +
-// residual(j) with a1h keeping 12 significant bits, so that a1h j is exact in
-// FP32 for the integer j; the residual holds the rest of the linear term and
-// the higher orders.
-struct BlockCoef32 {
-    float a1h;
-    float ph[kNodes];
-    float r[4][kNodes];
-};
-
+// One bin of the mixed path: FP32 phase a0 + frac(a1h j) + residual(j)
+// (a1h j exact, see the block set-up), hardware sin / cos of cycles, FP32
+// response; plain FP32 partial sums over at most kMixedRun bins, which then
+// enter the FP32 segment sums through Kahan-compensated additions.
 template <bool RESP>
-__device__ __forceinline__ void tbin_mixed(float jf, int kl, const unsigned char* __restrict__ sm, int L,
-                                           const BlockCoef32& u, float& zr, float& zi, float& hh)
+__device__ __forceinline__ void bin_mixed(float jf, const float* __restrict__ bin, const float* phf, float a1h,
+                                          const float (*rf)[kNodes], float amp, float& pzr, float& pzi, float& phh)
 {
-    const float pl = u.a1h * jf;
+    const float pl = a1h * jf;
     const float f1 = pl - rintf(pl);
-    float r = u.ph[5];
-    r = __builtin_fmaf(r, jf, u.ph[4]);
-    r = __builtin_fmaf(r, jf, u.ph[3]);
-    r = __builtin_fmaf(r, jf, u.ph[2]);
-    r = __builtin_fmaf(r, jf, u.ph[1]);
-    const float ph = __builtin_fmaf(r, jf, u.ph[0] + f1);
+    float r = phf[5];
+    r = __builtin_fmaf(r, jf, phf[4]);
+    r = __builtin_fmaf(r, jf, phf[3]);
+    r = __builtin_fmaf(r, jf, phf[2]);
+    r = __builtin_fmaf(r, jf, phf[1]);
+    const float ph = __builtin_fmaf(r, jf, phf[0] + f1);
     const float sn = __builtin_amdgcn_sinf(ph);
     const float cs = __builtin_amdgcn_cosf(ph);
     if constexpr (RESP) {
-        const float4 uu = reinterpret_cast<const float4*>(sm)[kl];
-        const float2 qq = reinterpret_cast<const float2*>(sm + (size_t)L * 16)[kl];
-        const float rar = horner5f(u.r[0], jf), rai = horner5f(u.r[1], jf);
-        const float rer = horner5f(u.r[2], jf), rei = horner5f(u.r[3], jf);
-        float sr = uu.x * rar;
-        sr = __builtin_fmaf(uu.y, rai, sr);
-        sr = __builtin_fmaf(uu.z, rer, sr);
-        sr = __builtin_fmaf(uu.w, rei, sr);
-        float si = uu.y * rar;
-        si = __builtin_fmaf(-uu.x, rai, si);
-        si = __builtin_fmaf(uu.w, rer, si);
-        si = __builtin_fmaf(-uu.z, rei, si);
-        zr = __builtin_fmaf(sr, cs, __builtin_fmaf(-si, sn, zr));
-        zi = __builtin_fmaf(sr, sn, __builtin_fmaf(si, cs, zi));
+        const float rar = horner5f(rf[0], jf), rai = horner5f(rf[1], jf);
+        const float rer = horner5f(rf[2], jf), rei = horner5f(rf[3], jf);
+        const float4 u = *reinterpret_cast<const float4*>(bin);
+        const float2 qq = *reinterpret_cast<const float2*>(bin + 4);
+        float sr = u.x * rar;
+        sr = __builtin_fmaf(u.y, rai, sr);
+        sr = __builtin_fmaf(u.z, rer, sr);
+        sr = __builtin_fmaf(u.w, rei, sr);
+        float si = u.y * rar;
+        si = __builtin_fmaf(-u.x, rai, si);
+        si = __builtin_fmaf(u.w, rer, si);
+        si = __builtin_fmaf(-u.z, rei, si);
+        pzr = __builtin_fmaf(sr, cs, __builtin_fmaf(-si, sn, pzr));
+        pzi = __builtin_fmaf(sr, sn, __builtin_fmaf(si, cs, pzi));
         const float wa = __builtin_fmaf(rar, rar, rai * rai);
         const float we = __builtin_fmaf(rer, rer, rei * rei);
-        hh = __builtin_fmaf(qq.x, wa, __builtin_fmaf(qq.y, we, hh));
+        phh = __builtin_fmaf(qq.x, wa, __builtin_fmaf(qq.y, we, phh));
     } else {
-        const float2 uu = reinterpret_cast<const float2*>(sm)[kl];
-        const float qq = reinterpret_cast<const float*>(sm + (size_t)L * 8)[kl];
-        zr = __builtin_fmaf(uu.x, cs, __builtin_fmaf(-uu.y, sn, zr));
-        zi = __builtin_fmaf(uu.x, sn, __builtin_fmaf(uu.y, cs, zi));
-        hh += qq;
+        const float ur = bin[0] * amp, ui = bin[1] * amp;
+        pzr = __builtin_fmaf(ur, cs, __builtin_fmaf(-ui, sn, pzr));
+        pzi = __builtin_fmaf(ur, sn, __builtin_fmaf(ui, cs, pzi));
+        phh = __builtin_fmaf(bin[2], amp, phh);
     }
 }
 
-// Occupancy target (waves per SIMD) of the generate-and-reduce kernel.
+// Occupancy target: the per-sub-block set-up needs more registers than the
+// bin loop; capping the allocation lets more waves share a SIMD, the set-up
+// spilling to scratch while the bin loop stays in registers.
 #ifndef SCS_WAVES_FP64
-#define SCS_WAVES_FP64 4
+#define SCS_WAVES_FP64 3
 #endif
 #ifndef SCS_WAVES_MIXED
 #define SCS_WAVES_MIXED 4
 #endif
+// Plain FP32 partial sums cover the bins between consecutive multiples of
+// this (and a lane's own segment edges) before their compensated addition.
+constexpr int kMixedRun = 32;
 
 // One work tile (chunk, particle group) of the generate-and-reduce.  Called
 // by every thread of the workgroup; returns early, uniformly, when no
-// particle of the group has support in the chunk.
+// particle of the group has support in the chunk.  s_trig holds the table
+// and, at kTrig, a zero entry for idle one-channel lanes.
 template <int NCH, bool MIXED>
 __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __restrict__ gtab, int64_t logical,
                                           unsigned char* smem, const double2* __restrict__ s_trig)
@@ -871,7 +741,6 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
     const int64_t chunk = a.chunk0 + logical / a.n_groups;
     const int64_t group = logical % a.n_groups;
     const int tid = threadIdx.x;
-    const int lane = tid & 63;
     // slot s in the support-sorted order; particle p = perm[s]
     const int64_t s_idx = a.p0 + group * (int64_t)blockDim.x + tid;
     const int64_t p = (a.perm && s_idx < a.P_end) ? a.p0 + a.perm[s_idx - a.p0] : s_idx;
@@ -891,316 +760,312 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
     hi = hi < Ke ? hi : Ke;
     const bool has = lo < hi;
     if (!__syncthreads_or(has)) return;
+    const int64_t S = a.stride;
     const int N = a.N;
-    // ---- segment state of this lane's particle (lane = slot)
-    int n = 0, nb = INT32_MAX, before = 0, head_done = 0;
+    const int32_t* __restrict__ bo = a.bounds + (p < a.P_end ? p : a.p0) * (int64_t)(N + 1);
+    // wave-uniform polynomial block length: the smallest requested in the wave
+    int lgw = has ? lg : 30;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const int t = __shfl_xor(lgw, o, 64);
+        lgw = t < lgw ? t : lgw;
+    }
+    lgw = __builtin_amdgcn_readfirstlane(lgw);  // uniform: scalar registers and scalar loads downstream
+    // segment state: current segment n, its end nb = b_{n+1}, and b_{n+2}
+    // loaded ahead so that closing a segment does not wait for memory
+    int n = 0, nb = INT32_MAX, nb2 = INT32_MAX;
+    bool before = false;
     if (has) {
-        const int32_t* __restrict__ bo = a.bounds + p * (int64_t)(N + 1);
         n = bsearch_seg(bo, N, lo);
         nb = bo[n + 1];
+        nb2 = (n + 2 <= N) ? bo[n + 2] : INT32_MAX;
         before = bo[n] < Kc;
     }
-    double zr = 0.0, zi = 0.0, hh = 0.0, part = 0.0;  // running sums of the open segment
-    const int64_t RS = a.rec_stride;
-    double* const rec_chunk = a.rec + (chunk - a.chunk0) * RS * 7;
-    const int64_t slot0 = s_idx - lane - a.p0;  // slot of lane 0 of this wave, relative to p0
-    const double four_df = 4.0 * a.g.df;
-    const double sz = MIXED ? a.zscale32 : 1.0, sh = MIXED ? a.hscale32 : 1.0;
-    double* const seg = a.seg;
+    // event state: 0 before the support, 1 inside, 2 after (or no support)
+    int stage = has ? 0 : 2;
+    int nxt = has ? lo : INT32_MAX;
+    double zr = 0.0, zi = 0.0, hh = 0.0;  // FP64 sums
+    // mixed: FP32 running sums with Kahan compensation (value = sum - comp)
+    float kzr = 0.f, kzi = 0.f, khh = 0.f, czr = 0.f, czi = 0.f, chh = 0.f;
+    // mixed: plain FP32 sums of the bins since the last multiple of kMixedRun
+    float qzr = 0.f, qzi = 0.f, qhh = 0.f;
+    auto kahan = [](float& sum, float& comp, float x) {
+        const float y = x - comp;
+        const float t = sum + y;
+        comp = (t - sum) - y;
+        sum = t;
+    };
+    auto clear_sums = [&]() {
+        zr = zi = hh = 0.0;
+        kzr = kzi = khh = czr = czi = chh = 0.f;
+        qzr = qzi = qhh = 0.f;
+    };
+    // chunk record of this slot: [0..2] head piece (Z re, Z im, H) of the
+    // segment open at the chunk start, [3..5] tail piece of the segment open
+    // at its end; sums of segments that close inside the chunk go to zs
+    double* const recp = a.rec + ((chunk - a.chunk0) * a.rec_stride + (s_idx < a.P_end ? s_idx - a.p0 : 0)) * kRec;
+    double* zsp = a.zs + ((p < a.P_end ? p : a.p0) * (int64_t)N + n) * 3;  // Z, H of segment n
+    auto sums = [&](double& fzr, double& fzi, double& fhh) {
+        if constexpr (MIXED) {
+            fzr = ((double)kzr - (double)czr + (double)qzr) * a.zscale32;
+            fzi = ((double)kzi - (double)czi + (double)qzi) * a.zscale32;
+            fhh = ((double)khh - (double)chh + (double)qhh) * a.hscale32;
+        } else {
+            fzr = zr;
+            fzi = zi;
+            fhh = hh;
+        }
+    };
+    // close segment n at bin k (exclusive): its sums go to the head record if
+    // it started in an earlier chunk, else to zs; move to the next non-empty one
+    auto flush = [&](int k) {
+        double fzr, fzi, fhh;
+        sums(fzr, fzi, fhh);
+        double* const dst = before ? recp : zsp;
+        dst[0] = fzr;
+        dst[1] = fzi;
+        dst[2] = fhh;
+        clear_sums();
+        before = false;
+        ++n;
+        zsp += 3;
+        nb = (n < N) ? nb2 : INT32_MAX;
+        nb2 = (n + 2 <= N) ? bo[n + 2] : INT32_MAX;
+        while (n < N - 1 && nb == k) {  // empty segments
+            ++n;
+            zsp += 3;
+            nb = bo[n + 1];
+            nb2 = (n + 2 <= N) ? bo[n + 2] : INT32_MAX;
+        }
+    };
     const int L = a.L;
     const int nthreads = blockDim.x;
-    const double lane_d = (double)lane;
-    const float lane_fl = (float)lane;
+    PhasePoly poly;
+    RespPoly rp;
+    float phf[kNodes], rf[4][kNodes];
+    float a1h = 0.f;
+    // one-channel idle lanes: table index of the zero entry, zero weight
+    int tmask = 0, toff = kTrig;
+    double amp = 0.0;
+    // Each lane builds its polynomials on the sub-blocks of its own length
+    // 2^lgl (aligned; the wave steps through the shortest in the wave, whose
+    // boundaries are boundaries of every lane's), so a particle's arithmetic
+    // does not depend on the particles that share its wave.  have: first bin
+    // of the lane's current sub-block (-1: zero polynomials); kcl its centre.
+    const int lgl = has ? lg : lgw;
+    const double* __restrict__ gtl = gtab + a.gtab_off[lgl] * kGStride;
+    int have = -1, kcl = 0;
+    auto zero_polys = [&]() {
+        if constexpr (MIXED) {
+            a1h = 0.f;
+#pragma unroll
+            for (int mm = 0; mm < kNodes; ++mm) phf[mm] = 0.f;
+            if constexpr (RESP) {
+#pragma unroll
+                for (int f = 0; f < 4; ++f)
+#pragma unroll
+                    for (int mm = 0; mm < kNodes; ++mm) rf[f][mm] = 0.f;
+            }
+        } else {
+#pragma unroll
+            for (int mm = 0; mm < kNodes; ++mm) poly.ph[mm] = 0.0;
+            if constexpr (RESP) {
+#pragma unroll
+                for (int f = 0; f < 4; ++f)
+#pragma unroll
+                    for (int mm = 0; mm < kNodes; ++mm) rp.r[f][mm] = 0.0;
+            }
+        }
+        tmask = 0;
+        toff = kTrig;
+        amp = 0.0;
+        have = -1;
+    };
+    // lanes whose event is due at bin k (nxt <= k)
+    auto handle = [&](int k) {
+        if (stage == 0) {
+            clear_sums();
+            stage = 1;
+        }
+        if (stage == 1) {
+            if (nb == k && k < hi) flush(k);
+            if (hi <= k) {
+                stage = 2;
+                zero_polys();
+            }
+        }
+        nxt = (stage == 1) ? (nb < hi ? nb : hi) : INT32_MAX;
+        if (nxt <= k) nxt = INT32_MAX;  // not reached; keeps the wave loop finite
+    };
     for (int b0 = Kc; b0 < Ke; b0 += L) {
         const int b1 = (b0 + L < Ke) ? b0 + L : Ke;
         const int nbins = b1 - b0;
-        // ---- stage bins [b0, b1) into LDS (structure of arrays)
+        // ---- stage bins [b0, b1) into LDS
         __syncthreads();
-        if constexpr (!MIXED && RESP) {
+        if constexpr (!MIXED && NV % 2 == 0) {
             const double2* src = reinterpret_cast<const double2*>(a.b64 + (int64_t)b0 * NV);
             double2* dst = reinterpret_cast<double2*>(smem);
-            for (int e = tid; e < nbins * 3; e += nthreads) {
-                const int bin = e / 3, part3 = e - 3 * bin;
-                dst[part3 * L + bin] = src[e];
-            }
+            const int cnt = nbins * NV / 2;
+            for (int i = tid; i < cnt; i += nthreads) dst[i] = src[i];
         } else if constexpr (!MIXED) {
             const double* src = a.b64 + (int64_t)b0 * NV;
-            double* du = reinterpret_cast<double*>(smem);
-            double* dq = reinterpret_cast<double*>(smem + (size_t)L * 16);
-            for (int e = tid; e < nbins * 3; e += nthreads) {
-                const int bin = e / 3, c3 = e - 3 * bin;
-                if (c3 < 2) du[2 * bin + c3] = src[e];
-                else dq[bin] = src[e];
-            }
-        } else if constexpr (RESP) {
-            const float* src = a.b32 + (int64_t)b0 * NV;
-            float* du = reinterpret_cast<float*>(smem);
-            float* dq = reinterpret_cast<float*>(smem + (size_t)L * 16);
-            for (int e = tid; e < nbins * 6; e += nthreads) {
-                const int bin = e / 6, c6 = e - 6 * bin;
-                if (c6 < 4) du[4 * bin + c6] = src[e];
-                else dq[2 * bin + (c6 - 4)] = src[e];
-            }
+            double* dst = reinterpret_cast<double*>(smem);
+            const int cnt = nbins * NV;
+            for (int i = tid; i < cnt; i += nthreads) dst[i] = src[i];
         } else {
             const float* src = a.b32 + (int64_t)b0 * NV;
-            float* du = reinterpret_cast<float*>(smem);
-            float* dq = reinterpret_cast<float*>(smem + (size_t)L * 8);
-            for (int e = tid; e < nbins * 3; e += nthreads) {
-                const int bin = e / 3, c3 = e - 3 * bin;
-                if (c3 < 2) du[2 * bin + c3] = src[e];
-                else dq[bin] = src[e];
-            }
+            float* dst = reinterpret_cast<float*>(smem);
+            const int cnt = nbins * NV;
+            for (int i = tid; i < cnt; i += nthreads) dst[i] = src[i];
         }
         __syncthreads();
         const int llo = lo > b0 ? lo : b0;
         const int lhi = hi < b1 ? hi : b1;
-        uint64_t todo = __ballot(llo < lhi);
-        while (todo) {
-            // ---- particle of lane i, wave-uniform from here on
-            const int i = __builtin_ctzll(todo);
-            todo &= todo - 1;
-            const int64_t pi = ((int64_t)__builtin_amdgcn_readlane((int)(p >> 32), i) << 32) |
-                               (uint32_t)__builtin_amdgcn_readlane((int)p, i);
-            const int lgi = __builtin_amdgcn_readlane(lg, i);
-            const int loi = __builtin_amdgcn_readlane(llo, i);
-            const int hii = __builtin_amdgcn_readlane(lhi, i);
-            int ni = __builtin_amdgcn_readlane(n, i);
-            int nbi = __builtin_amdgcn_readlane(nb, i);
-            int bef = __builtin_amdgcn_readlane(before, i);
-            int hdi = __builtin_amdgcn_readlane(head_done, i);
-            double zri = lane_f64(zr, i), zii = lane_f64(zi, i), hhi = lane_f64(hh, i);
-            double parti = lane_f64(part, i);
-            const int32_t* __restrict__ boi = a.bounds + pi * (int64_t)(N + 1);
-            double* const recpi = rec_chunk + (slot0 + i);
-            const double* __restrict__ gt = gtab + a.gtab_off[lgi] * kGStride;
-            const int Lp = 1 << lgi;
-            const int hp = Lp >> 1;
-            // lane sums of the open segment (FP64; the mixed path adds its FP32
-            // sums of at most L / 64 terms into them)
-            double pzr = 0.0, pzi = 0.0, phh = 0.0;
-            // close the open segment at edge e and move to the next non-empty one
-            auto close = [&](int e) {
-                wave_sum3(pzr, pzi, phh);
-                const double Zr = (zri + pzr) * sz, Zi = (zii + pzi) * sz, H = (hhi + phh) * sh;
-                pzr = pzi = phh = 0.0;
-                if (bef) {
-                    // head piece of a segment that started in an earlier chunk
-                    if (lane == 0) {
-                        recpi[1 * RS] = Zr;
-                        recpi[2 * RS] = Zi;
-                        recpi[3 * RS] = H;
-                    }
-                    hdi = 1;
-                } else {
-                    if (H > 0.0) parti += four_df * (Zr * Zr + Zi * Zi) / H;
-                    if (seg && lane == 0) {
-                        double* sp = seg + (pi * (int64_t)N + ni) * 3;
-                        sp[0] = Zr;
-                        sp[1] = Zi;
-                        sp[2] = H;
-                    }
-                }
-                zri = zii = hhi = 0.0;
-                bef = 0;
-                ++ni;
-                nbi = (ni < N) ? boi[ni + 1] : INT32_MAX;
-                while (ni < N - 1 && nbi == e) {  // empty segments
-                    ++ni;
-                    nbi = boi[ni + 1];
-                }
-            };
+        const bool act = llo < lhi;
+        // wave-uniform bin range: the union of the lanes' ranges
+        int wlo = act ? llo : INT32_MAX, whi = act ? lhi : INT32_MIN;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const int t1 = __shfl_xor(wlo, o, 64);
+            const int t2 = __shfl_xor(whi, o, 64);
+            wlo = t1 < wlo ? t1 : wlo;
+            whi = t2 > whi ? t2 : whi;
+        }
+        wlo = __builtin_amdgcn_readfirstlane(wlo);
+        whi = __builtin_amdgcn_readfirstlane(whi);
+        if (wlo >= whi) continue;
+        const int Lp = 1 << lgw;
 #pragma unroll 1
-            for (int sb = (loi >> lgi) << lgi; sb < hii; sb += Lp) {
-                const int s_lo = sb > loi ? sb : loi;
-                const int s_hi = (sb + Lp < hii) ? sb + Lp : hii;
-                const int kc = sb + hp;
-                BlockCoef bc;
-                coop_setup<RESP>(a.coef, pi, a.g.k0 + (double)kc, lgi, gt + (int64_t)(sb >> lgi) * kGStride, a.g,
-                                 a.m, lane, bc);
-                if constexpr (!MIXED) {
-                    // wave-uniform coefficients in scalar registers; phase in 1/kTrig cycles
+        for (int sb0 = (wlo >> lgw) << lgw; sb0 < whi; sb0 += Lp) {
+            const int s_lo = sb0 > wlo ? sb0 : wlo;
+            const int s_hi = (sb0 + Lp < whi) ? sb0 + Lp : whi;
+            const bool sact = act && llo < sb0 + Lp && lhi > sb0;
+            const int sbl = (sb0 >> lgl) << lgl;
+            if (sact && have != sbl) {
+                have = sbl;
+                kcl = sbl + (1 << (lgl - 1));
+                const double inv_h = 1.0 / (double)(1 << (lgl - 1));
+                block_setup<RESP>(a.coef, S, p, a.g.k0 + (double)kcl, lgl, gtl + (int64_t)(sbl >> lgl) * kGStride,
+                                  a.g, a.m, poly, rp);
+                // monomials in j = x h (h a power of two: exact rescaling); the
+                // FP64 phase also in units of 1/kTrig cycle
+                {
+                    double sc = 1.0;
 #pragma unroll
                     for (int mm = 0; mm < kNodes; ++mm) {
-                        bc.ph[mm] = uniform_f64(bc.ph[mm] * kTrig);
+                        poly.ph[mm] *= MIXED ? sc : sc * kTrig;
                         if constexpr (RESP) {
 #pragma unroll
-                            for (int f = 0; f < 4; ++f) bc.r[f][mm] = uniform_f64(bc.r[f][mm]);
+                            for (int f = 0; f < 4; ++f) rp.r[f][mm] *= sc;
                         }
+                        sc *= inv_h;
                     }
+                }
+                tmask = kTrig - 1;
+                toff = 0;
+                amp = 1.0;
+                if constexpr (MIXED) {
+                    // phase = a0 + frac(a1h j) + residual(j): j is an integer and
+                    // a1h keeps 12 significant bits, so a1h j is exact in FP32
+                    int ex;
+                    frexp(poly.ph[1], &ex);
+                    const double qd = ldexp(1.0, ex - 12);
+                    const double hi1 = rint(poly.ph[1] / qd) * qd;
+                    a1h = (float)hi1;
+                    phf[0] = (float)poly.ph[0];
+                    phf[1] = (float)(poly.ph[1] - hi1);
+#pragma unroll
+                    for (int mm = 2; mm < kNodes; ++mm) phf[mm] = (float)poly.ph[mm];
+                    if constexpr (RESP) {
+#pragma unroll
+                        for (int f = 0; f < 4; ++f)
+#pragma unroll
+                            for (int mm = 0; mm < kNodes; ++mm) rf[f][mm] = (float)rp.r[f][mm];
+                    }
+                }
+            } else if (!sact && have != -1) {
+                zero_polys();
+            }
+            int ev = wave_min_i32(nxt);
+            int k = s_lo;
+            while (true) {
+                const int kend = ev < s_hi ? ev : s_hi;
+                if constexpr (!MIXED) {
+                    double jd = (double)(k - kcl);
+                    const double* binp = reinterpret_cast<const double*>(smem) + (k - b0) * NV;
 #pragma unroll 1
-                    for (int base = s_lo; base < s_hi;) {
-                        const int cnt = (s_hi - base < 64) ? s_hi - base : 64;
-                        const int kl = base - b0 + lane;
-                        const double jb = (double)(base - kc);
-                        if (nbi < base + cnt) {
-                            // an edge inside: this lane's term, then split at the edges
-                            double dzr = 0.0, dzi = 0.0, dhh = 0.0;
-                            if (lane < cnt) tbin_fp64<RESP>(jb + lane_d, kl, smem, L, s_trig, bc, dzr, dzi, dhh);
-                            while (nbi < base + cnt) {
-                                const bool mine = lane < nbi - base;
-                                if (mine) {
-                                    pzr += dzr;
-                                    pzi += dzi;
-                                    phh += dhh;
-                                    dzr = dzi = dhh = 0.0;
-                                }
-                                close(nbi);
-                            }
-                            pzr += dzr;
-                            pzi += dzi;
-                            phh += dhh;
-                            base += cnt;
-                        } else if (cnt == 64 && base + 128 <= s_hi && nbi >= base + 128) {
-                            tbin_fp64<RESP>(jb + lane_d, kl, smem, L, s_trig, bc, pzr, pzi, phh);
-                            tbin_fp64<RESP>(jb + (lane_d + 64.0), kl + 64, smem, L, s_trig, bc, pzr, pzi, phh);
-                            base += 128;
-                        } else {
-                            if (lane < cnt) tbin_fp64<RESP>(jb + lane_d, kl, smem, L, s_trig, bc, pzr, pzi, phh);
-                            base += cnt;
-                        }
+                    for (; k + 1 < kend; k += 2) {
+                        bin_fp64<RESP>(jd, binp, s_trig, poly, rp, tmask, toff, amp, zr, zi, hh);
+                        bin_fp64<RESP>(jd + 1.0, binp + NV, s_trig, poly, rp, tmask, toff, amp, zr, zi, hh);
+                        jd += 2.0;
+                        binp += 2 * NV;
+                    }
+                    if (k < kend) {
+                        bin_fp64<RESP>(jd, binp, s_trig, poly, rp, tmask, toff, amp, zr, zi, hh);
+                        ++k;
                     }
                 } else {
-                    // FP32 coefficients (wave-uniform)
-                    BlockCoef32 bf;
-                    {
-                        int ex;
-                        frexp(bc.ph[1], &ex);
-                        const double qd = ldexp(1.0, ex - 12);
-                        const double hi1 = rint(bc.ph[1] / qd) * qd;
-                        bf.a1h = uniform_f32((float)hi1);
-                        bf.ph[0] = uniform_f32((float)bc.ph[0]);
-                        bf.ph[1] = uniform_f32((float)(bc.ph[1] - hi1));
-#pragma unroll
-                        for (int mm = 2; mm < kNodes; ++mm) bf.ph[mm] = uniform_f32((float)bc.ph[mm]);
-                        if constexpr (RESP) {
-#pragma unroll
-                            for (int f = 0; f < 4; ++f)
-#pragma unroll
-                                for (int mm = 0; mm < kNodes; ++mm) bf.r[f][mm] = uniform_f32((float)bc.r[f][mm]);
-                        }
-                    }
-                    float qzr = 0.f, qzi = 0.f, qhh = 0.f;  // FP32 lane sums of this sub-block
+                    const float ampf = (float)amp;
 #pragma unroll 1
-                    for (int base = s_lo; base < s_hi;) {
-                        const int cnt = (s_hi - base < 64) ? s_hi - base : 64;
-                        const int kl = base - b0 + lane;
-                        const float jb = (float)(base - kc);
-                        if (nbi < base + cnt) {
-                            float dzr = 0.f, dzi = 0.f, dhh = 0.f;
-                            if (lane < cnt) tbin_mixed<RESP>(jb + lane_fl, kl, smem, L, bf, dzr, dzi, dhh);
-                            pzr += (double)qzr;
-                            pzi += (double)qzi;
-                            phh += (double)qhh;
+                    while (k < kend) {
+                        // up to the next multiple of kMixedRun (a position fixed by
+                        // the bin index alone), or the end of the run
+                        const int pe = ((k | (kMixedRun - 1)) + 1 < kend) ? (k | (kMixedRun - 1)) + 1 : kend;
+                        float jf = (float)(k - kcl);
+                        const float* binp = reinterpret_cast<const float*>(smem) + (k - b0) * NV;
+#pragma unroll 1
+                        for (; k + 1 < pe; k += 2) {
+                            bin_mixed<RESP>(jf, binp, phf, a1h, rf, ampf, qzr, qzi, qhh);
+                            bin_mixed<RESP>(jf + 1.f, binp + NV, phf, a1h, rf, ampf, qzr, qzi, qhh);
+                            jf += 2.f;
+                            binp += 2 * NV;
+                        }
+                        if (k < pe) {
+                            bin_mixed<RESP>(jf, binp, phf, a1h, rf, ampf, qzr, qzi, qhh);
+                            ++k;
+                        }
+                        // (not past the support end: a compensated add of zero
+                        // still moves the compensation into the sum)
+                        if ((k & (kMixedRun - 1)) == 0 && stage != 2) {
+                            kahan(kzr, czr, qzr);
+                            kahan(kzi, czi, qzi);
+                            kahan(khh, chh, qhh);
                             qzr = qzi = qhh = 0.f;
-                            while (nbi < base + cnt) {
-                                const bool mine = lane < nbi - base;
-                                if (mine) {
-                                    pzr += (double)dzr;
-                                    pzi += (double)dzi;
-                                    phh += (double)dhh;
-                                    dzr = dzi = dhh = 0.f;
-                                }
-                                close(nbi);
-                            }
-                            qzr = dzr;
-                            qzi = dzi;
-                            qhh = dhh;
-                            base += cnt;
-                        } else if (cnt == 64 && base + 128 <= s_hi && nbi >= base + 128) {
-                            tbin_mixed<RESP>(jb + lane_fl, kl, smem, L, bf, qzr, qzi, qhh);
-                            tbin_mixed<RESP>(jb + (lane_fl + 64.f), kl + 64, smem, L, bf, qzr, qzi, qhh);
-                            base += 128;
-                        } else {
-                            if (lane < cnt) tbin_mixed<RESP>(jb + lane_fl, kl, smem, L, bf, qzr, qzi, qhh);
-                            base += cnt;
                         }
                     }
-                    pzr += (double)qzr;
-                    pzi += (double)qzi;
-                    phh += (double)qhh;
                 }
-            }
-            // fold the lane sums into the running sums; state back to lane i
-            wave_sum3(pzr, pzi, phh);
-            zri += pzr;
-            zii += pzi;
-            hhi += phh;
-            if (lane == i) {
-                n = ni;
-                nb = nbi;
-                before = bef;
-                head_done = hdi;
-                zr = zri;
-                zi = zii;
-                hh = hhi;
-                part = parti;
+                k = k > kend ? k : kend;
+                if (k >= s_hi) break;
+                if (nxt <= k) handle(k);
+                ev = wave_min_i32(nxt);
+                ev = ev > k ? ev : k + 1;  // every pass of this loop covers at least one bin
             }
         }
     }
-    // ---- close the chunk (each lane its own particle)
+    // ---- close the chunk
     if (has) {
-        double* const recp = rec_chunk + (slot0 + lane);
-        const double fzr = zr * sz, fzi = zi * sz, fhh = hh * sh;
-        double tl0 = 0.0, tl1 = 0.0, tl2 = 0.0;
-        if (nb <= hi || before) {
-            // the open segment ends at hi (or spans the whole chunk)
-            if (before) {
-                recp[1 * RS] = fzr;
-                recp[2 * RS] = fzi;
-                recp[3 * RS] = fhh;
-                head_done = 1;
-            } else {
-                if (fhh > 0.0) part += four_df * (fzr * fzr + fzi * fzi) / fhh;
-                if (seg) {
-                    double* sp = seg + (p * (int64_t)N + n) * 3;
-                    sp[0] = fzr;
-                    sp[1] = fzi;
-                    sp[2] = fhh;
-                }
-            }
+        if (nb <= hi) {
+            flush(hi);  // the open segment ends with the support or the chunk
         } else {
-            tl0 = fzr;
-            tl1 = fzi;
-            tl2 = fhh;
+            double fzr, fzi, fhh;
+            sums(fzr, fzi, fhh);
+            // continues into the next chunk: the whole-chunk piece of a segment
+            // that also started earlier goes to the head record, else the tail
+            double* const dst = recp + (before ? 0 : 3);
+            dst[0] = fzr;
+            dst[1] = fzi;
+            dst[2] = fhh;
         }
-        if (!head_done) {
-            recp[1 * RS] = 0.0;
-            recp[2 * RS] = 0.0;
-            recp[3 * RS] = 0.0;
-        }
-        recp[0] = part;
-        recp[4 * RS] = tl0;
-        recp[5 * RS] = tl1;
-        recp[6 * RS] = tl2;
     }
 }
 
-// One workgroup per tile.  The block-to-tile mapping is XCD-aware:
-// consecutive logical tiles (same chunk, neighbouring particle groups) land
-// on the same XCD and so share its L2.
-template <int NCH, bool MIXED>
-__global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(MIXED ? SCS_WAVES_MIXED : SCS_WAVES_FP64))) void k_main(
-    MainArgs a, const double* __restrict__ gtab)
-{
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double2 s_trig[MIXED ? 1 : kTrig];
-    const int64_t nwg = a.n_tiles;
-    const int64_t per_xcd = (nwg + 7) / 8;
-    const int64_t bid = blockIdx.x;
-    const int64_t logical = (bid & 7) * per_xcd + (bid >> 3);
-    if (logical >= nwg) return;
-    if constexpr (!MIXED) {
-        for (int i = threadIdx.x; i < kTrig; i += blockDim.x) s_trig[i] = g_trig[i];
-        // made visible by the barriers of the tile
-    }
-    main_tile<NCH, MIXED>(a, gtab, logical, smem, s_trig);
-}
-
-// Persistent form over the tiles of several evaluations (items): a fixed
-// grid of workgroups takes tiles from a device counter until none is left,
-// so swarms of uneven sizes share one launch and the chip stays full to the
-// end.  tile_start[i] is the first global tile of item i (prefix sums,
+// The generate-and-reduce kernel, persistent, over the tiles of one or
+// several evaluations (items): a fixed grid of workgroups takes tiles from a
+// device counter until none is left, so swarms of uneven sizes share one
+// launch, every XCD gets work wherever the particles' supports lie in the
+// band, and the chip stays full to the end.  Consecutive tiles are the
+// particle groups of one chunk, so workgroups running together share the
+// chunk's data in L2.  tile_start[i] is the first global tile of item i (prefix sums,
 // tile_start[n_items] = total); the counter starts at 0.
 template <int NCH, bool MIXED>
 __global__ __launch_bounds__(256)
@@ -1209,10 +1074,11 @@ __attribute__((amdgpu_waves_per_eu(MIXED ? SCS_WAVES_MIXED : SCS_WAVES_FP64))) v
     unsigned long long* __restrict__ counter)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double2 s_trig[MIXED ? 1 : kTrig];
+    __shared__ double2 s_trig[MIXED ? 1 : kTrig + 1];
     __shared__ unsigned long long s_next;
     if constexpr (!MIXED) {
         for (int i = threadIdx.x; i < kTrig; i += blockDim.x) s_trig[i] = g_trig[i];
+        if (threadIdx.x == 0) s_trig[kTrig] = make_double2(0.0, 0.0);
     }
     const int64_t total = tile_start[n_items];
     while (true) {
@@ -1229,69 +1095,94 @@ __attribute__((amdgpu_waves_per_eu(MIXED ? SCS_WAVES_MIXED : SCS_WAVES_FP64))) v
 }
 
 // ============================================================== finalize
-__global__ void k_finalize(FinalArgs a)
+// Sum of a double over the 64 lanes of a wave (every lane active), result in
+// every lane: prefix sums inside each row of 16 lanes by DPP row shifts,
+// then the four row totals.
+template <int CTRL>
+__device__ __forceinline__ double dpp_row_shr_f64(double v)
 {
-    const int64_t s_idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + a.p0;  // slot of the main kernel
-    if (s_idx >= a.P_end) return;
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double lane_f64(double x, int l)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_sum_f64(double v)
+{
+    v += dpp_row_shr_f64<0x111>(v);  // row_shr:1
+    v += dpp_row_shr_f64<0x112>(v);  // row_shr:2
+    v += dpp_row_shr_f64<0x114>(v);  // row_shr:4
+    v += dpp_row_shr_f64<0x118>(v);  // row_shr:8
+    return (lane_f64(v, 15) + lane_f64(v, 31)) + (lane_f64(v, 47) + lane_f64(v, 63));
+}
+
+// One wave per particle (slot of the main kernel): lane l takes segments
+// l, l + 64, ...; a segment inside one chunk has its (Z, H) in zs, one that
+// crosses chunks is the tail piece of its first chunk plus the head pieces
+// of the following ones.  term_n = 4 df |Z_n|^2 / H_n (0 if H_n = 0),
+// Upsilon = sum_n term_n.  With seg output, zs is that array and is completed
+// here (joined pieces, zeros for empty segments).
+__global__ __launch_bounds__(256) void k_finalize(FinalArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t s_idx = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64 + a.p0;
+    if (s_idx >= a.P_end) return;  // wave-uniform
     const int64_t p = a.perm ? a.p0 + a.perm[s_idx - a.p0] : s_idx;
     const int N = a.N;
     const int lg = a.lg[p];
-    double* seg = a.seg;
+    double* const zs = a.zs + p * (int64_t)N * 3;
+    const bool out_seg = a.seg != nullptr;
     if (lg == -1 || lg == -2) {
-        a.ups[p - a.p0] = __longlong_as_double(0x7ff8000000000000LL);  // NaN: invalid / unresolved theta
-        if (seg)
-            for (int n = 0; n < N; ++n)
-                for (int c = 0; c < 3; ++c) seg[(p * (int64_t)N + n) * 3 + c] = __longlong_as_double(0x7ff8000000000000LL);
+        const double nan = __longlong_as_double(0x7ff8000000000000LL);  // invalid / unresolved theta
+        if (lane == 0) a.ups[p - a.p0] = nan;
+        if (out_seg)
+            for (int n = lane; n < N; n += 64) zs[3 * n] = zs[3 * n + 1] = zs[3 * n + 2] = nan;
         return;
     }
     const int64_t klo = a.klo[p], khi = a.khi[p];
-    const int32_t* bo = a.bounds + p * (int64_t)(N + 1);
-    if (seg) {
-        for (int n = 0; n < N; ++n)
-            if (bo[n] == bo[n + 1])
-                for (int c = 0; c < 3; ++c) seg[(p * (int64_t)N + n) * 3 + c] = 0.0;
-    }
-    if (khi <= klo) {
-        a.ups[p - a.p0] = 0.0;
-        return;
-    }
-    const int64_t cb = a.cbins;
-    const int64_t c_first = klo / cb, c_last = (khi - 1) / cb;
-    const int64_t RS = a.rec_stride;
-    const double* rec = a.rec + (s_idx - a.p0);
+    const int32_t* __restrict__ bo = a.bounds + p * (int64_t)(N + 1);
+    const int64_t cb_len = a.cbins;
+    const double* const rec = a.rec + (s_idx - a.p0) * kRec;
+    const int64_t cstride = a.rec_stride * kRec;
     const double four_df = 4.0 * a.df;
     double sum = 0.0;
-    for (int64_t c = c_first; c <= c_last; ++c) sum += rec[(c - a.chunk0) * RS * 7];
-    double azr = 0.0, azi = 0.0, ahh = 0.0;
-    for (int64_t c = c_first; c <= c_last; ++c) {
-        const double* r = rec + (c - a.chunk0) * RS * 7;
-        const int64_t Kc = c * cb;
-        const int64_t Ke = (Kc + cb < a.K) ? Kc + cb : a.K;
-        if (Kc > klo) {
-            const int n = bsearch_seg(bo, N, Kc);
-            if (bo[n] < Kc) {
-                azr += r[1 * RS];
-                azi += r[2 * RS];
-                ahh += r[3 * RS];
-                if (bo[n + 1] <= Ke) {
-                    if (ahh > 0.0) sum += four_df * (azr * azr + azi * azi) / ahh;
-                    if (seg) {
-                        double* sp = seg + (p * (int64_t)N + n) * 3;
-                        sp[0] = azr; sp[1] = azi; sp[2] = ahh;
-                    }
-                    azr = azi = ahh = 0.0;
+    for (int n = lane; n < N; n += 64) {
+        const int64_t b = bo[n], e = bo[n + 1];
+        double zr = 0.0, zi = 0.0, h = 0.0;
+        if (khi > klo && e > b) {
+            const int64_t c0 = b / cb_len, c1 = (e - 1) / cb_len;
+            if (c0 == c1) {
+                zr = zs[3 * n];
+                zi = zs[3 * n + 1];
+                h = zs[3 * n + 2];
+            } else {
+                const double* r = rec + (c0 - a.chunk0) * cstride;
+                zr = r[3];
+                zi = r[4];
+                h = r[5];
+                for (int64_t c = c0 + 1; c <= c1; ++c) {
+                    r = rec + (c - a.chunk0) * cstride;
+                    zr += r[0];
+                    zi += r[1];
+                    h += r[2];
+                }
+                if (out_seg) {
+                    zs[3 * n] = zr;
+                    zs[3 * n + 1] = zi;
+                    zs[3 * n + 2] = h;
                 }
             }
-        }
-        const int64_t last = ((Ke < khi) ? Ke : khi) - 1;
-        const int n2 = bsearch_seg(bo, N, last);
-        if (bo[n2 + 1] > Ke && bo[n2] >= Kc) {
-            azr = r[4 * RS];
-            azi = r[5 * RS];
-            ahh = r[6 * RS];
+            if (h > 0.0) sum += four_df * (zr * zr + zi * zi) / h;
+        } else if (out_seg) {
+            zs[3 * n] = zs[3 * n + 1] = zs[3 * n + 2] = 0.0;
         }
     }
-    a.ups[p - a.p0] = sum;
+    sum = wave_sum_f64(sum);
+    if (lane == 0) a.ups[p - a.p0] = sum;
 }
 
 // ============================================================== waveform
@@ -1520,20 +1411,6 @@ void launch_bounds(const BoundArgs& a, hipStream_t s)
     }
 }
 size_t main_lds_bytes(int nch, int L, bool mixed) { return (size_t)L * 3 * nch * (mixed ? 4 : 8); }
-void launch_main(const MainArgs& a, int waves, bool mixed, hipStream_t s)
-{
-    if (a.n_tiles <= 0) return;
-    const unsigned grid = (unsigned)(((a.n_tiles + 7) / 8) * 8);
-    const size_t lds = main_lds_bytes(a.g.nch, a.L, mixed);
-    const dim3 blk(64 * waves);
-    if (a.g.nch == 2) {
-        if (mixed) hipLaunchKernelGGL((k_main<2, true>), dim3(grid), blk, lds, s, a, a.gtab);
-        else hipLaunchKernelGGL((k_main<2, false>), dim3(grid), blk, lds, s, a, a.gtab);
-    } else {
-        if (mixed) hipLaunchKernelGGL((k_main<1, true>), dim3(grid), blk, lds, s, a, a.gtab);
-        else hipLaunchKernelGGL((k_main<1, false>), dim3(grid), blk, lds, s, a, a.gtab);
-    }
-}
 hipError_t launch_main_multi(const MainArgs* items, const int64_t* tile_start, int n_items, unsigned long long* counter,
                              int nch, int L, int waves, bool mixed, int grid, hipStream_t s)
 {
@@ -1563,8 +1440,8 @@ int main_multi_blocks_per_cu(int nch, int L, int waves, bool mixed)
 }
 void launch_finalize(const FinalArgs& a, hipStream_t s)
 {
-    const int64_t n = a.P_end - a.p0;
-    if (n > 0) hipLaunchKernelGGL(k_finalize, dim3(nblk(n, 128)), dim3(128), 0, s, a);
+    const int64_t n = a.P_end - a.p0;  // one wave per slot
+    if (n > 0) hipLaunchKernelGGL(k_finalize, dim3(nblk(n, 4)), dim3(256), 0, s, a);
 }
 
 // Order particles by support window so that the particles of a workgroup
