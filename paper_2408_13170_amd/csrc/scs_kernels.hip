@@ -608,10 +608,12 @@ __device__ __forceinline__ int wave_min_i32(int v)
     return m01 < m23 ? m01 : m23;
 }
 
-// sin and cos of 2 pi s / kTrig for |s| <= 1/2: Taylor polynomials in
-// z = s^2 with the powers of 2 pi / kTrig folded in (sine to degree 5,
-// cosine to degree 4; remainders below 1e-19 and 8e-17).
-constexpr double kArg = kTwoPi / kTrig;
+// The FP64 phase is carried in units of 1/kTrig cycle.  sin and cos of
+// 2 pi s / kTrig for |s| <= 1/2: Taylor polynomials in z = s^2 with the
+// powers of the angle unit folded in (sine to degree 5, cosine to degree 4;
+// remainders below 1e-19 and 8e-17).
+constexpr double kPhaseUnits = kTrig;
+constexpr double kArg = kTwoPi / kPhaseUnits;
 constexpr double kSin1 = kArg;
 constexpr double kSin3 = -(kArg * kArg * kArg) / 6.0;
 constexpr double kSin5 = (kArg * kArg * kArg * kArg * kArg) / 120.0;
@@ -620,6 +622,8 @@ constexpr double kCos4 = (kArg * kArg * kArg * kArg) / 24.0;
 // Adding 1.5 * 2^52 to a double of magnitude below 2^51 rounds it to the
 // nearest integer, which then sits in the low mantissa bits.
 constexpr double kRoundShift = 0x1.8p52;
+constexpr int kTabMask = kTrig - 1;  // table index of an entry
+constexpr int kTabZero = kTrig;      // index of the zero entry
 
 // One bin of the FP64 path: template phase at bin offset j from the block
 // centre, in units of 1/kTrig cycle (the block polynomial carries that
@@ -628,19 +632,25 @@ constexpr double kRoundShift = 0x1.8p52;
 // Z += (sum_alpha u_alpha conj(R_alpha)) e^{2 pi i phase},
 // H += sum_alpha q_alpha |R_alpha|^2.  bin = [uA re, uA im, uE re, uE im, qA, qE]
 // (two channels) or [u re, u im, q]; amp scales the one-channel terms (0 or 1).
+// Constants of the remainder polynomials, held in vector registers for the
+// whole loop (an FP64 FMA reads at most one scalar register, so constants
+// kept in scalar registers would be copied into a vector register per use).
+struct SinCosK {
+    double s5, s3, c4, c2;
+};
+
 template <bool RESP>
 __device__ __forceinline__ void bin_fp64(double j, const double* __restrict__ bin, const double2* __restrict__ tab,
-                                         const PhasePoly& poly, const RespPoly& rp, int tmask, int toff, double amp,
-                                         double& zr, double& zi, double& hh)
+                                         const SinCosK& kk, const PhasePoly& poly, const RespPoly& rp, int tmask,
+                                         int toff, double amp, double& zr, double& zi, double& hh)
 {
     const double pc = horner5(poly.ph, j);
     const double t = pc + kRoundShift;
-    const double q = t - kRoundShift;  // rint(pc)
     const int iq = ((int)(uint32_t)__double_as_longlong(t) & tmask) | toff;
-    const double s = pc - q;  // exact, |s| <= 1/2
+    const double s = pc - (t - kRoundShift);  // exact, |s| <= 1/2
     const double z = s * s;
-    const double sn = s * __builtin_fma(z, __builtin_fma(z, kSin5, kSin3), kSin1);
-    const double cn = __builtin_fma(z, __builtin_fma(z, kCos4, kCos2), 1.0);
+    const double sn = s * __builtin_fma(z, __builtin_fma(z, kk.s5, kk.s3), kSin1);
+    const double cn = __builtin_fma(z, __builtin_fma(z, kk.c4, kk.c2), 1.0);
     const double2 tt = tab[iq];
     const double sv = __builtin_fma(tt.y, cn, tt.x * sn);
     const double cv = __builtin_fma(tt.x, cn, -(tt.y * sn));
@@ -715,14 +725,14 @@ __device__ __forceinline__ void bin_mixed(float jf, const float* __restrict__ bi
     }
 }
 
-// Occupancy target: the per-sub-block set-up needs more registers than the
-// bin loop; capping the allocation lets more waves share a SIMD, the set-up
-// spilling to scratch while the bin loop stays in registers.
+// Occupancy target (waves per SIMD), measured on MI355X: two for the FP64
+// kernel (256 VGPRs, nothing spills; one and three waves are no faster),
+// three for mixed.
 #ifndef SCS_WAVES_FP64
-#define SCS_WAVES_FP64 3
+#define SCS_WAVES_FP64 2
 #endif
 #ifndef SCS_WAVES_MIXED
-#define SCS_WAVES_MIXED 4
+#define SCS_WAVES_MIXED 3
 #endif
 // Plain FP32 partial sums cover the bins between consecutive multiples of
 // this (and a lane's own segment edges) before their compensated addition.
@@ -844,8 +854,10 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
     RespPoly rp;
     float phf[kNodes], rf[4][kNodes];
     float a1h = 0.f;
-    // one-channel idle lanes: table index of the zero entry, zero weight
-    int tmask = 0, toff = kTrig;
+    SinCosK kk{kSin5, kSin3, kCos4, kCos2};
+    __asm__ volatile("" : "+v"(kk.s5), "+v"(kk.s3), "+v"(kk.c4), "+v"(kk.c2));
+    // one-channel idle lanes: index of the zero entry, zero weight
+    int tmask = 0, toff = kTabZero;
     double amp = 0.0;
     // Each lane builds its polynomials on the sub-blocks of its own length
     // 2^lgl (aligned; the wave steps through the shortest in the wave, whose
@@ -877,7 +889,7 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
             }
         }
         tmask = 0;
-        toff = kTrig;
+        toff = kTabZero;
         amp = 0.0;
         have = -1;
     };
@@ -953,7 +965,7 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
                     double sc = 1.0;
 #pragma unroll
                     for (int mm = 0; mm < kNodes; ++mm) {
-                        poly.ph[mm] *= MIXED ? sc : sc * kTrig;
+                        poly.ph[mm] *= MIXED ? sc : sc * kPhaseUnits;
                         if constexpr (RESP) {
 #pragma unroll
                             for (int f = 0; f < 4; ++f) rp.r[f][mm] *= sc;
@@ -961,7 +973,7 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
                         sc *= inv_h;
                     }
                 }
-                tmask = kTrig - 1;
+                tmask = kTabMask;
                 toff = 0;
                 amp = 1.0;
                 if constexpr (MIXED) {
@@ -995,13 +1007,13 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
                     const double* binp = reinterpret_cast<const double*>(smem) + (k - b0) * NV;
 #pragma unroll 1
                     for (; k + 1 < kend; k += 2) {
-                        bin_fp64<RESP>(jd, binp, s_trig, poly, rp, tmask, toff, amp, zr, zi, hh);
-                        bin_fp64<RESP>(jd + 1.0, binp + NV, s_trig, poly, rp, tmask, toff, amp, zr, zi, hh);
+                        bin_fp64<RESP>(jd, binp, s_trig, kk, poly, rp, tmask, toff, amp, zr, zi, hh);
+                        bin_fp64<RESP>(jd + 1.0, binp + NV, s_trig, kk, poly, rp, tmask, toff, amp, zr, zi, hh);
                         jd += 2.0;
                         binp += 2 * NV;
                     }
                     if (k < kend) {
-                        bin_fp64<RESP>(jd, binp, s_trig, poly, rp, tmask, toff, amp, zr, zi, hh);
+                        bin_fp64<RESP>(jd, binp, s_trig, kk, poly, rp, tmask, toff, amp, zr, zi, hh);
                         ++k;
                     }
                 } else {
