@@ -16,6 +16,12 @@
 #include "scs_internal.hpp"
 #include "scs_math.hpp"
 
+// Global-memory qualifier.  Pointers the kernels read from memory (launch
+// descriptors) are generic to the compiler, whose flat accesses also count
+// against the LDS wait counter; casting them keeps global accesses apart
+// from LDS waits.
+#define GLOBAL __attribute__((address_space(1)))
+
 namespace scs {
 
 // Chebyshev nodes of the degree-5 block interpolant and the matrix taking
@@ -298,8 +304,8 @@ struct RespPoly {
 // for the LISA response, response and Doppler interpolated at the Chebyshev
 // nodes.  Returns the GW phase coefficients a[] (x-space) for node times.
 template <bool RESP>
-__device__ inline void block_setup(const double* __restrict__ cf, int64_t S, int64_t p, double Kc, int lg,
-                                   const double* __restrict__ G, const GridArgs& g, const ModelArgs& m,
+__device__ inline void block_setup(const GLOBAL double* __restrict__ cf, int64_t S, int64_t p, double Kc, int lg,
+                                   const GLOBAL double* __restrict__ G, const GridArgs& g, const ModelArgs& m,
                                    PhasePoly& out, RespPoly& resp)
 {
     const double h = (double)(1 << (lg - 1));
@@ -365,7 +371,7 @@ __device__ inline void block_setup(const double* __restrict__ cf, int64_t S, int
 #pragma unroll
             for (int f = 0; f < 4; ++f) {
                 __asm__ volatile("" ::: "memory");  // nine coefficients live at a time
-                const double* cc = cf + p * kCoefStride + (C_RESP + 9 * f);
+                const GLOBAL double* cc = cf + p * kCoefStride + (C_RESP + 9 * f);
                 double rv = cc[0];
 #pragma unroll
                 for (int k = 1; k <= 4; ++k)
@@ -581,7 +587,8 @@ __global__ void k_bounds_simple(BoundArgs a)
 // add exact zeros).  The wave runs straight through the bins up to the
 // smallest pending event, lets the lanes whose event is due handle it, and
 // goes on.
-__device__ __forceinline__ int bsearch_seg(const int32_t* __restrict__ bo, int N, int64_t k)
+template <class IntPtr>
+__device__ __forceinline__ int bsearch_seg(IntPtr bo, int N, int64_t k)
 {
     // largest n in [0, N-1] with b_n <= k
     int lo = 0, hi = N - 1;
@@ -753,17 +760,18 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
     const int tid = threadIdx.x;
     // slot s in the support-sorted order; particle p = perm[s]
     const int64_t s_idx = a.p0 + group * (int64_t)blockDim.x + tid;
-    const int64_t p = (a.perm && s_idx < a.P_end) ? a.p0 + a.perm[s_idx - a.p0] : s_idx;
+    const int64_t p =
+        (a.perm && s_idx < a.P_end) ? a.p0 + ((const GLOBAL int32_t*)a.perm)[s_idx - a.p0] : s_idx;
     const int K = (int)a.g.K;
     const int cbins = a.L * a.CB;
     const int Kc = (int)chunk * cbins;
     const int Ke = (Kc + cbins < K) ? Kc + cbins : K;
     int lo = 0, hi = 0, lg = -1;
     if (p < a.P_end) {
-        lg = a.lg[p];
+        lg = ((const GLOBAL int8_t*)a.lg)[p];
         if (lg >= 0) {
-            lo = a.klo[p];
-            hi = a.khi[p];
+            lo = ((const GLOBAL int32_t*)a.klo)[p];
+            hi = ((const GLOBAL int32_t*)a.khi)[p];
         }
     }
     lo = lo > Kc ? lo : Kc;
@@ -772,7 +780,7 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
     if (!__syncthreads_or(has)) return;
     const int64_t S = a.stride;
     const int N = a.N;
-    const int32_t* __restrict__ bo = a.bounds + (p < a.P_end ? p : a.p0) * (int64_t)(N + 1);
+    const GLOBAL int32_t* __restrict__ bo = (const GLOBAL int32_t*)a.bounds + (p < a.P_end ? p : a.p0) * (int64_t)(N + 1);
     // wave-uniform polynomial block length: the smallest requested in the wave
     int lgw = has ? lg : 30;
 #pragma unroll
@@ -813,8 +821,9 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
     // chunk record of this slot: [0..2] head piece (Z re, Z im, H) of the
     // segment open at the chunk start, [3..5] tail piece of the segment open
     // at its end; sums of segments that close inside the chunk go to zs
-    double* const recp = a.rec + ((chunk - a.chunk0) * a.rec_stride + (s_idx < a.P_end ? s_idx - a.p0 : 0)) * kRec;
-    double* zsp = a.zs + ((p < a.P_end ? p : a.p0) * (int64_t)N + n) * 3;  // Z, H of segment n
+    GLOBAL double* const recp =
+        (GLOBAL double*)a.rec + ((chunk - a.chunk0) * a.rec_stride + (s_idx < a.P_end ? s_idx - a.p0 : 0)) * kRec;
+    GLOBAL double* zsp = (GLOBAL double*)a.zs + ((p < a.P_end ? p : a.p0) * (int64_t)N + n) * 3;  // Z, H of segment n
     auto sums = [&](double& fzr, double& fzi, double& fhh) {
         if constexpr (MIXED) {
             fzr = ((double)kzr - (double)czr + (double)qzr) * a.zscale32;
@@ -831,7 +840,7 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
     auto flush = [&](int k) {
         double fzr, fzi, fhh;
         sums(fzr, fzi, fhh);
-        double* const dst = before ? recp : zsp;
+        GLOBAL double* const dst = before ? recp : zsp;
         dst[0] = fzr;
         dst[1] = fzi;
         dst[2] = fhh;
@@ -865,7 +874,8 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
     // does not depend on the particles that share its wave.  have: first bin
     // of the lane's current sub-block (-1: zero polynomials); kcl its centre.
     const int lgl = has ? lg : lgw;
-    const double* __restrict__ gtl = gtab + a.gtab_off[lgl] * kGStride;
+    const GLOBAL double* __restrict__ gtl = (const GLOBAL double*)gtab + a.gtab_off[lgl] * kGStride;
+    const GLOBAL double* __restrict__ coef = (const GLOBAL double*)a.coef;
     int have = -1, kcl = 0;
     auto zero_polys = [&]() {
         if constexpr (MIXED) {
@@ -915,17 +925,18 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
         // ---- stage bins [b0, b1) into LDS
         __syncthreads();
         if constexpr (!MIXED && NV % 2 == 0) {
-            const double2* src = reinterpret_cast<const double2*>(a.b64 + (int64_t)b0 * NV);
-            double2* dst = reinterpret_cast<double2*>(smem);
+            typedef double dbl2 __attribute__((ext_vector_type(2)));
+            const GLOBAL dbl2* src = (const GLOBAL dbl2*)(a.b64 + (int64_t)b0 * NV);
+            dbl2* dst = reinterpret_cast<dbl2*>(smem);
             const int cnt = nbins * NV / 2;
             for (int i = tid; i < cnt; i += nthreads) dst[i] = src[i];
         } else if constexpr (!MIXED) {
-            const double* src = a.b64 + (int64_t)b0 * NV;
+            const GLOBAL double* src = (const GLOBAL double*)(a.b64 + (int64_t)b0 * NV);
             double* dst = reinterpret_cast<double*>(smem);
             const int cnt = nbins * NV;
             for (int i = tid; i < cnt; i += nthreads) dst[i] = src[i];
         } else {
-            const float* src = a.b32 + (int64_t)b0 * NV;
+            const GLOBAL float* src = (const GLOBAL float*)(a.b32 + (int64_t)b0 * NV);
             float* dst = reinterpret_cast<float*>(smem);
             const int cnt = nbins * NV;
             for (int i = tid; i < cnt; i += nthreads) dst[i] = src[i];
@@ -957,7 +968,7 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
                 have = sbl;
                 kcl = sbl + (1 << (lgl - 1));
                 const double inv_h = 1.0 / (double)(1 << (lgl - 1));
-                block_setup<RESP>(a.coef, S, p, a.g.k0 + (double)kcl, lgl, gtl + (int64_t)(sbl >> lgl) * kGStride,
+                block_setup<RESP>(coef, S, p, a.g.k0 + (double)kcl, lgl, gtl + (int64_t)(sbl >> lgl) * kGStride,
                                   a.g, a.m, poly, rp);
                 // monomials in j = x h (h a power of two: exact rescaling); the
                 // FP64 phase also in units of 1/kTrig cycle
@@ -1063,7 +1074,7 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
             sums(fzr, fzi, fhh);
             // continues into the next chunk: the whole-chunk piece of a segment
             // that also started earlier goes to the head record, else the tail
-            double* const dst = recp + (before ? 0 : 3);
+            GLOBAL double* const dst = recp + (before ? 0 : 3);
             dst[0] = fzr;
             dst[1] = fzi;
             dst[2] = fhh;
@@ -1219,7 +1230,8 @@ __global__ void k_waveform(MainArgs a, double* __restrict__ h_ri)
     const double f = (a.g.k0 + (double)k) * a.g.df;
     const double amp = pow(f, -7.0 / 6.0);
     if (nch == 2) {
-        block_setup<true>(a.coef, a.stride, 0, a.g.k0 + (double)kc, lg, G, a.g, a.m, poly, rp);
+        block_setup<true>((const GLOBAL double*)a.coef, a.stride, 0, a.g.k0 + (double)kc, lg, (const GLOBAL double*)G, a.g,
+                          a.m, poly, rp);
         double ph = horner5(poly.ph, x);
         ph -= rint(ph);
         double sn, cs;
@@ -1231,7 +1243,8 @@ __global__ void k_waveform(MainArgs a, double* __restrict__ h_ri)
             h_ri[((int64_t)c * a.g.K + k) * 2 + 1] = amp * (ri * cs - rr * sn);
         }
     } else {
-        block_setup<false>(a.coef, a.stride, 0, a.g.k0 + (double)kc, lg, G, a.g, a.m, poly, rp);
+        block_setup<false>((const GLOBAL double*)a.coef, a.stride, 0, a.g.k0 + (double)kc, lg, (const GLOBAL double*)G,
+                           a.g, a.m, poly, rp);
         double ph = horner5(poly.ph, x);
         ph -= rint(ph);
         double sn, cs;
