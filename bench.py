@@ -45,6 +45,39 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+PROFILE = os.path.join(ROOT, "profiles", "k_main_multi_fp64_lisa1m.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2408_13170_amd", "csrc", f)
+                  for f in ("scs_kernels.hip", "scs_internal.hpp", "scs_math.hpp")]
+
+
+def kernel_digest():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the FP64 generate-and-reduce kernel from the
+    committed rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, scaled by
+    a plain copy), or None when the kernel sources changed since it was taken."""
+    try:
+        kv = {}
+        with open(PROFILE) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith(" "):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("kernel_sha256") != kernel_digest():
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -162,7 +195,7 @@ def main():
                                "iteration per step", "particles": w.P, "bins": K, "N_seg": w.N},
         "latency_ms": {"p50": float(np.median(r64["step_ms"])), "p99": float(np.quantile(r64["step_ms"], 0.99))},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(),
                      "kernel": "k_main_multi<2,false> (FP64 generate-and-reduce)",
                      "avg_launch_ms": avg_main_ms, "flop_per_eval": FLOP_PER_EVAL_FP64,
                      "evals_per_launch": evals_per_launch},
