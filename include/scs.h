@@ -238,8 +238,8 @@ int scs_server_create(scs_server** out, int32_t device, int32_t max_inflight, ui
 /* Queue an evaluation of P particles (theta, HOST [P][7], copied before the
  * call returns) with N segments on search ctx.  ups (HOST [P]) must stay
  * valid until the request is reported by scs_server_poll.  A request whose
- * footprint alone exceeds the budget is rejected with ENOMEM.  Errors:
- * EINVAL, ENOMEM, ESTATE (server stopping). */
+ * footprint alone exceeds the budget is rejected with EBUSY.  Errors:
+ * EINVAL, EBUSY, ENOMEM (host copy of theta), ESTATE (server stopping). */
 int scs_server_submit(scs_server* srv, scs_ctx* ctx, int32_t N, int64_t P, const double* theta, int32_t prec,
                       double* ups, uint64_t* id);
 

@@ -17,6 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(_HERE, "libscs.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "scs.h")
 
+SCS_OK, SCS_EINVAL, SCS_ENOMEM, SCS_EDEVICE, SCS_EBUSY, SCS_ESTATE = 0, -1, -2, -3, -4, -5
 SCS_MEM_HOST, SCS_MEM_DEVICE = 0, 1
 SCS_PREC_FP64, SCS_PREC_MIXED = 0, 1
 SCS_RESP_NONE, SCS_RESP_LISA_LF_AE = 0, 1

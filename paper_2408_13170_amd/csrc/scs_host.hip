@@ -1138,7 +1138,7 @@ struct scs_server {
     std::chrono::steady_clock::time_point t0;
     std::vector<hipStream_t> streams;
     std::vector<bool> stream_busy;
-    std::vector<BatchSlot> bslots;  // descriptors, one per stream
+    std::vector<BatchSlot> bslots;  // descriptors, one per stream and precision
     std::vector<SrvSlot> slots;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -1209,7 +1209,9 @@ int scs_server::launch(std::vector<SrvRequest*>& batch, int si)
                 w2.push_back(wss[i]);
             }
         if (it2.empty()) continue;
-        BatchSlot& b = bslots[si];
+        // a slot of its own per precision, so that queuing the second part
+        // of a mixed batch does not wait for the first one to finish
+        BatchSlot& b = bslots[2 * si + (prec == SCS_PREC_MIXED)];
         if ((rc = slot_reserve(b, (int)it2.size()))) break;
         if ((rc = run_batched(it2.data(), (int)it2.size(), prec, s, b, true, w2.data()))) break;
         if (hipEventRecord(b.done, s) != hipSuccess) rc = fail(SCS_EDEVICE, "event record failed");
@@ -1346,7 +1348,7 @@ extern "C" int scs_server_create(scs_server** out, int32_t device, int32_t max_i
     s->budget = hbm_budget;
     s->t0 = std::chrono::steady_clock::now();
     s->slots.resize(max_inflight);
-    s->bslots.resize(n_streams);
+    s->bslots.resize(2 * n_streams);
     s->stream_busy.assign(n_streams, false);
     for (int i = 0; i < n_streams; ++i) {
         hipStream_t st;
@@ -1374,7 +1376,7 @@ extern "C" int scs_server_submit(scs_server* srv, scs_ctx* ctx, int32_t N, int64
     if (ctx->mode == SCS_SEG_EXPLICIT && N != ctx->N) return fail(SCS_EINVAL, "EXPLICIT edges were defined for N = %d", ctx->N);
     const uint64_t bytes = request_bytes(ctx, P, N, prec);
     if (bytes > srv->budget)
-        return fail(SCS_ENOMEM, "request needs %llu bytes, budget is %llu", (unsigned long long)bytes,
+        return fail(SCS_EBUSY, "request needs %llu bytes, budget is %llu", (unsigned long long)bytes,
                     (unsigned long long)srv->budget);
     SrvRequest* r = new (std::nothrow) SrvRequest();
     if (!r) return fail(SCS_ENOMEM, "host allocation failed");
@@ -1502,32 +1504,37 @@ extern "C" int scs_autotune(scs_ctx* c, int64_t P, const double* theta_dev, int3
     double* ups = nullptr;
     HIP_TRY(hipMalloc((void**)&ups, sizeof(double) * Pt));
     hipStream_t s;
-    HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+        hipFree(ups);
+        return fail(SCS_EDEVICE, "stream creation failed");
+    }
     Workspace tw;
     TuneChoice best;
     double best_ms = 1e300;
     const int cbs[] = {4, 8, 16, 32, 64};
     const int wvs[] = {1, 2, 4};
-    hipEvent_t e0, e1;
-    hipEventCreate(&e0);
-    hipEventCreate(&e1);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        rc = fail(SCS_EDEVICE, "event creation failed");
     for (int wv : wvs)
         for (int cb0 : cbs) {
+            if (rc) break;
             TuneChoice t{wv, std::max(1, cb0 * 512 / c->L)};
-            if ((rc = run_eval(c, tw, Pt, N, th, prec, ups, nullptr, s, &t))) break;
-            hipEventRecord(e0, s);
-            for (int r = 0; r < 3; ++r) run_eval(c, tw, Pt, N, th, prec, ups, nullptr, s, &t);
-            hipEventRecord(e1, s);
-            hipEventSynchronize(e1);
+            if ((rc = run_eval(c, tw, Pt, N, th, prec, ups, nullptr, s, &t))) break;  // warm-up, sizes tw
+            if (hipEventRecord(e0, s) != hipSuccess) rc = fail(SCS_EDEVICE, "event record failed");
+            for (int r = 0; r < 3 && !rc; ++r) rc = run_eval(c, tw, Pt, N, th, prec, ups, nullptr, s, &t);
+            if (!rc && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+                rc = fail(SCS_EDEVICE, "timing the candidate failed");
             float ms = 0.f;
-            hipEventElapsedTime(&ms, e0, e1);
-            if (ms < best_ms) {
+            if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = fail(SCS_EDEVICE, "event timing failed");
+            if (!rc && ms < best_ms) {
                 best_ms = ms;
                 best = t;
             }
         }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    hipStreamSynchronize(s);
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
     hipStreamDestroy(s);
     free_ws(tw);
     hipFree(ups);

@@ -1,0 +1,117 @@
+"""The launch-shape autotuner and the request loop's admission limits.
+
+The tuned shape changes only the order of the partial sums (chunk joins),
+so tuned results agree with the default shape to rounding and with the
+oracle to the FP64 bar; the cache file written by one context lets another
+skip the timing.  A request whose footprint exceeds the server's HBM budget
+is refused with EBUSY before any device work, and requests still waiting
+when the server is destroyed are dropped without touching their buffers.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from tests import datasets as D
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2408_13170_amd import B  # noqa: E402
+
+
+def _ctx(ds, N, G=16):
+    g = ds.grid
+    h = B.scs_ctx_create(0)
+    B.scs_load_data(h, np.ascontiguousarray(ds.d_ri), np.ascontiguousarray(ds.psd), g.k0 * g.df, g.df)
+    m = ds.model
+    B.scs_set_model(h, m.pn_order, m.response, m.support, m.t_obs)
+    B.scs_define_segmentation(h, N, B.SCS_SEG_EQUAL_SNR, G)
+    return h
+
+
+def _eval(h, th, prec):
+    u = torch.empty(th.shape[0], dtype=torch.float64, device="cuda")
+    B.scs_evaluate(h, th, u, prec)
+    torch.cuda.synchronize()
+    return u.cpu().numpy()
+
+
+def test_autotune_cache_and_results(tmp_path):
+    ds = D.lisa_small(seed=31)
+    N, P = 64, 700
+    theta = D.lisa_particles(P, seed=131)
+    th = torch.tensor(np.ascontiguousarray(theta), device="cuda")
+    cache = tmp_path / "tune.txt"
+    h1, h2 = _ctx(ds, N), _ctx(ds, N)
+    try:
+        base = {p: _eval(h1, th, p) for p in (B.SCS_PREC_FP64, B.SCS_PREC_MIXED)}
+        for p in (B.SCS_PREC_FP64, B.SCS_PREC_MIXED):
+            B.scs_autotune(h1, th, N, p, str(cache))
+        lines = cache.read_text().split()
+        assert len(lines) == 6, lines  # two "key waves blocks" records
+        for w, cb in zip(lines[1::3], lines[2::3]):
+            assert int(w) in (1, 2, 4) and int(cb) >= 1
+        for p, tol in ((B.SCS_PREC_FP64, 1e-12), (B.SCS_PREC_MIXED, 1e-5)):
+            tuned = _eval(h1, th, p)
+            e = np.abs(tuned - base[p]) / np.maximum(np.abs(base[p]), 2.0 * N)
+            print("tuned vs default shape", p, e.max())
+            assert e.max() < tol
+        # a second context reads the cache: a hit needs no particles at all
+        lib = B.lib()
+        for p in (B.SCS_PREC_FP64, B.SCS_PREC_MIXED):
+            assert lib.scs_autotune(h2, P, None, N, p, str(cache).encode()) == 0
+        # a miss (other swarm-size class) without particles is an argument error
+        assert lib.scs_autotune(h2, 8 * P, None, N, B.SCS_PREC_FP64, str(cache).encode()) == B.SCS_EINVAL
+        u2 = _eval(h2, th, B.SCS_PREC_FP64)
+        assert np.array_equal(u2, _eval(h1, th, B.SCS_PREC_FP64))
+        ref = O.evaluate(ds.grid, ds.model, ds.d_ri, ds.psd, theta[:6], N, O.SEG_EQUAL_SNR, 16)
+        e = np.abs(u2[:6] - ref["ups"]) / np.maximum(np.abs(ref["ups"]), 2.0 * N)
+        print("tuned vs oracle", e.max())
+        assert e.max() < 1e-9
+    finally:
+        B.scs_ctx_destroy(h1)
+        B.scs_ctx_destroy(h2)
+
+
+def test_server_budget_and_drop_on_destroy():
+    ds = D.lisa_small(seed=32)
+    h = _ctx(ds, 16)
+    theta = D.lisa_particles(300, seed=132)
+    srv = B.scs_server_create(0, max_inflight=1, hbm_budget=64 << 20, n_streams=1)
+    try:
+        big = np.tile(theta, (400, 1))  # 120000 particles: about 140 MB of workspace
+        ups_big = np.full(big.shape[0], -1.0)
+        with pytest.raises(B.ScsError) as ei:
+            B.scs_server_submit(srv, h, 16, big, ups_big)
+        assert ei.value.code == B.SCS_EBUSY and "budget" in str(ei.value)
+        assert np.all(ups_big == -1.0)
+        # a request that fits is served and equals the evaluation alone
+        ups = np.full(300, -1.0)
+        rid = B.scs_server_submit(srv, h, 16, theta, ups)
+        done = []
+        for _ in range(200):
+            done += B.scs_server_poll(srv, wait_ms=50)
+            if done:
+                break
+        assert [d["id"] for d in done] == [rid] and done[0]["status"] == 0
+        st = B.scs_server_stats(srv)
+        assert st["submitted"] == 1 and st["completed"] == 1 and st["failed"] == 0
+        assert 0 < st["hbm_peak"] <= 64 << 20 and st["hbm_in_use"] == 0
+    finally:
+        B.scs_server_destroy(srv)
+    th = torch.tensor(np.ascontiguousarray(theta), device="cuda")
+    alone = _eval(h, th, B.SCS_PREC_FP64)
+    assert np.array_equal(ups, alone)
+    # destroy with requests still queued: they are dropped, their buffers untouched
+    srv = B.scs_server_create(0, max_inflight=1, hbm_budget=1 << 30, n_streams=1)
+    bufs = [np.full(300, -1.0) for _ in range(6)]
+    try:
+        for b in bufs:
+            B.scs_server_submit(srv, h, 16, theta, b)
+    finally:
+        B.scs_server_destroy(srv)
+    served = [b for b in bufs if not np.all(b == -1.0)]
+    for b in served:
+        assert np.array_equal(b, alone)
+    print("served before destroy:", len(served), "of", len(bufs))
+    B.scs_ctx_destroy(h)
