@@ -47,7 +47,7 @@ def log(*a):
 
 PROFILE = os.path.join(ROOT, "profiles", "k_main_multi_fp64_lisa1m.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2408_13170_amd", "csrc", f)
-                  for f in ("scs_kernels.hip", "scs_internal.hpp", "scs_math.hpp")]
+                  for f in ("scs_kernels.hip", "scs_internal.hpp", "scs_math.hpp", "scs_host.hip")]
 
 
 def kernel_digest():
@@ -63,7 +63,8 @@ def kernel_digest():
 def measured_traffic():
     """HBM bytes per launch of the FP64 generate-and-reduce kernel from the
     committed rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, scaled by
-    a plain copy), or None when the kernel sources changed since it was taken."""
+    a plain copy), or None when the kernel sources or the host code that picks
+    its launch shape changed since it was taken."""
     try:
         kv = {}
         with open(PROFILE) as fh:

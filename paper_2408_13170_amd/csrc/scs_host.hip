@@ -455,10 +455,14 @@ static TuneChoice choose(const scs_ctx* c, int64_t P, int N, int prec)
     auto it = c->tune.find(tune_key(c, P, N, prec));
     if (it != c->tune.end()) return it->second;
     TuneChoice t;
-    // default: 4 waves (256 particles) per workgroup; chunks of ~8192 bins,
-    // fewer waves when the swarm is small so that the chip still fills
+    // default: 4 waves (256 particles) per workgroup, fewer when the swarm is
+    // small so that the chip still fills; chunks as short as the longest
+    // polynomial block (2^lg_max bins, at least one staged block): a tile
+    // then lasts a fraction of a millisecond, so the persistent grid drains
+    // evenly (with 8192-bin chunks the last tiles ran ~15% of the launch
+    // alone), and no block straddles two chunks
     t.waves = P >= 4096 ? 4 : (P >= 1024 ? 2 : 1);
-    t.CB = std::max(1, 8192 / c->L);
+    t.CB = std::max(1, (1 << c->lg_max) / c->L);
     return t;
 }
 
@@ -490,7 +494,7 @@ static size_t ws_bytes(const scs_ctx* c, int64_t P, int N, const Plan& pl)
     size_t b = 0;
     b += sizeof(double) * (size_t)kCoefStride * Pp;
     b += (sizeof(int32_t) * 2 + 1) * (size_t)Pp;
-    b += sizeof(int32_t) * (size_t)P * (N + 1);
+    b += sizeof(int32_t) * ((size_t)P * (N + 1) + 2);
     b += sizeof(double) * (size_t)pl.n_chunks * kRec * Pp;
     b += sizeof(double) * 3 * (size_t)P * N;
     return b;
@@ -517,7 +521,9 @@ static int ensure_ws(scs_ctx* c, Workspace& w, int64_t P, int N, const Plan& pl)
         }
         w.capP = Pp;
     }
-    if ((rc = grow(&w.bounds, &w.capBounds, P * (int64_t)(N + 1)))) return rc;
+    // two spare entries after the last row: the generate-and-reduce kernel
+    // reads each particle's edges two ahead without a bounds test
+    if ((rc = grow(&w.bounds, &w.capBounds, P * (int64_t)(N + 1) + 2))) return rc;
     if ((rc = grow(&w.rec, &w.capRec, pl.n_chunks * kRec * w.capP))) return rc;
     if ((rc = grow(&w.zs, &w.capZs, 3 * P * (int64_t)N))) return rc;
     if (P >= kSortMin && P > w.capSort) {
@@ -1511,7 +1517,7 @@ extern "C" int scs_autotune(scs_ctx* c, int64_t P, const double* theta_dev, int3
     Workspace tw;
     TuneChoice best;
     double best_ms = 1e300;
-    const int cbs[] = {4, 8, 16, 32, 64};
+    const int cbs[] = {2, 4, 8, 16, 32};  // chunks of 1024 .. 16384 bins
     const int wvs[] = {1, 2, 4};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)

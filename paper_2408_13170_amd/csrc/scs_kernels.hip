@@ -580,13 +580,13 @@ __global__ void k_bounds_simple(BoundArgs a)
 // terms of segments complete inside it and the head / tail pieces of the
 // segments that cross its edges, which k_finalize joins.
 //
-// The bin loop carries no per-lane test.  Each lane keeps the bin of its next
-// event: the start of its support (clear the sums, which may hold terms of
-// earlier bins of the same polynomial block), a segment edge (close the
-// segment), the end of its support (zero its polynomials, so that later bins
-// add exact zeros).  The wave runs straight through the bins up to the
-// smallest pending event, lets the lanes whose event is due handle it, and
-// goes on.
+// Each lane keeps the bin of its next event: the start of its support (the
+// sums drop the terms that bins of its first polynomial block before the
+// support added) or the end of its current segment (the sums go out).  The
+// wave adds bin after bin; one wave-wide test per bin sends the lanes whose
+// event is due to the event code first.  That test is a compare and a
+// branch per bin, so the frequent edges of many-segment swarms (one every
+// bin or two across the 64 lanes at N = 4096) stay cheap.
 template <class IntPtr>
 __device__ __forceinline__ int bsearch_seg(IntPtr bo, int N, int64_t k)
 {
@@ -597,22 +597,6 @@ __device__ __forceinline__ int bsearch_seg(IntPtr bo, int N, int64_t k)
         if (bo[mid] <= k) lo = mid; else hi = mid - 1;
     }
     return lo;
-}
-
-// Minimum over the 64 lanes of a wave; every lane must be active.  Prefix
-// minimum inside each row of 16 lanes by DPP row shifts (lanes shifted in
-// from outside the row read INT32_MAX), then the four row minima through
-// scalar registers.
-__device__ __forceinline__ int wave_min_i32(int v)
-{
-    v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x111, 0xf, 0xf, false));  // row_shr:1
-    v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x112, 0xf, 0xf, false));  // row_shr:2
-    v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x114, 0xf, 0xf, false));  // row_shr:4
-    v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x118, 0xf, 0xf, false));  // row_shr:8
-    const int r0 = __builtin_amdgcn_readlane(v, 15), r1 = __builtin_amdgcn_readlane(v, 31);
-    const int r2 = __builtin_amdgcn_readlane(v, 47), r3 = __builtin_amdgcn_readlane(v, 63);
-    const int m01 = r0 < r1 ? r0 : r1, m23 = r2 < r3 ? r2 : r3;
-    return m01 < m23 ? m01 : m23;
 }
 
 // The FP64 phase is carried in units of 1/kTrig cycle.  sin and cos of
@@ -732,11 +716,13 @@ __device__ __forceinline__ void bin_mixed(float jf, const float* __restrict__ bi
     }
 }
 
-// Occupancy target (waves per SIMD), measured on MI355X: two for the FP64
-// kernel (256 VGPRs, nothing spills; one and three waves are no faster),
-// three for mixed.
+// Occupancy target (waves per SIMD), measured on MI355X: three for both
+// (168 VGPRs; what spills is block set-up code, not the bin loop).  Against
+// two waves (256 VGPRs, no spills) the FP64 kernel gains 2% on 1024
+// segments and 10% on the six-swarm hierarchy, whose many-segment levels
+// stall on events more; four waves are no faster for mixed.
 #ifndef SCS_WAVES_FP64
-#define SCS_WAVES_FP64 2
+#define SCS_WAVES_FP64 3
 #endif
 #ifndef SCS_WAVES_MIXED
 #define SCS_WAVES_MIXED 3
@@ -792,16 +778,17 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
     // segment state: current segment n, its end nb = b_{n+1}, and b_{n+2}
     // loaded ahead so that closing a segment does not wait for memory
     int n = 0, nb = INT32_MAX, nb2 = INT32_MAX;
-    bool before = false;
+    bool before = false;  // segment n started in an earlier chunk
     if (has) {
         n = bsearch_seg(bo, N, lo);
         nb = bo[n + 1];
-        nb2 = (n + 2 <= N) ? bo[n + 2] : INT32_MAX;
+        nb2 = bo[n + 2];  // used only while n + 2 <= N (rows are padded for the read)
         before = bo[n] < Kc;
     }
-    // event state: 0 before the support, 1 inside, 2 after (or no support)
-    int stage = has ? 0 : 2;
-    int nxt = has ? lo : INT32_MAX;
+    // bin of the lane's next event: the support start when it lies inside
+    // the chunk (the sums then drop what the lane's first polynomial block
+    // added before it), else the end of the current segment
+    int nxt = has ? (lo > Kc ? lo : nb) : INT32_MAX;
     double zr = 0.0, zi = 0.0, hh = 0.0;  // FP64 sums
     // mixed: FP32 running sums with Kahan compensation (value = sum - comp)
     float kzr = 0.f, kzi = 0.f, khh = 0.f, czr = 0.f, czi = 0.f, chh = 0.f;
@@ -824,38 +811,56 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
     GLOBAL double* const recp =
         (GLOBAL double*)a.rec + ((chunk - a.chunk0) * a.rec_stride + (s_idx < a.P_end ? s_idx - a.p0 : 0)) * kRec;
     GLOBAL double* zsp = (GLOBAL double*)a.zs + ((p < a.P_end ? p : a.p0) * (int64_t)N + n) * 3;  // Z, H of segment n
-    auto sums = [&](double& fzr, double& fzi, double& fhh) {
+    // where segment n's sums go when it ends: the head record if it started
+    // in an earlier chunk, else zs (a pointer rather than a flag, so that the
+    // bin loop carries no per-lane condition)
+    GLOBAL double* dst = before ? recp : zsp;
+    auto store_sums = [&](GLOBAL double* dst) {
         if constexpr (MIXED) {
-            fzr = ((double)kzr - (double)czr + (double)qzr) * a.zscale32;
-            fzi = ((double)kzi - (double)czi + (double)qzi) * a.zscale32;
-            fhh = ((double)khh - (double)chh + (double)qhh) * a.hscale32;
+            dst[0] = ((double)kzr - (double)czr + (double)qzr) * a.zscale32;
+            dst[1] = ((double)kzi - (double)czi + (double)qzi) * a.zscale32;
+            dst[2] = ((double)khh - (double)chh + (double)qhh) * a.hscale32;
         } else {
-            fzr = zr;
-            fzi = zi;
-            fhh = hh;
+            dst[0] = zr;
+            dst[1] = zi;
+            dst[2] = hh;
         }
     };
-    // close segment n at bin k (exclusive): its sums go to the head record if
-    // it started in an earlier chunk, else to zs; move to the next non-empty one
-    auto flush = [&](int k) {
-        double fzr, fzi, fhh;
-        sums(fzr, fzi, fhh);
-        GLOBAL double* const dst = before ? recp : zsp;
-        dst[0] = fzr;
-        dst[1] = fzi;
-        dst[2] = fhh;
+    // Event of the lanes with nxt <= k, before bin k is added.  The sums go
+    // out and are cleared: at a segment end (reached here, or passed while
+    // the wave skipped bins where this lane has none after its support) to
+    // dst; at the support start to zs of the first segment, which that
+    // segment's own store replaces later (or nothing reads, if it continues
+    // into the next chunk).  A segment end moves the lane to the next
+    // non-empty segment; after the last one the lane has no more events and
+    // nothing reads its sums.
+    //
+    // The next edge but one is read ahead with no wait: the bounds rows
+    // carry two spare entries after the last, and the value is used only
+    // while it is an edge of this particle (n + 2 <= N).  Only a run of empty
+    // segments needs edges at once: a search finds the segment that holds
+    // bin k, or none if the support ended at or before k.
+    auto handle = [&](int k) {
+        store_sums(dst);
         clear_sums();
-        before = false;
-        ++n;
-        zsp += 3;
-        nb = (n < N) ? nb2 : INT32_MAX;
-        nb2 = (n + 2 <= N) ? bo[n + 2] : INT32_MAX;
-        while (n < N - 1 && nb == k) {  // empty segments
+        if (nb <= k) {
             ++n;
             zsp += 3;
-            nb = bo[n + 1];
-            nb2 = (n + 2 <= N) ? bo[n + 2] : INT32_MAX;
+            nb = (n < N) ? nb2 : INT32_MAX;
+            nb2 = bo[n + 2];
+            if (nb <= k) {
+                n = bsearch_seg(bo, N, k);
+                nb = bo[n + 1];
+                if (nb <= k) {
+                    n = N;
+                    nb = INT32_MAX;
+                }
+                nb2 = bo[n + 2];
+                zsp = (GLOBAL double*)a.zs + ((p < a.P_end ? p : a.p0) * (int64_t)N + n) * 3;
+            }
+            dst = zsp;
         }
+        nxt = nb;
     };
     const int L = a.L;
     const int nthreads = blockDim.x;
@@ -865,60 +870,41 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
     float a1h = 0.f;
     SinCosK kk{kSin5, kSin3, kCos4, kCos2};
     __asm__ volatile("" : "+v"(kk.s5), "+v"(kk.s3), "+v"(kk.c4), "+v"(kk.c2));
-    // one-channel idle lanes: index of the zero entry, zero weight
+    // Polynomials are zero until the lane's first block set-up (one-channel
+    // lanes also read the table's zero entry, with zero weight), so bins the
+    // wave runs before a lane's support add exact zeros.
     int tmask = 0, toff = kTabZero;
     double amp = 0.0;
+    if constexpr (MIXED) {
+#pragma unroll
+        for (int mm = 0; mm < kNodes; ++mm) phf[mm] = 0.f;
+        if constexpr (RESP) {
+#pragma unroll
+            for (int f = 0; f < 4; ++f)
+#pragma unroll
+                for (int mm = 0; mm < kNodes; ++mm) rf[f][mm] = 0.f;
+        }
+    } else {
+#pragma unroll
+        for (int mm = 0; mm < kNodes; ++mm) poly.ph[mm] = 0.0;
+        if constexpr (RESP) {
+#pragma unroll
+            for (int f = 0; f < 4; ++f)
+#pragma unroll
+                for (int mm = 0; mm < kNodes; ++mm) rp.r[f][mm] = 0.0;
+        }
+    }
     // Each lane builds its polynomials on the sub-blocks of its own length
     // 2^lgl (aligned; the wave steps through the shortest in the wave, whose
     // boundaries are boundaries of every lane's), so a particle's arithmetic
     // does not depend on the particles that share its wave.  have: first bin
-    // of the lane's current sub-block (-1: zero polynomials); kcl its centre.
+    // of the lane's current sub-block (-1: none yet); kcl its centre.  After
+    // its support a lane keeps its last polynomials: what they add is never
+    // read.
     const int lgl = has ? lg : lgw;
     const GLOBAL double* __restrict__ gtl = (const GLOBAL double*)gtab + a.gtab_off[lgl] * kGStride;
     const GLOBAL double* __restrict__ coef = (const GLOBAL double*)a.coef;
     int have = -1, kcl = 0;
-    auto zero_polys = [&]() {
-        if constexpr (MIXED) {
-            a1h = 0.f;
-#pragma unroll
-            for (int mm = 0; mm < kNodes; ++mm) phf[mm] = 0.f;
-            if constexpr (RESP) {
-#pragma unroll
-                for (int f = 0; f < 4; ++f)
-#pragma unroll
-                    for (int mm = 0; mm < kNodes; ++mm) rf[f][mm] = 0.f;
-            }
-        } else {
-#pragma unroll
-            for (int mm = 0; mm < kNodes; ++mm) poly.ph[mm] = 0.0;
-            if constexpr (RESP) {
-#pragma unroll
-                for (int f = 0; f < 4; ++f)
-#pragma unroll
-                    for (int mm = 0; mm < kNodes; ++mm) rp.r[f][mm] = 0.0;
-            }
-        }
-        tmask = 0;
-        toff = kTabZero;
-        amp = 0.0;
-        have = -1;
-    };
-    // lanes whose event is due at bin k (nxt <= k)
-    auto handle = [&](int k) {
-        if (stage == 0) {
-            clear_sums();
-            stage = 1;
-        }
-        if (stage == 1) {
-            if (nb == k && k < hi) flush(k);
-            if (hi <= k) {
-                stage = 2;
-                zero_polys();
-            }
-        }
-        nxt = (stage == 1) ? (nb < hi ? nb : hi) : INT32_MAX;
-        if (nxt <= k) nxt = INT32_MAX;  // not reached; keeps the wave loop finite
-    };
     for (int b0 = Kc; b0 < Ke; b0 += L) {
         const int b1 = (b0 + L < Ke) ? b0 + L : Ke;
         const int nbins = b1 - b0;
@@ -1006,80 +992,46 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
                             for (int mm = 0; mm < kNodes; ++mm) rf[f][mm] = (float)rp.r[f][mm];
                     }
                 }
-            } else if (!sact && have != -1) {
-                zero_polys();
             }
-            int ev = wave_min_i32(nxt);
-            int k = s_lo;
-            while (true) {
-                const int kend = ev < s_hi ? ev : s_hi;
-                if constexpr (!MIXED) {
-                    double jd = (double)(k - kcl);
-                    const double* binp = reinterpret_cast<const double*>(smem) + (k - b0) * NV;
+            // ---- bins [s_lo, s_hi), one at a time; a wave-wide test per bin
+            // sends the lanes whose event is due to handle() first
+            if constexpr (!MIXED) {
+                double jd = (double)(s_lo - kcl);
+                const double* binp = reinterpret_cast<const double*>(smem) + (s_lo - b0) * NV;
 #pragma unroll 1
-                    for (; k + 1 < kend; k += 2) {
-                        bin_fp64<RESP>(jd, binp, s_trig, kk, poly, rp, tmask, toff, amp, zr, zi, hh);
-                        bin_fp64<RESP>(jd + 1.0, binp + NV, s_trig, kk, poly, rp, tmask, toff, amp, zr, zi, hh);
-                        jd += 2.0;
-                        binp += 2 * NV;
-                    }
-                    if (k < kend) {
-                        bin_fp64<RESP>(jd, binp, s_trig, kk, poly, rp, tmask, toff, amp, zr, zi, hh);
-                        ++k;
-                    }
-                } else {
-                    const float ampf = (float)amp;
+                for (int k = s_lo; k < s_hi; ++k) {
+                    if (nxt <= k) handle(k);
+                    bin_fp64<RESP>(jd, binp, s_trig, kk, poly, rp, tmask, toff, amp, zr, zi, hh);
+                    jd += 1.0;
+                    binp += NV;
+                }
+            } else {
+                const float ampf = (float)amp;
+                float jf = (float)(s_lo - kcl);
+                const float* binp = reinterpret_cast<const float*>(smem) + (s_lo - b0) * NV;
 #pragma unroll 1
-                    while (k < kend) {
-                        // up to the next multiple of kMixedRun (a position fixed by
-                        // the bin index alone), or the end of the run
-                        const int pe = ((k | (kMixedRun - 1)) + 1 < kend) ? (k | (kMixedRun - 1)) + 1 : kend;
-                        float jf = (float)(k - kcl);
-                        const float* binp = reinterpret_cast<const float*>(smem) + (k - b0) * NV;
-#pragma unroll 1
-                        for (; k + 1 < pe; k += 2) {
-                            bin_mixed<RESP>(jf, binp, phf, a1h, rf, ampf, qzr, qzi, qhh);
-                            bin_mixed<RESP>(jf + 1.f, binp + NV, phf, a1h, rf, ampf, qzr, qzi, qhh);
-                            jf += 2.f;
-                            binp += 2 * NV;
-                        }
-                        if (k < pe) {
-                            bin_mixed<RESP>(jf, binp, phf, a1h, rf, ampf, qzr, qzi, qhh);
-                            ++k;
-                        }
-                        // (not past the support end: a compensated add of zero
-                        // still moves the compensation into the sum)
-                        if ((k & (kMixedRun - 1)) == 0 && stage != 2) {
-                            kahan(kzr, czr, qzr);
-                            kahan(kzi, czi, qzi);
-                            kahan(khh, chh, qhh);
-                            qzr = qzi = qhh = 0.f;
-                        }
+                for (int k = s_lo; k < s_hi; ++k) {
+                    if (nxt <= k) handle(k);
+                    bin_mixed<RESP>(jf, binp, phf, a1h, rf, ampf, qzr, qzi, qhh);
+                    jf += 1.f;
+                    binp += NV;
+                    // the plain FP32 sums enter the compensated ones at every
+                    // multiple of kMixedRun (a position fixed by the bin index)
+                    if (((k + 1) & (kMixedRun - 1)) == 0) {
+                        kahan(kzr, czr, qzr);
+                        kahan(kzi, czi, qzi);
+                        kahan(khh, chh, qhh);
+                        qzr = qzi = qhh = 0.f;
                     }
                 }
-                k = k > kend ? k : kend;
-                if (k >= s_hi) break;
-                if (nxt <= k) handle(k);
-                ev = wave_min_i32(nxt);
-                ev = ev > k ? ev : k + 1;  // every pass of this loop covers at least one bin
             }
         }
     }
-    // ---- close the chunk
-    if (has) {
-        if (nb <= hi) {
-            flush(hi);  // the open segment ends with the support or the chunk
-        } else {
-            double fzr, fzi, fhh;
-            sums(fzr, fzi, fhh);
-            // continues into the next chunk: the whole-chunk piece of a segment
-            // that also started earlier goes to the head record, else the tail
-            GLOBAL double* const dst = recp + (before ? 0 : 3);
-            dst[0] = fzr;
-            dst[1] = fzi;
-            dst[2] = fhh;
-        }
-    }
+    // ---- close the chunk: the open segment ends at hi (with the support or
+    // exactly at the chunk end), or continues into the next chunk, where the
+    // whole-chunk piece of a segment that also started earlier goes to the
+    // head record, else the tail
+    if (has && n < N) store_sums(nb <= hi ? dst : (dst == recp ? recp : recp + 3));
 }
 
 // The generate-and-reduce kernel, persistent, over the tiles of one or
