@@ -604,6 +604,9 @@ static int eval_front(EvalJob& j, const double* theta, double* ups, double* seg,
     ba.b64 = c->b64;
     ba.edges = c->d_edges;
     ba.bounds = w.bounds;
+    // node weights kept in LDS between the two passes of the equal-[h|h]
+    // edges: every node of the widest support (K bins), up to 4096 (32 KiB)
+    ba.wcache = (int)std::min<int64_t>((c->g.K - 1) / std::max<int64_t>(c->G, 1) + 2, 4096);
     launch_bounds(ba, s);
     MainArgs& ma = j.ma;
     ma = MainArgs{};

@@ -68,6 +68,7 @@ struct BoundArgs {
     const double* b64;
     const int64_t* edges;  // device, EXPLICIT mode
     int32_t* bounds;       // [P][N+1]
+    int wcache;            // EQUAL_SNR: node weights kept in LDS between the passes
 };
 
 struct MainArgs {

@@ -446,7 +446,8 @@ __device__ inline double weight_at(const double* __restrict__ cf, int64_t S, int
 // Equal-[h|h] edges (rule: nodes k_lo + jG and k_hi - 1, W linear between
 // nodes, C(k) = sum_{i<k} W(i), b_n = min{k : C(k) >= (n/N) C(k_hi)}).  One
 // wave per particle; 63 node intervals per round; two passes (total, then
-// edges) so that no per-node scratch is needed.
+// edges), the second reading the first's node weights from LDS as far as
+// a.wcache reaches and recomputing the rest.
 template <int NCH>
 __global__ __launch_bounds__(64) void k_bounds_equal(BoundArgs a)
 {
@@ -474,14 +475,28 @@ __global__ __launch_bounds__(64) void k_bounds_equal(BoundArgs a)
     auto node = [&](int64_t j) -> int64_t { return j >= nn ? khi : (j == nn - 1 ? khi - 1 : klo + j * G); };
     // interval integral over [node j, node j+1): g w_j + (w_{j+1} - w_j)(g - 1)/2,
     // the last interval being the single bin khi - 1 (w_{j+1} := w_j).
+    // LDS: the weights of the first a.wcache nodes, computed in the first
+    // pass and read in the second; C(node j0 + l + 1), l < 63, of the
+    // current round, which each target lane searches by bisection
+    extern __shared__ double s_w[];
+    __shared__ double s_c[64];
     double total = 0.0;
-    for (int pass = 0; pass < 2; ++pass) {
+    const int passes = N > 1 ? 2 : 1;  // one segment: no inner edges to place
+    for (int pass = 0; pass < passes; ++pass) {
+        __syncthreads();  // first-pass weights are in LDS
         double C0 = 0.0;
         int n_next = 1;
         for (int64_t j0 = 0; j0 < nn; j0 += 63) {
             const int64_t j = j0 + lane;
             double w = 0.0;
-            if (j < nn) w = weight_at<NCH>(a.coef, S, p, node(j), a.g, a.m, a.b64, bcoef, tc);
+            if (j < nn) {
+                if (pass == 1 && j < a.wcache) {
+                    w = s_w[j];
+                } else {
+                    w = weight_at<NCH>(a.coef, S, p, node(j), a.g, a.m, a.b64, bcoef, tc);
+                    if (j < a.wcache) s_w[j] = w;
+                }
+            }
             double wn = __shfl_down(w, 1, 64);
             if (j + 1 >= nn) wn = w;
             const int64_t xj = node(j), gj = node(j + 1) - xj;
@@ -497,20 +512,23 @@ __global__ __launch_bounds__(64) void k_bounds_equal(BoundArgs a)
             const double cend = C0 + incl;     // C(node j+1)
             const double cbeg = cend - I;      // C(node j)
             const double chunk_end = C0 + chunk;
+            const int last_live = (nn - 1 - j0) < 62 ? (int)(nn - 1 - j0) : 62;
+            __syncthreads();  // the previous round's searches are done
+            if (lane < 63) s_c[lane] = cend;
+            __syncthreads();
             // targets falling in this round
             while (n_next < N) {
                 const int n = n_next + lane;
                 const double tgt = ((double)n / (double)N) * total;
                 const bool mine = n < N && (tgt <= chunk_end || j0 + 63 >= nn);
-                // interval: first live lane with C(node j+1) >= tgt
-                int sel = 62;
-                for (int l = 62; l >= 0; --l) {
-                    const double ce = __shfl(cend, l, 64);
-                    const bool lv = (j0 + l) < nn;
-                    if (lv && ce >= tgt) sel = l;
+                // interval: first live lane with C(node j+1) >= tgt, else the
+                // last live one (C is non-decreasing: the weights are >= 0)
+                int sl = 0, sh = last_live;
+                while (sl < sh) {
+                    const int mid = (sl + sh) >> 1;
+                    if (s_c[mid] >= tgt) sh = mid; else sl = mid + 1;
                 }
-                const int64_t last_live = (nn - 1 - j0) < 62 ? (nn - 1 - j0) : 62;
-                if (sel > last_live) sel = (int)last_live;
+                const int sel = sl;
                 const double cb = __shfl(cbeg, sel, 64);
                 const double ws = __shfl(w, sel, 64);
                 const double wns = __shfl(wn, sel, 64);
@@ -1381,8 +1399,9 @@ void launch_bounds(const BoundArgs& a, hipStream_t s)
 {
     if (a.P <= 0) return;
     if (a.mode == 0) {
-        if (a.g.nch == 2) hipLaunchKernelGGL(k_bounds_equal<2>, dim3((unsigned)a.P), dim3(64), 0, s, a);
-        else hipLaunchKernelGGL(k_bounds_equal<1>, dim3((unsigned)a.P), dim3(64), 0, s, a);
+        const size_t lds = sizeof(double) * (size_t)a.wcache;
+        if (a.g.nch == 2) hipLaunchKernelGGL(k_bounds_equal<2>, dim3((unsigned)a.P), dim3(64), lds, s, a);
+        else hipLaunchKernelGGL(k_bounds_equal<1>, dim3((unsigned)a.P), dim3(64), lds, s, a);
     } else {
         hipLaunchKernelGGL(k_bounds_simple, dim3(nblk(a.P * (a.N + 1), 256)), dim3(256), 0, s, a);
     }
