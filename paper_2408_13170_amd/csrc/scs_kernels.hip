@@ -21,6 +21,9 @@
 // against the LDS wait counter; casting them keeps global accesses apart
 // from LDS waits.
 #define GLOBAL __attribute__((address_space(1)))
+// Constant-memory qualifier: read-only data at a wave-uniform address, which
+// the compiler then reads with scalar loads into scalar registers.
+#define CONSTANT __attribute__((address_space(4)))
 
 namespace scs {
 
@@ -419,7 +422,7 @@ __device__ __forceinline__ double wave_incl_scan(double v, int lane)
 
 // Dense weight w(k) = sum_alpha q_alpha(k) |R_alpha(t(f_k))|^2.
 template <int NCH>
-__device__ inline double weight_at(const double* __restrict__ cf, int64_t S, int64_t p, int64_t k, const GridArgs& g,
+__device__ inline double weight_at(const CONSTANT double* __restrict__ cf, int64_t S, int64_t p, int64_t k, const GridArgs& g,
                                    const ModelArgs& m, const double* __restrict__ b64, const double* bcoef, double tc)
 {
     if constexpr (NCH == 1) {
@@ -448,8 +451,10 @@ __device__ inline double weight_at(const double* __restrict__ cf, int64_t S, int
 // wave per particle; 63 node intervals per round; two passes (total, then
 // edges), the second reading the first's node weights from LDS as far as
 // a.wcache reaches and recomputing the rest.
+// Three waves per SIMD fit without spills (168 VGPRs); the kernel is
+// latency-bound, so residency is what counts.
 template <int NCH>
-__global__ __launch_bounds__(64) void k_bounds_equal(BoundArgs a)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_bounds_equal(BoundArgs a)
 {
     const int64_t p = blockIdx.x;
     const int lane = threadIdx.x;
@@ -463,10 +468,13 @@ __global__ __launch_bounds__(64) void k_bounds_equal(BoundArgs a)
         return;
     }
     const int64_t S = a.stride;
+    // the particle's coefficients are the same in every lane: scalar loads
+    // (the kernel writes only the edges, so the scalar cache stays valid)
+    const CONSTANT double* cfc = (const CONSTANT double*)a.coef;
     double bcoef[8];
-    bcoef[0] = a.coef[p * kCoefStride + C_C0H];
-    for (int i = 1; i < 8; ++i) bcoef[i] = a.coef[p * kCoefStride + (C_B1 + i - 1)];
-    const double tc = a.coef[p * kCoefStride + C_TC];
+    bcoef[0] = cfc[p * kCoefStride + C_C0H];
+    for (int i = 1; i < 8; ++i) bcoef[i] = cfc[p * kCoefStride + (C_B1 + i - 1)];
+    const double tc = cfc[p * kCoefStride + C_TC];
     const int64_t G = a.G;
     const int64_t len = khi - klo;
     const int64_t nreg = (len - 1) / G + 1;
@@ -493,7 +501,7 @@ __global__ __launch_bounds__(64) void k_bounds_equal(BoundArgs a)
                 if (pass == 1 && j < a.wcache) {
                     w = s_w[j];
                 } else {
-                    w = weight_at<NCH>(a.coef, S, p, node(j), a.g, a.m, a.b64, bcoef, tc);
+                    w = weight_at<NCH>(cfc, S, p, node(j), a.g, a.m, a.b64, bcoef, tc);
                     if (j < a.wcache) s_w[j] = w;
                 }
             }
@@ -645,7 +653,7 @@ constexpr int kTabZero = kTrig;      // index of the zero entry
 // whole loop (an FP64 FMA reads at most one scalar register, so constants
 // kept in scalar registers would be copied into a vector register per use).
 struct SinCosK {
-    double s5, s3, c4, c2;
+    double s5, s3, s1, c4, c2;
 };
 
 template <bool RESP>
@@ -653,41 +661,51 @@ __device__ __forceinline__ void bin_fp64(double j, const double* __restrict__ bi
                                          const SinCosK& kk, const PhasePoly& poly, const RespPoly& rp, int tmask,
                                          int toff, double amp, double& zr, double& zi, double& hh)
 {
+    // the bin's data first, then the table read, so that both are in flight
+    // while the response and the noise weight are evaluated
+    double2 uA, uE, qq;
+    double ur, ui, q1;
+    if constexpr (RESP) {
+        uA = *reinterpret_cast<const double2*>(bin);
+        uE = *reinterpret_cast<const double2*>(bin + 2);
+        qq = *reinterpret_cast<const double2*>(bin + 4);
+    } else {
+        ur = bin[0];
+        ui = bin[1];
+        q1 = bin[2];
+    }
     const double pc = horner5(poly.ph, j);
     const double t = pc + kRoundShift;
     const int iq = ((int)(uint32_t)__double_as_longlong(t) & tmask) | toff;
-    const double s = pc - (t - kRoundShift);  // exact, |s| <= 1/2
-    const double z = s * s;
-    const double sn = s * __builtin_fma(z, __builtin_fma(z, kk.s5, kk.s3), kSin1);
-    const double cn = __builtin_fma(z, __builtin_fma(z, kk.c4, kk.c2), 1.0);
     const double2 tt = tab[iq];
-    const double sv = __builtin_fma(tt.y, cn, tt.x * sn);
-    const double cv = __builtin_fma(tt.x, cn, -(tt.y * sn));
+    double sr, si;
     if constexpr (RESP) {
-        const double2 uA = *reinterpret_cast<const double2*>(bin);
-        const double2 uE = *reinterpret_cast<const double2*>(bin + 2);
-        const double2 qq = *reinterpret_cast<const double2*>(bin + 4);
         const double rar = horner5(rp.r[0], j), rai = horner5(rp.r[1], j);
         const double rer = horner5(rp.r[2], j), rei = horner5(rp.r[3], j);
-        double sr = uA.x * rar;
+        sr = uA.x * rar;
         sr = __builtin_fma(uA.y, rai, sr);
         sr = __builtin_fma(uE.x, rer, sr);
         sr = __builtin_fma(uE.y, rei, sr);
-        double si = uA.y * rar;
+        si = uA.y * rar;
         si = __builtin_fma(-uA.x, rai, si);
         si = __builtin_fma(uE.y, rer, si);
         si = __builtin_fma(-uE.x, rei, si);
-        zr = __builtin_fma(sr, cv, __builtin_fma(-si, sv, zr));
-        zi = __builtin_fma(sr, sv, __builtin_fma(si, cv, zi));
         const double wa = __builtin_fma(rar, rar, rai * rai);
         const double we = __builtin_fma(rer, rer, rei * rei);
         hh = __builtin_fma(qq.x, wa, __builtin_fma(qq.y, we, hh));
     } else {
-        const double ur = bin[0], ui = bin[1], qq = bin[2];
-        zr = __builtin_fma(ur, cv, __builtin_fma(-ui, sv, zr));
-        zi = __builtin_fma(ur, sv, __builtin_fma(ui, cv, zi));
-        hh = __builtin_fma(qq, amp, hh);
+        sr = ur;
+        si = ui;
+        hh = __builtin_fma(q1, amp, hh);
     }
+    const double s = pc - (t - kRoundShift);  // exact, |s| <= 1/2
+    const double z = s * s;
+    const double sn = s * __builtin_fma(z, __builtin_fma(z, kk.s5, kk.s3), kk.s1);
+    const double cn = __builtin_fma(z, __builtin_fma(z, kk.c4, kk.c2), 1.0);
+    const double sv = __builtin_fma(tt.y, cn, tt.x * sn);
+    const double cv = __builtin_fma(tt.x, cn, -(tt.y * sn));
+    zr = __builtin_fma(sr, cv, __builtin_fma(-si, sv, zr));
+    zi = __builtin_fma(sr, sv, __builtin_fma(si, cv, zi));
 }
 
 // One bin of the mixed path: FP32 phase a0 + frac(a1h j) + residual(j)
@@ -698,6 +716,18 @@ template <bool RESP>
 __device__ __forceinline__ void bin_mixed(float jf, const float* __restrict__ bin, const float* phf, float a1h,
                                           const float (*rf)[kNodes], float amp, float& pzr, float& pzi, float& phh)
 {
+    // the bin's data first, in flight while the phase and sin / cos are formed
+    float4 u;
+    float2 qq;
+    float ur, ui, q1;
+    if constexpr (RESP) {
+        u = *reinterpret_cast<const float4*>(bin);
+        qq = *reinterpret_cast<const float2*>(bin + 4);
+    } else {
+        ur = bin[0];
+        ui = bin[1];
+        q1 = bin[2];
+    }
     const float pl = a1h * jf;
     const float f1 = pl - rintf(pl);
     float r = phf[5];
@@ -711,8 +741,6 @@ __device__ __forceinline__ void bin_mixed(float jf, const float* __restrict__ bi
     if constexpr (RESP) {
         const float rar = horner5f(rf[0], jf), rai = horner5f(rf[1], jf);
         const float rer = horner5f(rf[2], jf), rei = horner5f(rf[3], jf);
-        const float4 u = *reinterpret_cast<const float4*>(bin);
-        const float2 qq = *reinterpret_cast<const float2*>(bin + 4);
         float sr = u.x * rar;
         sr = __builtin_fmaf(u.y, rai, sr);
         sr = __builtin_fmaf(u.z, rer, sr);
@@ -727,10 +755,11 @@ __device__ __forceinline__ void bin_mixed(float jf, const float* __restrict__ bi
         const float we = __builtin_fmaf(rer, rer, rei * rei);
         phh = __builtin_fmaf(qq.x, wa, __builtin_fmaf(qq.y, we, phh));
     } else {
-        const float ur = bin[0] * amp, ui = bin[1] * amp;
+        ur *= amp;
+        ui *= amp;
         pzr = __builtin_fmaf(ur, cs, __builtin_fmaf(-ui, sn, pzr));
         pzi = __builtin_fmaf(ur, sn, __builtin_fmaf(ui, cs, pzi));
-        phh = __builtin_fmaf(bin[2], amp, phh);
+        phh = __builtin_fmaf(q1, amp, phh);
     }
 }
 
@@ -886,8 +915,8 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
     RespPoly rp;
     float phf[kNodes], rf[4][kNodes];
     float a1h = 0.f;
-    SinCosK kk{kSin5, kSin3, kCos4, kCos2};
-    __asm__ volatile("" : "+v"(kk.s5), "+v"(kk.s3), "+v"(kk.c4), "+v"(kk.c2));
+    SinCosK kk{kSin5, kSin3, kSin1, kCos4, kCos2};
+    __asm__ volatile("" : "+v"(kk.s5), "+v"(kk.s3), "+v"(kk.s1), "+v"(kk.c4), "+v"(kk.c2));
     // Polynomials are zero until the lane's first block set-up (one-channel
     // lanes also read the table's zero entry, with zero weight), so bins the
     // wave runs before a lane's support add exact zeros.
@@ -1013,6 +1042,9 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
             }
             // ---- bins [s_lo, s_hi), one at a time; a wave-wide test per bin
             // sends the lanes whose event is due to handle() first
+            // no vector-memory operation of the set-up (spill reloads
+            // included) is left pending, so the bin loop needs no wait for one
+            __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
             if constexpr (!MIXED) {
                 double jd = (double)(s_lo - kcl);
                 const double* binp = reinterpret_cast<const double*>(smem) + (s_lo - b0) * NV;
@@ -1450,11 +1482,25 @@ __global__ void k_sort_hist(int64_t P, int64_t K, const int32_t* __restrict__ kl
                             unsigned* __restrict__ hist, int32_t* __restrict__ bucket, int32_t* __restrict__ rank)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= P) return;
+    const bool live = i < P;
     const int64_t w = K / 256 + 1;  // level width
-    const int b = (int)(((int64_t)khi[i] / w) * 256 + (int64_t)klo[i] / w);
-    bucket[i] = b;
-    rank[i] = (int32_t)atomicAdd(&hist[b], 1u);
+    const int b = live ? (int)(((int64_t)khi[i] / w) * 256 + (int64_t)klo[i] / w) : -1;
+    if (live) bucket[i] = b;
+    // one atomic per distinct bucket of the wave (a converged swarm puts
+    // most particles in a few buckets, where per-particle atomics serialise)
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = (1ULL << lane) - 1ULL;
+    unsigned long long todo = __ballot(live);
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int bl = __shfl(b, leader, 64);
+        const unsigned long long peers = __ballot(live && b == bl);
+        unsigned base = 0;
+        if (lane == leader) base = atomicAdd(&hist[bl], (unsigned)__popcll(peers));
+        base = __shfl(base, leader, 64);
+        if (live && b == bl) rank[i] = (int32_t)(base + (unsigned)__popcll(peers & below));
+        todo &= ~peers;
+    }
 }
 // Exclusive prefix sums of the histogram, one workgroup of 1024 threads.
 __global__ __launch_bounds__(1024) void k_sort_scan(unsigned* __restrict__ hist)
