@@ -337,8 +337,8 @@ def bench_serve(args):
     budget = 64 << 30
     srv = B.scs_server_create(0, max_inflight=32, hbm_budget=budget, n_streams=4)
 
-    def run(reqs, arrivals):
-        outs, t_sub = {}, {}
+    def run(reqs, arrivals, prec):
+        outs = {}
         done = []
         t0 = time.perf_counter()
         k = 0
@@ -347,7 +347,7 @@ def bench_serve(args):
             while k < len(reqs) and (arrivals is None or arrivals[k] <= now):
                 ctx, N, th, si = reqs[k]
                 ups = np.empty(th.shape[0])
-                rid = B.scs_server_submit(srv, ctx, N, th, ups, B.SCS_PREC_FP64)
+                rid = B.scs_server_submit(srv, ctx, N, th, ups, prec)
                 outs[rid] = (ups, k)
                 k += 1
             wait = 1 if k < len(reqs) else 20
@@ -355,41 +355,62 @@ def bench_serve(args):
         t1 = time.perf_counter() - t0
         lat = np.array([d["t_done"] - d["t_submit"] for d in done]) * 1e3
         assert all(d["status"] == 0 for d in done)
-        return t1, lat
+        results = [None] * len(reqs)
+        for rid, (ups, i) in outs.items():
+            results[i] = ups
+        return t1, lat, results
 
-    # capacity: a closed burst of requests
-    for _, ctx in searches:
-        B.scs_ctx_stats(ctx, reset=True)
     burst = make_requests(max(64, args.requests // 8))
-    run(burst[:16], None)  # warm-up: workspaces, slots
-    for _, ctx in searches:
-        B.scs_ctx_stats(ctx, reset=True)
-    t_b, _ = run(burst, None)
-    ev_b = sum(B.scs_ctx_stats(ctx, reset=True)[0] for _, ctx in searches)
-    capacity = len(burst) / t_b
-    log(f"capacity {capacity:.1f} requests/s, {ev_b / t_b:.4g} evals/s")
-    levels = []
-    for load in [float(x) for x in args.loads.split(",")]:
-        reqs = make_requests(args.requests)
-        arrivals = np.cumsum(rng.exponential(1.0 / (load * capacity), len(reqs)))
-        t, lat = run(reqs, arrivals)
-        ev = sum(B.scs_ctx_stats(ctx, reset=True)[0] for _, ctx in searches)
-        levels.append({"offered_load": load, "offered_rps": load * capacity, "achieved_rps": len(reqs) / t,
-                       "evals_per_s": ev / t, "requests": len(reqs),
-                       "latency_ms": {"p50": float(np.median(lat)), "p99": float(np.quantile(lat, 0.99))}})
-        log(f"load {load}: {len(reqs) / t:.1f} req/s, p50 {np.median(lat):.1f} ms, p99 {np.quantile(lat, 0.99):.1f} ms")
+    run(burst[:16], None, B.SCS_PREC_FP64)  # warm-up: workspaces, slots
+    run(burst[:16], None, B.SCS_PREC_MIXED)
+    report = {}
+    burst_out = {}
+    for pname, prec in (("fp64", B.SCS_PREC_FP64), ("mixed", B.SCS_PREC_MIXED)):
+        # capacity: a closed burst of requests
+        for _, ctx in searches:
+            B.scs_ctx_stats(ctx, reset=True)
+        t_b, _, burst_out[pname] = run(burst, None, prec)
+        ev_b = sum(B.scs_ctx_stats(ctx, reset=True)[0] for _, ctx in searches)
+        capacity = len(burst) / t_b
+        log(f"{pname}: capacity {capacity:.1f} requests/s, {ev_b / t_b:.4g} evals/s")
+        levels = []
+        for load in [float(x) for x in args.loads.split(",")]:
+            reqs = make_requests(args.requests)
+            arrivals = np.cumsum(rng.exponential(1.0 / (load * capacity), len(reqs)))
+            t, lat, _ = run(reqs, arrivals, prec)
+            ev = sum(B.scs_ctx_stats(ctx, reset=True)[0] for _, ctx in searches)
+            levels.append({"offered_load": load, "offered_rps": load * capacity, "achieved_rps": len(reqs) / t,
+                           "evals_per_s": ev / t, "requests": len(reqs),
+                           "latency_ms": {"p50": float(np.median(lat)), "p99": float(np.quantile(lat, 0.99))}})
+            log(f"{pname} load {load}: {len(reqs) / t:.1f} req/s, p50 {np.median(lat):.1f} ms, "
+                f"p99 {np.quantile(lat, 0.99):.1f} ms")
+        report[pname] = {"capacity_rps": capacity, "capacity_evals_per_s": ev_b / t_b, "levels": levels}
+    # mixed against FP64 on the burst's requests (each served in both precisions)
+    errs = []
+    for (ctx, N, th, si), a, b in zip(burst, burst_out["fp64"], burst_out["mixed"]):
+        ok = np.isfinite(a)
+        errs.append(np.abs(b[ok] - a[ok]) / np.maximum(np.abs(a[ok]), 2.0 * N))
+    err = np.concatenate(errs)
+    report["mixed"]["err_vs_fp64"] = {"median": float(np.median(err)), "p99": float(np.quantile(err, 0.99)),
+                                      "max": float(err.max()), "requests": len(burst),
+                                      "measure": "|U_mixed - U_fp64| / max(U_fp64, 2N), same requests served "
+                                                 "in both precisions"}
+    log(f"mixed vs fp64 on {len(burst)} served requests: median {np.median(err):.3g}, max {err.max():.3g}")
     st = B.scs_server_stats(srv)
     B.scs_server_destroy(srv)
     for _, ctx in searches:
         B.scs_ctx_destroy(ctx)
-    out = {"metric": "served statistic evaluations: p50/p99 request latency and throughput, FP64",
+    levels = report["fp64"]["levels"]
+    out = {"metric": "served statistic evaluations: p50/p99 request latency and throughput, FP64; mixed beside",
            "value": levels[-1]["evals_per_s"], "unit": "evals/s", "n_gpus": 1, "steps": len(levels),
            "warmup": 1, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f64", "data": "synthetic: eight seeded searches",
            "config": {"workload": "8 searches, K in {2^19, 2^20, 2^21}, A+E; requests of 256-16384 particles "
                                   "(log-uniform), N in " + str(ladder) + ", Poisson arrivals",
                       "max_inflight": 32, "streams": 4, "hbm_budget_gib": budget >> 30},
-           "capacity_rps": capacity, "capacity_evals_per_s": ev_b / t_b, "levels": levels,
+           "capacity_rps": report["fp64"]["capacity_rps"],
+           "capacity_evals_per_s": report["fp64"]["capacity_evals_per_s"], "levels": levels,
+           "mixed": report["mixed"],
            "server": {k: int(v) for k, v in st.items()}}
     print(json.dumps(out), flush=True)
 
