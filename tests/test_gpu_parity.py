@@ -153,18 +153,39 @@ def test_edge_cases_lisa_small():
     th[1, 0] = -1.0        # invalid chirp mass
     th[2, 1] = 0.3         # eta > 1/4
     th[3, 2] = 0.0195      # support empty (f_low above the band)
-    th[4, 2] = 0.01895     # a few bins of support: more segments than bins
-    th[5:, :] = D.lisa_particles(65, seed=8)
+    th[4, 2] = 0.018999    # 10 bins of support: 22 of the 32 segments empty
+    th[5, 2] = 0.0189975   # 24 bins: 8 empty segments
+    th[6, 2] = 0.01895     # 499 bins
+    th[7:, :] = D.lisa_particles(63, seed=8)
     N = 32
-    ref = _ref(ds, th, N, O.SEG_EQUAL_SNR, 1)
+    ref = _ref(ds, th, N, O.SEG_EQUAL_SNR, 1, seg=True)
     c = Ctx(ds, N, B.SCS_SEG_EQUAL_SNR, 1)
     try:
-        got, _ = c.eval(th)
+        got, seg = c.eval(th, seg=True)
         assert np.isnan(got[1]) and np.isnan(got[2])
         assert got[3] == 0.0
         ok = ~np.isnan(ref["ups"])
         e = _floored(got[ok], ref["ups"][ok], N)
         assert e.max() < TOL64
+        # per-segment (Z, H): empty segments (particles 4 and 5 have runs of
+        # them) exactly zero, the others against the oracle
+        sup, bnd = B.scs_last_bounds(c.h, th.shape[0], N)
+        rows = np.flatnonzero(ok & np.all(bnd == ref["bounds"], axis=1))
+        assert 4 in rows and 5 in rows and len(rows) >= 0.9 * ok.sum()
+        rs = ref["seg"]
+        empty = bnd[:, 1:] == bnd[:, :-1]
+        assert empty[4].sum() == 22 and empty[5].sum() == 8
+        for p in rows:
+            assert np.all(seg[p][empty[p]] == 0.0)
+            full = ~empty[p]
+            if not full.any():  # empty support
+                continue
+            zscale = np.abs(rs[p][full, :2]).max()
+            assert np.abs(seg[p][full, :2] - rs[p][full, :2]).max() <= 1e-9 * zscale
+            # H carries |R|^2 of the interpolated response: the block length is
+            # chosen for 1e-11 relative on R, so 2e-11 on |R|^2 (seen as such on
+            # one-bin segments, where nothing averages it down)
+            assert np.abs(seg[p][full, 2] / rs[p][full, 2] - 1.0).max() < 5e-11
         # determinism: bitwise identical on a second run
         got2, _ = c.eval(th)
         assert np.array_equal(got[ok], got2[ok])
