@@ -172,6 +172,30 @@ def main():
     a, b = u64.cpu().numpy(), u32.cpu().numpy()
     ok = np.isfinite(a)
     err = np.abs(b[ok] - a[ok]) / np.maximum(np.abs(a[ok]), 2.0 * w.N)
+    # likelihood epilogue (Sec 2.1 - 2.2) on the same swarm: the same
+    # generate-and-reduce with more sums in the epilogue, then log hat L_N and log L
+    st = torch.empty((w.P, B.SCS_NSTATS), dtype=torch.float64, device=dev)
+    amp = torch.ones(w.P, dtype=torch.float64, device=dev)
+    ls, lc = torch.empty_like(amp), torch.empty_like(amp)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    reps = 3
+    ev[0].record(stream)
+    for _ in range(reps):
+        B.scs_evaluate(ctx, th, u64, B.SCS_PREC_FP64)
+    ev[1].record(stream)
+    for _ in range(reps):
+        B.scs_evaluate_stats(ctx, th, st, B.SCS_PREC_FP64)
+    ev[2].record(stream)
+    for _ in range(reps):
+        B.scs_loglike(ctx, st, amp, None, ls, lc)
+    ev[3].record(stream)
+    torch.cuda.synchronize()
+    epi = {"evaluate_ms": ev[0].elapsed_time(ev[1]) / reps, "evaluate_stats_ms": ev[1].elapsed_time(ev[2]) / reps,
+           "loglike_ms": ev[2].elapsed_time(ev[3]) / reps,
+           "what": "one FP64 evaluation of the fixed 10^4-particle swarm: Upsilon only, then with hat O_N, "
+                   "<h|h>, <d|h> (Sec 2.1 - 2.2), then log hat L_N and log L from those rows"}
+    log(f"likelihood epilogue: evaluate {epi['evaluate_ms']:.3f} ms, with statistics "
+        f"{epi['evaluate_stats_ms']:.3f} ms, loglike {epi['loglike_ms']:.4f} ms")
 
     value = r64["evals"] / r64["wall_s"]
     ms_step = 1e3 * r64["wall_s"] / args.steps
@@ -201,6 +225,7 @@ def main():
                      "avg_launch_ms": avg_main_ms, "flop_per_eval": FLOP_PER_EVAL_FP64,
                      "evals_per_launch": evals_per_launch},
         "unresolved_particles": r64["unresolved"],
+        "likelihood_epilogue": epi,
     }
     if rmx is not None:
         out["mixed"] = {"value": rmx["evals"] / rmx["wall_s"], "unit": "evals/s",

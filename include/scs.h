@@ -129,6 +129,39 @@ int scs_define_segmentation(scs_ctx* ctx, int32_t N, int32_t mode, int32_t G, co
 int scs_evaluate(scs_ctx* ctx, int64_t P, const double* theta, int32_t prec, double* ups, double* seg,
                  int32_t mem_kind, void* stream);
 
+/* ---- likelihood epilogues (Sec 2.1 - 2.2) ---------------------------- */
+
+/* Statistics per row of scs_evaluate_stats. */
+#define SCS_NSTATS 5
+
+/* The generate-and-reduce of scs_evaluate with the likelihood epilogue.  For
+ * the template h at unit amplitude and zero phase offset (the h of
+ * scs_waveform), stats [P][SCS_NSTATS] out:
+ *   [0] Upsilon_N                              (Sec 2.2)
+ *   [1] hat O_N(d, h) = sum_n max_phi_n [d|h e^{i phi_n}]_n  (eq:semi-coherent_O)
+ *   [2] <h|h>, the squared optimal SNR         (eqn:SNR_coherent)
+ *   [3] Re <d|h>, [4] Im <d|h>, so that <d|h e^{i phi}> = Re(e^{-i phi} <d|h>)
+ *                                              (eqn:inner_prod)
+ * A row is NaN for an invalid theta and zero for an empty support.  Arguments,
+ * memory kinds, stream semantics and errors as for scs_evaluate. */
+int scs_evaluate_stats(scs_ctx* ctx, int64_t P, const double* theta, int32_t prec, double* stats, int32_t mem_kind,
+                       void* stream);
+
+/* <d|d> of the loaded data (eqn:inner_prod with a = b = d), computed when the
+ * data are loaded; *dd is a host double.  Errors: EINVAL, ESTATE (no data). */
+int scs_data_norm(const scs_ctx* ctx, double* dd);
+
+/* Log-likelihoods of the templates A h e^{i phi} from scs_evaluate_stats rows,
+ * without the normalisation constant (as Sec 2.1 drops it):
+ *   logl_semi = -<d|d>/2 - A^2 <h|h>/2 + |A| hat O_N   (log hat L_N, Sec 2.2)
+ *   logl_coh  = -<d|d>/2 - A^2 <h|h>/2 + A Re(e^{-i phi} <d|h>)  (eqn:LogL_coherent)
+ * amp [P] (A); phase [P] (phi) or NULL, which maximises logl_coh over phi;
+ * either output [P] may be NULL.  mem_kind applies to every array; device
+ * arrays are read on the stream, host arrays are staged and the call
+ * synchronises.  Errors: EINVAL, ESTATE (no data), EDEVICE. */
+int scs_loglike(scs_ctx* ctx, int64_t P, const double* stats, const double* amp, const double* phase,
+                double* logl_semi, double* logl_coh, int32_t mem_kind, void* stream);
+
 /* Per-particle support [k_lo, k_hi) and segment edges b_0..b_N (int32) from
  * the last scs_evaluate on this context, copied to host arrays
  * support [P][2] and bounds [P][N+1] (either may be NULL).  Synchronises the

@@ -6,6 +6,10 @@ code with the HIP library ``paper_2408_13170_amd`` and neither imports the
 other.  The arithmetic lives in ``oracle.c`` (built by ``oracle/build.py``);
 this module only marshals numpy arrays through ctypes.
 
+Besides Upsilon_N it gives the likelihood quantities of Sec 2.1 - 2.2
+(``data_norm``, ``likelihood_stats``, ``loglike``), written in numpy on top of
+the per-segment sums of ``evaluate``.
+
 Parameter vector theta (7 doubles):
     Mc [Msun, detector frame], eta, f_low [Hz], lambda, beta, iota, psi
 (the searched parameters of Table tab:GW150914-like_injection, without e0).
@@ -152,6 +156,51 @@ def evaluate(grid: Grid, model: Model, d_ri, psd, theta, N, mode=SEG_EQUAL_SNR, 
     if want_bounds:
         out["bounds"] = bnd
     return out
+
+
+def data_norm(grid: Grid, d_ri, psd):
+    """<d|d> = sum_alpha 4 df sum_k |d_alpha(f_k)|^2 / S_alpha(f_k)
+    (eqn:inner_prod with a = b = d, rectangle rule on the bins)."""
+    d_ri, psd = _f64(d_ri), _f64(psd)
+    return float(4.0 * grid.df * np.sum((d_ri[..., 0] ** 2 + d_ri[..., 1] ** 2) / psd))
+
+
+def likelihood_stats(grid: Grid, model: Model, d_ri, psd, theta, N, mode=SEG_EQUAL_SNR, G=1, edges=None):
+    """Sufficient statistics of the likelihoods of Sec 2.1 - 2.2 for every row
+    of theta, for the template h of ``template()`` at unit amplitude and zero
+    phase offset; with Z_n = sum over segment n of d conj(h) / S and
+    H_n = sum |h|^2 / S (the per-segment sums of ``evaluate``):
+        ups      Upsilon_N = sum_n x_n^2 / [h|h]_n
+        overlap  hat O_N(d, h) = sum_n max_phi_n [d|h e^{i phi_n}]_n
+                 = sum_n 4 df |Z_n|                       (eq:semi-coherent_O)
+        hh       <h|h> = sum_n [h|h]_n = 4 df sum_n H_n    (eqn:SNR_coherent, squared)
+        dh       <d|h> as a complex number 4 df sum_n Z_n, so that
+                 <d|h e^{i phi}> = Re(e^{-i phi} dh)       (eqn:inner_prod)
+    Returns a dict of [P] arrays (dh complex); NaN rows for invalid theta."""
+    out = evaluate(grid, model, d_ri, psd, theta, N, mode, G, edges, want_seg=True)
+    seg = out["seg"]
+    Z = seg[..., 0] + 1j * seg[..., 1]
+    H = seg[..., 2]
+    w = 4.0 * grid.df
+    return {"ups": out["ups"], "overlap": w * np.sum(np.abs(Z), axis=1), "hh": w * np.sum(H, axis=1),
+            "dh": w * np.sum(Z, axis=1)}
+
+
+def loglike(dd, stats, amp, phase=None):
+    """Log-likelihoods for templates A h e^{i phi} (A real), dropping the
+    normalisation constant as the paper does:
+        semi  log hat L_N = -<d|d>/2 - A^2 <h|h>/2 + hat O_N(d, A h)
+                          = -<d|d>/2 - A^2 <h|h>/2 + |A| hat O_N(d, h)
+        coh   log L       = -<d|d>/2 - A^2 <h|h>/2 + A Re(e^{-i phi} <d|h>)   (eqn:LogL_coherent)
+    With phase None the coherent one is maximised over phi (|A| |<d|h>|)."""
+    amp = np.asarray(amp, dtype=np.float64)
+    base = -0.5 * dd - 0.5 * amp ** 2 * stats["hh"]
+    semi = base + np.abs(amp) * stats["overlap"]
+    if phase is None:
+        coh = base + np.abs(amp) * np.abs(stats["dh"])
+    else:
+        coh = base + amp * np.real(np.exp(-1j * np.asarray(phase, dtype=np.float64)) * stats["dh"])
+    return semi, coh
 
 
 def template(grid: Grid, model: Model, theta):

@@ -68,6 +68,10 @@ _SIGS = {
     "scs_define_segmentation": [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p],
     "scs_evaluate": [C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p],
     "scs_last_bounds": [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p],
+    "scs_evaluate_stats": [C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p],
+    "scs_data_norm": [C.c_void_p, C.POINTER(C.c_double)],
+    "scs_loglike": [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                    C.c_void_p],
     "scs_waveform": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p],
     "scs_ctx_stats": [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_int32],
     "scs_ctx_profile": [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)],
@@ -209,6 +213,42 @@ def scs_evaluate(ctx, theta, ups, prec=SCS_PREC_FP64, seg=None, stream=None):
     if kt == SCS_MEM_DEVICE and stream is None:
         stream = current_stream()
     _check(lib().scs_evaluate(ctx, P, pt, prec, pu, ps, kt, _stream(stream)))
+
+
+SCS_NSTATS = 5
+
+
+def scs_evaluate_stats(ctx, theta, stats, prec=SCS_PREC_FP64, stream=None):
+    """theta [P,7] -> stats [P,5] = (Upsilon_N, hat O_N, <h|h>, Re <d|h>, Im <d|h>)
+    for the unit-amplitude template; both numpy or both CUDA tensors."""
+    P = theta.shape[0]
+    pt, kt = ptr(theta)
+    ps, ks = ptr(stats)
+    if kt != ks:
+        raise ValueError("theta and stats must live in the same memory")
+    if kt == SCS_MEM_DEVICE and stream is None:
+        stream = current_stream()
+    _check(lib().scs_evaluate_stats(ctx, P, pt, prec, ps, kt, _stream(stream)))
+
+
+def scs_data_norm(ctx):
+    v = C.c_double()
+    _check(lib().scs_data_norm(ctx, C.byref(v)))
+    return v.value
+
+
+def scs_loglike(ctx, stats, amp, phase=None, logl_semi=None, logl_coh=None, stream=None):
+    """Log-likelihoods of A h e^{i phi} from scs_evaluate_stats rows into the
+    given output arrays (either may be None); all arrays in one memory."""
+    P = stats.shape[0]
+    ptrs = [ptr(x) for x in (stats, amp, phase, logl_semi, logl_coh)]
+    kinds = {k for (p, k), x in zip(ptrs, (stats, amp, phase, logl_semi, logl_coh)) if x is not None}
+    if len(kinds) != 1:
+        raise ValueError("stats, amp, phase and the outputs must live in the same memory")
+    kind = kinds.pop()
+    if kind == SCS_MEM_DEVICE and stream is None:
+        stream = current_stream()
+    _check(lib().scs_loglike(ctx, P, *(p for p, _ in ptrs), kind, _stream(stream)))
 
 
 def scs_last_bounds(ctx, P, N):

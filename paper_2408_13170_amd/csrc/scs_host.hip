@@ -181,6 +181,7 @@ struct scs_ctx {
     double* b64 = nullptr;
     float* b32 = nullptr;
     double zscale32 = 1.0, hscale32 = 1.0;  // undo the FP32 table scaling
+    double dd = 0.0;                        // <d|d> of the loaded data
     double* gtab = nullptr;  // basis Taylor tables, every sub-block level
     int64_t gtab_cap = 0;
     int64_t gtab_off[kMaxLevel] = {0};
@@ -376,7 +377,18 @@ extern "C" int scs_load_data(scs_ctx* c, int32_t n_chan, int64_t K, double f_min
         c->hscale32 = 1.0 / sq;
         launch_bins(c->g, dd_, dp, c->b64, c->b32, su, sq, nullptr);
     }
+    // <d|d>: workgroup partials, then their fixed-order total, in the tail of
+    // the bin table (overwritten by nothing until the next load)
+    double* nrm = nullptr;
+    if (hipMalloc((void**)&nrm, sizeof(double) * (kNormBlocks + 1)) != hipSuccess) {
+        hipFree(dd_);
+        hipFree(dp);
+        return fail(SCS_ENOMEM, "norm scratch allocation failed");
+    }
+    launch_data_norm(c->g, dd_, dp, nrm, nrm + kNormBlocks, nullptr);
     hipError_t e3 = hipDeviceSynchronize();
+    if (e3 == hipSuccess) e3 = hipMemcpy(&c->dd, nrm + kNormBlocks, sizeof(double), hipMemcpyDeviceToHost);
+    hipFree(nrm);
     hipFree(dd_);
     hipFree(dp);
     if (e3 != hipSuccess) return fail(SCS_EDEVICE, "bin precompute failed: %s", hipGetErrorString(e3));
@@ -556,7 +568,8 @@ struct EvalJob {
     FinalArgs fa{};
 };
 
-static int eval_front(EvalJob& j, const double* theta, double* ups, double* seg, const TuneChoice& t, hipStream_t s)
+static int eval_front(EvalJob& j, const double* theta, double* ups, double* seg, const TuneChoice& t, hipStream_t s,
+                      double* stats = nullptr)
 {
     scs_ctx* c = j.c;
     Workspace& w = *j.w;
@@ -655,6 +668,7 @@ static int eval_front(EvalJob& j, const double* theta, double* ups, double* seg,
     fa.zs = seg ? seg : w.zs;
     fa.ups = ups;
     fa.seg = seg;
+    fa.stats = stats;
     return SCS_OK;
 }
 
@@ -678,7 +692,7 @@ static int eval_main(scs_ctx* c, EvalJob& j, int prec, hipStream_t s);
 
 // Queue the whole evaluation on stream s (device pointers).
 static int run_eval(scs_ctx* c, Workspace& w, int64_t P, int N, const double* theta, int prec, double* ups,
-                    double* seg, hipStream_t s, const TuneChoice* force = nullptr)
+                    double* seg, hipStream_t s, const TuneChoice* force = nullptr, double* stats = nullptr)
 {
     EvalJob j;
     j.c = c;
@@ -686,7 +700,7 @@ static int run_eval(scs_ctx* c, Workspace& w, int64_t P, int N, const double* th
     j.P = P;
     j.N = N;
     const TuneChoice t = force ? *force : choose(c, P, N, prec);
-    int rc = eval_front(j, theta, ups, seg, t, s);
+    int rc = eval_front(j, theta, ups, seg, t, s, stats);
     if (rc || P == 0) return rc;
     if ((rc = eval_main(c, j, prec, s))) return rc;
     launch_finalize(j.fa, s);
@@ -747,6 +761,78 @@ extern "C" int scs_evaluate(scs_ctx* c, int64_t P, const double* theta, int32_t 
     if ((rc = run_eval(c, w, P, N, dth, prec, dup, dseg, s))) return rc;
     HIP_TRY(hipMemcpyAsync(ups, dup, sizeof(double) * P, hipMemcpyDeviceToHost, s));
     if (seg) HIP_TRY(hipMemcpyAsync(seg, dseg, sizeof(double) * P * N * 3, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return SCS_OK;
+}
+
+extern "C" int scs_evaluate_stats(scs_ctx* c, int64_t P, const double* theta, int32_t prec, double* stats,
+                                  int32_t mem_kind, void* stream)
+{
+    int rc = check_ready(c);
+    if (rc) return rc;
+    if (P < 0) return fail(SCS_EINVAL, "P < 0");
+    if (P > 0 && (!theta || !stats)) return fail(SCS_EINVAL, "theta or stats is NULL");
+    if (prec != SCS_PREC_FP64 && prec != SCS_PREC_MIXED) return fail(SCS_EINVAL, "bad precision");
+    if (mem_kind != SCS_MEM_HOST && mem_kind != SCS_MEM_DEVICE) return fail(SCS_EINVAL, "bad mem_kind");
+    DevScope ds(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    Workspace& w = c->ws[0];
+    const int N = c->N;
+    // staging: theta, Upsilon (also written by the epilogue) and the statistics
+    const int64_t need = P * (7 + 1 + kNStats);
+    if ((rc = grow(&w.stage, &w.capStage, std::max<int64_t>(need, 1)))) return rc;
+    double* dth = w.stage;
+    double* dup = dth + P * 7;
+    double* dst = dup + P;
+    if (mem_kind == SCS_MEM_DEVICE) return run_eval(c, w, P, N, theta, prec, dup, nullptr, s, nullptr, stats);
+    HIP_TRY(hipMemcpyAsync(dth, theta, sizeof(double) * 7 * P, hipMemcpyHostToDevice, s));
+    if ((rc = run_eval(c, w, P, N, dth, prec, dup, nullptr, s, nullptr, dst))) return rc;
+    HIP_TRY(hipMemcpyAsync(stats, dst, sizeof(double) * kNStats * P, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return SCS_OK;
+}
+
+extern "C" int scs_data_norm(const scs_ctx* c, double* dd)
+{
+    if (!c || !dd) return fail(SCS_EINVAL, "NULL argument");
+    if (!c->has_data) return fail(SCS_ESTATE, "no data loaded");
+    *dd = c->dd;
+    return SCS_OK;
+}
+
+extern "C" int scs_loglike(scs_ctx* c, int64_t P, const double* stats, const double* amp, const double* phase,
+                           double* logl_semi, double* logl_coh, int32_t mem_kind, void* stream)
+{
+    if (!c) return fail(SCS_EINVAL, "ctx is NULL");
+    if (!c->has_data) return fail(SCS_ESTATE, "no data loaded");
+    if (P < 0) return fail(SCS_EINVAL, "P < 0");
+    if (P > 0 && (!stats || !amp)) return fail(SCS_EINVAL, "stats or amp is NULL");
+    if (mem_kind != SCS_MEM_HOST && mem_kind != SCS_MEM_DEVICE) return fail(SCS_EINVAL, "bad mem_kind");
+    if (P == 0 || (!logl_semi && !logl_coh)) return SCS_OK;
+    DevScope ds(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    if (mem_kind == SCS_MEM_DEVICE) {
+        launch_loglike(P, c->dd, stats, amp, phase, logl_semi, logl_coh, s);
+        hipError_t e = hipGetLastError();
+        return e == hipSuccess ? SCS_OK : fail(SCS_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    }
+    Workspace& w = c->ws[-2];
+    const int64_t need = P * (kNStats + 4);
+    int rc = grow(&w.stage, &w.capStage, need);
+    if (rc) return rc;
+    double* dstat = w.stage;
+    double* damp = dstat + P * kNStats;
+    double* dph = damp + P;
+    double* dsemi = dph + P;
+    double* dcoh = dsemi + P;
+    HIP_TRY(hipMemcpyAsync(dstat, stats, sizeof(double) * kNStats * P, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(damp, amp, sizeof(double) * P, hipMemcpyHostToDevice, s));
+    if (phase) HIP_TRY(hipMemcpyAsync(dph, phase, sizeof(double) * P, hipMemcpyHostToDevice, s));
+    launch_loglike(P, c->dd, dstat, damp, phase ? dph : nullptr, logl_semi ? dsemi : nullptr,
+                   logl_coh ? dcoh : nullptr, s);
+    HIP_TRY(hipGetLastError());
+    if (logl_semi) HIP_TRY(hipMemcpyAsync(logl_semi, dsemi, sizeof(double) * P, hipMemcpyDeviceToHost, s));
+    if (logl_coh) HIP_TRY(hipMemcpyAsync(logl_coh, dcoh, sizeof(double) * P, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     return SCS_OK;
 }

@@ -116,6 +116,7 @@ struct FinalArgs {
     double* zs;   // as in MainArgs
     double* ups;  // [P_end - p0]
     double* seg;  // non-null: zs is the caller's segment output, completed here
+    double* stats;  // non-null: [P_end - p0][kNStats] likelihood statistics
 };
 
 struct PsoBox {
@@ -129,6 +130,12 @@ struct PsoParams {
 
 hipError_t upload_cheb(const double* x, const double* m);
 hipError_t upload_trig(const double* cs);
+constexpr int kNStats = 5;  // Upsilon_N, hat O_N, <h|h>, Re <d|h>, Im <d|h>
+constexpr int kNormBlocks = 256;
+void launch_data_norm(const GridArgs& g, const double* d_ri, const double* psd, double* part, double* out,
+                      hipStream_t s);
+void launch_loglike(int64_t P, double dd, const double* stats, const double* amp, const double* phase, double* semi,
+                    double* coh, hipStream_t s);
 void launch_bins(const GridArgs& g, const double* d_ri, const double* psd, double* b64, float* b32, double su,
                  double sq, hipStream_t s);
 void launch_prologue(const PrologueArgs& a, hipStream_t s);

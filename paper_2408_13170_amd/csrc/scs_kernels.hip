@@ -10,7 +10,9 @@
 //                 data staged in LDS, one particle per lane, per-lane
 //                 segmented accumulation                            (Sec 2.2)
 //   k_finalize    term_n = 4 df |Z_n|^2 / H_n with the pieces of segments
-//                 that straddle chunks joined, Upsilon = sum_n      (Sec 2.2)
+//                 that straddle chunks joined, Upsilon = sum_n      (Sec 2.2);
+//                 optionally the likelihood sums hat O_N, <h|h>, <d|h>
+//   k_data_norm   <d|d>; k_loglike: log hat L_N and log L          (Sec 2.1-2.2)
 //   k_waveform    template on the grid for one theta (injections, parity)
 //   k_pso_*       particle-swarm move and best update               (Sec 3.1)
 #include "scs_internal.hpp"
@@ -1164,6 +1166,7 @@ __global__ __launch_bounds__(256) void k_finalize(FinalArgs a)
     if (lg == -1 || lg == -2) {
         const double nan = __longlong_as_double(0x7ff8000000000000LL);  // invalid / unresolved theta
         if (lane == 0) a.ups[p - a.p0] = nan;
+        if (a.stats && lane < kNStats) a.stats[(p - a.p0) * kNStats + lane] = nan;
         if (out_seg)
             for (int n = lane; n < N; n += 64) zs[3 * n] = zs[3 * n + 1] = zs[3 * n + 2] = nan;
         return;
@@ -1175,6 +1178,7 @@ __global__ __launch_bounds__(256) void k_finalize(FinalArgs a)
     const int64_t cstride = a.rec_stride * kRec;
     const double four_df = 4.0 * a.df;
     double sum = 0.0;
+    double ov = 0.0, hs = 0.0, zrs = 0.0, zis = 0.0;  // likelihood sums (stats only)
     for (int n = lane; n < N; n += 64) {
         const int64_t b = bo[n], e = bo[n + 1];
         double zr = 0.0, zi = 0.0, h = 0.0;
@@ -1202,12 +1206,93 @@ __global__ __launch_bounds__(256) void k_finalize(FinalArgs a)
                 }
             }
             if (h > 0.0) sum += four_df * (zr * zr + zi * zi) / h;
+            ov += sqrt(zr * zr + zi * zi);
+            hs += h;
+            zrs += zr;
+            zis += zi;
         } else if (out_seg) {
             zs[3 * n] = zs[3 * n + 1] = zs[3 * n + 2] = 0.0;
         }
     }
     sum = wave_sum_f64(sum);
     if (lane == 0) a.ups[p - a.p0] = sum;
+    if (a.stats) {
+        // hat O_N = sum_n 4 df |Z_n| (eq:semi-coherent_O), <h|h> = 4 df sum_n H_n,
+        // <d|h> = 4 df sum_n Z_n (eqn:inner_prod) for the unit-amplitude template
+        ov = wave_sum_f64(ov);
+        hs = wave_sum_f64(hs);
+        zrs = wave_sum_f64(zrs);
+        zis = wave_sum_f64(zis);
+        if (lane == 0) {
+            double* o = a.stats + (p - a.p0) * kNStats;
+            o[0] = sum;
+            o[1] = four_df * ov;
+            o[2] = four_df * hs;
+            o[3] = four_df * zrs;
+            o[4] = four_df * zis;
+        }
+    }
+}
+
+// ============================================================== likelihoods
+// <d|d> = 4 df sum over channels and bins of |d|^2 / S (eqn:inner_prod with
+// a = b = d): every workgroup sums a fixed strided share of the bins and a
+// fixed tree adds them, so the value does not depend on timing.
+__global__ __launch_bounds__(256) void k_data_norm(GridArgs g, const double* __restrict__ d_ri,
+                                                   const double* __restrict__ psd, double* __restrict__ part)
+{
+    __shared__ double s[256];
+    const int64_t n = (int64_t)g.nch * g.K;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const double dr = d_ri[2 * i], di = d_ri[2 * i + 1];
+        acc += (dr * dr + di * di) / psd[i];
+    }
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+__global__ __launch_bounds__(kNormBlocks) void k_data_norm_total(const double* __restrict__ part, double df,
+                                                                 double* __restrict__ out)
+{
+    __shared__ double s[kNormBlocks];
+    s[threadIdx.x] = part[threadIdx.x];
+    __syncthreads();
+    for (int o = kNormBlocks / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = 4.0 * df * s[0];
+}
+
+// Log-likelihoods of the templates A h e^{i phi}, without the normalisation
+// constant: the semi-coherent log hat L_N = -<d|d>/2 - A^2 <h|h>/2 + |A| hat O_N
+// and the coherent log L = -<d|d>/2 - A^2 <h|h>/2 + A Re(e^{-i phi} <d|h>)
+// (eqn:LogL_coherent), the latter maximised over phi when phase is null.
+__global__ void k_loglike(int64_t P, double dd, const double* __restrict__ stats, const double* __restrict__ amp,
+                          const double* __restrict__ phase, double* __restrict__ semi, double* __restrict__ coh)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P) return;
+    const double* st = stats + i * kNStats;
+    const double A = amp[i];
+    const double base = -0.5 * dd - 0.5 * A * A * st[2];
+    if (semi) semi[i] = base + fabs(A) * st[1];
+    if (coh) {
+        double x;
+        if (phase) {
+            double sp, cp;
+            sincos(phase[i], &sp, &cp);
+            x = A * (cp * st[3] + sp * st[4]);
+        } else {
+            x = fabs(A) * sqrt(st[3] * st[3] + st[4] * st[4]);
+        }
+        coh[i] = base + x;
+    }
 }
 
 // ============================================================== waveform
@@ -1418,6 +1503,16 @@ hipError_t upload_trig(const double* cs)
     return hipMemcpyToSymbol(HIP_SYMBOL(g_trig), cs, sizeof(double) * 2 * kTrig);
 }
 
+void launch_data_norm(const GridArgs& g, const double* d_ri, const double* psd, double* part, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_data_norm, dim3(kNormBlocks), dim3(256), 0, s, g, d_ri, psd, part);
+    hipLaunchKernelGGL(k_data_norm_total, dim3(1), dim3(kNormBlocks), 0, s, part, g.df, out);
+}
+void launch_loglike(int64_t P, double dd, const double* stats, const double* amp, const double* phase, double* semi,
+                    double* coh, hipStream_t s)
+{
+    if (P > 0) hipLaunchKernelGGL(k_loglike, dim3(nblk(P, 256)), dim3(256), 0, s, P, dd, stats, amp, phase, semi, coh);
+}
 void launch_bins(const GridArgs& g, const double* d_ri, const double* psd, double* b64, float* b32, double su,
                  double sq, hipStream_t s)
 {

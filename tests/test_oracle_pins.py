@@ -504,3 +504,96 @@ def test_chi2_law_two_channels_share_phase():
         vals.append(_ups(ds, base.injection, 4, mode=O.SEG_UNIFORM)["ups"][0])
     p = stats.kstest(np.array(vals), stats.ncx2(8, base.snr ** 2).cdf).pvalue
     assert p > 1e-3
+
+
+# ---------------------------------------------------------------- likelihoods (Sec 2.1 - 2.2)
+def _stats(ds, theta, N, mode=O.SEG_EQUAL_SNR, G=1, edges=None):
+    return O.likelihood_stats(ds.grid, ds.model, ds.d_ri, ds.psd, np.atleast_2d(theta), N, mode, G, edges)
+
+
+def test_likelihood_noise_free_injection_is_zero():
+    """d = A h(theta*): <d|d> = A^2 <h|h>, and at the true amplitude and phase
+    the coherent log L (eqn:LogL_coherent) and, for every N, the semi-coherent
+    log hat L_N are exactly zero (d - A h = 0; every segment's phase is already
+    right).  <h|h> against a direct sum over the template's bins."""
+    for ds in (D.white_small(K=2048, noise=False, snr=20.0), D.lisa_small(noise=False, snr=17.0)):
+        h = O.template(ds.grid, ds.model, ds.injection)
+        hh_bf = D.inner(ds.grid, ds.psd, h, h)
+        amp = ds.snr / math.sqrt(hh_bf)
+        dd = O.data_norm(ds.grid, ds.d_ri, ds.psd)
+        assert abs(dd / (amp ** 2 * hh_bf) - 1) < 1e-12
+        for N in (1, 5, 32):
+            st = _stats(ds, ds.injection, N, G=16)
+            assert abs(st["hh"][0] / hh_bf - 1) < 1e-12
+            semi, coh = O.loglike(dd, st, amp, phase=0.0)
+            assert abs(semi[0]) < 1e-10 * dd and abs(coh[0]) < 1e-10 * dd, (N, semi, coh)
+
+
+def test_likelihood_phase_convention():
+    """With d = A h e^{i phi0}, <d|h e^{i phi}> = A <h|h> cos(phi - phi0)
+    (eqn:inner_prod: the second argument is conjugated), so the coherent log L
+    is zero at phi = phi0 and below zero at -phi0."""
+    ds = D.lisa_small(noise=False, snr=17.0)
+    phi0 = 0.7
+    d = ds.d * np.exp(1j * phi0)
+    d_ri = np.stack([d.real, d.imag], -1)
+    st = O.likelihood_stats(ds.grid, ds.model, d_ri, ds.psd, np.atleast_2d(ds.injection), 8, O.SEG_EQUAL_SNR, 1)
+    assert abs(np.angle(st["dh"][0]) - phi0) < 1e-12
+    dd = O.data_norm(ds.grid, d_ri, ds.psd)
+    amp = ds.snr / math.sqrt(st["hh"][0])
+    _, coh = O.loglike(dd, st, amp, phase=phi0)
+    _, coh_neg = O.loglike(dd, st, amp, phase=-phi0)
+    assert abs(coh[0]) < 1e-10 * dd
+    assert coh_neg[0] < -0.1 * dd
+
+
+def test_likelihood_inner_products_against_direct_sums():
+    """On noisy data and off-peak particles, <h|h> and the complex <d|h> equal
+    4 df sum_k d conj(h) / S summed directly over the template's bins (which
+    vanish outside the support), for any segmentation; Upsilon_1 = |<d|h>|^2/<h|h>."""
+    ds = D.lisa_small(seed=12)
+    th = D.lisa_particles(3, seed=41)
+    th[0] = ds.injection
+    for p in range(th.shape[0]):
+        h = O.template(ds.grid, ds.model, th[p])
+        hh = D.inner(ds.grid, ds.psd, h, h)
+        dh = 4.0 * ds.grid.df * np.sum(ds.d * np.conj(h) / ds.psd)
+        for N in (1, 16):
+            st = _stats(ds, th[p], N)
+            assert abs(st["hh"][0] / hh - 1) < 1e-12
+            assert abs(st["dh"][0] - dh) < 1e-11 * abs(dh) + 1e-12 * math.sqrt(hh)
+        st1 = _stats(ds, th[p], 1)
+        assert abs(st1["ups"][0] / (abs(dh) ** 2 / hh) - 1) < 1e-11
+
+
+def test_semicoherent_overlap_inequalities():
+    """Cauchy-Schwarz: hat O_N^2 <= <h|h> Upsilon_N, with equality at N = 1;
+    per-segment phase maximisation: log hat L_N >= max_phi log L, equal at
+    N = 1; splitting segments (nested explicit edges) cannot lower hat O_N
+    (triangle inequality, eq:semi-coherent_O)."""
+    ds = D.lisa_small(seed=13)
+    th = D.lisa_particles(8, seed=42)
+    th[0] = ds.injection
+    dd = O.data_norm(ds.grid, ds.d_ri, ds.psd)
+    for N in (1, 4, 32):
+        st = _stats(ds, th, N, G=16)
+        ok = np.isfinite(st["ups"]) & (st["hh"] > 0)
+        lhs, rhs = st["overlap"][ok] ** 2, st["hh"][ok] * st["ups"][ok]
+        if N == 1:
+            assert np.allclose(lhs, rhs, rtol=1e-12, atol=0)
+        else:
+            assert np.all(lhs <= rhs * (1 + 1e-12))
+        amp = 0.7 * st["overlap"][ok] / st["hh"][ok]
+        semi, coh = O.loglike(dd, {k: v[ok] for k, v in st.items()}, amp)
+        if N == 1:
+            assert np.allclose(semi, coh, rtol=0, atol=1e-9 * dd)
+        else:
+            assert np.all(semi >= coh - 1e-9 * dd)
+    K = ds.grid.K
+    coarse = np.linspace(0, K, 5).astype(np.int64)
+    fine = np.linspace(0, K, 17).astype(np.int64)
+    assert set(coarse) <= set(fine)
+    oc = _stats(ds, th, 4, O.SEG_EXPLICIT, edges=coarse)["overlap"]
+    of = _stats(ds, th, 16, O.SEG_EXPLICIT, edges=fine)["overlap"]
+    ok = np.isfinite(oc)
+    assert np.all(of[ok] >= oc[ok] * (1 - 1e-13))
