@@ -110,6 +110,8 @@ def lib():
         L.orc_pso_move.restype = None
         L.orc_pso_best.argtypes = [C.c_int64, C.c_int32, dp, dp, dp, dp, i32p, dp, dp, dp, dp]
         L.orc_pso_best.restype = None
+        L.orc_noise.argtypes = [C.c_int64, C.c_int32, dp, C.c_double, C.c_uint64, C.c_uint32, dp]
+        L.orc_noise.restype = None
         _lib = L
     return _lib
 
@@ -201,6 +203,16 @@ def loglike(dd, stats, amp, phase=None):
     else:
         coh = base + amp * np.real(np.exp(-1j * np.asarray(phase, dtype=np.float64)) * stats["dh"])
     return semi, coh
+
+
+def noise(grid: Grid, psd, seed, r):
+    """Noise realisation r [n_chan, K] complex: sqrt(S / (4 df)) (g1 + i g2) with
+    Box-Muller normals from Philox4x32-10, counter (k, channel, r, stream), key seed
+    (the generator the GPU's realisation kernel implements on its own)."""
+    psd = _f64(psd)
+    out = np.empty((grid.n_chan, grid.K, 2))
+    lib().orc_noise(grid.K, grid.n_chan, _dp(psd), grid.df, seed, r, _dp(out))
+    return out[..., 0] + 1j * out[..., 1]
 
 
 def template(grid: Grid, model: Model, theta):

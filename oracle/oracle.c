@@ -739,3 +739,35 @@ void orc_pso_best(int64_t P, int32_t D, const double* theta, const double* vals,
         for (int d = 0; d < D; ++d) gbest[d] = pbest[best * D + d];
     }
 }
+
+/* ---------------------------------------------------------------- noise realisations (Sec 5.1)
+ * Realisation r of Gaussian noise of one-sided PSD S on the grid, in the
+ * convention under which <n|h> ~ N(0, <h|h>) (eqn:inner_prod):
+ *     n_{r,alpha,k} = sqrt(S_alpha(f_k) / (4 df)) (g1 + i g2),
+ * g1, g2 independent standard normals from the Box-Muller transform (Box &
+ * Muller 1958) of two uniforms in (0,1), each made of 52 bits of one
+ * Philox4x32-10 block (Salmon et al. 2011) with counter (k, alpha, r,
+ * ORC_NOISE_STREAM) and key (seed low word, seed high word):
+ *     u1 = ((o0 >> 6) 2^26 + (o1 >> 6) + 1/2) 2^-52, u2 likewise from (o2, o3),
+ *     g1 = sqrt(-2 ln u1) cos(2 pi u2),  g2 = sqrt(-2 ln u1) sin(2 pi u2).
+ * out [n_chan][K][2]. */
+#define ORC_NOISE_STREAM 0x6e6f6973u
+void orc_noise(int64_t K, int32_t n_chan, const double* psd, double df, uint64_t seed, uint32_t r, double* out)
+{
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (int32_t a = 0; a < n_chan; ++a)
+        for (int64_t k = 0; k < K; ++k) {
+            const uint32_t ctr[4] = {(uint32_t)k, (uint32_t)a, r, ORC_NOISE_STREAM};
+            uint32_t o[4];
+            orc_philox4x32_10(ctr, key, o);
+            const uint64_t x1 = ((uint64_t)(o[0] >> 6) << 26) | (uint64_t)(o[1] >> 6);
+            const uint64_t x2 = ((uint64_t)(o[2] >> 6) << 26) | (uint64_t)(o[3] >> 6);
+            const double u1 = ((double)x1 + 0.5) * 0x1p-52;
+            const double u2 = ((double)x2 + 0.5) * 0x1p-52;
+            const double rad = sqrt(-2.0 * log(u1));
+            const double ang = 2.0 * M_PI * u2;
+            const double sig = sqrt(psd[a * K + k] / (4.0 * df));
+            out[(a * K + k) * 2] = sig * (rad * cos(ang));
+            out[(a * K + k) * 2 + 1] = sig * (rad * sin(ang));
+        }
+}

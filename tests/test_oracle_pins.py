@@ -597,3 +597,38 @@ def test_semicoherent_overlap_inequalities():
     of = _stats(ds, th, 16, O.SEG_EXPLICIT, edges=fine)["overlap"]
     ok = np.isfinite(oc)
     assert np.all(of[ok] >= oc[ok] * (1 - 1e-13))
+
+
+# ---------------------------------------------------------------- noise realisations (Sec 5.1)
+def test_noise_counter_layout_and_box_muller():
+    """One element by hand: the Philox4x32-10 block of counter (k, channel, r,
+    'nois') and key (seed low, seed high) gives two 52-bit uniforms, and
+    Box-Muller turns them into the element's real and imaginary parts."""
+    ds = D.lisa_small(noise=False)
+    seed, r = 0x1234_5678_9ABC, 7
+    n = O.noise(ds.grid, ds.psd, seed, r)
+    for a, k in ((0, 0), (1, 12345), (0, ds.grid.K - 1)):
+        o = O.philox4x32_10([k, a, r, 0x6E6F6973], [seed & 0xFFFFFFFF, seed >> 32])
+        u1 = (((o[0] >> 6) << 26 | (o[1] >> 6)) + 0.5) * 2.0 ** -52
+        u2 = (((o[2] >> 6) << 26 | (o[3] >> 6)) + 0.5) * 2.0 ** -52
+        rad = math.sqrt(-2.0 * math.log(u1))
+        sig = math.sqrt(ds.psd[a, k] / (4.0 * ds.grid.df))
+        assert abs(n[a, k] - sig * rad * complex(math.cos(2 * math.pi * u2), math.sin(2 * math.pi * u2))) <= 1e-15 * sig * rad
+
+
+def test_noise_is_gaussian_with_the_inner_product_variance():
+    """Whitened samples are standard normal (KS), and over realisations
+    <n|h> has mean 0 and variance <h|h> (eqn:inner_prod convention)."""
+    from scipy import stats
+
+    ds = D.lisa_small(noise=False, snr=17.0)
+    z = O.noise(ds.grid, ds.psd, 99, 0) / np.sqrt(ds.psd / (4.0 * ds.grid.df))
+    assert stats.kstest(z.real.ravel(), "norm").pvalue > 1e-3
+    assert stats.kstest(z.imag.ravel(), "norm").pvalue > 1e-3
+    assert abs(np.corrcoef(z.real.ravel(), z.imag.ravel())[0, 1]) < 0.03
+    h = ds.d
+    hh = D.inner(ds.grid, ds.psd, h, h)
+    x = np.array([D.inner(ds.grid, ds.psd, O.noise(ds.grid, ds.psd, 99, r), h) for r in range(400)])
+    assert abs(x.mean()) < 4 * math.sqrt(hh / len(x))
+    # sample variance of 400 normals: relative sd sqrt(2/399) ~ 0.071
+    assert abs(x.var(ddof=1) / hh - 1) < 4 * math.sqrt(2 / 399)
