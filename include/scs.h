@@ -162,6 +162,32 @@ int scs_data_norm(const scs_ctx* ctx, double* dd);
 int scs_loglike(scs_ctx* ctx, int64_t P, const double* stats, const double* amp, const double* phase,
                 double* logl_semi, double* logl_coh, int32_t mem_kind, void* stream);
 
+/* ---- one theta against many data streams (Sec 5.1) -------------------- */
+
+/* Fill streams (DEVICE [n_chan][K][R][2], realisations innermost) with
+ * d_r = scale * d + n_{r0 + r}, r = 0..R-1: d the loaded data, n Gaussian
+ * noise of the loaded PSD in the convention <n|h> ~ N(0, <h|h>)
+ * (eqn:inner_prod), n = sqrt(S / (4 df)) (g1 + i g2).  g1, g2 are the
+ * Box-Muller normals of two 52-bit uniforms taken from one Philox4x32-10
+ * block, counter (k, channel, r0 + r, 0x6e6f6973), key (seed low word, seed
+ * high word), so that any realisation can be regenerated on its own.
+ * Asynchronous on stream.  Errors: EINVAL (r0 + R > 2^32, NULL streams,
+ * non-finite scale), ESTATE (no data), EDEVICE. */
+int scs_make_realisations(scs_ctx* ctx, int64_t R, uint64_t seed, int64_t r0, double scale, double* streams,
+                          void* stream);
+
+/* For one theta (HOST [7]) and R data streams (DEVICE [n_chan][K][R][2], as
+ * made by scs_make_realisations or by the caller), stats (DEVICE
+ * [R][SCS_NSTATS]) = the rows of scs_evaluate_stats for each stream in place
+ * of the loaded data.  The segment edges are theta's under the context's
+ * segmentation (so, for EQUAL_SNR, the same for every stream).  The template
+ * weights conj(h)/S are formed once; the reduction then streams every
+ * stream's bins from HBM once.  NaN rows for an invalid theta.  The call
+ * synchronises the stream (the edges are read back to cut the work).
+ * Errors: EINVAL, ESTATE, ENOMEM, EDEVICE. */
+int scs_evaluate_streams(scs_ctx* ctx, const double* theta, int64_t R, const double* streams, double* stats,
+                         void* stream);
+
 /* Per-particle support [k_lo, k_hi) and segment edges b_0..b_N (int32) from
  * the last scs_evaluate on this context, copied to host arrays
  * support [P][2] and bounds [P][N+1] (either may be NULL).  Synchronises the
@@ -177,9 +203,11 @@ int scs_waveform(scs_ctx* ctx, const double* theta, double* h_ri, int32_t mem_ki
  * scheme could not resolve.  Synchronises the device. */
 int scs_ctx_stats(scs_ctx* ctx, int64_t* evals_support, int64_t* evals_band, int64_t* unresolved, int32_t reset);
 
-/* Time the dominant (generate-and-reduce) kernel with HIP events on the
- * stream it is launched on.  enable = 1 starts recording; the query returns
- * the number of launches and the summed milliseconds since enabling. */
+/* Time the dominant kernel with HIP events on the stream it is launched on:
+ * the generate-and-reduce, and in scs_evaluate_streams the streamed
+ * reduction (its one-particle set-up evaluation is not recorded).
+ * enable = 1 starts recording; the query returns the number of launches and
+ * the summed milliseconds since enabling. */
 int scs_ctx_profile(scs_ctx* ctx, int32_t enable, int64_t* launches, double* total_ms);
 
 /* HBM bytes an evaluation of P particles with N segments needs on this

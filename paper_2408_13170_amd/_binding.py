@@ -70,6 +70,8 @@ _SIGS = {
     "scs_last_bounds": [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p],
     "scs_evaluate_stats": [C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p],
     "scs_data_norm": [C.c_void_p, C.POINTER(C.c_double)],
+    "scs_make_realisations": [C.c_void_p, C.c_int64, C.c_uint64, C.c_int64, C.c_double, C.c_void_p, C.c_void_p],
+    "scs_evaluate_streams": [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p],
     "scs_loglike": [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                     C.c_void_p],
     "scs_waveform": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p],
@@ -249,6 +251,26 @@ def scs_loglike(ctx, stats, amp, phase=None, logl_semi=None, logl_coh=None, stre
     if kind == SCS_MEM_DEVICE and stream is None:
         stream = current_stream()
     _check(lib().scs_loglike(ctx, P, *(p for p, _ in ptrs), kind, _stream(stream)))
+
+
+def scs_make_realisations(ctx, streams, seed, r0=0, scale=1.0, stream=None):
+    """Fill the CUDA tensor streams [n_chan, K, R, 2] with scale * d + noise realisations r0 .. r0 + R - 1."""
+    if not _is_torch(streams) or not streams.is_cuda:
+        raise TypeError("streams must be a CUDA tensor [n_chan, K, R, 2]")
+    R = streams.shape[2]
+    p, _ = ptr(streams)
+    _check(lib().scs_make_realisations(ctx, R, seed, r0, scale, p, _stream(stream or current_stream())))
+
+
+def scs_evaluate_streams(ctx, theta, streams, stats, stream=None):
+    """theta numpy [7]; streams CUDA [n_chan, K, R, 2]; stats CUDA [R, 5] out."""
+    th = np.ascontiguousarray(theta, dtype=np.float64).reshape(7)
+    if not (_is_torch(streams) and streams.is_cuda and _is_torch(stats) and stats.is_cuda):
+        raise TypeError("streams and stats must be CUDA tensors")
+    R = streams.shape[2]
+    ps, _ = ptr(streams)
+    pt, _ = ptr(stats)
+    _check(lib().scs_evaluate_streams(ctx, C.c_void_p(th.ctypes.data), R, ps, pt, _stream(stream or current_stream())))
 
 
 def scs_last_bounds(ctx, P, N):

@@ -16,6 +16,7 @@
 #include <thread>
 #include <sstream>
 #include <string>
+#include <limits>
 #include <vector>
 
 #include "../../include/scs.h"
@@ -180,6 +181,8 @@ struct scs_ctx {
     int64_t edges_cap = 0;
     double* b64 = nullptr;
     float* b32 = nullptr;
+    double* d_dev = nullptr;    // the loaded data [nch][K][2] and PSD [nch][K], kept for the
+    double* psd_dev = nullptr;  // fixed-theta streams
     double zscale32 = 1.0, hscale32 = 1.0;  // undo the FP32 table scaling
     double dd = 0.0;                        // <d|d> of the loaded data
     double* gtab = nullptr;  // basis Taylor tables, every sub-block level
@@ -297,6 +300,8 @@ extern "C" int scs_ctx_destroy(scs_ctx* c)
     }
     hipFree(c->b64);
     hipFree(c->b32);
+    hipFree(c->d_dev);
+    hipFree(c->psd_dev);
     hipFree(c->gtab);
     hipFree(c->d_edges);
     hipFree(c->counters);
@@ -389,8 +394,10 @@ extern "C" int scs_load_data(scs_ctx* c, int32_t n_chan, int64_t K, double f_min
     hipError_t e3 = hipDeviceSynchronize();
     if (e3 == hipSuccess) e3 = hipMemcpy(&c->dd, nrm + kNormBlocks, sizeof(double), hipMemcpyDeviceToHost);
     hipFree(nrm);
-    hipFree(dd_);
-    hipFree(dp);
+    hipFree(c->d_dev);
+    hipFree(c->psd_dev);
+    c->d_dev = dd_;
+    c->psd_dev = dp;
     if (e3 != hipSuccess) return fail(SCS_EDEVICE, "bin precompute failed: %s", hipGetErrorString(e3));
     c->has_data = true;
     c->gtab_ok = false;
@@ -910,6 +917,120 @@ extern "C" int scs_waveform(scs_ctx* c, const double* theta, double* h_ri, int32
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(SCS_EDEVICE, "waveform launch failed: %s", hipGetErrorString(e));
+    return SCS_OK;
+}
+
+// ---------------------------------------------------------------- fixed theta, many data streams (Sec 5.1)
+extern "C" int scs_make_realisations(scs_ctx* c, int64_t R, uint64_t seed, int64_t r0, double scale, double* streams,
+                                     void* stream)
+{
+    if (!c) return fail(SCS_EINVAL, "ctx is NULL");
+    if (!c->has_data) return fail(SCS_ESTATE, "no data loaded");
+    if (R < 0 || r0 < 0 || r0 + R > ((int64_t)1 << 32)) return fail(SCS_EINVAL, "realisations [r0, r0 + R) must lie in [0, 2^32)");
+    if (R > 0 && !streams) return fail(SCS_EINVAL, "streams is NULL");
+    if (!std::isfinite(scale)) return fail(SCS_EINVAL, "scale is not finite");
+    DevScope ds(c->device);
+    StreamGenArgs a{};
+    a.K = c->g.K;
+    a.R = R;
+    a.r0 = r0;
+    a.nch = c->g.nch;
+    a.df = c->g.df;
+    a.scale = scale;
+    a.seed = seed;
+    a.d = c->d_dev;
+    a.psd = c->psd_dev;
+    a.streams = streams;
+    launch_make_streams(a, c->n_cu, (hipStream_t)stream);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SCS_OK : fail(SCS_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+}
+
+extern "C" int scs_evaluate_streams(scs_ctx* c, const double* theta, int64_t R, const double* streams, double* stats,
+                                    void* stream)
+{
+    int rc = check_ready(c);
+    if (rc) return rc;
+    if (!theta) return fail(SCS_EINVAL, "theta is NULL");
+    if (R < 0) return fail(SCS_EINVAL, "R < 0");
+    if (R > 0 && (!streams || !stats)) return fail(SCS_EINVAL, "streams or stats is NULL");
+    if (R == 0) return SCS_OK;
+    DevScope ds(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    Workspace& w = c->ws[-3];
+    const int N = c->N;
+    const int nch = c->g.nch;
+    const int64_t K = c->g.K;
+    // edges of theta with the context's segmentation (one-particle evaluation)
+    if ((rc = grow(&w.stage, &w.capStage, 8))) return rc;
+    HIP_TRY(hipMemcpyAsync(w.stage, theta, sizeof(double) * 7, hipMemcpyHostToDevice, s));
+    const bool prof = c->prof;
+    c->prof = false;  // with profiling on, only the streamed reduction below is timed
+    rc = run_eval(c, w, 1, N, w.stage, SCS_PREC_FP64, w.stage + 7, nullptr, s);
+    c->prof = prof;
+    if (rc) return rc;
+    std::vector<int32_t> bo(N + 1);
+    int8_t lg = -1;
+    HIP_TRY(hipMemcpyAsync(bo.data(), w.bounds, sizeof(int32_t) * (N + 1), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&lg, w.lg, 1, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (lg < 0) {  // invalid or unresolved theta
+        launch_fill(stats, R * kNStats, std::numeric_limits<double>::quiet_NaN(), s);
+        HIP_TRY(hipGetLastError());
+        return SCS_OK;
+    }
+    // pieces: every segment cut into runs of at most kPieceBins bins, in order
+    std::vector<int32_t> pcs;
+    for (int n = 0; n < N; ++n)
+        for (int32_t k = bo[n]; k < bo[n + 1]; k += kPieceBins) {
+            pcs.push_back(k);
+            pcs.push_back(std::min<int32_t>(k + kPieceBins, bo[n + 1]));
+            pcs.push_back(n);
+        }
+    const int64_t np = (int64_t)pcs.size() / 3;
+    // stage: template [nch][K][2], weights [nch][K][2], hq [K], hpart [np],
+    // zpart [np][R][2], pieces [np][3] int32
+    const int64_t off_h = 0, off_w = off_h + 2 * nch * K, off_q = off_w + 2 * nch * K, off_hp = off_q + K;
+    const int64_t off_z = off_hp + np, off_p = off_z + 2 * np * R;
+    if ((rc = grow(&w.stage, &w.capStage, off_p + (3 * np + 1) / 2 + 1))) return rc;
+    double* st = w.stage;
+    MainArgs ma{};
+    ma.g = c->g;
+    ma.m = c->m;
+    ma.stride = w.capP;
+    ma.coef = w.coef;
+    ma.klo = w.klo;
+    ma.khi = w.khi;
+    ma.lg = w.lg;
+    ma.gtab = c->gtab;
+    for (int l = 0; l < kMaxLevel; ++l) ma.gtab_off[l] = c->gtab_off[l];
+    launch_waveform(ma, st + off_h, s);
+    launch_stream_weights(nch, K, st + off_h, c->psd_dev, st + off_w, st + off_q, s);
+    int32_t* dpcs = reinterpret_cast<int32_t*>(st + off_p);
+    if (np > 0) {
+        HIP_TRY(hipMemcpyAsync(dpcs, pcs.data(), sizeof(int32_t) * pcs.size(), hipMemcpyHostToDevice, s));
+    }
+    StreamArgs a{};
+    a.K = K;
+    a.R = R;
+    a.nch = nch;
+    a.df = c->g.df;
+    a.streams = streams;
+    a.wts = st + off_w;
+    a.hq = st + off_q;
+    a.pieces = dpcs;
+    a.n_pieces = np;
+    a.zpart = st + off_z;
+    a.hpart = st + off_hp;
+    a.stats = stats;
+    hipEvent_t e0;
+    prof_begin(c, s, &e0);
+    launch_streams(a, s);
+    prof_end(c, s, e0);
+    launch_streams_final(a, s);
+    HIP_TRY(hipGetLastError());
+    // the piece table is read from pageable host memory: finish before it goes
+    HIP_TRY(hipStreamSynchronize(s));
     return SCS_OK;
 }
 

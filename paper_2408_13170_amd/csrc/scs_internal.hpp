@@ -131,6 +131,38 @@ struct PsoParams {
 hipError_t upload_cheb(const double* x, const double* m);
 hipError_t upload_trig(const double* cs);
 constexpr int kNStats = 5;  // Upsilon_N, hat O_N, <h|h>, Re <d|h>, Im <d|h>
+
+// Fixed-theta evaluation over many data streams (noise realisations).  The
+// streams are stored [n_chan][K][R][2]: realisations innermost, so that the
+// lanes of a wave (consecutive r) read consecutive memory.
+constexpr int kPieceBins = 1024;  // bins per work piece of the streamed reduction
+struct StreamGenArgs {
+    int64_t K, R, r0;
+    int nch;
+    double df, scale;
+    uint64_t seed;
+    const double* d;    // loaded data [nch][K][2]
+    const double* psd;  // [nch][K]
+    double* streams;    // [nch][K][R][2]
+};
+struct StreamArgs {
+    int64_t K, R;
+    int nch;
+    double df;
+    const double* streams;  // [nch][K][R][2]
+    const double* wts;      // [nch][K][2]: conj(h) / S
+    const double* hq;       // [K]: sum over channels of |h|^2 / S
+    const int32_t* pieces;  // [n_pieces][3]: first bin, end bin, segment (in segment order)
+    int64_t n_pieces;
+    double* zpart;          // [n_pieces][R][2]
+    double* hpart;          // [n_pieces]
+    double* stats;          // [R][kNStats]
+};
+void launch_make_streams(const StreamGenArgs& a, int n_cu, hipStream_t s);
+void launch_stream_weights(int nch, int64_t K, const double* h_ri, const double* psd, double* wts, double* hq,
+                           hipStream_t s);
+void launch_streams(const StreamArgs& a, hipStream_t s);        // the streamed reduction
+void launch_streams_final(const StreamArgs& a, hipStream_t s);  // per-stream statistics
 constexpr int kNormBlocks = 256;
 void launch_data_norm(const GridArgs& g, const double* d_ri, const double* psd, double* part, double* out,
                       hipStream_t s);

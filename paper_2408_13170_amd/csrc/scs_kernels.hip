@@ -1368,6 +1368,140 @@ __device__ __forceinline__ double uniform01(uint64_t seed, uint32_t swarm, uint3
     return ((double)x + 0.5) * 0x1p-52;
 }
 
+// ============================================================== noise realisations (Sec 5.1)
+// streams[alpha][k][r] = scale d_alpha,k + n_{r0 + r, alpha, k} with
+// n = sqrt(S / (4 df)) (g1 + i g2), the convention under which
+// <n|h> ~ N(0, <h|h>) (eqn:inner_prod).  g1, g2: Box-Muller (Box & Muller
+// 1958) of two 52-bit uniforms from one Philox4x32-10 block with counter
+// (k, alpha, r, kNoiseStream) and key (seed low word, seed high word).
+constexpr uint32_t kNoiseStream = 0x6e6f6973u;
+__global__ void k_make_streams(StreamGenArgs a)
+{
+    const int64_t n = (int64_t)a.nch * a.K * a.R;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i % a.R;
+        const int64_t ak = i / a.R;  // alpha * K + k
+        const int64_t k = ak % a.K;
+        const int alpha = (int)(ak / a.K);
+        uint32_t c[4] = {(uint32_t)k, (uint32_t)alpha, (uint32_t)(a.r0 + r), kNoiseStream};
+        philox10(c, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+        const uint64_t x1 = ((uint64_t)(c[0] >> 6) << 26) | (uint64_t)(c[1] >> 6);
+        const uint64_t x2 = ((uint64_t)(c[2] >> 6) << 26) | (uint64_t)(c[3] >> 6);
+        const double u1 = ((double)x1 + 0.5) * 0x1p-52;
+        const double u2 = ((double)x2 + 0.5) * 0x1p-52;
+        const double rad = sqrt(-2.0 * log(u1));
+        double sn, cs;
+        sincos(kTwoPi * u2, &sn, &cs);
+        const double sig = sqrt(a.psd[ak] / (4.0 * a.df));
+        double* o = a.streams + 2 * i;
+        o[0] = a.scale * a.d[2 * ak] + sig * (rad * cs);
+        o[1] = a.scale * a.d[2 * ak + 1] + sig * (rad * sn);
+    }
+}
+
+// Template weights of the streamed reduction: w = conj(h) / S per channel and
+// bin, and sum over channels of |h|^2 / S per bin.
+__global__ void k_stream_weights(int nch, int64_t K, const double* __restrict__ h_ri, const double* __restrict__ psd,
+                                 double* __restrict__ wts, double* __restrict__ hq)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    double q = 0.0;
+    for (int a = 0; a < nch; ++a) {
+        const int64_t i = (int64_t)a * K + k;
+        const double hr = h_ri[2 * i], hi = h_ri[2 * i + 1];
+        const double inv = 1.0 / psd[i];
+        wts[2 * i] = hr * inv;
+        wts[2 * i + 1] = -hi * inv;
+        q += (hr * hr + hi * hi) * inv;
+    }
+    hq[k] = q;
+}
+
+// Streamed reduction, HBM-bound: workgroup (piece, group of 256 streams), one
+// stream per lane.  The piece's weights sit in LDS and are read as
+// broadcasts; every lane reads its stream's 16 bytes per bin and channel,
+// consecutive lanes consecutive addresses.  Z of the piece goes to zpart; the
+// piece's share of H (the same for every stream) to hpart.
+__global__ __launch_bounds__(256) void k_streams(StreamArgs a)
+{
+    extern __shared__ double s_w[];  // [len][nch][2] weights, then [len] hq
+    const int64_t pc = blockIdx.x;
+    const int k0 = a.pieces[3 * pc], k1 = a.pieces[3 * pc + 1];
+    const int len = k1 - k0;
+    const int nch = a.nch;
+    double* s_h = s_w + (int64_t)kPieceBins * nch * 2;
+    for (int i = threadIdx.x; i < len * nch; i += blockDim.x) {
+        const int kk = i / nch, al = i % nch;
+        const int64_t src = ((int64_t)al * a.K + k0 + kk) * 2;
+        s_w[2 * i] = a.wts[src];
+        s_w[2 * i + 1] = a.wts[src + 1];
+    }
+    for (int i = threadIdx.x; i < len; i += blockDim.x) s_h[i] = a.hq[k0 + i];
+    __syncthreads();
+    const int64_t r = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
+    if (r < a.R) {
+        double zr = 0.0, zi = 0.0;
+        const int64_t stride_k = a.R * 2;                 // doubles between consecutive bins
+        const int64_t stride_a = a.K * a.R * 2;           // between channels
+        const double* base = a.streams + (int64_t)k0 * stride_k + 2 * r;
+        for (int al = 0; al < nch; ++al) {
+            const double* sp = base + al * stride_a;
+#pragma unroll 8
+            for (int kk = 0; kk < len; ++kk) {
+                const double2 dv = *reinterpret_cast<const double2*>(sp + (int64_t)kk * stride_k);
+                const double wr = s_w[2 * (kk * nch + al)], wi = s_w[2 * (kk * nch + al) + 1];
+                zr = __builtin_fma(dv.x, wr, __builtin_fma(-dv.y, wi, zr));
+                zi = __builtin_fma(dv.x, wi, __builtin_fma(dv.y, wr, zi));
+            }
+        }
+        a.zpart[(pc * a.R + r) * 2] = zr;
+        a.zpart[(pc * a.R + r) * 2 + 1] = zi;
+    }
+    if (blockIdx.y == 0 && threadIdx.x == 0) {
+        double h = 0.0;
+        for (int i = 0; i < len; ++i) h += s_h[i];
+        a.hpart[pc] = h;
+    }
+}
+
+// Per stream: join the pieces of every segment and form the statistics of
+// scs_evaluate_stats (Upsilon_N, hat O_N, <h|h>, Re and Im <d_r|h>).
+__global__ void k_streams_final(StreamArgs a)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= a.R) return;
+    const double four_df = 4.0 * a.df;
+    double ups = 0.0, ov = 0.0, hs = 0.0, zrs = 0.0, zis = 0.0;
+    double zr = 0.0, zi = 0.0, h = 0.0;
+    int cur = -1;
+    auto close = [&]() {
+        if (h > 0.0) ups += four_df * (zr * zr + zi * zi) / h;
+        ov += sqrt(zr * zr + zi * zi);
+        hs += h;
+        zrs += zr;
+        zis += zi;
+    };
+    for (int64_t i = 0; i < a.n_pieces; ++i) {
+        const int n = a.pieces[3 * i + 2];
+        if (n != cur) {
+            if (cur >= 0) close();
+            zr = zi = h = 0.0;
+            cur = n;
+        }
+        zr += a.zpart[(i * a.R + r) * 2];
+        zi += a.zpart[(i * a.R + r) * 2 + 1];
+        h += a.hpart[i];
+    }
+    if (cur >= 0) close();
+    double* o = a.stats + r * kNStats;
+    o[0] = ups;
+    o[1] = four_df * ov;
+    o[2] = four_df * hs;
+    o[3] = four_df * zrs;
+    o[4] = four_df * zis;
+}
+
 // Every arithmetic step is a single IEEE operation (no contraction) so the
 // result is reproducible bit for bit on any IEEE machine.
 #pragma clang fp contract(off)
@@ -1512,6 +1646,27 @@ void launch_loglike(int64_t P, double dd, const double* stats, const double* amp
                     double* coh, hipStream_t s)
 {
     if (P > 0) hipLaunchKernelGGL(k_loglike, dim3(nblk(P, 256)), dim3(256), 0, s, P, dd, stats, amp, phase, semi, coh);
+}
+void launch_make_streams(const StreamGenArgs& a, int n_cu, hipStream_t s)
+{
+    const int64_t n = (int64_t)a.nch * a.K * a.R;
+    const int64_t blocks = std::min<int64_t>(nblk(n, 256), (int64_t)n_cu * 16);
+    if (n > 0) hipLaunchKernelGGL(k_make_streams, dim3((unsigned)blocks), dim3(256), 0, s, a);
+}
+void launch_stream_weights(int nch, int64_t K, const double* h_ri, const double* psd, double* wts, double* hq,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL(k_stream_weights, dim3(nblk(K, 256)), dim3(256), 0, s, nch, K, h_ri, psd, wts, hq);
+}
+void launch_streams(const StreamArgs& a, hipStream_t s)
+{
+    if (a.R <= 0 || a.n_pieces <= 0) return;
+    const size_t lds = sizeof(double) * (size_t)kPieceBins * (2 * a.nch + 1);
+    hipLaunchKernelGGL(k_streams, dim3((unsigned)a.n_pieces, nblk(a.R, 256)), dim3(256), lds, s, a);
+}
+void launch_streams_final(const StreamArgs& a, hipStream_t s)
+{
+    if (a.R > 0) hipLaunchKernelGGL(k_streams_final, dim3(nblk(a.R, 256)), dim3(256), 0, s, a);
 }
 void launch_bins(const GridArgs& g, const double* d_ri, const double* psd, double* b64, float* b32, double su,
                  double sq, hipStream_t s)
