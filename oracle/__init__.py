@@ -8,7 +8,8 @@ this module only marshals numpy arrays through ctypes.
 
 Besides Upsilon_N it gives the likelihood quantities of Sec 2.1 - 2.2
 (``data_norm``, ``likelihood_stats``, ``loglike``), written in numpy on top of
-the per-segment sums of ``evaluate``.
+the per-segment sums of ``evaluate``.  ``oracle/search.py`` is the
+hierarchical multi-swarm search of Sec 3.2 over a caller-given objective.
 
 Parameter vector theta (7 doubles):
     Mc [Msun, detector frame], eta, f_low [Hz], lambda, beta, iota, psi
