@@ -340,6 +340,20 @@ int scs_swarm_destroy(scs_swarm* sw);
  * update particle and swarm bests (out-of-box or NaN values count as -inf). */
 int scs_pso_step(scs_swarm* sw, const scs_pso_params* params, int32_t prec, void* stream);
 
+/* One iteration of n swarms at once (the swarms of one rung of the
+ * hierarchical search, Sec 3.2): each swarm's move as in scs_pso_step, then
+ * ONE batched generate-and-reduce over all of them (scs_evaluate_batched:
+ * each swarm at its context's current N), then each swarm's best update.
+ * Every swarm ends in the state scs_pso_step would leave it in, bit for bit.
+ * gbest_vals (host [n], nullable) receives each swarm's best value after the
+ * iteration; the call then waits for the stream.  All swarms on one device,
+ * each at most once; swarms of one context use its batch workspaces (one per
+ * position in sws), so such calls go on one stream.  Errors: EINVAL (NULL or
+ * repeated swarm, negative eps, swarms on different devices), ENOMEM,
+ * EDEVICE. */
+int scs_pso_step_swarms(scs_swarm* const* sws, int32_t n, const scs_pso_params* params, int32_t prec,
+                        double* gbest_vals, void* stream);
+
 /* Copy the swarm state to host arrays (any may be NULL): theta, vel, pbest
  * [P][7], pbest_val [P], gbest [7], gbest_val, iteration.  Synchronous. */
 int scs_swarm_read(scs_swarm* sw, double* theta, double* vel, double* pbest, double* pbest_val, double* gbest,
@@ -363,6 +377,70 @@ int scs_pso_move(int64_t P, double* theta, double* vel, const double* pbest, con
 int scs_pso_best(int64_t P, const double* theta, const double* vals, const double* lo, const double* hi,
                  const int32_t* periodic, double* pbest, double* pbest_val, double* gbest, double* gbest_val,
                  void* stream);
+
+/* ---- hierarchical multi-swarm search (Sec 3.1 - 3.2, app:PSO_params) -- */
+
+typedef struct scs_search scs_search;
+
+typedef struct scs_search_params {
+    int32_t n_swarms;     /* swarms at the start, and clusters of every re-grouping (6 in the paper) */
+    int32_t G;            /* node stride of the equal-[h|h] edges at every rung */
+    int64_t particles;    /* per swarm at the start (10^4 in the paper); the total is conserved */
+    double conv_tol;      /* a swarm has converged when its best value gained at most conv_tol ... */
+    int32_t conv_window;  /* ... over its last conv_window iterations (2 over 50 in the paper) */
+    int32_t kmeans_iters; /* cap on the Lloyd iterations of a re-grouping */
+    int32_t prec;         /* SCS_PREC_* of every evaluation */
+    int32_t pad;
+    uint64_t seed;        /* swarm Philox key and k-means++ draws */
+} scs_search_params;
+
+/* One rung of the ladder: Upsilon_N with N segments (equal [h|h]) and the
+ * rung's hyper-parameters and minimum speeds (tab:PSO_hyperparams). */
+typedef struct scs_rung {
+    int32_t N;
+    int32_t max_iters;    /* iterations at most, converged or not */
+    scs_pso_params prm;
+} scs_rung;
+
+typedef struct scs_rung_report {
+    int32_t N;
+    int32_t n_swarms;     /* swarms during the rung */
+    int32_t iterations;   /* iterations run (the rung stops when every swarm converged) */
+    int32_t converged;    /* swarms that met the convergence rule */
+    double best_val;      /* best Upsilon_N over all swarms at the end of the rung */
+    double seconds;       /* wall time of the rung, re-grouping included */
+} scs_rung_report;
+
+/* Create a search on ctx: n_swarms swarms of `particles` particles, uniform
+ * in [lo, hi] (host [7]; periodic[d] = 1 wraps dimension d, may be NULL).
+ * Errors: EINVAL, ENOMEM, and those of scs_swarm_create. */
+int scs_search_create(scs_ctx* ctx, const scs_search_params* params, const double* lo, const double* hi,
+                      const int32_t* periodic, scs_search** out);
+
+/* Run one rung: before every rung but the first, re-group all particles by
+ * k-means of their positions (features: each dimension scaled to the prior
+ * box, periodic ones as the point (cos, sin) / 2 pi on the circle;
+ * k = n_swarms; empty clusters dropped) into new swarms whose bests start
+ * afresh; then define the rung's segmentation on the context and iterate
+ * scs_pso_step on every swarm until each has converged (a converged swarm
+ * stops moving) or max_iters.  report may be NULL.  Synchronises the stream
+ * once per iteration (one value per swarm). */
+int scs_search_run_rung(scs_search* s, const scs_rung* rung, scs_rung_report* report, void* stream);
+
+/* Current swarms: their number, sizes [n] and bests [n][8] (position, value);
+ * sizes and best may be NULL.  Synchronous. */
+int scs_search_swarms(scs_search* s, int32_t* n_swarms, int64_t* sizes, double* best);
+
+int scs_search_destroy(scs_search* s);
+
+/* k-means on host data x [n][dim] (squared Euclidean distance): k-means++
+ * seeding with splitmix64 draws from seed, then Lloyd iterations until no
+ * label changes or iters; ties go to the lower index; empty clusters are
+ * dropped and labels [n] renumbered by first appearance; centers [k][dim]
+ * (may be NULL); *k_out = clusters kept.  The re-grouping step of the search,
+ * exported for its tests.  Errors: EINVAL. */
+int scs_kmeans(const double* x, int64_t n, int32_t dim, int32_t k, int32_t iters, uint64_t seed, int32_t* labels,
+               double* centers, int32_t* k_out);
 
 /* Thread-local description of the last error on this thread ("" if none). */
 const char* scs_last_error(void);

@@ -58,6 +58,21 @@ class scs_pso_params(C.Structure):
                 ("eps", C.c_double * 7)]
 
 
+class scs_search_params(C.Structure):
+    _fields_ = [("n_swarms", C.c_int32), ("G", C.c_int32), ("particles", C.c_int64), ("conv_tol", C.c_double),
+                ("conv_window", C.c_int32), ("kmeans_iters", C.c_int32), ("prec", C.c_int32), ("pad", C.c_int32),
+                ("seed", C.c_uint64)]
+
+
+class scs_rung(C.Structure):
+    _fields_ = [("N", C.c_int32), ("max_iters", C.c_int32), ("prm", scs_pso_params)]
+
+
+class scs_rung_report(C.Structure):
+    _fields_ = [("N", C.c_int32), ("n_swarms", C.c_int32), ("iterations", C.c_int32), ("converged", C.c_int32),
+                ("best_val", C.c_double), ("seconds", C.c_double)]
+
+
 _lib = None
 
 _SIGS = {
@@ -87,6 +102,7 @@ _SIGS = {
                          C.c_uint64, C.c_uint32],
     "scs_swarm_destroy": [C.c_void_p],
     "scs_pso_step": [C.c_void_p, C.POINTER(scs_pso_params), C.c_int32, C.c_void_p],
+    "scs_pso_step_swarms": [C.c_void_p, C.c_int32, C.POINTER(scs_pso_params), C.c_int32, C.c_void_p, C.c_void_p],
     "scs_swarm_read": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                        C.POINTER(C.c_double), C.POINTER(C.c_uint32)],
     "scs_swarm_write": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
@@ -103,6 +119,13 @@ _SIGS = {
     "scs_server_stats": [C.c_void_p, C.POINTER(scs_server_counters)],
     "scs_server_clock": [C.c_void_p],
     "scs_server_destroy": [C.c_void_p],
+    "scs_search_create": [C.c_void_p, C.POINTER(scs_search_params), C.c_void_p, C.c_void_p, C.c_void_p,
+                          C.POINTER(C.c_void_p)],
+    "scs_search_run_rung": [C.c_void_p, C.POINTER(scs_rung), C.POINTER(scs_rung_report), C.c_void_p],
+    "scs_search_swarms": [C.c_void_p, C.POINTER(C.c_int32), C.c_void_p, C.c_void_p],
+    "scs_search_destroy": [C.c_void_p],
+    "scs_kmeans": [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_uint64, C.c_void_p, C.c_void_p,
+                   C.POINTER(C.c_int32)],
     "scs_last_error": [],
 }
 _RESTYPES = {"scs_last_error": C.c_char_p, "scs_server_clock": C.c_double}
@@ -369,10 +392,65 @@ def pso_params(omega, phi_p, phi_g, eps):
     return scs_pso_params(omega, phi_p, phi_g, (C.c_double * 7)(*[float(e) for e in eps]))
 
 
+def scs_search_create(ctx, n_swarms, particles, lo, hi, periodic=None, G=1, conv_tol=2.0, conv_window=50,
+                      kmeans_iters=100, prec=SCS_PREC_FP64, seed=0):
+    prm = scs_search_params(n_swarms, G, particles, conv_tol, conv_window, kmeans_iters, prec, 0, seed)
+    lo, hi = _f64(lo), _f64(hi)
+    per = np.ascontiguousarray(periodic if periodic is not None else np.zeros(7), dtype=np.int32)
+    h = C.c_void_p()
+    _check(lib().scs_search_create(ctx, C.byref(prm), C.c_void_p(lo.ctypes.data), C.c_void_p(hi.ctypes.data),
+                                   C.c_void_p(per.ctypes.data), C.byref(h)))
+    return h
+
+
+def scs_search_run_rung(search, N, max_iters, params, stream=None):
+    """One rung; returns the report as a dict."""
+    r = scs_rung(N, max_iters, params)
+    rep = scs_rung_report()
+    _check(lib().scs_search_run_rung(search, C.byref(r), C.byref(rep), _stream(stream or current_stream())))
+    return {k: getattr(rep, k) for k, _ in scs_rung_report._fields_}
+
+
+def scs_search_swarms(search, max_swarms=64):
+    n = C.c_int32()
+    sizes = np.zeros(max_swarms, dtype=np.int64)
+    best = np.zeros((max_swarms, 8))
+    _check(lib().scs_search_swarms(search, C.byref(n), C.c_void_p(sizes.ctypes.data), C.c_void_p(best.ctypes.data)))
+    return sizes[:n.value].copy(), best[:n.value].copy()
+
+
+def scs_search_destroy(search):
+    _check(lib().scs_search_destroy(search))
+
+
+def scs_kmeans(x, k, iters=100, seed=0):
+    """x numpy [n, dim] -> (labels [n], centers [k_out, dim])."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    n, dim = x.shape
+    labels = np.empty(n, dtype=np.int32)
+    centers = np.empty((k, dim))
+    ko = C.c_int32()
+    _check(lib().scs_kmeans(C.c_void_p(x.ctypes.data), n, dim, k, iters, seed, C.c_void_p(labels.ctypes.data),
+                            C.c_void_p(centers.ctypes.data), C.byref(ko)))
+    return labels, centers[:ko.value].copy()
+
+
 def scs_pso_step(sw, params, prec=SCS_PREC_FP64, stream=None):
     if stream is None:
         stream = current_stream()
     _check(lib().scs_pso_step(sw, C.byref(params), prec, _stream(stream)))
+
+
+def scs_pso_step_swarms(sws, params, prec=SCS_PREC_FP64, stream=None, read_best=True):
+    """One iteration of several swarms with one batched evaluation; returns
+    each swarm's best value (numpy [n]) when read_best, else None."""
+    if stream is None:
+        stream = current_stream()
+    arr = (C.c_void_p * len(sws))(*[sw.value if isinstance(sw, C.c_void_p) else sw for sw in sws])
+    vals = np.empty(len(sws)) if read_best else None
+    _check(lib().scs_pso_step_swarms(C.cast(arr, C.c_void_p), len(sws), C.byref(params), prec,
+                                     C.c_void_p(vals.ctypes.data) if read_best else None, _stream(stream)))
+    return vals
 
 
 def scs_swarm_read(sw, P):

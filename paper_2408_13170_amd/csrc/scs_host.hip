@@ -259,6 +259,9 @@ static void free_ws(Workspace& w)
     w = Workspace();
 }
 
+// Error record for the library's other translation units (the search driver).
+int scs_record_error(int code, const char* msg) { return fail(code, "%s", msg); }
+
 extern "C" const char* scs_last_error(void) { return g_last_error.c_str(); }
 
 extern "C" int scs_ctx_create(scs_ctx** out, int device)
@@ -468,6 +471,7 @@ static std::string tune_key(const scs_ctx* c, int64_t P, int N, int prec)
     return o.str();
 }
 
+// ==== launch shape of the generate-and-reduce (begin)
 static TuneChoice choose(const scs_ctx* c, int64_t P, int N, int prec)
 {
     if (c->has_override) return c->override_choice;
@@ -501,6 +505,8 @@ static Plan make_plan(const scs_ctx* c, int64_t P, const TuneChoice& t)
     pl.n_tiles = pl.n_chunks * pl.n_groups;
     return pl;
 }
+
+// ==== launch shape of the generate-and-reduce (end)
 
 static int64_t pad64(int64_t v) { return (v + 63) / 64 * 64; }
 
@@ -1142,6 +1148,7 @@ static int check_items(const scs_batch_item* items, int32_t n_items, int32_t pre
     return SCS_OK;
 }
 
+// ==== launch shape of the generate-and-reduce (begin)
 // The generate-and-reduce of prepared evaluations: one persistent launch per
 // channel count over the tiles of all of them (descriptors in slot b;
 // upload: copy them from the pinned host copy first).
@@ -1199,6 +1206,8 @@ static int eval_main(scs_ctx* c, EvalJob& j, int prec, hipStream_t s)
     HIP_TRY(hipEventRecord(b.done, s));
     return SCS_OK;
 }
+
+// ==== launch shape of the generate-and-reduce (end)
 
 // Queue a batch on s using the descriptors of slot b.  upload: copy the
 // descriptors from the pinned host copy (skipped under graph capture, where
@@ -1866,6 +1875,48 @@ extern "C" int scs_pso_step(scs_swarm* sw, const scs_pso_params* prm, int32_t pr
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(SCS_EDEVICE, "pso launch failed: %s", hipGetErrorString(e));
     sw->iteration += 1;
+    return SCS_OK;
+}
+
+extern "C" int scs_pso_step_swarms(scs_swarm* const* sws, int32_t n, const scs_pso_params* prm, int32_t prec,
+                                   double* gbest_vals, void* stream)
+{
+    if (!sws || n < 0 || !prm) return fail(SCS_EINVAL, "bad arguments");
+    for (int d = 0; d < 7; ++d)
+        if (!(prm->eps[d] >= 0.0)) return fail(SCS_EINVAL, "eps[%d] must be >= 0", d);
+    if (n == 0) return SCS_OK;
+    std::vector<scs_batch_item> items(n);
+    for (int i = 0; i < n; ++i) {
+        scs_swarm* sw = sws[i];
+        if (!sw) return fail(SCS_EINVAL, "swarm %d is NULL", i);
+        for (int j = 0; j < i; ++j)
+            if (sws[j] == sw) return fail(SCS_EINVAL, "swarm %d appears twice", i);
+        items[i] = scs_batch_item{sw->ctx, sw->ctx ? sw->ctx->N : 0, 0, sw->P, sw->theta, sw->ups, nullptr};
+    }
+    // items are checked (ready contexts, one device) before anything is queued
+    int rc = check_items(items.data(), n, prec);
+    if (rc) return rc;
+    DevScope ds(sws[0]->ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    for (int i = 0; i < n; ++i) {
+        scs_swarm* sw = sws[i];
+        if (sw->iteration > 0)
+            launch_pso_move(sw->P, sw->box, to_params(prm), sw->seed, sw->swarm_id, sw->iteration, sw->theta, sw->vel,
+                            sw->pbest, sw->gbest, s);
+    }
+    if ((rc = scs_evaluate_batched(items.data(), n, prec, stream))) return rc;
+    for (int i = 0; i < n; ++i) {
+        scs_swarm* sw = sws[i];
+        launch_pso_best(sw->P, sw->box, sw->theta, sw->ups, sw->pbest, sw->pbest_val, sw->gbest, sw->gbest + 7, s);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(SCS_EDEVICE, "pso launch failed: %s", hipGetErrorString(e));
+    for (int i = 0; i < n; ++i) sws[i]->iteration += 1;
+    if (gbest_vals) {
+        for (int i = 0; i < n; ++i)
+            HIP_TRY(hipMemcpyAsync(gbest_vals + i, sws[i]->gbest + 7, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
     return SCS_OK;
 }
 

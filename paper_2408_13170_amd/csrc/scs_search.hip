@@ -1,0 +1,338 @@
+// Hierarchical multi-swarm search (arXiv:2408.13170, Sec 3.1 - 3.2 and the PSO
+// appendix app:PSO_params), written on top of the library's public calls: the
+// swarms live on the device and every iteration is one scs_pso_step_swarms
+// over the swarms still moving (their moves, ONE batched generate-and-reduce
+// over all of their particles, their bests); the host keeps one number per
+// swarm per iteration (its best value) for the convergence rule, and
+// re-groups the particles between rungs with k-means.
+//
+//   rung:      Upsilon_N with the rung's N, equal-[h|h] edges, and the rung's
+//              hyper-parameters and minimum speeds (tab:PSO_hyperparams);
+//   converged: a swarm's best value gained no more than conv_tol over its
+//              last conv_window iterations (2 over 50 in the paper); a
+//              converged swarm stops moving until the rung ends;
+//   regroup:   before every rung but the first, k-means on the positions of
+//              all particles of all swarms (k = the initial number of
+//              swarms); every non-empty cluster becomes a swarm; the number of
+//              particles is conserved.  Positions and velocities carry over;
+//              the bests start afresh because the objective changed.
+//
+// k-means runs on the host: once per rung on P x 7 numbers (about 60000 x 7
+// for the paper's search), milliseconds against the seconds of a rung.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <vector>
+
+#include "../../include/scs.h"
+
+namespace {
+
+// splitmix64 (Steele, Lea & Flood 2014): the k-means++ draws.
+struct SplitMix {
+    uint64_t s;
+    uint64_t next()
+    {
+        uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    }
+    double uniform() { return ((double)(next() >> 11) + 0.5) * 0x1p-53; }  // (0, 1)
+};
+
+}  // namespace
+
+// The library's error record (scs_last_error), defined beside the other entry points.
+int scs_record_error(int code, const char* msg);
+static int err(int code, const char* msg) { return scs_record_error(code, msg); }
+
+struct scs_search {
+    scs_ctx* ctx = nullptr;
+    scs_search_params p{};
+    double lo[7], hi[7];
+    int32_t per[7];
+    std::vector<scs_swarm*> swarms;
+    std::vector<int64_t> sizes;
+    uint32_t next_id = 0;
+    int rungs_done = 0;
+};
+
+// k-means with k-means++ seeding (Arthur & Vassilvitskii 2007) and Lloyd
+// iterations until no label changes (or iters); squared Euclidean distance.
+// Ties go to the lower cluster index.  Empty clusters are dropped and the
+// labels renumbered in order of first appearance of the kept clusters.
+extern "C" int scs_kmeans(const double* x, int64_t n, int32_t dim, int32_t k, int32_t iters, uint64_t seed,
+                          int32_t* labels, double* centers, int32_t* k_out)
+{
+    if (!x || !labels || !k_out || n < 1 || dim < 1 || k < 1 || iters < 1) return err(SCS_EINVAL, "bad k-means arguments");
+    k = (int32_t)std::min<int64_t>(k, n);
+    std::vector<double> c((size_t)k * dim), d2(n, std::numeric_limits<double>::infinity());
+    SplitMix rng{seed};
+    auto dist = [&](int64_t i, const double* ctr) {
+        double s = 0.0;
+        for (int j = 0; j < dim; ++j) {
+            const double t = x[i * dim + j] - ctr[j];
+            s += t * t;
+        }
+        return s;
+    };
+    // seeding: first centre uniform, the others with probability ~ D^2
+    int64_t first = (int64_t)(rng.uniform() * (double)n);
+    first = std::min<int64_t>(first, n - 1);
+    std::copy(x + first * dim, x + (first + 1) * dim, c.begin());
+    for (int m = 1; m < k; ++m) {
+        double tot = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            d2[i] = std::min(d2[i], dist(i, &c[(size_t)(m - 1) * dim]));
+            tot += d2[i];
+        }
+        int64_t pick = n - 1;
+        if (tot > 0.0) {
+            const double u = rng.uniform() * tot;
+            double acc = 0.0;
+            for (int64_t i = 0; i < n; ++i) {
+                acc += d2[i];
+                if (acc >= u) {
+                    pick = i;
+                    break;
+                }
+            }
+        } else {
+            pick = (int64_t)(rng.uniform() * (double)n);
+            pick = std::min<int64_t>(pick, n - 1);
+        }
+        std::copy(x + pick * dim, x + (pick + 1) * dim, c.begin() + (size_t)m * dim);
+    }
+    std::vector<int32_t> lab(n, -1);
+    std::vector<double> sum((size_t)k * dim);
+    std::vector<int64_t> cnt(k);
+    for (int it = 0; it < iters; ++it) {
+        bool changed = false;
+        for (int64_t i = 0; i < n; ++i) {
+            int best = 0;
+            double bd = dist(i, &c[0]);
+            for (int m = 1; m < k; ++m) {
+                const double dm = dist(i, &c[(size_t)m * dim]);
+                if (dm < bd) {
+                    bd = dm;
+                    best = m;
+                }
+            }
+            if (lab[i] != best) {
+                lab[i] = best;
+                changed = true;
+            }
+        }
+        if (!changed && it > 0) break;
+        std::fill(sum.begin(), sum.end(), 0.0);
+        std::fill(cnt.begin(), cnt.end(), 0);
+        for (int64_t i = 0; i < n; ++i) {
+            ++cnt[lab[i]];
+            for (int j = 0; j < dim; ++j) sum[(size_t)lab[i] * dim + j] += x[i * dim + j];
+        }
+        for (int m = 0; m < k; ++m)
+            if (cnt[m] > 0)
+                for (int j = 0; j < dim; ++j) c[(size_t)m * dim + j] = sum[(size_t)m * dim + j] / (double)cnt[m];
+    }
+    // drop empty clusters, renumber by first appearance
+    std::vector<int32_t> map(k, -1);
+    int32_t kk = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (map[lab[i]] < 0) map[lab[i]] = kk++;
+        labels[i] = map[lab[i]];
+    }
+    if (centers)
+        for (int m = 0; m < k; ++m)
+            if (map[m] >= 0) std::copy(&c[(size_t)m * dim], &c[(size_t)(m + 1) * dim], centers + (size_t)map[m] * dim);
+    *k_out = kk;
+    return SCS_OK;
+}
+
+extern "C" int scs_search_create(scs_ctx* ctx, const scs_search_params* p, const double* lo, const double* hi,
+                                 const int32_t* periodic, scs_search** out)
+{
+    if (!ctx || !p || !lo || !hi || !out) return err(SCS_EINVAL, "NULL argument");
+    if (p->n_swarms < 1 || p->particles < 1 || p->G < 1 || p->conv_window < 1 || p->kmeans_iters < 1 ||
+        !(p->conv_tol >= 0.0) || (p->prec != SCS_PREC_FP64 && p->prec != SCS_PREC_MIXED))
+        return err(SCS_EINVAL, "bad search parameters");
+    scs_search* s = new (std::nothrow) scs_search();
+    if (!s) return err(SCS_ENOMEM, "host allocation failed");
+    s->ctx = ctx;
+    s->p = *p;
+    for (int d = 0; d < 7; ++d) {
+        s->lo[d] = lo[d];
+        s->hi[d] = hi[d];
+        s->per[d] = periodic ? periodic[d] : 0;
+    }
+    for (int i = 0; i < p->n_swarms; ++i) {
+        scs_swarm* sw = nullptr;
+        int rc = scs_swarm_create(ctx, &sw, p->particles, s->lo, s->hi, s->per, p->seed, s->next_id++);
+        if (rc) {
+            scs_search_destroy(s);
+            return rc;
+        }
+        s->swarms.push_back(sw);
+        s->sizes.push_back(p->particles);
+    }
+    *out = s;
+    return SCS_OK;
+}
+
+// Regroup all particles into k-means clusters of their positions (features:
+// each dimension scaled to the prior box, periodic ones as the point on the
+// circle (cos, sin) / 2 pi, so that a full turn spans about the same as a box).
+static int regroup(scs_search* s)
+{
+    const int nsw = (int)s->swarms.size();
+    int64_t P = 0;
+    for (int64_t n : s->sizes) P += n;
+    std::vector<double> th((size_t)P * 7), vel((size_t)P * 7);
+    int64_t off = 0;
+    for (int i = 0; i < nsw; ++i) {
+        int rc = scs_swarm_read(s->swarms[i], &th[(size_t)off * 7], &vel[(size_t)off * 7], nullptr, nullptr, nullptr,
+                                nullptr, nullptr);
+        if (rc) return rc;
+        off += s->sizes[i];
+    }
+    int dim = 0;
+    for (int d = 0; d < 7; ++d) dim += s->per[d] ? 2 : 1;
+    std::vector<double> f((size_t)P * dim);
+    for (int64_t i = 0; i < P; ++i) {
+        int j = 0;
+        for (int d = 0; d < 7; ++d) {
+            const double w = s->hi[d] - s->lo[d];
+            const double u = w > 0.0 ? (th[(size_t)i * 7 + d] - s->lo[d]) / w : 0.0;
+            if (s->per[d]) {
+                const double a = 2.0 * M_PI * u;
+                f[(size_t)i * dim + j++] = std::cos(a) / (2.0 * M_PI);
+                f[(size_t)i * dim + j++] = std::sin(a) / (2.0 * M_PI);
+            } else {
+                f[(size_t)i * dim + j++] = u;
+            }
+        }
+    }
+    std::vector<int32_t> lab(P);
+    int32_t k = 0;
+    int rc = scs_kmeans(f.data(), P, dim, s->p.n_swarms, s->p.kmeans_iters,
+                        s->p.seed ^ (0x6b6d65616e73ull + (uint64_t)s->rungs_done), lab.data(), nullptr, &k);
+    if (rc) return rc;
+    std::vector<scs_swarm*> nsws;
+    std::vector<int64_t> nsizes;
+    for (int c = 0; c < k; ++c) {
+        std::vector<double> tc, vc;
+        for (int64_t i = 0; i < P; ++i)
+            if (lab[i] == c) {
+                tc.insert(tc.end(), &th[(size_t)i * 7], &th[(size_t)i * 7 + 7]);
+                vc.insert(vc.end(), &vel[(size_t)i * 7], &vel[(size_t)i * 7 + 7]);
+            }
+        const int64_t pc = (int64_t)tc.size() / 7;
+        scs_swarm* sw = nullptr;
+        if ((rc = scs_swarm_create(s->ctx, &sw, pc, s->lo, s->hi, s->per, s->p.seed, s->next_id++))) break;
+        nsws.push_back(sw);
+        nsizes.push_back(pc);
+        // bests start afresh: the first step of the rung only evaluates
+        std::vector<double> pv(pc, -std::numeric_limits<double>::infinity());
+        if ((rc = scs_swarm_write(sw, tc.data(), vc.data(), tc.data(), pv.data(), tc.data(),
+                                  -std::numeric_limits<double>::infinity(), 0u)))
+            break;
+    }
+    if (rc) {
+        for (scs_swarm* sw : nsws) scs_swarm_destroy(sw);
+        return rc;
+    }
+    for (scs_swarm* sw : s->swarms) scs_swarm_destroy(sw);
+    s->swarms = nsws;
+    s->sizes = nsizes;
+    return SCS_OK;
+}
+
+extern "C" int scs_search_run_rung(scs_search* s, const scs_rung* r, scs_rung_report* rep, void* stream)
+{
+    if (!s || !r) return err(SCS_EINVAL, "NULL argument");
+    if (r->N < 1 || r->max_iters < 1) return err(SCS_EINVAL, "bad rung");
+    const auto t0 = std::chrono::steady_clock::now();
+    int rc;
+    if (s->rungs_done > 0 && (rc = regroup(s))) return rc;
+    if ((rc = scs_define_segmentation(s->ctx, r->N, SCS_SEG_EQUAL_SNR, s->p.G, nullptr))) return rc;
+    const int nsw = (int)s->swarms.size();
+    std::vector<std::vector<double>> hist(nsw);
+    std::vector<char> done(nsw, 0);
+    std::vector<scs_swarm*> act;
+    std::vector<int> idx;
+    std::vector<double> g;
+    int it = 0;
+    for (; it < r->max_iters; ++it) {
+        act.clear();
+        idx.clear();
+        for (int i = 0; i < nsw; ++i)
+            if (!done[i]) {
+                act.push_back(s->swarms[i]);
+                idx.push_back(i);
+            }
+        if (act.empty()) break;
+        // every active swarm moves and is evaluated in one batched launch
+        g.resize(act.size());
+        if ((rc = scs_pso_step_swarms(act.data(), (int32_t)act.size(), &r->prm, s->p.prec, g.data(), stream)))
+            return rc;
+        for (size_t a = 0; a < act.size(); ++a) {
+            const int i = idx[a];
+            hist[i].push_back(g[a]);
+            const size_t h = hist[i].size();
+            const size_t w = (size_t)s->p.conv_window;
+            if (h > w && std::isfinite(hist[i][h - 1 - w]) && hist[i][h - 1] - hist[i][h - 1 - w] <= s->p.conv_tol)
+                done[i] = 1;
+        }
+        bool all = true;
+        for (int i = 0; i < nsw; ++i) all = all && done[i];
+        if (all) {
+            ++it;
+            break;
+        }
+    }
+    s->rungs_done += 1;
+    if (rep) {
+        rep->N = r->N;
+        rep->n_swarms = nsw;
+        rep->iterations = it;
+        int conv = 0;
+        double best = -std::numeric_limits<double>::infinity();
+        for (int i = 0; i < nsw; ++i) {
+            conv += done[i];
+            if (!hist[i].empty()) best = std::max(best, hist[i].back());
+        }
+        rep->converged = conv;
+        rep->best_val = best;
+        rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return SCS_OK;
+}
+
+extern "C" int scs_search_swarms(scs_search* s, int32_t* n_swarms, int64_t* sizes, double* best)
+{
+    if (!s || !n_swarms) return err(SCS_EINVAL, "NULL argument");
+    *n_swarms = (int32_t)s->swarms.size();
+    for (size_t i = 0; i < s->swarms.size(); ++i) {
+        if (sizes) sizes[i] = s->sizes[i];
+        if (best) {
+            int rc = scs_swarm_read(s->swarms[i], nullptr, nullptr, nullptr, nullptr, best + 8 * i, best + 8 * i + 7,
+                                    nullptr);
+            if (rc) return rc;
+        }
+    }
+    return SCS_OK;
+}
+
+extern "C" int scs_search_destroy(scs_search* s)
+{
+    if (!s) return SCS_OK;
+    for (scs_swarm* sw : s->swarms) scs_swarm_destroy(sw);
+    delete s;
+    return SCS_OK;
+}

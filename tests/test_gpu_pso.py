@@ -104,3 +104,41 @@ def test_swarm_steps_and_checkpoint_resume():
         B.scs_swarm_destroy(sw3)
     finally:
         B.scs_ctx_destroy(h)
+
+
+def test_step_swarms_equals_single_steps():
+    """One batched iteration of several swarms leaves each swarm exactly as
+    scs_pso_step would, over several iterations; uneven P, two contexts."""
+    ds = D.lisa_small(seed=8)
+    g = ds.grid
+    hs = []
+    try:
+        for N in (8, 3):
+            h = B.scs_ctx_create(0)
+            hs.append(h)
+            B.scs_load_data(h, np.ascontiguousarray(ds.d_ri), np.ascontiguousarray(ds.psd), g.k0 * g.df, g.df)
+            B.scs_set_model(h, 7, 1, 1, ds.model.t_obs)
+            B.scs_define_segmentation(h, N, B.SCS_SEG_EQUAL_SNR, 16)
+        spec = [(hs[0], 300, 1), (hs[0], 77, 2), (hs[1], 513, 3)]
+        prm = B.pso_params(0.5, 0.2, 0.3, [0.1, 0.05, 5e-8, 0.1, 0.1, 0.2, 0.1])
+        for prec in (B.SCS_PREC_FP64, B.SCS_PREC_MIXED):
+            multi = [B.scs_swarm_create(h, P, LO, HI, PER, seed=21, swarm_id=i) for h, P, i in spec]
+            single = [B.scs_swarm_create(h, P, LO, HI, PER, seed=21, swarm_id=i) for h, P, i in spec]
+            try:
+                for it in range(4):
+                    vals = B.scs_pso_step_swarms(multi, prm, prec)
+                    for sw in single:
+                        B.scs_pso_step(sw, prm, prec)
+                    for k, ((_, P, _), a, b) in enumerate(zip(spec, multi, single)):
+                        sa, sb = B.scs_swarm_read(a, P), B.scs_swarm_read(b, P)
+                        for key in ("theta", "vel", "pbest", "pbest_val", "gbest"):
+                            assert np.array_equal(sa[key], sb[key]), (prec, it, k, key)
+                        assert sa["gbest_val"] == sb["gbest_val"] == vals[k] and sa["iteration"] == it + 1
+                with pytest.raises(B.ScsError):
+                    B.scs_pso_step_swarms([multi[0], multi[0]], prm, prec)
+            finally:
+                for sw in multi + single:
+                    B.scs_swarm_destroy(sw)
+    finally:
+        for h in hs:
+            B.scs_ctx_destroy(h)
