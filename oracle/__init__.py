@@ -33,6 +33,7 @@ SEG_EXPLICIT = 2
 
 RESP_NONE = 0
 RESP_LISA_LF_AE = 1
+RESP_LISA_FD = 2
 
 SUPPORT_FULL = 0
 SUPPORT_TOBS = 1
@@ -98,6 +99,8 @@ def lib():
         L.orc_phase_bins.restype = C.c_int
         L.orc_response.argtypes = [C.POINTER(_Model), dp, C.c_double, dp, dp, dp]
         L.orc_response.restype = C.c_int
+        L.orc_fd_transfer.argtypes = [C.POINTER(_Model), dp, C.c_double, C.c_double, dp]
+        L.orc_fd_transfer.restype = C.c_int
         u32p = C.POINTER(C.c_uint32)
         L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
         L.orc_philox4x32_10.restype = None
@@ -262,6 +265,17 @@ def response(model: Model, theta, t):
     if rc != 0:
         raise ValueError("invalid theta")
     return F.reshape(2, 2), dop.value, tch
+
+
+def fd_transfer(model: Model, theta, f, t):
+    """Full-response transfer functions (A, E, T), complex [3], at frequency
+    f [Hz] and time t [s] (response 2)."""
+    theta = _f64(theta).reshape(7)
+    R = np.empty(6)
+    m = model.c()
+    if lib().orc_fd_transfer(C.byref(m), _dp(theta), float(f), float(t), _dp(R)) != 0:
+        raise ValueError("invalid theta")
+    return R[0::2] + 1j * R[1::2]
 
 
 def philox4x32_10(ctr, key):

@@ -22,7 +22,8 @@
  *                          x_n = max_phi [d|h e^{i phi}]_n = 4 df |Z_n|  [Sec 2.2, Upsilon_N definition]
  *   equal-SNR boundaries   every segment holds the same [h|h]           [Sec 2.2, boundary choice]
  *   waveform               TaylorF2 (2,2) mode, restricted amplitude     [Sec 4, waveform paragraph]
- *   response               low-frequency LISA A/E channels               [Sec 4, response paragraph]
+ *   response               low-frequency LISA A/E channels, or the full   [Sec 4, response paragraph]
+ *                          frequency-domain TDI transfer functions A/E/T
  *   PSO update             velocity rule + minimum-velocity clamp       [Sec 3.1, eqn:PSO_velocity_rule,
  *                                                                         eqn:PSO_min_velocity]
  * Where the paper leaves a point open, the reading taken is stated next to
@@ -33,7 +34,12 @@
  * only through an extended-precision evaluation of the same formula and the
  * coalescence times of the injection tables), and the low-frequency response
  * beyond its invariants (the paper's full response code is not available).
+ * The full response is pinned to its own definition (link light-travel
+ * formula and TDI with explicit delays, evaluated in the time domain) and to
+ * the low-frequency limit, not to another implementation: its constellation
+ * is rigid with equal, static arms, a reading of the response paragraph.
  */
+#include <complex.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -51,6 +57,7 @@ typedef long double ld;
 #define YEAR_SI 31557600.0L         /* s, Julian year */
 #define EULER_GAMMA_L 0.577215664901532860606512090082402431L
 #define PI_L 3.141592653589793238462643383279502884L
+#define ARM_SI 2.5e9                /* m, arm length of the constellation (full response) */
 
 /* ---- public structures (mirrored by ctypes in oracle/__init__.py) ----- */
 typedef struct {
@@ -63,7 +70,8 @@ typedef struct {
 
 typedef struct {
     int32_t pn_order;        /* highest power j of v kept in the phase series, 0..7 */
-    int32_t response;        /* 0: none (one channel), 1: LISA low-frequency A,E */
+    int32_t response;        /* 0: none (one channel), 1: LISA low-frequency A,E,
+                                2: LISA full frequency-domain response A,E (,T) */
     int32_t support;         /* 0: whole band, 1: observation window */
     int32_t pad;
     double t_obs;            /* observation time [s] */
@@ -208,18 +216,26 @@ static void polarisation(src_t* s, double lam, double bet, double psi)
  * z/2 - (sqrt 3 / 2) r_hat); the spacecraft turn in that plane once per orbit
  * in the opposite sense (cartwheel).  D_X = (a01 a01 - a02 a02)/2 etc.,
  * A = (Z - X)/sqrt2, E = (X - 2Y + Z)/sqrt6. */
-static void detector_tensors(double Phi, double cart0, double DA[3][3], double DE[3][3])
+/* Unit in-plane positions p[a] of the three spacecraft relative to the
+ * constellation centre (the craft sit at R0 + (L / sqrt3) p[a]). */
+static void constellation(double Phi, double cart0, double p[3][3])
 {
     const double cp = cos(Phi), sp = sin(Phi);
     const double er[3] = {cp, sp, 0.0}, ephi[3] = {-sp, cp, 0.0}, ez[3] = {0.0, 0.0, 1.0};
     const double h3 = sqrt(3.0) / 2.0;
-    double e1[3], p[3][3];
+    double e1[3];
     for (int i = 0; i < 3; ++i) e1[i] = -0.5 * er[i] - h3 * ez[i];
     const double zeta = cart0 - Phi;
     for (int a = 0; a < 3; ++a) {
         const double th = zeta + 2.0 * M_PI * a / 3.0;
         for (int i = 0; i < 3; ++i) p[a][i] = cos(th) * e1[i] + sin(th) * ephi[i];
     }
+}
+
+static void detector_tensors(double Phi, double cart0, double DA[3][3], double DE[3][3])
+{
+    double p[3][3];
+    constellation(Phi, cart0, p);
     double arm[3][3][3]; /* arm[a][b] = unit vector from craft a to craft b */
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b)
@@ -266,6 +282,64 @@ static double doppler_cycles(const src_t* s, const orc_model* m, double f, doubl
     return -f * nR * (double)(AU_SI / C_SI);
 }
 
+/* Full frequency-domain response (response 2), from the light-travel
+ * formula of one link and first-generation TDI on the same rigid equal-arm
+ * constellation, at frequency f and stationary-phase time t.
+ *
+ * Link j -> i (unit vector n from craft j to craft i, light time L): for a
+ * plane wave travelling along k = -nhat, H(t - k.x) = h(t - k.x) P, the
+ * fractional frequency shift is
+ *     y_ij(t) = n.[H(t - L - k.x_j) - H(t - k.x_i)].n / (2 (1 - k.n)).
+ * A delay tau multiplies a Fourier component by e^{-2 pi i f tau}, so with
+ * the polarisation content P = a+ e+ - i ax ex of the template (the same as
+ * the low-frequency response's) and x_i - x_j = L n,
+ *     y_ij / h = -i pi f L sinc(pi f L (1 - k.n)) e^{-i pi f (L + k.(x_i + x_j))} n.P.n .
+ * The common delay of the constellation centre, e^{-2 pi i f k.R0}, is the
+ * Doppler factor already in the phase, so x are taken from the centre.
+ * TDI (equal, static arms; one-arm delay z = e^{-2 pi i f L}):
+ *     X = (1 - z^2) [(y_01 + z y_10) - (y_02 + z y_20)], Y and Z cyclic,
+ *     A = (Z - X)/sqrt2, E = (X - 2Y + Z)/sqrt6, T = (X + Y + Z)/sqrt3,
+ * each divided by 4 (2 pi f L)^2, so that A and E tend to the low-frequency
+ * response (D_A:P, D_E:P) as f L -> 0.  R[c] for c < nch. */
+static void fd_transfer(const src_t* s, const orc_model* m, double f, double t, int nch, double complex R[3])
+{
+    const double Phi = m->orbit_phase0 + 2.0 * M_PI * t / (double)YEAR_SI;
+    double p[3][3];
+    constellation(Phi, m->cartwheel_phase0, p);
+    const double L = ARM_SI / (double)C_SI; /* light time of one arm [s] */
+    const double r = L / sqrt(3.0);        /* centre-to-craft light time [s] */
+    double complex y[3][3] = {{0}};
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            if (i == j) continue;
+            double n[3];
+            for (int c = 0; c < 3; ++c) n[c] = (p[i][c] - p[j][c]) / sqrt(3.0);
+            double kn = 0.0, kx = 0.0, npp = 0.0, npx = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                kn -= s->nhat[c] * n[c];
+                kx -= r * s->nhat[c] * (p[i][c] + p[j][c]);
+                for (int d = 0; d < 3; ++d) {
+                    npp += n[c] * s->eplus[c][d] * n[d];
+                    npx += n[c] * s->ecross[c][d] * n[d];
+                }
+            }
+            const double complex nPn = s->a_plus * npp - I * s->a_cross * npx;
+            const double arg = M_PI * f * L * (1.0 - kn);
+            const double sinc = arg == 0.0 ? 1.0 : sin(arg) / arg;
+            y[i][j] = -I * M_PI * f * L * sinc * cexp(-I * M_PI * f * (L + kx)) * nPn;
+        }
+    const double complex z = cexp(-2.0 * I * M_PI * f * L);
+    const double complex w = 1.0 - z * z;
+    const double complex X = w * ((y[0][1] + z * y[1][0]) - (y[0][2] + z * y[2][0]));
+    const double complex Y = w * ((y[1][2] + z * y[2][1]) - (y[1][0] + z * y[0][1]));
+    const double complex Z = w * ((y[2][0] + z * y[0][2]) - (y[2][1] + z * y[1][2]));
+    const double x = 2.0 * M_PI * f * L;
+    const double norm = 4.0 * x * x;
+    R[0] = (Z - X) / sqrt(2.0) / norm;
+    R[1] = (X - 2.0 * Y + Z) / sqrt(6.0) / norm;
+    if (nch > 2) R[2] = (X + Y + Z) / sqrt(3.0) / norm;
+}
+
 /* Derive everything that depends on theta only.  Invalid theta -> valid = 0. */
 static void make_source(const double* th, const orc_model* m, src_t* s)
 {
@@ -300,7 +374,7 @@ static ld freq(const orc_grid* g, int64_t k) { return (ld)(g->k0 + k) * (ld)g->d
  * constant (distance and phase, which the statistic removes).  Returns the
  * number of channels written. */
 static int template_bin(const src_t* s, const orc_model* m, const orc_grid* g, int64_t k,
-                        double hre[2], double him[2])
+                        double hre[3], double him[3])
 {
     const ld f = freq(g, k);
     const ld ph = phase_cycles(s, f);
@@ -313,11 +387,22 @@ static int template_bin(const src_t* s, const orc_model* m, const orc_grid* g, i
         return 1;
     }
     const double t = (double)spa_time(s, f);
-    double F[2][2];
-    antenna(s, m, t, F);
     double tot = (double)phf + doppler_cycles(s, m, (double)f, t);
     tot -= floor(tot);
     const double c = cos(2.0 * M_PI * tot), sn = sin(2.0 * M_PI * tot);
+    if (m->response == 2) {
+        double complex R[3];
+        fd_transfer(s, m, (double)f, t, g->n_chan, R);
+        for (int a = 0; a < g->n_chan; ++a) {
+            /* h = amp R e^{-i 2 pi tot} */
+            const double rr = creal(R[a]), ri = cimag(R[a]);
+            hre[a] = amp * (rr * c + ri * sn);
+            him[a] = amp * (ri * c - rr * sn);
+        }
+        return g->n_chan;
+    }
+    double F[2][2];
+    antenna(s, m, t, F);
     for (int a = 0; a < 2; ++a) {
         /* R = F+ A+ - i Fx Ax ; h = amp R e^{-i 2 pi tot} */
         const double rr = F[a][0] * s->a_plus, ri = -F[a][1] * s->a_cross;
@@ -351,7 +436,7 @@ static void support(const src_t* s, const orc_model* m, const orc_grid* g, doubl
 static double weight(const src_t* s, const orc_model* m, const orc_grid* g, const double* psd,
                      int64_t k)
 {
-    double hr[2], hi[2];
+    double hr[3], hi[3];
     const int nc = template_bin(s, m, g, k, hr, hi);
     double w = 0.0;
     for (int a = 0; a < nc; ++a) w += (hr[a] * hr[a] + hi[a] * hi[a]) / psd[(int64_t)a * g->K + k];
@@ -423,6 +508,16 @@ static void boundaries(const src_t* s, const orc_model* m, const orc_grid* g, co
     free(xs);
 }
 
+/* Channels each response model produces: none 1, low-frequency 2 (A, E),
+ * full 2 (A, E) or 3 (A, E, T). */
+static int channels_ok(const orc_model* m, const orc_grid* g)
+{
+    if (m->response == 0) return g->n_chan == 1;
+    if (m->response == 1) return g->n_chan == 2;
+    if (m->response == 2) return g->n_chan == 2 || g->n_chan == 3;
+    return 0;
+}
+
 /* ---- exported: statistic ---------------------------------------------- */
 
 /* Upsilon_N for P particles.
@@ -441,7 +536,7 @@ int orc_evaluate(const orc_grid* g, const orc_model* m, const double* d_ri, cons
                  int32_t n_threads)
 {
     if (N < 1 || G < 1 || P < 0) return -1;
-    if ((m->response == 0 && g->n_chan != 1) || (m->response == 1 && g->n_chan != 2)) return -2;
+    if (!channels_ok(m, g)) return -2;
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
 #else
@@ -469,7 +564,7 @@ int orc_evaluate(const orc_grid* g, const orc_model* m, const double* d_ri, cons
         for (int n = 0; n < N; ++n) {
             ld zr = 0.0L, zi = 0.0L, hh = 0.0L;
             for (int64_t k = b[n]; k < b[n + 1]; ++k) {
-                double hr[2], hi[2];
+                double hr[3], hi[3];
                 const int nc = template_bin(&s, m, g, k, hr, hi);
                 for (int a = 0; a < nc; ++a) {
                     const double S = psd[(int64_t)a * g->K + k];
@@ -506,13 +601,14 @@ int orc_evaluate(const orc_grid* g, const orc_model* m, const double* d_ri, cons
 int orc_template(const orc_grid* g, const orc_model* m, const double* theta, double* h_ri)
 {
     src_t s;
+    if (!channels_ok(m, g)) return -2;
     make_source(theta, m, &s);
     memset(h_ri, 0, sizeof(double) * 2 * (size_t)g->n_chan * (size_t)g->K);
     if (!s.valid) return -1;
     int64_t klo, khi;
     support(&s, m, g, theta[TH_FLOW], &klo, &khi);
     for (int64_t k = klo; k < khi; ++k) {
-        double hr[2], hi[2];
+        double hr[3], hi[3];
         const int nc = template_bin(&s, m, g, k, hr, hi);
         for (int a = 0; a < nc; ++a) {
             h_ri[((int64_t)a * g->K + k) * 2] = hr[a];
@@ -598,6 +694,22 @@ int orc_response(const orc_model* m, const double* theta, double t, double* F, d
         }
         tchan[0] = contract(D, s.eplus);
         tchan[1] = contract(D, s.ecross);
+    }
+    return 0;
+}
+
+/* Full-response transfer functions R [3][2] (A, E, T as real, imaginary) at
+ * frequency f and time t, for pins. */
+int orc_fd_transfer(const orc_model* m, const double* theta, double f, double t, double* R)
+{
+    src_t s;
+    make_source(theta, m, &s);
+    if (!s.valid) return -1;
+    double complex r[3];
+    fd_transfer(&s, m, f, t, 3, r);
+    for (int a = 0; a < 3; ++a) {
+        R[2 * a] = creal(r[a]);
+        R[2 * a + 1] = cimag(r[a]);
     }
     return 0;
 }

@@ -61,6 +61,25 @@ def lisa_pn(f, L=2.5e9, s_oms=15e-12, s_acc=3e-15):
     return p_oms / L ** 2 + 2.0 * (1.0 + np.cos(f / fstar) ** 2) * p_acc / ((2 * math.pi * f) ** 4 * L ** 2)
 
 
+def lisa_tdi_psd(f, L=2.5e9, s_oms=15e-12, s_acc=3e-15):
+    """Noise PSDs [3, len(f)] of the A, E and T channels of first-generation
+    TDI on an equal-arm constellation (uncorrelated optical-metrology noise on
+    each of the six links, acceleration noise on each of the six test masses,
+    the same two-component levels as ``lisa_pn``), in fractional frequency
+    S_A = S_E = 8 sin^2 x [(2 + cos x) S_oms + 2 (3 + 2 cos x + cos 2x) S_acc],
+    S_T = 32 sin^2 x sin^2(x/2) [S_oms + 4 sin^2(x/2) S_acc], x = 2 pi f L / c,
+    then divided by 16 x^4: the normalisation of the full response's
+    channels (TDI / (4 x^2)), under which A and E tend to 1.5 P_n at low f."""
+    f = np.asarray(f, dtype=np.float64)
+    c = 299792458.0
+    x = 2 * math.pi * f * L / c
+    oms = s_oms ** 2 * (2 * math.pi * f / c) ** 2 * (1.0 + (2e-3 / f) ** 4)
+    acc = s_acc ** 2 / (2 * math.pi * f * c) ** 2 * (1.0 + (0.4e-3 / f) ** 2) * (1.0 + (f / 8e-3) ** 4)
+    sa = 8 * np.sin(x) ** 2 * ((2 + np.cos(x)) * oms + 2 * (3 + 2 * np.cos(x) + np.cos(2 * x)) * acc)
+    st = 32 * np.sin(x) ** 2 * np.sin(x / 2) ** 2 * (oms + 4 * np.sin(x / 2) ** 2 * acc)
+    return np.stack([sa, sa, st]) / (16 * x ** 4)
+
+
 @dataclass
 class GridSpec:
     K: int

@@ -68,17 +68,22 @@ def white16k(seed=None, noise=True):
                 w.seed if seed is None else seed, noise, w.prior_lo, w.prior_hi)
 
 
-def lisa_small(K=20000, df=1e-7, f_min=0.017, pn_order=7, snr=17.0, seed=21, noise=True, t_obs=None):
+def lisa_small(K=20000, df=1e-7, f_min=0.017, pn_order=7, snr=17.0, seed=21, noise=True, t_obs=None,
+               response=O.RESP_LISA_LF_AE, n_chan=2):
     """A+E low-frequency response on a short band around the GW150914-like
     source: f in [0.017, 0.019) Hz at df = 1e-7 Hz (T_obs = 1e7 s), so that the
-    observation window covers a few thousand bins."""
+    observation window covers a few thousand bins.  With the full response,
+    A+E (n_chan 2) or A+E+T (n_chan 3) and the TDI noise PSDs."""
     k0 = int(round(f_min / df))
-    grid = O.Grid(K, k0, df, 2)
-    model = O.Model(pn_order=pn_order, response=O.RESP_LISA_LF_AE, support=O.SUPPORT_TOBS,
+    grid = O.Grid(K, k0, df, n_chan)
+    model = O.Model(pn_order=pn_order, response=response, support=O.SUPPORT_TOBS,
                     t_obs=(1.0 / df) if t_obs is None else t_obs)
     f = (k0 + np.arange(K)) * df
-    s = 1.5 * synth.lisa_pn(f)
-    psd = np.stack([s, s])
+    if response == O.RESP_LISA_FD:
+        psd = synth.lisa_tdi_psd(f)[:n_chan]
+    else:
+        s = 1.5 * synth.lisa_pn(f)
+        psd = np.stack([s, s])
     return make(grid, model, psd, synth.GW150914_LIKE, snr, seed, noise,
                 synth.GW150914_PRIOR_LO, synth.GW150914_PRIOR_HI)
 

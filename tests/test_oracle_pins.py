@@ -135,7 +135,9 @@ def test_upsilon1_is_phase_maximised_matched_filter():
 def test_noise_free_injection_gives_rho_squared():
     """d = h(theta*): every segment term equals [h|h]_n, so Upsilon_N = rho^2
     for every N and every segmentation."""
-    for ds in (D.white_small(K=2048, noise=False, snr=20.0), D.lisa_small(noise=False, snr=17.0)):
+    for ds in (D.white_small(K=2048, noise=False, snr=20.0), D.lisa_small(noise=False, snr=17.0),
+               D.lisa_small(noise=False, snr=17.0, response=O.RESP_LISA_FD),
+               D.lisa_small(noise=False, snr=17.0, response=O.RESP_LISA_FD, n_chan=3)):
         for N in (1, 5, 32):
             for mode in (O.SEG_EQUAL_SNR, O.SEG_UNIFORM):
                 u = _ups(ds, ds.injection, N, mode=mode, G=16)["ups"][0]
@@ -155,16 +157,36 @@ def test_scale_and_phase_invariance():
     assert np.allclose(scaled, base * abs(c) ** 2, rtol=1e-12, atol=0)
 
 
-def test_polarisation_period_quarter_turn():
+@pytest.mark.parametrize("response,n_chan", [(O.RESP_LISA_LF_AE, 2), (O.RESP_LISA_FD, 2), (O.RESP_LISA_FD, 3)])
+def test_polarisation_period_quarter_turn(response, n_chan):
     """psi -> psi + pi/2 flips the sign of both polarisation tensors, i.e. of
     the whole template, which the statistic cannot see."""
-    ds = D.lisa_small(seed=12)
+    ds = D.lisa_small(seed=12, response=response, n_chan=n_chan)
     th = D.lisa_particles(5, seed=13)
     th2 = th.copy()
     th2[:, 6] += np.pi / 2
     a = _ups(ds, th, 8, G=32)["ups"]
     b = _ups(ds, th2, 8, G=32)["ups"]
     assert np.allclose(a, b, rtol=1e-11, atol=0)
+
+
+def test_full_response_t_channel_adds_its_own_terms():
+    """With A, E and T the per-segment sums are those of A+E plus those of T
+    alone (the channels add inside each segment at fixed edges)."""
+    ds3 = D.lisa_small(seed=16, response=O.RESP_LISA_FD, n_chan=3)
+    th = D.lisa_particles(4, seed=17)
+    th[0] = ds3.injection
+    edges = np.linspace(ds3.grid.K // 4, ds3.grid.K, 9).astype(np.int64)
+    full = O.evaluate(ds3.grid, ds3.model, ds3.d_ri, ds3.psd, th, 8, O.SEG_EXPLICIT, 1, edges, want_seg=True)
+    h = [O.template(ds3.grid, ds3.model, t) for t in th]
+    for p in range(th.shape[0]):
+        for n in range(8):
+            sl = slice(max(edges[n], full["support"][p][0]), min(edges[n + 1], full["support"][p][1]))
+            z = np.sum(ds3.d[:, sl] * np.conj(h[p][:, sl]) / ds3.psd[:, sl], axis=1)
+            hh = np.sum(np.abs(h[p][:, sl]) ** 2 / ds3.psd[:, sl], axis=1)
+            assert abs(complex(*full["seg"][p, n, :2]) - z.sum()) <= 1e-12 * np.sqrt(hh.sum() * np.sum(
+                np.abs(ds3.d[:, sl]) ** 2 / ds3.psd[:, sl]))
+            assert abs(full["seg"][p, n, 2] - hh.sum()) <= 1e-12 * hh.sum()
 
 
 def test_cauchy_schwarz_bound():
@@ -516,7 +538,9 @@ def test_likelihood_noise_free_injection_is_zero():
     the coherent log L (eqn:LogL_coherent) and, for every N, the semi-coherent
     log hat L_N are exactly zero (d - A h = 0; every segment's phase is already
     right).  <h|h> against a direct sum over the template's bins."""
-    for ds in (D.white_small(K=2048, noise=False, snr=20.0), D.lisa_small(noise=False, snr=17.0)):
+    for ds in (D.white_small(K=2048, noise=False, snr=20.0), D.lisa_small(noise=False, snr=17.0),
+               D.lisa_small(noise=False, snr=17.0, response=O.RESP_LISA_FD),
+               D.lisa_small(noise=False, snr=17.0, response=O.RESP_LISA_FD, n_chan=3)):
         h = O.template(ds.grid, ds.model, ds.injection)
         hh_bf = D.inner(ds.grid, ds.psd, h, h)
         amp = ds.snr / math.sqrt(hh_bf)
