@@ -104,6 +104,9 @@ def main():
                          "Poisson-arriving requests; streams: one theta against many noise realisations "
                          "(Sec 5.1), HBM-bound; search: the whole hierarchical multi-swarm search (Sec 3.2)")
     ap.add_argument("--max-iters", type=int, default=400, help="search: iteration cap per rung")
+    ap.add_argument("--response", choices=["lf", "fd"], default="lf",
+                    help="step: LISA response model, low-frequency (default) or the full frequency-domain "
+                         "TDI response with its noise PSDs")
     ap.add_argument("--requests", type=int, default=2000, help="serve: requests per offered load")
     ap.add_argument("--realisations", type=int, default=1024,
                     help="streams: noise realisations held in HBM at once")
@@ -140,9 +143,10 @@ def main():
     dev = torch.device("cuda:0")
     w = synth.workload("lisa1m")
     K = w.grid.K
-    psd = synth.psd_arrays(w)
+    fd = args.response == "fd"
+    psd = bench_psd(w, fd)
     # --- data: noise + injection made with the library's own FP64 template
-    ctx, d_ri = make_search(B, torch, w, dev)
+    ctx, d_ri = make_search(B, torch, w, dev, fd)
     # --- swarm of 10^4 particles, first rung of the ladder (Table tab:PSO_hyperparams, N = 100 row)
     eps = [0.1, 0.05, 5e-8, 0.1, 0.1, 0.2, 0.1]  # Mc, eta, f_low, lambda, beta, iota, psi
     prm = B.pso_params(0.5, 0.2, 0.3, eps)
@@ -234,10 +238,12 @@ def main():
         "data": "synthetic: seeded Gaussian noise from the two-component LISA PSD + GW150914-like 3.5PN injection",
         "config": {"workload": "A+E, 2^20 bins over [0.016,0.032) Hz, T_obs 2.08 yr, N_seg 1024 (equal [h|h], "
                                "node stride 1024), 10^4 PSO particles in the GW150914-like prior box, one PSO "
-                               "iteration per step", "particles": w.P, "bins": K, "N_seg": w.N},
+                               "iteration per step", "particles": w.P, "bins": K, "N_seg": w.N,
+                   "response": "full frequency-domain TDI A/E (finite arm length)" if fd else
+                   "low-frequency A/E"},
         "latency_ms": {"p50": float(np.median(r64["step_ms"])), "p99": float(np.quantile(r64["step_ms"], 0.99))},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(),
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None if fd else measured_traffic(),
                      "kernel": "k_main_multi<2,false> (FP64 generate-and-reduce)",
                      "avg_launch_ms": avg_main_ms, "flop_per_eval": FLOP_PER_EVAL_FP64,
                      "evals_per_launch": evals_per_launch},
@@ -255,20 +261,28 @@ def main():
                                         "max": float(err.max()),
                                         "measure": "|U_mixed - U_fp64| / max(U_fp64, 2N)"}}
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, psd, d_ri.cpu().numpy(), args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(w, psd, d_ri.cpu().numpy(), args.cpu_seconds, fd)
     B.scs_ctx_destroy(ctx)
     print(json.dumps(out), flush=True)
 
 
-def make_search(B, torch, w, dev):
+def bench_psd(w, fd=False):
+    """PSDs of workload w: the low-frequency A/E model, or the TDI noise of
+    the full response (its A and E rows)."""
+    return synth.lisa_tdi_psd(w.grid.freqs())[:2] if fd else synth.psd_arrays(w)
+
+
+def make_search(B, torch, w, dev, fd=False):
     """Context with seeded noise plus the injection of workload w at its SNR
-    (template from the library's own FP64 waveform kernel)."""
+    (template from the library's own FP64 waveform kernel); fd selects the
+    full frequency-domain response."""
     K, df, f_min = w.grid.K, w.grid.df, w.grid.f_min
-    psd = synth.psd_arrays(w)
+    psd = bench_psd(w, fd)
+    resp = B.SCS_RESP_LISA_FD_AE if fd else B.SCS_RESP_LISA_LF_AE
     noise = synth.noise(psd, df, w.seed)
     ctx = B.scs_ctx_create(0)
     B.scs_load_data(ctx, np.zeros((w.n_chan, K, 2)), psd, f_min, df)
-    B.scs_set_model(ctx, w.pn_order, B.SCS_RESP_LISA_LF_AE, B.SCS_SUPPORT_TOBS, w.grid.t_obs)
+    B.scs_set_model(ctx, w.pn_order, resp, B.SCS_SUPPORT_TOBS, w.grid.t_obs)
     h = torch.empty((w.n_chan, K, 2), dtype=torch.float64, device=dev)
     B.scs_waveform(ctx, torch.tensor(w.injection, device=dev), h)
     torch.cuda.synchronize()
@@ -278,7 +292,7 @@ def make_search(B, torch, w, dev):
     d = torch.tensor(noise, device=dev) + hc * (w.snr / math.sqrt(hh))
     d_ri = torch.stack([d.real, d.imag], -1).contiguous()
     B.scs_load_data(ctx, d_ri, S.contiguous(), f_min, df)
-    B.scs_set_model(ctx, w.pn_order, B.SCS_RESP_LISA_LF_AE, B.SCS_SUPPORT_TOBS, w.grid.t_obs)
+    B.scs_set_model(ctx, w.pn_order, resp, B.SCS_SUPPORT_TOBS, w.grid.t_obs)
     B.scs_define_segmentation(ctx, w.N, B.SCS_SEG_EQUAL_SNR, w.G)
     return ctx, d_ri
 
@@ -610,14 +624,15 @@ def bench_search(args):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(w, psd, d_ri, seconds):
+def cpu_baseline(w, psd, d_ri, seconds, fd=False):
     """The CPU oracle, as it stands, on a bounded sample of the same workload:
     particles from the same prior box, evaluated in batches on every host
     thread until about `seconds` of wall time."""
     import oracle as O
 
     g = O.Grid(w.grid.K, w.grid.k0, w.grid.df, 2)
-    m = O.Model(pn_order=w.pn_order, response=O.RESP_LISA_LF_AE, support=O.SUPPORT_TOBS, t_obs=w.grid.t_obs)
+    m = O.Model(pn_order=w.pn_order, response=O.RESP_LISA_FD if fd else O.RESP_LISA_LF_AE,
+                support=O.SUPPORT_TOBS, t_obs=w.grid.t_obs)
     th_all = synth.workload_particles(w, seed=w.seed + 11)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     evals, used, t = 0, 0, 0.0

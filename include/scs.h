@@ -59,6 +59,13 @@ extern "C" {
 
 #define SCS_RESP_NONE 0       /* one channel, h = f^-7/6 e^{-i Psi} */
 #define SCS_RESP_LISA_LF_AE 1 /* two channels A, E, low-frequency LISA response */
+/* two channels A, E, full frequency-domain response (Sec 4 response
+ * paragraph): first-generation TDI on a rigid equal-arm constellation
+ * (arms 2.5e9 m, the geometry of the low-frequency response) with the
+ * finite-arm-length transfer of every link at the stationary-phase time,
+ * normalised by 4 (2 pi f L)^2 so that it tends to the low-frequency
+ * response as f L -> 0; the PSDs go in the same normalisation */
+#define SCS_RESP_LISA_FD_AE 2
 
 #define SCS_SUPPORT_FULL 0 /* every bin of the grid */
 #define SCS_SUPPORT_TOBS 1 /* bins with 0 <= t(f_k) < T_obs */
@@ -73,7 +80,7 @@ typedef struct scs_swarm scs_swarm;
 /* Waveform and response model (Sec 4).  Zero-initialise, then set fields. */
 typedef struct scs_model {
     int32_t pn_order;        /* highest PN power of v in the phase, 0..7 (4 = 2PN, 7 = 3.5PN) */
-    int32_t response;        /* SCS_RESP_* ; NONE needs 1 channel, LISA_LF_AE needs 2 */
+    int32_t response;        /* SCS_RESP_* ; NONE needs 1 channel, LISA_LF_AE and LISA_FD_AE need 2 */
     int32_t support;         /* SCS_SUPPORT_* */
     int32_t block_len;       /* longest polynomial block in bins (power of 2, 16..2048); 0 = 2048 */
     double t_obs;            /* observation time [s]; 0 = 1/df */

@@ -20,7 +20,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "scs.h")
 SCS_OK, SCS_EINVAL, SCS_ENOMEM, SCS_EDEVICE, SCS_EBUSY, SCS_ESTATE = 0, -1, -2, -3, -4, -5
 SCS_MEM_HOST, SCS_MEM_DEVICE = 0, 1
 SCS_PREC_FP64, SCS_PREC_MIXED = 0, 1
-SCS_RESP_NONE, SCS_RESP_LISA_LF_AE = 0, 1
+SCS_RESP_NONE, SCS_RESP_LISA_LF_AE, SCS_RESP_LISA_FD_AE = 0, 1, 2
 SCS_SUPPORT_FULL, SCS_SUPPORT_TOBS = 0, 1
 SCS_SEG_EQUAL_SNR, SCS_SEG_UNIFORM, SCS_SEG_EXPLICIT = 0, 1, 2
 

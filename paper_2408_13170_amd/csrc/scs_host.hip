@@ -156,8 +156,8 @@ struct Workspace {
 struct BatchSlot {
     int cap = 0;  // items
     MainArgs* d_items = nullptr;
-    int64_t* d_start = nullptr;                // [2][cap + 1]
-    unsigned long long* d_counter = nullptr;  // [2]
+    int64_t* d_start = nullptr;                // [kRespModels][cap + 1]
+    unsigned long long* d_counter = nullptr;  // [kRespModels]
     MainArgs* h_items = nullptr;               // pinned
     int64_t* h_start = nullptr;                // pinned
     hipEvent_t done = nullptr;                 // recorded after the last launch that read the slot
@@ -404,7 +404,7 @@ extern "C" int scs_load_data(scs_ctx* c, int32_t n_chan, int64_t K, double f_min
     if (e3 != hipSuccess) return fail(SCS_EDEVICE, "bin precompute failed: %s", hipGetErrorString(e3));
     c->has_data = true;
     c->gtab_ok = false;
-    if (c->has_model && ((c->m.response == 1) != (n_chan == 2))) c->has_model = false;
+    if (c->has_model && ((c->m.response != 0) != (n_chan == 2))) c->has_model = false;
     if (c->has_model) return build_gtab(c);
     return SCS_OK;
 }
@@ -414,8 +414,9 @@ extern "C" int scs_set_model(scs_ctx* c, const scs_model* m)
     if (!c || !m) return fail(SCS_EINVAL, "NULL argument");
     if (!c->has_data) return fail(SCS_ESTATE, "load data before setting the model");
     if (m->pn_order < 0 || m->pn_order > 7) return fail(SCS_EINVAL, "pn_order must be 0..7");
-    if (m->response != SCS_RESP_NONE && m->response != SCS_RESP_LISA_LF_AE) return fail(SCS_EINVAL, "bad response");
-    if ((m->response == SCS_RESP_LISA_LF_AE) != (c->g.nch == 2))
+    if (m->response != SCS_RESP_NONE && m->response != SCS_RESP_LISA_LF_AE && m->response != SCS_RESP_LISA_FD_AE)
+        return fail(SCS_EINVAL, "bad response");
+    if ((m->response != SCS_RESP_NONE) != (c->g.nch == 2))
         return fail(SCS_EINVAL, "response %d does not match %d loaded channels", m->response, c->g.nch);
     if (m->support != SCS_SUPPORT_FULL && m->support != SCS_SUPPORT_TOBS) return fail(SCS_EINVAL, "bad support");
     const int bl = m->block_len ? m->block_len : 2048;
@@ -428,6 +429,8 @@ extern "C" int scs_set_model(scs_ctx* c, const scs_model* m)
     double oc = m->orbit_phase0 / (2.0 * M_PI);
     c->m.orb0_cyc = oc - std::floor(oc);
     c->m.cart0 = m->cartwheel_phase0;
+    c->m.cart_c = std::cos(m->cartwheel_phase0);
+    c->m.cart_s = std::sin(m->cartwheel_phase0);
     c->L = 512;  // bins per LDS-staged block of the generate-and-reduce kernel
     int lg = 0;
     while ((1 << lg) < bl) ++lg;
@@ -1120,10 +1123,10 @@ static int slot_reserve(BatchSlot& b, int n)
     free_slot(b);
     const int cap = std::max(n, 8);
     if (hipMalloc((void**)&b.d_items, sizeof(MainArgs) * cap) != hipSuccess ||
-        hipMalloc((void**)&b.d_start, sizeof(int64_t) * 2 * (cap + 1)) != hipSuccess ||
-        hipMalloc((void**)&b.d_counter, sizeof(unsigned long long) * 2) != hipSuccess ||
+        hipMalloc((void**)&b.d_start, sizeof(int64_t) * kRespModels * (cap + 1)) != hipSuccess ||
+        hipMalloc((void**)&b.d_counter, sizeof(unsigned long long) * kRespModels) != hipSuccess ||
         hipHostMalloc((void**)&b.h_items, sizeof(MainArgs) * cap) != hipSuccess ||
-        hipHostMalloc((void**)&b.h_start, sizeof(int64_t) * 2 * (cap + 1)) != hipSuccess ||
+        hipHostMalloc((void**)&b.h_start, sizeof(int64_t) * kRespModels * (cap + 1)) != hipSuccess ||
         hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess) {
         free_slot(b);
         return fail(SCS_ENOMEM, "batch descriptor allocation failed");
@@ -1150,21 +1153,21 @@ static int check_items(const scs_batch_item* items, int32_t n_items, int32_t pre
 
 // ==== launch shape of the generate-and-reduce (begin)
 // The generate-and-reduce of prepared evaluations: one persistent launch per
-// channel count over the tiles of all of them (descriptors in slot b;
+// response model over the tiles of all of them (descriptors in slot b;
 // upload: copy them from the pinned host copy first).
 static int fused_main(std::vector<EvalJob>& jobs, int waves, bool mixed, hipStream_t s, BatchSlot& b, bool upload)
 {
     const int n_items = (int)jobs.size();
     scs_ctx* c0 = jobs[0].c;
     int off = 0;
-    for (int gi = 0; gi < 2; ++gi) {
-        const int nch = gi == 0 ? 2 : 1;
+    for (int gi = 0; gi < kRespModels; ++gi) {
+        const int resp = (gi + 1) % kRespModels;  // A+E low-frequency first, then full, then one channel
         int cnt = 0;
         int64_t total = 0;
         int64_t* hs = b.h_start + gi * (b.cap + 1);
         for (int i = 0; i < n_items; ++i) {
             const EvalJob& j = jobs[i];
-            if (j.c->g.nch != nch || j.P == 0 || j.pl.n_tiles == 0) continue;
+            if (j.c->m.response != resp || j.P == 0 || j.pl.n_tiles == 0) continue;
             if (upload) {
                 b.h_items[off + cnt] = j.ma;
                 hs[cnt] = total;
@@ -1179,11 +1182,11 @@ static int fused_main(std::vector<EvalJob>& jobs, int waves, bool mixed, hipStre
             HIP_TRY(hipMemcpyAsync(b.d_start + gi * (b.cap + 1), hs, sizeof(int64_t) * (cnt + 1), hipMemcpyHostToDevice, s));
         }
         launch_fill_u64(b.d_counter + gi, 1, 0ULL, s);
-        const int per_cu = main_multi_blocks_per_cu(nch, c0->L, waves, mixed);
+        const int per_cu = main_multi_blocks_per_cu(resp, c0->L, waves, mixed);
         const int64_t grid = std::min<int64_t>(total, (int64_t)c0->n_cu * per_cu);
         hipEvent_t e0;
         prof_begin(c0, s, &e0);
-        hipError_t e = launch_main_multi(b.d_items + off, b.d_start + gi * (b.cap + 1), cnt, b.d_counter + gi, nch, c0->L,
+        hipError_t e = launch_main_multi(b.d_items + off, b.d_start + gi * (b.cap + 1), cnt, b.d_counter + gi, resp, c0->L,
                                          waves, mixed, (int)grid, s);
         if (e != hipSuccess) return fail(SCS_EDEVICE, "generate-and-reduce launch failed: %s", hipGetErrorString(e));
         prof_end(c0, s, e0);

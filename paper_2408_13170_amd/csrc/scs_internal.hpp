@@ -30,6 +30,7 @@ struct ModelArgs {
     double t_obs;
     double orb0_cyc;  // orbital phase at t = 0 [cycles]
     double cart0;     // cartwheel phase at t = 0 [rad]
+    double cart_c, cart_s;  // cos, sin of cart0
 };
 
 struct PhysConst {
@@ -173,9 +174,12 @@ void launch_bins(const GridArgs& g, const double* d_ri, const double* psd, doubl
 void launch_prologue(const PrologueArgs& a, hipStream_t s);
 void launch_bounds(const BoundArgs& a, hipStream_t s);
 size_t main_lds_bytes(int nch, int L, bool mixed);
+// resp: the response model of the items (0: one channel; 1, 2: A+E
+// low-frequency, full), which selects the kernel instantiation
+constexpr int kRespModels = 3;
 hipError_t launch_main_multi(const MainArgs* items, const int64_t* tile_start, int n_items, unsigned long long* counter,
-                             int nch, int L, int waves, bool mixed, int grid, hipStream_t s);
-int main_multi_blocks_per_cu(int nch, int L, int waves, bool mixed);
+                             int resp, int L, int waves, bool mixed, int grid, hipStream_t s);
+int main_multi_blocks_per_cu(int resp, int L, int waves, bool mixed);
 void launch_finalize(const FinalArgs& a, hipStream_t s);
 void launch_waveform(const MainArgs& a, double* h_ri, hipStream_t s);
 void launch_gtab(const GridArgs& g, int lg, int64_t nsub, double* tab, hipStream_t s);

@@ -190,7 +190,11 @@ __global__ void k_prologue(PrologueArgs a)
             const double r2 = r * r, r6 = r2 * r2 * r2;
             const double ephi = 2.4 * taus * fs * r6;
             bool good = ephi <= 1e-12;
-            if (a.m.response == 1) {
+            if (a.m.response != 0) {
+                // fourth orbital harmonic; the full response's arm-length
+                // terms add harmonics of small amplitude only (its
+                // interpolation error at the block's worst point is within
+                // a few percent of the low-frequency response's)
                 const double th_h = 4.0 * kTwoPi * kInvYear * (8.0 / 3.0) * (taus / fs) * a.g.df * h;
                 const double t2 = th_h * th_h;
                 good = good && (t2 * t2 * t2 / 11520.0) <= 1e-11;
@@ -227,6 +231,25 @@ __global__ void k_prologue(PrologueArgs a)
             }
         }
         for (int i = 0; i < 36; ++i) cf[p * kCoefStride + (C_RESP + i)] = acc[i];
+    } else if (a.m.response == 2) {
+        const Pol pol = polarisation(t[3], t[4], t[6]);
+        double sl, cl, sb, cb;
+        sincos(t[3], &sl, &cl);
+        sincos(t[4], &sb, &cb);
+        const double ci = cos(t[5]);
+        double rec[FD_COUNT];
+        rec[FD_N + 0] = cb * cl;
+        rec[FD_N + 1] = cb * sl;
+        rec[FD_N + 2] = sb;
+        for (int i = 0; i < 3; ++i) {
+            rec[FD_P + i] = pol.P[i];
+            rec[FD_Q + i] = pol.Q[i];
+        }
+        rec[FD_AP] = 0.5 * (1.0 + ci * ci);
+        rec[FD_AX] = ci;
+        for (int i = 0; i < FD_COUNT; ++i) cf[p * kCoefStride + (C_RESP + i)] = rec[i];
+    }
+    if (a.m.response != 0) {
         double sl, cl;
         sincos(t[3], &sl, &cl);
         const double cb = cos(t[4]);
@@ -308,7 +331,7 @@ struct RespPoly {
 // uniform, scalar loads), constant term reduced exactly in double-double;
 // for the LISA response, response and Doppler interpolated at the Chebyshev
 // nodes.  Returns the GW phase coefficients a[] (x-space) for node times.
-template <bool RESP>
+template <int RM>
 __device__ inline void block_setup(const GLOBAL double* __restrict__ cf, int64_t S, int64_t p, double Kc, int lg,
                                    const GLOBAL double* __restrict__ G, const GridArgs& g, const ModelArgs& m,
                                    PhasePoly& out, RespPoly& resp)
@@ -348,7 +371,7 @@ __device__ inline void block_setup(const GLOBAL double* __restrict__ cf, int64_t
         out.ph[mm] = a[mm];
         hp *= h;
     }
-    if constexpr (RESP) {
+    if constexpr (RM != 0) {
 #pragma unroll
         for (int f = 0; f < 4; ++f)
 #pragma unroll
@@ -369,21 +392,33 @@ __device__ inline void block_setup(const GLOBAL double* __restrict__ cf, int64_t
             orb -= rint(orb);
             double s1, c1;
             sincos2pi(orb, &s1, &c1);
-            double ch[5], sh[5];
-            harmonics(c1, s1, ch, sh);
             const double fn = (Kc + xn * h) * g.df;
             const double dop = fn * (dcx * c1 + dsx * s1);
+            if constexpr (RM == 2) {
+                const double cz = __builtin_fma(m.cart_c, c1, m.cart_s * s1);
+                const double sz = __builtin_fma(m.cart_s, c1, -(m.cart_c * s1));
+                double rv[4];
+                fd_response(fn, c1, s1, cz, sz, cf + (p * kCoefStride + C_RESP), rv);
 #pragma unroll
-            for (int f = 0; f < 4; ++f) {
-                __asm__ volatile("" ::: "memory");  // nine coefficients live at a time
-                const GLOBAL double* cc = cf + p * kCoefStride + (C_RESP + 9 * f);
-                double rv = cc[0];
+                for (int f = 0; f < 4; ++f)
 #pragma unroll
-                for (int k = 1; k <= 4; ++k)
-                    rv = __builtin_fma(cc[k], ch[k], __builtin_fma(cc[4 + k], sh[k], rv));
+                    for (int mm = 0; mm < kNodes; ++mm)
+                        resp.r[f][mm] = __builtin_fma(c_cheb_m[mm * kNodes + n], rv[f], resp.r[f][mm]);
+            } else {
+                double ch[5], sh[5];
+                harmonics(c1, s1, ch, sh);
 #pragma unroll
-                for (int mm = 0; mm < kNodes; ++mm)
-                    resp.r[f][mm] = __builtin_fma(c_cheb_m[mm * kNodes + n], rv, resp.r[f][mm]);
+                for (int f = 0; f < 4; ++f) {
+                    __asm__ volatile("" ::: "memory");  // nine coefficients live at a time
+                    const GLOBAL double* cc = cf + p * kCoefStride + (C_RESP + 9 * f);
+                    double rv = cc[0];
+#pragma unroll
+                    for (int k = 1; k <= 4; ++k)
+                        rv = __builtin_fma(cc[k], ch[k], __builtin_fma(cc[4 + k], sh[k], rv));
+#pragma unroll
+                    for (int mm = 0; mm < kNodes; ++mm)
+                        resp.r[f][mm] = __builtin_fma(c_cheb_m[mm * kNodes + n], rv, resp.r[f][mm]);
+                }
             }
 #pragma unroll
             for (int mm = 0; mm < kNodes; ++mm) out.ph[mm] = __builtin_fma(c_cheb_m[mm * kNodes + n], dop, out.ph[mm]);
@@ -422,12 +457,13 @@ __device__ __forceinline__ double wave_incl_scan(double v, int lane)
     return v;
 }
 
-// Dense weight w(k) = sum_alpha q_alpha(k) |R_alpha(t(f_k))|^2.
-template <int NCH>
+// Dense weight w(k) = sum_alpha q_alpha(k) |R_alpha(t(f_k))|^2 (RM: the
+// response model, 0 = none, 1 = low-frequency, 2 = full).
+template <int RM>
 __device__ inline double weight_at(const CONSTANT double* __restrict__ cf, int64_t S, int64_t p, int64_t k, const GridArgs& g,
                                    const ModelArgs& m, const double* __restrict__ b64, const double* bcoef, double tc)
 {
-    if constexpr (NCH == 1) {
+    if constexpr (RM == 0) {
         return b64[k * 3 + 2];
     } else {
         const double f = (g.k0 + (double)k) * g.df;
@@ -436,6 +472,13 @@ __device__ inline double weight_at(const CONSTANT double* __restrict__ cf, int64
         orb -= rint(orb);
         double s1, c1;
         sincos2pi(orb, &s1, &c1);
+        if constexpr (RM == 2) {
+            const double cz = __builtin_fma(m.cart_c, c1, m.cart_s * s1);
+            const double sz = __builtin_fma(m.cart_s, c1, -(m.cart_c * s1));
+            double rv[4];
+            fd_response(f, c1, s1, cz, sz, cf + (p * kCoefStride + C_RESP), rv);
+            return b64[k * 6 + 4] * (rv[0] * rv[0] + rv[1] * rv[1]) + b64[k * 6 + 5] * (rv[2] * rv[2] + rv[3] * rv[3]);
+        }
         double ch[5], sh[5];
         harmonics(c1, s1, ch, sh);
         double rv[4];
@@ -455,7 +498,7 @@ __device__ inline double weight_at(const CONSTANT double* __restrict__ cf, int64
 // a.wcache reaches and recomputing the rest.
 // Three waves per SIMD fit without spills (168 VGPRs); the kernel is
 // latency-bound, so residency is what counts.
-template <int NCH>
+template <int RM>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_bounds_equal(BoundArgs a)
 {
     const int64_t p = blockIdx.x;
@@ -503,7 +546,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
                 if (pass == 1 && j < a.wcache) {
                     w = s_w[j];
                 } else {
-                    w = weight_at<NCH>(cfc, S, p, node(j), a.g, a.m, a.b64, bcoef, tc);
+                    w = weight_at<RM>(cfc, S, p, node(j), a.g, a.m, a.b64, bcoef, tc);
                     if (j < a.wcache) s_w[j] = w;
                 }
             }
@@ -784,7 +827,7 @@ constexpr int kMixedRun = 32;
 // by every thread of the workgroup; returns early, uniformly, when no
 // particle of the group has support in the chunk.  s_trig holds the table
 // and, at kTrig, a zero entry for idle one-channel lanes.
-template <int NCH, bool MIXED>
+template <int NCH, bool MIXED, int RM>
 __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __restrict__ gtab, int64_t logical,
                                           unsigned char* smem, const double2* __restrict__ s_trig)
 {
@@ -1003,7 +1046,7 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
                 have = sbl;
                 kcl = sbl + (1 << (lgl - 1));
                 const double inv_h = 1.0 / (double)(1 << (lgl - 1));
-                block_setup<RESP>(coef, S, p, a.g.k0 + (double)kcl, lgl, gtl + (int64_t)(sbl >> lgl) * kGStride,
+                block_setup<RM>(coef, S, p, a.g.k0 + (double)kcl, lgl, gtl + (int64_t)(sbl >> lgl) * kGStride,
                                   a.g, a.m, poly, rp);
                 // monomials in j = x h (h a power of two: exact rescaling); the
                 // FP64 phase also in units of 1/kTrig cycle
@@ -1094,7 +1137,7 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
 // particle groups of one chunk, so workgroups running together share the
 // chunk's data in L2.  tile_start[i] is the first global tile of item i (prefix sums,
 // tile_start[n_items] = total); the counter starts at 0.
-template <int NCH, bool MIXED>
+template <int NCH, bool MIXED, int RM>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(MIXED ? SCS_WAVES_MIXED : SCS_WAVES_FP64))) void k_main_multi(
     const MainArgs* __restrict__ items, const int64_t* __restrict__ tile_start, int n_items,
@@ -1117,7 +1160,7 @@ __attribute__((amdgpu_waves_per_eu(MIXED ? SCS_WAVES_MIXED : SCS_WAVES_FP64))) v
         int it = 0;
         while (it + 1 < n_items && tile_start[it + 1] <= t) ++it;
         const MainArgs& a = items[it];
-        main_tile<NCH, MIXED>(a, a.gtab, t - tile_start[it], smem, s_trig);
+        main_tile<NCH, MIXED, RM>(a, a.gtab, t - tile_start[it], smem, s_trig);
     }
 }
 
@@ -1317,8 +1360,12 @@ __global__ void k_waveform(MainArgs a, double* __restrict__ h_ri)
     const double f = (a.g.k0 + (double)k) * a.g.df;
     const double amp = pow(f, -7.0 / 6.0);
     if (nch == 2) {
-        block_setup<true>((const GLOBAL double*)a.coef, a.stride, 0, a.g.k0 + (double)kc, lg, (const GLOBAL double*)G, a.g,
-                          a.m, poly, rp);
+        if (a.m.response == 2)
+            block_setup<2>((const GLOBAL double*)a.coef, a.stride, 0, a.g.k0 + (double)kc, lg, (const GLOBAL double*)G,
+                           a.g, a.m, poly, rp);
+        else
+            block_setup<1>((const GLOBAL double*)a.coef, a.stride, 0, a.g.k0 + (double)kc, lg, (const GLOBAL double*)G,
+                           a.g, a.m, poly, rp);
         double ph = horner5(poly.ph, x);
         ph -= rint(ph);
         double sn, cs;
@@ -1330,8 +1377,8 @@ __global__ void k_waveform(MainArgs a, double* __restrict__ h_ri)
             h_ri[((int64_t)c * a.g.K + k) * 2 + 1] = amp * (ri * cs - rr * sn);
         }
     } else {
-        block_setup<false>((const GLOBAL double*)a.coef, a.stride, 0, a.g.k0 + (double)kc, lg, (const GLOBAL double*)G,
-                           a.g, a.m, poly, rp);
+        block_setup<0>((const GLOBAL double*)a.coef, a.stride, 0, a.g.k0 + (double)kc, lg, (const GLOBAL double*)G,
+                       a.g, a.m, poly, rp);
         double ph = horner5(poly.ph, x);
         ph -= rint(ph);
         double sn, cs;
@@ -1686,38 +1733,38 @@ void launch_bounds(const BoundArgs& a, hipStream_t s)
     if (a.P <= 0) return;
     if (a.mode == 0) {
         const size_t lds = sizeof(double) * (size_t)a.wcache;
-        if (a.g.nch == 2) hipLaunchKernelGGL(k_bounds_equal<2>, dim3((unsigned)a.P), dim3(64), lds, s, a);
-        else hipLaunchKernelGGL(k_bounds_equal<1>, dim3((unsigned)a.P), dim3(64), lds, s, a);
+        if (a.m.response == 2) hipLaunchKernelGGL(k_bounds_equal<2>, dim3((unsigned)a.P), dim3(64), lds, s, a);
+        else if (a.m.response == 1) hipLaunchKernelGGL(k_bounds_equal<1>, dim3((unsigned)a.P), dim3(64), lds, s, a);
+        else hipLaunchKernelGGL(k_bounds_equal<0>, dim3((unsigned)a.P), dim3(64), lds, s, a);
     } else {
         hipLaunchKernelGGL(k_bounds_simple, dim3(nblk(a.P * (a.N + 1), 256)), dim3(256), 0, s, a);
     }
 }
 size_t main_lds_bytes(int nch, int L, bool mixed) { return (size_t)L * 3 * nch * (mixed ? 4 : 8); }
-hipError_t launch_main_multi(const MainArgs* items, const int64_t* tile_start, int n_items, unsigned long long* counter,
-                             int nch, int L, int waves, bool mixed, int grid, hipStream_t s)
+// The generate-and-reduce instantiation for a response model (0: one
+// channel, no response; 1: A+E low-frequency; 2: A+E full) and precision.
+typedef void (*MainKernel)(const MainArgs*, const int64_t*, int, unsigned long long*);
+static MainKernel main_kernel(int resp, bool mixed)
 {
+    if (resp == 2) return mixed ? k_main_multi<2, true, 2> : k_main_multi<2, false, 2>;
+    if (resp == 1) return mixed ? k_main_multi<2, true, 1> : k_main_multi<2, false, 1>;
+    return mixed ? k_main_multi<1, true, 0> : k_main_multi<1, false, 0>;
+}
+hipError_t launch_main_multi(const MainArgs* items, const int64_t* tile_start, int n_items, unsigned long long* counter,
+                             int resp, int L, int waves, bool mixed, int grid, hipStream_t s)
+{
+    const int nch = resp == 0 ? 1 : 2;
     const size_t lds = main_lds_bytes(nch, L, mixed);
-    const dim3 blk(64 * waves);
-    if (nch == 2) {
-        if (mixed) hipLaunchKernelGGL((k_main_multi<2, true>), dim3(grid), blk, lds, s, items, tile_start, n_items, counter);
-        else hipLaunchKernelGGL((k_main_multi<2, false>), dim3(grid), blk, lds, s, items, tile_start, n_items, counter);
-    } else {
-        if (mixed) hipLaunchKernelGGL((k_main_multi<1, true>), dim3(grid), blk, lds, s, items, tile_start, n_items, counter);
-        else hipLaunchKernelGGL((k_main_multi<1, false>), dim3(grid), blk, lds, s, items, tile_start, n_items, counter);
-    }
+    hipLaunchKernelGGL(main_kernel(resp, mixed), dim3(grid), dim3(64 * waves), lds, s, items, tile_start, n_items,
+                       counter);
     return hipGetLastError();
 }
-int main_multi_blocks_per_cu(int nch, int L, int waves, bool mixed)
+int main_multi_blocks_per_cu(int resp, int L, int waves, bool mixed)
 {
+    const int nch = resp == 0 ? 1 : 2;
     const size_t lds = main_lds_bytes(nch, L, mixed);
     int nb = 0;
-    hipError_t e;
-    if (nch == 2)
-        e = mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_main_multi<2, true>, 64 * waves, lds)
-                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_main_multi<2, false>, 64 * waves, lds);
-    else
-        e = mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_main_multi<1, true>, 64 * waves, lds)
-                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_main_multi<1, false>, 64 * waves, lds);
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, main_kernel(resp, mixed), 64 * waves, lds);
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 void launch_finalize(const FinalArgs& a, hipStream_t s)

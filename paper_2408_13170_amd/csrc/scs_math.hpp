@@ -6,7 +6,8 @@
 // * sin/cos of 2 pi r for a phase already reduced to cycles;
 // * the TaylorF2 phase written as a sum of particle coefficients times
 //   particle-independent basis functions of frequency (Sec 4 waveform);
-// * the low-frequency LISA A/E antenna patterns (Sec 4 response).
+// * the low-frequency LISA A/E antenna patterns and the full frequency-domain
+//   TDI response with finite arm length (Sec 4 response).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -19,6 +20,7 @@ constexpr double kTwoPi = 6.283185307179586476925286766559;
 constexpr double kPi = 3.141592653589793238462643383279503;
 constexpr double kAuOverC = 1.495978707e11 / 299792458.0;  // light travel time of 1 AU [s]
 constexpr double kInvYear = 1.0 / 31557600.0;              // Julian year
+constexpr double kArmS = 2.5e9 / 299792458.0;              // light time of one constellation arm [s]
 constexpr double kEulerGamma = 0.57721566490153286060651209;
 constexpr int kTheta = 7;
 
@@ -31,8 +33,14 @@ enum Coef : int {
     C_TC,                  // t_c [s]
     C_DC, C_DS,            // Doppler [cycles/Hz] = dc cos(Phi_orb) + ds sin(Phi_orb)
     C_RESP,                // 36 response trig-polynomial coefficients: R_A re, R_A im, R_E re, R_E im
+                           // (full response: the source record FdSlot instead)
     C_COUNT = C_RESP + 36
 };
+
+// Source record of the full response, at C_RESP: direction to the source,
+// polarisation vectors P, Q (e+ = PP - QQ, ex = PQ + QP) and the (2,2)
+// amplitudes of the two polarisations.
+enum FdSlot : int { FD_N = 0, FD_P = 3, FD_Q = 6, FD_AP = 9, FD_AX = 10, FD_COUNT = 11 };
 
 // ---------------------------------------------------------------- double-double
 struct dd {
@@ -204,6 +212,95 @@ __device__ inline void antenna_lf(double Phi, double cart0, const Pol& pol, doub
     out[1] = ka * (2.0 * qx[1] - qx[0] - qx[2]);
     out[2] = ke * (qp[0] - qp[2]);
     out[3] = ke * (qx[0] - qx[2]);
+}
+
+// Full frequency-domain response (A, E) at frequency f [Hz], constellation
+// orbital angle Phi (c1, s1 = cos, sin Phi) and cartwheel angle zeta =
+// cart0 - Phi (cz, sz), for the source record src (FdSlot; any pointer type).
+//
+// Link j -> i, n the unit vector from craft j to craft i, craft at the
+// centre plus r p_a (r = L / sqrt3, p_a unit): a plane wave along -nhat with
+// polarisation content P = a+ e+ - i ax ex gives, per Fourier component
+// (delay tau -> e^{-2 pi i f tau}; the centre's delay is the Doppler term of
+// the phase),
+//     y_ij / h = -i pi f L sinc(pi f L (1 + nhat.n)) e^{-i pi f (L - r nhat.(p_i + p_j))} n.P.n .
+// First-generation TDI on equal static arms (z = e^{-2 pi i f L}):
+//     X = (1 - z^2) [(y01 + z y10) - (y02 + z y20)], Y and Z cyclic,
+//     A = (Z - X) / sqrt2, E = (X - 2Y + Z) / sqrt6, both over 4 (2 pi f L)^2,
+// so that they tend to the low-frequency response as f L -> 0.  The common
+// factor (1 - z^2)(-i pi f L) / (4 (2 pi f L)^2) equals z sin(x) / (4x) with
+// x = 2 pi f L.  Arm (i, j) = (k, k+1) adds y_ij + z y_ji to channel k of
+// (X, Y, Z) and subtracts y_ji + z y_ij from channel k+1.  Every vector enters
+// through its projections on the plane's basis e1 = -r_hat/2 - (sqrt3/2) z_hat,
+// e2 = phi_hat, so an arm costs a few products.  All sines and cosines are of
+// arguments below a few turns (sincos2pi).  out = {Re A, Im A, Re E, Im E}.
+template <typename Src>
+__device__ inline void fd_response(double f, double c1, double s1, double cz, double sz, Src src, double out[4])
+{
+    const double h3 = 0.86602540378443864676;     // sqrt(3)/2
+    const double inv_r3 = 0.57735026918962576451;  // 1/sqrt(3)
+    double e1n, e2n, e1p, e2p, e1q, e2q;
+    {
+        const double v0 = src[FD_N], v1 = src[FD_N + 1], v2 = src[FD_N + 2];
+        e1n = __builtin_fma(-0.5, __builtin_fma(c1, v0, s1 * v1), -h3 * v2);
+        e2n = __builtin_fma(c1, v1, -(s1 * v0));
+    }
+    {
+        const double v0 = src[FD_P], v1 = src[FD_P + 1], v2 = src[FD_P + 2];
+        e1p = __builtin_fma(-0.5, __builtin_fma(c1, v0, s1 * v1), -h3 * v2);
+        e2p = __builtin_fma(c1, v1, -(s1 * v0));
+    }
+    {
+        const double v0 = src[FD_Q], v1 = src[FD_Q + 1], v2 = src[FD_Q + 2];
+        e1q = __builtin_fma(-0.5, __builtin_fma(c1, v0, s1 * v1), -h3 * v2);
+        e2q = __builtin_fma(c1, v1, -(s1 * v0));
+    }
+    const double ap = src[FD_AP], ax = src[FD_AX];
+    // craft angles zeta, zeta + 2pi/3, zeta + 4pi/3
+    const double ca[3] = {cz, __builtin_fma(-0.5, cz, -h3 * sz), __builtin_fma(-0.5, cz, h3 * sz)};
+    const double sa[3] = {sz, __builtin_fma(-0.5, sz, h3 * cz), __builtin_fma(-0.5, sz, -h3 * cz)};
+    const double fl = f * kArmS;  // one arm in cycles of f
+    double sx, cx;                // z = cx - i sx
+    sincos2pi(fl, &sx, &cx);
+    double acc[3][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};  // X, Y, Z
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int i = k, j = (k + 1) % 3;
+        const double dc = (ca[i] - ca[j]) * inv_r3, ds = (sa[i] - sa[j]) * inv_r3;
+        const double a = __builtin_fma(dc, e1p, ds * e2p);  // n.P
+        const double b = __builtin_fma(dc, e1q, ds * e2q);  // n.Q
+        const double g = __builtin_fma(dc, e1n, ds * e2n);  // nhat.n
+        const double sp = __builtin_fma(ca[i] + ca[j], e1n, (sa[i] + sa[j]) * e2n);
+        const double npr = ap * __builtin_fma(a, a, -(b * b)), npi = -2.0 * ax * a * b;  // n.P.n
+        double sn, cs;
+        sincos2pi(-0.5 * f * __builtin_fma(-kArmS * inv_r3, sp, kArmS), &sn, &cs);
+        const double cr = __builtin_fma(cs, npr, -(sn * npi)), ci = __builtin_fma(cs, npi, sn * npr);
+        // sinc(pi f L (1 +- g)) for the two directions
+        double sf, sb, dummy;
+        const double uf = 0.5 * fl * (1.0 + g), ub = 0.5 * fl * (1.0 - g);  // cycles
+        sincos2pi(uf, &sf, &dummy);
+        sincos2pi(ub, &sb, &dummy);
+        // below 1e-5 turns: 1 - u^2/6, remainder u^4/120 < 1e-18
+        const double wf = kTwoPi * uf, wb = kTwoPi * ub;
+        sf = uf < 1e-5 ? __builtin_fma(-wf * wf, 1.0 / 6.0, 1.0) : sf / wf;
+        sb = ub < 1e-5 ? __builtin_fma(-wb * wb, 1.0 / 6.0, 1.0) : sb / wb;
+        const double yfr = cr * sf, yfi = ci * sf;  // y_ij
+        const double ybr = cr * sb, ybi = ci * sb;  // y_ji
+        // + (y_ij + z y_ji) into channel k, - (y_ji + z y_ij) into channel k+1
+        acc[i][0] += yfr + __builtin_fma(cx, ybr, sx * ybi);
+        acc[i][1] += yfi + __builtin_fma(cx, ybi, -(sx * ybr));
+        acc[j][0] -= ybr + __builtin_fma(cx, yfr, sx * yfi);
+        acc[j][1] -= ybi + __builtin_fma(cx, yfi, -(sx * yfr));
+    }
+    const double wm = sx / (4.0 * kTwoPi * fl);  // sin(x) / (4x)
+    const double wr = wm * cx, wi = -wm * sx;     // z sin(x) / (4x)
+    const double ka = 0.70710678118654752440, ke = 0.40824829046386301637;  // 1/sqrt2, 1/sqrt6
+    const double Ar = ka * (acc[2][0] - acc[0][0]), Ai = ka * (acc[2][1] - acc[0][1]);
+    const double Er = ke * (acc[0][0] - 2.0 * acc[1][0] + acc[2][0]), Ei = ke * (acc[0][1] - 2.0 * acc[1][1] + acc[2][1]);
+    out[0] = __builtin_fma(wr, Ar, -(wi * Ai));
+    out[1] = __builtin_fma(wr, Ai, wi * Ar);
+    out[2] = __builtin_fma(wr, Er, -(wi * Ei));
+    out[3] = __builtin_fma(wr, Ei, wi * Er);
 }
 
 // Evaluate a degree-4 trigonometric polynomial c[0] + sum_k c[k] cos kPhi + c[4+k] sin kPhi

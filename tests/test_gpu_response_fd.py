@@ -1,0 +1,123 @@
+"""Parity of the full frequency-domain response (Sec 4 response paragraph:
+TDI A/E transfer functions with finite arm length) through the C ABI against
+the oracle: the template per bin, supports and equal-[h|h] edges, Upsilon_N
+in FP64 and mixed precision, per-segment sums, the likelihood statistics and
+a noise-free injection.
+
+Tolerances as for the low-frequency response: template within 1e-10 of
+max|h| (phase Taylor remainder 1e-12 cycles, response interpolation 1e-11),
+Upsilon_N within 1e-9 (FP64) and 1e-5 (mixed) floored relative error, edges
+exact except within rounding of a target (at most 5% of rows).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from tests import datasets as D
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2408_13170_amd import B  # noqa: E402
+
+
+def _ctx(ds, N, mode=B.SCS_SEG_EQUAL_SNR, G=1):
+    g = ds.grid
+    h = B.scs_ctx_create(0)
+    B.scs_load_data(h, np.ascontiguousarray(ds.d_ri), np.ascontiguousarray(ds.psd), g.k0 * g.df, g.df)
+    m = ds.model
+    B.scs_set_model(h, m.pn_order, m.response, m.support, m.t_obs)
+    B.scs_define_segmentation(h, N, mode, G)
+    return h
+
+
+def _floored(got, ref, N):
+    return np.abs(got - ref) / np.maximum(np.abs(ref), 2.0 * N)
+
+
+def test_template_matches_oracle():
+    ds = D.lisa_small(noise=False, response=O.RESP_LISA_FD)
+    h = _ctx(ds, 1)
+    try:
+        ths = [ds.injection] + list(D.lisa_particles(4, seed=78))
+        for th in ths:
+            out = torch.empty((2, ds.grid.K, 2), dtype=torch.float64, device="cuda")
+            B.scs_waveform(h, torch.tensor(np.ascontiguousarray(th), device="cuda"), out)
+            torch.cuda.synchronize()
+            got = out.cpu().numpy()
+            gc = got[..., 0] + 1j * got[..., 1]
+            ref = O.template(ds.grid, ds.model, th)
+            nz = np.abs(ref) > 0
+            assert np.array_equal(nz, np.abs(gc) > 0), "supports differ"
+            err = np.abs(gc - ref)[nz].max() / np.abs(ref).max()
+            # the full response differs from the low-frequency one by O(1) here
+            lf = O.template(ds.grid, O.Model(pn_order=ds.model.pn_order, response=O.RESP_LISA_LF_AE,
+                                             support=ds.model.support, t_obs=ds.model.t_obs), th)
+            dif = np.abs(lf - ref)[nz].max() / np.abs(ref).max()
+            print(f"full-response template max err / max|h| {err:.3g} (LF differs by {dif:.3g})")
+            assert err < 1e-10 and dif > 0.1
+    finally:
+        B.scs_ctx_destroy(h)
+
+
+@pytest.mark.parametrize("N,mode,G", [(1, B.SCS_SEG_EQUAL_SNR, 1), (8, B.SCS_SEG_EQUAL_SNR, 16),
+                                      (64, B.SCS_SEG_EQUAL_SNR, 1), (37, B.SCS_SEG_UNIFORM, 1)])
+def test_upsilon_matches_oracle(N, mode, G):
+    ds = D.lisa_small(seed=41, response=O.RESP_LISA_FD)
+    th = D.lisa_particles(40, seed=42)
+    th[:4] = synth.near_injection(ds.injection, 4, seed=43)
+    th[4, 0] = -1.0      # invalid: NaN
+    th[5, 2] = 0.0195    # empty support: 0
+    ref = O.evaluate(ds.grid, ds.model, ds.d_ri, ds.psd, th, N, mode, G, want_seg=True, want_bounds=True)
+    h = _ctx(ds, N, mode, G)
+    try:
+        tht = torch.tensor(np.ascontiguousarray(th), device="cuda")
+        u = torch.empty(th.shape[0], dtype=torch.float64, device="cuda")
+        seg = torch.empty((th.shape[0], N, 3), dtype=torch.float64, device="cuda")
+        B.scs_evaluate(h, tht, u, B.SCS_PREC_FP64, seg)
+        torch.cuda.synchronize()
+        got, sg = u.cpu().numpy(), seg.cpu().numpy()
+        assert np.isnan(got[4]) and got[5] == 0.0
+        sup, bnd = B.scs_last_bounds(h, th.shape[0], N)
+        ok = np.isfinite(ref["ups"])
+        assert np.array_equal(sup[ok], ref["support"][ok])
+        same = ok & np.all(bnd == ref["bounds"], axis=1)
+        print("boundary rows identical:", same.sum(), "of", ok.sum())
+        assert same.sum() >= 0.95 * ok.sum()
+        e = _floored(got[same], ref["ups"][same], N)
+        rs = ref["seg"][same]
+        live = rs[..., 2] > 0
+        herr = np.abs(sg[same][..., 2][live] / rs[..., 2][live] - 1).max()
+        print(f"N={N}: fp64 max floored rel err {e.max():.3g}, H max rel err {herr:.3g}")
+        assert e.max() < 1e-9 and herr < 5e-11
+        B.scs_evaluate(h, tht, u, B.SCS_PREC_MIXED)
+        torch.cuda.synchronize()
+        em = _floored(u.cpu().numpy()[same], ref["ups"][same], N)
+        print(f"N={N}: mixed max floored rel err {em.max():.3g}")
+        assert em.max() < 1e-5
+    finally:
+        B.scs_ctx_destroy(h)
+
+
+def test_noise_free_injection_and_statistics():
+    """d = A h(theta*): Upsilon_N = rho^2 for every N, log L = 0 at the true
+    amplitude, and the statistics rows against the oracle's."""
+    ds = D.lisa_small(noise=False, snr=17.0, response=O.RESP_LISA_FD)
+    for N in (1, 16):
+        h = _ctx(ds, N, G=16)
+        try:
+            th = np.ascontiguousarray(ds.injection[None, :])
+            st = np.empty((1, B.SCS_NSTATS))
+            B.scs_evaluate_stats(h, th, st)
+            print(f"N={N}: Upsilon at the injection {st[0, 0]:.12f} (rho^2 = {ds.snr ** 2})")
+            assert abs(st[0, 0] / ds.snr ** 2 - 1) < 1e-9
+            ref = O.likelihood_stats(ds.grid, ds.model, ds.d_ri, ds.psd, th, N, O.SEG_EQUAL_SNR, 16)
+            assert abs(st[0, 2] / ref["hh"][0] - 1) < 5e-11
+            dd = B.scs_data_norm(h)
+            amp = np.array([ds.snr / np.sqrt(st[0, 2])])
+            semi, coh = np.empty(1), np.empty(1)
+            B.scs_loglike(h, st, amp, np.zeros(1), semi, coh)
+            assert abs(semi[0]) < 1e-9 * dd and abs(coh[0]) < 1e-9 * dd
+        finally:
+            B.scs_ctx_destroy(h)
