@@ -46,7 +46,7 @@ class _Grid(C.Structure):
 
 class _Model(C.Structure):
     _fields_ = [("pn_order", C.c_int32), ("response", C.c_int32), ("support", C.c_int32),
-                ("pad", C.c_int32), ("t_obs", C.c_double), ("orbit_phase0", C.c_double),
+                ("eccentric", C.c_int32), ("t_obs", C.c_double), ("orbit_phase0", C.c_double),
                 ("cartwheel_phase0", C.c_double)]
 
 
@@ -73,9 +73,14 @@ class Model:
     t_obs: float = 0.0
     orbit_phase0: float = 0.0
     cartwheel_phase0: float = 0.0
+    eccentric: int = 0  # 1: theta rows carry an 8th entry, e0 at GW frequency f_low
+
+    @property
+    def theta_dim(self):
+        return 8 if self.eccentric else 7
 
     def c(self):
-        return _Model(self.pn_order, self.response, self.support, 0, self.t_obs,
+        return _Model(self.pn_order, self.response, self.support, int(self.eccentric), self.t_obs,
                       self.orbit_phase0, self.cartwheel_phase0)
 
 
@@ -139,7 +144,7 @@ def evaluate(grid: Grid, model: Model, d_ri, psd, theta, N, mode=SEG_EQUAL_SNR, 
     'support' [P,2]."""
     d_ri = _f64(d_ri)
     psd = _f64(psd)
-    theta = _f64(theta).reshape(-1, 7)
+    theta = _f64(theta).reshape(-1, model.theta_dim)
     P = theta.shape[0]
     assert d_ri.shape == (grid.n_chan, grid.K, 2)
     assert psd.shape == (grid.n_chan, grid.K)
@@ -221,7 +226,7 @@ def noise(grid: Grid, psd, seed, r):
 
 def template(grid: Grid, model: Model, theta):
     """h_alpha(f_k) over the grid, complex array [n_chan, K] (zero off support)."""
-    theta = _f64(theta).reshape(7)
+    theta = _f64(theta).reshape(model.theta_dim)
     h = np.zeros((grid.n_chan, grid.K, 2))
     g, m = grid.c(), model.c()
     rc = lib().orc_template(C.byref(g), C.byref(m), _dp(theta), _dp(h))
@@ -232,7 +237,7 @@ def template(grid: Grid, model: Model, theta):
 
 def phase(model: Model, theta, f_hz):
     """(phase mod 1 [cycles], integer part, SPA time [s], t_c [s]) at frequencies f_hz."""
-    theta = _f64(theta).reshape(7)
+    theta = _f64(theta).reshape(model.theta_dim)
     f = _f64(np.atleast_1d(f_hz))
     fr, it, t = np.empty_like(f), np.empty_like(f), np.empty_like(f)
     tc = C.c_double()
@@ -244,7 +249,7 @@ def phase(model: Model, theta, f_hz):
 
 
 def phase_bins(grid: Grid, model: Model, theta, bins):
-    theta = _f64(theta).reshape(7)
+    theta = _f64(theta).reshape(model.theta_dim)
     b = np.ascontiguousarray(bins, dtype=np.int64)
     fr, t = np.empty(b.size), np.empty(b.size)
     g, m = grid.c(), model.c()
@@ -256,7 +261,7 @@ def phase_bins(grid: Grid, model: Model, theta, bins):
 
 def response(model: Model, theta, t):
     """(F [2 chan, 2 pol], Doppler cycles per Hz, T-channel (F+, Fx)) at time t."""
-    theta = _f64(theta).reshape(7)
+    theta = _f64(theta).reshape(model.theta_dim)
     F = np.empty(4)
     dop = C.c_double()
     tch = np.empty(2)
@@ -270,7 +275,7 @@ def response(model: Model, theta, t):
 def fd_transfer(model: Model, theta, f, t):
     """Full-response transfer functions (A, E, T), complex [3], at frequency
     f [Hz] and time t [s] (response 2)."""
-    theta = _f64(theta).reshape(7)
+    theta = _f64(theta).reshape(model.theta_dim)
     R = np.empty(6)
     m = model.c()
     if lib().orc_fd_transfer(C.byref(m), _dp(theta), float(f), float(t), _dp(R)) != 0:

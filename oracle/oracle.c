@@ -29,6 +29,9 @@
  * Where the paper leaves a point open, the reading taken is stated next to
  * the code that takes it.
  *
+ * Eccentric models (TaylorF2Ecc, Sec 4) keep the leading-order correction in
+ * e0^2 at Newtonian order, pinned against the Peters-Mathews evolution.
+ *
  * Parity unpinned: the PN phase coefficients above the Newtonian term (the
  * paper does not print them; they are the standard TaylorF2 values, checked
  * only through an extended-precision evaluation of the same formula and the
@@ -73,14 +76,17 @@ typedef struct {
     int32_t response;        /* 0: none (one channel), 1: LISA low-frequency A,E,
                                 2: LISA full frequency-domain response A,E (,T) */
     int32_t support;         /* 0: whole band, 1: observation window */
-    int32_t pad;
+    int32_t eccentric;       /* 0: circular, theta has 7 entries; 1: an 8th entry e0 */
     double t_obs;            /* observation time [s] */
     double orbit_phase0;     /* orbital angle of the constellation centre at t = 0 [rad] */
     double cartwheel_phase0; /* in-plane angle of spacecraft 0 at t = 0 [rad] */
 } orc_model;
 
-/* theta layout: Mc [Msun, detector frame], eta, f_low [Hz], lambda, beta, iota, psi */
-enum { TH_MC = 0, TH_ETA, TH_FLOW, TH_LAMBDA, TH_BETA, TH_IOTA, TH_PSI, TH_DIM };
+/* theta layout: Mc [Msun, detector frame], eta, f_low [Hz], lambda, beta, iota, psi
+ * (, e0: the eccentricity at GW frequency f_low, eccentric models only) */
+enum { TH_MC = 0, TH_ETA, TH_FLOW, TH_LAMBDA, TH_BETA, TH_IOTA, TH_PSI, TH_DIM, TH_E0 = TH_DIM };
+
+static int theta_dim(const orc_model* m) { return m->eccentric ? TH_DIM + 1 : TH_DIM; }
 
 /* ---- per-source derived quantities ------------------------------------ */
 typedef struct {
@@ -93,6 +99,7 @@ typedef struct {
     ld b6log;    /* multiplies ln(4 v) in psi6 (= -6848/21) */
     int order;
     ld tc;       /* coalescence time [s], fixed by t(f_low) = 0 */
+    ld ecc;      /* eccentric term: -(2355/1462) e0^2 v0^(19/3), multiplies v^(-19/3) in the series */
     /* extrinsic */
     double a_plus, a_cross; /* (1 + cos^2 iota)/2, cos iota */
     double eplus[3][3], ecross[3][3];
@@ -141,6 +148,7 @@ static ld pn_series(const src_t* s, ld v)
             c = s->psi[j];
         sum += c * vp[j];
     }
+    if (s->ecc != 0.0L) sum += s->ecc * powl(v, -19.0L / 3.0L);
     return sum / (vp[5]);
 }
 
@@ -164,6 +172,8 @@ static ld pn_series_fderiv(const src_t* s, ld v)
             sum += s->psi[j] * ((ld)(j - 5) / 3.0L) * vp[j];
         }
     }
+    /* f d/df of ecc v^(-34/3) = ecc (-34/9) v^(-34/3) */
+    if (s->ecc != 0.0L) sum += s->ecc * (-34.0L / 9.0L) * powl(v, -19.0L / 3.0L);
     return sum / vp[5];
 }
 
@@ -345,9 +355,11 @@ static void make_source(const double* th, const orc_model* m, src_t* s)
 {
     memset(s, 0, sizeof *s);
     const double Mc = th[TH_MC], eta = th[TH_ETA], flow = th[TH_FLOW];
-    for (int i = 0; i < TH_DIM; ++i)
+    for (int i = 0; i < theta_dim(m); ++i)
         if (!isfinite(th[i])) return;
     if (!(Mc > 0.0) || !(eta > 0.0) || !(eta <= 0.25) || !(flow > 0.0)) return;
+    const double e0 = m->eccentric ? th[TH_E0] : 0.0;
+    if (!(e0 >= 0.0) || !(e0 < 0.5)) return; /* a leading-order expansion in e0^2 */
     if (m->pn_order < 0 || m->pn_order > 7) return;
     s->valid = 1;
     s->order = m->pn_order;
@@ -361,6 +373,10 @@ static void make_source(const double* th, const orc_model* m, src_t* s)
      * observation (Table tab:GW150914-like_injection lists t_c as derived). */
     const ld fl = (ld)flow;
     const ld v = cbrtl(s->piM * fl);
+    /* Eccentric phase (the TaylorF2Ecc model of Sec 4): the leading-order
+     * correction in e0^2 to the Newtonian term of the SPA phase, with e0 the
+     * eccentricity at GW frequency f_low (v0 = v(f_low)); Yunes & Arun 2009. */
+    s->ecc = -(2355.0L / 1462.0L) * (ld)e0 * (ld)e0 * powl(v, 19.0L / 3.0L);
     s->tc = -s->pref * pn_series_fderiv(s, v) / fl;
     const double iota = th[TH_IOTA];
     s->a_plus = 0.5 * (1.0 + cos(iota) * cos(iota));
@@ -545,7 +561,7 @@ int orc_evaluate(const orc_grid* g, const orc_model* m, const double* d_ri, cons
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t p = 0; p < P; ++p) {
         src_t s;
-        const double* th = theta + p * TH_DIM;
+        const double* th = theta + p * theta_dim(m);
         make_source(th, m, &s);
         if (!s.valid) {
             ups[p] = NAN;
