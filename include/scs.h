@@ -29,8 +29,11 @@
  *   beta    ecliptic latitude [rad]
  *   iota    inclination [rad]
  *   psi     polarisation angle [rad]
- * (the searched parameters of Table tab:GW150914-like_injection with e0 = 0;
- * distance and phase are maximised out of the statistic, Sec 4).
+ * and, for an eccentric model (scs_model.eccentric = 1), an 8th entry
+ *   e0      orbital eccentricity at GW frequency f_low, 0 <= e0 < 0.5
+ * (the searched parameters of Table tab:GW150914-like_injection; distance and
+ * phase are maximised out of the statistic, Sec 4).  scs_theta_dim gives
+ * the row width of a context.
  */
 #ifndef SCS_H
 #define SCS_H
@@ -86,6 +89,11 @@ typedef struct scs_model {
     double t_obs;            /* observation time [s]; 0 = 1/df */
     double orbit_phase0;     /* orbital angle of the constellation centre at t = 0 [rad] */
     double cartwheel_phase0; /* in-plane angle of spacecraft 0 at t = 0 [rad] */
+    int32_t eccentric;       /* 1: the eccentric phase of the TaylorF2Ecc model (Sec 4) at its
+                                leading order in e0^2: the Newtonian term times
+                                1 - (2355/1462) e0^2 (f_low / f)^(19/9), e0 the 8th theta
+                                entry; 0: circular, 7 entries */
+    int32_t pad;
 } scs_model;
 
 /* ---- context --------------------------------------------------------- */
@@ -123,7 +131,7 @@ int scs_set_model(scs_ctx* ctx, const scs_model* model);
 int scs_define_segmentation(scs_ctx* ctx, int32_t N, int32_t mode, int32_t G, const int64_t* edges);
 
 /* Evaluate Upsilon_N (Sec 2.2, the statistic's definition) for P particles.
- *   theta  [P][7]
+ *   theta  [P][D], D = scs_theta_dim (7, or 8 for an eccentric model)
  *   ups    [P] out: Upsilon_N; NaN for invalid theta (Mc <= 0, eta outside
  *          (0, 1/4], f_low <= 0, non-finite) or a theta the polynomial block
  *          scheme cannot resolve (counted by scs_ctx_stats); 0 when the
@@ -183,7 +191,7 @@ int scs_loglike(scs_ctx* ctx, int64_t P, const double* stats, const double* amp,
 int scs_make_realisations(scs_ctx* ctx, int64_t R, uint64_t seed, int64_t r0, double scale, double* streams,
                           void* stream);
 
-/* For one theta (HOST [7]) and R data streams (DEVICE [n_chan][K][R][2], as
+/* For one theta (HOST [D]) and R data streams (DEVICE [n_chan][K][R][2], as
  * made by scs_make_realisations or by the caller), stats (DEVICE
  * [R][SCS_NSTATS]) = the rows of scs_evaluate_stats for each stream in place
  * of the loaded data.  The segment edges are theta's under the context's
@@ -231,7 +239,7 @@ typedef struct scs_batch_item {
     int32_t N;
     int32_t pad;
     int64_t P;
-    const double* theta; /* dev [P][7] */
+    const double* theta; /* dev [P][D] of the item's context */
     double* ups;         /* dev [P] */
     double* seg;         /* dev [P][N][3] or NULL */
 } scs_batch_item;
@@ -256,7 +264,7 @@ int scs_graph_destroy(scs_graph* g);
 
 /* Tile-shape autotuner: time the candidate launch shapes (waves per
  * workgroup, bins per chunk) of the generate-and-reduce kernel on this
- * context for the P particles theta_dev (device [P][7]) and N segments, and
+ * context for the P particles theta_dev (device [P][D]) and N segments, and
  * keep the fastest for later calls with a similar (P, N, prec).  cache_path
  * (nullable) is a text file of "key waves blocks" lines, read before tuning
  * (a hit skips the timing) and rewritten after. */
@@ -303,7 +311,7 @@ typedef struct scs_server_counters {
  * HIP streams the launches rotate over (1..16, default priority). */
 int scs_server_create(scs_server** out, int32_t device, int32_t max_inflight, uint64_t hbm_budget, int32_t n_streams);
 
-/* Queue an evaluation of P particles (theta, HOST [P][7], copied before the
+/* Queue an evaluation of P particles (theta, HOST [P][D], copied before the
  * call returns) with N segments on search ctx.  ups (HOST [P]) must stay
  * valid until the request is reported by scs_server_poll.  A request whose
  * footprint alone exceeds the budget is rejected with EBUSY.  Errors:
@@ -329,11 +337,13 @@ typedef struct scs_pso_params {
     double omega;  /* inertia */
     double phi_p;  /* pull to the particle best */
     double phi_g;  /* pull to the swarm best */
-    double eps[7]; /* minimum speed per dimension (eqn:PSO_min_velocity) */
+    double eps[8]; /* minimum speed per dimension (eqn:PSO_min_velocity); eps[7] (e0) is
+                      read by eccentric swarms only */
 } scs_pso_params;
 
 /* Create a swarm of P particles bound to ctx (its data, model and
- * segmentation), positions uniform in [lo, hi] (host [7] each), zero
+ * segmentation), positions uniform in [lo, hi] (host [D] each, D the context's
+ * theta width), zero
  * velocity.  periodic[d] = 1 wraps dimension d into [lo, hi).  Random numbers
  * come from Philox4x32-10 with key (seed low word, seed high word + swarm_id)
  * and counter (iteration, particle, dimension, stream). */
@@ -362,7 +372,7 @@ int scs_pso_step_swarms(scs_swarm* const* sws, int32_t n, const scs_pso_params* 
                         double* gbest_vals, void* stream);
 
 /* Copy the swarm state to host arrays (any may be NULL): theta, vel, pbest
- * [P][7], pbest_val [P], gbest [7], gbest_val, iteration.  Synchronous. */
+ * [P][D], pbest_val [P], gbest [D], gbest_val, iteration.  Synchronous. */
 int scs_swarm_read(scs_swarm* sw, double* theta, double* vel, double* pbest, double* pbest_val, double* gbest,
                    double* gbest_val, uint32_t* iteration);
 
@@ -370,20 +380,24 @@ int scs_swarm_read(scs_swarm* sw, double* theta, double* vel, double* pbest, dou
 int scs_swarm_write(scs_swarm* sw, const double* theta, const double* vel, const double* pbest,
                     const double* pbest_val, const double* gbest, double gbest_val, uint32_t iteration);
 
-/* Device pointers to the swarm's live arrays (theta [P][7], ups [P]). */
+/* Device pointers to the swarm's live arrays (theta [P][D], ups [P]). */
 int scs_swarm_device_ptrs(scs_swarm* sw, double** theta, double** ups);
 
-/* Raw move kernel on caller buffers (dev): theta, vel [P][7] updated in
- * place from pbest [P][7] and gbest [7]; lo, hi, eps as host [7]. */
-int scs_pso_move(int64_t P, double* theta, double* vel, const double* pbest, const double* gbest,
+/* Raw move kernel on caller buffers (dev): theta, vel [P][dim] updated in
+ * place from pbest [P][dim] and gbest [dim]; lo, hi, periodic host [dim];
+ * dim 7 or 8. */
+int scs_pso_move(int64_t P, int32_t dim, double* theta, double* vel, const double* pbest, const double* gbest,
                  const scs_pso_params* params, const double* lo, const double* hi, const int32_t* periodic,
                  uint64_t seed, uint32_t swarm_id, uint32_t iteration, void* stream);
 
 /* Raw best-update kernel on caller buffers (dev): vals [P]; pbest, pbest_val,
- * gbest [7], gbest_val [1] updated in place. */
-int scs_pso_best(int64_t P, const double* theta, const double* vals, const double* lo, const double* hi,
+ * gbest [dim], gbest_val [1] updated in place; dim 7 or 8. */
+int scs_pso_best(int64_t P, int32_t dim, const double* theta, const double* vals, const double* lo, const double* hi,
                  const int32_t* periodic, double* pbest, double* pbest_val, double* gbest, double* gbest_val,
                  void* stream);
+
+/* Entries per theta row of the context's model: 7, or 8 when eccentric. */
+int scs_theta_dim(const scs_ctx* ctx, int32_t* dim);
 
 /* ---- hierarchical multi-swarm search (Sec 3.1 - 3.2, app:PSO_params) -- */
 
@@ -419,7 +433,8 @@ typedef struct scs_rung_report {
 } scs_rung_report;
 
 /* Create a search on ctx: n_swarms swarms of `particles` particles, uniform
- * in [lo, hi] (host [7]; periodic[d] = 1 wraps dimension d, may be NULL).
+ * in [lo, hi] (host [D], D the context's theta width; periodic[d] = 1 wraps
+ * dimension d, may be NULL).
  * Errors: EINVAL, ENOMEM, and those of scs_swarm_create. */
 int scs_search_create(scs_ctx* ctx, const scs_search_params* params, const double* lo, const double* hi,
                       const int32_t* periodic, scs_search** out);
@@ -429,13 +444,15 @@ int scs_search_create(scs_ctx* ctx, const scs_search_params* params, const doubl
  * box, periodic ones as the point (cos, sin) / 2 pi on the circle;
  * k = n_swarms; empty clusters dropped) into new swarms whose bests start
  * afresh; then define the rung's segmentation on the context and iterate
- * scs_pso_step on every swarm until each has converged (a converged swarm
- * stops moving) or max_iters.  report may be NULL.  Synchronises the stream
- * once per iteration (one value per swarm). */
+ * every swarm that has not converged, all of them in one scs_pso_step_swarms
+ * per iteration, until each has converged (a converged swarm stops moving)
+ * or max_iters.  report may be NULL.  Synchronises the stream once per
+ * iteration (one value per swarm). */
 int scs_search_run_rung(scs_search* s, const scs_rung* rung, scs_rung_report* report, void* stream);
 
-/* Current swarms: their number, sizes [n] and bests [n][8] (position, value);
- * sizes and best may be NULL.  Synchronous. */
+/* Current swarms: their number, sizes [n] and bests [n][D + 1] (position,
+ * value; D the context's theta width); sizes and best may be NULL.
+ * Synchronous. */
 int scs_search_swarms(scs_search* s, int32_t* n_swarms, int64_t* sizes, double* best);
 
 int scs_search_destroy(scs_search* s);

@@ -34,7 +34,7 @@ class ScsError(RuntimeError):
 class scs_model(C.Structure):
     _fields_ = [("pn_order", C.c_int32), ("response", C.c_int32), ("support", C.c_int32),
                 ("block_len", C.c_int32), ("t_obs", C.c_double), ("orbit_phase0", C.c_double),
-                ("cartwheel_phase0", C.c_double)]
+                ("cartwheel_phase0", C.c_double), ("eccentric", C.c_int32), ("pad", C.c_int32)]
 
 
 class scs_batch_item(C.Structure):
@@ -55,7 +55,7 @@ class scs_server_counters(C.Structure):
 
 class scs_pso_params(C.Structure):
     _fields_ = [("omega", C.c_double), ("phi_p", C.c_double), ("phi_g", C.c_double),
-                ("eps", C.c_double * 7)]
+                ("eps", C.c_double * 8)]
 
 
 class scs_search_params(C.Structure):
@@ -108,10 +108,12 @@ _SIGS = {
     "scs_swarm_write": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
                         C.c_uint32],
     "scs_swarm_device_ptrs": [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)],
-    "scs_pso_move": [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(scs_pso_params),
-                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint32, C.c_void_p],
-    "scs_pso_best": [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
-                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+    "scs_pso_move": [C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                     C.POINTER(scs_pso_params), C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_uint32,
+                     C.c_uint32, C.c_void_p],
+    "scs_pso_best": [C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+    "scs_theta_dim": [C.c_void_p, C.POINTER(C.c_int32)],
     "scs_server_create": [C.POINTER(C.c_void_p), C.c_int32, C.c_int32, C.c_uint64, C.c_int32],
     "scs_server_submit": [C.c_void_p, C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p,
                           C.POINTER(C.c_uint64)],
@@ -214,8 +216,8 @@ def scs_load_data(ctx, d_ri, psd, f_min, df):
 
 
 def scs_set_model(ctx, pn_order, response, support, t_obs=0.0, block_len=0, orbit_phase0=0.0,
-                  cartwheel_phase0=0.0):
-    m = scs_model(pn_order, response, support, block_len, t_obs, orbit_phase0, cartwheel_phase0)
+                  cartwheel_phase0=0.0, eccentric=0):
+    m = scs_model(pn_order, response, support, block_len, t_obs, orbit_phase0, cartwheel_phase0, eccentric, 0)
     _check(lib().scs_set_model(ctx, C.byref(m)))
 
 
@@ -286,8 +288,8 @@ def scs_make_realisations(ctx, streams, seed, r0=0, scale=1.0, stream=None):
 
 
 def scs_evaluate_streams(ctx, theta, streams, stats, stream=None):
-    """theta numpy [7]; streams CUDA [n_chan, K, R, 2]; stats CUDA [R, 5] out."""
-    th = np.ascontiguousarray(theta, dtype=np.float64).reshape(7)
+    """theta numpy [D] (the context's theta width); streams CUDA [n_chan, K, R, 2]; stats CUDA [R, 5] out."""
+    th = np.ascontiguousarray(theta, dtype=np.float64).ravel()
     if not (_is_torch(streams) and streams.is_cuda and _is_torch(stats) and stats.is_cuda):
         raise TypeError("streams and stats must be CUDA tensors")
     R = streams.shape[2]
@@ -377,7 +379,7 @@ def _f64(a):
 
 def scs_swarm_create(ctx, P, lo, hi, periodic=None, seed=0, swarm_id=0):
     lo, hi = _f64(lo), _f64(hi)
-    per = np.ascontiguousarray(periodic if periodic is not None else np.zeros(7), dtype=np.int32)
+    per = np.ascontiguousarray(periodic if periodic is not None else np.zeros(lo.size), dtype=np.int32)
     h = C.c_void_p()
     _check(lib().scs_swarm_create(ctx, C.byref(h), P, C.c_void_p(lo.ctypes.data), C.c_void_p(hi.ctypes.data),
                                   C.c_void_p(per.ctypes.data), seed, swarm_id))
@@ -389,14 +391,22 @@ def scs_swarm_destroy(sw):
 
 
 def pso_params(omega, phi_p, phi_g, eps):
-    return scs_pso_params(omega, phi_p, phi_g, (C.c_double * 7)(*[float(e) for e in eps]))
+    """eps: 7 minimum speeds, or 8 (the last for e0) for eccentric swarms."""
+    e = [float(x) for x in eps] + [0.0] * (8 - len(eps))
+    return scs_pso_params(omega, phi_p, phi_g, (C.c_double * 8)(*e))
+
+
+def scs_theta_dim(ctx):
+    d = C.c_int32()
+    _check(lib().scs_theta_dim(ctx, C.byref(d)))
+    return d.value
 
 
 def scs_search_create(ctx, n_swarms, particles, lo, hi, periodic=None, G=1, conv_tol=2.0, conv_window=50,
                       kmeans_iters=100, prec=SCS_PREC_FP64, seed=0):
     prm = scs_search_params(n_swarms, G, particles, conv_tol, conv_window, kmeans_iters, prec, 0, seed)
     lo, hi = _f64(lo), _f64(hi)
-    per = np.ascontiguousarray(periodic if periodic is not None else np.zeros(7), dtype=np.int32)
+    per = np.ascontiguousarray(periodic if periodic is not None else np.zeros(lo.size), dtype=np.int32)
     h = C.c_void_p()
     _check(lib().scs_search_create(ctx, C.byref(prm), C.c_void_p(lo.ctypes.data), C.c_void_p(hi.ctypes.data),
                                    C.c_void_p(per.ctypes.data), C.byref(h)))
@@ -411,10 +421,11 @@ def scs_search_run_rung(search, N, max_iters, params, stream=None):
     return {k: getattr(rep, k) for k, _ in scs_rung_report._fields_}
 
 
-def scs_search_swarms(search, max_swarms=64):
+def scs_search_swarms(search, max_swarms=64, dim=7):
+    """(sizes [n], bests [n, dim + 1]: position, value); dim = the context's theta width."""
     n = C.c_int32()
     sizes = np.zeros(max_swarms, dtype=np.int64)
-    best = np.zeros((max_swarms, 8))
+    best = np.zeros((max_swarms, dim + 1))
     _check(lib().scs_search_swarms(search, C.byref(n), C.c_void_p(sizes.ctypes.data), C.c_void_p(best.ctypes.data)))
     return sizes[:n.value].copy(), best[:n.value].copy()
 
@@ -453,9 +464,9 @@ def scs_pso_step_swarms(sws, params, prec=SCS_PREC_FP64, stream=None, read_best=
     return vals
 
 
-def scs_swarm_read(sw, P):
-    th, v, pb = np.empty((P, 7)), np.empty((P, 7)), np.empty((P, 7))
-    pv, gb = np.empty(P), np.empty(7)
+def scs_swarm_read(sw, P, dim=7):
+    th, v, pb = np.empty((P, dim)), np.empty((P, dim)), np.empty((P, dim))
+    pv, gb = np.empty(P), np.empty(dim)
     gv, it = C.c_double(), C.c_uint32()
     _check(lib().scs_swarm_read(sw, C.c_void_p(th.ctypes.data), C.c_void_p(v.ctypes.data),
                                 C.c_void_p(pb.ctypes.data), C.c_void_p(pv.ctypes.data),
@@ -481,7 +492,8 @@ def scs_pso_move(theta, vel, pbest, gbest, params, lo, hi, periodic, seed, swarm
     per = np.ascontiguousarray(periodic, dtype=np.int32)
     if stream is None:
         stream = current_stream()
-    _check(lib().scs_pso_move(theta.shape[0], theta.data_ptr(), vel.data_ptr(), pbest.data_ptr(), gbest.data_ptr(),
+    _check(lib().scs_pso_move(theta.shape[0], theta.shape[1], theta.data_ptr(), vel.data_ptr(), pbest.data_ptr(),
+                              gbest.data_ptr(),
                               C.byref(params), C.c_void_p(lo.ctypes.data), C.c_void_p(hi.ctypes.data),
                               C.c_void_p(per.ctypes.data), seed, swarm_id, iteration, _stream(stream)))
 
@@ -491,7 +503,8 @@ def scs_pso_best(theta, vals, lo, hi, periodic, pbest, pbest_val, gbest, gbest_v
     per = np.ascontiguousarray(periodic, dtype=np.int32)
     if stream is None:
         stream = current_stream()
-    _check(lib().scs_pso_best(theta.shape[0], theta.data_ptr(), vals.data_ptr(), C.c_void_p(lo.ctypes.data),
+    _check(lib().scs_pso_best(theta.shape[0], theta.shape[1], theta.data_ptr(), vals.data_ptr(),
+                              C.c_void_p(lo.ctypes.data),
                               C.c_void_p(hi.ctypes.data), C.c_void_p(per.ctypes.data), pbest.data_ptr(),
                               pbest_val.data_ptr(), gbest.data_ptr(), gbest_val.data_ptr(), _stream(stream)))
 

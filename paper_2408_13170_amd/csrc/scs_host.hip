@@ -211,6 +211,9 @@ struct scs_ctx {
 static int build_gtab(scs_ctx* c);
 static void free_slot(BatchSlot& b);
 
+// Entries per theta row: 7, or 8 with the eccentricity of an eccentric model.
+static int theta_dim(const scs_ctx* c) { return c->m.ecc ? kThetaMax : kTheta; }
+
 struct DevScope {
     int prev = -1;
     explicit DevScope(int d)
@@ -422,6 +425,7 @@ extern "C" int scs_set_model(scs_ctx* c, const scs_model* m)
     const int bl = m->block_len ? m->block_len : 2048;
     if (bl < 16 || bl > 2048 || (bl & (bl - 1))) return fail(SCS_EINVAL, "block_len must be a power of 2 in 16..2048");
     if (m->t_obs < 0.0 || !std::isfinite(m->t_obs)) return fail(SCS_EINVAL, "bad t_obs");
+    if (m->eccentric != 0 && m->eccentric != 1) return fail(SCS_EINVAL, "eccentric must be 0 or 1");
     c->m.pn_order = m->pn_order;
     c->m.response = m->response;
     c->m.support = m->support;
@@ -431,6 +435,7 @@ extern "C" int scs_set_model(scs_ctx* c, const scs_model* m)
     c->m.cart0 = m->cartwheel_phase0;
     c->m.cart_c = std::cos(m->cartwheel_phase0);
     c->m.cart_s = std::sin(m->cartwheel_phase0);
+    c->m.ecc = m->eccentric;
     c->L = 512;  // bins per LDS-staged block of the generate-and-reduce kernel
     int lg = 0;
     while ((1 << lg) < bl) ++lg;
@@ -768,12 +773,13 @@ extern "C" int scs_evaluate(scs_ctx* c, int64_t P, const double* theta, int32_t 
     const int N = c->N;
     if (mem_kind == SCS_MEM_DEVICE) return run_eval(c, w, P, N, theta, prec, ups, seg, s);
     // host pointers: stage through device memory
-    const int64_t need = P * 8 + P + (seg ? P * (int64_t)N * 3 : 0);
+    const int td = theta_dim(c);
+    const int64_t need = P * td + P + (seg ? P * (int64_t)N * 3 : 0);
     if ((rc = grow(&w.stage, &w.capStage, std::max<int64_t>(need, 1)))) return rc;
     double* dth = w.stage;
-    double* dup = dth + P * 7;
+    double* dup = dth + P * td;
     double* dseg = seg ? dup + P : nullptr;
-    HIP_TRY(hipMemcpyAsync(dth, theta, sizeof(double) * 7 * P, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(dth, theta, sizeof(double) * td * P, hipMemcpyHostToDevice, s));
     if ((rc = run_eval(c, w, P, N, dth, prec, dup, dseg, s))) return rc;
     HIP_TRY(hipMemcpyAsync(ups, dup, sizeof(double) * P, hipMemcpyDeviceToHost, s));
     if (seg) HIP_TRY(hipMemcpyAsync(seg, dseg, sizeof(double) * P * N * 3, hipMemcpyDeviceToHost, s));
@@ -795,13 +801,14 @@ extern "C" int scs_evaluate_stats(scs_ctx* c, int64_t P, const double* theta, in
     Workspace& w = c->ws[0];
     const int N = c->N;
     // staging: theta, Upsilon (also written by the epilogue) and the statistics
-    const int64_t need = P * (7 + 1 + kNStats);
+    const int td = theta_dim(c);
+    const int64_t need = P * (td + 1 + kNStats);
     if ((rc = grow(&w.stage, &w.capStage, std::max<int64_t>(need, 1)))) return rc;
     double* dth = w.stage;
-    double* dup = dth + P * 7;
+    double* dup = dth + P * td;
     double* dst = dup + P;
     if (mem_kind == SCS_MEM_DEVICE) return run_eval(c, w, P, N, theta, prec, dup, nullptr, s, nullptr, stats);
-    HIP_TRY(hipMemcpyAsync(dth, theta, sizeof(double) * 7 * P, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(dth, theta, sizeof(double) * td * P, hipMemcpyHostToDevice, s));
     if ((rc = run_eval(c, w, P, N, dth, prec, dup, nullptr, s, nullptr, dst))) return rc;
     HIP_TRY(hipMemcpyAsync(stats, dst, sizeof(double) * kNStats * P, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -886,13 +893,14 @@ extern "C" int scs_waveform(scs_ctx* c, const double* theta, double* h_ri, int32
     const Plan pl = make_plan(c, 1, t);
     if ((rc = ensure_ws(c, w, 1, 1, pl))) return rc;
     const int64_t nout = 2 * (int64_t)c->g.nch * c->g.K;
-    if ((rc = grow(&w.stage, &w.capStage, 7 + nout))) return rc;
+    const int td = theta_dim(c);
+    if ((rc = grow(&w.stage, &w.capStage, td + nout))) return rc;
     const double* dth = theta;
     double* dh = h_ri;
     if (mem_kind == SCS_MEM_HOST) {
-        HIP_TRY(hipMemcpyAsync(w.stage, theta, sizeof(double) * 7, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(w.stage, theta, sizeof(double) * td, hipMemcpyHostToDevice, s));
         dth = w.stage;
-        dh = w.stage + 7;
+        dh = w.stage + td;
     }
     PrologueArgs pa{};
     pa.g = c->g;
@@ -971,11 +979,12 @@ extern "C" int scs_evaluate_streams(scs_ctx* c, const double* theta, int64_t R, 
     const int nch = c->g.nch;
     const int64_t K = c->g.K;
     // edges of theta with the context's segmentation (one-particle evaluation)
-    if ((rc = grow(&w.stage, &w.capStage, 8))) return rc;
-    HIP_TRY(hipMemcpyAsync(w.stage, theta, sizeof(double) * 7, hipMemcpyHostToDevice, s));
+    const int td = theta_dim(c);
+    if ((rc = grow(&w.stage, &w.capStage, td + 1))) return rc;
+    HIP_TRY(hipMemcpyAsync(w.stage, theta, sizeof(double) * td, hipMemcpyHostToDevice, s));
     const bool prof = c->prof;
     c->prof = false;  // with profiling on, only the streamed reduction below is timed
-    rc = run_eval(c, w, 1, N, w.stage, SCS_PREC_FP64, w.stage + 7, nullptr, s);
+    rc = run_eval(c, w, 1, N, w.stage, SCS_PREC_FP64, w.stage + td, nullptr, s);
     c->prof = prof;
     if (rc) return rc;
     std::vector<int32_t> bo(N + 1);
@@ -1400,9 +1409,9 @@ static int slot_grow(SrvSlot& s, int64_t P)
     s.d_theta = s.d_ups = s.h_theta = s.h_ups = nullptr;
     s.cap = 0;
     const int64_t cap = std::max<int64_t>(P, 256);
-    if (hipMalloc((void**)&s.d_theta, sizeof(double) * 7 * cap) != hipSuccess ||
+    if (hipMalloc((void**)&s.d_theta, sizeof(double) * kThetaMax * cap) != hipSuccess ||
         hipMalloc((void**)&s.d_ups, sizeof(double) * cap) != hipSuccess ||
-        hipHostMalloc((void**)&s.h_theta, sizeof(double) * 7 * cap) != hipSuccess ||
+        hipHostMalloc((void**)&s.h_theta, sizeof(double) * kThetaMax * cap) != hipSuccess ||
         hipHostMalloc((void**)&s.h_ups, sizeof(double) * cap) != hipSuccess)
         return fail(SCS_ENOMEM, "request buffers of %lld particles", (long long)P);
     s.cap = cap;
@@ -1420,8 +1429,9 @@ int scs_server::launch(std::vector<SrvRequest*>& batch, int si)
         SrvRequest* r = batch[i];
         SrvSlot& sl = slots[r->slot];
         if ((rc = slot_grow(sl, r->P))) break;
-        std::memcpy(sl.h_theta, r->theta.data(), sizeof(double) * 7 * r->P);
-        if (hipMemcpyAsync(sl.d_theta, sl.h_theta, sizeof(double) * 7 * r->P, hipMemcpyHostToDevice, s) != hipSuccess)
+        std::memcpy(sl.h_theta, r->theta.data(), sizeof(double) * r->theta.size());
+        if (hipMemcpyAsync(sl.d_theta, sl.h_theta, sizeof(double) * r->theta.size(), hipMemcpyHostToDevice, s) !=
+            hipSuccess)
             rc = fail(SCS_EDEVICE, "theta upload failed");
         items[i] = scs_batch_item{r->ctx, r->N, 0, r->P, sl.d_theta, sl.d_ups, nullptr};
         wss[i] = &sl.ws;
@@ -1613,7 +1623,7 @@ extern "C" int scs_server_submit(scs_server* srv, scs_ctx* ctx, int32_t N, int64
     r->P = P;
     r->prec = prec;
     r->ups_user = ups;
-    r->theta.assign(theta, theta + 7 * P);
+    r->theta.assign(theta, theta + (int64_t)theta_dim(ctx) * P);
     r->bytes = bytes;
     {
         std::lock_guard<std::mutex> lk(srv->mu);
@@ -1777,16 +1787,19 @@ struct scs_swarm {
     scs_ctx* ctx = nullptr;
     int64_t P = 0;
     double *theta = nullptr, *vel = nullptr, *pbest = nullptr, *pbest_val = nullptr;
-    double *gbest = nullptr, *ups = nullptr;  // gbest[7], gbest[7] = value
+    double *gbest = nullptr, *ups = nullptr;  // gbest[dim] position, gbest[dim] = value
+    int dim = kTheta;                          // entries per theta row (the context's)
     PsoBox box{};
     uint64_t seed = 0;
     uint32_t swarm_id = 0;
     uint32_t iteration = 0;
 };
 
-static int make_box(const double* lo, const double* hi, const int32_t* periodic, PsoBox* box)
+static int make_box(const double* lo, const double* hi, const int32_t* periodic, int dim, PsoBox* box)
 {
-    for (int d = 0; d < 7; ++d) {
+    if (dim != kTheta && dim != kThetaMax) return fail(SCS_EINVAL, "dim must be 7 or 8");
+    box->dim = dim;
+    for (int d = 0; d < dim; ++d) {
         if (!std::isfinite(lo[d]) || !std::isfinite(hi[d]) || hi[d] < lo[d]) return fail(SCS_EINVAL, "bad box in dimension %d", d);
         box->lo[d] = lo[d];
         box->hi[d] = hi[d];
@@ -1805,28 +1818,30 @@ extern "C" int scs_swarm_create(scs_ctx* c, scs_swarm** out, int64_t P, const do
     if (rc) return rc;
     if (P < 1 || !lo || !hi) return fail(SCS_EINVAL, "bad P or box");
     scs_swarm* sw = new scs_swarm();
-    if ((rc = make_box(lo, hi, periodic, &sw->box))) {
+    const int D = theta_dim(c);
+    if ((rc = make_box(lo, hi, periodic, D, &sw->box))) {
         delete sw;
         return rc;
     }
     DevScope ds(c->device);
     sw->ctx = c;
     sw->P = P;
+    sw->dim = D;
     sw->seed = seed;
     sw->swarm_id = swarm_id;
-    const size_t n7 = sizeof(double) * 7 * P;
-    if (hipMalloc((void**)&sw->theta, n7) || hipMalloc((void**)&sw->vel, n7) || hipMalloc((void**)&sw->pbest, n7) ||
-        hipMalloc((void**)&sw->pbest_val, sizeof(double) * P) || hipMalloc((void**)&sw->gbest, sizeof(double) * 8) ||
-        hipMalloc((void**)&sw->ups, sizeof(double) * P)) {
+    const size_t nb = sizeof(double) * D * P;
+    if (hipMalloc((void**)&sw->theta, nb) || hipMalloc((void**)&sw->vel, nb) || hipMalloc((void**)&sw->pbest, nb) ||
+        hipMalloc((void**)&sw->pbest_val, sizeof(double) * P) ||
+        hipMalloc((void**)&sw->gbest, sizeof(double) * (D + 1)) || hipMalloc((void**)&sw->ups, sizeof(double) * P)) {
         scs_swarm_destroy(sw);
         return fail(SCS_ENOMEM, "swarm allocation failed");
     }
     launch_pso_init(P, sw->box, seed, swarm_id, sw->theta, nullptr);
-    launch_fill(sw->vel, 7 * P, 0.0, nullptr);
-    launch_fill(sw->pbest, 7 * P, 0.0, nullptr);
+    launch_fill(sw->vel, D * P, 0.0, nullptr);
+    launch_fill(sw->pbest, D * P, 0.0, nullptr);
     launch_fill(sw->pbest_val, P, -INFINITY, nullptr);
-    launch_fill(sw->gbest, 7, 0.0, nullptr);
-    launch_fill(sw->gbest + 7, 1, -INFINITY, nullptr);
+    launch_fill(sw->gbest, D, 0.0, nullptr);
+    launch_fill(sw->gbest + D, 1, -INFINITY, nullptr);
     if (hipDeviceSynchronize() != hipSuccess) {
         scs_swarm_destroy(sw);
         return fail(SCS_EDEVICE, "swarm initialisation failed");
@@ -1850,31 +1865,38 @@ extern "C" int scs_swarm_destroy(scs_swarm* sw)
     return SCS_OK;
 }
 
-static PsoParams to_params(const scs_pso_params* p)
+static PsoParams to_params(const scs_pso_params* p, int dim)
 {
     PsoParams q;
     q.omega = p->omega;
     q.phi_p = p->phi_p;
     q.phi_g = p->phi_g;
-    for (int d = 0; d < 7; ++d) q.eps[d] = p->eps[d];
+    for (int d = 0; d < kThetaMax; ++d) q.eps[d] = d < dim ? p->eps[d] : 0.0;
     return q;
+}
+
+static int check_eps(const scs_pso_params* p, int dim)
+{
+    for (int d = 0; d < dim; ++d)
+        if (!(p->eps[d] >= 0.0)) return fail(SCS_EINVAL, "eps[%d] must be >= 0", d);
+    return SCS_OK;
 }
 
 extern "C" int scs_pso_step(scs_swarm* sw, const scs_pso_params* prm, int32_t prec, void* stream)
 {
     if (!sw || !prm) return fail(SCS_EINVAL, "NULL argument");
-    for (int d = 0; d < 7; ++d)
-        if (!(prm->eps[d] >= 0.0)) return fail(SCS_EINVAL, "eps[%d] must be >= 0", d);
+    int rc0 = check_eps(prm, sw->dim);
+    if (rc0) return rc0;
     scs_ctx* c = sw->ctx;
     int rc = check_ready(c);
     if (rc) return rc;
     DevScope ds(c->device);
     hipStream_t s = (hipStream_t)stream;
     if (sw->iteration > 0)
-        launch_pso_move(sw->P, sw->box, to_params(prm), sw->seed, sw->swarm_id, sw->iteration, sw->theta, sw->vel,
-                        sw->pbest, sw->gbest, s);
+        launch_pso_move(sw->P, sw->box, to_params(prm, sw->dim), sw->seed, sw->swarm_id, sw->iteration, sw->theta,
+                        sw->vel, sw->pbest, sw->gbest, s);
     if ((rc = run_eval(c, c->ws[0], sw->P, c->N, sw->theta, prec, sw->ups, nullptr, s))) return rc;
-    launch_pso_best(sw->P, sw->box, sw->theta, sw->ups, sw->pbest, sw->pbest_val, sw->gbest, sw->gbest + 7, s);
+    launch_pso_best(sw->P, sw->box, sw->theta, sw->ups, sw->pbest, sw->pbest_val, sw->gbest, sw->gbest + sw->dim, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(SCS_EDEVICE, "pso launch failed: %s", hipGetErrorString(e));
     sw->iteration += 1;
@@ -1885,8 +1907,12 @@ extern "C" int scs_pso_step_swarms(scs_swarm* const* sws, int32_t n, const scs_p
                                    double* gbest_vals, void* stream)
 {
     if (!sws || n < 0 || !prm) return fail(SCS_EINVAL, "bad arguments");
-    for (int d = 0; d < 7; ++d)
-        if (!(prm->eps[d] >= 0.0)) return fail(SCS_EINVAL, "eps[%d] must be >= 0", d);
+    if (check_eps(prm, kThetaMax)) {
+        for (int i = 0; i < n; ++i) {  // eps[7] is read only by eccentric swarms
+            int rc = sws[i] ? check_eps(prm, sws[i]->dim) : SCS_OK;
+            if (rc) return rc;
+        }
+    }
     if (n == 0) return SCS_OK;
     std::vector<scs_batch_item> items(n);
     for (int i = 0; i < n; ++i) {
@@ -1904,20 +1930,21 @@ extern "C" int scs_pso_step_swarms(scs_swarm* const* sws, int32_t n, const scs_p
     for (int i = 0; i < n; ++i) {
         scs_swarm* sw = sws[i];
         if (sw->iteration > 0)
-            launch_pso_move(sw->P, sw->box, to_params(prm), sw->seed, sw->swarm_id, sw->iteration, sw->theta, sw->vel,
-                            sw->pbest, sw->gbest, s);
+            launch_pso_move(sw->P, sw->box, to_params(prm, sw->dim), sw->seed, sw->swarm_id, sw->iteration, sw->theta,
+                            sw->vel, sw->pbest, sw->gbest, s);
     }
     if ((rc = scs_evaluate_batched(items.data(), n, prec, stream))) return rc;
     for (int i = 0; i < n; ++i) {
         scs_swarm* sw = sws[i];
-        launch_pso_best(sw->P, sw->box, sw->theta, sw->ups, sw->pbest, sw->pbest_val, sw->gbest, sw->gbest + 7, s);
+        launch_pso_best(sw->P, sw->box, sw->theta, sw->ups, sw->pbest, sw->pbest_val, sw->gbest, sw->gbest + sw->dim, s);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(SCS_EDEVICE, "pso launch failed: %s", hipGetErrorString(e));
     for (int i = 0; i < n; ++i) sws[i]->iteration += 1;
     if (gbest_vals) {
         for (int i = 0; i < n; ++i)
-            HIP_TRY(hipMemcpyAsync(gbest_vals + i, sws[i]->gbest + 7, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(gbest_vals + i, sws[i]->gbest + sws[i]->dim, sizeof(double), hipMemcpyDeviceToHost,
+                                   s));
         HIP_TRY(hipStreamSynchronize(s));
     }
     return SCS_OK;
@@ -1929,15 +1956,16 @@ extern "C" int scs_swarm_read(scs_swarm* sw, double* theta, double* vel, double*
     if (!sw) return fail(SCS_EINVAL, "swarm is NULL");
     DevScope ds(sw->ctx->device);
     HIP_TRY(hipDeviceSynchronize());
-    const size_t n7 = sizeof(double) * 7 * sw->P;
-    if (theta) HIP_TRY(hipMemcpy(theta, sw->theta, n7, hipMemcpyDeviceToHost));
-    if (vel) HIP_TRY(hipMemcpy(vel, sw->vel, n7, hipMemcpyDeviceToHost));
-    if (pbest) HIP_TRY(hipMemcpy(pbest, sw->pbest, n7, hipMemcpyDeviceToHost));
+    const int D = sw->dim;
+    const size_t nb = sizeof(double) * D * sw->P;
+    if (theta) HIP_TRY(hipMemcpy(theta, sw->theta, nb, hipMemcpyDeviceToHost));
+    if (vel) HIP_TRY(hipMemcpy(vel, sw->vel, nb, hipMemcpyDeviceToHost));
+    if (pbest) HIP_TRY(hipMemcpy(pbest, sw->pbest, nb, hipMemcpyDeviceToHost));
     if (pbest_val) HIP_TRY(hipMemcpy(pbest_val, sw->pbest_val, sizeof(double) * sw->P, hipMemcpyDeviceToHost));
-    double g[8];
-    HIP_TRY(hipMemcpy(g, sw->gbest, sizeof g, hipMemcpyDeviceToHost));
-    if (gbest) memcpy(gbest, g, sizeof(double) * 7);
-    if (gbest_val) *gbest_val = g[7];
+    double g[kThetaMax + 1];
+    HIP_TRY(hipMemcpy(g, sw->gbest, sizeof(double) * (D + 1), hipMemcpyDeviceToHost));
+    if (gbest) memcpy(gbest, g, sizeof(double) * D);
+    if (gbest_val) *gbest_val = g[D];
     if (iteration) *iteration = sw->iteration;
     return SCS_OK;
 }
@@ -1948,16 +1976,26 @@ extern "C" int scs_swarm_write(scs_swarm* sw, const double* theta, const double*
     if (!sw || !theta || !vel || !pbest || !pbest_val || !gbest) return fail(SCS_EINVAL, "NULL argument");
     DevScope ds(sw->ctx->device);
     HIP_TRY(hipDeviceSynchronize());
-    const size_t n7 = sizeof(double) * 7 * sw->P;
-    HIP_TRY(hipMemcpy(sw->theta, theta, n7, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(sw->vel, vel, n7, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(sw->pbest, pbest, n7, hipMemcpyHostToDevice));
+    const int D = sw->dim;
+    const size_t nb = sizeof(double) * D * sw->P;
+    HIP_TRY(hipMemcpy(sw->theta, theta, nb, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(sw->vel, vel, nb, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(sw->pbest, pbest, nb, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(sw->pbest_val, pbest_val, sizeof(double) * sw->P, hipMemcpyHostToDevice));
-    double g[8];
-    memcpy(g, gbest, sizeof(double) * 7);
-    g[7] = gbest_val;
-    HIP_TRY(hipMemcpy(sw->gbest, g, sizeof g, hipMemcpyHostToDevice));
+    double g[kThetaMax + 1];
+    memcpy(g, gbest, sizeof(double) * D);
+    g[D] = gbest_val;
+    HIP_TRY(hipMemcpy(sw->gbest, g, sizeof(double) * (D + 1), hipMemcpyHostToDevice));
     sw->iteration = iteration;
+    return SCS_OK;
+}
+
+extern "C" int scs_theta_dim(const scs_ctx* c, int32_t* dim)
+{
+    int rc = check_ready(const_cast<scs_ctx*>(c));
+    if (rc) return rc;
+    if (!dim) return fail(SCS_EINVAL, "dim is NULL");
+    *dim = theta_dim(c);
     return SCS_OK;
 }
 
@@ -1969,31 +2007,32 @@ extern "C" int scs_swarm_device_ptrs(scs_swarm* sw, double** theta, double** ups
     return SCS_OK;
 }
 
-extern "C" int scs_pso_move(int64_t P, double* theta, double* vel, const double* pbest, const double* gbest,
-                            const scs_pso_params* prm, const double* lo, const double* hi, const int32_t* periodic,
-                            uint64_t seed, uint32_t swarm_id, uint32_t iteration, void* stream)
+extern "C" int scs_pso_move(int64_t P, int32_t dim, double* theta, double* vel, const double* pbest,
+                            const double* gbest, const scs_pso_params* prm, const double* lo, const double* hi,
+                            const int32_t* periodic, uint64_t seed, uint32_t swarm_id, uint32_t iteration, void* stream)
 {
     if (P < 0 || !prm || !lo || !hi) return fail(SCS_EINVAL, "bad arguments");
     if (P == 0) return SCS_OK;
     if (!theta || !vel || !pbest || !gbest) return fail(SCS_EINVAL, "NULL buffer");
     PsoBox box;
-    int rc = make_box(lo, hi, periodic, &box);
-    if (rc) return rc;
-    launch_pso_move(P, box, to_params(prm), seed, swarm_id, iteration, theta, vel, pbest, gbest, (hipStream_t)stream);
+    int rc = make_box(lo, hi, periodic, dim, &box);
+    if (rc || (rc = check_eps(prm, dim))) return rc;
+    launch_pso_move(P, box, to_params(prm, dim), seed, swarm_id, iteration, theta, vel, pbest, gbest,
+                    (hipStream_t)stream);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(SCS_EDEVICE, "launch failed: %s", hipGetErrorString(e));
     return SCS_OK;
 }
 
-extern "C" int scs_pso_best(int64_t P, const double* theta, const double* vals, const double* lo, const double* hi,
-                            const int32_t* periodic, double* pbest, double* pbest_val, double* gbest, double* gbest_val,
-                            void* stream)
+extern "C" int scs_pso_best(int64_t P, int32_t dim, const double* theta, const double* vals, const double* lo,
+                            const double* hi, const int32_t* periodic, double* pbest, double* pbest_val, double* gbest,
+                            double* gbest_val, void* stream)
 {
     if (P < 0 || !lo || !hi) return fail(SCS_EINVAL, "bad arguments");
     if (P == 0) return SCS_OK;
     if (!theta || !vals || !pbest || !pbest_val || !gbest || !gbest_val) return fail(SCS_EINVAL, "NULL buffer");
     PsoBox box;
-    int rc = make_box(lo, hi, periodic, &box);
+    int rc = make_box(lo, hi, periodic, dim, &box);
     if (rc) return rc;
     launch_pso_best(P, box, theta, vals, pbest, pbest_val, gbest, gbest_val, (hipStream_t)stream);
     hipError_t e = hipGetLastError();

@@ -8,9 +8,14 @@
 namespace scs {
 
 constexpr int kNodes = 6;  // degree-5 block polynomials (6 coefficients / Chebyshev nodes)
-constexpr int kGStride = 56;  // doubles per basis-table entry: 8 functions x 6 orders, G00 hi/lo, padding
-constexpr int kGHi = 48;
-constexpr int kGLo = 49;
+// doubles per basis-table entry: 9 functions x 6 orders (the eighth PN
+// function, then f^-34/9 of the eccentric term), the value of f^-5/3 and of
+// f^-34/9 at the centre in double-double, padding
+constexpr int kGStride = 64;
+constexpr int kGHi = 54;
+constexpr int kGLo = 55;
+constexpr int kGEHi = 56;
+constexpr int kGELo = 57;
 constexpr int kMaxLevel = 12;  // sub-block lengths 2^3 .. 2^11
 constexpr int kTrig = 512;        // entries of the (cos, sin)(2 pi i / kTrig) table
 constexpr int kCoefStride = 56;  // doubles per particle record of the coefficient buffer
@@ -31,6 +36,7 @@ struct ModelArgs {
     double orb0_cyc;  // orbital phase at t = 0 [cycles]
     double cart0;     // cartwheel phase at t = 0 [rad]
     double cart_c, cart_s;  // cos, sin of cart0
+    int ecc;                // 1: eccentric phase, theta rows carry an 8th entry e0
 };
 
 struct PhysConst {
@@ -121,12 +127,13 @@ struct FinalArgs {
 };
 
 struct PsoBox {
-    double lo[7], hi[7];
-    int periodic[7];
+    double lo[8], hi[8];
+    int periodic[8];
+    int dim;  // 7, or 8 with e0
 };
 struct PsoParams {
     double omega, phi_p, phi_g;
-    double eps[7];
+    double eps[8];
 };
 
 hipError_t upload_cheb(const double* x, const double* m);

@@ -85,6 +85,10 @@ __device__ inline double dphase_pn(const double* cf, double f)
     s += (1.0 / 3.0) * cf[5] * u2;
     s += cf[6] * u2 * (lnf * (1.0 / 3.0) + 1.0);
     s += (2.0 / 3.0) * cf[7] * u;
+    if (cf[8] != 0.0) {
+        // eccentric term: d/df [b_e f^-34/9] = -(34/9) b_e f^-43/9, f^-43/9 = u^14 u^(1/3)
+        s += -(34.0 / 9.0) * cf[8] * (u8 * u6) * cbrt(u);
+    }
     return s;
 }
 
@@ -94,15 +98,17 @@ __global__ void k_prologue(PrologueArgs a)
     if (p >= a.P) return;
     const int64_t S = a.stride;
     double* cf = a.coef;
-    const double* th = a.theta + kTheta * p;
-    double t[kTheta];
+    const int td = a.m.ecc ? kThetaMax : kTheta;
+    const double* th = a.theta + (int64_t)td * p;
+    double t[kThetaMax];
     bool ok = true;
-    for (int i = 0; i < kTheta; ++i) {
+    for (int i = 0; i < td; ++i) {
         t[i] = th[i];
         ok = ok && isfinite(t[i]);
     }
     const double Mc = t[0], eta = t[1], flow = t[2];
-    ok = ok && Mc > 0.0 && eta > 0.0 && eta <= 0.25 && flow > 0.0;
+    const double e0 = a.m.ecc ? t[7] : 0.0;
+    ok = ok && Mc > 0.0 && eta > 0.0 && eta <= 0.25 && flow > 0.0 && e0 >= 0.0 && e0 < 0.5;
     if (!ok) {
         a.klo[p] = 0;
         a.khi[p] = 0;
@@ -128,8 +134,18 @@ __global__ void k_prologue(PrologueArgs a)
                          127825.0 * eta3 / 1296.0;
     const double b6 = -6848.0 / 21.0;
     const double psi7 = kPi * (77096675.0 / 254016.0 + 378515.0 * eta / 1512.0 - 74045.0 * eta2 / 756.0);
-    double b[8];
+    // eccentric term (TaylorF2Ecc at leading order in e0^2, Newtonian order):
+    // the Newtonian phase times -(2355/1462) e0^2 (f_low / f)^(19/9), i.e.
+    // b_e f^-34/9 with b_e = -(2355/1462) e0^2 f_low^(19/9) c0, double-double
+    dd be{0.0, 0.0};
+    if (e0 != 0.0) {
+        const dd k = dd_mul(dd_ratio(2355.0, 1462.0), two_prod(e0, e0));
+        be = dd_mul(dd_mul(k, dd_pow_ratio(dd{flow, 0.0}, 19, 9)), c0);
+        be = dd{-be.hi, -be.lo};
+    }
+    double b[9];
     b[0] = c0.hi;
+    b[8] = be.hi;
     b[1] = J >= 2 ? pref * psi2 / piM : 0.0;
     b[2] = J >= 3 ? pref * psi3 / (mu * mu) : 0.0;
     b[3] = J >= 4 ? pref * psi4 / mu : 0.0;
@@ -142,11 +158,17 @@ __global__ void k_prologue(PrologueArgs a)
     // ---- t_c from t(f_low) = 0: t_c = -dPhi_PN/df(f_low); Newtonian part in double-double
     const dd five3 = dd_ratio(5.0, 3.0);
     const dd tN = dd_mul(dd_mul(five3, c0), dd_pow_m83(dd{flow, 0.0}));
-    double cf_rest[8];
+    double cf_rest[9];
     cf_rest[0] = 0.0;
     for (int i = 1; i < 8; ++i) cf_rest[i] = b[i];
+    cf_rest[8] = 0.0;
     const double trest = -dphase_pn(cf_rest, flow);
-    const dd tc = dd_add(tN, dd{trest, 0.0});
+    dd tc = dd_add(tN, dd{trest, 0.0});
+    if (e0 != 0.0) {
+        // eccentric part of -dPhi/df(f_low): -(157/43) e0^2 times the Newtonian one
+        const dd te = dd_mul(dd_mul(dd_ratio(157.0, 43.0), two_prod(e0, e0)), tN);
+        tc = dd_add(tc, dd{-te.hi, -te.lo});
+    }
     const dd tau = dd_mul_d(tc, a.g.df);  // t_c / T, T = 1/df
     // ---- support window
     int64_t klo = 0, khi = a.g.K;
@@ -188,7 +210,9 @@ __global__ void k_prologue(PrologueArgs a)
             const double h = (double)(1 << (l - 1));
             const double r = h * a.g.df / fs;
             const double r2 = r * r, r6 = r2 * r2 * r2;
-            const double ephi = 2.4 * taus * fs * r6;
+            // the eccentric term's sixth Taylor coefficient is ~17 times the
+            // Newtonian one per unit size, and its size is <= 1.61 e0^2 of it
+            const double ephi = 2.4 * taus * fs * r6 * (1.0 + 27.0 * e0 * e0);
             bool good = ephi <= 1e-12;
             if (a.m.response != 0) {
                 // fourth orbital harmonic; the full response's arm-length
@@ -260,6 +284,8 @@ __global__ void k_prologue(PrologueArgs a)
     cf[p * kCoefStride + C_C0L] = c0.lo;
     for (int i = 1; i < 8; ++i) cf[p * kCoefStride + (C_B1 + i - 1)] = b[i];
     cf[p * kCoefStride + C_PHIC] = phic;
+    cf[p * kCoefStride + C_BEH] = be.hi;
+    cf[p * kCoefStride + C_BEL] = be.lo;
     cf[p * kCoefStride + C_TAUH] = tau.hi;
     cf[p * kCoefStride + C_TAUL] = tau.lo;
     cf[p * kCoefStride + C_TC] = tcs;
@@ -286,9 +312,11 @@ __global__ void k_gtab(GridArgs g, int lg, int64_t nsub, double* __restrict__ ta
     const double u = rcbrt(fc.hi);  // f^-1/3
     const double u2 = u * u;
     const double lnf = log(fc.hi) + fc.lo / fc.hi;
-    const double pw[6] = {u2 * u2 * u, u2 * u, u2, u, 1.0 / u, 1.0 / u2};
-    const double sig[6] = {-5.0 / 3.0, -1.0, -2.0 / 3.0, -1.0 / 3.0, 1.0 / 3.0, 2.0 / 3.0};
-    const int slot[6] = {0, 1, 2, 3, 5, 7};
+    // the power functions, the last the eccentric term's f^-34/9 = u^11 u^(1/3)
+    const double u11 = u2 * u2 * u2 * u2 * u2 * u;
+    const double pw[7] = {u2 * u2 * u, u2 * u, u2, u, 1.0 / u, 1.0 / u2, u11 * cbrt(u)};
+    const double sig[7] = {-5.0 / 3.0, -1.0, -2.0 / 3.0, -1.0 / 3.0, 1.0 / 3.0, 2.0 / 3.0, -34.0 / 9.0};
+    const int slot[7] = {0, 1, 2, 3, 5, 7, 8};
     double epow[kNodes], lnser[kNodes], f13[kNodes];
     double e = 1.0;
     for (int m = 0; m < kNodes; ++m) {
@@ -298,7 +326,7 @@ __global__ void k_gtab(GridArgs g, int lg, int64_t nsub, double* __restrict__ ta
     lnser[0] = lnf;
     for (int m = 1; m < kNodes; ++m) lnser[m] = ((m & 1) ? 1.0 : -1.0) * epow[m] / m;
     double* out = tab + sidx * kGStride;
-    for (int i = 0; i < 6; ++i) {
+    for (int i = 0; i < 7; ++i) {
         double bin = 1.0;
         for (int m = 0; m < kNodes; ++m) {
             const double gim = pw[i] * bin * epow[m];
@@ -316,7 +344,10 @@ __global__ void k_gtab(GridArgs g, int lg, int64_t nsub, double* __restrict__ ta
     const dd g0 = dd_pow_m53(fc);
     out[kGHi] = g0.hi;
     out[kGLo] = g0.lo;
-    for (int q = kGLo + 1; q < kGStride; ++q) out[q] = 0.0;
+    const dd ge = dd_pow_ratio(fc, -34, 9);
+    out[kGEHi] = ge.hi;
+    out[kGELo] = ge.lo;
+    for (int q = kGELo + 1; q < kGStride; ++q) out[q] = 0.0;
 }
 
 struct PhasePoly {
@@ -353,6 +384,15 @@ __device__ inline void block_setup(const GLOBAL double* __restrict__ cf, int64_t
         for (int mm = 0; mm < kNodes; ++mm)
             if (!(i == 0 && mm == 0)) a[mm] = __builtin_fma(ci[i], G[i * kNodes + mm], a[mm]);
     }
+    double ecc_c = 0.0;  // the eccentric term's constant, reduced in double-double
+    if (m.ecc) {
+        const double beh = cf[p * kCoefStride + C_BEH];
+        if (beh != 0.0) {
+#pragma unroll
+            for (int mm = 1; mm < kNodes; ++mm) a[mm] = __builtin_fma(beh, G[8 * kNodes + mm], a[mm]);
+            ecc_c = dd_frac(dd_mul(dd{beh, cf[p * kCoefStride + C_BEL]}, dd{G[kGEHi], G[kGELo]}));
+        }
+    }
     {
         // constant term: frac(Kc tau) + frac(c0 f^-5/3) + frac(rest), cycles
         const double tauh = cf[p * kCoefStride + C_TAUH], taul = cf[p * kCoefStride + C_TAUL];
@@ -360,7 +400,7 @@ __device__ inline void block_setup(const GLOBAL double* __restrict__ cf, int64_t
         lin.lo = __builtin_fma(Kc, taul, lin.lo);
         const dd n0 = dd_mul(dd{c0h, cf[p * kCoefStride + C_C0L]}, dd{G[kGHi], G[kGLo]});
         const double rest = a[0] + cf[p * kCoefStride + C_PHIC];
-        const double c = dd_frac(lin) + dd_frac(n0) + (rest - rint(rest));
+        const double c = dd_frac(lin) + dd_frac(n0) + (rest - rint(rest)) + ecc_c;
         a[0] = c - rint(c);
         a[1] += tauh + taul;
     }
@@ -516,9 +556,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     // the particle's coefficients are the same in every lane: scalar loads
     // (the kernel writes only the edges, so the scalar cache stays valid)
     const CONSTANT double* cfc = (const CONSTANT double*)a.coef;
-    double bcoef[8];
+    double bcoef[9];
     bcoef[0] = cfc[p * kCoefStride + C_C0H];
     for (int i = 1; i < 8; ++i) bcoef[i] = cfc[p * kCoefStride + (C_B1 + i - 1)];
+    bcoef[8] = cfc[p * kCoefStride + C_BEH];
     const double tc = cfc[p * kCoefStride + C_TC];
     const int64_t G = a.G;
     const int64_t len = khi - klo;
@@ -1559,9 +1600,9 @@ __global__ void k_streams_final(StreamArgs a)
 __global__ void k_pso_init(int64_t P, PsoBox box, uint64_t seed, uint32_t swarm, double* __restrict__ theta)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= P * kTheta) return;
-    const int64_t pp = i / kTheta;
-    const int d = (int)(i % kTheta);
+    if (i >= P * box.dim) return;
+    const int64_t pp = i / box.dim;
+    const int d = (int)(i % box.dim);
     const double r = uniform01(seed, swarm, 0u, (uint32_t)pp, (uint32_t)d, 3u);
     const double w = box.hi[d] - box.lo[d];
     const double x = r * w;
@@ -1573,9 +1614,9 @@ __global__ void k_pso_move(int64_t P, PsoBox box, PsoParams prm, uint64_t seed, 
                            const double* __restrict__ gbest)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= P * kTheta) return;
-    const int64_t pp = i / kTheta;
-    const int d = (int)(i % kTheta);
+    if (i >= P * box.dim) return;
+    const int64_t pp = i / box.dim;
+    const int d = (int)(i % box.dim);
     const double x = theta[i];
     const double rp = uniform01(seed, swarm, it, (uint32_t)pp, (uint32_t)d, 0u);
     const double rg = uniform01(seed, swarm, it, (uint32_t)pp, (uint32_t)d, 1u);
@@ -1617,18 +1658,19 @@ __global__ void k_pso_pbest(int64_t P, PsoBox box, const double* __restrict__ th
     if (pp >= P) return;
     double v = vals[pp];
     bool inbox = true;
-    for (int d = 0; d < kTheta; ++d) {
-        const double x = theta[pp * kTheta + d];
+    const int D = box.dim;
+    for (int d = 0; d < D; ++d) {
+        const double x = theta[pp * D + d];
         if (!box.periodic[d] && !(x >= box.lo[d] && x <= box.hi[d])) inbox = false;
     }
     if (!inbox || isnan(v)) v = -INFINITY;
     if (v > pbest_val[pp]) {
         pbest_val[pp] = v;
-        for (int d = 0; d < kTheta; ++d) pbest[pp * kTheta + d] = theta[pp * kTheta + d];
+        for (int d = 0; d < D; ++d) pbest[pp * D + d] = theta[pp * D + d];
     }
 }
 
-__global__ __launch_bounds__(1024) void k_pso_gbest(int64_t P, const double* __restrict__ pbest,
+__global__ __launch_bounds__(1024) void k_pso_gbest(int64_t P, int D, const double* __restrict__ pbest,
                                                      const double* __restrict__ pbest_val, double* __restrict__ gbest,
                                                      double* __restrict__ gbest_val)
 {
@@ -1658,7 +1700,7 @@ __global__ __launch_bounds__(1024) void k_pso_gbest(int64_t P, const double* __r
     if (tid == 0) {
         if (si[0] >= 0 && sv[0] > *gbest_val) {
             *gbest_val = sv[0];
-            for (int d = 0; d < kTheta; ++d) gbest[d] = pbest[si[0] * kTheta + d];
+            for (int d = 0; d < D; ++d) gbest[d] = pbest[si[0] * D + d];
         }
     }
 }
@@ -1861,19 +1903,19 @@ void launch_waveform(const MainArgs& a, double* h_ri, hipStream_t s)
 }
 void launch_pso_init(int64_t P, const PsoBox& box, uint64_t seed, uint32_t swarm, double* theta, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_pso_init, dim3(nblk(P * kTheta, 256)), dim3(256), 0, s, P, box, seed, swarm, theta);
+    hipLaunchKernelGGL(k_pso_init, dim3(nblk(P * box.dim, 256)), dim3(256), 0, s, P, box, seed, swarm, theta);
 }
 void launch_pso_move(int64_t P, const PsoBox& box, const PsoParams& prm, uint64_t seed, uint32_t swarm, uint32_t it,
                      double* theta, double* vel, const double* pbest, const double* gbest, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_pso_move, dim3(nblk(P * kTheta, 256)), dim3(256), 0, s, P, box, prm, seed, swarm, it, theta,
+    hipLaunchKernelGGL(k_pso_move, dim3(nblk(P * box.dim, 256)), dim3(256), 0, s, P, box, prm, seed, swarm, it, theta,
                        vel, pbest, gbest);
 }
 void launch_pso_best(int64_t P, const PsoBox& box, const double* theta, const double* vals, double* pbest,
                      double* pbest_val, double* gbest, double* gbest_val, hipStream_t s)
 {
     hipLaunchKernelGGL(k_pso_pbest, dim3(nblk(P, 256)), dim3(256), 0, s, P, box, theta, vals, pbest, pbest_val);
-    hipLaunchKernelGGL(k_pso_gbest, dim3(1), dim3(1024), 0, s, P, pbest, pbest_val, gbest, gbest_val);
+    hipLaunchKernelGGL(k_pso_gbest, dim3(1), dim3(1024), 0, s, P, box.dim, pbest, pbest_val, gbest, gbest_val);
 }
 void launch_fill(double* p, int64_t n, double v, hipStream_t s)
 {

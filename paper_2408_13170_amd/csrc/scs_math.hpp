@@ -22,12 +22,14 @@ constexpr double kAuOverC = 1.495978707e11 / 299792458.0;  // light travel time 
 constexpr double kInvYear = 1.0 / 31557600.0;              // Julian year
 constexpr double kArmS = 2.5e9 / 299792458.0;              // light time of one constellation arm [s]
 constexpr double kEulerGamma = 0.57721566490153286060651209;
-constexpr int kTheta = 7;
+constexpr int kTheta = 7;     // theta entries of a circular model
+constexpr int kThetaMax = 8;  // with the eccentricity e0
 
 // coefficient-buffer field indices (field-major SoA, stride = particle capacity)
 enum Coef : int {
     C_C0H = 0, C_C0L,      // Newtonian coefficient of f^-5/3, double-double
     C_B1, C_B2, C_B3, C_B4, C_B5, C_B6, C_B7,  // coefficients of f^-1, f^-2/3, f^-1/3, ln f, f^1/3, f^1/3 ln f, f^2/3
+    C_BEH, C_BEL,          // coefficient of f^-34/9 (eccentric term), double-double
     C_PHIC,                // constant phase [cycles]
     C_TAUH, C_TAUL,        // t_c * df, double-double
     C_TC,                  // t_c [s]
@@ -119,6 +121,39 @@ __device__ inline dd dd_pow_m83(dd x)
     const dd pr = dd_mul(y3, x8);
     const double r = (pr.hi - 1.0) + pr.lo;
     return two_sum(y0, -y0 * r * (1.0 / 3.0));
+}
+
+// Integer power of a double-double by repeated squaring (n >= 1).
+__device__ inline dd dd_powi(dd x, int n)
+{
+    dd r{1.0, 0.0};
+    bool first = true;
+    while (n > 0) {
+        if (n & 1) {
+            r = first ? x : dd_mul(r, x);
+            first = false;
+        }
+        n >>= 1;
+        if (n) x = dd_mul(x, x);
+    }
+    return r;
+}
+// x^(p/q) in double-double for x > 0 (q > 0, p != 0): one Newton step on
+// y^q = x^p from the double estimate.
+__device__ inline dd dd_pow_ratio(dd x, int p, int q)
+{
+    const double y0 = pow(x.hi, (double)p / (double)q);
+    const dd yq = dd_powi(dd{y0, 0.0}, q);
+    double r;
+    if (p < 0) {  // r = y0^q x^|p| - 1
+        const dd pr = dd_mul(yq, dd_powi(x, -p));
+        r = (pr.hi - 1.0) + pr.lo;
+    } else {  // r = (y0^q - x^p) / x^p
+        const dd xp = dd_powi(x, p);
+        const dd df = dd_add(yq, dd{-xp.hi, -xp.lo});
+        r = (df.hi + df.lo) / xp.hi;
+    }
+    return two_sum(y0, -y0 * r / (double)q);
 }
 
 // ---------------------------------------------------------------- sin/cos(2 pi r)

@@ -56,8 +56,9 @@ static int err(int code, const char* msg) { return scs_record_error(code, msg); 
 struct scs_search {
     scs_ctx* ctx = nullptr;
     scs_search_params p{};
-    double lo[7], hi[7];
-    int32_t per[7];
+    int dim = 7;  // theta entries of the context (7, or 8 with e0)
+    double lo[8], hi[8];
+    int32_t per[8];
     std::vector<scs_swarm*> swarms;
     std::vector<int64_t> sizes;
     uint32_t next_id = 0;
@@ -166,7 +167,14 @@ extern "C" int scs_search_create(scs_ctx* ctx, const scs_search_params* p, const
     if (!s) return err(SCS_ENOMEM, "host allocation failed");
     s->ctx = ctx;
     s->p = *p;
-    for (int d = 0; d < 7; ++d) {
+    int32_t dim = 0;
+    int rc0 = scs_theta_dim(ctx, &dim);
+    if (rc0) {
+        scs_search_destroy(s);
+        return rc0;
+    }
+    s->dim = dim;
+    for (int d = 0; d < dim; ++d) {
         s->lo[d] = lo[d];
         s->hi[d] = hi[d];
         s->per[d] = periodic ? periodic[d] : 0;
@@ -193,22 +201,23 @@ static int regroup(scs_search* s)
     const int nsw = (int)s->swarms.size();
     int64_t P = 0;
     for (int64_t n : s->sizes) P += n;
-    std::vector<double> th((size_t)P * 7), vel((size_t)P * 7);
+    const int D = s->dim;
+    std::vector<double> th((size_t)P * D), vel((size_t)P * D);
     int64_t off = 0;
     for (int i = 0; i < nsw; ++i) {
-        int rc = scs_swarm_read(s->swarms[i], &th[(size_t)off * 7], &vel[(size_t)off * 7], nullptr, nullptr, nullptr,
+        int rc = scs_swarm_read(s->swarms[i], &th[(size_t)off * D], &vel[(size_t)off * D], nullptr, nullptr, nullptr,
                                 nullptr, nullptr);
         if (rc) return rc;
         off += s->sizes[i];
     }
     int dim = 0;
-    for (int d = 0; d < 7; ++d) dim += s->per[d] ? 2 : 1;
+    for (int d = 0; d < D; ++d) dim += s->per[d] ? 2 : 1;
     std::vector<double> f((size_t)P * dim);
     for (int64_t i = 0; i < P; ++i) {
         int j = 0;
-        for (int d = 0; d < 7; ++d) {
+        for (int d = 0; d < D; ++d) {
             const double w = s->hi[d] - s->lo[d];
-            const double u = w > 0.0 ? (th[(size_t)i * 7 + d] - s->lo[d]) / w : 0.0;
+            const double u = w > 0.0 ? (th[(size_t)i * D + d] - s->lo[d]) / w : 0.0;
             if (s->per[d]) {
                 const double a = 2.0 * M_PI * u;
                 f[(size_t)i * dim + j++] = std::cos(a) / (2.0 * M_PI);
@@ -229,10 +238,10 @@ static int regroup(scs_search* s)
         std::vector<double> tc, vc;
         for (int64_t i = 0; i < P; ++i)
             if (lab[i] == c) {
-                tc.insert(tc.end(), &th[(size_t)i * 7], &th[(size_t)i * 7 + 7]);
-                vc.insert(vc.end(), &vel[(size_t)i * 7], &vel[(size_t)i * 7 + 7]);
+                tc.insert(tc.end(), &th[(size_t)i * D], &th[(size_t)i * D + D]);
+                vc.insert(vc.end(), &vel[(size_t)i * D], &vel[(size_t)i * D + D]);
             }
-        const int64_t pc = (int64_t)tc.size() / 7;
+        const int64_t pc = (int64_t)tc.size() / D;
         scs_swarm* sw = nullptr;
         if ((rc = scs_swarm_create(s->ctx, &sw, pc, s->lo, s->hi, s->per, s->p.seed, s->next_id++))) break;
         nsws.push_back(sw);
@@ -321,8 +330,8 @@ extern "C" int scs_search_swarms(scs_search* s, int32_t* n_swarms, int64_t* size
     for (size_t i = 0; i < s->swarms.size(); ++i) {
         if (sizes) sizes[i] = s->sizes[i];
         if (best) {
-            int rc = scs_swarm_read(s->swarms[i], nullptr, nullptr, nullptr, nullptr, best + 8 * i, best + 8 * i + 7,
-                                    nullptr);
+            int rc = scs_swarm_read(s->swarms[i], nullptr, nullptr, nullptr, nullptr, best + (s->dim + 1) * i,
+                                    best + (s->dim + 1) * i + s->dim, nullptr);
             if (rc) return rc;
         }
     }

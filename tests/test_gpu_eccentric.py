@@ -1,0 +1,189 @@
+"""The eccentric model (TaylorF2Ecc phase at leading order in e0^2, Sec 4)
+through the C ABI against the oracle: templates, Upsilon_N in FP64 and mixed
+precision with e0 across the paper's prior [0.005, 0.1], a noise-free
+eccentric injection, the eight-dimensional PSO (bit for bit) and a search
+over eight dimensions.
+
+Tolerances as for the circular model (template 1e-10 of max|h|, Upsilon_N
+1e-9 / 1e-5 floored relative, edges exact on at least 95% of rows).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from tests import datasets as D
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2408_13170_amd import B  # noqa: E402
+
+E0_LO, E0_HI = 0.005, 0.1
+LO8 = np.concatenate([synth.GW150914_PRIOR_LO, [E0_LO]])
+HI8 = np.concatenate([synth.GW150914_PRIOR_HI, [E0_HI]])
+PER8 = np.concatenate([synth.PERIODIC, [0]])
+
+
+def _dataset(e0=0.01, noise=True, seed=61, response=O.RESP_LISA_LF_AE):
+    base = D.lisa_small(noise=False, response=response)
+    m = O.Model(pn_order=7, response=response, support=O.SUPPORT_TOBS, t_obs=base.model.t_obs, eccentric=1)
+    inj = np.concatenate([synth.GW150914_LIKE, [e0]])
+    return D.make(base.grid, m, base.psd, inj, 17.0, seed, noise, LO8, HI8)
+
+
+def _ctx(ds, N, G=1):
+    g = ds.grid
+    h = B.scs_ctx_create(0)
+    B.scs_load_data(h, np.ascontiguousarray(ds.d_ri), np.ascontiguousarray(ds.psd), g.k0 * g.df, g.df)
+    m = ds.model
+    B.scs_set_model(h, m.pn_order, m.response, m.support, m.t_obs, eccentric=m.eccentric)
+    B.scs_define_segmentation(h, N, B.SCS_SEG_EQUAL_SNR, G)
+    assert B.scs_theta_dim(h) == 8
+    return h
+
+
+def _particles(n, seed):
+    th = D.lisa_particles(n, seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    return np.concatenate([th, rng.uniform(E0_LO, E0_HI, (n, 1))], axis=1)
+
+
+def test_template_matches_oracle():
+    for response in (O.RESP_LISA_LF_AE, O.RESP_LISA_FD):
+        ds = _dataset(noise=False, response=response)
+        h = _ctx(ds, 1)
+        try:
+            ths = [ds.injection] + list(_particles(4, seed=62))
+            for th in ths:
+                out = torch.empty((2, ds.grid.K, 2), dtype=torch.float64, device="cuda")
+                B.scs_waveform(h, torch.tensor(np.ascontiguousarray(th), device="cuda"), out)
+                torch.cuda.synchronize()
+                got = out.cpu().numpy()
+                gc = got[..., 0] + 1j * got[..., 1]
+                ref = O.template(ds.grid, ds.model, th)
+                nz = np.abs(ref) > 0
+                assert np.array_equal(nz, np.abs(gc) > 0), "supports differ"
+                err = np.abs(gc - ref)[nz].max() / np.abs(ref).max()
+                print(f"response {response}, e0 = {th[7]:.4f}: template max err / max|h| {err:.3g}")
+                assert err < 1e-10
+        finally:
+            B.scs_ctx_destroy(h)
+
+
+@pytest.mark.parametrize("N,G", [(1, 1), (8, 16), (64, 1)])
+def test_upsilon_matches_oracle(N, G):
+    ds = _dataset(seed=63)
+    th = _particles(40, seed=64)
+    th[0] = ds.injection
+    th[1, 7] = 0.0         # circular within the eccentric model
+    th[2, 7] = -0.01       # invalid e0: NaN
+    ref = O.evaluate(ds.grid, ds.model, ds.d_ri, ds.psd, th, N, O.SEG_EQUAL_SNR, G, want_bounds=True)
+    h = _ctx(ds, N, G)
+    try:
+        tht = torch.tensor(np.ascontiguousarray(th), device="cuda")
+        u = torch.empty(th.shape[0], dtype=torch.float64, device="cuda")
+        B.scs_evaluate(h, tht, u)
+        torch.cuda.synchronize()
+        got = u.cpu().numpy()
+        assert np.isnan(got[2]) and np.isnan(ref["ups"][2])
+        ok = np.isfinite(ref["ups"])
+        sup, bnd = B.scs_last_bounds(h, th.shape[0], N)
+        assert np.array_equal(sup[ok], ref["support"][ok])
+        same = ok & np.all(bnd == ref["bounds"], axis=1)
+        assert same.sum() >= 0.95 * ok.sum()
+        e = np.abs(got[same] - ref["ups"][same]) / np.maximum(np.abs(ref["ups"][same]), 2.0 * N)
+        print(f"N={N}: {same.sum()} rows, fp64 max floored rel err {e.max():.3g}")
+        assert e.max() < 1e-9
+        B.scs_evaluate(h, tht, u, B.SCS_PREC_MIXED)
+        torch.cuda.synchronize()
+        em = np.abs(u.cpu().numpy()[same] - ref["ups"][same]) / np.maximum(np.abs(ref["ups"][same]), 2.0 * N)
+        print(f"N={N}: mixed max floored rel err {em.max():.3g}")
+        assert em.max() < 1e-5
+        # e0 = 0 inside the eccentric model equals the circular model, bit for bit
+        hc = B.scs_ctx_create(0)
+        try:
+            g = ds.grid
+            B.scs_load_data(hc, np.ascontiguousarray(ds.d_ri), np.ascontiguousarray(ds.psd), g.k0 * g.df, g.df)
+            B.scs_set_model(hc, 7, ds.model.response, ds.model.support, ds.model.t_obs)
+            B.scs_define_segmentation(hc, N, B.SCS_SEG_EQUAL_SNR, G)
+            uc = np.empty(1)
+            B.scs_evaluate(hc, np.ascontiguousarray(th[1:2, :7]), uc)
+            assert uc[0] == got[1]
+        finally:
+            B.scs_ctx_destroy(hc)
+    finally:
+        B.scs_ctx_destroy(h)
+
+
+def test_noise_free_eccentric_injection():
+    ds = _dataset(e0=0.08, noise=False)
+    for N in (1, 16):
+        h = _ctx(ds, N, G=16)
+        try:
+            st = np.empty((1, B.SCS_NSTATS))
+            B.scs_evaluate_stats(h, np.ascontiguousarray(ds.injection[None, :]), st)
+            print(f"N={N}: Upsilon at the e0 = 0.08 injection {st[0, 0]:.12f}")
+            assert abs(st[0, 0] / ds.snr ** 2 - 1) < 1e-9
+            circ = ds.injection.copy()
+            circ[7] = 0.0
+            B.scs_evaluate_stats(h, np.ascontiguousarray(circ[None, :]), st)
+            assert st[0, 0] < 0.9 * ds.snr ** 2
+        finally:
+            B.scs_ctx_destroy(h)
+
+
+def test_pso_in_eight_dimensions_bitwise():
+    P = 500
+    th = O.pso_init(P, LO8, HI8, 5, 2)
+    rng = np.random.default_rng(3)
+    v = rng.normal(size=(P, 8)) * (HI8 - LO8) * 0.05
+    pb = O.pso_init(P, LO8, HI8, 6, 2)
+    gb = th[10].copy()
+    eps = np.array([0.01, 0.05, 1e-8, 0.01, 0.01, 0.2, 0.1, 0.1])
+    prm = B.pso_params(0.5, 0.2, 0.4, eps)
+    t = [torch.tensor(np.ascontiguousarray(a), device="cuda") for a in (th, v, pb, gb)]
+    B.scs_pso_move(*t, prm, LO8, HI8, PER8, 5, 2, 9)
+    torch.cuda.synchronize()
+    O.pso_move(th, v, pb, gb, 0.5, 0.2, 0.4, eps, LO8, HI8, PER8, 5, 2, 9)
+    assert np.array_equal(t[0].cpu().numpy(), th) and np.array_equal(t[1].cpu().numpy(), v)
+    # a swarm on an eccentric context starts at the oracle's draw and steps
+    ds = _dataset(seed=65)
+    h = _ctx(ds, 8, G=16)
+    try:
+        sw = B.scs_swarm_create(h, 256, LO8, HI8, PER8, seed=11, swarm_id=3)
+        st0 = B.scs_swarm_read(sw, 256, dim=8)
+        assert np.array_equal(st0["theta"], O.pso_init(256, LO8, HI8, 11, 3))
+        for _ in range(3):
+            B.scs_pso_step(sw, prm)
+        st = B.scs_swarm_read(sw, 256, dim=8)
+        assert st["iteration"] == 3 and np.isfinite(st["gbest_val"])
+        # the swarm best is the evaluation of its position
+        u = np.empty(1)
+        B.scs_evaluate(h, np.ascontiguousarray(st["gbest"][None, :]), u)
+        assert u[0] == st["gbest_val"]
+        B.scs_swarm_destroy(sw)
+    finally:
+        B.scs_ctx_destroy(h)
+
+
+def test_search_in_eight_dimensions():
+    ds = _dataset(e0=0.05, seed=66)
+    inj = ds.injection
+    w = np.array([0.15, 0.02, 2e-6, 0.15, 0.15, 0.3, 0.3, 0.04])
+    lo, hi = inj - w, inj + w
+    hi[1] = min(hi[1], 0.25)
+    h = _ctx(ds, 1, G=16)
+    try:
+        s = B.scs_search_create(h, 3, 128, lo, hi, PER8, G=16, conv_window=6, kmeans_iters=30, seed=4)
+        try:
+            for N, eps in ((8, [0.01, 0.005, 5e-9, 0.01, 0.01, 0.02, 0.01, 0.01]), (1, [0.0] * 8)):
+                rep = B.scs_search_run_rung(s, N, 20, B.pso_params(0.5, 0.2, 0.4, eps))
+                sizes, best = B.scs_search_swarms(s, dim=8)
+                print(rep, list(sizes), best[:, 8])
+                assert sizes.sum() == 3 * 128 and best.shape[1] == 9
+                assert np.all((best[:, 7] >= lo[7]) & (best[:, 7] <= hi[7]))
+        finally:
+            B.scs_search_destroy(s)
+    finally:
+        B.scs_ctx_destroy(h)
