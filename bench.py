@@ -244,7 +244,8 @@ def main():
         "latency_ms": {"p50": float(np.median(r64["step_ms"])), "p99": float(np.quantile(r64["step_ms"], 0.99))},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None if fd else measured_traffic(),
-                     "kernel": "k_main_multi<2,false> (FP64 generate-and-reduce)",
+                     "kernel": "k_main_multi<2,false,1> (FP64 generate-and-reduce, low-frequency response)" if not fd else
+                     "k_main_multi<2,false,2> (FP64 generate-and-reduce, full response)",
                      "avg_launch_ms": avg_main_ms, "flop_per_eval": FLOP_PER_EVAL_FP64,
                      "evals_per_launch": evals_per_launch},
         "unresolved_particles": r64["unresolved"],
