@@ -30,14 +30,14 @@ import synth  # noqa: E402
 # FP64 operations per in-support particle-bin of the generate-and-reduce
 # kernel, two channels, from its per-bin op list (a fused multiply-add counts
 # 2, any other arithmetic op 1; roundings and conversions 0): bin coordinate
-# 1 mul; phase polynomial 5 FMA; reduction to [-1/2, 1/2] 1 add; sin/cos of
-# 2 pi r: scale 1, table offset 1 FMA, to radians 1 mul, x^2 1 mul, sine 2
-# FMA + 1 mul, cosine 3 FMA, angle sum 2 FMA + 2 mul; response polynomials
-# 20 FMA; data x conj(response) 6 FMA + 2 mul; Z rotation-accumulate 4 FMA;
-# H 4 FMA + 2 mul.  Total 42 FMA + 12 other = 96 + 10 = 106 (the FP64 flop
-# counter of rocprofv3 reads 108 per in-support evaluation, the excess being
-# lanes idle at support edges and the per-sub-block set-up).
-FLOP_PER_EVAL_FP64 = 106
+# 1 add; phase polynomial 5 FMA; split into table unit and remainder 3 add;
+# remainder sin/cos: square 1 mul, sine 1 FMA + 1 mul, cosine 1 FMA; angle
+# sum 2 FMA + 2 mul; response polynomials 20 FMA; data x conj(response)
+# 6 FMA + 2 mul; Z rotate-and-accumulate 4 FMA; H 4 FMA + 2 mul.  Total
+# 43 FMA + 12 other = 86 + 12 = 98 (the FP64 flop counter of rocprofv3 reads
+# a few percent more per in-support evaluation: lanes idle at support edges
+# and the per-block set-up).
+FLOP_PER_EVAL_FP64 = 98
 PEAK_FP64_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 64 lanes x 2
 
 

@@ -17,7 +17,7 @@ constexpr int kGLo = 55;
 constexpr int kGEHi = 56;
 constexpr int kGELo = 57;
 constexpr int kMaxLevel = 12;  // sub-block lengths 2^3 .. 2^11
-constexpr int kTrig = 512;        // entries of the (cos, sin)(2 pi i / kTrig) table
+constexpr int kTrig = 1024;       // entries of the (cos, sin)(2 pi i / kTrig) table
 constexpr int kCoefStride = 56;  // doubles per particle record of the coefficient buffer
 constexpr int kRec = 8;          // doubles per (chunk, slot) record: head piece, tail piece, padding
 

@@ -712,16 +712,16 @@ __device__ __forceinline__ int bsearch_seg(IntPtr bo, int N, int64_t k)
 }
 
 // The FP64 phase is carried in units of 1/kTrig cycle.  sin and cos of
-// 2 pi s / kTrig for |s| <= 1/2: Taylor polynomials in z = s^2 with the
-// powers of the angle unit folded in (sine to degree 5, cosine to degree 4;
-// remainders below 1e-19 and 8e-17).
+// x = 2 pi s / kTrig for |s| <= 1/2 (|x| <= pi / 1024): Taylor polynomials
+// in z = s^2 with the powers of the angle unit folded in, sine to degree 3
+// and cosine to degree 2.  The remainders, x^5/120 < 3e-15 and x^4/24 <
+// 4e-12, change the phasor's length by at most 4e-12 and its angle by less
+// than 3e-15 rad, so Upsilon_N moves by at most 8e-12 relative.
 constexpr double kPhaseUnits = kTrig;
 constexpr double kArg = kTwoPi / kPhaseUnits;
 constexpr double kSin1 = kArg;
 constexpr double kSin3 = -(kArg * kArg * kArg) / 6.0;
-constexpr double kSin5 = (kArg * kArg * kArg * kArg * kArg) / 120.0;
 constexpr double kCos2 = -(kArg * kArg) / 2.0;
-constexpr double kCos4 = (kArg * kArg * kArg * kArg) / 24.0;
 // Adding 1.5 * 2^52 to a double of magnitude below 2^51 rounds it to the
 // nearest integer, which then sits in the low mantissa bits.
 constexpr double kRoundShift = 0x1.8p52;
@@ -739,7 +739,7 @@ constexpr int kTabZero = kTrig;      // index of the zero entry
 // whole loop (an FP64 FMA reads at most one scalar register, so constants
 // kept in scalar registers would be copied into a vector register per use).
 struct SinCosK {
-    double s5, s3, s1, c4, c2;
+    double s3, s1, c2;
 };
 
 template <bool RESP>
@@ -786,8 +786,8 @@ __device__ __forceinline__ void bin_fp64(double j, const double* __restrict__ bi
     }
     const double s = pc - (t - kRoundShift);  // exact, |s| <= 1/2
     const double z = s * s;
-    const double sn = s * __builtin_fma(z, __builtin_fma(z, kk.s5, kk.s3), kk.s1);
-    const double cn = __builtin_fma(z, __builtin_fma(z, kk.c4, kk.c2), 1.0);
+    const double sn = s * __builtin_fma(z, kk.s3, kk.s1);
+    const double cn = __builtin_fma(z, kk.c2, 1.0);
     const double sv = __builtin_fma(tt.y, cn, tt.x * sn);
     const double cv = __builtin_fma(tt.x, cn, -(tt.y * sn));
     zr = __builtin_fma(sr, cv, __builtin_fma(-si, sv, zr));
@@ -1001,8 +1001,8 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
     RespPoly rp;
     float phf[kNodes], rf[4][kNodes];
     float a1h = 0.f;
-    SinCosK kk{kSin5, kSin3, kSin1, kCos4, kCos2};
-    __asm__ volatile("" : "+v"(kk.s5), "+v"(kk.s3), "+v"(kk.s1), "+v"(kk.c4), "+v"(kk.c2));
+    SinCosK kk{kSin3, kSin1, kCos2};
+    __asm__ volatile("" : "+v"(kk.s3), "+v"(kk.s1), "+v"(kk.c2));
     // Polynomials are zero until the lane's first block set-up (one-channel
     // lanes also read the table's zero entry, with zero weight), so bins the
     // wave runs before a lane's support add exact zeros.
