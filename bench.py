@@ -46,6 +46,7 @@ def log(*a):
 
 
 PROFILE = os.path.join(ROOT, "profiles", "k_main_multi_fp64_lisa1m.txt")
+STREAMS_PROFILE = os.path.join(ROOT, "profiles", "k_streams_lisa1m.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2408_13170_amd", "csrc", f)
                   for f in ("scs_kernels.hip", "scs_internal.hpp", "scs_math.hpp")]
 LAUNCH_SOURCE = os.path.join(ROOT, "paper_2408_13170_amd", "csrc", "scs_host.hip")
@@ -69,14 +70,15 @@ def kernel_digest():
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per launch of the FP64 generate-and-reduce kernel from the
-    committed rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, scaled by
-    a plain copy), or None when the kernel sources or the host code that picks
-    its launch shape changed since it was taken."""
+def measured_traffic(path=PROFILE):
+    """HBM bytes per launch of the profiled kernel (the FP64 generate-and-reduce
+    by default) from the committed rocprofv3 counter summary (FETCH_SIZE and
+    WRITE_SIZE, scaled by a plain copy), or None when the kernel sources or the
+    host code that picks the generate-and-reduce's launch shape changed since
+    it was taken."""
     try:
         kv = {}
-        with open(PROFILE) as fh:
+        with open(path) as fh:
             for line in fh:
                 if ":" in line and not line.startswith(" "):
                     k, v = line.split(":", 1)
@@ -556,7 +558,8 @@ def bench_streams(args):
            "config": {"workload": f"2^20-bin A+E band, {R} noise realisations ({gen_bytes / 1e9:.1f} GB in HBM), "
                                   f"{nsup} in-support bins, N in (1, 10, 50, 100)"},
            "roofline": {"bound": "hbm", "achieved": best, "peak": 8000.0, "unit": "GB/s", "frac": best / 8000.0,
-                        "traffic": None, "kernel": "k_streams (streamed segmented reduction)",
+                        "traffic": measured_traffic(STREAMS_PROFILE) if R == 1024 else None,
+                        "kernel": "k_streams (streamed segmented reduction)",
                         "bytes_per_launch": read_bytes},
            "generate_ms": gen_ms, "generate_GBps_written": gen_bytes / gen_ms / 1e6, "levels": levels}
     print(json.dumps(out), flush=True)
