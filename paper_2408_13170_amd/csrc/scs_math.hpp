@@ -268,7 +268,8 @@ __device__ inline void antenna_lf(double Phi, double cart0, const Pol& pol, doub
 // (X, Y, Z) and subtracts y_ji + z y_ij from channel k+1.  Every vector enters
 // through its projections on the plane's basis e1 = -r_hat/2 - (sqrt3/2) z_hat,
 // e2 = phi_hat, so an arm costs a few products.  All sines and cosines are of
-// arguments below a few turns (sincos2pi).  out = {Re A, Im A, Re E, Im E}.
+// arguments below a few turns (sincos2pi), seven per call.  out = {Re A,
+// Im A, Re E, Im E}.
 template <typename Src>
 __device__ inline void fd_response(double f, double c1, double s1, double cz, double sz, Src src, double out[4])
 {
@@ -292,35 +293,39 @@ __device__ inline void fd_response(double f, double c1, double s1, double cz, do
     }
     const double ap = src[FD_AP], ax = src[FD_AX];
     // craft angles zeta, zeta + 2pi/3, zeta + 4pi/3
-    const double ca[3] = {cz, __builtin_fma(-0.5, cz, -h3 * sz), __builtin_fma(-0.5, cz, h3 * sz)};
-    const double sa[3] = {sz, __builtin_fma(-0.5, sz, h3 * cz), __builtin_fma(-0.5, sz, -h3 * cz)};
+    const double ca3[3] = {cz, __builtin_fma(-0.5, cz, -h3 * sz), __builtin_fma(-0.5, cz, h3 * sz)};
+    const double sa3[3] = {sz, __builtin_fma(-0.5, sz, h3 * cz), __builtin_fma(-0.5, sz, -h3 * cz)};
     const double fl = f * kArmS;  // one arm in cycles of f
-    double sx, cx;                // z = cx - i sx
-    sincos2pi(fl, &sx, &cx);
+    // a = pi f L: its sine and cosine give z = e^{-2ia} by the double angle,
+    // the common factor e^{-ia} of every link phase, and (with those of a g)
+    // sin(a (1 +- g)) by angle addition
+    double sa, ca;
+    sincos2pi(0.5 * fl, &sa, &ca);
+    const double sx = 2.0 * sa * ca, cx = __builtin_fma(ca, ca, -(sa * sa));  // z = cx - i sx
     double acc[3][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};  // X, Y, Z
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const int i = k, j = (k + 1) % 3;
-        const double dc = (ca[i] - ca[j]) * inv_r3, ds = (sa[i] - sa[j]) * inv_r3;
+        const double dc = (ca3[i] - ca3[j]) * inv_r3, ds = (sa3[i] - sa3[j]) * inv_r3;
         const double a = __builtin_fma(dc, e1p, ds * e2p);  // n.P
         const double b = __builtin_fma(dc, e1q, ds * e2q);  // n.Q
         const double g = __builtin_fma(dc, e1n, ds * e2n);  // nhat.n
-        const double sp = __builtin_fma(ca[i] + ca[j], e1n, (sa[i] + sa[j]) * e2n);
+        const double sp = __builtin_fma(ca3[i] + ca3[j], e1n, (sa3[i] + sa3[j]) * e2n);
         const double npr = ap * __builtin_fma(a, a, -(b * b)), npi = -2.0 * ax * a * b;  // n.P.n
-        double sn, cs;
-        sincos2pi(-0.5 * f * __builtin_fma(-kArmS * inv_r3, sp, kArmS), &sn, &cs);
+        // link phase -a + pi f r sp
+        double sb, cb;
+        sincos2pi(0.5 * f * kArmS * inv_r3 * sp, &sb, &cb);
+        const double cs = __builtin_fma(ca, cb, sa * sb), sn = __builtin_fma(sb, ca, -(cb * sa));
         const double cr = __builtin_fma(cs, npr, -(sn * npi)), ci = __builtin_fma(cs, npi, sn * npr);
-        // sinc(pi f L (1 +- g)) for the two directions
-        double sf, sb, dummy;
-        const double uf = 0.5 * fl * (1.0 + g), ub = 0.5 * fl * (1.0 - g);  // cycles
-        sincos2pi(uf, &sf, &dummy);
-        sincos2pi(ub, &sb, &dummy);
-        // below 1e-5 turns: 1 - u^2/6, remainder u^4/120 < 1e-18
-        const double wf = kTwoPi * uf, wb = kTwoPi * ub;
-        sf = uf < 1e-5 ? __builtin_fma(-wf * wf, 1.0 / 6.0, 1.0) : sf / wf;
-        sb = ub < 1e-5 ? __builtin_fma(-wb * wb, 1.0 / 6.0, 1.0) : sb / wb;
-        const double yfr = cr * sf, yfi = ci * sf;  // y_ij
-        const double ybr = cr * sb, ybi = ci * sb;  // y_ji
+        // sinc(a (1 +- g)): sin(a +- a g) = sin a cos(a g) +- cos a sin(a g); below
+        // 1e-5 turns of argument the series 1 - u^2/6 (remainder u^4/120 < 1e-18)
+        double sg, cg;
+        sincos2pi(0.5 * fl * g, &sg, &cg);
+        const double uf = kPi * fl * (1.0 + g), ub = kPi * fl * (1.0 - g);  // radians
+        const double sf = uf < 6.3e-5 ? __builtin_fma(-uf * uf, 1.0 / 6.0, 1.0) : __builtin_fma(sa, cg, ca * sg) / uf;
+        const double sbk = ub < 6.3e-5 ? __builtin_fma(-ub * ub, 1.0 / 6.0, 1.0) : __builtin_fma(sa, cg, -(ca * sg)) / ub;
+        const double yfr = cr * sf, yfi = ci * sf;    // y_ij
+        const double ybr = cr * sbk, ybi = ci * sbk;  // y_ji
         // + (y_ij + z y_ji) into channel k, - (y_ji + z y_ij) into channel k+1
         acc[i][0] += yfr + __builtin_fma(cx, ybr, sx * ybi);
         acc[i][1] += yfi + __builtin_fma(cx, ybi, -(sx * ybr));

@@ -73,3 +73,58 @@ def test_batched_and_graph_equal_solo():
     finally:
         B.scs_ctx_destroy(hl)
         B.scs_ctx_destroy(hw)
+
+
+def test_batch_mixes_response_models():
+    """One batched call (and its graph) over contexts of every kernel
+    instantiation: low-frequency A+E, full-response A+E, one channel, and an
+    eccentric low-frequency context (8-entry theta rows); each item equals
+    its solo evaluation bit for bit."""
+    lf = D.lisa_small(seed=31)
+    fd = D.lisa_small(seed=32, response=O.RESP_LISA_FD)
+    white = D.white16k()
+    hl, hf, hw = _ctx(lf), _ctx(fd), _ctx(white, G=1)
+    he = B.scs_ctx_create(0)
+    try:
+        g = lf.grid
+        B.scs_load_data(he, np.ascontiguousarray(lf.d_ri), np.ascontiguousarray(lf.psd), g.k0 * g.df, g.df)
+        B.scs_set_model(he, 7, lf.model.response, lf.model.support, lf.model.t_obs, eccentric=1)
+        B.scs_define_segmentation(he, 1, B.SCS_SEG_EQUAL_SNR, 16)
+        th_e = np.concatenate([D.lisa_particles(90, seed=107), np.linspace(0.0, 0.1, 90)[:, None]], axis=1)
+        wth = synth.workload_particles(synth.workload("white16k"))
+        shapes = [(hf, 16, 16, D.lisa_particles(200, seed=104)),
+                  (hl, 16, 8, D.lisa_particles(150, seed=105)),
+                  (hw, 1, 4, wth[:40]),
+                  (he, 16, 5, th_e),
+                  (hf, 16, 1, D.lisa_particles(70, seed=106))]
+        items = [(h, N, torch.tensor(np.ascontiguousarray(th), device="cuda"),
+                  torch.full((th.shape[0],), -1.0, dtype=torch.float64, device="cuda")) for h, G, N, th in shapes]
+        for prec in (B.SCS_PREC_FP64, B.SCS_PREC_MIXED):
+            B.scs_evaluate_batched(items, prec)
+            torch.cuda.synchronize()
+            batched = [it[3].cpu().numpy().copy() for it in items]
+            for (h, G, N, th), bv in zip(shapes, batched):
+                assert np.all(np.isfinite(bv))
+                B.scs_define_segmentation(h, N, B.SCS_SEG_EQUAL_SNR, G)
+                u = torch.empty(th.shape[0], dtype=torch.float64, device="cuda")
+                B.scs_evaluate(h, torch.tensor(np.ascontiguousarray(th), device="cuda"), u, prec)
+                torch.cuda.synchronize()
+                assert np.array_equal(u.cpu().numpy(), bv), (N, th.shape, prec)
+            graph = B.scs_graph_create(items, prec)
+            for it in items:
+                it[3].fill_(-1.0)
+            torch.cuda.synchronize()
+            B.scs_graph_launch(graph)
+            torch.cuda.synchronize()
+            for it, bv in zip(items, batched):
+                assert np.array_equal(it[3].cpu().numpy(), bv)
+            B.scs_graph_destroy(graph)
+        # the full-response item against the oracle
+        ref = O.evaluate(fd.grid, fd.model, fd.d_ri, fd.psd, shapes[0][3][:5], 16, O.SEG_EQUAL_SNR, 16)
+        B.scs_evaluate_batched(items, B.SCS_PREC_FP64)
+        torch.cuda.synchronize()
+        got = items[0][3].cpu().numpy()[:5]
+        assert np.max(np.abs(got - ref["ups"]) / np.maximum(np.abs(ref["ups"]), 32.0)) < 1e-9
+    finally:
+        for h in (hl, hf, hw, he):
+            B.scs_ctx_destroy(h)
