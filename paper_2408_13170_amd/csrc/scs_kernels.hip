@@ -476,11 +476,11 @@ __device__ __forceinline__ double horner5(const double* c, double x)
     v = __builtin_fma(v, x, c[1]);
     return __builtin_fma(v, x, c[0]);
 }
-__device__ __forceinline__ float horner5f(const float* c, float x)
+// The mixed path's response polynomials are cubic (see the block set-up).
+constexpr int kRespMixed = 4;
+__device__ __forceinline__ float horner3f(const float* c, float x)
 {
-    float v = c[5];
-    v = __builtin_fmaf(v, x, c[4]);
-    v = __builtin_fmaf(v, x, c[3]);
+    float v = c[3];
     v = __builtin_fmaf(v, x, c[2]);
     v = __builtin_fmaf(v, x, c[1]);
     return __builtin_fmaf(v, x, c[0]);
@@ -800,7 +800,7 @@ __device__ __forceinline__ void bin_fp64(double j, const double* __restrict__ bi
 // enter the FP32 segment sums through Kahan-compensated additions.
 template <bool RESP>
 __device__ __forceinline__ void bin_mixed(float jf, const float* __restrict__ bin, const float* phf, float a1h,
-                                          const float (*rf)[kNodes], float amp, float& pzr, float& pzi, float& phh)
+                                          const float (*rf)[kRespMixed], float amp, float& pzr, float& pzi, float& phh)
 {
     // the bin's data first, in flight while the phase and sin / cos are formed
     float4 u;
@@ -825,8 +825,8 @@ __device__ __forceinline__ void bin_mixed(float jf, const float* __restrict__ bi
     const float sn = __builtin_amdgcn_sinf(ph);
     const float cs = __builtin_amdgcn_cosf(ph);
     if constexpr (RESP) {
-        const float rar = horner5f(rf[0], jf), rai = horner5f(rf[1], jf);
-        const float rer = horner5f(rf[2], jf), rei = horner5f(rf[3], jf);
+        const float rar = horner3f(rf[0], jf), rai = horner3f(rf[1], jf);
+        const float rer = horner3f(rf[2], jf), rei = horner3f(rf[3], jf);
         float sr = u.x * rar;
         sr = __builtin_fmaf(u.y, rai, sr);
         sr = __builtin_fmaf(u.z, rer, sr);
@@ -999,7 +999,7 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
     const int nthreads = blockDim.x;
     PhasePoly poly;
     RespPoly rp;
-    float phf[kNodes], rf[4][kNodes];
+    float phf[kNodes], rf[4][kRespMixed];
     float a1h = 0.f;
     SinCosK kk{kSin3, kSin1, kCos2};
     __asm__ volatile("" : "+v"(kk.s3), "+v"(kk.s1), "+v"(kk.c2));
@@ -1015,7 +1015,7 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
 #pragma unroll
             for (int f = 0; f < 4; ++f)
 #pragma unroll
-                for (int mm = 0; mm < kNodes; ++mm) rf[f][mm] = 0.f;
+                for (int mm = 0; mm < kRespMixed; ++mm) rf[f][mm] = 0.f;
         }
     } else {
 #pragma unroll
@@ -1089,6 +1089,21 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
                 const double inv_h = 1.0 / (double)(1 << (lgl - 1));
                 block_setup<RM>(coef, S, p, a.g.k0 + (double)kcl, lgl, gtl + (int64_t)(sbl >> lgl) * kGStride,
                                   a.g, a.m, poly, rp);
+                if constexpr (MIXED && RESP) {
+                    // the FP32 response to degree 3: the interpolant's Chebyshev
+                    // series without its T4 and T5 terms (x^5 and x^4 folded into
+                    // the lower powers), off by |a4|/8 + |a5|/16 on [-1, 1]: at
+                    // most ~2e-7 of |R| on the blocks the FP64 bound selects, the
+                    // size of FP32 rounding
+#pragma unroll
+                    for (int f = 0; f < 4; ++f) {
+                        const double a5 = rp.r[f][5], a4 = rp.r[f][4];
+                        rp.r[f][3] += 1.25 * a5;
+                        rp.r[f][1] -= 0.3125 * a5;
+                        rp.r[f][2] += a4;
+                        rp.r[f][0] -= 0.125 * a4;
+                    }
+                }
                 // monomials in j = x h (h a power of two: exact rescaling); the
                 // FP64 phase also in units of 1/kTrig cycle
                 {
@@ -1122,7 +1137,7 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
 #pragma unroll
                         for (int f = 0; f < 4; ++f)
 #pragma unroll
-                            for (int mm = 0; mm < kNodes; ++mm) rf[f][mm] = (float)rp.r[f][mm];
+                            for (int mm = 0; mm < kRespMixed; ++mm) rf[f][mm] = (float)rp.r[f][mm];
                     }
                 }
             }
