@@ -476,7 +476,8 @@ __device__ __forceinline__ double horner5(const double* c, double x)
     v = __builtin_fma(v, x, c[1]);
     return __builtin_fma(v, x, c[0]);
 }
-// The mixed path's response polynomials are cubic (see the block set-up).
+// The mixed path's phase-residual and response polynomials are cubic (see
+// the block set-up).
 constexpr int kRespMixed = 4;
 __device__ __forceinline__ float horner3f(const float* c, float x)
 {
@@ -816,9 +817,7 @@ __device__ __forceinline__ void bin_mixed(float jf, const float* __restrict__ bi
     }
     const float pl = a1h * jf;
     const float f1 = pl - rintf(pl);
-    float r = phf[5];
-    r = __builtin_fmaf(r, jf, phf[4]);
-    r = __builtin_fmaf(r, jf, phf[3]);
+    float r = phf[3];
     r = __builtin_fmaf(r, jf, phf[2]);
     r = __builtin_fmaf(r, jf, phf[1]);
     const float ph = __builtin_fmaf(r, jf, phf[0] + f1);
@@ -999,7 +998,7 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
     const int nthreads = blockDim.x;
     PhasePoly poly;
     RespPoly rp;
-    float phf[kNodes], rf[4][kRespMixed];
+    float phf[kRespMixed], rf[4][kRespMixed];
     float a1h = 0.f;
     SinCosK kk{kSin3, kSin1, kCos2};
     __asm__ volatile("" : "+v"(kk.s3), "+v"(kk.s1), "+v"(kk.c2));
@@ -1010,7 +1009,7 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
     double amp = 0.0;
     if constexpr (MIXED) {
 #pragma unroll
-        for (int mm = 0; mm < kNodes; ++mm) phf[mm] = 0.f;
+        for (int mm = 0; mm < kRespMixed; ++mm) phf[mm] = 0.f;
         if constexpr (RESP) {
 #pragma unroll
             for (int f = 0; f < 4; ++f)
@@ -1089,6 +1088,17 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
                 const double inv_h = 1.0 / (double)(1 << (lgl - 1));
                 block_setup<RM>(coef, S, p, a.g.k0 + (double)kcl, lgl, gtl + (int64_t)(sbl >> lgl) * kGStride,
                                   a.g, a.m, poly, rp);
+                if constexpr (MIXED) {
+                    // the FP32 residual phase to degree 3 the same way: off by
+                    // |a4|/8 + |a5|/16 cycles, below 1e-6 even where the FP64
+                    // bound admits the most curvature, smooth within the block,
+                    // so second order in the statistic
+                    const double a5 = poly.ph[5], a4 = poly.ph[4];
+                    poly.ph[3] += 1.25 * a5;
+                    poly.ph[1] -= 0.3125 * a5;
+                    poly.ph[2] += a4;
+                    poly.ph[0] -= 0.125 * a4;
+                }
                 if constexpr (MIXED && RESP) {
                     // the FP32 response to degree 3: the interpolant's Chebyshev
                     // series without its T4 and T5 terms (x^5 and x^4 folded into
@@ -1132,7 +1142,7 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
                     phf[0] = (float)poly.ph[0];
                     phf[1] = (float)(poly.ph[1] - hi1);
 #pragma unroll
-                    for (int mm = 2; mm < kNodes; ++mm) phf[mm] = (float)poly.ph[mm];
+                    for (int mm = 2; mm < kRespMixed; ++mm) phf[mm] = (float)poly.ph[mm];
                     if constexpr (RESP) {
 #pragma unroll
                         for (int f = 0; f < 4; ++f)
