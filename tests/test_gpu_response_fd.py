@@ -121,3 +121,42 @@ def test_noise_free_injection_and_statistics():
             assert abs(semi[0]) < 1e-9 * dd and abs(coh[0]) < 1e-9 * dd
         finally:
             B.scs_ctx_destroy(h)
+
+
+def test_full_response_lisa1m_full_size_sampled():
+    """The benchmark's full-response configuration at its full size (2^20 bins,
+    10^4 particles, N = 1024, G = 1024, the TDI noise PSDs) in the launch
+    configuration `bench.py --response fd` times; the oracle recomputes a
+    seeded sample of particles one by one."""
+    w = synth.workload("lisa1m")
+    g = O.Grid(w.grid.K, w.grid.k0, w.grid.df, 2)
+    m = O.Model(pn_order=7, response=O.RESP_LISA_FD, support=O.SUPPORT_TOBS, t_obs=w.grid.t_obs)
+    psd = synth.lisa_tdi_psd(w.grid.freqs())[:2]
+    ds = D.make(g, m, psd, w.injection, w.snr, w.seed, True, w.prior_lo, w.prior_hi)
+    theta = synth.workload_particles(w)
+    theta[:2] = synth.near_injection(w.injection, 2, seed=6, lo=w.prior_lo, hi=w.prior_hi)
+    N = w.N
+    h = _ctx(ds, N, B.SCS_SEG_EQUAL_SNR, w.G)
+    try:
+        tht = torch.tensor(theta, device="cuda")
+        u = torch.empty(theta.shape[0], dtype=torch.float64, device="cuda")
+        B.scs_evaluate(h, tht, u)
+        torch.cuda.synchronize()
+        got = u.cpu().numpy()
+        sup, bnd = B.scs_last_bounds(h, theta.shape[0], N)
+        B.scs_evaluate(h, tht, u, B.SCS_PREC_MIXED)
+        torch.cuda.synchronize()
+        gm = u.cpu().numpy()
+        assert np.all(np.isfinite(got)) and np.all(got >= 0)
+        idx = np.concatenate([[0, 1], np.random.default_rng(4).choice(np.arange(2, len(theta)), 4, replace=False)])
+        ref = O.evaluate(g, m, ds.d_ri, psd, theta[idx], N, O.SEG_EQUAL_SNR, w.G, want_bounds=True)
+        assert np.array_equal(sup[idx], ref["support"])
+        same = np.all(bnd[idx] == ref["bounds"], axis=1)
+        assert same.sum() >= len(same) - 1
+        e = _floored(got[idx][same], ref["ups"][same], N)
+        em = _floored(gm[idx][same], ref["ups"][same], N)
+        print(f"full response, 2^20 bins: fp64 sampled max floored rel err {e.max():.3g}, mixed {em.max():.3g}; "
+              f"Upsilon near the injection {got[:2]} (oracle {ref['ups'][:2]})")
+        assert e.max() < 1e-9 and em.max() < 1e-5
+    finally:
+        B.scs_ctx_destroy(h)
