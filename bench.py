@@ -106,9 +106,9 @@ def main():
                          "Poisson-arriving requests; streams: one theta against many noise realisations "
                          "(Sec 5.1), HBM-bound; search: the whole hierarchical multi-swarm search (Sec 3.2)")
     ap.add_argument("--max-iters", type=int, default=400, help="search: iteration cap per rung")
-    ap.add_argument("--response", choices=["lf", "fd"], default="lf",
-                    help="step: LISA response model, low-frequency (default) or the full frequency-domain "
-                         "TDI response with its noise PSDs")
+    ap.add_argument("--response", choices=["lf", "fd", "fd3"], default="lf",
+                    help="step: LISA response model, low-frequency A+E (default), or the full frequency-domain "
+                         "TDI response with its noise PSDs on A+E (fd) or A+E+T (fd3)")
     ap.add_argument("--requests", type=int, default=2000, help="serve: requests per offered load")
     ap.add_argument("--realisations", type=int, default=1024,
                     help="streams: noise realisations held in HBM at once")
@@ -145,10 +145,10 @@ def main():
     dev = torch.device("cuda:0")
     w = synth.workload("lisa1m")
     K = w.grid.K
-    fd = args.response == "fd"
-    psd = bench_psd(w, fd)
+    fd = args.response in ("fd", "fd3")
+    psd = bench_psd(w, args.response)
     # --- data: noise + injection made with the library's own FP64 template
-    ctx, d_ri = make_search(B, torch, w, dev, fd)
+    ctx, d_ri = make_search(B, torch, w, dev, args.response)
     # --- swarm of 10^4 particles, first rung of the ladder (Table tab:PSO_hyperparams, N = 100 row)
     eps = [0.1, 0.05, 5e-8, 0.1, 0.1, 0.2, 0.1]  # Mc, eta, f_low, lambda, beta, iota, psi
     prm = B.pso_params(0.5, 0.2, 0.3, eps)
@@ -241,13 +241,15 @@ def main():
         "config": {"workload": "A+E, 2^20 bins over [0.016,0.032) Hz, T_obs 2.08 yr, N_seg 1024 (equal [h|h], "
                                "node stride 1024), 10^4 PSO particles in the GW150914-like prior box, one PSO "
                                "iteration per step", "particles": w.P, "bins": K, "N_seg": w.N,
-                   "response": "full frequency-domain TDI A/E (finite arm length)" if fd else
-                   "low-frequency A/E"},
+                   "response": {"lf": "low-frequency A/E", "fd": "full frequency-domain TDI A/E (finite arm length)",
+                                "fd3": "full frequency-domain TDI A/E/T (finite arm length)"}[args.response]},
         "latency_ms": {"p50": float(np.median(r64["step_ms"])), "p99": float(np.quantile(r64["step_ms"], 0.99))},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None if fd else measured_traffic(),
-                     "kernel": "k_main_multi<2,false,1> (FP64 generate-and-reduce, low-frequency response)" if not fd else
-                     "k_main_multi<2,false,2> (FP64 generate-and-reduce, full response)",
+                     "kernel": {"lf": "k_main_multi<2,false,1> (FP64 generate-and-reduce, low-frequency response)",
+                                "fd": "k_main_multi<2,false,2> (FP64 generate-and-reduce, full response)",
+                                "fd3": "k_main_multi<3,false,2> (FP64 generate-and-reduce, full response, A+E+T)"}[
+                         args.response],
                      "avg_launch_ms": avg_main_ms, "flop_per_eval": FLOP_PER_EVAL_FP64,
                      "evals_per_launch": evals_per_launch},
         "unresolved_particles": r64["unresolved"],
@@ -269,24 +271,27 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def bench_psd(w, fd=False):
+def bench_psd(w, response="lf"):
     """PSDs of workload w: the low-frequency A/E model, or the TDI noise of
-    the full response (its A and E rows)."""
-    return synth.lisa_tdi_psd(w.grid.freqs())[:2] if fd else synth.psd_arrays(w)
+    the full response (its A and E rows, or A, E and T)."""
+    if response == "lf":
+        return synth.psd_arrays(w)
+    return synth.lisa_tdi_psd(w.grid.freqs())[:3 if response == "fd3" else 2]
 
 
-def make_search(B, torch, w, dev, fd=False):
+def make_search(B, torch, w, dev, response="lf"):
     """Context with seeded noise plus the injection of workload w at its SNR
-    (template from the library's own FP64 waveform kernel); fd selects the
-    full frequency-domain response."""
+    (template from the library's own FP64 waveform kernel); response selects
+    the low-frequency or the full frequency-domain response (A+E or A+E+T)."""
     K, df, f_min = w.grid.K, w.grid.df, w.grid.f_min
-    psd = bench_psd(w, fd)
-    resp = B.SCS_RESP_LISA_FD_AE if fd else B.SCS_RESP_LISA_LF_AE
+    psd = bench_psd(w, response)
+    nch = psd.shape[0]
+    resp = B.SCS_RESP_LISA_LF_AE if response == "lf" else B.SCS_RESP_LISA_FD_AE
     noise = synth.noise(psd, df, w.seed)
     ctx = B.scs_ctx_create(0)
-    B.scs_load_data(ctx, np.zeros((w.n_chan, K, 2)), psd, f_min, df)
+    B.scs_load_data(ctx, np.zeros((nch, K, 2)), psd, f_min, df)
     B.scs_set_model(ctx, w.pn_order, resp, B.SCS_SUPPORT_TOBS, w.grid.t_obs)
-    h = torch.empty((w.n_chan, K, 2), dtype=torch.float64, device=dev)
+    h = torch.empty((nch, K, 2), dtype=torch.float64, device=dev)
     B.scs_waveform(ctx, torch.tensor(w.injection, device=dev), h)
     torch.cuda.synchronize()
     hc = torch.complex(h[..., 0], h[..., 1])
@@ -634,7 +639,7 @@ def cpu_baseline(w, psd, d_ri, seconds, fd=False):
     thread until about `seconds` of wall time."""
     import oracle as O
 
-    g = O.Grid(w.grid.K, w.grid.k0, w.grid.df, 2)
+    g = O.Grid(w.grid.K, w.grid.k0, w.grid.df, psd.shape[0])
     m = O.Model(pn_order=w.pn_order, response=O.RESP_LISA_FD if fd else O.RESP_LISA_LF_AE,
                 support=O.SUPPORT_TOBS, t_obs=w.grid.t_obs)
     th_all = synth.workload_particles(w, seed=w.seed + 11)

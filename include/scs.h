@@ -62,8 +62,9 @@ extern "C" {
 
 #define SCS_RESP_NONE 0       /* one channel, h = f^-7/6 e^{-i Psi} */
 #define SCS_RESP_LISA_LF_AE 1 /* two channels A, E, low-frequency LISA response */
-/* two channels A, E, full frequency-domain response (Sec 4 response
- * paragraph): first-generation TDI on a rigid equal-arm constellation
+/* channels A, E (two loaded) or A, E, T (three loaded), full frequency-domain
+ * response (Sec 4 response paragraph): first-generation TDI on a rigid
+ * equal-arm constellation
  * (arms 2.5e9 m, the geometry of the low-frequency response) with the
  * finite-arm-length transfer of every link at the stationary-phase time,
  * normalised by 4 (2 pi f L)^2 so that it tends to the low-frequency
@@ -83,7 +84,7 @@ typedef struct scs_swarm scs_swarm;
 /* Waveform and response model (Sec 4).  Zero-initialise, then set fields. */
 typedef struct scs_model {
     int32_t pn_order;        /* highest PN power of v in the phase, 0..7 (4 = 2PN, 7 = 3.5PN) */
-    int32_t response;        /* SCS_RESP_* ; NONE needs 1 channel, LISA_LF_AE and LISA_FD_AE need 2 */
+    int32_t response;        /* SCS_RESP_* ; NONE needs 1 channel, LISA_LF_AE 2, LISA_FD_AE 2 or 3 */
     int32_t support;         /* SCS_SUPPORT_* */
     int32_t block_len;       /* longest polynomial block in bins (power of 2, 16..2048); 0 = 2048 */
     double t_obs;            /* observation time [s]; 0 = 1/df */
@@ -107,7 +108,7 @@ int scs_ctx_destroy(scs_ctx* ctx);
 
 /* Load the data stream d_alpha(f_k) and its one-sided PSD S_alpha(f_k)
  * (eqn:inner_prod) on the grid f_k = f_min + k df, k = 0..K-1.
- *   n_chan  1 or 2 (A, E)
+ *   n_chan  1, 2 (A, E) or 3 (A, E, T; full response only)
  *   d_ri    [n_chan][K][2] real and imaginary parts
  *   psd     [n_chan][K], every value finite and > 0
  * f_min / df must be an integer (to 1e-9 relative): f_k are FFT bins and

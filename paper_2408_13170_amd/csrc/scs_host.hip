@@ -156,8 +156,8 @@ struct Workspace {
 struct BatchSlot {
     int cap = 0;  // items
     MainArgs* d_items = nullptr;
-    int64_t* d_start = nullptr;                // [kRespModels][cap + 1]
-    unsigned long long* d_counter = nullptr;  // [kRespModels]
+    int64_t* d_start = nullptr;                // [kVariants][cap + 1]
+    unsigned long long* d_counter = nullptr;  // [kVariants]
     MainArgs* h_items = nullptr;               // pinned
     int64_t* h_start = nullptr;                // pinned
     hipEvent_t done = nullptr;                 // recorded after the last launch that read the slot
@@ -210,6 +210,16 @@ struct scs_ctx {
 
 static int build_gtab(scs_ctx* c);
 static void free_slot(BatchSlot& b);
+
+// Channels each response model produces: none one, low-frequency A and E,
+// full A and E, or A, E and T.
+static bool model_fits(int response, int nch)
+{
+    if (response == SCS_RESP_NONE) return nch == 1;
+    if (response == SCS_RESP_LISA_LF_AE) return nch == 2;
+    if (response == SCS_RESP_LISA_FD_AE) return nch == 2 || nch == 3;
+    return false;
+}
 
 // Entries per theta row: 7, or 8 with the eccentricity of an eccentric model.
 static int theta_dim(const scs_ctx* c) { return c->m.ecc ? kThetaMax : kTheta; }
@@ -319,7 +329,7 @@ extern "C" int scs_load_data(scs_ctx* c, int32_t n_chan, int64_t K, double f_min
                              const double* psd, int32_t mem_kind)
 {
     if (!c) return fail(SCS_EINVAL, "ctx is NULL");
-    if (n_chan != 1 && n_chan != 2) return fail(SCS_EINVAL, "n_chan must be 1 or 2 (got %d)", n_chan);
+    if (n_chan < 1 || n_chan > 3) return fail(SCS_EINVAL, "n_chan must be 1, 2 or 3 (got %d)", n_chan);
     if (K < 1 || K > (int64_t)1 << 30) return fail(SCS_EINVAL, "K out of range (%lld)", (long long)K);
     if (!(df > 0.0) || !std::isfinite(df) || !(f_min >= 0.0) || !std::isfinite(f_min))
         return fail(SCS_EINVAL, "f_min and df must be finite, df > 0");
@@ -359,8 +369,8 @@ extern "C" int scs_load_data(scs_ctx* c, int32_t n_chan, int64_t K, double f_min
     hipFree(c->b32);
     c->b64 = nullptr;
     c->b32 = nullptr;
-    if (hipMalloc((void**)&c->b64, sizeof(double) * 3 * nd) != hipSuccess ||
-        hipMalloc((void**)&c->b32, sizeof(float) * 3 * nd) != hipSuccess) {
+    if (hipMalloc((void**)&c->b64, sizeof(double) * bin_stride(n_chan) * K) != hipSuccess ||
+        hipMalloc((void**)&c->b32, sizeof(float) * bin_stride(n_chan) * K) != hipSuccess) {
         hipFree(dd_);
         hipFree(dp);
         return fail(SCS_ENOMEM, "bin table allocation failed");
@@ -407,7 +417,7 @@ extern "C" int scs_load_data(scs_ctx* c, int32_t n_chan, int64_t K, double f_min
     if (e3 != hipSuccess) return fail(SCS_EDEVICE, "bin precompute failed: %s", hipGetErrorString(e3));
     c->has_data = true;
     c->gtab_ok = false;
-    if (c->has_model && ((c->m.response != 0) != (n_chan == 2))) c->has_model = false;
+    if (c->has_model && !model_fits(c->m.response, n_chan)) c->has_model = false;
     if (c->has_model) return build_gtab(c);
     return SCS_OK;
 }
@@ -419,7 +429,7 @@ extern "C" int scs_set_model(scs_ctx* c, const scs_model* m)
     if (m->pn_order < 0 || m->pn_order > 7) return fail(SCS_EINVAL, "pn_order must be 0..7");
     if (m->response != SCS_RESP_NONE && m->response != SCS_RESP_LISA_LF_AE && m->response != SCS_RESP_LISA_FD_AE)
         return fail(SCS_EINVAL, "bad response");
-    if ((m->response != SCS_RESP_NONE) != (c->g.nch == 2))
+    if (!model_fits(m->response, c->g.nch))
         return fail(SCS_EINVAL, "response %d does not match %d loaded channels", m->response, c->g.nch);
     if (m->support != SCS_SUPPORT_FULL && m->support != SCS_SUPPORT_TOBS) return fail(SCS_EINVAL, "bad support");
     const int bl = m->block_len ? m->block_len : 2048;
@@ -1132,10 +1142,10 @@ static int slot_reserve(BatchSlot& b, int n)
     free_slot(b);
     const int cap = std::max(n, 8);
     if (hipMalloc((void**)&b.d_items, sizeof(MainArgs) * cap) != hipSuccess ||
-        hipMalloc((void**)&b.d_start, sizeof(int64_t) * kRespModels * (cap + 1)) != hipSuccess ||
-        hipMalloc((void**)&b.d_counter, sizeof(unsigned long long) * kRespModels) != hipSuccess ||
+        hipMalloc((void**)&b.d_start, sizeof(int64_t) * kVariants * (cap + 1)) != hipSuccess ||
+        hipMalloc((void**)&b.d_counter, sizeof(unsigned long long) * kVariants) != hipSuccess ||
         hipHostMalloc((void**)&b.h_items, sizeof(MainArgs) * cap) != hipSuccess ||
-        hipHostMalloc((void**)&b.h_start, sizeof(int64_t) * kRespModels * (cap + 1)) != hipSuccess ||
+        hipHostMalloc((void**)&b.h_start, sizeof(int64_t) * kVariants * (cap + 1)) != hipSuccess ||
         hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess) {
         free_slot(b);
         return fail(SCS_ENOMEM, "batch descriptor allocation failed");
@@ -1162,21 +1172,21 @@ static int check_items(const scs_batch_item* items, int32_t n_items, int32_t pre
 
 // ==== launch shape of the generate-and-reduce (begin)
 // The generate-and-reduce of prepared evaluations: one persistent launch per
-// response model over the tiles of all of them (descriptors in slot b;
-// upload: copy them from the pinned host copy first).
+// kernel variant (response model and channels) over the tiles of all of
+// them (descriptors in slot b; upload: copy them from the pinned host copy
+// first).
 static int fused_main(std::vector<EvalJob>& jobs, int waves, bool mixed, hipStream_t s, BatchSlot& b, bool upload)
 {
     const int n_items = (int)jobs.size();
     scs_ctx* c0 = jobs[0].c;
     int off = 0;
-    for (int gi = 0; gi < kRespModels; ++gi) {
-        const int resp = (gi + 1) % kRespModels;  // A+E low-frequency first, then full, then one channel
+    for (int gi = 0; gi < kVariants; ++gi) {
         int cnt = 0;
         int64_t total = 0;
         int64_t* hs = b.h_start + gi * (b.cap + 1);
         for (int i = 0; i < n_items; ++i) {
             const EvalJob& j = jobs[i];
-            if (j.c->m.response != resp || j.P == 0 || j.pl.n_tiles == 0) continue;
+            if (variant_of(j.c->m.response, j.c->g.nch) != gi || j.P == 0 || j.pl.n_tiles == 0) continue;
             if (upload) {
                 b.h_items[off + cnt] = j.ma;
                 hs[cnt] = total;
@@ -1191,11 +1201,11 @@ static int fused_main(std::vector<EvalJob>& jobs, int waves, bool mixed, hipStre
             HIP_TRY(hipMemcpyAsync(b.d_start + gi * (b.cap + 1), hs, sizeof(int64_t) * (cnt + 1), hipMemcpyHostToDevice, s));
         }
         launch_fill_u64(b.d_counter + gi, 1, 0ULL, s);
-        const int per_cu = main_multi_blocks_per_cu(resp, c0->L, waves, mixed);
+        const int per_cu = main_multi_blocks_per_cu(gi, c0->L, waves, mixed);
         const int64_t grid = std::min<int64_t>(total, (int64_t)c0->n_cu * per_cu);
         hipEvent_t e0;
         prof_begin(c0, s, &e0);
-        hipError_t e = launch_main_multi(b.d_items + off, b.d_start + gi * (b.cap + 1), cnt, b.d_counter + gi, resp, c0->L,
+        hipError_t e = launch_main_multi(b.d_items + off, b.d_start + gi * (b.cap + 1), cnt, b.d_counter + gi, gi, c0->L,
                                          waves, mixed, (int)grid, s);
         if (e != hipSuccess) return fail(SCS_EDEVICE, "generate-and-reduce launch failed: %s", hipGetErrorString(e));
         prof_end(c0, s, e0);

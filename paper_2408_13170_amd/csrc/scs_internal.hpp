@@ -21,6 +21,11 @@ constexpr int kTrig = 1024;       // entries of the (cos, sin)(2 pi i / kTrig) t
 constexpr int kCoefStride = 56;  // doubles per particle record of the coefficient buffer
 constexpr int kRec = 8;          // doubles per (chunk, slot) record: head piece, tail piece, padding
 
+// Values per bin of the precomputed tables: [u_c re, u_c im]_c, [q_c]_c, and
+// for three channels three padding values so that every bin starts on a
+// 32-byte boundary.
+__host__ __device__ constexpr int bin_stride(int nch) { return nch == 3 ? 12 : 3 * nch; }
+
 struct GridArgs {
     int64_t K;
     double k0;  // f_min / df
@@ -181,12 +186,17 @@ void launch_bins(const GridArgs& g, const double* d_ri, const double* psd, doubl
 void launch_prologue(const PrologueArgs& a, hipStream_t s);
 void launch_bounds(const BoundArgs& a, hipStream_t s);
 size_t main_lds_bytes(int nch, int L, bool mixed);
-// resp: the response model of the items (0: one channel; 1, 2: A+E
-// low-frequency, full), which selects the kernel instantiation
-constexpr int kRespModels = 3;
+// The kernel instantiations of the generate-and-reduce, one per (response
+// model, channels): 0 = low-frequency A+E, 1 = full A+E, 2 = full A+E+T,
+// 3 = one channel without response.
+constexpr int kVariants = 4;
+__host__ __device__ constexpr int variant_of(int resp, int nch)
+{
+    return resp == 1 ? 0 : (resp == 2 ? (nch == 3 ? 2 : 1) : 3);
+}
 hipError_t launch_main_multi(const MainArgs* items, const int64_t* tile_start, int n_items, unsigned long long* counter,
-                             int resp, int L, int waves, bool mixed, int grid, hipStream_t s);
-int main_multi_blocks_per_cu(int resp, int L, int waves, bool mixed);
+                             int variant, int L, int waves, bool mixed, int grid, hipStream_t s);
+int main_multi_blocks_per_cu(int variant, int L, int waves, bool mixed);
 void launch_finalize(const FinalArgs& a, hipStream_t s);
 void launch_waveform(const MainArgs& a, double* h_ri, hipStream_t s);
 void launch_gtab(const GridArgs& g, int lg, int64_t nsub, double* tab, hipStream_t s);

@@ -48,7 +48,11 @@ __global__ void k_bins(GridArgs g, const double* __restrict__ d_ri, const double
     const double f = (g.k0 + (double)k) * g.df;
     const double a76 = pow(f, -7.0 / 6.0);
     const double a73 = a76 * a76;
-    const int nv = 3 * g.nch;
+    const int nv = bin_stride(g.nch);
+    for (int c = 3 * g.nch; c < nv; ++c) {  // padding
+        b64[k * nv + c] = 0.0;
+        b32[k * nv + c] = 0.f;
+    }
     for (int c = 0; c < g.nch; ++c) {
         const double S = psd[(int64_t)c * g.K + k];
         const double dr = d_ri[((int64_t)c * g.K + k) * 2];
@@ -353,19 +357,21 @@ __global__ void k_gtab(GridArgs g, int lg, int64_t nsub, double* __restrict__ ta
 struct PhasePoly {
     double ph[kNodes];  // phase [cycles] (GW + Doppler), monomials in x = j / h; ph[0] in [-0.5, 0.5)
 };
-struct RespPoly {
-    double r[4][kNodes];  // response R_A re, R_A im, R_E re, R_E im, monomials in x
+template <int NR>
+struct RespPolyN {
+    double r[NR][kNodes];  // response R_A re, R_A im, R_E re, R_E im (, R_T re, R_T im), monomials in x
 };
+using RespPoly = RespPolyN<4>;
 
 // Per-lane polynomial set-up for one sub-block of length 2h centred on
 // absolute bin Kc: phase Taylor coefficients from the basis table (wave-
 // uniform, scalar loads), constant term reduced exactly in double-double;
 // for the LISA response, response and Doppler interpolated at the Chebyshev
 // nodes.  Returns the GW phase coefficients a[] (x-space) for node times.
-template <int RM>
+template <int RM, int NR = 4>
 __device__ inline void block_setup(const GLOBAL double* __restrict__ cf, int64_t S, int64_t p, double Kc, int lg,
                                    const GLOBAL double* __restrict__ G, const GridArgs& g, const ModelArgs& m,
-                                   PhasePoly& out, RespPoly& resp)
+                                   PhasePoly& out, RespPolyN<NR>& resp)
 {
     const double h = (double)(1 << (lg - 1));
     const double c0h = cf[p * kCoefStride + C_C0H];
@@ -413,7 +419,7 @@ __device__ inline void block_setup(const GLOBAL double* __restrict__ cf, int64_t
     }
     if constexpr (RM != 0) {
 #pragma unroll
-        for (int f = 0; f < 4; ++f)
+        for (int f = 0; f < NR; ++f)
 #pragma unroll
             for (int mm = 0; mm < kNodes; ++mm) resp.r[f][mm] = 0.0;
         const double dcx = cf[p * kCoefStride + C_DC], dsx = cf[p * kCoefStride + C_DS];
@@ -437,10 +443,10 @@ __device__ inline void block_setup(const GLOBAL double* __restrict__ cf, int64_t
             if constexpr (RM == 2) {
                 const double cz = __builtin_fma(m.cart_c, c1, m.cart_s * s1);
                 const double sz = __builtin_fma(m.cart_s, c1, -(m.cart_c * s1));
-                double rv[4];
-                fd_response(fn, c1, s1, cz, sz, cf + (p * kCoefStride + C_RESP), rv);
+                double rv[NR];
+                fd_response<NR / 2>(fn, c1, s1, cz, sz, cf + (p * kCoefStride + C_RESP), rv);
 #pragma unroll
-                for (int f = 0; f < 4; ++f)
+                for (int f = 0; f < NR; ++f)
 #pragma unroll
                     for (int mm = 0; mm < kNodes; ++mm)
                         resp.r[f][mm] = __builtin_fma(c_cheb_m[mm * kNodes + n], rv[f], resp.r[f][mm]);
@@ -516,8 +522,15 @@ __device__ inline double weight_at(const CONSTANT double* __restrict__ cf, int64
         if constexpr (RM == 2) {
             const double cz = __builtin_fma(m.cart_c, c1, m.cart_s * s1);
             const double sz = __builtin_fma(m.cart_s, c1, -(m.cart_c * s1));
+            if (g.nch == 3) {
+                double rv[6];
+                fd_response<3>(f, c1, s1, cz, sz, cf + (p * kCoefStride + C_RESP), rv);
+                const double* q = b64 + k * bin_stride(3) + 6;
+                return q[0] * (rv[0] * rv[0] + rv[1] * rv[1]) + q[1] * (rv[2] * rv[2] + rv[3] * rv[3]) +
+                       q[2] * (rv[4] * rv[4] + rv[5] * rv[5]);
+            }
             double rv[4];
-            fd_response(f, c1, s1, cz, sz, cf + (p * kCoefStride + C_RESP), rv);
+            fd_response<2>(f, c1, s1, cz, sz, cf + (p * kCoefStride + C_RESP), rv);
             return b64[k * 6 + 4] * (rv[0] * rv[0] + rv[1] * rv[1]) + b64[k * 6 + 5] * (rv[2] * rv[2] + rv[3] * rv[3]);
         }
         double ch[5], sh[5];
@@ -743,16 +756,24 @@ struct SinCosK {
     double s3, s1, c2;
 };
 
-template <bool RESP>
+template <int NCH>
 __device__ __forceinline__ void bin_fp64(double j, const double* __restrict__ bin, const double2* __restrict__ tab,
-                                         const SinCosK& kk, const PhasePoly& poly, const RespPoly& rp, int tmask,
-                                         int toff, double amp, double& zr, double& zi, double& hh)
+                                         const SinCosK& kk, const PhasePoly& poly,
+                                         const RespPolyN<NCH == 3 ? 6 : 4>& rp, int tmask, int toff, double amp,
+                                         double& zr, double& zi, double& hh)
 {
+    constexpr bool RESP = NCH >= 2;
     // the bin's data first, then the table read, so that both are in flight
     // while the response and the noise weight are evaluated
-    double2 uA, uE, qq;
+    double2 uA, uE, uT, qq, qT;
     double ur, ui, q1;
-    if constexpr (RESP) {
+    if constexpr (NCH == 3) {
+        uA = *reinterpret_cast<const double2*>(bin);
+        uE = *reinterpret_cast<const double2*>(bin + 2);
+        uT = *reinterpret_cast<const double2*>(bin + 4);
+        qq = *reinterpret_cast<const double2*>(bin + 6);
+        qT = *reinterpret_cast<const double2*>(bin + 8);
+    } else if constexpr (RESP) {
         uA = *reinterpret_cast<const double2*>(bin);
         uE = *reinterpret_cast<const double2*>(bin + 2);
         qq = *reinterpret_cast<const double2*>(bin + 4);
@@ -766,7 +787,27 @@ __device__ __forceinline__ void bin_fp64(double j, const double* __restrict__ bi
     const int iq = ((int)(uint32_t)__double_as_longlong(t) & tmask) | toff;
     const double2 tt = tab[iq];
     double sr, si;
-    if constexpr (RESP) {
+    if constexpr (NCH == 3) {
+        const double rar = horner5(rp.r[0], j), rai = horner5(rp.r[1], j);
+        const double rer = horner5(rp.r[2], j), rei = horner5(rp.r[3], j);
+        const double rtr = horner5(rp.r[4], j), rti = horner5(rp.r[5], j);
+        sr = uA.x * rar;
+        sr = __builtin_fma(uA.y, rai, sr);
+        sr = __builtin_fma(uE.x, rer, sr);
+        sr = __builtin_fma(uE.y, rei, sr);
+        sr = __builtin_fma(uT.x, rtr, sr);
+        sr = __builtin_fma(uT.y, rti, sr);
+        si = uA.y * rar;
+        si = __builtin_fma(-uA.x, rai, si);
+        si = __builtin_fma(uE.y, rer, si);
+        si = __builtin_fma(-uE.x, rei, si);
+        si = __builtin_fma(uT.y, rtr, si);
+        si = __builtin_fma(-uT.x, rti, si);
+        const double wa = __builtin_fma(rar, rar, rai * rai);
+        const double we = __builtin_fma(rer, rer, rei * rei);
+        const double wt = __builtin_fma(rtr, rtr, rti * rti);
+        hh = __builtin_fma(qq.x, wa, __builtin_fma(qq.y, we, __builtin_fma(qT.x, wt, hh)));
+    } else if constexpr (RESP) {
         const double rar = horner5(rp.r[0], j), rai = horner5(rp.r[1], j);
         const double rer = horner5(rp.r[2], j), rei = horner5(rp.r[3], j);
         sr = uA.x * rar;
@@ -799,15 +840,20 @@ __device__ __forceinline__ void bin_fp64(double j, const double* __restrict__ bi
 // (a1h j exact, see the block set-up), hardware sin / cos of cycles, FP32
 // response; plain FP32 partial sums over at most kMixedRun bins, which then
 // enter the FP32 segment sums through Kahan-compensated additions.
-template <bool RESP>
+template <int NCH>
 __device__ __forceinline__ void bin_mixed(float jf, const float* __restrict__ bin, const float* phf, float a1h,
                                           const float (*rf)[kRespMixed], float amp, float& pzr, float& pzi, float& phh)
 {
+    constexpr bool RESP = NCH >= 2;
     // the bin's data first, in flight while the phase and sin / cos are formed
-    float4 u;
+    float4 u, tq;  // three channels: (uT re, uT im, qA, qE), then qT
     float2 qq;
-    float ur, ui, q1;
-    if constexpr (RESP) {
+    float ur, ui, q1, qt;
+    if constexpr (NCH == 3) {
+        u = *reinterpret_cast<const float4*>(bin);
+        tq = *reinterpret_cast<const float4*>(bin + 4);
+        qt = bin[8];
+    } else if constexpr (RESP) {
         u = *reinterpret_cast<const float4*>(bin);
         qq = *reinterpret_cast<const float2*>(bin + 4);
     } else {
@@ -823,7 +869,29 @@ __device__ __forceinline__ void bin_mixed(float jf, const float* __restrict__ bi
     const float ph = __builtin_fmaf(r, jf, phf[0] + f1);
     const float sn = __builtin_amdgcn_sinf(ph);
     const float cs = __builtin_amdgcn_cosf(ph);
-    if constexpr (RESP) {
+    if constexpr (NCH == 3) {
+        const float rar = horner3f(rf[0], jf), rai = horner3f(rf[1], jf);
+        const float rer = horner3f(rf[2], jf), rei = horner3f(rf[3], jf);
+        const float rtr = horner3f(rf[4], jf), rti = horner3f(rf[5], jf);
+        float sr = u.x * rar;
+        sr = __builtin_fmaf(u.y, rai, sr);
+        sr = __builtin_fmaf(u.z, rer, sr);
+        sr = __builtin_fmaf(u.w, rei, sr);
+        sr = __builtin_fmaf(tq.x, rtr, sr);
+        sr = __builtin_fmaf(tq.y, rti, sr);
+        float si = u.y * rar;
+        si = __builtin_fmaf(-u.x, rai, si);
+        si = __builtin_fmaf(u.w, rer, si);
+        si = __builtin_fmaf(-u.z, rei, si);
+        si = __builtin_fmaf(tq.y, rtr, si);
+        si = __builtin_fmaf(-tq.x, rti, si);
+        pzr = __builtin_fmaf(sr, cs, __builtin_fmaf(-si, sn, pzr));
+        pzi = __builtin_fmaf(sr, sn, __builtin_fmaf(si, cs, pzi));
+        const float wa = __builtin_fmaf(rar, rar, rai * rai);
+        const float we = __builtin_fmaf(rer, rer, rei * rei);
+        const float wt = __builtin_fmaf(rtr, rtr, rti * rti);
+        phh = __builtin_fmaf(tq.z, wa, __builtin_fmaf(tq.w, we, __builtin_fmaf(qt, wt, phh)));
+    } else if constexpr (RESP) {
         const float rar = horner3f(rf[0], jf), rai = horner3f(rf[1], jf);
         const float rer = horner3f(rf[2], jf), rei = horner3f(rf[3], jf);
         float sr = u.x * rar;
@@ -871,8 +939,9 @@ template <int NCH, bool MIXED, int RM>
 __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __restrict__ gtab, int64_t logical,
                                           unsigned char* smem, const double2* __restrict__ s_trig)
 {
-    constexpr int NV = 3 * NCH;  // values per bin
-    constexpr bool RESP = NCH == 2;
+    constexpr int NV = bin_stride(NCH);  // values per bin
+    constexpr bool RESP = NCH >= 2;
+    constexpr int NR = NCH == 3 ? 6 : 4;  // response components
     const int64_t chunk = a.chunk0 + logical / a.n_groups;
     const int64_t group = logical % a.n_groups;
     const int tid = threadIdx.x;
@@ -997,8 +1066,8 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
     const int L = a.L;
     const int nthreads = blockDim.x;
     PhasePoly poly;
-    RespPoly rp;
-    float phf[kRespMixed], rf[4][kRespMixed];
+    RespPolyN<NR> rp;
+    float phf[kRespMixed], rf[NR][kRespMixed];
     float a1h = 0.f;
     SinCosK kk{kSin3, kSin1, kCos2};
     __asm__ volatile("" : "+v"(kk.s3), "+v"(kk.s1), "+v"(kk.c2));
@@ -1012,7 +1081,7 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
         for (int mm = 0; mm < kRespMixed; ++mm) phf[mm] = 0.f;
         if constexpr (RESP) {
 #pragma unroll
-            for (int f = 0; f < 4; ++f)
+            for (int f = 0; f < NR; ++f)
 #pragma unroll
                 for (int mm = 0; mm < kRespMixed; ++mm) rf[f][mm] = 0.f;
         }
@@ -1021,7 +1090,7 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
         for (int mm = 0; mm < kNodes; ++mm) poly.ph[mm] = 0.0;
         if constexpr (RESP) {
 #pragma unroll
-            for (int f = 0; f < 4; ++f)
+            for (int f = 0; f < NR; ++f)
 #pragma unroll
                 for (int mm = 0; mm < kNodes; ++mm) rp.r[f][mm] = 0.0;
         }
@@ -1086,7 +1155,7 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
                 have = sbl;
                 kcl = sbl + (1 << (lgl - 1));
                 const double inv_h = 1.0 / (double)(1 << (lgl - 1));
-                block_setup<RM>(coef, S, p, a.g.k0 + (double)kcl, lgl, gtl + (int64_t)(sbl >> lgl) * kGStride,
+                block_setup<RM, NR>(coef, S, p, a.g.k0 + (double)kcl, lgl, gtl + (int64_t)(sbl >> lgl) * kGStride,
                                   a.g, a.m, poly, rp);
                 if constexpr (MIXED) {
                     // the FP32 residual phase to degree 3 the same way: off by
@@ -1106,7 +1175,7 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
                     // most ~2e-7 of |R| on the blocks the FP64 bound selects, the
                     // size of FP32 rounding
 #pragma unroll
-                    for (int f = 0; f < 4; ++f) {
+                    for (int f = 0; f < NR; ++f) {
                         const double a5 = rp.r[f][5], a4 = rp.r[f][4];
                         rp.r[f][3] += 1.25 * a5;
                         rp.r[f][1] -= 0.3125 * a5;
@@ -1123,7 +1192,7 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
                         poly.ph[mm] *= MIXED ? sc : sc * kPhaseUnits;
                         if constexpr (RESP) {
 #pragma unroll
-                            for (int f = 0; f < 4; ++f) rp.r[f][mm] *= sc;
+                            for (int f = 0; f < NR; ++f) rp.r[f][mm] *= sc;
                         }
                         sc *= inv_h;
                     }
@@ -1145,7 +1214,7 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
                     for (int mm = 2; mm < kRespMixed; ++mm) phf[mm] = (float)poly.ph[mm];
                     if constexpr (RESP) {
 #pragma unroll
-                        for (int f = 0; f < 4; ++f)
+                        for (int f = 0; f < NR; ++f)
 #pragma unroll
                             for (int mm = 0; mm < kRespMixed; ++mm) rf[f][mm] = (float)rp.r[f][mm];
                     }
@@ -1162,7 +1231,7 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
 #pragma unroll 1
                 for (int k = s_lo; k < s_hi; ++k) {
                     if (nxt <= k) handle(k);
-                    bin_fp64<RESP>(jd, binp, s_trig, kk, poly, rp, tmask, toff, amp, zr, zi, hh);
+                    bin_fp64<NCH>(jd, binp, s_trig, kk, poly, rp, tmask, toff, amp, zr, zi, hh);
                     jd += 1.0;
                     binp += NV;
                 }
@@ -1173,7 +1242,7 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
 #pragma unroll 1
                 for (int k = s_lo; k < s_hi; ++k) {
                     if (nxt <= k) handle(k);
-                    bin_mixed<RESP>(jf, binp, phf, a1h, rf, ampf, qzr, qzi, qhh);
+                    bin_mixed<NCH>(jf, binp, phf, a1h, rf, ampf, qzr, qzi, qhh);
                     jf += 1.f;
                     binp += NV;
                     // the plain FP32 sums enter the compensated ones at every
@@ -1205,7 +1274,7 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
 // tile_start[n_items] = total); the counter starts at 0.
 template <int NCH, bool MIXED, int RM>
 __global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(MIXED ? SCS_WAVES_MIXED : SCS_WAVES_FP64))) void k_main_multi(
+__attribute__((amdgpu_waves_per_eu(MIXED ? SCS_WAVES_MIXED : (NCH == 3 ? 2 : SCS_WAVES_FP64)))) void k_main_multi(
     const MainArgs* __restrict__ items, const int64_t* __restrict__ tile_start, int n_items,
     unsigned long long* __restrict__ counter)
 {
@@ -1425,7 +1494,20 @@ __global__ void k_waveform(MainArgs a, double* __restrict__ h_ri)
     const double x = (double)(k - kc) / (double)(Lp >> 1);
     const double f = (a.g.k0 + (double)k) * a.g.df;
     const double amp = pow(f, -7.0 / 6.0);
-    if (nch == 2) {
+    if (nch == 3) {
+        RespPolyN<6> rp3;
+        block_setup<2, 6>((const GLOBAL double*)a.coef, a.stride, 0, a.g.k0 + (double)kc, lg,
+                          (const GLOBAL double*)G, a.g, a.m, poly, rp3);
+        double ph = horner5(poly.ph, x);
+        ph -= rint(ph);
+        double sn, cs;
+        sincos2pi(ph, &sn, &cs);
+        for (int c = 0; c < 3; ++c) {
+            const double rr = horner5(rp3.r[2 * c], x), ri = horner5(rp3.r[2 * c + 1], x);
+            h_ri[((int64_t)c * a.g.K + k) * 2] = amp * (rr * cs + ri * sn);
+            h_ri[((int64_t)c * a.g.K + k) * 2 + 1] = amp * (ri * cs - rr * sn);
+        }
+    } else if (nch == 2) {
         if (a.m.response == 2)
             block_setup<2>((const GLOBAL double*)a.coef, a.stride, 0, a.g.k0 + (double)kc, lg, (const GLOBAL double*)G,
                            a.g, a.m, poly, rp);
@@ -1807,31 +1889,33 @@ void launch_bounds(const BoundArgs& a, hipStream_t s)
         hipLaunchKernelGGL(k_bounds_simple, dim3(nblk(a.P * (a.N + 1), 256)), dim3(256), 0, s, a);
     }
 }
-size_t main_lds_bytes(int nch, int L, bool mixed) { return (size_t)L * 3 * nch * (mixed ? 4 : 8); }
-// The generate-and-reduce instantiation for a response model (0: one
-// channel, no response; 1: A+E low-frequency; 2: A+E full) and precision.
+size_t main_lds_bytes(int nch, int L, bool mixed) { return (size_t)L * bin_stride(nch) * (mixed ? 4 : 8); }
+// The generate-and-reduce instantiation of a kernel variant (variant_of) and
+// precision.
 typedef void (*MainKernel)(const MainArgs*, const int64_t*, int, unsigned long long*);
-static MainKernel main_kernel(int resp, bool mixed)
+static MainKernel main_kernel(int variant, bool mixed)
 {
-    if (resp == 2) return mixed ? k_main_multi<2, true, 2> : k_main_multi<2, false, 2>;
-    if (resp == 1) return mixed ? k_main_multi<2, true, 1> : k_main_multi<2, false, 1>;
-    return mixed ? k_main_multi<1, true, 0> : k_main_multi<1, false, 0>;
+    switch (variant) {
+    case 0: return mixed ? k_main_multi<2, true, 1> : k_main_multi<2, false, 1>;
+    case 1: return mixed ? k_main_multi<2, true, 2> : k_main_multi<2, false, 2>;
+    case 2: return mixed ? k_main_multi<3, true, 2> : k_main_multi<3, false, 2>;
+    default: return mixed ? k_main_multi<1, true, 0> : k_main_multi<1, false, 0>;
+    }
 }
+static int variant_channels(int variant) { return variant == 2 ? 3 : (variant == 3 ? 1 : 2); }
 hipError_t launch_main_multi(const MainArgs* items, const int64_t* tile_start, int n_items, unsigned long long* counter,
-                             int resp, int L, int waves, bool mixed, int grid, hipStream_t s)
+                             int variant, int L, int waves, bool mixed, int grid, hipStream_t s)
 {
-    const int nch = resp == 0 ? 1 : 2;
-    const size_t lds = main_lds_bytes(nch, L, mixed);
-    hipLaunchKernelGGL(main_kernel(resp, mixed), dim3(grid), dim3(64 * waves), lds, s, items, tile_start, n_items,
+    const size_t lds = main_lds_bytes(variant_channels(variant), L, mixed);
+    hipLaunchKernelGGL(main_kernel(variant, mixed), dim3(grid), dim3(64 * waves), lds, s, items, tile_start, n_items,
                        counter);
     return hipGetLastError();
 }
-int main_multi_blocks_per_cu(int resp, int L, int waves, bool mixed)
+int main_multi_blocks_per_cu(int variant, int L, int waves, bool mixed)
 {
-    const int nch = resp == 0 ? 1 : 2;
-    const size_t lds = main_lds_bytes(nch, L, mixed);
+    const size_t lds = main_lds_bytes(variant_channels(variant), L, mixed);
     int nb = 0;
-    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, main_kernel(resp, mixed), 64 * waves, lds);
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, main_kernel(variant, mixed), 64 * waves, lds);
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 void launch_finalize(const FinalArgs& a, hipStream_t s)

@@ -269,9 +269,9 @@ __device__ inline void antenna_lf(double Phi, double cart0, const Pol& pol, doub
 // through its projections on the plane's basis e1 = -r_hat/2 - (sqrt3/2) z_hat,
 // e2 = phi_hat, so an arm costs a few products.  All sines and cosines are of
 // arguments below a few turns (sincos2pi), seven per call.  out = {Re A,
-// Im A, Re E, Im E}.
-template <typename Src>
-__device__ inline void fd_response(double f, double c1, double s1, double cz, double sz, Src src, double out[4])
+// Im A, Re E, Im E} and, for NC = 3, T = (X + Y + Z) / sqrt3 after them.
+template <int NC, typename Src>
+__device__ inline void fd_response(double f, double c1, double s1, double cz, double sz, Src src, double out[2 * NC])
 {
     const double h3 = 0.86602540378443864676;     // sqrt(3)/2
     const double inv_r3 = 0.57735026918962576451;  // 1/sqrt(3)
@@ -341,6 +341,12 @@ __device__ inline void fd_response(double f, double c1, double s1, double cz, do
     out[1] = __builtin_fma(wr, Ai, wi * Ar);
     out[2] = __builtin_fma(wr, Er, -(wi * Ei));
     out[3] = __builtin_fma(wr, Ei, wi * Er);
+    if constexpr (NC == 3) {
+        const double kt = 0.57735026918962576451;  // 1/sqrt3
+        const double Tr = kt * (acc[0][0] + acc[1][0] + acc[2][0]), Ti = kt * (acc[0][1] + acc[1][1] + acc[2][1]);
+        out[4] = __builtin_fma(wr, Tr, -(wi * Ti));
+        out[5] = __builtin_fma(wr, Ti, wi * Tr);
+    }
 }
 
 // Evaluate a degree-4 trigonometric polynomial c[0] + sum_k c[k] cos kPhi + c[4+k] sin kPhi

@@ -77,13 +77,14 @@ def test_batched_and_graph_equal_solo():
 
 def test_batch_mixes_response_models():
     """One batched call (and its graph) over contexts of every kernel
-    instantiation: low-frequency A+E, full-response A+E, one channel, and an
-    eccentric low-frequency context (8-entry theta rows); each item equals
-    its solo evaluation bit for bit."""
+    instantiation: low-frequency A+E, full-response A+E and A+E+T, one
+    channel, and an eccentric low-frequency context (8-entry theta rows);
+    each item equals its solo evaluation bit for bit."""
     lf = D.lisa_small(seed=31)
     fd = D.lisa_small(seed=32, response=O.RESP_LISA_FD)
+    fd3 = D.lisa_small(seed=33, response=O.RESP_LISA_FD, n_chan=3)
     white = D.white16k()
-    hl, hf, hw = _ctx(lf), _ctx(fd), _ctx(white, G=1)
+    hl, hf, hw, h3 = _ctx(lf), _ctx(fd), _ctx(white, G=1), _ctx(fd3)
     he = B.scs_ctx_create(0)
     try:
         g = lf.grid
@@ -96,6 +97,7 @@ def test_batch_mixes_response_models():
                   (hl, 16, 8, D.lisa_particles(150, seed=105)),
                   (hw, 1, 4, wth[:40]),
                   (he, 16, 5, th_e),
+                  (h3, 16, 12, D.lisa_particles(110, seed=108)),
                   (hf, 16, 1, D.lisa_particles(70, seed=106))]
         items = [(h, N, torch.tensor(np.ascontiguousarray(th), device="cuda"),
                   torch.full((th.shape[0],), -1.0, dtype=torch.float64, device="cuda")) for h, G, N, th in shapes]
@@ -126,5 +128,5 @@ def test_batch_mixes_response_models():
         got = items[0][3].cpu().numpy()[:5]
         assert np.max(np.abs(got - ref["ups"]) / np.maximum(np.abs(ref["ups"]), 32.0)) < 1e-9
     finally:
-        for h in (hl, hf, hw, he):
+        for h in (hl, hf, hw, he, h3):
             B.scs_ctx_destroy(h)
