@@ -32,11 +32,11 @@
  * Eccentric models (TaylorF2Ecc, Sec 4) keep the leading-order correction in
  * e0^2 at Newtonian order, pinned against the Peters-Mathews evolution.
  *
- * Parity unpinned: the PN phase coefficients above the Newtonian term (the
- * paper does not print them; they are the standard TaylorF2 values, checked
- * only through an extended-precision evaluation of the same formula and the
- * coalescence times of the injection tables), and the low-frequency response
- * beyond its invariants (the paper's full response code is not available).
+ * The PN phase coefficients above the Newtonian term (the paper does not
+ * print them; they are the standard TaylorF2 values) are pinned by rebuilding
+ * the stationary-phase time from the PN energy and flux functions.
+ * Parity unpinned: the low-frequency response beyond its invariants (the
+ * paper's full response code is not available).
  * The full response is pinned to its own definition (link light-travel
  * formula and TDI with explicit delays, evaluated in the time domain) and to
  * the low-frequency limit, not to another implementation: its constellation
