@@ -187,3 +187,52 @@ def test_search_in_eight_dimensions():
             B.scs_search_destroy(s)
     finally:
         B.scs_ctx_destroy(h)
+
+
+def test_eccentric_lisa1m_full_size_sampled():
+    """The eccentric model at the benchmark's full size (2^20 bins, 10^4
+    particles with e0 uniform in the paper's prior, N = 1024, G = 1024, the
+    low-frequency A/E response) in the step benchmark's launch configuration;
+    the oracle recomputes a seeded sample of particles one by one."""
+    w = synth.workload("lisa1m")
+    g = O.Grid(w.grid.K, w.grid.k0, w.grid.df, 2)
+    m = O.Model(pn_order=7, response=O.RESP_LISA_LF_AE, support=O.SUPPORT_TOBS, t_obs=w.grid.t_obs, eccentric=1)
+    psd = synth.psd_arrays(w)
+    lo8 = np.concatenate([w.prior_lo, [E0_LO]])
+    hi8 = np.concatenate([w.prior_hi, [E0_HI]])
+    inj = np.concatenate([w.injection, [0.05]])
+    ds = D.make(g, m, psd, inj, w.snr, w.seed, True, lo8, hi8)
+    rng = np.random.default_rng(67)
+    theta = np.concatenate([synth.workload_particles(w), rng.uniform(E0_LO, E0_HI, (w.P, 1))], axis=1)
+    theta[:2] = np.concatenate([synth.near_injection(w.injection, 2, seed=6, lo=w.prior_lo, hi=w.prior_hi),
+                                [[0.05], [0.05]]], axis=1)
+    theta = np.ascontiguousarray(theta)
+    N = w.N
+    h = B.scs_ctx_create(0)
+    try:
+        B.scs_load_data(h, np.ascontiguousarray(ds.d_ri), np.ascontiguousarray(psd), g.k0 * g.df, g.df)
+        B.scs_set_model(h, 7, m.response, m.support, m.t_obs, eccentric=1)
+        B.scs_define_segmentation(h, N, B.SCS_SEG_EQUAL_SNR, w.G)
+        assert B.scs_theta_dim(h) == 8
+        tht = torch.tensor(theta, device="cuda")
+        u = torch.empty(theta.shape[0], dtype=torch.float64, device="cuda")
+        B.scs_evaluate(h, tht, u)
+        torch.cuda.synchronize()
+        got = u.cpu().numpy()
+        sup, bnd = B.scs_last_bounds(h, theta.shape[0], N)
+        B.scs_evaluate(h, tht, u, B.SCS_PREC_MIXED)
+        torch.cuda.synchronize()
+        gm = u.cpu().numpy()
+        assert np.all(np.isfinite(got)) and np.all(got >= 0)
+        idx = np.concatenate([[0, 1], np.random.default_rng(5).choice(np.arange(2, len(theta)), 4, replace=False)])
+        ref = O.evaluate(g, m, ds.d_ri, psd, theta[idx], N, O.SEG_EQUAL_SNR, w.G, want_bounds=True)
+        assert np.array_equal(sup[idx], ref["support"])
+        same = np.all(bnd[idx] == ref["bounds"], axis=1)
+        assert same.sum() >= len(same) - 1
+        e = np.abs(got[idx][same] - ref["ups"][same]) / np.maximum(np.abs(ref["ups"][same]), 2.0 * N)
+        em = np.abs(gm[idx][same] - ref["ups"][same]) / np.maximum(np.abs(ref["ups"][same]), 2.0 * N)
+        print(f"eccentric, 2^20 bins: fp64 sampled max floored rel err {e.max():.3g}, mixed {em.max():.3g}; "
+              f"Upsilon near the injection {got[:2]} (oracle {ref['ups'][:2]})")
+        assert e.max() < 1e-9 and em.max() < 1e-5
+    finally:
+        B.scs_ctx_destroy(h)

@@ -128,15 +128,17 @@ def test_noise_free_injection_and_statistics(n_chan):
             B.scs_ctx_destroy(h)
 
 
-def test_full_response_lisa1m_full_size_sampled():
-    """The benchmark's full-response configuration at its full size (2^20 bins,
-    10^4 particles, N = 1024, G = 1024, the TDI noise PSDs) in the launch
-    configuration `bench.py --response fd` times; the oracle recomputes a
-    seeded sample of particles one by one."""
+@pytest.mark.parametrize("n_chan", [2, 3])
+def test_full_response_lisa1m_full_size_sampled(n_chan):
+    """The benchmark's full-response configurations at their full size (2^20
+    bins, 10^4 particles, N = 1024, G = 1024, the TDI noise PSDs) in the launch
+    configurations `bench.py --response fd` (A, E) and `--response fd3`
+    (A, E, T) time; the oracle recomputes a seeded sample of particles one by
+    one."""
     w = synth.workload("lisa1m")
-    g = O.Grid(w.grid.K, w.grid.k0, w.grid.df, 2)
+    g = O.Grid(w.grid.K, w.grid.k0, w.grid.df, n_chan)
     m = O.Model(pn_order=7, response=O.RESP_LISA_FD, support=O.SUPPORT_TOBS, t_obs=w.grid.t_obs)
-    psd = synth.lisa_tdi_psd(w.grid.freqs())[:2]
+    psd = synth.lisa_tdi_psd(w.grid.freqs())[:n_chan]
     ds = D.make(g, m, psd, w.injection, w.snr, w.seed, True, w.prior_lo, w.prior_hi)
     theta = synth.workload_particles(w)
     theta[:2] = synth.near_injection(w.injection, 2, seed=6, lo=w.prior_lo, hi=w.prior_hi)
@@ -160,7 +162,7 @@ def test_full_response_lisa1m_full_size_sampled():
         assert same.sum() >= len(same) - 1
         e = _floored(got[idx][same], ref["ups"][same], N)
         em = _floored(gm[idx][same], ref["ups"][same], N)
-        print(f"full response, 2^20 bins: fp64 sampled max floored rel err {e.max():.3g}, mixed {em.max():.3g}; "
+        print(f"full response, {n_chan} channels, 2^20 bins: fp64 sampled max floored rel err {e.max():.3g}, mixed {em.max():.3g}; "
               f"Upsilon near the injection {got[:2]} (oracle {ref['ups'][:2]})")
         assert e.max() < 1e-9 and em.max() < 1e-5
     finally:
