@@ -77,6 +77,7 @@ extern "C" {
 #define SCS_SEG_EQUAL_SNR 0 /* equal [h|h] per segment, per particle (Sec 2.2) */
 #define SCS_SEG_UNIFORM 1   /* equal bin counts inside the support */
 #define SCS_SEG_EXPLICIT 2  /* caller's bin edges, clamped to the support */
+#define SCS_MAX_SEGMENTS (1 << 20) /* largest N accepted by scs_define_segmentation */
 
 typedef struct scs_ctx scs_ctx;
 typedef struct scs_swarm scs_swarm;
@@ -124,7 +125,7 @@ int scs_load_data(scs_ctx* ctx, int32_t n_chan, int64_t K, double f_min, double 
 int scs_set_model(scs_ctx* ctx, const scs_model* model);
 
 /* Define the segmentation used by scs_evaluate (Sec 2.2).
- *   N      number of segments, >= 1
+ *   N      number of segments, 1..SCS_MAX_SEGMENTS (EINVAL outside)
  *   mode   SCS_SEG_*; EQUAL_SNR places the edges of every particle so that
  *          each segment holds the same [h|h], re-evaluated for every theta
  *   G      node stride of the EQUAL_SNR cumulative (1 = every bin); >= 1

@@ -23,6 +23,7 @@ SCS_PREC_FP64, SCS_PREC_MIXED = 0, 1
 SCS_RESP_NONE, SCS_RESP_LISA_LF_AE, SCS_RESP_LISA_FD_AE = 0, 1, 2
 SCS_SUPPORT_FULL, SCS_SUPPORT_TOBS = 0, 1
 SCS_SEG_EQUAL_SNR, SCS_SEG_UNIFORM, SCS_SEG_EXPLICIT = 0, 1, 2
+SCS_MAX_SEGMENTS = 1 << 20
 
 
 class ScsError(RuntimeError):

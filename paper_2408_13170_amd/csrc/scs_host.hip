@@ -458,7 +458,7 @@ extern "C" int scs_set_model(scs_ctx* c, const scs_model* m)
 extern "C" int scs_define_segmentation(scs_ctx* c, int32_t N, int32_t mode, int32_t G, const int64_t* edges)
 {
     if (!c) return fail(SCS_EINVAL, "ctx is NULL");
-    if (N < 1) return fail(SCS_EINVAL, "N must be >= 1");
+    if (N < 1 || N > SCS_MAX_SEGMENTS) return fail(SCS_EINVAL, "N must be in 1..%d (got %d)", SCS_MAX_SEGMENTS, N);
     if (G < 1) return fail(SCS_EINVAL, "G must be >= 1");
     if (mode < 0 || mode > 2) return fail(SCS_EINVAL, "bad segmentation mode");
     if (mode == SCS_SEG_EXPLICIT) {
@@ -1109,7 +1109,7 @@ extern "C" int scs_footprint(const scs_ctx* c, int64_t P, int32_t N, int32_t pre
 {
     if (!c || !bytes) return fail(SCS_EINVAL, "NULL argument");
     if (!c->has_data) return fail(SCS_ESTATE, "no data loaded");
-    if (P < 0 || N < 1) return fail(SCS_EINVAL, "bad P or N");
+    if (P < 0 || N < 1 || N > SCS_MAX_SEGMENTS) return fail(SCS_EINVAL, "bad P or N");
     const TuneChoice t = choose(c, P, N, prec);
     *bytes = ws_bytes(c, P, N, make_plan(c, P, t));
     return SCS_OK;
@@ -1162,7 +1162,7 @@ static int check_items(const scs_batch_item* items, int32_t n_items, int32_t pre
         const scs_batch_item& it = items[i];
         int rc = check_ready(it.ctx);
         if (rc) return rc;
-        if (it.N < 1 || it.P < 0 || (it.P > 0 && (!it.theta || !it.ups)))
+        if (it.N < 1 || it.N > SCS_MAX_SEGMENTS || it.P < 0 || (it.P > 0 && (!it.theta || !it.ups)))
             return fail(SCS_EINVAL, "item %d: bad N, P or pointers", i);
         if (it.ctx->device != items[0].ctx->device || it.ctx->L != items[0].ctx->L)
             return fail(SCS_EINVAL, "item %d: all items of a batch must share the device", i);
@@ -1619,7 +1619,7 @@ extern "C" int scs_server_submit(scs_server* srv, scs_ctx* ctx, int32_t N, int64
     int rc = check_ready(ctx);
     if (rc) return rc;
     if (ctx->device != srv->device) return fail(SCS_EINVAL, "context is on device %d, server on %d", ctx->device, srv->device);
-    if (N < 1 || P < 1 || !theta || !ups) return fail(SCS_EINVAL, "bad N, P or pointers");
+    if (N < 1 || N > SCS_MAX_SEGMENTS || P < 1 || !theta || !ups) return fail(SCS_EINVAL, "bad N, P or pointers");
     if (prec != SCS_PREC_FP64 && prec != SCS_PREC_MIXED) return fail(SCS_EINVAL, "bad precision");
     if (ctx->mode == SCS_SEG_EXPLICIT && N != ctx->N) return fail(SCS_EINVAL, "EXPLICIT edges were defined for N = %d", ctx->N);
     const uint64_t bytes = request_bytes(ctx, P, N, prec);
@@ -1739,7 +1739,7 @@ extern "C" int scs_autotune(scs_ctx* c, int64_t P, const double* theta_dev, int3
 {
     int rc = check_ready(c);
     if (rc) return rc;
-    if (P < 1 || N < 1) return fail(SCS_EINVAL, "bad P or N");
+    if (P < 1 || N < 1 || N > SCS_MAX_SEGMENTS) return fail(SCS_EINVAL, "bad P or N");
     const std::string key = tune_key(c, P, N, prec);
     if (cache_path) {
         load_cache(c, cache_path);

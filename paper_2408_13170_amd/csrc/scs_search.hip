@@ -265,7 +265,7 @@ static int regroup(scs_search* s)
 extern "C" int scs_search_run_rung(scs_search* s, const scs_rung* r, scs_rung_report* rep, void* stream)
 {
     if (!s || !r) return err(SCS_EINVAL, "NULL argument");
-    if (r->N < 1 || r->max_iters < 1) return err(SCS_EINVAL, "bad rung");
+    if (r->N < 1 || r->N > SCS_MAX_SEGMENTS || r->max_iters < 1) return err(SCS_EINVAL, "bad rung");
     const auto t0 = std::chrono::steady_clock::now();
     int rc;
     if (s->rungs_done > 0 && (rc = regroup(s))) return rc;

@@ -196,6 +196,33 @@ def test_edge_cases_lisa_small():
         c.close()
 
 
+def test_maximum_segment_count():
+    """N at its documented maximum (2^20 segments over a support of a few
+    thousand bins: nearly every segment empty or one bin long) against the
+    oracle, and N one above it rejected."""
+    ds = D.lisa_small(seed=4)
+    th = D.lisa_particles(8, seed=9)
+    th[0] = ds.injection
+    N = B.SCS_MAX_SEGMENTS
+    ref = _ref(ds, th, N, O.SEG_EQUAL_SNR, 1)
+    c = Ctx(ds, N, B.SCS_SEG_EQUAL_SNR, 1)
+    try:
+        got, _ = c.eval(th)
+        sup, bnd = B.scs_last_bounds(c.h, th.shape[0], N)
+        assert np.array_equal(sup, ref["support"])
+        same = np.all(bnd == ref["bounds"], axis=1)
+        assert same.sum() >= 0.95 * len(same)
+        e = _floored(got[same], ref["ups"][same], N)
+        print(f"N = 2^20: {same.sum()} rows with identical edges, fp64 max floored rel err {e.max():.3g}")
+        assert e.max() < TOL64
+        gm, _ = c.eval(th, B.SCS_PREC_MIXED)
+        assert _floored(gm[same], ref["ups"][same], N).max() < TOLMIX
+        with pytest.raises(B.ScsError):
+            B.scs_define_segmentation(c.h, N + 1, B.SCS_SEG_EQUAL_SNR, 1)
+    finally:
+        c.close()
+
+
 def _lisa1m_dataset():
     w = synth.workload("lisa1m")
     g = O.Grid(w.grid.K, w.grid.k0, w.grid.df, 2)
