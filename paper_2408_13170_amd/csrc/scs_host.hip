@@ -703,19 +703,31 @@ static int eval_front(EvalJob& j, const double* theta, double* ups, double* seg,
     return SCS_OK;
 }
 
+// Launch timing (scs_ctx_profile): an event before and after each main launch.
+// Timing is best effort: if an event cannot be created or recorded, that
+// launch is left out of the profile and the evaluation goes on.
 static void prof_begin(scs_ctx* c, hipStream_t s, hipEvent_t* e0)
 {
     *e0 = nullptr;
     if (!c->prof) return;
-    hipEventCreate(e0);
-    hipEventRecord(*e0, s);
+    if (hipEventCreate(e0) != hipSuccess) {
+        *e0 = nullptr;
+        return;
+    }
+    if (hipEventRecord(*e0, s) != hipSuccess) {
+        hipEventDestroy(*e0);
+        *e0 = nullptr;
+    }
 }
 static void prof_end(scs_ctx* c, hipStream_t s, hipEvent_t e0)
 {
     if (!c->prof || !e0) return;
     hipEvent_t e1 = nullptr;
-    hipEventCreate(&e1);
-    hipEventRecord(e1, s);
+    if (hipEventCreate(&e1) != hipSuccess || hipEventRecord(e1, s) != hipSuccess) {
+        if (e1) hipEventDestroy(e1);
+        hipEventDestroy(e0);
+        return;
+    }
     c->ev.emplace_back(e0, e1);
 }
 
@@ -1083,16 +1095,22 @@ extern "C" int scs_ctx_profile(scs_ctx* c, int32_t enable, int64_t* launches, do
 {
     if (!c) return fail(SCS_EINVAL, "ctx is NULL");
     DevScope ds(c->device);
+    // every recorded pair is read (until the first failure) and released
+    int rc = SCS_OK;
     for (auto& e : c->ev) {
-        HIP_TRY(hipEventSynchronize(e.second));
         float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, e.first, e.second));
-        c->prof_ms += ms;
-        c->prof_launches += 1;
+        if (rc == SCS_OK && (hipEventSynchronize(e.second) != hipSuccess ||
+                             hipEventElapsedTime(&ms, e.first, e.second) != hipSuccess))
+            rc = fail(SCS_EDEVICE, "reading the launch timing events failed");
+        if (rc == SCS_OK) {
+            c->prof_ms += ms;
+            c->prof_launches += 1;
+        }
         hipEventDestroy(e.first);
         hipEventDestroy(e.second);
     }
     c->ev.clear();
+    if (rc) return rc;
     if (launches) *launches = c->prof_launches;
     if (total_ms) *total_ms = c->prof_ms;
     if (enable >= 0) {

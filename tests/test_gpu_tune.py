@@ -115,3 +115,27 @@ def test_server_budget_and_drop_on_destroy():
         assert np.array_equal(b, alone)
     print("served before destroy:", len(served), "of", len(bufs))
     B.scs_ctx_destroy(h)
+
+
+def test_launch_profile():
+    """scs_ctx_profile: main launches of evaluations made while it is enabled
+    are counted and timed, none while it is disabled, and enabling it again
+    starts afresh (the query returns the counts before the change)."""
+    ds = D.lisa_small(seed=4)
+    th = torch.tensor(D.lisa_particles(64, seed=10), device="cuda")
+    u = torch.empty(64, dtype=torch.float64, device="cuda")
+    h = _ctx(ds, 8)
+    try:
+        B.scs_ctx_profile(h, 1)
+        for _ in range(3):
+            B.scs_evaluate(h, th, u)
+        torch.cuda.synchronize()
+        n, ms = B.scs_ctx_profile(h, 0)
+        assert n >= 3 and n % 3 == 0 and ms > 0.0
+        B.scs_evaluate(h, th, u)
+        torch.cuda.synchronize()
+        assert B.scs_ctx_profile(h) == (n, ms)
+        assert B.scs_ctx_profile(h, 1) == (n, ms)
+        assert B.scs_ctx_profile(h) == (0, 0.0)
+    finally:
+        B.scs_ctx_destroy(h)
