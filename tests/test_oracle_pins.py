@@ -84,6 +84,47 @@ def test_equal_snr_boundaries_brute_force_dense():
             assert abs(b[n] - k) <= 0, (N, n, b[n], k)
 
 
+def test_equal_snr_edges_two_nodes_closed_form():
+    """Node stride G >= the support length: the rule's only nodes are k_lo and
+    k_hi - 1, the weight is linear between them, the cumulative is the
+    quadratic C(k_lo + m) = m w0 + d m(m - 1)/2 with d = (w1 - w0)/(L - 1),
+    and the edges are its crossings of the targets (n/N) C(k_hi).  On the
+    white one-channel model the weight is f^-7/3 (the template's |h|^2, up to
+    a constant that the targets do not see), so the edges follow in exact
+    rational arithmetic; the oracle sums the interpolated weights bin by bin
+    in FP64 and may differ only where a target lies within its rounding."""
+    from fractions import Fraction as Fr
+
+    ds = D.white_small(K=600, noise=False, snr=0.0)
+    g = ds.grid
+    L = g.K
+    f = lambda k: (g.k0 + k) * g.df  # noqa: E731
+    w0, w1 = Fr(f(0) ** (-7.0 / 3.0)), Fr(f(L - 1) ** (-7.0 / 3.0))
+    d = (w1 - w0) / (L - 1)
+    C = lambda m: m * w0 + d * m * (m - 1) / 2  # noqa: E731
+    tot = C(L)
+    checked = 0
+    for N in (3, 7, 16, 50):
+        b = _ups(ds, ds.injection, N, G=4096, want_bounds=True)["bounds"][0]
+        assert b[0] == 0 and b[-1] == L
+        m = 0
+        for n in range(1, N):
+            tgt = Fr(n, N) * tot
+            while C(m) < tgt:
+                m += 1
+            near = min(abs(C(m) - tgt), abs(C(m - 1) - tgt) if m > 0 else tgt) < Fr(1, 10 ** 12) * tot
+            if not near:
+                assert b[n] == m, (N, n, b[n], m)
+                checked += 1
+            else:
+                assert abs(b[n] - m) <= 1
+    assert checked >= 70
+    # the interpolation matters: the dense rule (G = 1, the exact f^-7/3
+    # weights) moves at least one of these edges
+    assert not np.array_equal(_ups(ds, ds.injection, 50, G=1, want_bounds=True)["bounds"][0],
+                              _ups(ds, ds.injection, 50, G=4096, want_bounds=True)["bounds"][0])
+
+
 def test_boundaries_nest_and_refinement_increases_upsilon():
     """For N | N' the equal-SNR targets nest, so the boundaries nest; splitting
     a segment can only raise sum |Z|^2/H (Cauchy-Schwarz), hence
