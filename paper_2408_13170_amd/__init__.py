@@ -7,13 +7,13 @@ the C entry points one to one, `Context` bundles one search's handle.
 from __future__ import annotations
 
 from . import _binding as B
-from ._binding import (SCS_MEM_DEVICE, SCS_MEM_HOST, SCS_PREC_FP64, SCS_PREC_MIXED, SCS_RESP_LISA_LF_AE,
-                       SCS_RESP_NONE, SCS_SEG_EQUAL_SNR, SCS_SEG_EXPLICIT, SCS_SEG_UNIFORM, SCS_SUPPORT_FULL,
-                       SCS_SUPPORT_TOBS, ScsError)
+from ._binding import (SCS_MAX_SEGMENTS, SCS_MEM_DEVICE, SCS_MEM_HOST, SCS_PREC_FP64, SCS_PREC_MIXED,
+                       SCS_RESP_LISA_FD_AE, SCS_RESP_LISA_LF_AE, SCS_RESP_NONE, SCS_SEG_EQUAL_SNR, SCS_SEG_EXPLICIT,
+                       SCS_SEG_UNIFORM, SCS_SUPPORT_FULL, SCS_SUPPORT_TOBS, ScsError)
 
 __all__ = ["B", "Context", "ScsError", "SCS_PREC_FP64", "SCS_PREC_MIXED", "SCS_RESP_NONE", "SCS_RESP_LISA_LF_AE",
-           "SCS_SUPPORT_FULL", "SCS_SUPPORT_TOBS", "SCS_SEG_EQUAL_SNR", "SCS_SEG_UNIFORM", "SCS_SEG_EXPLICIT",
-           "SCS_MEM_HOST", "SCS_MEM_DEVICE"]
+           "SCS_RESP_LISA_FD_AE", "SCS_SUPPORT_FULL", "SCS_SUPPORT_TOBS", "SCS_SEG_EQUAL_SNR", "SCS_SEG_UNIFORM",
+           "SCS_SEG_EXPLICIT", "SCS_MAX_SEGMENTS", "SCS_MEM_HOST", "SCS_MEM_DEVICE"]
 
 
 class Context:

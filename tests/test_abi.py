@@ -52,3 +52,14 @@ def test_server_arguments_are_checked_before_any_device_work():
     assert L.scs_server_poll(None, None, 0, 0, C.byref(n)) == -1
     assert L.scs_server_destroy(None) == 0
     assert B.scs_server_clock(None) == 0.0
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without libscs.so the binding raises instead of computing anything
+    another way: the product path has no CPU fallback."""
+    monkeypatch.setattr(B, "LIBPATH", str(tmp_path / "libscs.so"))
+    monkeypatch.setattr(B, "_lib", None)
+    with pytest.raises(ImportError, match="missing"):
+        B.lib()
+    with pytest.raises(ImportError):
+        B.scs_ctx_create(0)
