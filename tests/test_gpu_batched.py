@@ -130,3 +130,44 @@ def test_batch_mixes_response_models():
     finally:
         for h in (hl, hf, hw, he, h3):
             B.scs_ctx_destroy(h)
+
+
+def test_batched_hierarchy_full_size_sampled():
+    """The configuration `bench.py --mode batched` times, at full size: the six
+    swarms of the hierarchy, (N, P) = (4096, 16384) ... (1, 128), on the
+    2^20-bin A+E data (G = 1024) in one graph-captured batched launch; two
+    particles of every level recomputed by the oracle, FP64 and mixed."""
+    w = synth.workload("lisa1m")
+    g = O.Grid(w.grid.K, w.grid.k0, w.grid.df, 2)
+    m = O.Model(pn_order=7, response=O.RESP_LISA_LF_AE, support=O.SUPPORT_TOBS, t_obs=w.grid.t_obs)
+    psd = synth.psd_arrays(w)
+    ds = D.make(g, m, psd, w.injection, w.snr, w.seed, True, w.prior_lo, w.prior_hi)
+    h = B.scs_ctx_create(0)
+    try:
+        B.scs_load_data(h, np.ascontiguousarray(ds.d_ri), np.ascontiguousarray(psd), g.k0 * g.df, g.df)
+        B.scs_set_model(h, 7, m.response, m.support, m.t_obs)
+        B.scs_define_segmentation(h, w.N, B.SCS_SEG_EQUAL_SNR, w.G)
+        thetas = [synth.particles(w.prior_lo, w.prior_hi, P, w.seed + 700 + i)
+                  for i, (N, P) in enumerate(synth.LADDER_SWARMS)]
+        items = [(h, N, torch.tensor(th, device="cuda"), torch.empty(P, dtype=torch.float64, device="cuda"))
+                 for (N, P), th in zip(synth.LADDER_SWARMS, thetas)]
+        got = {}
+        for prec in (B.SCS_PREC_FP64, B.SCS_PREC_MIXED):
+            graph = B.scs_graph_create(items, prec)
+            B.scs_graph_launch(graph)
+            torch.cuda.synchronize()
+            got[prec] = [it[3].cpu().numpy().copy() for it in items]
+            B.scs_graph_destroy(graph)
+        rng = np.random.default_rng(12)
+        worst64 = worstmx = 0.0
+        for lvl, ((N, P), th) in enumerate(zip(synth.LADDER_SWARMS, thetas)):
+            assert np.all(np.isfinite(got[B.SCS_PREC_FP64][lvl]))
+            idx = rng.choice(P, 2, replace=False)
+            ref = O.evaluate(g, m, ds.d_ri, psd, th[idx], N, O.SEG_EQUAL_SNR, w.G)["ups"]
+            e64 = np.abs(got[B.SCS_PREC_FP64][lvl][idx] - ref) / np.maximum(np.abs(ref), 2.0 * N)
+            emx = np.abs(got[B.SCS_PREC_MIXED][lvl][idx] - ref) / np.maximum(np.abs(ref), 2.0 * N)
+            worst64, worstmx = max(worst64, e64.max()), max(worstmx, emx.max())
+            assert e64.max() < 1e-9 and emx.max() < 1e-5, (N, P, e64, emx)
+        print(f"batched hierarchy, 2^20 bins: fp64 sampled max floored rel err {worst64:.3g}, mixed {worstmx:.3g}")
+    finally:
+        B.scs_ctx_destroy(h)
