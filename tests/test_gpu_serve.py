@@ -74,3 +74,57 @@ def test_served_results_equal_alone():
     finally:
         B.scs_ctx_destroy(hl)
         B.scs_ctx_destroy(hw)
+
+
+def test_served_full_size_sampled():
+    """The request loop on searches of the served benchmark at full size (2^20
+    and 2^21 bins, G = 1024, the benchmark's segment ladder and swarm sizes,
+    server shape as in `bench.py --mode serve`): every request completes and
+    sampled particles of every request agree with the oracle, FP64 and
+    mixed."""
+    import oracle as O
+
+    streams = synth.served_streams()
+    searches = []
+    for w in (streams[1], streams[2]):
+        g = O.Grid(w.grid.K, w.grid.k0, w.grid.df, 2)
+        m = O.Model(pn_order=7, response=O.RESP_LISA_LF_AE, support=O.SUPPORT_TOBS, t_obs=w.grid.t_obs)
+        psd = synth.psd_arrays(w)
+        ds = D.make(g, m, psd, w.injection, w.snr, w.seed, True, w.prior_lo, w.prior_hi)
+        searches.append((w, ds, _ctx(ds, w.G)))
+    rng = np.random.default_rng(17)
+    reqs = []
+    for r in range(6):
+        si = r % 2
+        w, ds, h = searches[si]
+        P = int(np.exp(rng.uniform(np.log(256), np.log(16384))))
+        N = int(rng.choice([4096, 1024, 256, 64, 16]))
+        reqs.append(dict(si=si, N=N, th=synth.particles(w.prior_lo, w.prior_hi, P, 1000 + r),
+                         prec=B.SCS_PREC_MIXED if r % 3 == 2 else B.SCS_PREC_FP64))
+    try:
+        srv = B.scs_server_create(0, max_inflight=32, hbm_budget=64 << 30, n_streams=4)
+        try:
+            for q in reqs:
+                q["ups"] = np.full(q["th"].shape[0], -1.0)
+                B.scs_server_submit(srv, searches[q["si"]][2], q["N"], q["th"], q["ups"], q["prec"])
+            done = []
+            t_end = time.time() + 90
+            while len(done) < len(reqs) and time.time() < t_end:
+                done += B.scs_server_poll(srv, wait_ms=50)
+        finally:
+            B.scs_server_destroy(srv)
+        assert len(done) == len(reqs) and all(d["status"] == 0 for d in done)
+        worst = {B.SCS_PREC_FP64: 0.0, B.SCS_PREC_MIXED: 0.0}
+        for q in reqs:
+            w, ds, _ = searches[q["si"]]
+            assert np.all(np.isfinite(q["ups"]))
+            idx = rng.choice(q["th"].shape[0], 2, replace=False)
+            ref = O.evaluate(ds.grid, ds.model, ds.d_ri, ds.psd, q["th"][idx], q["N"], O.SEG_EQUAL_SNR, w.G)["ups"]
+            e = np.abs(q["ups"][idx] - ref) / np.maximum(np.abs(ref), 2.0 * q["N"])
+            worst[q["prec"]] = max(worst[q["prec"]], e.max())
+            assert e.max() < (1e-9 if q["prec"] == B.SCS_PREC_FP64 else 1e-5), (q["N"], q["th"].shape[0], e)
+        print(f"served at 2^20 / 2^21 bins: fp64 sampled max floored rel err {worst[B.SCS_PREC_FP64]:.3g}, "
+              f"mixed {worst[B.SCS_PREC_MIXED]:.3g}")
+    finally:
+        for _, _, h in searches:
+            B.scs_ctx_destroy(h)
