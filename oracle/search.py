@@ -146,11 +146,17 @@ def converged(history, tol, window):
 
 
 class Swarm:
-    def __init__(self, theta, vel, swarm_id):
+    """A swarm's state.  Best values start at -inf; the best positions start
+    at the particles' own positions, or at the positions given (a re-grouped
+    swarm keeps its particles' earlier best positions as attractors)."""
+
+    def __init__(self, theta, vel, swarm_id, pbest=None, gbest=None):
         P = theta.shape[0]
         self.theta, self.vel, self.id = theta, vel, swarm_id
-        self.pbest, self.pbest_val = theta.copy(), np.full(P, -np.inf)
-        self.gbest, self.gbest_val = theta[0].copy(), -np.inf
+        self.pbest = theta.copy() if pbest is None else pbest.copy()
+        self.pbest_val = np.full(P, -np.inf)
+        self.gbest = (theta[0] if gbest is None else gbest).copy()
+        self.gbest_val = -np.inf
         self.iteration = 0
 
 
@@ -174,14 +180,25 @@ class Search:
             self.next_id += 1
 
     def regroup(self):
+        """k-means on all positions (Sec 3.2); every cluster becomes a swarm.
+        Positions, velocities and best positions carry over; best values
+        restart at -inf because the objective changed.  Positions outside the
+        prior box score -inf, so a best position is always inside the box:
+        keeping them as attractors pulls a cluster of particles that stand
+        outside the box back in.  The swarm's best position starts at the
+        best position of its particle with the highest earlier best value
+        (the first such particle on ties)."""
         th = np.concatenate([s.theta for s in self.swarms])
         vel = np.concatenate([s.vel for s in self.swarms])
+        pb = np.concatenate([s.pbest for s in self.swarms])
+        pv = np.concatenate([s.pbest_val for s in self.swarms])
         f = features(th, self.lo, self.hi, self.periodic)
         lab, _ = kmeans(f, self.k, self.kmeans_iters, self.seed ^ (0x6B6D65616E73 + self.rungs_done))
         self.swarms = []
         for c in range(int(lab.max()) + 1):
             sel = lab == c
-            self.swarms.append(Swarm(th[sel].copy(), vel[sel].copy(), self.next_id))
+            j = int(np.argmax(pv[sel]))
+            self.swarms.append(Swarm(th[sel].copy(), vel[sel].copy(), self.next_id, pbest=pb[sel], gbest=pb[sel][j]))
             self.next_id += 1
 
     def step(self, sw, N, prm):

@@ -14,8 +14,13 @@
 //   regroup:   before every rung but the first, k-means on the positions of
 //              all particles of all swarms (k = the initial number of
 //              swarms); every non-empty cluster becomes a swarm; the number of
-//              particles is conserved.  Positions and velocities carry over;
-//              the bests start afresh because the objective changed.
+//              particles is conserved.  Positions, velocities and best
+//              positions carry over; best values restart because the
+//              objective changed.  A position outside the prior box scores
+//              -inf, so best positions lie inside the box, and as attractors
+//              they pull a cluster of particles that stand outside back in.
+//              The swarm's best position starts at the best position of its
+//              particle with the highest earlier best value.
 //
 // k-means runs on the host: once per rung on P x 7 numbers (about 60000 x 7
 // for the paper's search), milliseconds against the seconds of a rung.
@@ -202,11 +207,11 @@ static int regroup(scs_search* s)
     int64_t P = 0;
     for (int64_t n : s->sizes) P += n;
     const int D = s->dim;
-    std::vector<double> th((size_t)P * D), vel((size_t)P * D);
+    std::vector<double> th((size_t)P * D), vel((size_t)P * D), pb((size_t)P * D), pv(P);
     int64_t off = 0;
     for (int i = 0; i < nsw; ++i) {
-        int rc = scs_swarm_read(s->swarms[i], &th[(size_t)off * D], &vel[(size_t)off * D], nullptr, nullptr, nullptr,
-                                nullptr, nullptr);
+        int rc = scs_swarm_read(s->swarms[i], &th[(size_t)off * D], &vel[(size_t)off * D], &pb[(size_t)off * D],
+                                &pv[off], nullptr, nullptr, nullptr);
         if (rc) return rc;
         off += s->sizes[i];
     }
@@ -234,22 +239,30 @@ static int regroup(scs_search* s)
     if (rc) return rc;
     std::vector<scs_swarm*> nsws;
     std::vector<int64_t> nsizes;
+    const double ninf = -std::numeric_limits<double>::infinity();
     for (int c = 0; c < k; ++c) {
-        std::vector<double> tc, vc;
+        std::vector<double> tc, vc, bc;
+        int64_t top = 0, n = 0;
+        double top_val = ninf;
         for (int64_t i = 0; i < P; ++i)
             if (lab[i] == c) {
                 tc.insert(tc.end(), &th[(size_t)i * D], &th[(size_t)i * D + D]);
                 vc.insert(vc.end(), &vel[(size_t)i * D], &vel[(size_t)i * D + D]);
+                bc.insert(bc.end(), &pb[(size_t)i * D], &pb[(size_t)i * D + D]);
+                if (pv[i] > top_val) {
+                    top_val = pv[i];
+                    top = n;
+                }
+                ++n;
             }
-        const int64_t pc = (int64_t)tc.size() / D;
         scs_swarm* sw = nullptr;
-        if ((rc = scs_swarm_create(s->ctx, &sw, pc, s->lo, s->hi, s->per, s->p.seed, s->next_id++))) break;
+        if ((rc = scs_swarm_create(s->ctx, &sw, n, s->lo, s->hi, s->per, s->p.seed, s->next_id++))) break;
         nsws.push_back(sw);
-        nsizes.push_back(pc);
-        // bests start afresh: the first step of the rung only evaluates
-        std::vector<double> pv(pc, -std::numeric_limits<double>::infinity());
-        if ((rc = scs_swarm_write(sw, tc.data(), vc.data(), tc.data(), pv.data(), tc.data(),
-                                  -std::numeric_limits<double>::infinity(), 0u)))
+        nsizes.push_back(n);
+        // best values restart (the first step of the rung only evaluates);
+        // the best positions carry over as attractors
+        std::vector<double> bv(n, ninf);
+        if ((rc = scs_swarm_write(sw, tc.data(), vc.data(), bc.data(), bv.data(), &bc[(size_t)top * D], ninf, 0u)))
             break;
     }
     if (rc) {

@@ -136,3 +136,52 @@ def test_search_matches_oracle():
             B.scs_search_destroy(s)
     finally:
         B.scs_ctx_destroy(h)
+
+
+# the rows of tab:PSO_hyperparams at the paper's prior (N = 100, 50, 10, 1)
+LADDER_PAPER = [(100, 0.5, 0.2, 0.3, [0.1, 0.05, 5e-8, 0.1, 0.1, 0.2, 0.1]),
+                (50, 0.5, 0.2, 0.4, [0.01, 0.05, 1e-8, 0.01, 0.01, 0.2, 0.1]),
+                (10, 0.3, 0.2, 0.5, [0.001, 0.05, 1e-8, 0.001, 0.001, 0.01, 0.1]),
+                (1, 0.72, 1.193, 1.193, [0.0] * 7)]
+
+
+def test_search_full_size_sampled():
+    """The search `bench.py --mode search` runs, at full size (6 swarms x 10^4
+    particles, 2^20 bins, G = 1024, the ladder N = 100, 50, 10, 1 with its
+    rung hyper-parameters), cut to 4 iterations per rung: particles are
+    conserved through every k-means re-grouping, every swarm's best position
+    lies in the prior box and its best value equals the oracle's Upsilon_N
+    there."""
+    w = synth.workload("lisa1m")
+    g = O.Grid(w.grid.K, w.grid.k0, w.grid.df, 2)
+    m = O.Model(pn_order=7, response=O.RESP_LISA_LF_AE, support=O.SUPPORT_TOBS, t_obs=w.grid.t_obs)
+    psd = synth.psd_arrays(w)
+    ds = D.make(g, m, psd, w.injection, w.snr, w.seed, True, w.prior_lo, w.prior_hi)
+    h = B.scs_ctx_create(0)
+    try:
+        B.scs_load_data(h, np.ascontiguousarray(ds.d_ri), np.ascontiguousarray(psd), g.k0 * g.df, g.df)
+        B.scs_set_model(h, 7, m.response, m.support, m.t_obs)
+        B.scs_define_segmentation(h, 1, B.SCS_SEG_EQUAL_SNR, w.G)
+        s = B.scs_search_create(h, 6, 10000, w.prior_lo, w.prior_hi, synth.PERIODIC, G=w.G, conv_tol=2.0,
+                                conv_window=50, kmeans_iters=100, seed=synth.BASE_SEED + 61)
+        try:
+            worst = 0.0
+            for N, om, pp, pg, eps in LADDER_PAPER:
+                rep = B.scs_search_run_rung(s, N, 4, B.pso_params(om, pp, pg, eps))
+                sizes, best = B.scs_search_swarms(s)
+                assert rep["N"] == N and 1 <= rep["iterations"] <= 4
+                assert sizes.sum() == 6 * 10000 and np.all(sizes > 0)
+                # best positions lie in the prior box, also for swarms re-grouped from
+                # particles that stood outside it
+                assert np.all((best[:, :7] >= w.prior_lo) & (best[:, :7] <= w.prior_hi))
+                ref = O.evaluate(g, m, ds.d_ri, psd, np.ascontiguousarray(best[:, :7]), N, O.SEG_EQUAL_SNR,
+                                 w.G)["ups"]
+                e = np.abs(best[:, 7] - ref) / np.maximum(np.abs(ref), 2.0 * N)
+                worst = max(worst, e.max())
+                print(f"rung N={N}: {len(sizes)} swarms {list(sizes)}, bests {np.round(best[:, 7], 2)}")
+                assert e.max() < 1e-9, (N, e)
+            print(f"full-size search: swarm bests against the oracle, max floored rel err {worst:.3g}")
+        finally:
+            B.scs_search_destroy(s)
+    finally:
+        B.scs_ctx_destroy(h)
