@@ -103,3 +103,38 @@ def test_search_on_a_known_peak():
     s2 = S.Search(objective, 3, 40, lo, hi, per, seed=77, conv_tol=0.5, conv_window=5, kmeans_iters=50)
     for N, prm in ((4, (0.5, 0.2, 0.3, [0.01] * 7)),):
         assert s2.run_rung(N, 60, prm) == reports[0]
+
+
+def test_regroup_keeps_best_positions_and_restarts_values():
+    """Between rungs (Sec 3.2): positions, velocities and best positions carry
+    over, best values restart at -inf, and a new swarm's best position is the
+    best position of its particle with the highest earlier best value.  A
+    cluster of particles standing outside the prior box keeps attractors
+    inside it, and its next move heads back in."""
+    lo, hi = np.zeros(7), np.ones(7)
+    per = np.zeros(7, dtype=np.int32)
+    s = S.Search(lambda th, N: np.zeros(th.shape[0]), 2, 40, lo, hi, per, seed=3, kmeans_iters=50)
+    rng = np.random.default_rng(0)
+    for sw in s.swarms:
+        sw.pbest = sw.theta.copy()
+        sw.pbest_val = rng.normal(size=sw.theta.shape[0])
+    # swarm 1's particles all stand outside the box in dimension 0
+    s.swarms[1].theta[:, 0] = 1.5 + 0.01 * np.arange(40)
+    th = np.concatenate([w.theta for w in s.swarms])
+    pb = np.concatenate([w.pbest for w in s.swarms])
+    pv = np.concatenate([w.pbest_val for w in s.swarms])
+    s.rungs_done = 1
+    s.regroup()
+    assert sum(w.theta.shape[0] for w in s.swarms) == 80
+    for w in s.swarms:
+        rows = [int(np.flatnonzero(np.all(th == x, axis=1))[0]) for x in w.theta]
+        assert np.array_equal(w.pbest, pb[rows])
+        assert np.all(w.pbest_val == -np.inf) and w.gbest_val == -np.inf
+        assert np.array_equal(w.gbest, pb[rows][int(np.argmax(pv[rows]))])
+        assert np.all((w.pbest >= lo) & (w.pbest <= hi)) and np.all((w.gbest >= lo) & (w.gbest <= hi))
+    outside = [w for w in s.swarms if np.all(w.theta[:, 0] > 1.0)]
+    assert outside, "the out-of-box particles form a cluster of their own"
+    w = outside[0]
+    before = w.theta[:, 0].copy()
+    S.pso_move(w.theta, w.vel, w.pbest, w.gbest, 0.5, 0.5, 0.5, np.zeros(7), lo, hi, per, 3, w.id, 1)
+    assert np.all(w.theta[:, 0] < before)
