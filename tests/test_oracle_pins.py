@@ -125,6 +125,24 @@ def test_equal_snr_edges_two_nodes_closed_form():
                               _ups(ds, ds.injection, 50, G=4096, want_bounds=True)["bounds"][0])
 
 
+def test_one_bin_per_segment_gives_the_data_norm():
+    """With one channel and one bin per segment, every term is
+    4 df |d conj(h)/S|^2 / (|h|^2/S) = 4 df |d|^2/S (Sec 2.2, the statistic
+    at its finest segmentation): Upsilon_N is <d|d> over the support whatever
+    the template, so on the full-support white model it does not depend on
+    Mc or eta at all."""
+    ds = D.white_small(K=512, noise=True, snr=12.0)
+    g = ds.grid
+    dd = O.data_norm(g, ds.d_ri, ds.psd)
+    th = np.tile(ds.injection, (4, 1))
+    th[1, 0], th[2, 1], th[3, :2] = 25.0, 0.2, (34.0, 0.16)
+    for mode, edges in ((O.SEG_UNIFORM, None), (O.SEG_EXPLICIT, np.arange(g.K + 1, dtype=np.int64))):
+        u = _ups(ds, th, g.K, mode=mode, edges=edges)["ups"]
+        assert np.allclose(u, dd, rtol=1e-12, atol=0), (mode, u, dd)
+    # and at any coarser segmentation it is below <d|d> (Cauchy-Schwarz)
+    assert np.all(_ups(ds, th, 64, mode=O.SEG_UNIFORM)["ups"] < dd)
+
+
 def test_boundaries_nest_and_refinement_increases_upsilon():
     """For N | N' the equal-SNR targets nest, so the boundaries nest; splitting
     a segment can only raise sum |Z|^2/H (Cauchy-Schwarz), hence
