@@ -444,8 +444,11 @@ int scs_search_create(scs_ctx* ctx, const scs_search_params* params, const doubl
 /* Run one rung: before every rung but the first, re-group all particles by
  * k-means of their positions (features: each dimension scaled to the prior
  * box, periodic ones as the point (cos, sin) / 2 pi on the circle;
- * k = n_swarms; empty clusters dropped) into new swarms whose bests start
- * afresh; then define the rung's segmentation on the context and iterate
+ * k = n_swarms; empty clusters dropped) into new swarms: positions,
+ * velocities and best positions carry over, best values restart at -inf (a
+ * swarm's best position starts at the best position of its particle with the
+ * highest earlier best value); then define the rung's segmentation on the
+ * context and iterate
  * every swarm that has not converged, all of them in one scs_pso_step_swarms
  * per iteration, until each has converged (a converged swarm stops moving)
  * or max_iters.  report may be NULL.  Synchronises the stream once per
