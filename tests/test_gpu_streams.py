@@ -105,3 +105,46 @@ def test_chi2_law_at_scale(snr):
             assert abs(u.mean() - mean) < 4 * math.sqrt(var / R)
     finally:
         B.scs_ctx_destroy(h)
+
+
+def test_streams_lisa1m_full_size_sampled():
+    """The configuration `bench.py --mode streams` times, at its full grid: the
+    GW150914-like injection alone in the 2^20-bin A+E band at SNR 20 (G =
+    1024), realisations generated on the device, then the streamed statistics
+    of the injected theta at N in {1, 10, 50, 100}; three realisations
+    recomputed by the oracle (its own noise generator and statistics).  The
+    benchmark streams 1024 realisations; 64 here keep the test's memory small,
+    and the per-realisation work is the same."""
+    w = synth.workload("lisa1m")
+    g = O.Grid(w.grid.K, w.grid.k0, w.grid.df, 2)
+    m = O.Model(pn_order=7, response=O.RESP_LISA_LF_AE, support=O.SUPPORT_TOBS, t_obs=w.grid.t_obs)
+    psd = synth.psd_arrays(w)
+    ds = D.make(g, m, psd, w.injection, 20.0, w.seed, False)
+    seed, R = synth.BASE_SEED + 51, 64
+    h = B.scs_ctx_create(0)
+    try:
+        B.scs_load_data(h, np.ascontiguousarray(ds.d_ri), np.ascontiguousarray(psd), g.k0 * g.df, g.df)
+        B.scs_set_model(h, 7, m.response, m.support, m.t_obs)
+        B.scs_define_segmentation(h, 1, B.SCS_SEG_EQUAL_SNR, w.G)
+        streams = torch.empty((2, g.K, R, 2), dtype=torch.float64, device="cuda")
+        B.scs_make_realisations(h, streams, seed, 0, 1.0)
+        stats = torch.empty((R, B.SCS_NSTATS), dtype=torch.float64, device="cuda")
+        sample = [0, 17, 63]
+        datas = {}
+        for r in sample:
+            n = ds.d + O.noise(g, psd, seed, r)
+            datas[r] = np.stack([n.real, n.imag], -1)
+        worst = 0.0
+        for N in (1, 10, 50, 100):
+            B.scs_define_segmentation(h, N, B.SCS_SEG_EQUAL_SNR, w.G)
+            B.scs_evaluate_streams(h, w.injection, streams, stats)
+            s = stats.cpu().numpy()
+            assert np.all(np.isfinite(s[:, 0]))
+            for r in sample:
+                ref = O.likelihood_stats(g, m, datas[r], psd, w.injection[None, :], N, O.SEG_EQUAL_SNR, w.G)
+                e = abs(s[r, 0] - ref["ups"][0]) / max(abs(ref["ups"][0]), 2.0 * N)
+                worst = max(worst, e)
+                assert e < 1e-9 and abs(s[r, 2] / ref["hh"][0] - 1) < 5e-11, (N, r, e)
+        print(f"streams, 2^20 bins: sampled realisations, max floored rel err {worst:.3g}")
+    finally:
+        B.scs_ctx_destroy(h)
