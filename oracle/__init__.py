@@ -96,6 +96,9 @@ def lib():
         L.orc_evaluate.argtypes = [C.POINTER(_Grid), C.POINTER(_Model), dp, dp, C.c_int64, dp,
                                    C.c_int32, C.c_int32, C.c_int32, ip, dp, dp, ip, ip, C.c_int32]
         L.orc_evaluate.restype = C.c_int
+        L.orc_edge_cumulative.argtypes = [C.POINTER(_Grid), C.POINTER(_Model), dp, dp, C.c_int32, C.c_int64, ip,
+                                          dp, dp, ip]
+        L.orc_edge_cumulative.restype = C.c_int
         L.orc_template.argtypes = [C.POINTER(_Grid), C.POINTER(_Model), dp, dp]
         L.orc_template.restype = C.c_int
         L.orc_phase.argtypes = [C.POINTER(_Model), dp, C.c_int64, dp, dp, dp, dp, dp]
@@ -169,6 +172,26 @@ def evaluate(grid: Grid, model: Model, d_ri, psd, theta, N, mode=SEG_EQUAL_SNR, 
     return out
 
 
+def edge_cumulative(grid: Grid, model: Model, psd, theta, G, ks):
+    """The equal-[h|h] edge rule's cumulative C(k) of one particle at bins ks
+    (clamped to its support), its total C(k_hi) and the support (k_lo, k_hi).
+    The rule: nodes k_lo + jG and k_hi - 1, weights linear between nodes,
+    C(k) = sum of the weights of bins k_lo..k-1 (Sec 2.2, equal [h|h] per
+    segment)."""
+    psd = _f64(psd)
+    theta = _f64(theta).reshape(model.theta_dim)
+    k = np.ascontiguousarray(np.atleast_1d(ks), dtype=np.int64)
+    Ck = np.empty(k.size)
+    tot = C.c_double()
+    sup = np.empty(2, dtype=np.int64)
+    g, m = grid.c(), model.c()
+    rc = lib().orc_edge_cumulative(C.byref(g), C.byref(m), _dp(psd), _dp(theta), int(G), k.size, _ip(k),
+                                   _dp(Ck), C.byref(tot), _ip(sup))
+    if rc != 0:
+        raise ValueError(f"orc_edge_cumulative failed ({rc})")
+    return Ck, tot.value, (int(sup[0]), int(sup[1]))
+
+
 def data_norm(grid: Grid, d_ri, psd):
     """<d|d> = sum_alpha 4 df sum_k |d_alpha(f_k)|^2 / S_alpha(f_k)
     (eqn:inner_prod with a = b = d, rectangle rule on the bins)."""
@@ -187,14 +210,15 @@ def likelihood_stats(grid: Grid, model: Model, d_ri, psd, theta, N, mode=SEG_EQU
         hh       <h|h> = sum_n [h|h]_n = 4 df sum_n H_n    (eqn:SNR_coherent, squared)
         dh       <d|h> as a complex number 4 df sum_n Z_n, so that
                  <d|h e^{i phi}> = Re(e^{-i phi} dh)       (eqn:inner_prod)
-    Returns a dict of [P] arrays (dh complex); NaN rows for invalid theta."""
-    out = evaluate(grid, model, d_ri, psd, theta, N, mode, G, edges, want_seg=True)
+    Returns a dict of [P] arrays (dh complex; 'bounds' [P, N+1] the edges);
+    NaN rows for invalid theta."""
+    out = evaluate(grid, model, d_ri, psd, theta, N, mode, G, edges, want_seg=True, want_bounds=True)
     seg = out["seg"]
     Z = seg[..., 0] + 1j * seg[..., 1]
     H = seg[..., 2]
     w = 4.0 * grid.df
     return {"ups": out["ups"], "overlap": w * np.sum(np.abs(Z), axis=1), "hh": w * np.sum(H, axis=1),
-            "dh": w * np.sum(Z, axis=1)}
+            "dh": w * np.sum(Z, axis=1), "bounds": out["bounds"]}
 
 
 def loglike(dd, stats, amp, phase=None):

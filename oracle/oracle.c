@@ -459,6 +459,42 @@ static double weight(const src_t* s, const orc_model* m, const orc_grid* g, cons
     return w;
 }
 
+/* Cumulative of the equal-[h|h] edge rule over a non-empty support:
+ * nodes x_j = k_lo + j G and k_hi - 1, W(k) = w(k) at nodes and linear in k
+ * between them, C(k) = sum_{i = k_lo}^{k-1} W(i), returned as a malloc'd
+ * array C[k - k_lo] for k = k_lo..k_hi, summed bin by bin. */
+static double* edge_cumulative(const src_t* s, const orc_model* m, const orc_grid* g, const double* psd,
+                               int64_t klo, int64_t khi, int32_t G)
+{
+    const int64_t len = khi - klo;
+    /* node list */
+    int64_t nn = (len - 1) / G + 1;
+    if (klo + (nn - 1) * (int64_t)G != khi - 1) ++nn;
+    int64_t* xs = (int64_t*)malloc(sizeof(int64_t) * nn);
+    double* ws = (double*)malloc(sizeof(double) * nn);
+    for (int64_t j = 0; j < nn; ++j) {
+        xs[j] = (j == nn - 1) ? khi - 1 : klo + j * (int64_t)G;
+        ws[j] = weight(s, m, g, psd, xs[j]);
+    }
+    double* C = (double*)malloc(sizeof(double) * (len + 1));
+    C[0] = 0.0;
+    int64_t j = 0;
+    for (int64_t k = klo; k < khi; ++k) {
+        while (j + 1 < nn && xs[j + 1] <= k) ++j;
+        double W;
+        if (j + 1 < nn) {
+            const double frac = (double)(k - xs[j]) / (double)(xs[j + 1] - xs[j]);
+            W = ws[j] + (ws[j + 1] - ws[j]) * frac;
+        } else {
+            W = ws[j];
+        }
+        C[k - klo + 1] = C[k - klo] + W;
+    }
+    free(ws);
+    free(xs);
+    return C;
+}
+
 /* Segment boundaries b[0..N].
  * mode 0 (equal [h|h], the paper's choice): nodes x_j = k_lo + j G and
  *   k_hi - 1; W(k) = w(k) at nodes, linear in k between nodes;
@@ -488,30 +524,7 @@ static void boundaries(const src_t* s, const orc_model* m, const orc_grid* g, co
         return;
     }
     const int64_t len = khi - klo;
-    /* node list */
-    int64_t nn = (len - 1) / G + 1;
-    if (klo + (nn - 1) * (int64_t)G != khi - 1) ++nn;
-    int64_t* xs = (int64_t*)malloc(sizeof(int64_t) * nn);
-    double* ws = (double*)malloc(sizeof(double) * nn);
-    for (int64_t j = 0; j < nn; ++j) {
-        xs[j] = (j == nn - 1) ? khi - 1 : klo + j * (int64_t)G;
-        ws[j] = weight(s, m, g, psd, xs[j]);
-    }
-    /* cumulative C(k) for k = klo..khi, summed bin by bin */
-    double* C = (double*)malloc(sizeof(double) * (len + 1));
-    C[0] = 0.0;
-    int64_t j = 0;
-    for (int64_t k = klo; k < khi; ++k) {
-        while (j + 1 < nn && xs[j + 1] <= k) ++j;
-        double W;
-        if (j + 1 < nn) {
-            const double frac = (double)(k - xs[j]) / (double)(xs[j + 1] - xs[j]);
-            W = ws[j] + (ws[j + 1] - ws[j]) * frac;
-        } else {
-            W = ws[j];
-        }
-        C[k - klo + 1] = C[k - klo] + W;
-    }
+    double* C = edge_cumulative(s, m, g, psd, klo, khi, G);
     const double tot = C[len];
     int64_t kk = 0;
     for (int n = 1; n < N; ++n) {
@@ -520,8 +533,6 @@ static void boundaries(const src_t* s, const orc_model* m, const orc_grid* g, co
         b[n] = klo + kk;
     }
     free(C);
-    free(ws);
-    free(xs);
 }
 
 /* Channels each response model produces: none 1, low-frequency 2 (A, E),
@@ -610,6 +621,39 @@ int orc_evaluate(const orc_grid* g, const orc_model* m, const double* d_ri, cons
         }
         free(b);
     }
+    return 0;
+}
+
+/* The edge rule's cumulative for one particle (test support: where an edge
+ * computed elsewhere differs from this oracle's, the cumulative shows
+ * whether the target sits within rounding of C there).  sup [2] receives
+ * the support; C(k) for the nk bins ks[i] (each clamped to [k_lo, k_hi]) goes
+ * to Ck, and C(k_hi) to *total.  Returns -1 for invalid theta, -2 for a bad
+ * channel count; an empty support gives total 0. */
+int orc_edge_cumulative(const orc_grid* g, const orc_model* m, const double* psd, const double* theta, int32_t G,
+                        int64_t nk, const int64_t* ks, double* Ck, double* total, int64_t* sup)
+{
+    if (G < 1) return -1;
+    if (!channels_ok(m, g)) return -2;
+    src_t s;
+    make_source(theta, m, &s);
+    if (!s.valid) return -1;
+    int64_t klo, khi;
+    support(&s, m, g, theta[TH_FLOW], &klo, &khi);
+    sup[0] = klo;
+    sup[1] = khi;
+    if (khi <= klo) {
+        *total = 0.0;
+        for (int64_t i = 0; i < nk; ++i) Ck[i] = 0.0;
+        return 0;
+    }
+    double* C = edge_cumulative(&s, m, g, psd, klo, khi, G);
+    *total = C[khi - klo];
+    for (int64_t i = 0; i < nk; ++i) {
+        int64_t k = ks[i] < klo ? klo : (ks[i] > khi ? khi : ks[i]);
+        Ck[i] = C[k - klo];
+    }
+    free(C);
     return 0;
 }
 

@@ -7,6 +7,7 @@ import pytest
 import oracle as O
 import synth
 from tests import datasets as D
+from tests import parity as PT
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -53,13 +54,19 @@ def test_batched_and_graph_equal_solo():
                 assert np.array_equal(u.cpu().numpy(), bv), (N, P, prec)
             if prec == B.SCS_PREC_FP64:
                 # oracle spot check on two items of different channel counts
+                # (edges from the solo evaluation of the same particles, which
+                # gave the batched values bit for bit)
                 for k in (0, 1):
                     h, ds, N, P, th = shapes[k]
-                    ref = O.evaluate(ds.grid, ds.model, ds.d_ri, ds.psd, th[:6], N, O.SEG_EQUAL_SNR,
-                                     1 if ds is white else 16)
-                    e = np.abs(batched[k][:6] - ref["ups"]) / np.maximum(np.abs(ref["ups"]), 2.0 * N)
-                    print("batched vs oracle, item", k, e.max())
-                    assert e.max() < 1e-9
+                    G = 1 if ds is white else 16
+                    ref = O.evaluate(ds.grid, ds.model, ds.d_ri, ds.psd, th[:6], N, O.SEG_EQUAL_SNR, G,
+                                     want_bounds=True)
+                    B.scs_define_segmentation(h, N, B.SCS_SEG_EQUAL_SNR, G)
+                    u = torch.empty(6, dtype=torch.float64, device="cuda")
+                    B.scs_evaluate(h, torch.tensor(np.ascontiguousarray(th[:6]), device="cuda"), u, prec)
+                    _, bnd = B.scs_last_bounds(h, 6, N)
+                    PT.check_rows(ds, th[:6], batched[k][:6], ref, bnd, G, PT.TOL64,
+                                  what=f"batched vs oracle, item {k}")
             graph = B.scs_graph_create(items, prec)
             for rep in range(3):
                 for it in items:
@@ -163,11 +170,18 @@ def test_batched_hierarchy_full_size_sampled():
         for lvl, ((N, P), th) in enumerate(zip(synth.LADDER_SWARMS, thetas)):
             assert np.all(np.isfinite(got[B.SCS_PREC_FP64][lvl]))
             idx = rng.choice(P, 2, replace=False)
-            ref = O.evaluate(g, m, ds.d_ri, psd, th[idx], N, O.SEG_EQUAL_SNR, w.G)["ups"]
-            e64 = np.abs(got[B.SCS_PREC_FP64][lvl][idx] - ref) / np.maximum(np.abs(ref), 2.0 * N)
-            emx = np.abs(got[B.SCS_PREC_MIXED][lvl][idx] - ref) / np.maximum(np.abs(ref), 2.0 * N)
-            worst64, worstmx = max(worst64, e64.max()), max(worstmx, emx.max())
-            assert e64.max() < 1e-9 and emx.max() < 1e-5, (N, P, e64, emx)
+            ref = O.evaluate(g, m, ds.d_ri, psd, th[idx], N, O.SEG_EQUAL_SNR, w.G, want_bounds=True)
+            # the sampled particles' edges, from a solo evaluation (edges are
+            # per particle; batched values equal solo ones bit for bit)
+            B.scs_define_segmentation(h, N, B.SCS_SEG_EQUAL_SNR, w.G)
+            B.scs_evaluate(h, torch.tensor(np.ascontiguousarray(th[idx]), device="cuda"),
+                           torch.empty(2, dtype=torch.float64, device="cuda"))
+            _, bnd = B.scs_last_bounds(h, 2, N)
+            e64 = PT.check_rows(ds, th[idx], got[B.SCS_PREC_FP64][lvl][idx], ref, bnd, w.G, PT.TOL64,
+                                what=f"hierarchy N={N} P={P} fp64")
+            emx = PT.check_rows(ds, th[idx], got[B.SCS_PREC_MIXED][lvl][idx], ref, bnd, w.G, PT.TOLMIX,
+                                what=f"hierarchy N={N} P={P} mixed")
+            worst64, worstmx = max(worst64, e64), max(worstmx, emx)
         print(f"batched hierarchy, 2^20 bins: fp64 sampled max floored rel err {worst64:.3g}, mixed {worstmx:.3g}")
     finally:
         B.scs_ctx_destroy(h)

@@ -13,6 +13,7 @@ import pytest
 import oracle as O
 import synth
 from tests import datasets as D
+from tests import parity as PT
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -90,16 +91,10 @@ def test_upsilon_matches_oracle(N, G):
         ok = np.isfinite(ref["ups"])
         sup, bnd = B.scs_last_bounds(h, th.shape[0], N)
         assert np.array_equal(sup[ok], ref["support"][ok])
-        same = ok & np.all(bnd == ref["bounds"], axis=1)
-        assert same.sum() >= 0.95 * ok.sum()
-        e = np.abs(got[same] - ref["ups"][same]) / np.maximum(np.abs(ref["ups"][same]), 2.0 * N)
-        print(f"N={N}: {same.sum()} rows, fp64 max floored rel err {e.max():.3g}")
-        assert e.max() < 1e-9
+        PT.check_rows(ds, th, got, ref, bnd, G, PT.TOL64, what=f"eccentric N={N} fp64")
         B.scs_evaluate(h, tht, u, B.SCS_PREC_MIXED)
         torch.cuda.synchronize()
-        em = np.abs(u.cpu().numpy()[same] - ref["ups"][same]) / np.maximum(np.abs(ref["ups"][same]), 2.0 * N)
-        print(f"N={N}: mixed max floored rel err {em.max():.3g}")
-        assert em.max() < 1e-5
+        PT.check_rows(ds, th, u.cpu().numpy(), ref, bnd, G, PT.TOLMIX, what=f"eccentric N={N} mixed")
         # e0 = 0 inside the eccentric model equals the circular model, bit for bit
         hc = B.scs_ctx_create(0)
         try:
@@ -227,12 +222,8 @@ def test_eccentric_lisa1m_full_size_sampled():
         idx = np.concatenate([[0, 1], np.random.default_rng(5).choice(np.arange(2, len(theta)), 4, replace=False)])
         ref = O.evaluate(g, m, ds.d_ri, psd, theta[idx], N, O.SEG_EQUAL_SNR, w.G, want_bounds=True)
         assert np.array_equal(sup[idx], ref["support"])
-        same = np.all(bnd[idx] == ref["bounds"], axis=1)
-        assert same.sum() >= len(same) - 1
-        e = np.abs(got[idx][same] - ref["ups"][same]) / np.maximum(np.abs(ref["ups"][same]), 2.0 * N)
-        em = np.abs(gm[idx][same] - ref["ups"][same]) / np.maximum(np.abs(ref["ups"][same]), 2.0 * N)
-        print(f"eccentric, 2^20 bins: fp64 sampled max floored rel err {e.max():.3g}, mixed {em.max():.3g}; "
-              f"Upsilon near the injection {got[:2]} (oracle {ref['ups'][:2]})")
-        assert e.max() < 1e-9 and em.max() < 1e-5
+        PT.check_rows(ds, theta[idx], got[idx], ref, bnd[idx], w.G, PT.TOL64, what="eccentric, 2^20 bins, fp64")
+        PT.check_rows(ds, theta[idx], gm[idx], ref, bnd[idx], w.G, PT.TOLMIX, what="eccentric, 2^20 bins, mixed")
+        print(f"Upsilon near the injection {got[:2]} (oracle {ref['ups'][:2]})")
     finally:
         B.scs_ctx_destroy(h)

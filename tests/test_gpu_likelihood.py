@@ -15,6 +15,7 @@ import pytest
 import oracle as O
 import synth
 from tests import datasets as D
+from tests import parity as PT
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -36,7 +37,7 @@ def _check(st, ref, dd, N, tol_ups, tol_lin, tol_hh):
     ok = np.isfinite(ref["ups"])
     assert np.all(np.isnan(st[~ok]))
     s, r = st[ok], {k: v[ok] for k, v in ref.items()}
-    e_ups = np.abs(s[:, 0] - r["ups"]) / np.maximum(np.abs(r["ups"]), 2.0 * N)
+    e_ups = PT.floored(s[:, 0], r["ups"], PT.n_eff(r["bounds"]))
     scale = np.sqrt(dd * np.maximum(r["hh"], 1e-300))
     e_ov = np.abs(s[:, 1] - r["overlap"]) / scale
     e_dh = np.abs((s[:, 3] + 1j * s[:, 4]) - r["dh"]) / scale

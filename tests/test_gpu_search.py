@@ -10,6 +10,7 @@ import pytest
 import oracle as O
 import synth
 from tests import datasets as D
+from tests import parity as PT
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -174,9 +175,10 @@ def test_search_full_size_sampled():
                 # best positions lie in the prior box, also for swarms re-grouped from
                 # particles that stood outside it
                 assert np.all((best[:, :7] >= w.prior_lo) & (best[:, :7] <= w.prior_hi))
-                ref = O.evaluate(g, m, ds.d_ri, psd, np.ascontiguousarray(best[:, :7]), N, O.SEG_EQUAL_SNR,
-                                 w.G)["ups"]
-                e = np.abs(best[:, 7] - ref) / np.maximum(np.abs(ref), 2.0 * N)
+                r = O.evaluate(g, m, ds.d_ri, psd, np.ascontiguousarray(best[:, :7]), N, O.SEG_EQUAL_SNR,
+                               w.G, want_bounds=True)
+                ref = r["ups"]
+                e = PT.floored(best[:, 7], ref, PT.n_eff(r["bounds"]))
                 worst = max(worst, e.max())
                 print(f"rung N={N}: {len(sizes)} swarms {list(sizes)}, bests {np.round(best[:, 7], 2)}")
                 assert e.max() < 1e-9, (N, e)

@@ -17,6 +17,7 @@ import pytest
 import oracle as O
 import synth
 from tests import datasets as D
+from tests import parity as PT
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -58,10 +59,13 @@ def test_realisations_and_streamed_statistics_match_oracle():
             for p in range(th.shape[0]):
                 B.scs_evaluate_streams(h, th[p], streams, stats)
                 s = stats.cpu().numpy()
+                # the edges depend on theta only: N_eff from the oracle's
+                neff = PT.n_eff(O.evaluate(g, ds.model, datas[0], ds.psd, th[p:p + 1], N, O.SEG_EQUAL_SNR, 1,
+                                           want_bounds=True)["bounds"])
                 for r in range(R):
                     ref = O.likelihood_stats(g, ds.model, datas[r], ds.psd, th[p:p + 1], N, O.SEG_EQUAL_SNR, 1)
                     dd = O.data_norm(g, datas[r], ds.psd)
-                    e_ups = abs(s[r, 0] - ref["ups"][0]) / max(abs(ref["ups"][0]), 2.0 * N)
+                    e_ups = float(PT.floored(s[r:r + 1, 0], ref["ups"], neff)[0])
                     cs = math.sqrt(dd * ref["hh"][0])
                     e_ov = abs(s[r, 1] - ref["overlap"][0]) / cs
                     e_dh = abs(complex(s[r, 3], s[r, 4]) - ref["dh"][0]) / cs
@@ -140,9 +144,11 @@ def test_streams_lisa1m_full_size_sampled():
             B.scs_evaluate_streams(h, w.injection, streams, stats)
             s = stats.cpu().numpy()
             assert np.all(np.isfinite(s[:, 0]))
+            neff = PT.n_eff(O.evaluate(g, m, datas[sample[0]], psd, w.injection[None, :], N, O.SEG_EQUAL_SNR, w.G,
+                                       want_bounds=True)["bounds"])
             for r in sample:
                 ref = O.likelihood_stats(g, m, datas[r], psd, w.injection[None, :], N, O.SEG_EQUAL_SNR, w.G)
-                e = abs(s[r, 0] - ref["ups"][0]) / max(abs(ref["ups"][0]), 2.0 * N)
+                e = float(PT.floored(s[r:r + 1, 0], ref["ups"], neff)[0])
                 worst = max(worst, e)
                 assert e < 1e-9 and abs(s[r, 2] / ref["hh"][0] - 1) < 5e-11, (N, r, e)
         print(f"streams, 2^20 bins: sampled realisations, max floored rel err {worst:.3g}")

@@ -12,6 +12,7 @@ import pytest
 
 import oracle as O
 from tests import datasets as D
+from tests import parity as PT
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -51,9 +52,10 @@ def test_autotune_cache_and_results(tmp_path):
         assert len(lines) == 6, lines  # two "key waves blocks" records
         for w, cb in zip(lines[1::3], lines[2::3]):
             assert int(w) in (1, 2, 4) and int(cb) >= 1
+        _, bnd = B.scs_last_bounds(h1, P, N)
         for p, tol in ((B.SCS_PREC_FP64, 1e-12), (B.SCS_PREC_MIXED, 1e-5)):
             tuned = _eval(h1, th, p)
-            e = np.abs(tuned - base[p]) / np.maximum(np.abs(base[p]), 2.0 * N)
+            e = PT.floored(tuned, base[p], PT.n_eff(bnd))
             print("tuned vs default shape", p, e.max())
             assert e.max() < tol
         # a second context reads the cache: a hit needs no particles at all
@@ -64,10 +66,8 @@ def test_autotune_cache_and_results(tmp_path):
         assert lib.scs_autotune(h2, 8 * P, None, N, B.SCS_PREC_FP64, str(cache).encode()) == B.SCS_EINVAL
         u2 = _eval(h2, th, B.SCS_PREC_FP64)
         assert np.array_equal(u2, _eval(h1, th, B.SCS_PREC_FP64))
-        ref = O.evaluate(ds.grid, ds.model, ds.d_ri, ds.psd, theta[:6], N, O.SEG_EQUAL_SNR, 16)
-        e = np.abs(u2[:6] - ref["ups"]) / np.maximum(np.abs(ref["ups"]), 2.0 * N)
-        print("tuned vs oracle", e.max())
-        assert e.max() < 1e-9
+        ref = O.evaluate(ds.grid, ds.model, ds.d_ri, ds.psd, theta[:6], N, O.SEG_EQUAL_SNR, 16, want_bounds=True)
+        PT.check_rows(ds, theta[:6], u2[:6], ref, bnd[:6], 16, PT.TOL64, what="tuned vs oracle")
     finally:
         B.scs_ctx_destroy(h1)
         B.scs_ctx_destroy(h2)

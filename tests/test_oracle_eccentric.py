@@ -7,7 +7,12 @@ evolution of orbital frequency F and eccentricity e (Peters 1964):
     de/dt = -(1/15) Mc^(5/3) (2 pi F)^(8/3) e (304 + 121 e^2) / (1 - e^2)^(5/2)
 (Mc in seconds), integrated numerically; the GW frequency of the dominant
 harmonic is f = 2F.  The stationary-phase time t(f) of the oracle must follow
-the integrated t(F) up to O(e0^4).
+the integrated t(F) up to O(e0^4), and so must its phase: in the stationary-
+phase approximation Psi(f)/2pi = f t(f) - Phi(f) + const, where Phi(f) is the
+number of GW cycles emitted up to the time the frequency is f, which the same
+evolution gives as the integral of f dt.  The phase and the time are written
+as separate terms in the oracle, so the two are pinned one by one, and their
+consistency (t = Psi'/2pi) is checked on the eccentric model as well.
 """
 import math
 
@@ -30,22 +35,39 @@ def _theta(mc, flow, e0):
     return np.array([mc, 0.24, flow, 0.0, 0.0, 0.0, 0.0, e0])
 
 
-def _peters_mathews_time(mc, f0, e0, freqs):
-    """t(f) - t(f0) from the Peters-Mathews equations, integrated in F."""
+def _peters_mathews(mc, f0, e0, freqs):
+    """t(f) - t(f0) and the GW cycles Phi(f) - Phi(f0) from the
+    Peters-Mathews equations, integrated in the orbital frequency F
+    (dt/dF = 1/Fdot, dPhi/dF = 2F/Fdot: the dominant harmonic has twice the
+    orbital frequency)."""
     mcs = mc * TSUN
 
     def rhs(F, y):
-        t, e = y
+        t, e, _ = y
         w = 2 * math.pi * F
         fdot = 48 / (5 * math.pi) * mcs ** (5 / 3) * w ** (11 / 3) * (1 + 73 / 24 * e * e + 37 / 96 * e ** 4) / (
             1 - e * e) ** 3.5
         edot = -mcs ** (5 / 3) * w ** (8 / 3) * e * (304 + 121 * e * e) / (15 * (1 - e * e) ** 2.5)
-        return [1.0 / fdot, edot / fdot]
+        return [1.0 / fdot, edot / fdot, 2.0 * F / fdot]
 
-    sol = scipy_integrate.solve_ivp(rhs, (f0 / 2, freqs[-1] / 2), [0.0, e0], t_eval=np.asarray(freqs) / 2,
-                                    rtol=1e-12, atol=1e-12 * 1e8, method="DOP853")
+    sol = scipy_integrate.solve_ivp(rhs, (f0 / 2, freqs[-1] / 2), [0.0, e0, 0.0], t_eval=np.asarray(freqs) / 2,
+                                    rtol=1e-13, atol=1e-14, method="DOP853")
     assert sol.success
-    return sol.y[0]
+    return sol.y[0], sol.y[2]
+
+
+def _peters_mathews_time(mc, f0, e0, freqs):
+    return _peters_mathews(mc, f0, e0, freqs)[0]
+
+
+def _oracle_cycles(m, mc, f0, e0, freqs):
+    """GW cycles from f0 to f by the stationary-phase relation, from the
+    oracle's phase Psi and time t: f t(f) - Psi(f)/2pi + Psi(f0)/2pi
+    (t(f0) = 0 defines the coalescence time)."""
+    fr, it, t, _ = O.phase(m, _theta(mc, f0, e0), np.concatenate([[f0], freqs]))
+    psi = it + fr
+    assert abs(t[0]) < 1e-6
+    return freqs * t[1:] - psi[1:] + psi[0]
 
 
 def test_time_follows_peters_mathews():
@@ -72,6 +94,57 @@ def test_time_follows_peters_mathews():
     scaled = np.array(scaled)
     assert np.all(np.abs(scaled) < 5.0)
     assert np.allclose(scaled[0], scaled[1], rtol=1e-3) and np.allclose(scaled[1], scaled[2], rtol=2e-3)
+
+
+def test_phase_follows_peters_mathews():
+    """The eccentric shift of the GW cycle count, formed from the oracle's
+    phase by the stationary-phase relation, agrees with the cycles the
+    Peters-Mathews evolution integrates, to leading order in e0^2:
+    (oracle / ODE - 1) / e0^2 tends to a constant as e0 -> 0 (the O(e0^4)
+    remainder).  The time shift is pinned on its own above, so a wrong
+    coefficient or exponent in the eccentric phase term alone (which moves
+    the cycle count by that term's change, hundreds of cycles here) fails
+    this check; a relative error of 1e-3 in the term would read about -40 at
+    e0 = 0.005."""
+    mc, f0 = 28.0, 0.018
+    freqs = f0 * np.array([1.05, 1.2, 1.5, 2.0, 3.0])
+    m = _model(1)
+    c_circ = _oracle_cycles(m, mc, f0, 0.0, freqs)
+    _, ode_circ = _peters_mathews(mc, f0, 0.0, freqs)
+    # circular Newtonian cycle count: the same to integration accuracy
+    assert np.allclose(c_circ, ode_circ, rtol=1e-10, atol=0)
+    scaled = []
+    for e0 in (0.005, 0.01, 0.02, 0.05):
+        d_or = _oracle_cycles(m, mc, f0, e0, freqs) - c_circ
+        d_ode = _peters_mathews(mc, f0, e0, freqs)[1] - ode_circ
+        assert np.all(np.sign(d_or) == np.sign(d_ode)) and np.all(np.abs(d_ode) > 10.0)
+        rel = d_or / d_ode - 1
+        print(f"e0={e0}: eccentric cycle shift {d_ode}, (oracle / ODE - 1) / e0^2 = {rel / e0 ** 2}")
+        scaled.append(rel / e0 ** 2)
+    scaled = np.array(scaled)
+    assert np.all(np.abs(scaled) < 5.0)
+    assert np.allclose(scaled[0], scaled[1], rtol=1e-3) and np.allclose(scaled[1], scaled[2], rtol=2e-3)
+
+
+@pytest.mark.parametrize("e0", [0.05, 0.1])
+def test_eccentric_time_is_phase_derivative(e0):
+    """t(f) = (1/2pi) dPsi/df on the eccentric model at 3.5PN: the phase
+    difference over a band equals the Gauss-Legendre integral of the oracle's
+    time, so the separately written eccentric terms of phase and time agree
+    (a factor off in either would leave a residual of order that term's
+    share, seconds against the 1e-8-cycle check)."""
+    import synth
+
+    th = np.concatenate([synth.GW150914_LIKE, [e0]])
+    m = O.Model(pn_order=7, eccentric=1)
+    x, w = np.polynomial.legendre.leggauss(24)
+    for f1, f2 in ((0.0181, 0.0186), (0.02, 0.0205), (0.024, 0.0245)):
+        fr, it, _, _ = O.phase(m, th, [f1, f2])
+        dphi = (it[1] - it[0]) + (fr[1] - fr[0])
+        fq = 0.5 * (f2 - f1) * x + 0.5 * (f1 + f2)
+        t = O.phase(m, th, fq)[2]
+        integral = 0.5 * (f2 - f1) * np.sum(w * t)
+        assert abs(dphi - integral) < 1e-8, (f1, dphi - integral)
 
 
 def test_zero_eccentricity_is_the_circular_model():
