@@ -47,7 +47,7 @@ class _Grid(C.Structure):
 class _Model(C.Structure):
     _fields_ = [("pn_order", C.c_int32), ("response", C.c_int32), ("support", C.c_int32),
                 ("eccentric", C.c_int32), ("t_obs", C.c_double), ("orbit_phase0", C.c_double),
-                ("cartwheel_phase0", C.c_double)]
+                ("cartwheel_phase0", C.c_double), ("sparse_stride", C.c_int32), ("pad", C.c_int32)]
 
 
 @dataclass
@@ -74,6 +74,10 @@ class Model:
     orbit_phase0: float = 0.0
     cartwheel_phase0: float = 0.0
     eccentric: int = 0  # 1: theta rows carry an 8th entry, e0 at GW frequency f_low
+    # 0: template evaluated at every bin; S > 0: the sparse-grid evaluation of
+    # Sec 4 (phase and response at every S-th bin of the support and its ends,
+    # not-a-knot cubic splines onto every bin)
+    sparse_stride: int = 0
 
     @property
     def theta_dim(self):
@@ -81,7 +85,7 @@ class Model:
 
     def c(self):
         return _Model(self.pn_order, self.response, self.support, int(self.eccentric), self.t_obs,
-                      self.orbit_phase0, self.cartwheel_phase0)
+                      self.orbit_phase0, self.cartwheel_phase0, int(self.sparse_stride), 0)
 
 
 def lib():

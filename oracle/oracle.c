@@ -80,6 +80,10 @@ typedef struct {
     double t_obs;            /* observation time [s] */
     double orbit_phase0;     /* orbital angle of the constellation centre at t = 0 [rad] */
     double cartwheel_phase0; /* in-plane angle of spacecraft 0 at t = 0 [rad] */
+    int32_t sparse_stride;   /* 0: template evaluated at every bin; > 0: the sparse-grid
+                                evaluation of Sec 4, nodes every sparse_stride bins, cubic
+                                spline onto the FFT grid (see sparse_spline below) */
+    int32_t pad;
 } orc_model;
 
 /* theta layout: Mc [Msun, detector frame], eta, f_low [Hz], lambda, beta, iota, psi
@@ -428,6 +432,196 @@ static int template_bin(const src_t* s, const orc_model* m, const orc_grid* g, i
     return 2;
 }
 
+/* ---- sparse-grid evaluation (Sec 4, waveform and response paragraphs) ----
+ * The paper evaluates the waveform and the response on a frequency grid far
+ * coarser than the FFT grid (by a factor 1000) and interpolates them onto the
+ * FFT grid with cubic splines.  Readings taken where the paper is silent:
+ *   - the coarse grid is every S-th FFT bin (S = sparse_stride), a fixed grid
+ *     in frequency, restricted to the particle's support; the support's first
+ *     and last bins are nodes too, so every support bin lies between nodes;
+ *   - the interpolated quantities are the template's phase in cycles (the GW
+ *     phase plus the Doppler phase of the response) and the real and
+ *     imaginary parts of each channel's response (transfer function); the
+ *     amplitude f^-7/6 is exact (it is folded into the data products);
+ *   - the spline is the not-a-knot cubic spline (third derivative continuous
+ *     at the second and the second-to-last node); with three nodes it is the
+ *     parabola through them, with two the line;
+ *   - the equal-[h|h] segment edges keep the template's exact weights at
+ *     their own nodes (Sec 2.2's rule does not depend on how the template is
+ *     evaluated on the dense grid).
+ * Node values are computed in extended precision like the exact template. */
+typedef struct {
+    int64_t n;  /* intervals: nodes x[0..n] */
+    int nq;     /* quantities: the phase, then re / im of each response channel */
+    int64_t* x; /* [n + 1] node bins */
+    ld* y;      /* [n + 1][nq] node values (phase unreduced, in cycles) */
+    ld* M;      /* [n + 1][nq] second derivatives of the spline at the nodes */
+} sparse_spline;
+
+/* Values at bin k of the spline's quantities: the template phase (cycles,
+ * GW + Doppler) and the response's real / imaginary parts per channel. */
+static int exact_quantities(const src_t* s, const orc_model* m, const orc_grid* g, int64_t k, ld* q)
+{
+    const ld f = freq(g, k);
+    q[0] = phase_cycles(s, f);
+    if (m->response == 0) return 1;
+    const double t = (double)spa_time(s, f);
+    q[0] += (ld)doppler_cycles(s, m, (double)f, t);
+    if (m->response == 2) {
+        double complex R[3];
+        fd_transfer(s, m, (double)f, t, g->n_chan, R);
+        for (int a = 0; a < g->n_chan; ++a) {
+            q[1 + 2 * a] = creal(R[a]);
+            q[2 + 2 * a] = cimag(R[a]);
+        }
+        return 1 + 2 * g->n_chan;
+    }
+    double F[2][2];
+    antenna(s, m, t, F);
+    for (int a = 0; a < 2; ++a) {
+        q[1 + 2 * a] = F[a][0] * s->a_plus;   /* R = F+ A+ - i Fx Ax */
+        q[2 + 2 * a] = -F[a][1] * s->a_cross;
+    }
+    return 5;
+}
+
+/* Node bins over [klo, khi): klo, the multiples of S strictly inside, khi - 1. */
+static void sparse_build(const src_t* s, const orc_model* m, const orc_grid* g, int64_t klo, int64_t khi,
+                         sparse_spline* sp)
+{
+    const int64_t S = m->sparse_stride;
+    int64_t n = 0;
+    int64_t* x = (int64_t*)malloc(sizeof(int64_t) * ((khi - klo) / S + 3));
+    x[n++] = klo;
+    for (int64_t k = (klo / S + 1) * S; k < khi - 1; k += S) x[n++] = k;
+    if (khi - 1 > klo) x[n++] = khi - 1;
+    sp->n = n - 1;
+    sp->x = x;
+    ld q[7];
+    sp->nq = exact_quantities(s, m, g, klo, q);
+    const int nq = sp->nq;
+    sp->y = (ld*)malloc(sizeof(ld) * n * nq);
+    sp->M = (ld*)calloc((size_t)(n * nq), sizeof(ld));
+    for (int64_t j = 0; j < n; ++j) {
+        exact_quantities(s, m, g, x[j], q);
+        for (int c = 0; c < nq; ++c) sp->y[j * nq + c] = q[c];
+    }
+    const int64_t N = sp->n; /* intervals */
+    if (N < 2) return;       /* one node (constant) or two (the line): M = 0 */
+    ld* h = (ld*)malloc(sizeof(ld) * N);
+    for (int64_t j = 0; j < N; ++j) h[j] = (ld)(x[j + 1] - x[j]);
+    for (int c = 0; c < nq; ++c) {
+        ld* y = sp->y + c;
+        ld* M = sp->M + c;
+#define Y(j) y[(int64_t)(j) * nq]
+#define MM(j) M[(int64_t)(j) * nq]
+        if (N == 2) { /* the parabola through the three nodes */
+            const ld s0 = (Y(1) - Y(0)) / h[0], s1 = (Y(2) - Y(1)) / h[1];
+            const ld v = 2.0L * (s1 - s0) / (h[0] + h[1]);
+            MM(0) = MM(1) = MM(2) = v;
+            continue;
+        }
+        /* Continuity of the first derivative at interior nodes i = 1..N-1:
+         *   h[i-1] M[i-1] + 2 (h[i-1] + h[i]) M[i] + h[i] M[i+1] = 6 (s[i] - s[i-1]),
+         * s[i] = (y[i+1] - y[i]) / h[i]; not-a-knot at both ends:
+         *   (M[1] - M[0]) / h[0] = (M[2] - M[1]) / h[1],
+         *   (M[N-1] - M[N-2]) / h[N-2] = (M[N] - M[N-1]) / h[N-1].
+         * M[0] and M[N] are eliminated from the first and last interior rows,
+         * leaving a tridiagonal system in M[1..N-1] (Thomas algorithm). */
+        const int64_t R = N - 1;
+        ld* a = (ld*)malloc(sizeof(ld) * R);
+        ld* b = (ld*)malloc(sizeof(ld) * R);
+        ld* cc = (ld*)malloc(sizeof(ld) * R);
+        ld* r = (ld*)malloc(sizeof(ld) * R);
+        for (int64_t i = 1; i <= R; ++i) {
+            const ld sl = (Y(i) - Y(i - 1)) / h[i - 1], sr = (Y(i + 1) - Y(i)) / h[i];
+            a[i - 1] = h[i - 1];
+            b[i - 1] = 2.0L * (h[i - 1] + h[i]);
+            cc[i - 1] = h[i];
+            r[i - 1] = 6.0L * (sr - sl);
+        }
+        /* M[0] = ((h0 + h1) M[1] - h0 M[2]) / h1 into row 1 */
+        b[0] += h[0] * (h[0] + h[1]) / h[1];
+        cc[0] -= h[0] * h[0] / h[1];
+        /* M[N] = ((h[N-2] + h[N-1]) M[N-1] - h[N-1] M[N-2]) / h[N-2] into row N-1 */
+        b[R - 1] += h[N - 1] * (h[N - 2] + h[N - 1]) / h[N - 2];
+        a[R - 1] -= h[N - 1] * h[N - 1] / h[N - 2];
+        for (int64_t i = 1; i < R; ++i) {
+            const ld w = a[i] / b[i - 1];
+            b[i] -= w * cc[i - 1];
+            r[i] -= w * r[i - 1];
+        }
+        MM(R) = r[R - 1] / b[R - 1];
+        for (int64_t i = R - 1; i >= 1; --i) MM(i) = (r[i - 1] - cc[i - 1] * MM(i + 1)) / b[i - 1];
+        MM(0) = ((h[0] + h[1]) * MM(1) - h[0] * MM(2)) / h[1];
+        MM(N) = ((h[N - 2] + h[N - 1]) * MM(N - 1) - h[N - 1] * MM(N - 2)) / h[N - 2];
+        free(a);
+        free(b);
+        free(cc);
+        free(r);
+#undef Y
+#undef MM
+    }
+    free(h);
+}
+
+static void sparse_free(sparse_spline* sp)
+{
+    free(sp->x);
+    free(sp->y);
+    free(sp->M);
+}
+
+/* The spline's quantities at bin k (inside [x0, xn]): on interval j,
+ * S(u) = y_j + b u + (M_j / 2) u^2 + (M_{j+1} - M_j) / (6 h) u^3, u = k - x_j,
+ * b = (y_{j+1} - y_j) / h - h (2 M_j + M_{j+1}) / 6. */
+static void sparse_eval(const sparse_spline* sp, int64_t k, ld* q)
+{
+    const int nq = sp->nq;
+    if (sp->n == 0) {
+        for (int c = 0; c < nq; ++c) q[c] = sp->y[c];
+        return;
+    }
+    int64_t lo = 0, hi = sp->n - 1; /* interval: the last j <= n-1 with x_j <= k */
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) / 2;
+        if (sp->x[mid] <= k) lo = mid; else hi = mid - 1;
+    }
+    const int64_t j = lo;
+    const ld h = (ld)(sp->x[j + 1] - sp->x[j]), u = (ld)(k - sp->x[j]);
+    for (int c = 0; c < nq; ++c) {
+        const ld y0 = sp->y[j * nq + c], y1 = sp->y[(j + 1) * nq + c];
+        const ld M0 = sp->M[j * nq + c], M1 = sp->M[(j + 1) * nq + c];
+        const ld b = (y1 - y0) / h - h * (2.0L * M0 + M1) / 6.0L;
+        q[c] = y0 + u * (b + u * (0.5L * M0 + u * (M1 - M0) / (6.0L * h)));
+    }
+}
+
+/* Template at bin k from the spline (the sparse-grid counterpart of
+ * template_bin; same conventions). */
+static int sparse_template_bin(const sparse_spline* sp, const orc_model* m, const orc_grid* g, int64_t k,
+                               double hre[3], double him[3])
+{
+    ld q[7];
+    sparse_eval(sp, k, q);
+    const ld f = freq(g, k);
+    const double amp = (double)powl(f, -7.0L / 6.0L);
+    const double tot = (double)(q[0] - floorl(q[0])); /* reduce before leaving extended precision */
+    const double c = cos(2.0 * M_PI * tot), sn = sin(2.0 * M_PI * tot);
+    if (m->response == 0) {
+        hre[0] = amp * c;
+        him[0] = -amp * sn;
+        return 1;
+    }
+    const int nc = (sp->nq - 1) / 2;
+    for (int a = 0; a < nc; ++a) {
+        const double rr = (double)q[1 + 2 * a], ri = (double)q[2 + 2 * a];
+        hre[a] = amp * (rr * c + ri * sn);
+        him[a] = amp * (ri * c - rr * sn);
+    }
+    return nc;
+}
+
 /* Support [k_lo, k_hi): whole band, or the bins whose SPA time lies in the
  * observation window, 0 <= t(f_k) < T_obs.  t(f_low) = 0 and t rises with f,
  * so the lower edge is the first bin with f_k >= f_low (compared exactly in
@@ -562,7 +756,7 @@ int orc_evaluate(const orc_grid* g, const orc_model* m, const double* d_ri, cons
                  const int64_t* edges, double* ups, double* seg, int64_t* bnd, int64_t* sup,
                  int32_t n_threads)
 {
-    if (N < 1 || G < 1 || P < 0) return -1;
+    if (N < 1 || G < 1 || P < 0 || m->sparse_stride < 0) return -1;
     if (!channels_ok(m, g)) return -2;
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
@@ -587,12 +781,15 @@ int orc_evaluate(const orc_grid* g, const orc_model* m, const double* d_ri, cons
         support(&s, m, g, th[TH_FLOW], &klo, &khi);
         int64_t* b = (int64_t*)malloc(sizeof(int64_t) * (N + 1));
         boundaries(&s, m, g, psd, klo, khi, N, mode, G, edges, b);
+        sparse_spline sp = {0};
+        const int sparse = m->sparse_stride > 0 && khi > klo;
+        if (sparse) sparse_build(&s, m, g, klo, khi, &sp);
         ld total = 0.0L;
         for (int n = 0; n < N; ++n) {
             ld zr = 0.0L, zi = 0.0L, hh = 0.0L;
             for (int64_t k = b[n]; k < b[n + 1]; ++k) {
                 double hr[3], hi[3];
-                const int nc = template_bin(&s, m, g, k, hr, hi);
+                const int nc = sparse ? sparse_template_bin(&sp, m, g, k, hr, hi) : template_bin(&s, m, g, k, hr, hi);
                 for (int a = 0; a < nc; ++a) {
                     const double S = psd[(int64_t)a * g->K + k];
                     const double dr = d_ri[((int64_t)a * g->K + k) * 2];
@@ -612,6 +809,7 @@ int orc_evaluate(const orc_grid* g, const orc_model* m, const double* d_ri, cons
                 seg[(p * N + n) * 3 + 2] = (double)hh;
             }
         }
+        if (sparse) sparse_free(&sp);
         ups[p] = (double)total;
         if (bnd)
             for (int n = 0; n <= N; ++n) bnd[p * (int64_t)(N + 1) + n] = b[n];
@@ -662,19 +860,24 @@ int orc_template(const orc_grid* g, const orc_model* m, const double* theta, dou
 {
     src_t s;
     if (!channels_ok(m, g)) return -2;
+    if (m->sparse_stride < 0) return -1;
     make_source(theta, m, &s);
     memset(h_ri, 0, sizeof(double) * 2 * (size_t)g->n_chan * (size_t)g->K);
     if (!s.valid) return -1;
     int64_t klo, khi;
     support(&s, m, g, theta[TH_FLOW], &klo, &khi);
+    sparse_spline sp = {0};
+    const int sparse = m->sparse_stride > 0 && khi > klo;
+    if (sparse) sparse_build(&s, m, g, klo, khi, &sp);
     for (int64_t k = klo; k < khi; ++k) {
         double hr[3], hi[3];
-        const int nc = template_bin(&s, m, g, k, hr, hi);
+        const int nc = sparse ? sparse_template_bin(&sp, m, g, k, hr, hi) : template_bin(&s, m, g, k, hr, hi);
         for (int a = 0; a < nc; ++a) {
             h_ri[((int64_t)a * g->K + k) * 2] = hr[a];
             h_ri[((int64_t)a * g->K + k) * 2 + 1] = hi[a];
         }
     }
+    if (sparse) sparse_free(&sp);
     return 0;
 }
 

@@ -37,3 +37,129 @@ def test_cubic_spline_on_a_grid_coarser_by_1000():
     loss = 1.0 - abs(np.mean(np.exp(2j * math.pi * err)))
     print(f"overlap lost at the injection: {loss:.3g}")
     assert loss < 1e-9
+
+
+# ---------------------------------------------------------------- the sparse-grid mode of the oracle
+# (Sec 4: waveform and response on a coarse grid, cubic-spline interpolated
+# onto the FFT grid).  Pinned against scipy's not-a-knot cubic spline through
+# node values computed independently from the oracle's exact phase, time and
+# antenna patterns, and against the exact template at the nodes.
+
+def _sparse_model(base, stride):
+    return O.Model(pn_order=base.pn_order, response=base.response, support=base.support, t_obs=base.t_obs,
+                   sparse_stride=stride)
+
+
+def _nodes(klo, khi, S):
+    x = [klo] + list(range((klo // S + 1) * S, khi - 1, S))
+    if khi - 1 > klo:
+        x.append(khi - 1)
+    return np.array(x)
+
+
+def _scipy_spline_template(ds, theta, S):
+    """The sparse-grid template rebuilt with scipy: node quantities (phase in
+    cycles with the Doppler term, the A and E responses) from the oracle's
+    exact phase, SPA time and antenna patterns; scipy's not-a-knot cubic
+    spline of each onto every support bin; h = f^-7/6 R e^{-2 pi i phase}."""
+    g, m = ds.grid, ds.model
+    f = g.freqs
+    frac, whole, t, _ = O.phase(m, theta, f)
+    # the support as the oracle decides it (its f_low comparison is exact)
+    klo, khi = (int(v) for v in O.evaluate(g, m, ds.d_ri, ds.psd, theta[None, :], 1)["support"][0])
+    x = _nodes(klo, khi, S)
+    ph0 = frac[klo]  # the integer part of the phase is no phase
+    q = []
+    for kk in x:
+        F, dop, _ = O.response(m, theta, t[kk])
+        ph = (whole[kk] - whole[klo]) + (frac[kk] - frac[klo]) + dop * f[kk]
+        ap, ax = 0.5 * (1 + math.cos(theta[5]) ** 2), math.cos(theta[5])
+        q.append([ph, F[0, 0] * ap, -F[0, 1] * ax, F[1, 0] * ap, -F[1, 1] * ax])
+    q = np.array(q)
+    kk = np.arange(klo, khi)
+    vals = [interpolate.CubicSpline(x, q[:, c], bc_type="not-a-knot")(kk) if len(x) > 2 else
+            np.interp(kk, x, q[:, c]) for c in range(5)]
+    tot = vals[0] + ph0
+    amp = f[kk] ** (-7.0 / 6.0)
+    e = np.exp(-2j * math.pi * np.mod(tot, 1.0))
+    h = np.zeros((2, g.K), dtype=complex)
+    for a in range(2):
+        h[a, kk] = amp * (vals[1 + 2 * a] + 1j * vals[2 + 2 * a]) * e
+    return h, x
+
+
+@pytest.mark.parametrize("S", [128, 1024])
+def test_sparse_template_is_the_not_a_knot_spline(S):
+    from tests import datasets as D
+
+    ds = D.lisa_small(seed=91, noise=False)
+    ms = _sparse_model(ds.model, S)
+    for th in [ds.injection] + list(D.lisa_particles(3, seed=92)):
+        got = O.template(ds.grid, ms, th)
+        want, x = _scipy_spline_template(ds, th, S)
+        scale = np.abs(want).max()
+        err = np.abs(got - want).max() / scale
+        exact = O.template(ds.grid, ds.model, th)
+        at_nodes = np.abs(got[:, x] - exact[:, x]).max() / scale
+        between = np.abs(got - exact).max() / scale
+        print(f"S = {S}, {len(x)} nodes: spline vs scipy {err:.3g}, at nodes vs exact {at_nodes:.3g}, "
+              f"between nodes vs exact {between:.3g}")
+        # the same spline to scipy's float64 arithmetic (other end conditions,
+        # natural or clamped, differ by orders of magnitude more near the ends)
+        assert err < 1e-9
+        assert at_nodes < 1e-12    # a spline passes through its nodes
+        assert between > 1e3 * at_nodes or S == 128  # interpolation, not evaluation
+
+
+def test_sparse_statistic_against_brute_force():
+    """Upsilon_N with the sparse-grid template: the oracle's evaluate against
+    the statistic summed here from the scipy-built template over the
+    oracle's (exact-weight) edges; and at the injection, noise-free, the
+    overlap lost to interpolation is second order (Upsilon_N within 1e-6 of
+    rho^2)."""
+    from tests import datasets as D
+
+    ds = D.lisa_small(seed=93)
+    S, N = 512, 8
+    ms = _sparse_model(ds.model, S)
+    th = D.lisa_particles(3, seed=94)
+    th[0] = ds.injection
+    r = O.evaluate(ds.grid, ms, ds.d_ri, ds.psd, th, N, O.SEG_EQUAL_SNR, 16, want_bounds=True)
+    r_exact = O.evaluate(ds.grid, ds.model, ds.d_ri, ds.psd, th, N, O.SEG_EQUAL_SNR, 16, want_bounds=True)
+    assert np.array_equal(r["bounds"], r_exact["bounds"])  # edges keep the exact weights
+    for p in range(th.shape[0]):
+        h, _ = _scipy_spline_template(ds, th[p], S)
+        b = r["bounds"][p]
+        ups = 0.0
+        for n in range(N):
+            sl = slice(b[n], b[n + 1])
+            Z = np.sum(ds.d[:, sl] * np.conj(h[:, sl]) / ds.psd[:, sl])
+            H = np.sum(np.abs(h[:, sl]) ** 2 / ds.psd[:, sl])
+            if H > 0:
+                ups += 4 * ds.grid.df * abs(Z) ** 2 / H
+        assert abs(r["ups"][p] - ups) <= 1e-8 * max(ups, 2 * N), (p, r["ups"][p], ups)
+    clean = D.lisa_small(seed=93, noise=False)
+    u = O.evaluate(clean.grid, ms, clean.d_ri, clean.psd, clean.injection[None, :], N, O.SEG_EQUAL_SNR, 16)["ups"][0]
+    print(f"noise-free injection, sparse template: Upsilon_{N} = {u:.9f} (rho^2 = {clean.snr ** 2})")
+    assert 0 < clean.snr ** 2 - u < 1e-6 * clean.snr ** 2
+
+
+def test_sparse_small_supports():
+    """Supports of one, two and three nodes: the constant, the line and the
+    parabola (scipy's not-a-knot with three points) through them."""
+    from tests import datasets as D
+
+    ds = D.lisa_small(seed=95, noise=False)
+    th = ds.injection.copy()
+    cases = [(0.018999, 4096, 1e7, 2), (0.01895, 512, 1e7, 3), (0.0185, 1024, 1.0, 1)]
+    for fl, S, t_obs, n_nodes in cases:
+        th[2] = fl
+        dsm = D.Dataset(ds.grid, O.Model(pn_order=ds.model.pn_order, response=ds.model.response,
+                                         support=ds.model.support, t_obs=t_obs), ds.psd, ds.d, th, 0.0, None, None)
+        got = O.template(dsm.grid, _sparse_model(dsm.model, S), th)
+        want, x = _scipy_spline_template(dsm, th, S)
+        nz = np.abs(want) > 0
+        print(f"f_low {fl}, stride {S}: {len(x)} nodes, {nz[0].sum()} bins")
+        assert len(x) == n_nodes
+        assert np.array_equal(np.abs(got) > 0, nz)
+        assert np.abs(got - want).max() <= 1e-9 * np.abs(want).max()
