@@ -258,7 +258,14 @@ typedef struct scs_batch_item {
 int scs_evaluate_batched(const scs_batch_item* items, int32_t n_items, int32_t prec, void* stream);
 
 /* Capture scs_evaluate_batched for fixed items into a HIP graph; replay it
- * with scs_graph_launch after updating theta in place. */
+ * with scs_graph_launch after updating theta in place (the items' theta, ups
+ * and seg buffers must stay valid while the graph lives).  The graph owns
+ * the workspaces its kernels use, so other calls on the same contexts, of
+ * any size, leave it intact.  It reads the contexts' data, model and
+ * segmentation as they were at the capture: the contexts must outlive the
+ * graph, and after scs_load_data, scs_set_model or scs_define_segmentation
+ * on one of them scs_graph_launch fails with SCS_ESTATE (build a new
+ * graph).  scs_graph_destroy waits for the graph's last replay. */
 typedef struct scs_graph scs_graph;
 int scs_graph_create(scs_graph** out, const scs_batch_item* items, int32_t n_items, int32_t prec);
 int scs_graph_launch(scs_graph* g, void* stream);
@@ -400,6 +407,13 @@ int scs_pso_best(int64_t P, int32_t dim, const double* theta, const double* vals
 
 /* Entries per theta row of the context's model: 7, or 8 when eccentric. */
 int scs_theta_dim(const scs_ctx* ctx, int32_t* dim);
+
+/* Shapes of a context's arguments, for callers that check their buffers:
+ * theta row width (7, or 8 when eccentric), the segment count N of the
+ * current segmentation (seg rows are [N][3]), and the channels and bins of
+ * the loaded data (0 before any data).  Any output may be NULL.  Errors:
+ * EINVAL (NULL ctx). */
+int scs_ctx_info(const scs_ctx* ctx, int32_t* theta_dim, int32_t* N, int32_t* n_chan, int64_t* K);
 
 /* ---- hierarchical multi-swarm search (Sec 3.1 - 3.2, app:PSO_params) -- */
 

@@ -115,6 +115,8 @@ _SIGS = {
     "scs_pso_best": [C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
     "scs_theta_dim": [C.c_void_p, C.POINTER(C.c_int32)],
+    "scs_ctx_info": [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                     C.POINTER(C.c_int64)],
     "scs_server_create": [C.POINTER(C.c_void_p), C.c_int32, C.c_int32, C.c_uint64, C.c_int32],
     "scs_server_submit": [C.c_void_p, C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p,
                           C.POINTER(C.c_uint64)],
@@ -181,6 +183,53 @@ def ptr(x):
     raise TypeError(f"unsupported buffer type {type(x)}")
 
 
+# ---- argument checks: the kernels index these buffers by the shapes below,
+# so a wrong dtype, width or length is refused here, before any call into the
+# library (a raw pointer carries no size for the library to check).
+def _is_f64(x):
+    if _is_torch(x):
+        import torch
+
+        return x.dtype == torch.float64
+    return isinstance(x, np.ndarray) and x.dtype == np.float64
+
+
+def need_f64(x, name, shape):
+    """x must be a float64 buffer of exactly this shape (None entries: any)."""
+    if x is None:
+        raise ValueError(f"{name} is missing")
+    if not _is_f64(x):
+        raise ValueError(f"{name} must be float64, got {getattr(x, 'dtype', type(x))}")
+    got = tuple(x.shape)
+    if len(got) != len(shape) or any(w is not None and g != w for g, w in zip(got, shape)):
+        want = tuple("*" if w is None else w for w in shape)
+        raise ValueError(f"{name} must have shape {want}, got {got}")
+
+
+def _same_kind(*pairs):
+    kinds = {k for _, k in pairs if k is not None}
+    if len(kinds) > 1:
+        raise ValueError("all buffers of a call must live in the same memory (host or device)")
+    return kinds.pop() if kinds else None
+
+
+def scs_ctx_info(ctx):
+    """{'theta_dim', 'N', 'n_chan', 'K'} of a context."""
+    d, n, c, k = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int64()
+    _check(lib().scs_ctx_info(ctx, C.byref(d), C.byref(n), C.byref(c), C.byref(k)))
+    return {"theta_dim": d.value, "N": n.value, "n_chan": c.value, "K": k.value}
+
+
+def check_eval_args(theta, ups, seg, dim, N, name_out="ups", width=1):
+    """theta [P, dim]; out [P] (width 1) or [P, width]; seg [P, N, 3] or None."""
+    need_f64(theta, "theta", (None, dim))
+    P = theta.shape[0]
+    need_f64(ups, name_out, (P,) if width == 1 else (P, width))
+    if seg is not None:
+        need_f64(seg, "seg", (P, N, 3))
+    return P
+
+
 def _stream(stream):
     if stream is None:
         return None
@@ -208,7 +257,9 @@ def scs_ctx_destroy(ctx):
 
 def scs_load_data(ctx, d_ri, psd, f_min, df):
     """d_ri [n_chan, K, 2] and psd [n_chan, K] (float64, host or device)."""
+    need_f64(psd, "psd", (None, None))
     n_chan, K = psd.shape[0], psd.shape[1]
+    need_f64(d_ri, "d_ri", (n_chan, K, 2))
     pd, kd = ptr(d_ri)
     pp, kp = ptr(psd)
     if kd != kp:
@@ -231,8 +282,9 @@ def scs_define_segmentation(ctx, N, mode=SCS_SEG_EQUAL_SNR, G=1024, edges=None):
 
 
 def scs_evaluate(ctx, theta, ups, prec=SCS_PREC_FP64, seg=None, stream=None):
-    """theta [P,7] -> ups [P] (and seg [P,N,3]); all numpy or all CUDA tensors."""
-    P = theta.shape[0]
+    """theta [P,D] -> ups [P] (and seg [P,N,3]); all numpy or all CUDA tensors."""
+    info = scs_ctx_info(ctx)
+    P = check_eval_args(theta, ups, seg, info["theta_dim"], info["N"])
     pt, kt = ptr(theta)
     pu, ku = ptr(ups)
     ps, ks = ptr(seg)
@@ -249,7 +301,8 @@ SCS_NSTATS = 5
 def scs_evaluate_stats(ctx, theta, stats, prec=SCS_PREC_FP64, stream=None):
     """theta [P,7] -> stats [P,5] = (Upsilon_N, hat O_N, <h|h>, Re <d|h>, Im <d|h>)
     for the unit-amplitude template; both numpy or both CUDA tensors."""
-    P = theta.shape[0]
+    info = scs_ctx_info(ctx)
+    P = check_eval_args(theta, stats, None, info["theta_dim"], info["N"], "stats", SCS_NSTATS)
     pt, kt = ptr(theta)
     ps, ks = ptr(stats)
     if kt != ks:
@@ -268,7 +321,12 @@ def scs_data_norm(ctx):
 def scs_loglike(ctx, stats, amp, phase=None, logl_semi=None, logl_coh=None, stream=None):
     """Log-likelihoods of A h e^{i phi} from scs_evaluate_stats rows into the
     given output arrays (either may be None); all arrays in one memory."""
+    need_f64(stats, "stats", (None, SCS_NSTATS))
     P = stats.shape[0]
+    need_f64(amp, "amp", (P,))
+    for name, x in (("phase", phase), ("logl_semi", logl_semi), ("logl_coh", logl_coh)):
+        if x is not None:
+            need_f64(x, name, (P,))
     ptrs = [ptr(x) for x in (stats, amp, phase, logl_semi, logl_coh)]
     kinds = {k for (p, k), x in zip(ptrs, (stats, amp, phase, logl_semi, logl_coh)) if x is not None}
     if len(kinds) != 1:
@@ -283,6 +341,8 @@ def scs_make_realisations(ctx, streams, seed, r0=0, scale=1.0, stream=None):
     """Fill the CUDA tensor streams [n_chan, K, R, 2] with scale * d + noise realisations r0 .. r0 + R - 1."""
     if not _is_torch(streams) or not streams.is_cuda:
         raise TypeError("streams must be a CUDA tensor [n_chan, K, R, 2]")
+    info = scs_ctx_info(ctx)
+    need_f64(streams, "streams", (info["n_chan"], info["K"], None, 2))
     R = streams.shape[2]
     p, _ = ptr(streams)
     _check(lib().scs_make_realisations(ctx, R, seed, r0, scale, p, _stream(stream or current_stream())))
@@ -293,7 +353,11 @@ def scs_evaluate_streams(ctx, theta, streams, stats, stream=None):
     th = np.ascontiguousarray(theta, dtype=np.float64).ravel()
     if not (_is_torch(streams) and streams.is_cuda and _is_torch(stats) and stats.is_cuda):
         raise TypeError("streams and stats must be CUDA tensors")
+    info = scs_ctx_info(ctx)
+    need_f64(th, "theta", (info["theta_dim"],))
+    need_f64(streams, "streams", (info["n_chan"], info["K"], None, 2))
     R = streams.shape[2]
+    need_f64(stats, "stats", (R, SCS_NSTATS))
     ps, _ = ptr(streams)
     pt, _ = ptr(stats)
     _check(lib().scs_evaluate_streams(ctx, C.c_void_p(th.ctypes.data), R, ps, pt, _stream(stream or current_stream())))
@@ -307,6 +371,9 @@ def scs_last_bounds(ctx, P, N):
 
 
 def scs_waveform(ctx, theta, h_ri, stream=None):
+    info = scs_ctx_info(ctx)
+    need_f64(theta, "theta", (info["theta_dim"],))
+    need_f64(h_ri, "h_ri", (info["n_chan"], info["K"], 2))
     pt, kt = ptr(theta)
     ph, kh = ptr(h_ri)
     if kt != kh:
@@ -339,6 +406,10 @@ def _items(items):
     for i, it in enumerate(items):
         ctx, N, theta, ups = it[:4]
         seg = it[4] if len(it) > 4 else None
+        for x in (theta, ups, seg):
+            if x is not None and not (_is_torch(x) and x.is_cuda and x.is_contiguous()):
+                raise ValueError(f"item {i}: theta, ups and seg must be contiguous CUDA tensors")
+        check_eval_args(theta, ups, seg, scs_ctx_info(ctx)["theta_dim"], N)
         arr[i] = scs_batch_item(ctx.value if isinstance(ctx, C.c_void_p) else ctx, N, 0, theta.shape[0],
                                 theta.data_ptr(), ups.data_ptr(), seg.data_ptr() if seg is not None else None)
     return arr
@@ -370,6 +441,9 @@ def scs_graph_destroy(graph):
 
 
 def scs_autotune(ctx, theta_cuda, N, prec=SCS_PREC_FP64, cache_path=None):
+    need_f64(theta_cuda, "theta", (None, scs_ctx_info(ctx)["theta_dim"]))
+    if not (_is_torch(theta_cuda) and theta_cuda.is_cuda and theta_cuda.is_contiguous()):
+        raise ValueError("theta must be a contiguous CUDA tensor")
     _check(lib().scs_autotune(ctx, theta_cuda.shape[0], C.c_void_p(theta_cuda.data_ptr()), N, prec,
                               cache_path.encode() if cache_path else None))
 
@@ -378,7 +452,15 @@ def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
+def _check_box(ctx, lo, hi, periodic):
+    D = scs_ctx_info(ctx)["theta_dim"]
+    for name, x in (("lo", lo), ("hi", hi)) + ((("periodic", periodic),) if periodic is not None else ()):
+        if np.asarray(x).shape != (D,):
+            raise ValueError(f"{name} must have the context's {D} theta entries, got shape {np.asarray(x).shape}")
+
+
 def scs_swarm_create(ctx, P, lo, hi, periodic=None, seed=0, swarm_id=0):
+    _check_box(ctx, lo, hi, periodic)
     lo, hi = _f64(lo), _f64(hi)
     per = np.ascontiguousarray(periodic if periodic is not None else np.zeros(lo.size), dtype=np.int32)
     h = C.c_void_p()
@@ -405,6 +487,7 @@ def scs_theta_dim(ctx):
 
 def scs_search_create(ctx, n_swarms, particles, lo, hi, periodic=None, G=1, conv_tol=2.0, conv_window=50,
                       kmeans_iters=100, prec=SCS_PREC_FP64, seed=0):
+    _check_box(ctx, lo, hi, periodic)
     prm = scs_search_params(n_swarms, G, particles, conv_tol, conv_window, kmeans_iters, prec, 0, seed)
     lo, hi = _f64(lo), _f64(hi)
     per = np.ascontiguousarray(periodic if periodic is not None else np.zeros(lo.size), dtype=np.int32)
@@ -488,7 +571,21 @@ def scs_swarm_device_ptrs(sw):
     return a.value, b.value
 
 
+def _check_swarm_bufs(theta, **kw):
+    need_f64(theta, "theta", (None, None))
+    P, D = theta.shape
+    if D not in (7, 8):
+        raise ValueError("theta rows must have 7 or 8 entries")
+    for name, (x, shape) in kw.items():
+        need_f64(x, name, tuple(P if v == "P" else (D if v == "D" else v) for v in shape))
+    for x in (theta, *(v[0] for v in kw.values())):
+        if not (_is_torch(x) and x.is_cuda and x.is_contiguous()):
+            raise ValueError("swarm buffers must be contiguous CUDA tensors")
+    return P, D
+
+
 def scs_pso_move(theta, vel, pbest, gbest, params, lo, hi, periodic, seed, swarm_id, iteration, stream=None):
+    _check_swarm_bufs(theta, vel=(vel, ("P", "D")), pbest=(pbest, ("P", "D")), gbest=(gbest, ("D",)))
     lo, hi = _f64(lo), _f64(hi)
     per = np.ascontiguousarray(periodic, dtype=np.int32)
     if stream is None:
@@ -500,6 +597,8 @@ def scs_pso_move(theta, vel, pbest, gbest, params, lo, hi, periodic, seed, swarm
 
 
 def scs_pso_best(theta, vals, lo, hi, periodic, pbest, pbest_val, gbest, gbest_val, stream=None):
+    _check_swarm_bufs(theta, vals=(vals, ("P",)), pbest=(pbest, ("P", "D")), pbest_val=(pbest_val, ("P",)),
+                      gbest=(gbest, ("D",)), gbest_val=(gbest_val, (1,)))
     lo, hi = _f64(lo), _f64(hi)
     per = np.ascontiguousarray(periodic, dtype=np.int32)
     if stream is None:
@@ -527,8 +626,12 @@ def scs_server_submit(srv, ctx, N, theta, ups, prec=SCS_PREC_FP64):
     if not (isinstance(theta, np.ndarray) and isinstance(ups, np.ndarray)):
         raise TypeError("theta and ups must be numpy arrays (host memory)")
     theta = np.ascontiguousarray(theta, dtype=np.float64)
-    if ups.dtype != np.float64 or not ups.flags["C_CONTIGUOUS"] or ups.shape[0] != theta.shape[0]:
+    if theta.ndim != 2:
+        raise ValueError("theta must be [P, D]")
+    if ups.dtype != np.float64 or not ups.flags["C_CONTIGUOUS"] or ups.shape != (theta.shape[0],):
         raise ValueError("ups must be a contiguous float64 array of P entries")
+    if ctx is not None:
+        need_f64(theta, "theta", (None, scs_ctx_info(ctx)["theta_dim"]))
     rid = C.c_uint64()
     _check(lib().scs_server_submit(srv, ctx, N, theta.shape[0], C.c_void_p(theta.ctypes.data), prec,
                                    C.c_void_p(ups.ctypes.data), C.byref(rid)))

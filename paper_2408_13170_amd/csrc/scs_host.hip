@@ -49,6 +49,7 @@ static int fail(int code, const char* fmt, ...)
 static std::mutex g_dev_mu;
 static std::map<int, bool> g_dev_ready;
 
+
 // Chebyshev nodes x_n = cos(pi (2n+1) / (2 kNodes)) and the inverse of the
 // Vandermonde matrix V[n][m] = x_n^m (computed in extended precision).
 static void cheb_matrix(double* x, double* minv)
@@ -107,6 +108,7 @@ static int device_setup(int device)
     g_dev_ready[device] = true;
     return SCS_OK;
 }
+
 
 static PhysConst phys_const()
 {
@@ -191,6 +193,7 @@ struct scs_ctx {
     bool gtab_ok = false;
     unsigned long long* counters = nullptr;  // evals_support, evals_band, unresolved
     std::map<int, Workspace> ws;             // slot -> workspace
+    uint64_t gen = 0;  // bumped by every change of data, model or segmentation (graphs built earlier go stale)
     hipStream_t last_stream = nullptr;
     // profiling of the generate-and-reduce kernel
     bool prof = false;
@@ -416,6 +419,7 @@ extern "C" int scs_load_data(scs_ctx* c, int32_t n_chan, int64_t K, double f_min
     c->psd_dev = dp;
     if (e3 != hipSuccess) return fail(SCS_EDEVICE, "bin precompute failed: %s", hipGetErrorString(e3));
     c->has_data = true;
+    ++c->gen;
     c->gtab_ok = false;
     if (c->has_model && !model_fits(c->m.response, n_chan)) c->has_model = false;
     if (c->has_model) return build_gtab(c);
@@ -451,6 +455,7 @@ extern "C" int scs_set_model(scs_ctx* c, const scs_model* m)
     while ((1 << lg) < bl) ++lg;
     c->lg_max = lg;
     c->has_model = true;
+    ++c->gen;
     DevScope ds(c->device);
     return build_gtab(c);
 }
@@ -471,6 +476,7 @@ extern "C" int scs_define_segmentation(scs_ctx* c, int32_t N, int32_t mode, int3
         HIP_TRY(hipMemcpy(c->d_edges, edges, sizeof(int64_t) * (N + 1), hipMemcpyHostToDevice));
     }
     c->N = N;
+    ++c->gen;
     c->mode = mode;
     c->G = G;
     return SCS_OK;
@@ -600,7 +606,7 @@ struct EvalJob {
 };
 
 static int eval_front(EvalJob& j, const double* theta, double* ups, double* seg, const TuneChoice& t, hipStream_t s,
-                      double* stats = nullptr)
+                      double* stats = nullptr, bool fixed_ws = false)
 {
     scs_ctx* c = j.c;
     Workspace& w = *j.w;
@@ -608,7 +614,9 @@ static int eval_front(EvalJob& j, const double* theta, double* ups, double* seg,
     const int N = j.N;
     if (c->mode == SCS_SEG_EXPLICIT && N != c->N) return fail(SCS_EINVAL, "EXPLICIT edges were defined for N = %d", c->N);
     j.pl = make_plan(c, P, t);
-    int rc = ensure_ws(c, w, P, N, j.pl);
+    // a fixed workspace was laid out by the caller for exactly this P, N and
+    // plan (the evaluation without allocations); anything else grows to fit
+    int rc = fixed_ws ? SCS_OK : ensure_ws(c, w, P, N, j.pl);
     if (rc) return rc;
     w.P_last = P;
     w.N_last = N;
@@ -1302,7 +1310,20 @@ struct scs_graph {
     hipGraphExec_t exec = nullptr;
     int device = 0;
     BatchSlot slot;  // descriptors read by the captured fused launches
+    // the graph's own workspaces (one per item): the captured kernels hold
+    // their addresses, so no later call on the contexts may move them
+    std::vector<Workspace> ws;
+    std::vector<std::pair<const scs_ctx*, uint64_t>> ctx_gen;  // contexts and their state when captured
 };
+
+static void graph_free(scs_graph* g)
+{
+    if (g->exec) hipGraphExecDestroy(g->exec);
+    if (g->graph) hipGraphDestroy(g->graph);
+    free_slot(g->slot);
+    for (auto& w : g->ws) free_ws(w);
+    delete g;
+}
 
 extern "C" int scs_graph_create(scs_graph** out, const scs_batch_item* items, int32_t n_items, int32_t prec)
 {
@@ -1317,23 +1338,27 @@ extern "C" int scs_graph_create(scs_graph** out, const scs_batch_item* items, in
     HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
     scs_graph* g = new scs_graph();
     g->device = dev;
+    g->ws.resize(n_items);
+    std::vector<Workspace*> wsp(n_items);
+    for (int i = 0; i < n_items; ++i) {
+        wsp[i] = &g->ws[i];
+        g->ctx_gen.emplace_back(items[i].ctx, items[i].ctx->gen);
+    }
     // one eager pass: allocates every workspace and uploads the descriptors
-    if ((rc = slot_reserve(g->slot, n_items)) == SCS_OK) rc = run_batched(items, n_items, prec, s, g->slot, true);
+    if ((rc = slot_reserve(g->slot, n_items)) == SCS_OK)
+        rc = run_batched(items, n_items, prec, s, g->slot, true, wsp.data());
     hipError_t e = hipStreamSynchronize(s);
     if (rc == SCS_OK && e == hipSuccess) {
         e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            rc = run_batched(items, n_items, prec, s, g->slot, false);
+            rc = run_batched(items, n_items, prec, s, g->slot, false, wsp.data());
             e = hipStreamEndCapture(s, &g->graph);
         }
         if (e == hipSuccess && rc == SCS_OK) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
     }
     hipStreamDestroy(s);
     if (e != hipSuccess || rc != SCS_OK) {
-        if (g->exec) hipGraphExecDestroy(g->exec);
-        if (g->graph) hipGraphDestroy(g->graph);
-        free_slot(g->slot);
-        delete g;
+        graph_free(g);
         return rc ? rc : fail(SCS_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
     }
     *out = g;
@@ -1343,6 +1368,10 @@ extern "C" int scs_graph_create(scs_graph** out, const scs_batch_item* items, in
 extern "C" int scs_graph_launch(scs_graph* g, void* stream)
 {
     if (!g) return fail(SCS_EINVAL, "graph is NULL");
+    for (const auto& cg : g->ctx_gen)
+        if (cg.first->gen != cg.second)
+            return fail(SCS_ESTATE, "a context of this graph changed its data, model or segmentation after the "
+                                    "capture; build a new graph");
     DevScope ds(g->device);
     HIP_TRY(hipGraphLaunch(g->exec, (hipStream_t)stream));
     HIP_TRY(hipEventRecord(g->slot.done, (hipStream_t)stream));
@@ -1353,10 +1382,8 @@ extern "C" int scs_graph_destroy(scs_graph* g)
 {
     if (!g) return SCS_OK;
     DevScope ds(g->device);
-    hipGraphExecDestroy(g->exec);
-    hipGraphDestroy(g->graph);
-    free_slot(g->slot);
-    delete g;
+    if (g->slot.done) hipEventSynchronize(g->slot.done);
+    graph_free(g);
     return SCS_OK;
 }
 
@@ -1416,15 +1443,59 @@ struct scs_server {
     std::thread worker;
 
     double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+    uint64_t resident() const;  // device bytes held by all request slots
     void run();
     int launch(std::vector<SrvRequest*>& batch, int si);
     void finish(SrvBatch& b, int status);
 };
 
+// Device bytes a request slot holds: its workspace (as ensure_ws sized it)
+// and its theta and result buffers.
+static uint64_t slot_bytes(const SrvSlot& s)
+{
+    const Workspace& w = s.ws;
+    uint64_t b = (uint64_t)w.capP * (sizeof(double) * kCoefStride + 2 * sizeof(int32_t) + 1);
+    b += (uint64_t)w.capBounds * sizeof(int32_t) + (uint64_t)(w.capRec + w.capZs) * sizeof(double);
+    if (w.capSort) b += (uint64_t)w.capSort * 3 * sizeof(int32_t) + sizeof(unsigned) * (uint64_t)kSortBuckets;
+    b += (uint64_t)s.cap * sizeof(double) * (kThetaMax + 1);
+    return b;
+}
+
+// The bytes slot s holds after serving P particles with N segments of
+// context c: slot_grow and ensure_ws grow each buffer to fit and shrink none.
+static uint64_t slot_bytes_after(const SrvSlot& s, const scs_ctx* c, int64_t P, int N, int prec)
+{
+    TuneChoice t = choose(c, P, N, prec);
+    t.waves = 4;  // the workgroup shape of batched launches (the chunk count does not depend on it)
+    const Plan pl = make_plan(c, P, t);
+    SrvSlot x;
+    x.cap = P <= s.cap ? s.cap : std::max<int64_t>(P, 256);
+    Workspace& w = x.ws;
+    w.capP = std::max(s.ws.capP, pad64(std::max<int64_t>(P, 1)));
+    w.capBounds = std::max(s.ws.capBounds, P * (int64_t)(N + 1) + 2);
+    w.capRec = std::max(s.ws.capRec, pl.n_chunks * kRec * w.capP);
+    w.capZs = std::max(s.ws.capZs, 3 * P * (int64_t)N);
+    w.capSort = (P >= kSortMin && P > s.ws.capSort) ? w.capP : s.ws.capSort;
+    return slot_bytes(x);
+}
+
+// Device bytes of a request in a slot of its own: what admission must find
+// free for it at least.
 static uint64_t request_bytes(const scs_ctx* c, int64_t P, int N, int prec)
 {
-    const TuneChoice t = choose(c, P, N, prec);
-    return (uint64_t)ws_bytes(c, P, N, make_plan(c, P, t)) + (uint64_t)sizeof(double) * 8 * (uint64_t)std::max<int64_t>(P, 1);
+    return slot_bytes_after(SrvSlot(), c, P, N, prec);
+}
+
+// Free a slot's device buffers (an idle slot, to make room under the budget).
+static void slot_release(SrvSlot& s)
+{
+    free_ws(s.ws);
+    hipFree(s.d_theta);
+    hipFree(s.d_ups);
+    hipHostFree(s.h_theta);
+    hipHostFree(s.h_ups);
+    s.d_theta = s.d_ups = s.h_theta = s.h_ups = nullptr;
+    s.cap = 0;
 }
 
 static int slot_grow(SrvSlot& s, int64_t P)
@@ -1444,6 +1515,13 @@ static int slot_grow(SrvSlot& s, int64_t P)
         return fail(SCS_ENOMEM, "request buffers of %lld particles", (long long)P);
     s.cap = cap;
     return SCS_OK;
+}
+
+uint64_t scs_server::resident() const
+{
+    uint64_t b = 0;
+    for (const SrvSlot& sl : slots) b += slot_bytes(sl);
+    return b;
 }
 
 // Queue one batched launch of the admitted requests on stream si.
@@ -1505,7 +1583,6 @@ void scs_server::finish(SrvBatch& b, int status)
         {
             std::lock_guard<std::mutex> lk(mu);
             slots[r->slot].busy = false;
-            st.hbm_in_use -= r->bytes;
             if (status == SCS_OK) ++st.completed; else ++st.failed;
             done.push_back(d);
         }
@@ -1543,22 +1620,44 @@ void scs_server::run()
                     break;
                 }
             if (si >= 0) {
+                // Memory is charged as the slots hold it: every slot keeps
+                // its buffers at the largest size it has served, so the
+                // charge is the device bytes of all slots after the chosen
+                // one has grown to fit the request.  The free slot that grows
+                // least is taken; if the budget would still be exceeded, the
+                // buffers of the idle slots are released (the chosen slot
+                // then starts from nothing), else the request waits.
+                uint64_t held = resident();
                 while (!pending.empty()) {
                     SrvRequest* r = pending.front();
-                    if (st.hbm_in_use + r->bytes > budget) break;
-                    int free_slot_i = -1;
-                    for (int i = 0; i < max_inflight; ++i)
-                        if (!slots[i].busy) {
-                            free_slot_i = i;
-                            break;
+                    int pick = -1;
+                    uint64_t pick_now = 0, pick_after = 0;
+                    for (int i = 0; i < max_inflight; ++i) {
+                        if (slots[i].busy) continue;
+                        const uint64_t nw = slot_bytes(slots[i]);
+                        const uint64_t af = slot_bytes_after(slots[i], r->ctx, r->P, r->N, r->prec);
+                        if (pick < 0 || af - nw < pick_after - pick_now) {
+                            pick = i;
+                            pick_now = nw;
+                            pick_after = af;
                         }
-                    if (free_slot_i < 0) break;
+                    }
+                    if (pick < 0) break;
+                    if (held - pick_now + pick_after > budget) {
+                        for (SrvSlot& sl : slots)
+                            if (!sl.busy && sl.cap + sl.ws.capP > 0) slot_release(sl);
+                        held = resident();
+                        pick_now = 0;
+                        pick_after = slot_bytes_after(slots[pick], r->ctx, r->P, r->N, r->prec);
+                        if (held + pick_after > budget) break;
+                    }
                     pending.pop_front();
-                    slots[free_slot_i].busy = true;
-                    r->slot = free_slot_i;
+                    slots[pick].busy = true;
+                    r->slot = pick;
                     r->t_admit = now();
-                    st.hbm_in_use += r->bytes;
-                    st.hbm_peak = std::max(st.hbm_peak, st.hbm_in_use);
+                    held = held - pick_now + pick_after;
+                    st.hbm_in_use = held;
+                    st.hbm_peak = std::max(st.hbm_peak, held);
                     batch.push_back(r);
                 }
                 int64_t busy = 0;
@@ -1712,13 +1811,7 @@ extern "C" int scs_server_destroy(scs_server* srv)
         hipStreamDestroy(st);
     }
     for (auto& b : srv->bslots) free_slot(b);
-    for (auto& sl : srv->slots) {
-        hipFree(sl.d_theta);
-        hipFree(sl.d_ups);
-        hipHostFree(sl.h_theta);
-        hipHostFree(sl.h_ups);
-        free_ws(sl.ws);
-    }
+    for (auto& sl : srv->slots) slot_release(sl);
     delete srv;
     return SCS_OK;
 }
@@ -2024,6 +2117,16 @@ extern "C" int scs_theta_dim(const scs_ctx* c, int32_t* dim)
     if (rc) return rc;
     if (!dim) return fail(SCS_EINVAL, "dim is NULL");
     *dim = theta_dim(c);
+    return SCS_OK;
+}
+
+extern "C" int scs_ctx_info(const scs_ctx* c, int32_t* dim, int32_t* N, int32_t* n_chan, int64_t* K)
+{
+    if (!c) return fail(SCS_EINVAL, "ctx is NULL");
+    if (dim) *dim = theta_dim(c);
+    if (N) *N = c->N;
+    if (n_chan) *n_chan = c->has_data ? c->g.nch : 0;
+    if (K) *K = c->has_data ? c->g.K : 0;
     return SCS_OK;
 }
 

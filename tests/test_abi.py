@@ -63,3 +63,59 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
         B.lib()
     with pytest.raises(ImportError):
         B.scs_ctx_create(0)
+
+
+class _NoLibrary:
+    """Stands in for libscs.so: any call into it fails the test, so a check
+    that raises ValueError is shown to act before the library is reached."""
+
+    def __getattr__(self, name):
+        raise AssertionError(f"the binding called {name} with arguments it should have refused")
+
+
+@pytest.fixture
+def fake_ctx(monkeypatch):
+    info = {"theta_dim": 7, "N": 4, "n_chan": 2, "K": 100}
+    monkeypatch.setattr(B, "scs_ctx_info", lambda ctx: dict(info))
+    monkeypatch.setattr(B, "_lib", _NoLibrary())
+    return C.c_void_p(1)
+
+
+def test_binding_refuses_wrong_buffers(fake_ctx):
+    """dtype, theta width and buffer lengths are checked against the context
+    before a raw pointer goes to the kernels (which would index past a short
+    or narrow buffer)."""
+    import numpy as np
+
+    ctx = fake_ctx
+    P = 5
+    good_th, good_u = np.zeros((P, 7)), np.zeros(P)
+    bad = [
+        lambda: B.scs_evaluate(ctx, good_th.astype(np.float32), good_u),       # float32 theta
+        lambda: B.scs_evaluate(ctx, np.zeros((P, 8)), good_u),                 # 8 entries on a 7-entry context
+        lambda: B.scs_evaluate(ctx, good_th, np.zeros(P - 1)),                 # short ups
+        lambda: B.scs_evaluate(ctx, good_th, good_u.astype(np.float32)),       # float32 ups
+        lambda: B.scs_evaluate(ctx, good_th, good_u, seg=np.zeros((P, 3, 3))),  # seg rows for another N
+        lambda: B.scs_evaluate_stats(ctx, good_th, np.zeros((P, 4))),          # stats rows too narrow
+        lambda: B.scs_loglike(ctx, np.zeros((P, 5)), np.ones(P - 1)),          # amp too short
+        lambda: B.scs_load_data(ctx, np.zeros((2, 99, 2)), np.ones((2, 100)), 0.016, 1e-6),  # data / psd shapes
+        lambda: B.scs_waveform(ctx, np.zeros(7), np.zeros((1, 100, 2))),       # h for another channel count
+        lambda: B.scs_waveform(ctx, np.zeros(6), np.zeros((2, 100, 2))),       # short theta
+        lambda: B.scs_swarm_create(ctx, 8, np.zeros(6), np.ones(6)),           # prior box of 6 entries
+        lambda: B.scs_server_submit(None, ctx, 4, np.zeros((P, 8)), good_u),   # theta width
+    ]
+    for i, f in enumerate(bad):
+        with pytest.raises(ValueError):
+            f()
+
+
+def test_binding_refuses_host_buffers_for_device_only_calls(fake_ctx):
+    torch = pytest.importorskip("torch")
+    ctx = fake_ctx
+    th = torch.zeros((3, 7), dtype=torch.float64)  # CPU tensors: host memory
+    u = torch.zeros(3, dtype=torch.float64)
+    with pytest.raises(ValueError):
+        B.scs_evaluate_batched([(ctx, 4, th, u)])
+    with pytest.raises(ValueError):
+        B.scs_pso_move(th, torch.zeros((3, 6), dtype=torch.float64), th, torch.zeros(7, dtype=torch.float64),
+                       None, None, None, None, 0, 0, 0)

@@ -82,6 +82,49 @@ def test_batched_and_graph_equal_solo():
         B.scs_ctx_destroy(hw)
 
 
+def test_graph_keeps_its_workspaces():
+    """A graph owns the workspaces its captured kernels use: batched calls
+    and PSO-sized evaluations of larger swarms and segment counts on the same
+    context (which grow the context's own workspaces) leave its replays
+    intact; a change of the context's segmentation makes the next replay fail
+    with ESTATE instead of replaying stale state."""
+    lisa = D.lisa_small(seed=25)
+    h = _ctx(lisa)
+    try:
+        th_small = [D.lisa_particles(100, seed=120), D.lisa_particles(64, seed=121)]
+        items = [(h, N, torch.tensor(th, device="cuda"), torch.full((th.shape[0],), -1.0, dtype=torch.float64,
+                                                                    device="cuda"))
+                 for N, th in zip((16, 4), th_small)]
+        graph = B.scs_graph_create(items, B.SCS_PREC_FP64)
+        B.scs_graph_launch(graph)
+        torch.cuda.synchronize()
+        first = [it[3].cpu().numpy().copy() for it in items]
+        # bigger work on the same context: its workspaces grow (reallocate)
+        big = [(h, 256, torch.tensor(D.lisa_particles(3000, seed=122), device="cuda"),
+                torch.empty(3000, dtype=torch.float64, device="cuda")),
+               (h, 64, torch.tensor(D.lisa_particles(2000, seed=123), device="cuda"),
+                torch.empty(2000, dtype=torch.float64, device="cuda"))]
+        B.scs_evaluate_batched(big, B.SCS_PREC_FP64)
+        u = torch.empty(3000, dtype=torch.float64, device="cuda")
+        B.scs_evaluate(h, big[0][2], u)
+        torch.cuda.synchronize()
+        for rep in range(2):
+            for it in items:
+                it[3].fill_(-1.0)
+            torch.cuda.synchronize()
+            B.scs_graph_launch(graph)
+            torch.cuda.synchronize()
+            for it, f in zip(items, first):
+                assert np.array_equal(it[3].cpu().numpy(), f), rep
+        B.scs_define_segmentation(h, 8, B.SCS_SEG_EQUAL_SNR, 16)
+        with pytest.raises(B.ScsError) as ei:
+            B.scs_graph_launch(graph)
+        assert ei.value.code == B.SCS_ESTATE
+        B.scs_graph_destroy(graph)
+    finally:
+        B.scs_ctx_destroy(h)
+
+
 def test_batch_mixes_response_models():
     """One batched call (and its graph) over contexts of every kernel
     instantiation: low-frequency A+E, full-response A+E and A+E+T, one
