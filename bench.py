@@ -39,6 +39,23 @@ import synth  # noqa: E402
 # and the per-block set-up).
 FLOP_PER_EVAL_FP64 = 98
 PEAK_FP64_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 64 lanes x 2
+# FP32 operations per in-support particle-bin of the mixed-precision
+# generate-and-reduce kernel, two channels, from its per-bin op list (same
+# counting): bin coordinate 1 add; linear phase a1h j 1 mul, its fraction
+# 1 sub; residual cubic 3 FMA and 1 add; response cubics 4 x 3 FMA; data x
+# conj(response) 6 FMA + 2 mul; Z rotate-and-accumulate 4 FMA; H 4 FMA +
+# 2 mul.  Total 29 FMA + 8 other = 66, plus 2 hardware transcendentals
+# (sin and cos of revolutions), counted apart.  The compensated additions
+# (12 ops per 32 bins) are left out.
+FLOP_PER_EVAL_MIXED = 66
+TRANS_PER_EVAL_MIXED = 2
+# FP32 vector peak as published (256 CU x 2.4 GHz x 128 FMA lanes x 2: the
+# packed dual-rate path).  Packed FP32 instructions are kept out of the
+# library's code, so its FP32 work issues at the non-packed rate, half of
+# this (78.6); transcendentals issue at a quarter of the non-packed rate.
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP32_NONPACKED_TFLOPS = 78.6
+PEAK_TRANS_PER_S = 256 * 4 * 16 * 2.4e9 / 4  # 9.8e12 per second
 
 
 def log(*a):
@@ -46,6 +63,7 @@ def log(*a):
 
 
 PROFILE = os.path.join(ROOT, "profiles", "k_main_multi_fp64_lisa1m.txt")
+MIXED_PROFILE = os.path.join(ROOT, "profiles", "k_main_multi_mixed_lisa1m.txt")
 STREAMS_PROFILE = os.path.join(ROOT, "profiles", "k_streams_lisa1m.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2408_13170_amd", "csrc", f)
                   for f in ("scs_kernels.hip", "scs_internal.hpp", "scs_math.hpp")]
@@ -90,6 +108,18 @@ def measured_traffic(path=PROFILE):
         return None
 
 
+def n_eff(bounds):
+    """Non-empty segments per row of edges [P, N+1]."""
+    return np.sum(bounds[:, 1:] > bounds[:, :-1], axis=1)
+
+
+def floored_err(got, ref, neff):
+    """|got - ref| / max(|ref|, 2 N_eff): the relative error, floored at the
+    statistic's noise mean (each non-empty segment adds chi^2 with two
+    degrees of freedom)."""
+    return np.abs(got - ref) / np.maximum(np.abs(ref), 2.0 * np.maximum(neff, 1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,6 +143,10 @@ def main():
     ap.add_argument("--realisations", type=int, default=1024,
                     help="streams: noise realisations held in HBM at once")
     ap.add_argument("--loads", type=str, default="0.5,0.8,0.95", help="serve: offered loads (x capacity)")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="step: skip the short batched, served and 16384-bin legs of the default run")
+    ap.add_argument("--tune-cache", type=str, default=None,
+                    help="batched: autotuner cache file (read, then rewritten)")
     args = ap.parse_args()
     if args.copy_probe_mib:
         import torch
@@ -190,11 +224,13 @@ def main():
     u64 = torch.empty(w.P, dtype=torch.float64, device=dev)
     u32 = torch.empty(w.P, dtype=torch.float64, device=dev)
     B.scs_evaluate(ctx, th, u64, B.SCS_PREC_FP64)
+    torch.cuda.synchronize()
+    neff = n_eff(B.scs_last_bounds(ctx, w.P, w.N)[1])
     B.scs_evaluate(ctx, th, u32, B.SCS_PREC_MIXED)
     torch.cuda.synchronize()
     a, b = u64.cpu().numpy(), u32.cpu().numpy()
     ok = np.isfinite(a)
-    err = np.abs(b[ok] - a[ok]) / np.maximum(np.abs(a[ok]), 2.0 * w.N)
+    err = floored_err(b[ok], a[ok], neff[ok])
     # likelihood epilogue (Sec 2.1 - 2.2) on the same swarm: the same
     # generate-and-reduce with more sums in the epilogue, then log hat L_N and log L
     st = torch.empty((w.P, B.SCS_NSTATS), dtype=torch.float64, device=dev)
@@ -256,7 +292,24 @@ def main():
         "likelihood_epilogue": epi,
     }
     if rmx is not None:
+        mx_launch_ms = rmx["main_ms"] / max(rmx["main_launches"], 1)
+        mx_evals_per_launch = rmx["evals"] / max(rmx["main_launches"], 1)
+        mx_rate = mx_evals_per_launch / (mx_launch_ms * 1e-3)
+        mx_achieved = mx_rate * FLOP_PER_EVAL_MIXED / 1e12
         out["mixed"] = {"value": rmx["evals"] / rmx["wall_s"], "unit": "evals/s",
+                        "roofline": {"bound": "alu", "achieved": mx_achieved, "peak": PEAK_FP32_TFLOPS,
+                                     "unit": "TFLOP/s", "frac": mx_achieved / PEAK_FP32_TFLOPS,
+                                     "frac_of_nonpacked_fp32": mx_achieved / PEAK_FP32_NONPACKED_TFLOPS,
+                                     "traffic": None if fd else measured_traffic(MIXED_PROFILE),
+                                     "kernel": {"lf": "k_main_multi<2,true,1>", "fd": "k_main_multi<2,true,2>",
+                                                "fd3": "k_main_multi<3,true,2>"}[args.response]
+                                     + " (mixed-precision generate-and-reduce)",
+                                     "avg_launch_ms": mx_launch_ms, "flop_per_eval": FLOP_PER_EVAL_MIXED,
+                                     "evals_per_launch": mx_evals_per_launch,
+                                     "transcendentals_per_eval": TRANS_PER_EVAL_MIXED,
+                                     "transcendental_rate": mx_rate * TRANS_PER_EVAL_MIXED,
+                                     "transcendental_peak": PEAK_TRANS_PER_S,
+                                     "transcendental_frac": mx_rate * TRANS_PER_EVAL_MIXED / PEAK_TRANS_PER_S},
                         "ms_per_step": 1e3 * rmx["wall_s"] / args.steps,
                         "latency_ms": {"p50": float(np.median(rmx["step_ms"])),
                                        "p99": float(np.quantile(rmx["step_ms"], 0.99))},
@@ -264,7 +317,11 @@ def main():
                         "speedup_vs_fp64": (rmx["evals"] / rmx["wall_s"]) / value,
                         "err_vs_fp64": {"median": float(np.median(err)), "p99": float(np.quantile(err, 0.99)),
                                         "max": float(err.max()),
-                                        "measure": "|U_mixed - U_fp64| / max(U_fp64, 2N)"}}
+                                        "measure": "|U_mixed - U_fp64| / max(U_fp64, 2 N_eff)"}}
+    if not args.no_legs:
+        out["config1"] = leg_config1(B, torch, dev)
+        out["batched"] = bench_batched_core(B, torch, dev, steps=5, warmup=2, tune_cache=args.tune_cache)
+        out["served"] = bench_serve_core(B, torch, dev, n_requests=200, loads=[0.8])
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, psd, d_ri.cpu().numpy(), args.cpu_seconds, fd)
     B.scs_ctx_destroy(ctx)
@@ -306,15 +363,28 @@ def make_search(B, torch, w, dev, response="lf"):
 
 
 def bench_batched(args):
-    """Six swarms of the hierarchy, (N, P) = (4096, 16384) ... (1, 128), on the
-    2^20-bin A+E data in ONE graph-captured batched launch (one persistent
-    generate-and-reduce kernel over all tiles), FP64 and mixed; mixed error
-    per level against FP64."""
     import torch
 
     from paper_2408_13170_amd import B
 
     dev = torch.device("cuda:0")
+    res = bench_batched_core(B, torch, dev, args.steps, args.warmup, args.tune_cache)
+    out = {"metric": "particle x freq-bin statistic evals/s (in-support), batched hierarchy, FP64; mixed beside",
+           "value": res["fp64"]["value"], "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": res["fp64"]["ms_per_batch"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic: same data as the step benchmark",
+           "config": {"workload": res["workload"]}}
+    out.update({k: v for k, v in res.items() if k != "workload"})
+    print(json.dumps(out), flush=True)
+
+
+def bench_batched_core(B, torch, dev, steps, warmup, tune_cache=None):
+    """Six swarms of the hierarchy, (N, P) = (4096, 16384) ... (1, 128), on the
+    2^20-bin A+E data in ONE graph-captured batched launch (one persistent
+    generate-and-reduce kernel over all tiles), FP64 and mixed, first with
+    the default launch shapes, then with the shapes the autotuner picks for
+    each swarm (cached in tune_cache when given); mixed error per level
+    against FP64 (floored at 2 N_eff)."""
     w = synth.workload("lisa1m")
     ctx, _ = make_search(B, torch, w, dev)
     stream = torch.cuda.current_stream()
@@ -322,68 +392,145 @@ def bench_batched(args):
     for i, (N, P) in enumerate(synth.LADDER_SWARMS):
         th = torch.tensor(synth.particles(w.prior_lo, w.prior_hi, P, w.seed + 700 + i), device=dev)
         items.append((ctx, N, th, torch.empty(P, dtype=torch.float64, device=dev)))
-    res = {}
-    for prec, name in ((B.SCS_PREC_FP64, "fp64"), (B.SCS_PREC_MIXED, "mixed")):
+
+    def timed(prec):
         g = B.scs_graph_create(items, prec)
-        for _ in range(args.warmup):
+        for _ in range(warmup):
             B.scs_graph_launch(g, stream)
         torch.cuda.synchronize()
         B.scs_ctx_stats(ctx, reset=True)
         B.scs_ctx_profile(ctx, 1)
-        evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
         t0 = time.perf_counter()
         evs[0].record(stream)
-        for i in range(args.steps):
+        for i in range(steps):
             B.scs_graph_launch(g, stream)
             evs[i + 1].record(stream)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         n_launch, main_ms = B.scs_ctx_profile(ctx, 0)
         ev_support, _, _ = B.scs_ctx_stats(ctx, reset=True)
-        step_ms = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
+        step_ms = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(steps)])
         B.scs_graph_destroy(g)
-        res[name] = {"value": ev_support / (t1 - t0), "unit": "evals/s", "ms_per_batch": 1e3 * (t1 - t0) / args.steps,
-                     "latency_ms": {"p50": float(np.median(step_ms)), "p99": float(np.quantile(step_ms, 0.99))},
-                     "evals_per_batch": ev_support / args.steps,
-                     "ups": [it[3].cpu().numpy().copy() for it in items]}
-        log(f"batched {name}: {res[name]['value']:.4g} evals/s, {res[name]['ms_per_batch']:.2f} ms per batch")
+        return {"value": ev_support / (t1 - t0), "unit": "evals/s", "ms_per_batch": 1e3 * (t1 - t0) / steps,
+                "latency_ms": {"p50": float(np.median(step_ms)), "p99": float(np.quantile(step_ms, 0.99))},
+                "avg_main_launch_ms": main_ms / max(n_launch, 1), "evals_per_batch": ev_support / steps,
+                "ups": [it[3].cpu().numpy().copy() for it in items]}
+
+    res = {"default_shapes": {}}
+    for prec, name in ((B.SCS_PREC_FP64, "fp64"), (B.SCS_PREC_MIXED, "mixed")):
+        r = timed(prec)
+        del r["ups"]
+        res["default_shapes"][name] = r
+        log(f"batched {name}, default shapes: {r['value']:.4g} evals/s, {r['ms_per_batch']:.2f} ms per batch")
+    t0 = time.perf_counter()
+    for prec in (B.SCS_PREC_FP64, B.SCS_PREC_MIXED):
+        for it in items:
+            B.scs_autotune(ctx, it[2], it[1], prec, tune_cache)
+    tune_s = time.perf_counter() - t0
+    for prec, name in ((B.SCS_PREC_FP64, "fp64"), (B.SCS_PREC_MIXED, "mixed")):
+        res[name] = timed(prec)
+        log(f"batched {name}, tuned shapes: {res[name]['value']:.4g} evals/s, "
+            f"{res[name]['ms_per_batch']:.2f} ms per batch")
     per_level = []
-    for (N, P), a, b in zip(synth.LADDER_SWARMS, res["fp64"]["ups"], res["mixed"]["ups"]):
+    for (N, P), it, a, b in zip(synth.LADDER_SWARMS, items, res["fp64"]["ups"], res["mixed"]["ups"]):
+        # edges of the level's particles (a solo evaluation gives the batched values bit for bit)
+        B.scs_define_segmentation(ctx, N, B.SCS_SEG_EQUAL_SNR, w.G)
+        B.scs_evaluate(ctx, it[2], torch.empty(P, dtype=torch.float64, device=dev))
+        torch.cuda.synchronize()
+        neff = n_eff(B.scs_last_bounds(ctx, P, N)[1])
         ok = np.isfinite(a)
-        e = np.abs(b[ok] - a[ok]) / np.maximum(np.abs(a[ok]), 2.0 * N)
+        e = floored_err(b[ok], a[ok], neff[ok])
         per_level.append({"N": N, "P": P, "median": float(np.median(e)), "p99": float(np.quantile(e, 0.99)),
                           "max": float(e.max())})
-    for r in res.values():
+    for r in (res["fp64"], res["mixed"]):
         del r["ups"]
-    out = {"metric": "particle x freq-bin statistic evals/s (in-support), batched hierarchy, FP64; mixed beside",
-           "value": res["fp64"]["value"], "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "ms_per_step": res["fp64"]["ms_per_batch"], "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f64", "data": "synthetic: same data as the step benchmark",
-           "config": {"workload": "six swarms (N, P) = " + str(synth.LADDER_SWARMS) + " on the 2^20-bin A+E data, "
-                                  "one HIP graph per precision, one persistent fused generate-and-reduce launch"},
-           "fp64": res["fp64"], "mixed": res["mixed"],
-           "mixed_speedup": res["mixed"]["value"] / res["fp64"]["value"],
-           "mixed_err_vs_fp64_per_level": per_level}
     B.scs_ctx_destroy(ctx)
-    print(json.dumps(out), flush=True)
+    res["mixed_speedup"] = res["mixed"]["value"] / res["fp64"]["value"]
+    res["tuned_vs_default"] = {n: res[n]["value"] / res["default_shapes"][n]["value"] for n in ("fp64", "mixed")}
+    res["tune_seconds"] = tune_s
+    res["mixed_err_vs_fp64_per_level"] = per_level
+    res["workload"] = ("six swarms (N, P) = " + str(synth.LADDER_SWARMS) + " on the 2^20-bin A+E data, one HIP "
+                       "graph per precision, one persistent fused generate-and-reduce launch, autotuned shapes")
+    return res
+
+
+def leg_config1(B, torch, dev, reps=50):
+    """The 16384-bin single-channel configuration: unit white PSD, 2PN
+    injection (Mc 30, q 0.8) at SNR 20, N = 16, 64 particles in the
+    Mc +-1% / q +-10% box, one evaluation per particle per call; FP64 and
+    mixed call latency and throughput (a launch-bound size: 10^6
+    particle-bins per call)."""
+    w = synth.workload("white16k")
+    K, df = w.grid.K, w.grid.df
+    psd = synth.psd_arrays(w)
+    ctx = B.scs_ctx_create(0)
+    B.scs_load_data(ctx, np.zeros((1, K, 2)), psd, w.grid.f_min, df)
+    B.scs_set_model(ctx, w.pn_order, B.SCS_RESP_NONE, B.SCS_SUPPORT_FULL, w.grid.t_obs)
+    h = torch.empty((1, K, 2), dtype=torch.float64, device=dev)
+    B.scs_waveform(ctx, torch.tensor(w.injection, device=dev), h)
+    torch.cuda.synchronize()
+    hc = torch.complex(h[..., 0], h[..., 1])
+    hh = float(4 * df * torch.sum(hc.abs() ** 2))
+    d = torch.tensor(synth.noise(psd, df, w.seed), device=dev) + hc * (w.snr / math.sqrt(hh))
+    B.scs_load_data(ctx, torch.stack([d.real, d.imag], -1).contiguous(), torch.tensor(psd, device=dev),
+                    w.grid.f_min, df)
+    B.scs_set_model(ctx, w.pn_order, B.SCS_RESP_NONE, B.SCS_SUPPORT_FULL, w.grid.t_obs)
+    B.scs_define_segmentation(ctx, w.N, B.SCS_SEG_EQUAL_SNR, w.G)
+    th = torch.tensor(synth.workload_particles(w), device=dev)
+    u = torch.empty(w.P, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    out = {"workload": "16384 bins over [0.016, 0.032) Hz, one channel, unit white PSD, 2PN, N_seg 16, "
+                       "64 particles", "evals_per_call": w.P * K}
+    for prec, name in ((B.SCS_PREC_FP64, "fp64"), (B.SCS_PREC_MIXED, "mixed")):
+        for _ in range(5):
+            B.scs_evaluate(ctx, th, u, prec)
+        torch.cuda.synchronize()
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        evs[0].record(stream)
+        for i in range(reps):
+            B.scs_evaluate(ctx, th, u, prec)
+            evs[i + 1].record(stream)
+        torch.cuda.synchronize()
+        ms = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(reps)])
+        out[name] = {"evals_per_s": w.P * K / (ms.mean() * 1e-3),
+                     "latency_ms": {"p50": float(np.median(ms)), "p99": float(np.quantile(ms, 0.99))}}
+        log(f"16384-bin configuration {name}: {out[name]['evals_per_s']:.3g} evals/s, "
+            f"p50 {np.median(ms):.3f} ms per call")
+    B.scs_ctx_destroy(ctx)
+    return out
 
 
 def bench_serve(args):
-    """Eight independent searches (2^19 - 2^21 bins, A+E, GW150914-like and
-    GW190521-like injections at SNR 15 - 40) behind the native request loop.
-    Requests of 256 - 16384 particles (log-uniform) at a segment count from
-    the ladder arrive as a Poisson process at fractions of the measured
-    capacity; p50 / p99 latency (submit to result) and throughput."""
     import torch
 
     from paper_2408_13170_amd import B
 
     dev = torch.device("cuda:0")
+    rep = bench_serve_core(B, torch, dev, args.requests, [float(x) for x in args.loads.split(",")])
+    levels = rep["fp64"]["levels"]
+    out = {"metric": "served statistic evaluations: p50/p99 request latency and throughput, FP64; mixed beside",
+           "value": levels[-1]["evals_per_s"], "unit": "evals/s", "n_gpus": 1, "steps": len(levels),
+           "warmup": 1, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic: eight seeded searches",
+           "config": {"workload": rep["workload"], **rep["server_shape"]},
+           "capacity_rps": rep["fp64"]["capacity_rps"],
+           "capacity_evals_per_s": rep["fp64"]["capacity_evals_per_s"], "levels": levels,
+           "mixed": rep["mixed"], "server": rep["server"]}
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve_core(B, torch, dev, n_requests, loads):
+    """Eight independent searches (2^19 - 2^21 bins, A+E, GW150914-like and
+    GW190521-like injections at SNR 15 - 40) behind the native request loop.
+    Requests of 256 - 16384 particles (log-uniform) at a segment count from
+    the ladder arrive as a Poisson process at fractions of the measured
+    capacity; p50 / p99 latency (submit to result) and throughput, FP64 and
+    mixed; mixed against FP64 on the same requests (floored at 2 N_eff)."""
     searches = []
     for w in synth.served_streams():
         ctx, _ = make_search(B, torch, w, dev)
         searches.append((w, ctx))
-        log(f"search {w.name}: K = {w.grid.K}, SNR {w.snr}")
     torch.cuda.synchronize()
     ladder = [4096, 1024, 256, 64, 16]
     rng = np.random.default_rng(synth.BASE_SEED + 900)
@@ -398,8 +545,8 @@ def bench_serve(args):
                                                                          int(rng.integers(1 << 30))), si))
         return reqs
 
-    budget = 64 << 30
-    srv = B.scs_server_create(0, max_inflight=32, hbm_budget=budget, n_streams=4)
+    budget, inflight, n_streams = 64 << 30, 32, 4
+    srv = B.scs_server_create(0, max_inflight=inflight, hbm_budget=budget, n_streams=n_streams)
 
     def run(reqs, arrivals, prec):
         outs = {}
@@ -418,13 +565,14 @@ def bench_serve(args):
             done += B.scs_server_poll(srv, max_out=1024, wait_ms=wait)
         t1 = time.perf_counter() - t0
         lat = np.array([d["t_done"] - d["t_submit"] for d in done]) * 1e3
+        queue = np.array([d["t_launch"] - d["t_submit"] for d in done]) * 1e3
         assert all(d["status"] == 0 for d in done)
         results = [None] * len(reqs)
         for rid, (ups, i) in outs.items():
             results[i] = ups
-        return t1, lat, results
+        return t1, lat, queue, results
 
-    burst = make_requests(max(64, args.requests // 8))
+    burst = make_requests(max(32, n_requests // 8))
     run(burst[:16], None, B.SCS_PREC_FP64)  # warm-up: workspaces, slots
     run(burst[:16], None, B.SCS_PREC_MIXED)
     report = {}
@@ -433,50 +581,47 @@ def bench_serve(args):
         # capacity: a closed burst of requests
         for _, ctx in searches:
             B.scs_ctx_stats(ctx, reset=True)
-        t_b, _, burst_out[pname] = run(burst, None, prec)
+        t_b, _, _, burst_out[pname] = run(burst, None, prec)
         ev_b = sum(B.scs_ctx_stats(ctx, reset=True)[0] for _, ctx in searches)
         capacity = len(burst) / t_b
-        log(f"{pname}: capacity {capacity:.1f} requests/s, {ev_b / t_b:.4g} evals/s")
+        log(f"served {pname}: capacity {capacity:.1f} requests/s, {ev_b / t_b:.4g} evals/s")
         levels = []
-        for load in [float(x) for x in args.loads.split(",")]:
-            reqs = make_requests(args.requests)
+        for load in loads:
+            reqs = make_requests(n_requests)
             arrivals = np.cumsum(rng.exponential(1.0 / (load * capacity), len(reqs)))
-            t, lat, _ = run(reqs, arrivals, prec)
+            t, lat, queue, _ = run(reqs, arrivals, prec)
             ev = sum(B.scs_ctx_stats(ctx, reset=True)[0] for _, ctx in searches)
             levels.append({"offered_load": load, "offered_rps": load * capacity, "achieved_rps": len(reqs) / t,
                            "evals_per_s": ev / t, "requests": len(reqs),
-                           "latency_ms": {"p50": float(np.median(lat)), "p99": float(np.quantile(lat, 0.99))}})
-            log(f"{pname} load {load}: {len(reqs) / t:.1f} req/s, p50 {np.median(lat):.1f} ms, "
-                f"p99 {np.quantile(lat, 0.99):.1f} ms")
+                           "latency_ms": {"p50": float(np.median(lat)), "p99": float(np.quantile(lat, 0.99))},
+                           "queue_ms": {"p50": float(np.median(queue)), "p99": float(np.quantile(queue, 0.99))}})
+            log(f"served {pname} load {load}: {len(reqs) / t:.1f} req/s, p50 {np.median(lat):.1f} ms, "
+                f"p99 {np.quantile(lat, 0.99):.1f} ms (queue p50 {np.median(queue):.1f} ms)")
         report[pname] = {"capacity_rps": capacity, "capacity_evals_per_s": ev_b / t_b, "levels": levels}
     # mixed against FP64 on the burst's requests (each served in both precisions)
     errs = []
     for (ctx, N, th, si), a, b in zip(burst, burst_out["fp64"], burst_out["mixed"]):
+        B.scs_define_segmentation(ctx, N, B.SCS_SEG_EQUAL_SNR, searches[si][0].G)
+        B.scs_evaluate(ctx, torch.tensor(th, device=dev), torch.empty(th.shape[0], dtype=torch.float64, device=dev))
+        torch.cuda.synchronize()
+        neff = n_eff(B.scs_last_bounds(ctx, th.shape[0], N)[1])
         ok = np.isfinite(a)
-        errs.append(np.abs(b[ok] - a[ok]) / np.maximum(np.abs(a[ok]), 2.0 * N))
+        errs.append(floored_err(b[ok], a[ok], neff[ok]))
     err = np.concatenate(errs)
     report["mixed"]["err_vs_fp64"] = {"median": float(np.median(err)), "p99": float(np.quantile(err, 0.99)),
                                       "max": float(err.max()), "requests": len(burst),
-                                      "measure": "|U_mixed - U_fp64| / max(U_fp64, 2N), same requests served "
-                                                 "in both precisions"}
-    log(f"mixed vs fp64 on {len(burst)} served requests: median {np.median(err):.3g}, max {err.max():.3g}")
+                                      "measure": "|U_mixed - U_fp64| / max(U_fp64, 2 N_eff), same requests "
+                                                 "served in both precisions"}
+    log(f"served mixed vs fp64 on {len(burst)} requests: median {np.median(err):.3g}, max {err.max():.3g}")
     st = B.scs_server_stats(srv)
     B.scs_server_destroy(srv)
     for _, ctx in searches:
         B.scs_ctx_destroy(ctx)
-    levels = report["fp64"]["levels"]
-    out = {"metric": "served statistic evaluations: p50/p99 request latency and throughput, FP64; mixed beside",
-           "value": levels[-1]["evals_per_s"], "unit": "evals/s", "n_gpus": 1, "steps": len(levels),
-           "warmup": 1, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f64", "data": "synthetic: eight seeded searches",
-           "config": {"workload": "8 searches, K in {2^19, 2^20, 2^21}, A+E; requests of 256-16384 particles "
-                                  "(log-uniform), N in " + str(ladder) + ", Poisson arrivals",
-                      "max_inflight": 32, "streams": 4, "hbm_budget_gib": budget >> 30},
-           "capacity_rps": report["fp64"]["capacity_rps"],
-           "capacity_evals_per_s": report["fp64"]["capacity_evals_per_s"], "levels": levels,
-           "mixed": report["mixed"],
-           "server": {k: int(v) for k, v in st.items()}}
-    print(json.dumps(out), flush=True)
+    report["server"] = {k: int(v) for k, v in st.items()}
+    report["server_shape"] = {"max_inflight": inflight, "streams": n_streams, "hbm_budget_gib": budget >> 30}
+    report["workload"] = ("8 searches, K in {2^19, 2^20, 2^21}, A+E; requests of 256-16384 particles "
+                          "(log-uniform), N in " + str(ladder) + ", Poisson arrivals")
+    return report
 
 
 def bench_streams(args):
@@ -633,10 +778,25 @@ def bench_search(args):
     print(json.dumps(out), flush=True)
 
 
+def cpu_model():
+    """The host CPU's model name and logical CPU count."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return name, os.cpu_count()
+
+
 def cpu_baseline(w, psd, d_ri, seconds, fd=False):
     """The CPU oracle, as it stands, on a bounded sample of the same workload:
     particles from the same prior box, evaluated in batches on every host
-    thread until about `seconds` of wall time."""
+    thread until about `seconds` of wall time, then a few particles on one
+    thread."""
     import oracle as O
 
     g = O.Grid(w.grid.K, w.grid.k0, w.grid.df, psd.shape[0])
@@ -653,8 +813,21 @@ def cpu_baseline(w, psd, d_ri, seconds, fd=False):
         t += time.perf_counter() - t0
         evals += int((out["support"][:, 1] - out["support"][:, 0]).sum())
         used += batch
+    # one thread: particles one at a time until about a third of the budget
+    e1, n1, t1 = 0, 0, 0.0
+    while t1 < seconds / 3 and n1 < 64:
+        th = th_all[used + n1:used + n1 + 1]
+        t0 = time.perf_counter()
+        out = O.evaluate(g, m, d_ri, psd, th, w.N, O.SEG_EQUAL_SNR, w.G, n_threads=1)
+        t1 += time.perf_counter() - t0
+        e1 += int(out["support"][0, 1] - out["support"][0, 0])
+        n1 += 1
+    model, ncpu = cpu_model()
     return {"value": evals / t, "unit": "evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"{used} particles of the same workload (full 2^20-bin grid, N_seg 1024), {t:.1f} s"}
+            "sample": f"{used} particles of the same workload (full 2^20-bin grid, N_seg 1024), {t:.1f} s "
+                      f"on {threads} threads; {n1} more particles on one thread, {t1:.1f} s",
+            "single_core": {"value": e1 / t1, "unit": "evals/s", "particles": n1, "seconds": t1},
+            "cpu_model": model, "logical_cpus": ncpu}
 
 
 if __name__ == "__main__":
