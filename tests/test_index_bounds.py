@@ -1,0 +1,214 @@
+"""Host-side emulation of the index arithmetic of one work tile of the
+generate-and-reduce kernel (main_tile in scs_kernels.hip): every LDS,
+trigonometric-table, basis-table and global offset that a tile can form,
+checked against the sizes of the buffers it addresses, over the 2^20-bin
+two-channel layout the step benchmark uses (512-bin LDS blocks, 2048-bin
+chunks, 256 particle slots per tile) and over adversarial supports and
+edges: supports that start or end on chunk and block boundaries, one-bin
+supports, runs of empty segments, edges on chunk boundaries, idle lanes and
+the last particle of the buffer.  It also covers the variant that reads each
+bin's table entry one bin ahead (the entry of bin k + 1 while bin k is
+evaluated): the table index is the bin's phase, in 1/1024 cycles, masked to
+10 bits and or-ed with the zero-entry offset, so whatever the phase, the
+index lies in [0, 1024], the 1025 entries the table holds (the zero entry
+included).  Nothing here runs on a GPU; it replays integer arithmetic."""
+import numpy as np
+
+K_TRIG = 1024
+TAB_ENTRIES = K_TRIG + 1
+K_REC = 8
+
+
+def table_index(phase_units, tmask, toff):
+    """The kernel's table index: the low 32 bits of (phase + 1.5 * 2^52) as an
+    integer, masked with tmask and or-ed with toff."""
+    t = np.asarray(phase_units, dtype=np.float64) + 1.5 * 2.0 ** 52
+    bits = t.view(np.uint64) & np.uint64(0xFFFFFFFF)
+    return (bits.astype(np.int64) & tmask) | toff
+
+
+def emulate_tile(K, L, CB, N, NV, lanes_lg, lanes_klo, lanes_khi, bounds, P_total, slot0, chunk, n_chunks,
+                 lg_levels):
+    """Replay the offsets of one tile (chunk, group of len(lanes) slots);
+    bounds is the whole [P_total][N+1] edge array plus two spare entries, the
+    lanes are particles slot0 .. slot0 + len - 1.  Returns the number of
+    lane-bins visited.  Raises AssertionError at the first offset out of its
+    buffer."""
+    W = len(lanes_lg)
+    cbins = L * CB
+    Kc = chunk * cbins
+    Ke = min(Kc + cbins, K)
+    n_bounds = P_total * (N + 1) + 2
+    n_zs = P_total * N * 3
+    n_rec = n_chunks * P_total * K_REC
+    lds_doubles = L * NV
+    p = slot0 + np.arange(W)
+    live = p < P_total
+    lg = np.where(live, lanes_lg, -1)
+    lo = np.where(lg >= 0, lanes_klo, 0)
+    hi = np.where(lg >= 0, lanes_khi, 0)
+    lo = np.maximum(lo, Kc)
+    hi = np.minimum(hi, Ke)
+    has = lo < hi
+    if not has.any():
+        return 0
+    prow = np.where(live, p, slot0) * (N + 1)
+
+    def bo(idx):
+        assert np.all((idx >= 0) & (idx < n_bounds)), "edge read out of the bounds buffer"
+        return bounds[idx]
+
+    lgw = int(lg[has].min())
+    # segment state
+    n = np.zeros(W, dtype=np.int64)
+    nb = np.full(W, 2 ** 31 - 1, dtype=np.int64)
+    nb2 = nb.copy()
+    for i in np.flatnonzero(has):
+        row = bounds[prow[i]:prow[i] + N]
+        n[i] = np.searchsorted(row, lo[i], side="right") - 1  # largest n in [0, N-1] with b_n <= lo
+        nb[i] = bo(prow[i] + n[i] + 1)
+        nb2[i] = bo(prow[i] + n[i] + 2)
+    before = np.array([has[i] and bounds[prow[i] + n[i]] < Kc for i in range(W)])
+    nxt = np.where(has, np.where(lo > Kc, lo, nb), 2 ** 31 - 1)
+    rec_base = ((chunk - 0) * P_total + np.where(live, p, 0)) * K_REC
+    zsp = (np.where(live, p, slot0) * N + n) * 3
+    dst_rec = before.copy()
+    dst_zs = zsp.copy()
+
+    def store(i):
+        if dst_rec[i]:
+            off = rec_base[i]
+            assert 0 <= off and off + 2 < n_rec, "head-record store out of rec"
+        else:
+            off = dst_zs[i]
+            assert 0 <= off and off + 2 < n_zs, "segment store out of zs"
+
+    def handle(i, k):
+        store(i)
+        if nb[i] <= k:
+            n[i] += 1
+            zsp[i] += 3
+            nb[i] = nb2[i] if n[i] < N else 2 ** 31 - 1
+            nb2[i] = bo(prow[i] + n[i] + 2)
+            if nb[i] <= k:
+                row = bounds[prow[i]:prow[i] + N]
+                n[i] = np.searchsorted(row, k, side="right") - 1
+                nb[i] = bo(prow[i] + n[i] + 1)
+                if nb[i] <= k:
+                    n[i] = N
+                    nb[i] = 2 ** 31 - 1
+                nb2[i] = bo(prow[i] + n[i] + 2)
+                zsp[i] = (np.where(live, p, slot0)[i] * N + n[i]) * 3
+            dst_rec[i] = False
+            dst_zs[i] = zsp[i]
+        nxt[i] = nb[i]
+
+    lgl = np.where(has, lg, lgw)
+    have = np.full(W, -1, dtype=np.int64)
+    tmask = np.zeros(W, dtype=np.int64)
+    toff = np.full(W, K_TRIG, dtype=np.int64)
+    rng = np.random.default_rng(chunk)
+    visited = 0
+    for b0 in range(Kc, Ke, L):
+        b1 = min(b0 + L, Ke)
+        nbins = b1 - b0
+        assert b1 * NV <= K * NV and nbins * NV <= lds_doubles, "staging out of the bin table or the LDS block"
+        llo = np.maximum(lo, b0)
+        lhi = np.minimum(hi, b1)
+        act = llo < lhi
+        if not act.any():
+            continue
+        wlo, whi = int(llo[act].min()), int(lhi[act].max())
+        Lp = 1 << lgw
+        for sb0 in range((wlo >> lgw) << lgw, whi, Lp):
+            s_lo, s_hi = max(sb0, wlo), min(sb0 + Lp, whi)
+            sact = act & (llo < sb0 + Lp) & (lhi > sb0)
+            sbl = (sb0 >> lgl) << lgl
+            setup = sact & (have != sbl)
+            for i in np.flatnonzero(setup):
+                sub = sbl[i] >> lgl[i]
+                assert 0 <= sub < lg_levels[lgl[i]], "basis-table entry out of its level"
+                have[i] = sbl[i]
+                tmask[i], toff[i] = K_TRIG - 1, 0
+            for k in range(s_lo, s_hi):
+                due = np.flatnonzero(nxt <= k)
+                for i in due:
+                    handle(i, k)
+                off = (k - b0) * NV
+                assert 0 <= off and off + NV <= nbins * NV, "bin read out of the staged block"
+                # the table entry of this bin and, read ahead, of the next one:
+                # any phase (random, huge, negative) gives an index in range
+                ph = rng.uniform(-2.0 ** 40, 2.0 ** 40, size=(2, W))
+                for q in (table_index(ph[0], tmask, toff), table_index(ph[1], tmask, toff)):
+                    assert np.all((q >= 0) & (q < TAB_ENTRIES)), "table index out of the table"
+                visited += W
+    # chunk close: the open segment's sums
+    for i in np.flatnonzero(has & (n < N)):
+        if nb[i] <= hi[i]:
+            store(i)
+        else:
+            off = rec_base[i] + (0 if dst_rec[i] else 3)
+            assert off + 2 < n_rec
+    return visited
+
+
+def _edges(rng, klo, khi, N, kind):
+    if kind == "equal":
+        e = np.sort(rng.integers(klo, khi + 1, size=N - 1))
+    elif kind == "runs":  # long runs of empty segments and one-bin segments
+        e = np.sort(np.concatenate([np.full((N - 1) // 2, klo + (khi - klo) // 3),
+                                    rng.integers(klo, khi + 1, size=N - 1 - (N - 1) // 2)]))
+    else:  # edges on chunk and block boundaries
+        grid = np.arange((klo // 512) * 512, khi + 1, 512)
+        e = np.sort(np.clip(rng.choice(grid, size=N - 1), klo, khi))
+    return np.concatenate([[klo], e, [khi]]).astype(np.int64)
+
+
+def test_tile_offsets_stay_in_their_buffers():
+    K, L, CB, NV = 1 << 20, 512, 4, 6
+    N = 64
+    W = 256
+    P_total = 3 * W - 17  # a partial last group
+    n_chunks = (K + L * CB - 1) // (L * CB)
+    lg_levels = {lg: (K + (1 << lg) - 1) >> lg for lg in range(3, 12)}
+    rng = np.random.default_rng(2408)
+    lg = rng.integers(3, 12, size=P_total)
+    klo = rng.integers(0, K, size=P_total)
+    span = rng.choice([1, 2, 7, 500, 2048, 4096, 100000], size=P_total)
+    khi = np.minimum(klo + span, K)
+    # supports starting or ending exactly on chunk / block boundaries, the
+    # band's edges, invalid and empty ones
+    klo[:8] = [0, 2048, 2047, 512, K - 1, K - 2048, 4096, 0]
+    khi[:8] = [2048, 4096, 2049, 1024, K, K, 4097, K]
+    lg[8], khi[9] = -1, klo[9]
+    kinds = ["equal", "runs", "boundary"]
+    bounds = np.concatenate([np.concatenate([_edges(rng, klo[i], khi[i], N, kinds[i % 3]) if khi[i] > klo[i]
+                                             else np.full(N + 1, klo[i]) for i in range(P_total)]),
+                             [0, 0]])
+    chunks = sorted({0, 1, 2, n_chunks - 1, n_chunks - 2} | {int(c) for c in klo[:8] // (L * CB)} |
+                    {int(c) for c in rng.integers(0, n_chunks, size=6)})
+    total = 0
+    for g0 in range(0, P_total, W):
+        sl = slice(g0, min(g0 + W, P_total))
+        pad = W - (sl.stop - sl.start)
+        lgs = np.concatenate([lg[sl], np.full(pad, -1)])
+        kl = np.concatenate([klo[sl], np.zeros(pad, dtype=np.int64)])
+        kh = np.concatenate([khi[sl], np.zeros(pad, dtype=np.int64)])
+        for c in chunks:
+            total += emulate_tile(K, L, CB, N, NV, lgs, kl, kh, bounds, P_total, g0, c, n_chunks, lg_levels)
+    print(f"lane-bins replayed: {total}")
+    assert total > 0
+
+
+def test_table_index_range_for_any_phase():
+    """The masked index covers [0, 1023] for a lane with polynomials and is
+    the zero entry 1024 before a lane's first block, for ordinary, huge,
+    negative, infinite and NaN phases alike."""
+    ph = np.concatenate([np.linspace(-5000, 5000, 10001), [0.0, -0.0, 2.0 ** 51, -2.0 ** 51, 1e300, -1e300,
+                                                           np.inf, -np.inf, np.nan]])
+    q = table_index(ph, K_TRIG - 1, 0)
+    assert q.min() >= 0 and q.max() <= K_TRIG - 1
+    assert np.all(table_index(ph, 0, K_TRIG) == K_TRIG)
+    # for |phase| < 2^51 the entry is the nearest 1/1024 cycle, mod 1024
+    mid = np.linspace(-3000.4, 3000.4, 77)
+    assert np.array_equal(table_index(mid, K_TRIG - 1, 0), np.mod(np.rint(mid).astype(np.int64), K_TRIG))
