@@ -312,8 +312,9 @@ typedef struct scs_server_counters {
     int64_t launches;          /* batched launches */
     int64_t max_batch;         /* most requests in one launch */
     int64_t max_inflight;      /* most requests admitted at once */
-    uint64_t hbm_in_use;       /* footprint of the admitted requests [bytes] */
-    uint64_t hbm_peak;
+    uint64_t hbm_in_use;       /* device bytes the request slots hold: the buffers of the admitted
+                                  requests and those idle slots keep for reuse [bytes] */
+    uint64_t hbm_peak;         /* the largest hbm_in_use seen at an admission */
 } scs_server_counters;
 
 /* max_inflight: request slots (1..1024); hbm_budget: bytes (> 0); n_streams:

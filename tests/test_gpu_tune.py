@@ -96,7 +96,8 @@ def test_server_budget_and_drop_on_destroy():
         assert [d["id"] for d in done] == [rid] and done[0]["status"] == 0
         st = B.scs_server_stats(srv)
         assert st["submitted"] == 1 and st["completed"] == 1 and st["failed"] == 0
-        assert 0 < st["hbm_peak"] <= 64 << 20 and st["hbm_in_use"] == 0
+        # the idle slot keeps its buffers for reuse, and they stay charged
+        assert 0 < st["hbm_in_use"] <= st["hbm_peak"] <= 64 << 20
     finally:
         B.scs_server_destroy(srv)
     th = torch.tensor(np.ascontiguousarray(theta), device="cuda")
