@@ -25,10 +25,12 @@ point (cos, sin) / 2 pi of its angle; the k-means is k-means++ seeding
 (Arthur & Vassilvitskii 2007) with draws from splitmix64 (Steele, Lea & Flood
 2014) followed by Lloyd iterations until no label changes, ties going to the
 lower cluster index, empty clusters dropped and clusters numbered by first
-appearance; a re-grouped particle keeps its position and velocity and starts
-with no particle best (the objective changed), its new swarm with no swarm
-best; swarms are numbered in creation order, which with the search seed keys
-their random numbers.
+appearance; a re-grouped particle keeps its position, velocity and best
+position, its best value restarts at -inf (the objective changed), and its new
+swarm's best position starts at the best position of its member with the
+highest earlier best value, with a swarm best value of -inf (see
+``Search.regroup``); swarms are numbered in creation order, which with the
+search seed keys their random numbers.
 """
 from __future__ import annotations
 
