@@ -151,6 +151,33 @@ int scs_evaluate(scs_ctx* ctx, int64_t P, const double* theta, int32_t prec, dou
 /* Statistics per row of scs_evaluate_stats. */
 #define SCS_NSTATS 5
 
+/* scs_evaluate for callers that cannot allocate memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  It calls no
+ * hipMalloc, hipFree or other allocating routine: every buffer of the
+ * evaluation (particle records, supports, edges, chunk records, per-segment
+ * sums, the support sort, the launch descriptor) lives in one static device
+ * array of SCS_NOALLOC_SCRATCH_BYTES, which every GPU the library runs on
+ * holds from its first context until the process ends.
+ *   theta, ups, seg  DEVICE pointers, layouts as for scs_evaluate (seg
+ *                    nullable; when given, the per-segment sums use it and
+ *                    need no scratch)
+ *   stream           HIP stream the work is queued on (asynchronous)
+ * The launch shape is the default one (the context's forced shape if a test
+ * set one); a tuning cache is not consulted.  Results equal scs_evaluate's
+ * with that shape, bit for bit.
+ * The scratch is shared by every call on a GPU, from every context, thread
+ * and stream, and keeps the last call's contents (what must start at zero is
+ * cleared by kernels on the stream, no memset): calls that overlap on one GPU
+ * race, and the caller must order them (one stream, or events).
+ * Errors: EINVAL (bad arguments, or a request whose buffers exceed the
+ * scratch, in which case nothing is launched: a particle takes about
+ * 470 + 4 (N + 1) + 64 n_chunks bytes, plus 24 N without seg, with n_chunks
+ * = K / 2048 on the default 2048-bin chunks), ESTATE (no data or model),
+ * EDEVICE. */
+#define SCS_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int scs_evaluate_noalloc(scs_ctx* ctx, int64_t P, const double* theta, int32_t prec, double* ups, double* seg,
+                         void* stream);
+
 /* The generate-and-reduce of scs_evaluate with the likelihood epilogue.  For
  * the template h at unit amplitude and zero phase offset (the h of
  * scs_waveform), stats [P][SCS_NSTATS] out:

@@ -83,6 +83,7 @@ _SIGS = {
     "scs_set_model": [C.c_void_p, C.POINTER(scs_model)],
     "scs_define_segmentation": [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p],
     "scs_evaluate": [C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p],
+    "scs_evaluate_noalloc": [C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p],
     "scs_last_bounds": [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p],
     "scs_evaluate_stats": [C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p],
     "scs_data_norm": [C.c_void_p, C.POINTER(C.c_double)],
@@ -295,6 +296,23 @@ def scs_evaluate(ctx, theta, ups, prec=SCS_PREC_FP64, seg=None, stream=None):
     _check(lib().scs_evaluate(ctx, P, pt, prec, pu, ps, kt, _stream(stream)))
 
 
+def scs_evaluate_noalloc(ctx, theta, ups, prec=SCS_PREC_FP64, seg=None, stream=None):
+    """scs_evaluate without any allocation: theta [P,D] -> ups [P] (and seg
+    [P,N,3]), CUDA tensors only; buffers live in the library's static device
+    scratch of SCS_NOALLOC_SCRATCH_BYTES."""
+    info = scs_ctx_info(ctx)
+    P = check_eval_args(theta, ups, seg, info["theta_dim"], info["N"])
+    pt, kt = ptr(theta)
+    pu, ku = ptr(ups)
+    ps, ks = ptr(seg)
+    if kt != SCS_MEM_DEVICE or ku != SCS_MEM_DEVICE or (seg is not None and ks != SCS_MEM_DEVICE):
+        raise ValueError("scs_evaluate_noalloc takes device tensors only")
+    if stream is None:
+        stream = current_stream()
+    _check(lib().scs_evaluate_noalloc(ctx, P, pt, prec, pu, ps, _stream(stream)))
+
+
+SCS_NOALLOC_SCRATCH_BYTES = 64 << 20
 SCS_NSTATS = 5
 
 

@@ -83,10 +83,19 @@ static void cheb_matrix(double* x, double* minv)
         for (int n = 0; n < kNodes; ++n) minv[m * kNodes + n] = (double)V[m][kNodes + n];
 }
 
+// ---------------------------------------------------------------- scratch
+// Device memory of scs_evaluate_noalloc: a static array every GPU the library
+// runs on holds until the process ends.  Its name is a host-side stand-in in
+// host code; the device address of each GPU's copy is taken once, at that
+// device's set-up, and only that address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[SCS_NOALLOC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 256;
+static void* g_scratch[kMaxDevices] = {nullptr};  // written under g_dev_mu before the device is marked ready
+
 static int device_setup(int device)
 {
     std::lock_guard<std::mutex> lk(g_dev_mu);
-    if (g_dev_ready[device]) return SCS_OK;
+    if (device >= 0 && device < kMaxDevices && g_dev_ready[device]) return SCS_OK;
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return fail(SCS_EDEVICE, "no HIP device");
     if (device < 0 || device >= count) return fail(SCS_EDEVICE, "device %d out of range (%d devices)", device, count);
@@ -105,6 +114,12 @@ static int device_setup(int device)
         trig[2 * i + 1] = (double)sinl(a);
     }
     HIP_TRY(upload_trig(trig.data()));
+    if (device >= kMaxDevices) return fail(SCS_EDEVICE, "device %d: at most %d devices", device, kMaxDevices);
+    void* sp = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !sp)
+        return fail(SCS_EDEVICE, "device %d: address of the no-allocation scratch: %s", device, hipGetErrorString(e));
+    g_scratch[device] = sp;
     g_dev_ready[device] = true;
     return SCS_OK;
 }
@@ -496,11 +511,17 @@ static std::string tune_key(const scs_ctx* c, int64_t P, int N, int prec)
 }
 
 // ==== launch shape of the generate-and-reduce (begin)
+static TuneChoice default_choice(const scs_ctx* c, int64_t P);
 static TuneChoice choose(const scs_ctx* c, int64_t P, int N, int prec)
 {
     if (c->has_override) return c->override_choice;
     auto it = c->tune.find(tune_key(c, P, N, prec));
     if (it != c->tune.end()) return it->second;
+    return default_choice(c, P);
+}
+
+static TuneChoice default_choice(const scs_ctx* c, int64_t P)
+{
     TuneChoice t;
     // default: 4 waves (256 particles) per workgroup, fewer when the swarm is
     // small so that the chip still fills; chunks as short as the longest
@@ -814,6 +835,124 @@ extern "C" int scs_evaluate(scs_ctx* c, int64_t P, const double* theta, int32_t 
     HIP_TRY(hipMemcpyAsync(ups, dup, sizeof(double) * P, hipMemcpyDeviceToHost, s));
     if (seg) HIP_TRY(hipMemcpyAsync(seg, dseg, sizeof(double) * P * N * 3, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    return SCS_OK;
+}
+
+// ---------------------------------------------------------------- no allocation
+// The one-item launch descriptor, its tile range and the cleared work counter
+// written into device memory by a kernel (the descriptor travels as a kernel
+// argument), so that the evaluation needs no pinned staging and no memset.
+__global__ void k_put_main_args(MainArgs a, MainArgs* d, int64_t* start, int64_t total, unsigned long long* counter)
+{
+    *d = a;
+    start[0] = 0;
+    start[1] = total;
+    *counter = 0ULL;
+}
+
+// Regions of one evaluation inside the scratch (offsets in bytes, each
+// 256-byte aligned); total = bytes needed.
+struct NoallocLayout {
+    size_t coef, klo, khi, lg, bounds, rec, zs, bucket, rank, perm, hist, items, start, counter, total;
+};
+
+static NoallocLayout noalloc_layout(int64_t P, int N, const Plan& pl, bool own_zs)
+{
+    const uint64_t Pp = (uint64_t)pad64(std::max<int64_t>(P, 1));
+    NoallocLayout l{};
+    size_t off = 0;
+    auto take = [&](size_t& at, uint64_t bytes) {
+        at = off;
+        off += (size_t)((bytes + 255) / 256 * 256);
+    };
+    take(l.coef, sizeof(double) * kCoefStride * Pp);
+    take(l.klo, sizeof(int32_t) * Pp);
+    take(l.khi, sizeof(int32_t) * Pp);
+    take(l.lg, Pp);
+    take(l.bounds, sizeof(int32_t) * ((uint64_t)P * (uint64_t)(N + 1) + 2));
+    take(l.rec, sizeof(double) * (uint64_t)pl.n_chunks * kRec * Pp);
+    take(l.zs, own_zs ? sizeof(double) * 3 * (uint64_t)P * (uint64_t)N : 0);
+    const bool sorted = P >= kSortMin;
+    take(l.bucket, sorted ? sizeof(int32_t) * Pp : 0);
+    take(l.rank, sorted ? sizeof(int32_t) * Pp : 0);
+    take(l.perm, sorted ? sizeof(int32_t) * Pp : 0);
+    take(l.hist, sorted ? sizeof(unsigned) * (uint64_t)kSortBuckets : 0);
+    take(l.items, sizeof(MainArgs));
+    take(l.start, 2 * sizeof(int64_t));
+    take(l.counter, sizeof(unsigned long long));
+    l.total = off;
+    return l;
+}
+
+extern "C" int scs_evaluate_noalloc(scs_ctx* c, int64_t P, const double* theta, int32_t prec, double* ups, double* seg,
+                                    void* stream)
+{
+    int rc = check_ready(c);
+    if (rc) return rc;
+    if (P < 0) return fail(SCS_EINVAL, "P < 0");
+    if (P > 0 && (!theta || !ups)) return fail(SCS_EINVAL, "theta or ups is NULL");
+    if (prec != SCS_PREC_FP64 && prec != SCS_PREC_MIXED) return fail(SCS_EINVAL, "bad precision");
+    if (c->device < 0 || c->device >= kMaxDevices || !g_scratch[c->device])
+        return fail(SCS_ESTATE, "device %d has no no-allocation scratch", c->device);
+    if (P == 0) return SCS_OK;
+    const int N = c->N;
+    // every particle needs its coefficient record at least: a cheap bound
+    // that keeps the layout arithmetic below far from overflow
+    if (P > (int64_t)(SCS_NOALLOC_SCRATCH_BYTES / (sizeof(double) * kCoefStride)))
+        return fail(SCS_EINVAL, "P = %lld exceeds what the %zu-byte device scratch of scs_evaluate_noalloc holds",
+                    (long long)P, (size_t)SCS_NOALLOC_SCRATCH_BYTES);
+    // the default launch shape (or the context's forced one); the tuning
+    // cache is not consulted, its lookup would allocate host memory
+    const TuneChoice t = c->has_override ? c->override_choice : default_choice(c, P);
+    const Plan pl = make_plan(c, P, t);
+    const NoallocLayout l = noalloc_layout(P, N, pl, seg == nullptr);
+    if (l.total > (size_t)SCS_NOALLOC_SCRATCH_BYTES)
+        return fail(SCS_EINVAL, "P = %lld, N = %d on %lld bins needs %zu bytes of device scratch; "
+                    "scs_evaluate_noalloc has %zu", (long long)P, N, (long long)c->g.K, l.total,
+                    (size_t)SCS_NOALLOC_SCRATCH_BYTES);
+    DevScope ds(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    unsigned char* base = (unsigned char*)g_scratch[c->device];
+    const int64_t Pp = pad64(P);
+    Workspace w;  // views into the scratch, freed by no one
+    w.capP = Pp;
+    w.capBounds = P * (int64_t)(N + 1) + 2;
+    w.capRec = pl.n_chunks * kRec * Pp;
+    w.capZs = seg ? 0 : 3 * P * (int64_t)N;
+    w.coef = (double*)(base + l.coef);
+    w.klo = (int32_t*)(base + l.klo);
+    w.khi = (int32_t*)(base + l.khi);
+    w.lg = (int8_t*)(base + l.lg);
+    w.bounds = (int32_t*)(base + l.bounds);
+    w.rec = (double*)(base + l.rec);
+    w.zs = seg ? nullptr : (double*)(base + l.zs);
+    if (P >= kSortMin) {
+        w.capSort = Pp;
+        w.bucket = (int32_t*)(base + l.bucket);
+        w.rank = (int32_t*)(base + l.rank);
+        w.perm = (int32_t*)(base + l.perm);
+        w.hist = (unsigned*)(base + l.hist);
+    }
+    EvalJob j;
+    j.c = c;
+    j.w = &w;
+    j.P = P;
+    j.N = N;
+    if ((rc = eval_front(j, theta, ups, seg, t, s, nullptr, /*fixed_ws=*/true))) return rc;
+    MainArgs* d_items = (MainArgs*)(base + l.items);
+    int64_t* d_start = (int64_t*)(base + l.start);
+    unsigned long long* d_counter = (unsigned long long*)(base + l.counter);
+    hipLaunchKernelGGL(k_put_main_args, dim3(1), dim3(1), 0, s, j.ma, d_items, d_start, j.pl.n_tiles, d_counter);
+    const int variant = variant_of(c->m.response, c->g.nch);
+    const bool mixed = prec == SCS_PREC_MIXED;
+    const int per_cu = main_multi_blocks_per_cu(variant, c->L, j.pl.waves, mixed);
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(j.pl.n_tiles, (int64_t)c->n_cu * per_cu));
+    hipError_t e = launch_main_multi(d_items, d_start, 1, d_counter, variant, c->L, j.pl.waves, mixed, (int)grid, s);
+    if (e != hipSuccess) return fail(SCS_EDEVICE, "generate-and-reduce launch failed: %s", hipGetErrorString(e));
+    launch_finalize(j.fa, s);
+    e = hipGetLastError();
+    if (e != hipSuccess) return fail(SCS_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    c->last_stream = s;
     return SCS_OK;
 }
 
