@@ -14,6 +14,11 @@
  * (long double, 64-bit mantissa): the phase reaches ~1e6-1e7 cycles, so
  * double would leave ~1e-9 rad of rounding in every bin, which is the size of
  * the parity tolerance itself.  Segment sums accumulate in long double.
+ * The sparse-grid template's node phases and their spline are evaluated in
+ * quad precision (__float128): a not-a-knot spline whose end interval is a
+ * few bins long multiplies the rounding of the node values by up to ~S/h
+ * there (S the node stride, h the end interval), which in extended precision
+ * would reach ~1e-10 cycles.
  *
  * Definitions (paper section / equation in brackets):
  *   inner product          <a|b> = sum_alpha 4 Re sum_k df a b* / S      [Sec 2.1, eqn:inner_prod]
@@ -44,6 +49,7 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <quadmath.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -52,6 +58,7 @@
 #endif
 
 typedef long double ld;
+typedef __float128 qd; /* quad precision: the node phases of the sparse-grid template */
 
 /* ---- physical constants (SI) ---------------------------------------- */
 #define GM_SUN_SI 1.32712440018e20L /* m^3 s^-2, IAU nominal solar mass parameter */
@@ -187,6 +194,35 @@ static ld phase_cycles(const src_t* s, ld f)
 {
     const ld v = cbrtl(s->piM * f);
     return f * s->tc - 0.125L + s->pref * pn_series(s, v);
+}
+
+/* The same phase in quad precision (the coefficients as computed above,
+ * every operation on them in __float128), for the sparse-grid nodes. */
+static qd pn_series_q(const src_t* s, qd v)
+{
+    const qd lnv = logq(v);
+    qd vp[8];
+    vp[0] = 1.0Q;
+    for (int j = 1; j < 8; ++j) vp[j] = vp[j - 1] * v;
+    qd sum = 0.0Q;
+    for (int j = 0; j <= s->order; ++j) {
+        qd c;
+        if (j == 5)
+            c = (qd)s->a5 * (1.0Q + 3.0Q * (lnv + 0.5Q * logq(6.0Q)));
+        else if (j == 6)
+            c = (qd)s->psi[6] + (qd)s->b6log * (logq(4.0Q) + lnv);
+        else
+            c = (qd)s->psi[j];
+        sum += c * vp[j];
+    }
+    if (s->ecc != 0.0L) sum += (qd)s->ecc * powq(v, -19.0Q / 3.0Q);
+    return sum / vp[5];
+}
+
+static qd phase_cycles_q(const src_t* s, qd f)
+{
+    const qd v = cbrtq((qd)s->piM * f);
+    return f * (qd)s->tc - 0.125Q + (qd)s->pref * pn_series_q(s, v);
 }
 
 /* SPA time t(f) = (1/2pi) dPsi/df [s]. */
@@ -449,40 +485,102 @@ static int template_bin(const src_t* s, const orc_model* m, const orc_grid* g, i
  *   - the equal-[h|h] segment edges keep the template's exact weights at
  *     their own nodes (Sec 2.2's rule does not depend on how the template is
  *     evaluated on the dense grid).
- * Node values are computed in extended precision like the exact template. */
+ * Node phases and their spline are taken in quad precision (see the file
+ * header), the response parts in extended precision like the exact template. */
 typedef struct {
     int64_t n;  /* intervals: nodes x[0..n] */
-    int nq;     /* quantities: the phase, then re / im of each response channel */
+    int nr;     /* response quantities: re / im of each response channel (0 without response) */
     int64_t* x; /* [n + 1] node bins */
-    ld* y;      /* [n + 1][nq] node values (phase unreduced, in cycles) */
-    ld* M;      /* [n + 1][nq] second derivatives of the spline at the nodes */
+    qd* yph;    /* [n + 1] node phases (cycles, unreduced) */
+    qd* Mph;    /* [n + 1] second derivatives of the phase spline at the nodes */
+    ld* y;      /* [n + 1][nr] node values of the response parts */
+    ld* M;      /* [n + 1][nr] second derivatives of their splines */
 } sparse_spline;
 
-/* Values at bin k of the spline's quantities: the template phase (cycles,
- * GW + Doppler) and the response's real / imaginary parts per channel. */
-static int exact_quantities(const src_t* s, const orc_model* m, const orc_grid* g, int64_t k, ld* q)
+/* Exact values at bin k of the spline's quantities: the template phase in
+ * cycles (GW + Doppler), in quad precision, and the response's real and
+ * imaginary parts per channel in r[].  Returns the number of response parts. */
+static int exact_quantities(const src_t* s, const orc_model* m, const orc_grid* g, int64_t k, qd* phase, ld* r)
 {
     const ld f = freq(g, k);
-    q[0] = phase_cycles(s, f);
-    if (m->response == 0) return 1;
+    const qd fq = (qd)(g->k0 + k) * (qd)g->df;
+    *phase = phase_cycles_q(s, fq);
+    if (m->response == 0) return 0;
     const double t = (double)spa_time(s, f);
-    q[0] += (ld)doppler_cycles(s, m, (double)f, t);
+    *phase += (qd)doppler_cycles(s, m, (double)f, t);
     if (m->response == 2) {
         double complex R[3];
         fd_transfer(s, m, (double)f, t, g->n_chan, R);
         for (int a = 0; a < g->n_chan; ++a) {
-            q[1 + 2 * a] = creal(R[a]);
-            q[2 + 2 * a] = cimag(R[a]);
+            r[2 * a] = creal(R[a]);
+            r[2 * a + 1] = cimag(R[a]);
         }
-        return 1 + 2 * g->n_chan;
+        return 2 * g->n_chan;
     }
     double F[2][2];
     antenna(s, m, t, F);
     for (int a = 0; a < 2; ++a) {
-        q[1 + 2 * a] = F[a][0] * s->a_plus;   /* R = F+ A+ - i Fx Ax */
-        q[2 + 2 * a] = -F[a][1] * s->a_cross;
+        r[2 * a] = F[a][0] * s->a_plus;   /* R = F+ A+ - i Fx Ax */
+        r[2 * a + 1] = -F[a][1] * s->a_cross;
     }
-    return 5;
+    return 4;
+}
+
+/* Second derivatives M[0..N] of the not-a-knot cubic spline through
+ * (x[j], y[j]), j = 0..N (N >= 1 intervals), in quad precision.
+ * Continuity of the first derivative at interior nodes i = 1..N-1:
+ *   h[i-1] M[i-1] + 2 (h[i-1] + h[i]) M[i] + h[i] M[i+1] = 6 (s[i] - s[i-1]),
+ * s[i] = (y[i+1] - y[i]) / h[i]; not-a-knot at both ends:
+ *   (M[1] - M[0]) / h[0] = (M[2] - M[1]) / h[1],
+ *   (M[N-1] - M[N-2]) / h[N-2] = (M[N] - M[N-1]) / h[N-1].
+ * M[0] and M[N] are eliminated from the first and last interior rows,
+ * leaving a tridiagonal system in M[1..N-1] (Thomas algorithm).  With two
+ * intervals the spline is the parabola through the three nodes, with one the
+ * line (M = 0). */
+static void spline_second_derivatives(int64_t N, const int64_t* x, const qd* y, qd* M)
+{
+    for (int64_t j = 0; j <= N; ++j) M[j] = 0.0Q;
+    if (N < 2) return;
+    qd* h = (qd*)malloc(sizeof(qd) * N);
+    for (int64_t j = 0; j < N; ++j) h[j] = (qd)(x[j + 1] - x[j]);
+    if (N == 2) {
+        const qd s0 = (y[1] - y[0]) / h[0], s1 = (y[2] - y[1]) / h[1];
+        M[0] = M[1] = M[2] = 2.0Q * (s1 - s0) / (h[0] + h[1]);
+        free(h);
+        return;
+    }
+    const int64_t R = N - 1;
+    qd* a = (qd*)malloc(sizeof(qd) * R);
+    qd* b = (qd*)malloc(sizeof(qd) * R);
+    qd* cc = (qd*)malloc(sizeof(qd) * R);
+    qd* r = (qd*)malloc(sizeof(qd) * R);
+    for (int64_t i = 1; i <= R; ++i) {
+        const qd sl = (y[i] - y[i - 1]) / h[i - 1], sr = (y[i + 1] - y[i]) / h[i];
+        a[i - 1] = h[i - 1];
+        b[i - 1] = 2.0Q * (h[i - 1] + h[i]);
+        cc[i - 1] = h[i];
+        r[i - 1] = 6.0Q * (sr - sl);
+    }
+    /* M[0] = ((h0 + h1) M[1] - h0 M[2]) / h1 into row 1 */
+    b[0] += h[0] * (h[0] + h[1]) / h[1];
+    cc[0] -= h[0] * h[0] / h[1];
+    /* M[N] = ((h[N-2] + h[N-1]) M[N-1] - h[N-1] M[N-2]) / h[N-2] into row N-1 */
+    b[R - 1] += h[N - 1] * (h[N - 2] + h[N - 1]) / h[N - 2];
+    a[R - 1] -= h[N - 1] * h[N - 1] / h[N - 2];
+    for (int64_t i = 1; i < R; ++i) {
+        const qd w = a[i] / b[i - 1];
+        b[i] -= w * cc[i - 1];
+        r[i] -= w * r[i - 1];
+    }
+    M[R] = r[R - 1] / b[R - 1];
+    for (int64_t i = R - 1; i >= 1; --i) M[i] = (r[i - 1] - cc[i - 1] * M[i + 1]) / b[i - 1];
+    M[0] = ((h[0] + h[1]) * M[1] - h[0] * M[2]) / h[1];
+    M[N] = ((h[N - 2] + h[N - 1]) * M[N - 1] - h[N - 1] * M[N - 2]) / h[N - 2];
+    free(a);
+    free(b);
+    free(cc);
+    free(r);
+    free(h);
 }
 
 /* Node bins over [klo, khi): klo, the multiples of S strictly inside, khi - 1. */
@@ -497,90 +595,49 @@ static void sparse_build(const src_t* s, const orc_model* m, const orc_grid* g, 
     if (khi - 1 > klo) x[n++] = khi - 1;
     sp->n = n - 1;
     sp->x = x;
-    ld q[7];
-    sp->nq = exact_quantities(s, m, g, klo, q);
-    const int nq = sp->nq;
-    sp->y = (ld*)malloc(sizeof(ld) * n * nq);
-    sp->M = (ld*)calloc((size_t)(n * nq), sizeof(ld));
+    qd ph;
+    ld r[6];
+    sp->nr = exact_quantities(s, m, g, klo, &ph, r);
+    const int nr = sp->nr;
+    sp->yph = (qd*)malloc(sizeof(qd) * n);
+    sp->Mph = (qd*)malloc(sizeof(qd) * n);
+    sp->y = (ld*)malloc(sizeof(ld) * n * (nr > 0 ? nr : 1));
+    sp->M = (ld*)malloc(sizeof(ld) * n * (nr > 0 ? nr : 1));
     for (int64_t j = 0; j < n; ++j) {
-        exact_quantities(s, m, g, x[j], q);
-        for (int c = 0; c < nq; ++c) sp->y[j * nq + c] = q[c];
+        exact_quantities(s, m, g, x[j], &sp->yph[j], r);
+        for (int c = 0; c < nr; ++c) sp->y[j * nr + c] = r[c];
     }
-    const int64_t N = sp->n; /* intervals */
-    if (N < 2) return;       /* one node (constant) or two (the line): M = 0 */
-    ld* h = (ld*)malloc(sizeof(ld) * N);
-    for (int64_t j = 0; j < N; ++j) h[j] = (ld)(x[j + 1] - x[j]);
-    for (int c = 0; c < nq; ++c) {
-        ld* y = sp->y + c;
-        ld* M = sp->M + c;
-#define Y(j) y[(int64_t)(j) * nq]
-#define MM(j) M[(int64_t)(j) * nq]
-        if (N == 2) { /* the parabola through the three nodes */
-            const ld s0 = (Y(1) - Y(0)) / h[0], s1 = (Y(2) - Y(1)) / h[1];
-            const ld v = 2.0L * (s1 - s0) / (h[0] + h[1]);
-            MM(0) = MM(1) = MM(2) = v;
-            continue;
-        }
-        /* Continuity of the first derivative at interior nodes i = 1..N-1:
-         *   h[i-1] M[i-1] + 2 (h[i-1] + h[i]) M[i] + h[i] M[i+1] = 6 (s[i] - s[i-1]),
-         * s[i] = (y[i+1] - y[i]) / h[i]; not-a-knot at both ends:
-         *   (M[1] - M[0]) / h[0] = (M[2] - M[1]) / h[1],
-         *   (M[N-1] - M[N-2]) / h[N-2] = (M[N] - M[N-1]) / h[N-1].
-         * M[0] and M[N] are eliminated from the first and last interior rows,
-         * leaving a tridiagonal system in M[1..N-1] (Thomas algorithm). */
-        const int64_t R = N - 1;
-        ld* a = (ld*)malloc(sizeof(ld) * R);
-        ld* b = (ld*)malloc(sizeof(ld) * R);
-        ld* cc = (ld*)malloc(sizeof(ld) * R);
-        ld* r = (ld*)malloc(sizeof(ld) * R);
-        for (int64_t i = 1; i <= R; ++i) {
-            const ld sl = (Y(i) - Y(i - 1)) / h[i - 1], sr = (Y(i + 1) - Y(i)) / h[i];
-            a[i - 1] = h[i - 1];
-            b[i - 1] = 2.0L * (h[i - 1] + h[i]);
-            cc[i - 1] = h[i];
-            r[i - 1] = 6.0L * (sr - sl);
-        }
-        /* M[0] = ((h0 + h1) M[1] - h0 M[2]) / h1 into row 1 */
-        b[0] += h[0] * (h[0] + h[1]) / h[1];
-        cc[0] -= h[0] * h[0] / h[1];
-        /* M[N] = ((h[N-2] + h[N-1]) M[N-1] - h[N-1] M[N-2]) / h[N-2] into row N-1 */
-        b[R - 1] += h[N - 1] * (h[N - 2] + h[N - 1]) / h[N - 2];
-        a[R - 1] -= h[N - 1] * h[N - 1] / h[N - 2];
-        for (int64_t i = 1; i < R; ++i) {
-            const ld w = a[i] / b[i - 1];
-            b[i] -= w * cc[i - 1];
-            r[i] -= w * r[i - 1];
-        }
-        MM(R) = r[R - 1] / b[R - 1];
-        for (int64_t i = R - 1; i >= 1; --i) MM(i) = (r[i - 1] - cc[i - 1] * MM(i + 1)) / b[i - 1];
-        MM(0) = ((h[0] + h[1]) * MM(1) - h[0] * MM(2)) / h[1];
-        MM(N) = ((h[N - 2] + h[N - 1]) * MM(N - 1) - h[N - 1] * MM(N - 2)) / h[N - 2];
-        free(a);
-        free(b);
-        free(cc);
-        free(r);
-#undef Y
-#undef MM
+    spline_second_derivatives(sp->n, x, sp->yph, sp->Mph);
+    qd* yc = (qd*)malloc(sizeof(qd) * n);
+    qd* Mc = (qd*)malloc(sizeof(qd) * n);
+    for (int c = 0; c < nr; ++c) {
+        for (int64_t j = 0; j < n; ++j) yc[j] = (qd)sp->y[j * nr + c];
+        spline_second_derivatives(sp->n, x, yc, Mc);
+        for (int64_t j = 0; j < n; ++j) sp->M[j * nr + c] = (ld)Mc[j];
     }
-    free(h);
+    free(yc);
+    free(Mc);
 }
 
 static void sparse_free(sparse_spline* sp)
 {
     free(sp->x);
+    free(sp->yph);
+    free(sp->Mph);
     free(sp->y);
     free(sp->M);
 }
 
 /* The spline's quantities at bin k (inside [x0, xn]): on interval j,
  * S(u) = y_j + b u + (M_j / 2) u^2 + (M_{j+1} - M_j) / (6 h) u^3, u = k - x_j,
- * b = (y_{j+1} - y_j) / h - h (2 M_j + M_{j+1}) / 6. */
-static void sparse_eval(const sparse_spline* sp, int64_t k, ld* q)
+ * b = (y_{j+1} - y_j) / h - h (2 M_j + M_{j+1}) / 6.  The phase comes back
+ * reduced to [0, 1) cycles (taken in quad precision), the response parts in r[]. */
+static double sparse_eval(const sparse_spline* sp, int64_t k, ld* r)
 {
-    const int nq = sp->nq;
+    const int nr = sp->nr;
     if (sp->n == 0) {
-        for (int c = 0; c < nq; ++c) q[c] = sp->y[c];
-        return;
+        for (int c = 0; c < nr; ++c) r[c] = sp->y[c];
+        return (double)(sp->yph[0] - floorq(sp->yph[0]));
     }
     int64_t lo = 0, hi = sp->n - 1; /* interval: the last j <= n-1 with x_j <= k */
     while (lo < hi) {
@@ -588,12 +645,20 @@ static void sparse_eval(const sparse_spline* sp, int64_t k, ld* q)
         if (sp->x[mid] <= k) lo = mid; else hi = mid - 1;
     }
     const int64_t j = lo;
-    const ld h = (ld)(sp->x[j + 1] - sp->x[j]), u = (ld)(k - sp->x[j]);
-    for (int c = 0; c < nq; ++c) {
-        const ld y0 = sp->y[j * nq + c], y1 = sp->y[(j + 1) * nq + c];
-        const ld M0 = sp->M[j * nq + c], M1 = sp->M[(j + 1) * nq + c];
-        const ld b = (y1 - y0) / h - h * (2.0L * M0 + M1) / 6.0L;
-        q[c] = y0 + u * (b + u * (0.5L * M0 + u * (M1 - M0) / (6.0L * h)));
+    const int64_t hb = sp->x[j + 1] - sp->x[j], ub = k - sp->x[j];
+    {
+        const qd h = (qd)hb, u = (qd)ub;
+        const qd y0 = sp->yph[j], y1 = sp->yph[j + 1], M0 = sp->Mph[j], M1 = sp->Mph[j + 1];
+        const qd b = (y1 - y0) / h - h * (2.0Q * M0 + M1) / 6.0Q;
+        const qd q = y0 + u * (b + u * (0.5Q * M0 + u * (M1 - M0) / (6.0Q * h)));
+        for (int c = 0; c < nr; ++c) {
+            const ld hl = (ld)hb, ul = (ld)ub;
+            const ld z0 = sp->y[j * nr + c], z1 = sp->y[(j + 1) * nr + c];
+            const ld N0 = sp->M[j * nr + c], N1 = sp->M[(j + 1) * nr + c];
+            const ld bb = (z1 - z0) / hl - hl * (2.0L * N0 + N1) / 6.0L;
+            r[c] = z0 + ul * (bb + ul * (0.5L * N0 + ul * (N1 - N0) / (6.0L * hl)));
+        }
+        return (double)(q - floorq(q));
     }
 }
 
@@ -602,20 +667,19 @@ static void sparse_eval(const sparse_spline* sp, int64_t k, ld* q)
 static int sparse_template_bin(const sparse_spline* sp, const orc_model* m, const orc_grid* g, int64_t k,
                                double hre[3], double him[3])
 {
-    ld q[7];
-    sparse_eval(sp, k, q);
+    ld r[6];
+    const double tot = sparse_eval(sp, k, r);
     const ld f = freq(g, k);
     const double amp = (double)powl(f, -7.0L / 6.0L);
-    const double tot = (double)(q[0] - floorl(q[0])); /* reduce before leaving extended precision */
     const double c = cos(2.0 * M_PI * tot), sn = sin(2.0 * M_PI * tot);
     if (m->response == 0) {
         hre[0] = amp * c;
         him[0] = -amp * sn;
         return 1;
     }
-    const int nc = (sp->nq - 1) / 2;
+    const int nc = sp->nr / 2;
     for (int a = 0; a < nc; ++a) {
-        const double rr = (double)q[1 + 2 * a], ri = (double)q[2 + 2 * a];
+        const double rr = (double)r[2 * a], ri = (double)r[2 * a + 1];
         hre[a] = amp * (rr * c + ri * sn);
         him[a] = amp * (ri * c - rr * sn);
     }

@@ -107,7 +107,9 @@ def test_sparse_template_is_the_not_a_knot_spline(S):
         # the same spline to scipy's float64 arithmetic (other end conditions,
         # natural or clamped, differ by orders of magnitude more near the ends)
         assert err < 1e-9
-        assert at_nodes < 1e-12    # a spline passes through its nodes
+        # a spline passes through its nodes: the node phases are quad precision,
+        # the per-bin template's extended precision (~1e-13 cycles at ~1e6)
+        assert at_nodes < 5e-12
         assert between > 1e3 * at_nodes or S == 128  # interpolation, not evaluation
 
 
@@ -163,3 +165,80 @@ def test_sparse_small_supports():
         assert len(x) == n_nodes
         assert np.array_equal(np.abs(got) > 0, nz)
         assert np.abs(got - want).max() <= 1e-9 * np.abs(want).max()
+
+
+def test_sparse_phase_spline_precision_at_a_one_bin_end_interval():
+    """Rounding of the node phases, multiplied by a short end interval.  With
+    nodes every S bins and a support that ends one bin after the last
+    multiple of S, the not-a-knot condition ties the last two intervals, and
+    an error e in a node phase moves the spline next to it by ~0.75 S e.  The
+    phase spline here is rebuilt in 40-digit arithmetic (node phases from the
+    2PN series, the not-a-knot system solved densely by mpmath), and the
+    oracle's sparse-grid template must carry the same interpolation error
+    (spline minus exact phase) at every bin to 5e-12 cycles; node phases
+    rounded at ~2e-13 cycles (extended precision at ~4e6 cycles) would miss it
+    by more than an order of magnitude next to the short interval."""
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 40
+    S = 1024
+    K = 4 * S + 2  # nodes 0, S, 2S, 3S, 4S and K - 1 = 4S + 1: the last interval is one bin
+    # the 2^20-bin grid's bin width, from 0.018 Hz (where the interpolation
+    # error of the phase is ~1e-7 cycles, so that its difference is a phase)
+    spec = synth.GridSpec(1 << 20)
+    k0 = int(round(0.018 / spec.df))
+    grid = O.Grid(K, k0, spec.df, 1)
+    t_obs = 1.0 / spec.df
+    model = O.Model(pn_order=4, response=O.RESP_NONE, support=O.SUPPORT_FULL, t_obs=t_obs, sparse_stride=S)
+    th = np.array([28.0, float(synth.eta_from_q(0.8)), k0 * spec.df, 0, 0, 0, 0])
+    eta, mc = mp.mpf(th[1]), mp.mpf(th[0])
+    tsun = mp.mpf("1.32712440018e20") / mp.mpf(299792458) ** 3
+    piM = mp.pi * mc * eta ** mp.mpf("-0.6") * tsun
+    pref = 3 / (256 * mp.pi * eta)
+    psi2 = mp.mpf(3715) / 756 + 55 * eta / 9
+    psi3 = -16 * mp.pi
+    psi4 = mp.mpf(15293365) / 508032 + 27145 * eta / 504 + 3085 * eta ** 2 / 72
+
+    def series(v):
+        return (1 + psi2 * v ** 2 + psi3 * v ** 3 + psi4 * v ** 4) / v ** 5
+
+    def dseries(v):  # f d/df of the series, dv/df = v / (3 f)
+        return (-5 + -3 * psi2 * v ** 2 - 2 * psi3 * v ** 3 - psi4 * v ** 4) / v ** 5 / 3
+
+    fl = mp.mpf(k0) * mp.mpf(spec.df)
+    tc = -pref * dseries(mp.cbrt(piM * fl)) / fl
+
+    def phase(k):
+        f = mp.mpf(int(k0 + k)) * mp.mpf(spec.df)
+        return f * tc - mp.mpf(1) / 8 + pref * series(mp.cbrt(piM * f))
+
+    x = _nodes(0, K, S)
+    assert list(x) == [0, S, 2 * S, 3 * S, 4 * S, K - 1]
+    y = [phase(int(k)) for k in x]
+    n = len(x) - 1
+    h = [mp.mpf(int(x[j + 1] - x[j])) for j in range(n)]
+    # unknowns M_0 .. M_n: n - 1 continuity rows and two not-a-knot rows
+    A = mp.zeros(n + 1, n + 1)
+    r = mp.zeros(n + 1, 1)
+    for i in range(1, n):
+        A[i, i - 1], A[i, i], A[i, i + 1] = h[i - 1], 2 * (h[i - 1] + h[i]), h[i]
+        r[i] = 6 * ((y[i + 1] - y[i]) / h[i] - (y[i] - y[i - 1]) / h[i - 1])
+    A[0, 0], A[0, 1], A[0, 2] = -1 / h[0], 1 / h[0] + 1 / h[1], -1 / h[1]
+    A[n, n - 2], A[n, n - 1], A[n, n] = -1 / h[n - 2], 1 / h[n - 2] + 1 / h[n - 1], -1 / h[n - 1]
+    M = mp.lu_solve(A, r)
+    # compared: the interpolation error (spline minus exact phase) of the
+    # oracle and of the 40-digit rebuild, so that the oracle's own t_c (a
+    # phase linear in f, which any spline reproduces) drops out
+    sp = O.template(grid, model, th)[0]
+    ex = O.template(grid, O.Model(pn_order=4, response=O.RESP_NONE, support=O.SUPPORT_FULL, t_obs=t_obs), th)[0]
+    got = np.angle(sp / ex) / (2 * math.pi)  # spline minus exact phase, cycles (the template is e^{-2 pi i phase})
+    got = -got
+    worst = 0.0
+    for k in range(K):
+        j = min(int(np.searchsorted(x, k, side="right")) - 1, n - 1)
+        u, hj = mp.mpf(int(k - x[j])), h[j]
+        b = (y[j + 1] - y[j]) / hj - hj * (2 * M[j] + M[j + 1]) / 6
+        q = y[j] + u * (b + u * (M[j] / 2 + u * (M[j + 1] - M[j]) / (6 * hj)))
+        worst = max(worst, abs(float(q - phase(k)) - got[k]))
+    print(f"one-bin end interval, S = {S}: interpolation error of the sparse-grid phase against the 40-digit "
+          f"spline's, max difference {worst:.3g} cycles")
+    assert worst < 5e-12
