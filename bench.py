@@ -38,6 +38,9 @@ import synth  # noqa: E402
 # a few percent more per in-support evaluation: lanes idle at support edges
 # and the per-block set-up).
 FLOP_PER_EVAL_FP64 = 98
+# The same with the sparse-grid template (cubic splines): the phase and the
+# four response polynomials are cubic instead of quintic, 2 + 8 FMA fewer.
+FLOP_PER_EVAL_FP64_SPLINE = 78
 PEAK_FP64_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 64 lanes x 2
 # FP32 operations per in-support particle-bin of the mixed-precision
 # generate-and-reduce kernel, two channels, from its per-bin op list (same
@@ -147,6 +150,9 @@ def main():
                     help="step: skip the short batched, served and 16384-bin legs of the default run")
     ap.add_argument("--tune-cache", type=str, default=None,
                     help="batched: autotuner cache file (read, then rewritten)")
+    ap.add_argument("--sparse-stride", type=int, default=0,
+                    help="step: evaluate the template on the sparse grid of Sec 4 (nodes every this many bins, "
+                         "cubic splines onto every bin) instead of per bin; the paper's stride is 1000")
     args = ap.parse_args()
     if args.copy_probe_mib:
         import torch
@@ -182,7 +188,8 @@ def main():
     fd = args.response in ("fd", "fd3")
     psd = bench_psd(w, args.response)
     # --- data: noise + injection made with the library's own FP64 template
-    ctx, d_ri = make_search(B, torch, w, dev, args.response)
+    ctx, d_ri = make_search(B, torch, w, dev, args.response, args.sparse_stride)
+    resp = B.SCS_RESP_LISA_LF_AE if args.response == "lf" else B.SCS_RESP_LISA_FD_AE
     # --- swarm of 10^4 particles, first rung of the ladder (Table tab:PSO_hyperparams, N = 100 row)
     eps = [0.1, 0.05, 5e-8, 0.1, 0.1, 0.2, 0.1]  # Mc, eta, f_low, lambda, beta, iota, psi
     prm = B.pso_params(0.5, 0.2, 0.3, eps)
@@ -260,7 +267,8 @@ def main():
     ms_step = 1e3 * r64["wall_s"] / args.steps
     avg_main_ms = r64["main_ms"] / max(r64["main_launches"], 1)
     evals_per_launch = r64["evals"] / max(r64["main_launches"], 1)
-    achieved = evals_per_launch * FLOP_PER_EVAL_FP64 / (avg_main_ms * 1e-3) / 1e12
+    flop64 = FLOP_PER_EVAL_FP64_SPLINE if args.sparse_stride else FLOP_PER_EVAL_FP64
+    achieved = evals_per_launch * flop64 / (avg_main_ms * 1e-3) / 1e12
     out = {
         "metric": "particle x freq-bin statistic evals/s (in-support), FP64; p50/p99 step latency; mixed vs FP64",
         "value": value,
@@ -278,15 +286,18 @@ def main():
                                "node stride 1024), 10^4 PSO particles in the GW150914-like prior box, one PSO "
                                "iteration per step", "particles": w.P, "bins": K, "N_seg": w.N,
                    "response": {"lf": "low-frequency A/E", "fd": "full frequency-domain TDI A/E (finite arm length)",
-                                "fd3": "full frequency-domain TDI A/E/T (finite arm length)"}[args.response]},
+                                "fd3": "full frequency-domain TDI A/E/T (finite arm length)"}[args.response],
+                   "template": (f"sparse grid, nodes every {args.sparse_stride} bins, cubic splines"
+                                if args.sparse_stride else "per bin (block polynomials)")},
         "latency_ms": {"p50": float(np.median(r64["step_ms"])), "p99": float(np.quantile(r64["step_ms"], 0.99))},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None if fd else measured_traffic(),
+                     "frac": achieved / PEAK_FP64_TFLOPS,
+                     "traffic": None if (fd or args.sparse_stride) else measured_traffic(),
                      "kernel": {"lf": "k_main_multi<2,false,1> (FP64 generate-and-reduce, low-frequency response)",
                                 "fd": "k_main_multi<2,false,2> (FP64 generate-and-reduce, full response)",
                                 "fd3": "k_main_multi<3,false,2> (FP64 generate-and-reduce, full response, A+E+T)"}[
-                         args.response],
-                     "avg_launch_ms": avg_main_ms, "flop_per_eval": FLOP_PER_EVAL_FP64,
+                         args.response] + (", sparse-grid template" if args.sparse_stride else ""),
+                     "avg_launch_ms": avg_main_ms, "flop_per_eval": flop64,
                      "evals_per_launch": evals_per_launch},
         "unresolved_particles": r64["unresolved"],
         "likelihood_epilogue": epi,
@@ -300,7 +311,8 @@ def main():
                         "roofline": {"bound": "alu", "achieved": mx_achieved, "peak": PEAK_FP32_TFLOPS,
                                      "unit": "TFLOP/s", "frac": mx_achieved / PEAK_FP32_TFLOPS,
                                      "frac_of_nonpacked_fp32": mx_achieved / PEAK_FP32_NONPACKED_TFLOPS,
-                                     "traffic": None if fd else measured_traffic(MIXED_PROFILE),
+                                     "traffic": None if (fd or args.sparse_stride)
+                                     else measured_traffic(MIXED_PROFILE),
                                      "kernel": {"lf": "k_main_multi<2,true,1>", "fd": "k_main_multi<2,true,2>",
                                                 "fd3": "k_main_multi<3,true,2>"}[args.response]
                                      + " (mixed-precision generate-and-reduce)",
@@ -318,6 +330,8 @@ def main():
                         "err_vs_fp64": {"median": float(np.median(err)), "p99": float(np.quantile(err, 0.99)),
                                         "max": float(err.max()),
                                         "measure": "|U_mixed - U_fp64| / max(U_fp64, 2 N_eff)"}}
+    if not args.no_legs and not args.sparse_stride:
+        out["sparse_template"] = leg_sparse(B, ctx, w, resp, run, th, a, neff, args.no_mixed)
     if not args.no_legs:
         out["config1"] = leg_config1(B, torch, dev)
         out["batched"] = bench_batched_core(B, torch, dev, steps=5, warmup=2, tune_cache=args.tune_cache)
@@ -336,10 +350,11 @@ def bench_psd(w, response="lf"):
     return synth.lisa_tdi_psd(w.grid.freqs())[:3 if response == "fd3" else 2]
 
 
-def make_search(B, torch, w, dev, response="lf"):
+def make_search(B, torch, w, dev, response="lf", sparse_stride=0):
     """Context with seeded noise plus the injection of workload w at its SNR
-    (template from the library's own FP64 waveform kernel); response selects
-    the low-frequency or the full frequency-domain response (A+E or A+E+T)."""
+    (template from the library's own FP64 per-bin waveform kernel); response
+    selects the low-frequency or the full frequency-domain response (A+E or
+    A+E+T); sparse_stride > 0 makes the context's template the sparse-grid one."""
     K, df, f_min = w.grid.K, w.grid.df, w.grid.f_min
     psd = bench_psd(w, response)
     nch = psd.shape[0]
@@ -357,7 +372,7 @@ def make_search(B, torch, w, dev, response="lf"):
     d = torch.tensor(noise, device=dev) + hc * (w.snr / math.sqrt(hh))
     d_ri = torch.stack([d.real, d.imag], -1).contiguous()
     B.scs_load_data(ctx, d_ri, S.contiguous(), f_min, df)
-    B.scs_set_model(ctx, w.pn_order, resp, B.SCS_SUPPORT_TOBS, w.grid.t_obs)
+    B.scs_set_model(ctx, w.pn_order, resp, B.SCS_SUPPORT_TOBS, w.grid.t_obs, sparse_stride=sparse_stride)
     B.scs_define_segmentation(ctx, w.N, B.SCS_SEG_EQUAL_SNR, w.G)
     return ctx, d_ri
 
@@ -453,6 +468,36 @@ def bench_batched_core(B, torch, dev, steps, warmup, tune_cache=None):
     res["workload"] = ("six swarms (N, P) = " + str(synth.LADDER_SWARMS) + " on the 2^20-bin A+E data, one HIP "
                        "graph per precision, one persistent fused generate-and-reduce launch, autotuned shapes")
     return res
+
+
+def leg_sparse(B, ctx, w, resp, run, th, ups_per_bin, neff, no_mixed, stride=1000, steps=10, warmup=2):
+    """The step workload with the paper's sparse-grid template (Sec 4: nodes
+    every 1000 bins, cubic splines onto every bin) on the same context: PSO
+    steps in FP64 and mixed, and on the fixed swarm how far Upsilon_N moves
+    from the per-bin template's (the interpolation's effect, second order)."""
+    import torch
+
+    B.scs_set_model(ctx, w.pn_order, resp, B.SCS_SUPPORT_TOBS, w.grid.t_obs, sparse_stride=stride)
+    out = {"stride": stride, "flop_per_eval_fp64": FLOP_PER_EVAL_FP64_SPLINE}
+    for prec, name in ((B.SCS_PREC_FP64, "fp64"), (B.SCS_PREC_MIXED, "mixed")):
+        if no_mixed and prec == B.SCS_PREC_MIXED:
+            continue
+        r = run(prec, steps, warmup, 101)
+        launch_ms = r["main_ms"] / max(r["main_launches"], 1)
+        out[name] = {"value": r["evals"] / r["wall_s"], "unit": "evals/s",
+                     "ms_per_step": 1e3 * r["wall_s"] / steps, "avg_main_launch_ms": launch_ms,
+                     "latency_ms": {"p50": float(np.median(r["step_ms"])),
+                                    "p99": float(np.quantile(r["step_ms"], 0.99))}}
+        log(f"sparse-grid template {name}: {out[name]['value']:.4g} evals/s, main kernel {launch_ms:.3f} ms/launch")
+    u = torch.empty(th.shape[0], dtype=torch.float64, device=th.device)
+    B.scs_evaluate(ctx, th, u, B.SCS_PREC_FP64)
+    torch.cuda.synchronize()
+    us = u.cpu().numpy()
+    ok = np.isfinite(ups_per_bin) & np.isfinite(us)
+    dif = floored_err(us[ok], ups_per_bin[ok], neff[ok])
+    out["ups_vs_per_bin_template"] = {"median": float(np.median(dif)), "max": float(dif.max()),
+                                      "measure": "|U_sparse - U_per_bin| / max(U_per_bin, 2 N_eff), FP64"}
+    return out
 
 
 def leg_config1(B, torch, dev, reps=50):

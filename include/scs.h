@@ -95,7 +95,19 @@ typedef struct scs_model {
                                 leading order in e0^2: the Newtonian term times
                                 1 - (2355/1462) e0^2 (f_low / f)^(19/9), e0 the 8th theta
                                 entry; 0: circular, 7 entries */
-    int32_t pad;
+    int32_t sparse_stride;   /* 0: the template is evaluated at every bin (per-block polynomials
+                                with remainders below 1e-12 cycles); S in 1..65536: the sparse-grid
+                                evaluation of Sec 4 (waveform and response paragraphs): the
+                                template phase (GW and Doppler terms, in cycles) and the real and
+                                imaginary parts of every channel's response are evaluated exactly
+                                at nodes, the first bin of the support, every multiple of S inside
+                                it and its last bin, and interpolated onto every bin by not-a-knot
+                                cubic splines (three nodes: the parabola, two: the line, one: the
+                                constant); the amplitude f^-7/6 stays exact and the equal-[h|h]
+                                edges keep the exact weights.  Needs about
+                                8 ((K + S - 1) / S + 2) (2 + 3 NR + 2) bytes of device memory per
+                                particle (NR = 0, 4, 6 for 1, 2, 3 channels; scs_footprint counts
+                                it); every theta resolves (no NaN for an unresolved theta) */
 } scs_model;
 
 /* ---- context --------------------------------------------------------- */

@@ -35,7 +35,7 @@ class ScsError(RuntimeError):
 class scs_model(C.Structure):
     _fields_ = [("pn_order", C.c_int32), ("response", C.c_int32), ("support", C.c_int32),
                 ("block_len", C.c_int32), ("t_obs", C.c_double), ("orbit_phase0", C.c_double),
-                ("cartwheel_phase0", C.c_double), ("eccentric", C.c_int32), ("pad", C.c_int32)]
+                ("cartwheel_phase0", C.c_double), ("eccentric", C.c_int32), ("sparse_stride", C.c_int32)]
 
 
 class scs_batch_item(C.Structure):
@@ -269,8 +269,9 @@ def scs_load_data(ctx, d_ri, psd, f_min, df):
 
 
 def scs_set_model(ctx, pn_order, response, support, t_obs=0.0, block_len=0, orbit_phase0=0.0,
-                  cartwheel_phase0=0.0, eccentric=0):
-    m = scs_model(pn_order, response, support, block_len, t_obs, orbit_phase0, cartwheel_phase0, eccentric, 0)
+                  cartwheel_phase0=0.0, eccentric=0, sparse_stride=0):
+    m = scs_model(pn_order, response, support, block_len, t_obs, orbit_phase0, cartwheel_phase0, eccentric,
+                  sparse_stride)
     _check(lib().scs_set_model(ctx, C.byref(m)))
 
 

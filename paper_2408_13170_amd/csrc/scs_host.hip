@@ -153,6 +153,8 @@ struct Workspace {
     int32_t* bounds = nullptr;
     double* rec = nullptr;
     double* zs = nullptr;  // [P][N][3] per-segment sums (when the caller asks for no segment output)
+    int64_t capSpl = 0;     // doubles
+    double* spl = nullptr;  // sparse-grid template: node records [capP][nmax][spl_rec]
     // host-pointer staging
     int64_t capStage = 0;
     double* stage = nullptr;
@@ -282,6 +284,7 @@ static void free_ws(Workspace& w)
     hipFree(w.bounds);
     hipFree(w.rec);
     hipFree(w.zs);
+    hipFree(w.spl);
     hipFree(w.stage);
     hipFree(w.bucket);
     hipFree(w.rank);
@@ -455,6 +458,8 @@ extern "C" int scs_set_model(scs_ctx* c, const scs_model* m)
     if (bl < 16 || bl > 2048 || (bl & (bl - 1))) return fail(SCS_EINVAL, "block_len must be a power of 2 in 16..2048");
     if (m->t_obs < 0.0 || !std::isfinite(m->t_obs)) return fail(SCS_EINVAL, "bad t_obs");
     if (m->eccentric != 0 && m->eccentric != 1) return fail(SCS_EINVAL, "eccentric must be 0 or 1");
+    if (m->sparse_stride < 0 || m->sparse_stride > kMaxSparseStride)
+        return fail(SCS_EINVAL, "sparse_stride must be 0 (template per bin) or 1..%d", kMaxSparseStride);
     c->m.pn_order = m->pn_order;
     c->m.response = m->response;
     c->m.support = m->support;
@@ -465,6 +470,7 @@ extern "C" int scs_set_model(scs_ctx* c, const scs_model* m)
     c->m.cart_c = std::cos(m->cartwheel_phase0);
     c->m.cart_s = std::sin(m->cartwheel_phase0);
     c->m.ecc = m->eccentric;
+    c->m.sparse = m->sparse_stride;
     c->L = 512;  // bins per LDS-staged block of the generate-and-reduce kernel
     int lg = 0;
     while ((1 << lg) < bl) ++lg;
@@ -558,6 +564,14 @@ static int64_t pad64(int64_t v) { return (v + 63) / 64 * 64; }
 // Swarms of at least this many particles are evaluated in support order.
 static constexpr int64_t kSortMin = 128;
 
+// Node records of the sparse-grid template for Pp particle slots (0 when the
+// template is evaluated per bin).
+static int64_t spl_doubles(const scs_ctx* c, int64_t Pp)
+{
+    if (c->m.sparse <= 0) return 0;
+    return Pp * spl_max_nodes(c->g.K, c->m.sparse) * spl_rec(c->g.nch);
+}
+
 static size_t ws_bytes(const scs_ctx* c, int64_t P, int N, const Plan& pl)
 {
     const int64_t Pp = pad64(std::max<int64_t>(P, 1));
@@ -567,6 +581,7 @@ static size_t ws_bytes(const scs_ctx* c, int64_t P, int N, const Plan& pl)
     b += sizeof(int32_t) * ((size_t)P * (N + 1) + 2);
     b += sizeof(double) * (size_t)pl.n_chunks * kRec * Pp;
     b += sizeof(double) * 3 * (size_t)P * N;
+    b += sizeof(double) * (size_t)spl_doubles(c, Pp);
     return b;
 }
 
@@ -596,6 +611,7 @@ static int ensure_ws(scs_ctx* c, Workspace& w, int64_t P, int N, const Plan& pl)
     if ((rc = grow(&w.bounds, &w.capBounds, P * (int64_t)(N + 1) + 2))) return rc;
     if ((rc = grow(&w.rec, &w.capRec, pl.n_chunks * kRec * w.capP))) return rc;
     if ((rc = grow(&w.zs, &w.capZs, 3 * P * (int64_t)N))) return rc;
+    if (c->m.sparse > 0 && (rc = grow(&w.spl, &w.capSpl, spl_doubles(c, w.capP)))) return rc;
     if (P >= kSortMin && P > w.capSort) {
         int64_t c1 = 0, c2 = 0, c3 = 0, c4 = 0;
         hipFree(w.bucket);
@@ -657,6 +673,21 @@ static int eval_front(EvalJob& j, const double* theta, double* ups, double* seg,
     pa.evals = c->counters;
     pa.unresolved = c->counters + 2;
     launch_prologue(pa, s);
+    const int64_t spl_nmax = c->m.sparse > 0 ? spl_max_nodes(c->g.K, c->m.sparse) : 0;
+    if (c->m.sparse > 0) {
+        SplineArgs sa{};
+        sa.g = c->g;
+        sa.m = c->m;
+        sa.P = P;
+        sa.stride = w.capP;
+        sa.coef = w.coef;
+        sa.klo = w.klo;
+        sa.khi = w.khi;
+        sa.lg = w.lg;
+        sa.nmax = spl_nmax;
+        sa.spl = w.spl;
+        launch_spline(sa, s);
+    }
     const int32_t* perm = nullptr;
     if (P >= kSortMin && w.perm) {
         launch_sort_perm(P, c->g.K, w.klo, w.khi, w.hist, w.bucket, w.rank, w.perm, s);
@@ -709,6 +740,8 @@ static int eval_front(EvalJob& j, const double* theta, double* ups, double* seg,
     ma.zs = seg ? seg : w.zs;
     ma.zscale32 = c->zscale32;
     ma.hscale32 = c->hscale32;
+    ma.spl = c->m.sparse > 0 ? w.spl : nullptr;
+    ma.spl_nmax = spl_nmax;
     FinalArgs& fa = j.fa;
     fa = FinalArgs{};
     fa.K = c->g.K;
@@ -853,10 +886,10 @@ __global__ void k_put_main_args(MainArgs a, MainArgs* d, int64_t* start, int64_t
 // Regions of one evaluation inside the scratch (offsets in bytes, each
 // 256-byte aligned); total = bytes needed.
 struct NoallocLayout {
-    size_t coef, klo, khi, lg, bounds, rec, zs, bucket, rank, perm, hist, items, start, counter, total;
+    size_t coef, klo, khi, lg, bounds, rec, zs, spl, bucket, rank, perm, hist, items, start, counter, total;
 };
 
-static NoallocLayout noalloc_layout(int64_t P, int N, const Plan& pl, bool own_zs)
+static NoallocLayout noalloc_layout(const scs_ctx* c, int64_t P, int N, const Plan& pl, bool own_zs)
 {
     const uint64_t Pp = (uint64_t)pad64(std::max<int64_t>(P, 1));
     NoallocLayout l{};
@@ -872,6 +905,7 @@ static NoallocLayout noalloc_layout(int64_t P, int N, const Plan& pl, bool own_z
     take(l.bounds, sizeof(int32_t) * ((uint64_t)P * (uint64_t)(N + 1) + 2));
     take(l.rec, sizeof(double) * (uint64_t)pl.n_chunks * kRec * Pp);
     take(l.zs, own_zs ? sizeof(double) * 3 * (uint64_t)P * (uint64_t)N : 0);
+    take(l.spl, sizeof(double) * (uint64_t)spl_doubles(c, (int64_t)Pp));
     const bool sorted = P >= kSortMin;
     take(l.bucket, sorted ? sizeof(int32_t) * Pp : 0);
     take(l.rank, sorted ? sizeof(int32_t) * Pp : 0);
@@ -905,7 +939,7 @@ extern "C" int scs_evaluate_noalloc(scs_ctx* c, int64_t P, const double* theta, 
     // cache is not consulted, its lookup would allocate host memory
     const TuneChoice t = c->has_override ? c->override_choice : default_choice(c, P);
     const Plan pl = make_plan(c, P, t);
-    const NoallocLayout l = noalloc_layout(P, N, pl, seg == nullptr);
+    const NoallocLayout l = noalloc_layout(c, P, N, pl, seg == nullptr);
     if (l.total > (size_t)SCS_NOALLOC_SCRATCH_BYTES)
         return fail(SCS_EINVAL, "P = %lld, N = %d on %lld bins needs %zu bytes of device scratch; "
                     "scs_evaluate_noalloc has %zu", (long long)P, N, (long long)c->g.K, l.total,
@@ -926,6 +960,8 @@ extern "C" int scs_evaluate_noalloc(scs_ctx* c, int64_t P, const double* theta, 
     w.bounds = (int32_t*)(base + l.bounds);
     w.rec = (double*)(base + l.rec);
     w.zs = seg ? nullptr : (double*)(base + l.zs);
+    w.capSpl = spl_doubles(c, Pp);
+    w.spl = w.capSpl ? (double*)(base + l.spl) : nullptr;
     if (P >= kSortMin) {
         w.capSort = Pp;
         w.bucket = (int32_t*)(base + l.bucket);
@@ -943,7 +979,7 @@ extern "C" int scs_evaluate_noalloc(scs_ctx* c, int64_t P, const double* theta, 
     int64_t* d_start = (int64_t*)(base + l.start);
     unsigned long long* d_counter = (unsigned long long*)(base + l.counter);
     hipLaunchKernelGGL(k_put_main_args, dim3(1), dim3(1), 0, s, j.ma, d_items, d_start, j.pl.n_tiles, d_counter);
-    const int variant = variant_of(c->m.response, c->g.nch);
+    const int variant = variant_of(c->m.response, c->g.nch, c->m.sparse);
     const bool mixed = prec == SCS_PREC_MIXED;
     const int per_cu = main_multi_blocks_per_cu(variant, c->L, j.pl.waves, mixed);
     const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(j.pl.n_tiles, (int64_t)c->n_cu * per_cu));
@@ -1096,6 +1132,22 @@ extern "C" int scs_waveform(scs_ctx* c, const double* theta, double* h_ri, int32
     ma.lg = w.lg;
     ma.gtab = c->gtab;
     for (int l = 0; l < kMaxLevel; ++l) ma.gtab_off[l] = c->gtab_off[l];
+    if (c->m.sparse > 0) {
+        SplineArgs sa{};
+        sa.g = c->g;
+        sa.m = c->m;
+        sa.P = 1;
+        sa.stride = w.capP;
+        sa.coef = w.coef;
+        sa.klo = w.klo;
+        sa.khi = w.khi;
+        sa.lg = w.lg;
+        sa.nmax = spl_max_nodes(c->g.K, c->m.sparse);
+        sa.spl = w.spl;
+        launch_spline(sa, s);
+        ma.spl = w.spl;
+        ma.spl_nmax = sa.nmax;
+    }
     launch_waveform(ma, dh, s);
     if (mem_kind == SCS_MEM_HOST) {
         HIP_TRY(hipMemcpyAsync(h_ri, dh, sizeof(double) * nout, hipMemcpyDeviceToHost, s));
@@ -1191,6 +1243,8 @@ extern "C" int scs_evaluate_streams(scs_ctx* c, const double* theta, int64_t R, 
     ma.lg = w.lg;
     ma.gtab = c->gtab;
     for (int l = 0; l < kMaxLevel; ++l) ma.gtab_off[l] = c->gtab_off[l];
+    ma.spl = w.spl;  // the sparse-grid template's nodes of theta, from the evaluation above
+    ma.spl_nmax = c->m.sparse > 0 ? spl_max_nodes(c->g.K, c->m.sparse) : 0;
     launch_waveform(ma, st + off_h, s);
     launch_stream_weights(nch, K, st + off_h, c->psd_dev, st + off_w, st + off_q, s);
     int32_t* dpcs = reinterpret_cast<int32_t*>(st + off_p);
@@ -1351,7 +1405,7 @@ static int fused_main(std::vector<EvalJob>& jobs, int waves, bool mixed, hipStre
         int64_t* hs = b.h_start + gi * (b.cap + 1);
         for (int i = 0; i < n_items; ++i) {
             const EvalJob& j = jobs[i];
-            if (variant_of(j.c->m.response, j.c->g.nch) != gi || j.P == 0 || j.pl.n_tiles == 0) continue;
+            if (variant_of(j.c->m.response, j.c->g.nch, j.c->m.sparse) != gi || j.P == 0 || j.pl.n_tiles == 0) continue;
             if (upload) {
                 b.h_items[off + cnt] = j.ma;
                 hs[cnt] = total;
@@ -1594,7 +1648,7 @@ static uint64_t slot_bytes(const SrvSlot& s)
 {
     const Workspace& w = s.ws;
     uint64_t b = (uint64_t)w.capP * (sizeof(double) * kCoefStride + 2 * sizeof(int32_t) + 1);
-    b += (uint64_t)w.capBounds * sizeof(int32_t) + (uint64_t)(w.capRec + w.capZs) * sizeof(double);
+    b += (uint64_t)w.capBounds * sizeof(int32_t) + (uint64_t)(w.capRec + w.capZs + w.capSpl) * sizeof(double);
     if (w.capSort) b += (uint64_t)w.capSort * 3 * sizeof(int32_t) + sizeof(unsigned) * (uint64_t)kSortBuckets;
     b += (uint64_t)s.cap * sizeof(double) * (kThetaMax + 1);
     return b;
@@ -1614,6 +1668,7 @@ static uint64_t slot_bytes_after(const SrvSlot& s, const scs_ctx* c, int64_t P, 
     w.capBounds = std::max(s.ws.capBounds, P * (int64_t)(N + 1) + 2);
     w.capRec = std::max(s.ws.capRec, pl.n_chunks * kRec * w.capP);
     w.capZs = std::max(s.ws.capZs, 3 * P * (int64_t)N);
+    w.capSpl = std::max(s.ws.capSpl, spl_doubles(c, w.capP));
     w.capSort = (P >= kSortMin && P > s.ws.capSort) ? w.capP : s.ws.capSort;
     return slot_bytes(x);
 }

@@ -42,7 +42,47 @@ struct ModelArgs {
     double cart0;     // cartwheel phase at t = 0 [rad]
     double cart_c, cart_s;  // cos, sin of cart0
     int ecc;                // 1: eccentric phase, theta rows carry an 8th entry e0
+    int sparse;             // 0: template per bin (block polynomials); S > 0: the sparse-grid
+                            // template, nodes every S bins, cubic splines onto every bin
 };
+
+// ---- sparse-grid template (Sec 4: waveform and response on a coarse grid,
+// cubic splines onto the FFT grid).  A particle's nodes are the first bin of
+// its support, the multiples of S strictly inside it and its last bin; n is
+// the number of intervals (nodes - 1).  Each node has a record
+//   [I, phi, R_1 .. R_NR, M_0 .. M_NQ-1, T_0 .. T_NQ-1]
+// with the template phase I + phi in cycles (I an integer, |phi| <= 1/2), the
+// NR real and imaginary parts of the channel responses, the spline's second
+// derivatives M of the NQ = 1 + NR quantities and the solver's work space T.
+__host__ __device__ constexpr int spl_nr(int nch) { return nch == 1 ? 0 : 2 * nch; }
+__host__ __device__ constexpr int spl_nq(int nch) { return 1 + spl_nr(nch); }
+__host__ __device__ constexpr int spl_rec(int nch) { return 2 + spl_nr(nch) + 2 * spl_nq(nch); }
+__host__ __device__ constexpr int64_t spl_max_nodes(int64_t K, int64_t S) { return (K + S - 1) / S + 2; }
+constexpr int kMaxSparseStride = 65536;
+__host__ __device__ inline int64_t spl_intervals(int64_t klo, int64_t khi, int64_t S)
+{
+    if (khi - 1 <= klo) return 0;
+    const int64_t first = (klo / S + 1) * S;  // first multiple of S after klo
+    return 1 + (first < khi - 1 ? (khi - 2 - first) / S + 1 : 0);
+}
+__host__ __device__ inline int64_t spl_node(int64_t j, int64_t n, int64_t klo, int64_t khi, int64_t S)
+{
+    return j == 0 ? klo : (j == n ? khi - 1 : (klo / S + j) * S);
+}
+
+struct SplineArgs {
+    GridArgs g;
+    ModelArgs m;
+    int64_t P;
+    int64_t stride;  // coefficient buffer stride
+    const double* coef;
+    const int32_t* klo;
+    const int32_t* khi;
+    const int8_t* lg;
+    int64_t nmax;  // node records per particle
+    double* spl;   // [P][nmax][spl_rec(nch)]
+};
+void launch_spline(const SplineArgs& a, hipStream_t s);  // node values, then the spline solve
 
 struct PhysConst {
     double pitsun_hi, pitsun_lo;  // pi G Msun / c^3 [s], double-double
@@ -109,6 +149,8 @@ struct MainArgs {
     double* zs;            // [P][N][3]: (Z re, Z im, H) of segments closed inside a chunk
     double zscale32;       // FP32 tables hold u * sqrt(s), q * s: Z32 * zscale32 = Z, H32 * hscale32 = H
     double hscale32;
+    const double* spl;     // sparse-grid template: node records (SplineArgs), else null
+    int64_t spl_nmax;
 };
 
 struct FinalArgs {
@@ -187,12 +229,13 @@ void launch_prologue(const PrologueArgs& a, hipStream_t s);
 void launch_bounds(const BoundArgs& a, hipStream_t s);
 size_t main_lds_bytes(int nch, int L, bool mixed);
 // The kernel instantiations of the generate-and-reduce, one per (response
-// model, channels): 0 = low-frequency A+E, 1 = full A+E, 2 = full A+E+T,
-// 3 = one channel without response.
-constexpr int kVariants = 4;
-__host__ __device__ constexpr int variant_of(int resp, int nch)
+// model, channels, template): 0 = low-frequency A+E, 1 = full A+E, 2 = full
+// A+E+T, 3 = one channel without response; 4 .. 7 the same with the
+// sparse-grid template.
+constexpr int kVariants = 8;
+__host__ __device__ constexpr int variant_of(int resp, int nch, int sparse)
 {
-    return resp == 1 ? 0 : (resp == 2 ? (nch == 3 ? 2 : 1) : 3);
+    return (resp == 1 ? 0 : (resp == 2 ? (nch == 3 ? 2 : 1) : 3)) + (sparse > 0 ? 4 : 0);
 }
 hipError_t launch_main_multi(const MainArgs* items, const int64_t* tile_start, int n_items, unsigned long long* counter,
                              int variant, int L, int waves, bool mixed, int grid, hipStream_t s);

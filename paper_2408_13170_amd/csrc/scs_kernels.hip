@@ -229,6 +229,8 @@ __global__ void k_prologue(PrologueArgs a)
             }
             if (good) { lg = l; break; }
         }
+        // the sparse-grid template expands nothing in blocks: every theta resolves
+        if (lg < 0 && a.m.sparse > 0) lg = a.lg_max;
         if (lg < 0) atomicAdd(a.unresolved, 1ULL);
     } else {
         lg = a.lg_max;  // empty support: nothing to resolve
@@ -293,6 +295,7 @@ __global__ void k_prologue(PrologueArgs a)
     cf[p * kCoefStride + C_TAUH] = tau.hi;
     cf[p * kCoefStride + C_TAUL] = tau.lo;
     cf[p * kCoefStride + C_TC] = tcs;
+    cf[p * kCoefStride + C_TCL] = tc.lo - (tcs - tc.hi);
     a.klo[p] = (int32_t)klo;
     a.khi[p] = (int32_t)khi;
     a.lg[p] = (int8_t)lg;
@@ -473,6 +476,15 @@ __device__ inline void block_setup(const GLOBAL double* __restrict__ cf, int64_t
     }
 }
 
+// Horner's rule for a polynomial of degree D (D + 1 coefficients, lowest first).
+template <int D>
+__device__ __forceinline__ double horner(const double* c, double x)
+{
+    double v = c[D];
+#pragma unroll
+    for (int i = D - 1; i >= 0; --i) v = __builtin_fma(v, x, c[i]);
+    return v;
+}
 __device__ __forceinline__ double horner5(const double* c, double x)
 {
     double v = c[5];
@@ -698,6 +710,302 @@ __global__ void k_bounds_simple(BoundArgs a)
     a.bounds[p * (int64_t)(N + 1) + n] = (int32_t)v;
 }
 
+// ============================================================== sparse-grid template
+// The paper's way of evaluating the template (Sec 4, waveform and response
+// paragraphs): waveform and response on a grid coarser than the FFT grid,
+// cubic splines onto every bin.  The nodes of a particle are every S-th bin
+// of its support plus the support's ends (spl_node); the quantities are the
+// template phase in cycles (GW and Doppler terms, unreduced) and the real and
+// imaginary parts of each channel's response; the splines are the not-a-knot
+// cubic splines through the nodes.  Node values are exact evaluations (the
+// phase reduced in double-double like the block set-up, its whole cycles
+// from a plain FP64 evaluation), so the template differs from the per-bin
+// one only by the interpolation.
+
+// Node values of the quantities, one thread per (particle, node).
+template <int NCH, int RM>
+__global__ void k_spline_nodes(SplineArgs a)
+{
+    constexpr int NR = spl_nr(NCH), REC = spl_rec(NCH);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t p = i / a.nmax, j = i - p * a.nmax;
+    if (p >= a.P || a.lg[p] < 0) return;
+    const int64_t klo = a.klo[p], khi = a.khi[p];
+    if (khi <= klo) return;
+    const int64_t S = a.m.sparse;
+    const int64_t n = spl_intervals(klo, khi, S);
+    if (j > n) return;
+    const double* cf = a.coef + p * kCoefStride;
+    const double K = a.g.k0 + (double)spl_node(j, n, klo, khi, S);  // absolute bin, an integer
+    const dd fK = two_prod(K, a.g.df);
+    const double f = fK.hi;
+    // A spline whose end interval is a few bins long multiplies the rounding
+    // of the node values by up to ~S / (that length) next to it, so every term
+    // of the phase above a few cycles, and the SPA time that sets the
+    // Doppler term, is taken in double-double; the terms left in double stay
+    // below ~10 cycles (rounding ~1e-15 cycles).
+    const double u = 1.0 / cbrt(f), u2 = u * u, lnf = log(f) + fK.lo / fK.hi;
+    // f^-1 in double-double: one Newton step from y0 = 1/f, with r = 1 - f y0
+    const double y0 = 1.0 / f;
+    const dd fy = two_prod(fK.hi, y0);
+    const double rr = ((1.0 - fy.hi) - fy.lo) - fK.lo * y0;
+    const dd inv = fast_two_sum(y0, y0 * rr);
+    const dd t1 = dd_mul_d(inv, cf[C_B1]);
+    const dd t2 = dd_mul_d(dd_pow_ratio(fK, -2, 3), cf[C_B2]);
+    const dd t3 = dd_mul_d(dd_pow_ratio(fK, -1, 3), cf[C_B3]);
+    const double small = cf[C_B4] * lnf + cf[C_B5] / u + cf[C_B6] * (lnf / u) + cf[C_B7] / u2 + cf[C_PHIC];
+    const double u5 = u2 * u2 * u;
+    const double beh = cf[C_BEH];
+    // SPA time: t_c and the Newtonian term in double-double, the rest in double
+    double bc[9];
+    bc[0] = 0.0;
+    for (int q = 1; q < 8; ++q) bc[q] = cf[C_B1 + q - 1];
+    bc[8] = beh;
+    const dd c0 = dd{cf[C_C0H], cf[C_C0L]};
+    const dd tN = dd_mul(dd_mul(dd_ratio(5.0, 3.0), c0), dd_pow_m83(fK));
+    const dd tcd = dd_add(dd{cf[C_TC], cf[C_TCL]}, dd{-tN.hi, -tN.lo});
+    const double t = tcd.hi + (tcd.lo + dphase_pn(bc, f));  // stationary-phase time [s]
+    double s1 = 0.0, c1 = 1.0, dop = 0.0;
+    if constexpr (RM != 0) {
+        double orb = a.m.orb0_cyc + t * kInvYear;
+        orb -= rint(orb);
+        sincos2pi(orb, &s1, &c1);
+        dop = f * (cf[C_DC] * c1 + cf[C_DS] * s1);
+    }
+    // the phase modulo one cycle
+    dd lin = two_prod(K, cf[C_TAUH]);
+    lin.lo = __builtin_fma(K, cf[C_TAUL], lin.lo);
+    const dd n0 = dd_mul(c0, dd_pow_m53(fK));
+    double ecc = 0.0, ecc_whole = 0.0;
+    if (beh != 0.0) {
+        const dd fe = dd_pow_ratio(fK, -34, 9);
+        ecc = dd_frac(dd_mul(dd{beh, cf[C_BEL]}, fe));
+        ecc_whole = beh * fe.hi;
+    }
+    double phi = dd_frac(lin) + dd_frac(n0) + dd_frac(t1) + dd_frac(t2) + dd_frac(t3) + (small - rint(small)) +
+                 ecc + dop;
+    phi -= rint(phi);
+    // whole cycles from the unreduced phase in double (error far below a cycle)
+    const double whole = K * (cf[C_TAUH] + cf[C_TAUL]) + cf[C_C0H] * u5 + t1.hi + t2.hi + t3.hi + small +
+                         ecc_whole + dop;
+    double* r = a.spl + (p * a.nmax + j) * REC;
+    r[0] = rint(whole - phi);
+    r[1] = phi;
+    if constexpr (RM == 1) {
+        double ch[5], sh[5];
+        harmonics(c1, s1, ch, sh);
+        for (int fi = 0; fi < 4; ++fi) r[2 + fi] = trig4(cf + C_RESP + 9 * fi, ch, sh);
+    } else if constexpr (RM == 2) {
+        const double cz = __builtin_fma(a.m.cart_c, c1, a.m.cart_s * s1);
+        const double sz = __builtin_fma(a.m.cart_s, c1, -(a.m.cart_c * s1));
+        double rv[NR];
+        fd_response<NCH>(f, c1, s1, cz, sz, cf + C_RESP, rv);
+        for (int fi = 0; fi < NR; ++fi) r[2 + fi] = rv[fi];
+    }
+}
+
+// Second derivatives M of the not-a-knot cubic spline through the nodes, one
+// thread per (particle, quantity).  Interior nodes i = 1 .. n-1 make the
+// first derivative continuous,
+//   h_{i-1} M_{i-1} + 2 (h_{i-1} + h_i) M_i + h_i M_{i+1} = 6 (s_i - s_{i-1}),
+// with h_i the length and s_i the slope of interval i; not-a-knot makes the
+// third derivative continuous at nodes 1 and n-1, which expresses M_0 and M_n
+// through their neighbours and leaves a tridiagonal system in M_1 .. M_n-1,
+// solved by forward elimination (slopes formed on the way) and back
+// substitution.  Two intervals: the parabola through the three nodes (one
+// M); one interval: the line (M = 0).  The phase enters as whole cycles plus
+// fraction, so that differences keep their precision.  Each pass reads its
+// node values BLK at a time into registers before using them, so one memory
+// latency covers BLK steps of the recurrence.
+template <int NCH>
+__global__ __launch_bounds__(64) void k_spline_solve(SplineArgs a)
+{
+    constexpr int NR = spl_nr(NCH), NQ = spl_nq(NCH), REC = spl_rec(NCH);
+    constexpr int BLK = 32;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t p = i / NQ;
+    const int q = (int)(i - p * NQ);
+    if (p >= a.P || a.lg[p] < 0) return;
+    const int64_t klo = a.klo[p], khi = a.khi[p];
+    if (khi <= klo) return;
+    const int64_t S = a.m.sparse;
+    const int64_t n = spl_intervals(klo, khi, S);
+    double* base = a.spl + p * a.nmax * REC;
+    const int mo = 2 + NR + q, to = 2 + NR + NQ + q;
+    if (n <= 1) {
+        for (int64_t j = 0; j <= n; ++j) base[j * REC + mo] = 0.0;
+        return;
+    }
+    // the quantity at node j as a pair whose sum is its value: the phase as
+    // whole cycles and fraction, a response part as itself and 0
+    const int ia = q == 0 ? 0 : 1 + q, ib = q == 0 ? 1 : 1 + q;
+    const double wb = q == 0 ? 1.0 : 0.0;
+    const int64_t kb = klo / S;
+    auto node = [&](int64_t jj) { return jj == 0 ? klo : (jj == n ? khi - 1 : (kb + jj) * S); };  // spl_node
+    auto len = [&](int64_t jj) { return (double)(node(jj + 1) - node(jj)); };
+    const double h0 = len(0), h1 = len(1);
+    double a0 = base[ia], b0 = wb * base[ib];
+    double a1 = base[REC + ia], b1 = wb * base[REC + ib];
+    double a2 = base[2 * REC + ia], b2 = wb * base[2 * REC + ib];
+    const double s0 = ((a1 - a0) + (b1 - b0)) / h0, s1 = ((a2 - a1) + (b2 - b1)) / h1;
+    if (n == 2) {
+        const double v = 2.0 * (s1 - s0) / (h0 + h1);
+        for (int64_t j = 0; j <= 2; ++j) base[j * REC + mo] = v;
+        return;
+    }
+    // forward elimination over rows 1 .. n-1; row 1 with
+    // M_0 = ((h0 + h1) M_1 - h0 M_2) / h1 substituted, row n-1 with
+    // M_n = ((h_{n-2} + h_{n-1}) M_{n-1} - h_{n-1} M_{n-2}) / h_{n-2}
+    double dpv = 2.0 * (h0 + h1) + h0 * (h0 + h1) / h1;
+    double upv = h1 - h0 * h0 / h1;
+    double rpv = 6.0 * (s1 - s0);
+    base[1 * REC + to] = dpv;
+    base[1 * REC + mo] = rpv;
+    double sp = s1, ap = a2, bp = b2;  // slope of row r's left interval, values at node r
+    for (int64_t r0 = 2; r0 <= n - 1; r0 += BLK) {
+        double va[BLK], vb[BLK];  // values at nodes r0 + 1 .. r0 + BLK
+#pragma unroll
+        for (int t = 0; t < BLK; ++t) {
+            const int64_t j = r0 + 1 + t <= n ? r0 + 1 + t : n;
+            va[t] = base[j * REC + ia];
+            vb[t] = wb * base[j * REC + ib];
+        }
+#pragma unroll
+        for (int t = 0; t < BLK; ++t) {
+            const int64_t r = r0 + t;
+            if (r <= n - 1) {
+                const double hl = len(r - 1), hr = len(r);
+                const double sr = ((va[t] - ap) + (vb[t] - bp)) / hr;
+                double lower = hl, diag = 2.0 * (hl + hr);
+                if (r == n - 1) {
+                    diag += hr * (hl + hr) / hl;
+                    lower -= hr * hr / hl;
+                }
+                const double w = lower / dpv;
+                diag -= w * upv;
+                const double rhs = 6.0 * (sr - sp) - w * rpv;
+                base[r * REC + to] = diag;
+                base[r * REC + mo] = rhs;
+                dpv = diag;
+                rpv = rhs;
+                upv = hr;
+                sp = sr;
+                ap = va[t];
+                bp = vb[t];
+            }
+        }
+    }
+    // back substitution, rows n-1 .. 1
+    double mnext = rpv / dpv;
+    base[(n - 1) * REC + mo] = mnext;
+    for (int64_t r0 = n - 2; r0 >= 1; r0 -= BLK) {
+        double rr[BLK], dg[BLK];
+#pragma unroll
+        for (int t = 0; t < BLK; ++t) {
+            const int64_t r = r0 - t >= 1 ? r0 - t : 1;
+            rr[t] = base[r * REC + mo];
+            dg[t] = base[r * REC + to];
+        }
+#pragma unroll
+        for (int t = 0; t < BLK; ++t) {
+            const int64_t r = r0 - t;
+            if (r >= 1) {
+                const double up = r == 1 ? h1 - h0 * h0 / h1 : len(r);
+                const double m = (rr[t] - up * mnext) / dg[t];
+                base[r * REC + mo] = m;
+                mnext = m;
+            }
+        }
+    }
+    const double m1 = base[1 * REC + mo], m2 = base[2 * REC + mo];
+    base[mo] = ((h0 + h1) * m1 - h0 * m2) / h1;
+    const double hl = len(n - 2), hr = len(n - 1);
+    const double ma = base[(n - 1) * REC + mo], mb = base[(n - 2) * REC + mo];
+    base[n * REC + mo] = ((hl + hr) * ma - hr * mb) / hl;
+}
+
+// The cubics of one spline interval [x_j, x_j + h] in u = k - x_j, from the
+// node records of its two ends (r0 and the record after it):
+// S(u) = y0 + c1 u + (M0 / 2) u^2 + (M1 - M0) / (6 h) u^3 with
+// c1 = (y1 - y0) / h - h (2 M0 + M1) / 6; the phase's y1 - y0 is taken as
+// (I1 - I0) + (phi1 - phi0) and its constant term is phi0 (cycles).  Without
+// a right end (a one-bin support) the cubics are constants.
+template <int NCH>
+__device__ inline void spline_interval(const GLOBAL double* __restrict__ r0, bool right, double h, double* cph,
+                                       double (*crs)[4])
+{
+    constexpr int NR = spl_nr(NCH), REC = spl_rec(NCH), MO = 2 + NR;
+    if (!right) {
+        cph[0] = r0[1];
+        cph[1] = cph[2] = cph[3] = 0.0;
+#pragma unroll
+        for (int f = 0; f < NR; ++f) {
+            crs[f][0] = r0[2 + f];
+            crs[f][1] = crs[f][2] = crs[f][3] = 0.0;
+        }
+        return;
+    }
+    const GLOBAL double* r1 = r0 + REC;
+    const double ih = 1.0 / h, h6 = h * (1.0 / 6.0), ih6 = ih * (1.0 / 6.0);
+    {
+        const double m0 = r0[MO], m1 = r1[MO];
+        const double dy = (r1[0] - r0[0]) + (r1[1] - r0[1]);
+        cph[0] = r0[1];
+        cph[1] = dy * ih - h6 * (2.0 * m0 + m1);
+        cph[2] = 0.5 * m0;
+        cph[3] = (m1 - m0) * ih6;
+    }
+#pragma unroll
+    for (int f = 0; f < NR; ++f) {
+        const double m0 = r0[MO + 1 + f], m1 = r1[MO + 1 + f];
+        const double y0 = r0[2 + f], y1 = r1[2 + f];
+        crs[f][0] = y0;
+        crs[f][1] = (y1 - y0) * ih - h6 * (2.0 * m0 + m1);
+        crs[f][2] = 0.5 * m0;
+        crs[f][3] = (m1 - m0) * ih6;
+    }
+}
+
+// The sparse-grid template of particle 0 on the grid (injections, parity).
+template <int NCH>
+__global__ void k_waveform_spline(MainArgs a, double* __restrict__ h_ri)
+{
+    constexpr int NR = spl_nr(NCH);
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.g.K) return;
+    for (int c = 0; c < NCH; ++c) {
+        h_ri[((int64_t)c * a.g.K + k) * 2] = 0.0;
+        h_ri[((int64_t)c * a.g.K + k) * 2 + 1] = 0.0;
+    }
+    const int64_t klo = a.klo[0], khi = a.khi[0];
+    if (a.lg[0] < 0 || k < klo || k >= khi) return;
+    const int64_t S = a.m.sparse;
+    const int64_t n = spl_intervals(klo, khi, S);
+    int64_t j = k / S - klo / S;
+    j = j < n - 1 ? j : n - 1;
+    j = j > 0 ? j : 0;
+    const int64_t xl = spl_node(j, n, klo, khi, S);
+    const int64_t xr = spl_node(j < n ? j + 1 : j, n, klo, khi, S);
+    double cph[4], crs[NR > 0 ? NR : 1][4];
+    spline_interval<NCH>((const GLOBAL double*)a.spl + j * (int64_t)spl_rec(NCH), j < n, (double)(xr - xl), cph, crs);
+    const double u = (double)(k - xl);
+    double ph = horner<3>(cph, u);
+    ph -= rint(ph);
+    double sn, cs;
+    sincos2pi(ph, &sn, &cs);
+    const double amp = pow((a.g.k0 + (double)k) * a.g.df, -7.0 / 6.0);
+    if constexpr (NR == 0) {
+        h_ri[2 * k] = amp * cs;
+        h_ri[2 * k + 1] = -amp * sn;
+    } else {
+        for (int c = 0; c < NCH; ++c) {
+            const double rr = horner<3>(crs[2 * c], u), ri = horner<3>(crs[2 * c + 1], u);
+            h_ri[((int64_t)c * a.g.K + k) * 2] = amp * (rr * cs + ri * sn);
+            h_ri[((int64_t)c * a.g.K + k) * 2 + 1] = amp * (ri * cs - rr * sn);
+        }
+    }
+}
+
 // ============================================================== main kernel
 // Work tile = (chunk of CB LDS blocks of L bins, group of 64 W particles).
 // One lane = one particle; all lanes of a workgroup read the same staged bins
@@ -756,7 +1064,7 @@ struct SinCosK {
     double s3, s1, c2;
 };
 
-template <int NCH>
+template <int NCH, int D = 5>
 __device__ __forceinline__ void bin_fp64(double j, const double* __restrict__ bin, const double2* __restrict__ tab,
                                          const SinCosK& kk, const PhasePoly& poly,
                                          const RespPolyN<NCH == 3 ? 6 : 4>& rp, int tmask, int toff, double amp,
@@ -782,15 +1090,15 @@ __device__ __forceinline__ void bin_fp64(double j, const double* __restrict__ bi
         ui = bin[1];
         q1 = bin[2];
     }
-    const double pc = horner5(poly.ph, j);
+    const double pc = horner<D>(poly.ph, j);
     const double t = pc + kRoundShift;
     const int iq = ((int)(uint32_t)__double_as_longlong(t) & tmask) | toff;
     const double2 tt = tab[iq];
     double sr, si;
     if constexpr (NCH == 3) {
-        const double rar = horner5(rp.r[0], j), rai = horner5(rp.r[1], j);
-        const double rer = horner5(rp.r[2], j), rei = horner5(rp.r[3], j);
-        const double rtr = horner5(rp.r[4], j), rti = horner5(rp.r[5], j);
+        const double rar = horner<D>(rp.r[0], j), rai = horner<D>(rp.r[1], j);
+        const double rer = horner<D>(rp.r[2], j), rei = horner<D>(rp.r[3], j);
+        const double rtr = horner<D>(rp.r[4], j), rti = horner<D>(rp.r[5], j);
         sr = uA.x * rar;
         sr = __builtin_fma(uA.y, rai, sr);
         sr = __builtin_fma(uE.x, rer, sr);
@@ -808,8 +1116,8 @@ __device__ __forceinline__ void bin_fp64(double j, const double* __restrict__ bi
         const double wt = __builtin_fma(rtr, rtr, rti * rti);
         hh = __builtin_fma(qq.x, wa, __builtin_fma(qq.y, we, __builtin_fma(qT.x, wt, hh)));
     } else if constexpr (RESP) {
-        const double rar = horner5(rp.r[0], j), rai = horner5(rp.r[1], j);
-        const double rer = horner5(rp.r[2], j), rei = horner5(rp.r[3], j);
+        const double rar = horner<D>(rp.r[0], j), rai = horner<D>(rp.r[1], j);
+        const double rer = horner<D>(rp.r[2], j), rei = horner<D>(rp.r[3], j);
         sr = uA.x * rar;
         sr = __builtin_fma(uA.y, rai, sr);
         sr = __builtin_fma(uE.x, rer, sr);
@@ -840,9 +1148,13 @@ __device__ __forceinline__ void bin_fp64(double j, const double* __restrict__ bi
 // (a1h j exact, see the block set-up), hardware sin / cos of cycles, FP32
 // response; plain FP32 partial sums over at most kMixedRun bins, which then
 // enter the FP32 segment sums through Kahan-compensated additions.
-template <int NCH>
+// PH64: the phase is the FP64 cubic ph64 at ud (cycles), reduced and then
+// rounded to FP32 (the sparse-grid template, whose spline intervals are too
+// long for an FP32 residual), instead of a0 + frac(a1h j) + residual.
+template <int NCH, bool PH64 = false>
 __device__ __forceinline__ void bin_mixed(float jf, const float* __restrict__ bin, const float* phf, float a1h,
-                                          const float (*rf)[kRespMixed], float amp, float& pzr, float& pzi, float& phh)
+                                          const float (*rf)[kRespMixed], float amp, float& pzr, float& pzi, float& phh,
+                                          const double* ph64 = nullptr, double ud = 0.0)
 {
     constexpr bool RESP = NCH >= 2;
     // the bin's data first, in flight while the phase and sin / cos are formed
@@ -861,12 +1173,18 @@ __device__ __forceinline__ void bin_mixed(float jf, const float* __restrict__ bi
         ui = bin[1];
         q1 = bin[2];
     }
-    const float pl = a1h * jf;
-    const float f1 = pl - rintf(pl);
-    float r = phf[3];
-    r = __builtin_fmaf(r, jf, phf[2]);
-    r = __builtin_fmaf(r, jf, phf[1]);
-    const float ph = __builtin_fmaf(r, jf, phf[0] + f1);
+    float ph;
+    if constexpr (PH64) {
+        const double pd = horner<3>(ph64, ud);
+        ph = (float)(pd - rint(pd));
+    } else {
+        const float pl = a1h * jf;
+        const float f1 = pl - rintf(pl);
+        float r = phf[3];
+        r = __builtin_fmaf(r, jf, phf[2]);
+        r = __builtin_fmaf(r, jf, phf[1]);
+        ph = __builtin_fmaf(r, jf, phf[0] + f1);
+    }
     const float sn = __builtin_amdgcn_sinf(ph);
     const float cs = __builtin_amdgcn_cosf(ph);
     if constexpr (NCH == 3) {
@@ -935,7 +1253,7 @@ constexpr int kMixedRun = 32;
 // by every thread of the workgroup; returns early, uniformly, when no
 // particle of the group has support in the chunk.  s_trig holds the table
 // and, at kTrig, a zero entry for idle one-channel lanes.
-template <int NCH, bool MIXED, int RM>
+template <int NCH, bool MIXED, int RM, int TM>
 __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __restrict__ gtab, int64_t logical,
                                           unsigned char* smem, const double2* __restrict__ s_trig)
 {
@@ -961,6 +1279,7 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
             hi = ((const GLOBAL int32_t*)a.khi)[p];
         }
     }
+    const int plo = lo, phi = hi;  // the whole support (the sparse-grid template's nodes)
     lo = lo > Kc ? lo : Kc;
     hi = hi < Ke ? hi : Ke;
     const bool has = lo < hi;
@@ -1106,6 +1425,99 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
     const GLOBAL double* __restrict__ gtl = (const GLOBAL double*)gtab + a.gtab_off[lgl] * kGStride;
     const GLOBAL double* __restrict__ coef = (const GLOBAL double*)a.coef;
     int have = -1, kcl = 0;
+    // Sparse-grid template: bins are taken in pieces between multiples of
+    // the node stride S, inside which every lane stays on one spline
+    // interval (the last interval also takes the support's last bin, which
+    // lies past the last multiple of S).  On its first piece of an interval a
+    // lane forms the interval's cubics from the node records and evaluates
+    // them at u = k - (left node): all in FP64 on the FP64 path; on the mixed
+    // path the phase cubic in FP64 (an interval of S bins holds far more
+    // phase curvature than an FP32 residual can carry) and the response
+    // cubics in FP32.
+    [[maybe_unused]] int64_t nint = 0;
+    [[maybe_unused]] int xl = 0;
+    [[maybe_unused]] double cph[4] = {0.0, 0.0, 0.0, 0.0};
+    [[maybe_unused]] double crs[NR][4];
+    if constexpr (TM == 1) {
+#pragma unroll
+        for (int f = 0; f < NR; ++f)
+#pragma unroll
+            for (int mm = 0; mm < 4; ++mm) crs[f][mm] = 0.0;
+        if (has) nint = spl_intervals(plo, phi, a.m.sparse);
+    }
+    auto spline_pieces = [&](int b0, int wlo, int whi, bool act, int llo, int lhi) {
+        if constexpr (TM == 1) {
+            const int S = a.m.sparse;
+#pragma unroll 1
+            for (int sb0 = (wlo / S) * S; sb0 < whi; sb0 += S) {
+                const int s_lo = sb0 > wlo ? sb0 : wlo;
+                const int s_hi = (sb0 + S < whi) ? sb0 + S : whi;
+                const bool sact = act && llo < s_hi && lhi > s_lo;
+                if (sact) {
+                    int64_t jint = (int64_t)(sb0 / S) - (int64_t)(plo / S);
+                    jint = jint < nint - 1 ? jint : nint - 1;
+                    jint = jint > 0 ? jint : 0;
+                    if (have != (int)jint) {
+                        have = (int)jint;
+                        xl = (int)spl_node(jint, nint, plo, phi, S);
+                        const int xr = (int)spl_node(jint < nint ? jint + 1 : jint, nint, plo, phi, S);
+                        const GLOBAL double* r0 =
+                            (const GLOBAL double*)a.spl + (p * a.spl_nmax + jint) * (int64_t)spl_rec(NCH);
+                        spline_interval<NCH>(r0, jint < nint, (double)(xr - xl), cph, crs);
+                        if constexpr (MIXED && RESP) {
+#pragma unroll
+                            for (int f = 0; f < NR; ++f)
+#pragma unroll
+                                for (int mm = 0; mm < 4; ++mm) rf[f][mm] = (float)crs[f][mm];
+                        }
+                        if constexpr (!MIXED) {
+                            double sc = kPhaseUnits;
+#pragma unroll
+                            for (int mm = 0; mm < 4; ++mm) poly.ph[mm] = cph[mm] * sc;
+                            if constexpr (RESP) {
+#pragma unroll
+                                for (int f = 0; f < NR; ++f)
+#pragma unroll
+                                    for (int mm = 0; mm < 4; ++mm) rp.r[f][mm] = crs[f][mm];
+                            }
+                        }
+                    }
+                    tmask = kTabMask;
+                    toff = 0;
+                    amp = 1.0;
+                }
+                __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): nothing of the set-up pending in the bin loop
+                if constexpr (!MIXED) {
+                    double jd = (double)(s_lo - xl);
+                    const double* binp = reinterpret_cast<const double*>(smem) + (s_lo - b0) * NV;
+#pragma unroll 1
+                    for (int k = s_lo; k < s_hi; ++k) {
+                        if (nxt <= k) handle(k);
+                        bin_fp64<NCH, 3>(jd, binp, s_trig, kk, poly, rp, tmask, toff, amp, zr, zi, hh);
+                        jd += 1.0;
+                        binp += NV;
+                    }
+                } else {
+                    const float ampf = (float)amp;
+                    double ud = (double)(s_lo - xl);
+                    const float* binp = reinterpret_cast<const float*>(smem) + (s_lo - b0) * NV;
+#pragma unroll 1
+                    for (int k = s_lo; k < s_hi; ++k) {
+                        if (nxt <= k) handle(k);
+                        bin_mixed<NCH, true>((float)ud, binp, phf, a1h, rf, ampf, qzr, qzi, qhh, cph, ud);
+                        ud += 1.0;
+                        binp += NV;
+                        if (((k + 1) & (kMixedRun - 1)) == 0) {
+                            kahan(kzr, czr, qzr);
+                            kahan(kzi, czi, qzi);
+                            kahan(khh, chh, qhh);
+                            qzr = qzi = qhh = 0.f;
+                        }
+                    }
+                }
+            }
+        }
+    };
     for (int b0 = Kc; b0 < Ke; b0 += L) {
         const int b1 = (b0 + L < Ke) ? b0 + L : Ke;
         const int nbins = b1 - b0;
@@ -1144,6 +1556,10 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
         wlo = __builtin_amdgcn_readfirstlane(wlo);
         whi = __builtin_amdgcn_readfirstlane(whi);
         if (wlo >= whi) continue;
+        if constexpr (TM == 1) {
+            spline_pieces(b0, wlo, whi, act, llo, lhi);
+            continue;
+        }
         const int Lp = 1 << lgw;
 #pragma unroll 1
         for (int sb0 = (wlo >> lgw) << lgw; sb0 < whi; sb0 += Lp) {
@@ -1272,7 +1688,7 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
 // particle groups of one chunk, so workgroups running together share the
 // chunk's data in L2.  tile_start[i] is the first global tile of item i (prefix sums,
 // tile_start[n_items] = total); the counter starts at 0.
-template <int NCH, bool MIXED, int RM>
+template <int NCH, bool MIXED, int RM, int TM>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(MIXED ? SCS_WAVES_MIXED : (NCH == 3 ? 2 : SCS_WAVES_FP64)))) void k_main_multi(
     const MainArgs* __restrict__ items, const int64_t* __restrict__ tile_start, int n_items,
@@ -1295,7 +1711,7 @@ __attribute__((amdgpu_waves_per_eu(MIXED ? SCS_WAVES_MIXED : (NCH == 3 ? 2 : SCS
         int it = 0;
         while (it + 1 < n_items && tile_start[it + 1] <= t) ++it;
         const MainArgs& a = items[it];
-        main_tile<NCH, MIXED, RM>(a, a.gtab, t - tile_start[it], smem, s_trig);
+        main_tile<NCH, MIXED, RM, TM>(a, a.gtab, t - tile_start[it], smem, s_trig);
     }
 }
 
@@ -1896,13 +2312,21 @@ typedef void (*MainKernel)(const MainArgs*, const int64_t*, int, unsigned long l
 static MainKernel main_kernel(int variant, bool mixed)
 {
     switch (variant) {
-    case 0: return mixed ? k_main_multi<2, true, 1> : k_main_multi<2, false, 1>;
-    case 1: return mixed ? k_main_multi<2, true, 2> : k_main_multi<2, false, 2>;
-    case 2: return mixed ? k_main_multi<3, true, 2> : k_main_multi<3, false, 2>;
-    default: return mixed ? k_main_multi<1, true, 0> : k_main_multi<1, false, 0>;
+    case 0: return mixed ? k_main_multi<2, true, 1, 0> : k_main_multi<2, false, 1, 0>;
+    case 1: return mixed ? k_main_multi<2, true, 2, 0> : k_main_multi<2, false, 2, 0>;
+    case 2: return mixed ? k_main_multi<3, true, 2, 0> : k_main_multi<3, false, 2, 0>;
+    case 3: return mixed ? k_main_multi<1, true, 0, 0> : k_main_multi<1, false, 0, 0>;
+    case 4: return mixed ? k_main_multi<2, true, 1, 1> : k_main_multi<2, false, 1, 1>;
+    case 5: return mixed ? k_main_multi<2, true, 2, 1> : k_main_multi<2, false, 2, 1>;
+    case 6: return mixed ? k_main_multi<3, true, 2, 1> : k_main_multi<3, false, 2, 1>;
+    default: return mixed ? k_main_multi<1, true, 0, 1> : k_main_multi<1, false, 0, 1>;
     }
 }
-static int variant_channels(int variant) { return variant == 2 ? 3 : (variant == 3 ? 1 : 2); }
+static int variant_channels(int variant)
+{
+    const int v = variant & 3;
+    return v == 2 ? 3 : (v == 3 ? 1 : 2);
+}
 hipError_t launch_main_multi(const MainArgs* items, const int64_t* tile_start, int n_items, unsigned long long* counter,
                              int variant, int L, int waves, bool mixed, int grid, hipStream_t s)
 {
@@ -2008,7 +2432,34 @@ void launch_gtab(const GridArgs& g, int lg, int64_t nsub, double* tab, hipStream
 }
 void launch_waveform(const MainArgs& a, double* h_ri, hipStream_t s)
 {
+    if (a.m.sparse > 0) {
+        const dim3 grid(nblk(a.g.K, 128));
+        if (a.g.nch == 3) hipLaunchKernelGGL(k_waveform_spline<3>, grid, dim3(128), 0, s, a, h_ri);
+        else if (a.g.nch == 2) hipLaunchKernelGGL(k_waveform_spline<2>, grid, dim3(128), 0, s, a, h_ri);
+        else hipLaunchKernelGGL(k_waveform_spline<1>, grid, dim3(128), 0, s, a, h_ri);
+        return;
+    }
     hipLaunchKernelGGL(k_waveform, dim3(nblk(a.g.K, 128)), dim3(128), 0, s, a, h_ri);
+}
+void launch_spline(const SplineArgs& a, hipStream_t s)
+{
+    if (a.P <= 0 || a.m.sparse <= 0) return;
+    const dim3 gn(nblk(a.P * a.nmax, 256)), b(256);
+    const int nq = spl_nq(a.g.nch);
+    const dim3 gs(nblk(a.P * nq, 64)), bs(64);
+    if (a.m.response == 2 && a.g.nch == 3) {
+        hipLaunchKernelGGL((k_spline_nodes<3, 2>), gn, b, 0, s, a);
+        hipLaunchKernelGGL(k_spline_solve<3>, gs, bs, 0, s, a);
+    } else if (a.m.response == 2) {
+        hipLaunchKernelGGL((k_spline_nodes<2, 2>), gn, b, 0, s, a);
+        hipLaunchKernelGGL(k_spline_solve<2>, gs, bs, 0, s, a);
+    } else if (a.m.response == 1) {
+        hipLaunchKernelGGL((k_spline_nodes<2, 1>), gn, b, 0, s, a);
+        hipLaunchKernelGGL(k_spline_solve<2>, gs, bs, 0, s, a);
+    } else {
+        hipLaunchKernelGGL((k_spline_nodes<1, 0>), gn, b, 0, s, a);
+        hipLaunchKernelGGL(k_spline_solve<1>, gs, bs, 0, s, a);
+    }
 }
 void launch_pso_init(int64_t P, const PsoBox& box, uint64_t seed, uint32_t swarm, double* theta, hipStream_t s)
 {

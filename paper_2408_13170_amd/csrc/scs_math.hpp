@@ -36,7 +36,8 @@ enum Coef : int {
     C_DC, C_DS,            // Doppler [cycles/Hz] = dc cos(Phi_orb) + ds sin(Phi_orb)
     C_RESP,                // 36 response trig-polynomial coefficients: R_A re, R_A im, R_E re, R_E im
                            // (full response: the source record FdSlot instead)
-    C_COUNT = C_RESP + 36
+    C_TCL = C_RESP + 36,   // low part of t_c in double-double: t_c = C_TC + C_TCL
+    C_COUNT
 };
 
 // Source record of the full response, at C_RESP: direction to the source,
