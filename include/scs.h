@@ -528,6 +528,19 @@ int scs_kmeans(const double* x, int64_t n, int32_t dim, int32_t k, int32_t iters
 /* Thread-local description of the last error on this thread ("" if none). */
 const char* scs_last_error(void);
 
+/* ---- measurement ---------------------------------------------------- */
+
+/* Peak microbenchmark of device `device`, the measured ceilings beside the
+ * published ones that the generate-and-reduce kernels are compared with:
+ *   out[0]  FP64 FMA rate, TFLOP/s (eight independent chains per lane)
+ *   out[1]  FP32 FMA rate, TFLOP/s (non-packed instructions)
+ *   out[2]  FP32 hardware sine rate, 1e12 per second
+ *   out[3]  HBM streaming copy, TB/s of bytes read plus written (512 MiB each way)
+ *   out[4]  the device clock HIP reports, GHz
+ * Allocates 1 GiB of device memory for the copy and frees it.  Synchronous.
+ * Errors: SCS_EINVAL (out NULL), SCS_ENOMEM, SCS_EDEVICE. */
+int scs_peak_probe(int32_t device, double* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -116,6 +116,7 @@ _SIGS = {
     "scs_pso_best": [C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
     "scs_theta_dim": [C.c_void_p, C.POINTER(C.c_int32)],
+    "scs_peak_probe": [C.c_int32, C.POINTER(C.c_double)],
     "scs_ctx_info": [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                      C.POINTER(C.c_int64)],
     "scs_server_create": [C.POINTER(C.c_void_p), C.c_int32, C.c_int32, C.c_uint64, C.c_int32],
@@ -678,3 +679,12 @@ def scs_server_clock(srv):
 
 def scs_server_destroy(srv):
     _check(lib().scs_server_destroy(srv))
+
+
+def scs_peak_probe(device=0):
+    """Measured device ceilings: FP64 and FP32 FMA TFLOP/s, FP32 sines per
+    second (1e12), HBM copy TB/s (read + write), HIP's clock in GHz."""
+    out = np.zeros(5)
+    _check(lib().scs_peak_probe(device, out.ctypes.data_as(C.POINTER(C.c_double))))
+    return {"fp64_tflops": out[0], "fp32_tflops": out[1], "sin32_per_s_1e12": out[2], "hbm_copy_tbps": out[3],
+            "clock_ghz": out[4]}

@@ -5,7 +5,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = [os.path.join(HERE, "csrc", f) for f in ("scs_kernels.hip", "scs_host.hip", "scs_search.hip")]
+SRC = [os.path.join(HERE, "csrc", f) for f in ("scs_kernels.hip", "scs_host.hip", "scs_search.hip", "scs_probe.hip")]
 OUT = os.path.join(HERE, "libscs.so")
 
 FLAGS = [
@@ -22,7 +22,7 @@ FLAGS = [
 ]
 
 
-def build(verbose=False, jobs=3):
+def build(verbose=False, jobs=4):
     os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
     objs = []
     procs = []
