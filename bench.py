@@ -409,8 +409,9 @@ def bench_batched_core(B, torch, dev, steps, warmup, tune_cache=None):
     """Six swarms of the hierarchy, (N, P) = (4096, 16384) ... (1, 128), on the
     2^20-bin A+E data in ONE graph-captured batched launch (one persistent
     generate-and-reduce kernel over all tiles), FP64 and mixed, first with
-    the default launch shapes, then with the shapes the autotuner picks for
-    each swarm (cached in tune_cache when given); mixed error per level
+    the default launch shapes, then with the shapes the batch autotuner picks
+    (the launch occupancy and each swarm's LDS block and chunk, timed as the
+    whole batched evaluation; cached in tune_cache when given); mixed error per level
     against FP64 (floored at 2 N_eff)."""
     w = synth.workload("lisa1m")
     ctx, _ = make_search(B, torch, w, dev)
@@ -452,8 +453,7 @@ def bench_batched_core(B, torch, dev, steps, warmup, tune_cache=None):
         log(f"batched {name}, default shapes: {r['value']:.4g} evals/s, {r['ms_per_batch']:.2f} ms per batch")
     t0 = time.perf_counter()
     for prec in (B.SCS_PREC_FP64, B.SCS_PREC_MIXED):
-        for it in items:
-            B.scs_autotune(ctx, it[2], it[1], prec, tune_cache)
+        B.scs_autotune_batch(items, prec, tune_cache)
     tune_s = time.perf_counter() - t0
     for prec, name in ((B.SCS_PREC_FP64, "fp64"), (B.SCS_PREC_MIXED, "mixed")):
         res[name] = timed(prec)
@@ -892,12 +892,30 @@ def cpu_baseline(w, psd, d_ri, seconds, fd=False):
         t1 += time.perf_counter() - t0
         e1 += int(out["support"][0, 1] - out["support"][0, 0])
         n1 += 1
+    # the 16384-bin single-channel configuration in full: 64 particles, one
+    # thread, then every thread (data: the configuration's noise; the oracle's
+    # cost does not depend on the values)
+    w1 = synth.workload("white16k")
+    g1 = O.Grid(w1.grid.K, w1.grid.k0, w1.grid.df, 1)
+    m1 = O.Model(pn_order=w1.pn_order, response=O.RESP_NONE, support=O.SUPPORT_FULL, t_obs=w1.grid.t_obs)
+    psd1 = synth.psd_arrays(w1)
+    n1c = synth.noise(psd1, w1.grid.df, w1.seed)
+    d1 = np.ascontiguousarray(np.stack([n1c.real, n1c.imag], -1))
+    th1 = synth.workload_particles(w1)
+    cfg1 = {}
+    for nt, name in ((1, "single_core"), (threads, "all_cores")):
+        t0 = time.perf_counter()
+        O.evaluate(g1, m1, d1, psd1, th1, w1.N, O.SEG_EQUAL_SNR, w1.G, n_threads=nt)
+        dt = time.perf_counter() - t0
+        cfg1[name] = {"value": th1.shape[0] * w1.grid.K / dt, "unit": "evals/s", "threads": nt, "seconds": dt}
     model, ncpu = cpu_model()
     return {"value": evals / t, "unit": "evals/s", "cores": threads, "kind": "oracle",
             "sample": f"{used} particles of the same workload (full 2^20-bin grid, N_seg 1024), {t:.1f} s "
                       f"on {threads} threads; {n1} more particles on one thread, {t1:.1f} s",
             "single_core": {"value": e1 / t1, "unit": "evals/s", "particles": n1, "seconds": t1},
-            "cpu_model": model, "logical_cpus": ncpu}
+            "cpu_model": model, "logical_cpus": ncpu,
+            "config1": dict(cfg1, workload="16384 bins, one channel, unit white PSD, 2PN, N_seg 16, 64 particles "
+                                           "(the whole configuration)")}
 
 
 if __name__ == "__main__":

@@ -148,8 +148,12 @@ int scs_define_segmentation(scs_ctx* ctx, int32_t N, int32_t mode, int32_t G, co
  *   theta  [P][D], D = scs_theta_dim (7, or 8 for an eccentric model)
  *   ups    [P] out: Upsilon_N; NaN for invalid theta (Mc <= 0, eta outside
  *          (0, 1/4], f_low <= 0, non-finite) or a theta the polynomial block
- *          scheme cannot resolve (counted by scs_ctx_stats); 0 when the
- *          support is empty
+ *          scheme cannot resolve (counted by scs_ctx_stats): one whose SPA
+ *          time moves so fast per bin that even 8-bin blocks leave the phase
+ *          remainder above 1e-12 cycles or the response's above 1e-11, i.e. a
+ *          slowly chirping low-mass source on a coarse grid (on the 2^20-bin
+ *          band from 0.016 Hz, chirp times above ~270 yr at the support start;
+ *          never with the sparse-grid template); 0 when the support is empty
  *   seg    [P][N][3] out, nullable: (Re Z_n, Im Z_n, H_n) with
  *          Z_n = sum_{k in n} sum_alpha d conj(h) / S and H_n = sum w(k), so that
  *          x_n = 4 df |Z_n| and [h|h]_n = 4 df H_n
@@ -310,13 +314,27 @@ int scs_graph_create(scs_graph** out, const scs_batch_item* items, int32_t n_ite
 int scs_graph_launch(scs_graph* g, void* stream);
 int scs_graph_destroy(scs_graph* g);
 
-/* Tile-shape autotuner: time the candidate launch shapes (waves per
- * workgroup, bins per chunk) of the generate-and-reduce kernel on this
- * context for the P particles theta_dev (device [P][D]) and N segments, and
- * keep the fastest for later calls with a similar (P, N, prec).  cache_path
- * (nullable) is a text file of "key waves blocks" lines, read before tuning
- * (a hit skips the timing) and rewritten after. */
+/* Tile-shape autotuner.  A launch shape of the generate-and-reduce kernel is
+ * (waves per workgroup 1 | 2 | 4, bins per LDS-staged block 256 | 512 | 1024,
+ * bins per chunk 1024 .. 8192, occupancy: the default instantiation or the
+ * alternative one, two waves per SIMD for FP64 and four for mixed, with the
+ * per-bin template on one or two channels).  scs_autotune times candidate
+ * shapes for the P particles theta_dev (device [P][D]) and N segments of
+ * this context by coordinate descent from the default shape (each
+ * coordinate in turn, twice over) and keeps the fastest for later calls of
+ * the same (P, N, precision) class, solo or batched.  The shape changes only
+ * the order in which segment pieces are joined: results agree to rounding.
+ * cache_path (nullable) is a text file of "key waves blocks L alt" lines, read
+ * before tuning (a hit skips the timing) and rewritten after. */
 int scs_autotune(scs_ctx* ctx, int64_t P, const double* theta_dev, int32_t N, int32_t prec, const char* cache_path);
+
+/* The same for a batch as scs_evaluate_batched runs it (one fused launch,
+ * four waves per workgroup): the launch's occupancy, then each item's LDS
+ * block and chunk length (items with the most work first), each candidate
+ * timed as the whole batched evaluation.  The shapes found are kept per item
+ * class like scs_autotune's, so later batched calls, graphs built afterwards
+ * and the server use them.  Errors as scs_evaluate_batched. */
+int scs_autotune_batch(const scs_batch_item* items, int32_t n_items, int32_t prec, const char* cache_path);
 
 /* ---- serving ------------------------------------------------------- */
 

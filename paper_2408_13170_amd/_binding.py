@@ -117,6 +117,7 @@ _SIGS = {
                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
     "scs_theta_dim": [C.c_void_p, C.POINTER(C.c_int32)],
     "scs_peak_probe": [C.c_int32, C.POINTER(C.c_double)],
+    "scs_autotune_batch": [C.POINTER(scs_batch_item), C.c_int32, C.c_int32, C.c_char_p],
     "scs_ctx_info": [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                      C.POINTER(C.c_int64)],
     "scs_server_create": [C.POINTER(C.c_void_p), C.c_int32, C.c_int32, C.c_uint64, C.c_int32],
@@ -458,6 +459,12 @@ def scs_graph_launch(graph, stream=None):
 
 def scs_graph_destroy(graph):
     _check(lib().scs_graph_destroy(graph))
+
+
+def scs_autotune_batch(items, prec=SCS_PREC_FP64, cache_path=None):
+    """items: as scs_evaluate_batched."""
+    arr = _items(items)
+    _check(lib().scs_autotune_batch(arr, len(items), prec, cache_path.encode() if cache_path else None))
 
 
 def scs_autotune(ctx, theta_cuda, N, prec=SCS_PREC_FP64, cache_path=None):

@@ -182,9 +182,14 @@ struct BatchSlot {
     hipEvent_t done = nullptr;                 // recorded after the last launch that read the slot
 };
 
+// Launch shape of the generate-and-reduce: waves per workgroup (64 particle
+// slots each), LDS-staged blocks per chunk, bins per LDS block, and the
+// occupancy instantiation (alt: two waves per SIMD for FP64, four for mixed).
 struct TuneChoice {
     int waves = 4;
     int CB = 16;
+    int L = 512;
+    int alt = 0;
 };
 
 struct scs_ctx {
@@ -512,7 +517,8 @@ static std::string tune_key(const scs_ctx* c, int64_t P, int N, int prec)
         return b;
     };
     std::ostringstream o;
-    o << "K" << c->g.K << "_c" << c->g.nch << "_L" << c->L << "_p" << prec << "_P" << cls(P) << "_N" << cls(N);
+    o << "K" << c->g.K << "_c" << c->g.nch << "_r" << c->m.response << "_s" << c->m.sparse << "_p" << prec << "_P"
+      << cls(P) << "_N" << cls(N);
     return o.str();
 }
 
@@ -536,12 +542,14 @@ static TuneChoice default_choice(const scs_ctx* c, int64_t P)
     // evenly (with 8192-bin chunks the last tiles ran ~15% of the launch
     // alone), and no block straddles two chunks
     t.waves = P >= 4096 ? 4 : (P >= 1024 ? 2 : 1);
-    t.CB = std::max(1, (1 << c->lg_max) / c->L);
+    t.L = c->L;
+    t.CB = std::max(1, (1 << c->lg_max) / t.L);
+    t.alt = 0;
     return t;
 }
 
 struct Plan {
-    int waves, CB;
+    int waves, CB, L, alt;
     int64_t cbins, n_chunks, n_groups, n_tiles;
 };
 
@@ -550,7 +558,9 @@ static Plan make_plan(const scs_ctx* c, int64_t P, const TuneChoice& t)
     Plan pl;
     pl.waves = t.waves;
     pl.CB = t.CB;
-    pl.cbins = (int64_t)c->L * t.CB;
+    pl.L = t.L;
+    pl.alt = t.alt;
+    pl.cbins = (int64_t)t.L * t.CB;
     pl.n_chunks = (c->g.K + pl.cbins - 1) / pl.cbins;
     pl.n_groups = (P + 64 * t.waves - 1) / (64 * t.waves);
     pl.n_tiles = pl.n_chunks * pl.n_groups;
@@ -720,7 +730,7 @@ static int eval_front(EvalJob& j, const double* theta, double* ups, double* seg,
     ma.P_end = P;
     ma.stride = w.capP;
     ma.N = N;
-    ma.L = c->L;
+    ma.L = j.pl.L;
     ma.CB = j.pl.CB;
     ma.chunk0 = 0;
     ma.n_groups = j.pl.n_groups;
@@ -981,9 +991,10 @@ extern "C" int scs_evaluate_noalloc(scs_ctx* c, int64_t P, const double* theta, 
     hipLaunchKernelGGL(k_put_main_args, dim3(1), dim3(1), 0, s, j.ma, d_items, d_start, j.pl.n_tiles, d_counter);
     const int variant = variant_of(c->m.response, c->g.nch, c->m.sparse);
     const bool mixed = prec == SCS_PREC_MIXED;
-    const int per_cu = main_multi_blocks_per_cu(variant, c->L, j.pl.waves, mixed);
+    const int per_cu = main_multi_blocks_per_cu(variant, j.pl.L, j.pl.waves, mixed, j.pl.alt != 0);
     const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(j.pl.n_tiles, (int64_t)c->n_cu * per_cu));
-    hipError_t e = launch_main_multi(d_items, d_start, 1, d_counter, variant, c->L, j.pl.waves, mixed, (int)grid, s);
+    hipError_t e = launch_main_multi(d_items, d_start, 1, d_counter, variant, j.pl.L, j.pl.waves, mixed,
+                                     j.pl.alt != 0, (int)grid, s);
     if (e != hipSuccess) return fail(SCS_EDEVICE, "generate-and-reduce launch failed: %s", hipGetErrorString(e));
     launch_finalize(j.fa, s);
     e = hipGetLastError();
@@ -1402,6 +1413,9 @@ static int fused_main(std::vector<EvalJob>& jobs, int waves, bool mixed, hipStre
     for (int gi = 0; gi < kVariants; ++gi) {
         int cnt = 0;
         int64_t total = 0;
+        int Lmax = 0;           // the launch stages up to the longest LDS block of its items
+        int alt = 0;            // and takes the occupancy of its item with the most tiles
+        int64_t most = -1;
         int64_t* hs = b.h_start + gi * (b.cap + 1);
         for (int i = 0; i < n_items; ++i) {
             const EvalJob& j = jobs[i];
@@ -1411,6 +1425,11 @@ static int fused_main(std::vector<EvalJob>& jobs, int waves, bool mixed, hipStre
                 hs[cnt] = total;
             }
             total += j.pl.n_tiles;
+            Lmax = std::max(Lmax, j.pl.L);
+            if (j.pl.n_tiles > most) {
+                most = j.pl.n_tiles;
+                alt = j.pl.alt;
+            }
             ++cnt;
         }
         if (!cnt) continue;
@@ -1420,12 +1439,12 @@ static int fused_main(std::vector<EvalJob>& jobs, int waves, bool mixed, hipStre
             HIP_TRY(hipMemcpyAsync(b.d_start + gi * (b.cap + 1), hs, sizeof(int64_t) * (cnt + 1), hipMemcpyHostToDevice, s));
         }
         launch_fill_u64(b.d_counter + gi, 1, 0ULL, s);
-        const int per_cu = main_multi_blocks_per_cu(gi, c0->L, waves, mixed);
+        const int per_cu = main_multi_blocks_per_cu(gi, Lmax, waves, mixed, alt != 0);
         const int64_t grid = std::min<int64_t>(total, (int64_t)c0->n_cu * per_cu);
         hipEvent_t e0;
         prof_begin(c0, s, &e0);
-        hipError_t e = launch_main_multi(b.d_items + off, b.d_start + gi * (b.cap + 1), cnt, b.d_counter + gi, gi, c0->L,
-                                         waves, mixed, (int)grid, s);
+        hipError_t e = launch_main_multi(b.d_items + off, b.d_start + gi * (b.cap + 1), cnt, b.d_counter + gi, gi, Lmax,
+                                         waves, mixed, alt != 0, (int)grid, s);
         if (e != hipSuccess) return fail(SCS_EDEVICE, "generate-and-reduce launch failed: %s", hipGetErrorString(e));
         prof_end(c0, s, e0);
         off += cnt;
@@ -1456,7 +1475,7 @@ static int eval_main(scs_ctx* c, EvalJob& j, int prec, hipStream_t s)
 // wss[i] (nullable) is the workspace of item i; by default slot 1 + i of its
 // context.
 static int run_batched(const scs_batch_item* items, int n_items, int prec, hipStream_t s, BatchSlot& b, bool upload,
-                       Workspace* const* wss = nullptr)
+                       Workspace* const* wss = nullptr, const TuneChoice* force = nullptr)
 {
     const bool mixed = prec == SCS_PREC_MIXED;
     constexpr int kWaves = 4;  // workgroup shape of the fused launch
@@ -1468,7 +1487,7 @@ static int run_batched(const scs_batch_item* items, int n_items, int prec, hipSt
         j.w = (wss && wss[i]) ? wss[i] : &it.ctx->ws[1 + i];
         j.P = it.P;
         j.N = it.N;
-        TuneChoice t = choose(it.ctx, it.P, it.N, prec);
+        TuneChoice t = force ? force[i] : choose(it.ctx, it.P, it.N, prec);
         t.waves = kWaves;
         int rc = eval_front(j, it.theta, it.ups, it.seg, t, s);
         if (rc) return rc;
@@ -2011,32 +2030,90 @@ extern "C" int scs_server_destroy(scs_server* srv)
 }
 
 // ---------------------------------------------------------------- autotuner
-static void load_cache(scs_ctx* c, const char* path)
+// Cache file: one "key waves blocks L alt" line per evaluation class (a line
+// of the older "key waves blocks" form reads as L = 512 and alt = 0).
+static bool choice_ok(const TuneChoice& t)
+{
+    return (t.waves == 1 || t.waves == 2 || t.waves == 4) && t.CB >= 1 && t.CB <= 64 &&
+           (t.L == 256 || t.L == 512 || t.L == 1024) && (t.alt == 0 || t.alt == 1);
+}
+
+static void read_cache(const char* path, std::map<std::string, TuneChoice>& into)
 {
     std::ifstream f(path);
-    std::string key;
-    int w, cb;
-    while (f >> key >> w >> cb) {
-        if (w == 1 || w == 2 || w == 4) c->tune[key] = TuneChoice{w, std::max(1, cb)};
+    std::string line;
+    while (std::getline(f, line)) {
+        std::istringstream is(line);
+        std::string key;
+        TuneChoice t;
+        if (!(is >> key >> t.waves >> t.CB)) continue;
+        if (!(is >> t.L >> t.alt)) {
+            t.L = 512;
+            t.alt = 0;
+        }
+        if (choice_ok(t)) into[key] = t;
     }
 }
 
-static void save_cache(const scs_ctx* c, const char* path)
+static void save_cache(const std::map<std::string, TuneChoice>& tune, const char* path)
 {
     std::map<std::string, TuneChoice> all;
-    {
-        std::ifstream f(path);
-        std::string key;
-        int w, cb;
-        while (f >> key >> w >> cb) all[key] = TuneChoice{w, cb};
-    }
-    for (auto& kv : c->tune) all[kv.first] = kv.second;
+    read_cache(path, all);
+    for (auto& kv : tune) all[kv.first] = kv.second;
     std::string tmp = std::string(path) + ".tmp";
     {
         std::ofstream o(tmp);
-        for (auto& kv : all) o << kv.first << " " << kv.second.waves << " " << kv.second.CB << "\n";
+        for (auto& kv : all)
+            o << kv.first << " " << kv.second.waves << " " << kv.second.CB << " " << kv.second.L << " "
+              << kv.second.alt << "\n";
     }
     std::rename(tmp.c_str(), path);
+}
+
+// The candidate values of each coordinate of a shape.  The alternative
+// occupancy exists for the per-bin template on one and two channels.
+static const int kTuneWaves[] = {1, 2, 4};
+static const int kTuneL[] = {256, 512, 1024};
+static const int kTuneChunk[] = {1024, 2048, 4096, 8192};  // bins per chunk (L x CB)
+static bool has_alt(const scs_ctx* c) { return c->m.sparse == 0 && c->g.nch <= 2; }
+
+// Candidates along one coordinate d (0 waves, 1 LDS block, 2 chunk, 3
+// occupancy) of shape t.
+static std::vector<TuneChoice> along(const scs_ctx* c, const TuneChoice& t, int d, bool waves_fixed)
+{
+    std::vector<TuneChoice> v;
+    if (d == 0 && !waves_fixed)
+        for (int w : kTuneWaves) { TuneChoice x = t; x.waves = w; v.push_back(x); }
+    if (d == 1) {
+        const int chunk = t.L * t.CB;
+        for (int L : kTuneL) { TuneChoice x = t; x.L = L; x.CB = std::max(1, chunk / L); v.push_back(x); }
+    }
+    if (d == 2)
+        for (int ch : kTuneChunk) { TuneChoice x = t; x.CB = std::max(1, ch / t.L); v.push_back(x); }
+    if (d == 3 && has_alt(c))
+        for (int a = 0; a <= 1; ++a) { TuneChoice x = t; x.alt = a; v.push_back(x); }
+    return v;
+}
+
+static bool same_shape(const TuneChoice& a, const TuneChoice& b)
+{
+    return a.waves == b.waves && a.CB == b.CB && a.L == b.L && a.alt == b.alt;
+}
+
+// Time fn (which queues one evaluation on s): one untimed run, then the mean
+// of `reps`; negative on an error (recorded).
+template <class Fn>
+static double time_on(hipStream_t s, hipEvent_t e0, hipEvent_t e1, int reps, Fn fn)
+{
+    if (fn()) return -1.0;
+    if (hipEventRecord(e0, s) != hipSuccess) return fail(SCS_EDEVICE, "event record failed"), -1.0;
+    for (int r = 0; r < reps; ++r)
+        if (fn()) return -1.0;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+        return fail(SCS_EDEVICE, "timing a candidate failed"), -1.0;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return fail(SCS_EDEVICE, "event timing failed"), -1.0;
+    return ms / reps;
 }
 
 extern "C" int scs_autotune(scs_ctx* c, int64_t P, const double* theta_dev, int32_t N, int32_t prec,
@@ -2047,44 +2124,42 @@ extern "C" int scs_autotune(scs_ctx* c, int64_t P, const double* theta_dev, int3
     if (P < 1 || N < 1 || N > SCS_MAX_SEGMENTS) return fail(SCS_EINVAL, "bad P or N");
     const std::string key = tune_key(c, P, N, prec);
     if (cache_path) {
-        load_cache(c, cache_path);
+        read_cache(cache_path, c->tune);
         if (c->tune.count(key)) return SCS_OK;
     }
     if (!theta_dev) return fail(SCS_EINVAL, "theta is NULL");
     DevScope ds(c->device);
-    const int64_t Pt = P;
-    const double* th = theta_dev;
     double* ups = nullptr;
-    HIP_TRY(hipMalloc((void**)&ups, sizeof(double) * Pt));
+    HIP_TRY(hipMalloc((void**)&ups, sizeof(double) * P));
     hipStream_t s;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
         hipFree(ups);
         return fail(SCS_EDEVICE, "stream creation failed");
     }
     Workspace tw;
-    TuneChoice best;
-    double best_ms = 1e300;
-    const int cbs[] = {2, 4, 8, 16, 32};  // chunks of 1024 .. 16384 bins
-    const int wvs[] = {1, 2, 4};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         rc = fail(SCS_EDEVICE, "event creation failed");
-    for (int wv : wvs)
-        for (int cb0 : cbs) {
-            if (rc) break;
-            TuneChoice t{wv, std::max(1, cb0 * 512 / c->L)};
-            if ((rc = run_eval(c, tw, Pt, N, th, prec, ups, nullptr, s, &t))) break;  // warm-up, sizes tw
-            if (hipEventRecord(e0, s) != hipSuccess) rc = fail(SCS_EDEVICE, "event record failed");
-            for (int r = 0; r < 3 && !rc; ++r) rc = run_eval(c, tw, Pt, N, th, prec, ups, nullptr, s, &t);
-            if (!rc && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
-                rc = fail(SCS_EDEVICE, "timing the candidate failed");
-            float ms = 0.f;
-            if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = fail(SCS_EDEVICE, "event timing failed");
-            if (!rc && ms < best_ms) {
-                best_ms = ms;
-                best = t;
+    // coordinate descent from the default shape: waves, LDS block, chunk,
+    // occupancy, twice over
+    TuneChoice best = default_choice(c, P);
+    double best_ms = 1e300;
+    for (int pass = 0; pass < 2 && !rc; ++pass)
+        for (int d = 0; d < 4 && !rc; ++d)
+            for (const TuneChoice& t : along(c, best, d, false)) {
+                if (pass + d > 0 && same_shape(t, best)) continue;  // timed already
+                const double ms = time_on(s, e0, e1, 3, [&] {
+                    return run_eval(c, tw, P, N, theta_dev, prec, ups, nullptr, s, &t);
+                });
+                if (ms < 0.0) {
+                    rc = SCS_EDEVICE;
+                    break;
+                }
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = t;
+                }
             }
-        }
     hipStreamSynchronize(s);
     if (e0) hipEventDestroy(e0);
     if (e1) hipEventDestroy(e1);
@@ -2093,7 +2168,92 @@ extern "C" int scs_autotune(scs_ctx* c, int64_t P, const double* theta_dev, int3
     hipFree(ups);
     if (rc) return rc;
     c->tune[key] = best;
-    if (cache_path) save_cache(c, cache_path);
+    if (cache_path) save_cache(c->tune, cache_path);
+    return SCS_OK;
+}
+
+extern "C" int scs_autotune_batch(const scs_batch_item* items, int32_t n_items, int32_t prec, const char* cache_path)
+{
+    int rc = check_items(items, n_items, prec);
+    if (rc || n_items == 0) return rc;
+    scs_ctx* c0 = items[0].ctx;
+    std::vector<std::string> keys(n_items);
+    bool all_cached = cache_path != nullptr;
+    for (int i = 0; i < n_items; ++i) {
+        keys[i] = tune_key(items[i].ctx, items[i].P, items[i].N, prec);
+        if (cache_path) read_cache(cache_path, items[i].ctx->tune);
+        all_cached = all_cached && items[i].ctx->tune.count(keys[i]);
+    }
+    if (all_cached) return SCS_OK;
+    DevScope ds(c0->device);
+    hipStream_t s;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return fail(SCS_EDEVICE, "stream creation failed");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        rc = fail(SCS_EDEVICE, "event creation failed");
+    BatchSlot& b = c0->ring[c0->ring_next];
+    c0->ring_next = (c0->ring_next + 1) % scs_ctx::kRing;
+    if (!rc) rc = slot_reserve(b, n_items);
+    std::vector<TuneChoice> cur(n_items);
+    for (int i = 0; i < n_items; ++i) {
+        cur[i] = choose(items[i].ctx, items[i].P, items[i].N, prec);
+        cur[i].waves = 4;  // the fused launch's workgroup shape
+    }
+    auto batch_ms = [&](const std::vector<TuneChoice>& sh) {
+        return time_on(s, e0, e1, 2, [&] { return run_batched(items, n_items, prec, s, b, true, nullptr, sh.data()); });
+    };
+    double best_ms = rc ? -1.0 : batch_ms(cur);
+    if (best_ms < 0.0 && !rc) rc = SCS_EDEVICE;
+    // the occupancy of the launch, then each item's LDS block and chunk,
+    // items with the most tiles first
+    if (!rc) {
+        bool any_alt = false;
+        for (int i = 0; i < n_items; ++i) any_alt = any_alt || has_alt(items[i].ctx);
+        if (any_alt) {
+            std::vector<TuneChoice> alt = cur;
+            for (auto& t : alt) t.alt = 1 - t.alt;
+            const double ms = batch_ms(alt);
+            if (ms < 0.0) rc = SCS_EDEVICE;
+            else if (ms < best_ms) {
+                best_ms = ms;
+                cur = alt;
+            }
+        }
+    }
+    std::vector<int> order(n_items);
+    for (int i = 0; i < n_items; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int a, int b2) {
+        return (double)items[a].P * items[a].N > (double)items[b2].P * items[b2].N;
+    });
+    for (int oi = 0; oi < n_items && !rc; ++oi) {
+        const int i = order[oi];
+        if (items[i].P == 0) continue;
+        for (int d = 1; d <= 2 && !rc; ++d)
+            for (const TuneChoice& t : along(items[i].ctx, cur[i], d, true)) {
+                if (same_shape(t, cur[i])) continue;
+                std::vector<TuneChoice> trial = cur;
+                trial[i] = t;
+                const double ms = batch_ms(trial);
+                if (ms < 0.0) {
+                    rc = SCS_EDEVICE;
+                    break;
+                }
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    cur = trial;
+                }
+            }
+    }
+    if (b.done) hipEventRecord(b.done, s);
+    hipStreamSynchronize(s);
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    hipStreamDestroy(s);
+    if (rc) return rc;
+    for (int i = 0; i < n_items; ++i) {
+        items[i].ctx->tune[keys[i]] = cur[i];
+        if (cache_path) save_cache(items[i].ctx->tune, cache_path);
+    }
     return SCS_OK;
 }
 

@@ -237,9 +237,12 @@ __host__ __device__ constexpr int variant_of(int resp, int nch, int sparse)
 {
     return (resp == 1 ? 0 : (resp == 2 ? (nch == 3 ? 2 : 1) : 3)) + (sparse > 0 ? 4 : 0);
 }
+// alt: the instantiation with the alternative occupancy target (two waves
+// per SIMD for FP64, four for mixed; the per-bin template on one and two
+// channels), for the autotuner
 hipError_t launch_main_multi(const MainArgs* items, const int64_t* tile_start, int n_items, unsigned long long* counter,
-                             int variant, int L, int waves, bool mixed, int grid, hipStream_t s);
-int main_multi_blocks_per_cu(int variant, int L, int waves, bool mixed);
+                             int variant, int L, int waves, bool mixed, bool alt, int grid, hipStream_t s);
+int main_multi_blocks_per_cu(int variant, int L, int waves, bool mixed, bool alt);
 void launch_finalize(const FinalArgs& a, hipStream_t s);
 void launch_waveform(const MainArgs& a, double* h_ri, hipStream_t s);
 void launch_gtab(const GridArgs& g, int lg, int64_t nsub, double* tab, hipStream_t s);

@@ -1235,16 +1235,20 @@ __device__ __forceinline__ void bin_mixed(float jf, const float* __restrict__ bi
 }
 
 // Occupancy target (waves per SIMD), measured on MI355X: three for both
-// (168 VGPRs; what spills is block set-up code, not the bin loop).  Against
-// two waves (256 VGPRs, no spills) the FP64 kernel gains 2% on 1024
-// segments and 10% on the six-swarm hierarchy, whose many-segment levels
-// stall on events more; four waves are no faster for mixed.
+// (168 VGPRs; what spills is block set-up code, not the bin loop).  On the
+// 2^20-bin step two waves (256 VGPRs, no spills) are within noise of three
+// for FP64, and four are no faster for mixed; the autotuner can pick these
+// alternatives (ALT) per evaluation class.
 #ifndef SCS_WAVES_FP64
 #define SCS_WAVES_FP64 3
 #endif
 #ifndef SCS_WAVES_MIXED
 #define SCS_WAVES_MIXED 3
 #endif
+__host__ __device__ constexpr int main_waves_per_eu(int nch, bool mixed, bool alt)
+{
+    return mixed ? (alt ? 4 : SCS_WAVES_MIXED) : (nch == 3 ? 2 : (alt ? 2 : SCS_WAVES_FP64));
+}
 // Plain FP32 partial sums cover the bins between consecutive multiples of
 // this (and a lane's own segment edges) before their compensated addition.
 constexpr int kMixedRun = 32;
@@ -1688,9 +1692,9 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
 // particle groups of one chunk, so workgroups running together share the
 // chunk's data in L2.  tile_start[i] is the first global tile of item i (prefix sums,
 // tile_start[n_items] = total); the counter starts at 0.
-template <int NCH, bool MIXED, int RM, int TM>
+template <int NCH, bool MIXED, int RM, int TM, bool ALT = false>
 __global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(MIXED ? SCS_WAVES_MIXED : (NCH == 3 ? 2 : SCS_WAVES_FP64)))) void k_main_multi(
+__attribute__((amdgpu_waves_per_eu(main_waves_per_eu(NCH, MIXED, ALT)))) void k_main_multi(
     const MainArgs* __restrict__ items, const int64_t* __restrict__ tile_start, int n_items,
     unsigned long long* __restrict__ counter)
 {
@@ -2309,8 +2313,18 @@ size_t main_lds_bytes(int nch, int L, bool mixed) { return (size_t)L * bin_strid
 // The generate-and-reduce instantiation of a kernel variant (variant_of) and
 // precision.
 typedef void (*MainKernel)(const MainArgs*, const int64_t*, int, unsigned long long*);
-static MainKernel main_kernel(int variant, bool mixed)
+static MainKernel main_kernel(int variant, bool mixed, bool alt)
 {
+    // the alternative occupancy exists for the per-bin template on one and
+    // two channels (three channels already run at two waves)
+    if (alt) {
+        switch (variant) {
+        case 0: return mixed ? k_main_multi<2, true, 1, 0, true> : k_main_multi<2, false, 1, 0, true>;
+        case 1: return mixed ? k_main_multi<2, true, 2, 0, true> : k_main_multi<2, false, 2, 0, true>;
+        case 3: return mixed ? k_main_multi<1, true, 0, 0, true> : k_main_multi<1, false, 0, 0, true>;
+        default: break;
+        }
+    }
     switch (variant) {
     case 0: return mixed ? k_main_multi<2, true, 1, 0> : k_main_multi<2, false, 1, 0>;
     case 1: return mixed ? k_main_multi<2, true, 2, 0> : k_main_multi<2, false, 2, 0>;
@@ -2328,18 +2342,19 @@ static int variant_channels(int variant)
     return v == 2 ? 3 : (v == 3 ? 1 : 2);
 }
 hipError_t launch_main_multi(const MainArgs* items, const int64_t* tile_start, int n_items, unsigned long long* counter,
-                             int variant, int L, int waves, bool mixed, int grid, hipStream_t s)
+                             int variant, int L, int waves, bool mixed, bool alt, int grid, hipStream_t s)
 {
     const size_t lds = main_lds_bytes(variant_channels(variant), L, mixed);
-    hipLaunchKernelGGL(main_kernel(variant, mixed), dim3(grid), dim3(64 * waves), lds, s, items, tile_start, n_items,
-                       counter);
+    hipLaunchKernelGGL(main_kernel(variant, mixed, alt), dim3(grid), dim3(64 * waves), lds, s, items, tile_start,
+                       n_items, counter);
     return hipGetLastError();
 }
-int main_multi_blocks_per_cu(int variant, int L, int waves, bool mixed)
+int main_multi_blocks_per_cu(int variant, int L, int waves, bool mixed, bool alt)
 {
     const size_t lds = main_lds_bytes(variant_channels(variant), L, mixed);
     int nb = 0;
-    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, main_kernel(variant, mixed), 64 * waves, lds);
+    const hipError_t e =
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, main_kernel(variant, mixed, alt), 64 * waves, lds);
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 void launch_finalize(const FinalArgs& a, hipStream_t s)

@@ -272,3 +272,42 @@ def test_sparse_noalloc_equals_evaluate():
                 assert torch.equal(u_na, u_ref)
     finally:
         B.scs_ctx_destroy(h)
+
+
+def test_unresolved_theta_is_nan_per_bin_and_finite_on_the_sparse_grid():
+    """The per-bin template needs a polynomial block length whose remainder
+    bounds hold; a slowly chirping low-mass source on a coarse grid has none
+    (here Mc = 4 on the 1e-7 Hz grid: its SPA time moves ~3e4 s per bin, so
+    even an 8-bin block leaves the response's fourth orbital harmonic above
+    the 1e-11 bound).  Such a theta gives NaN and is counted by
+    scs_ctx_stats; the sparse-grid template expands nothing in blocks and
+    evaluates it like any other (against the oracle)."""
+    ds = D.lisa_small(seed=71)
+    th = np.tile(ds.injection, (3, 1))
+    th[1, 0] = 4.0  # unresolved
+    th[2, 0] = 27.5
+    N = 4
+    h = _ctx(ds, ds.model, N, G=16)
+    try:
+        B.scs_ctx_stats(h, reset=True)
+        u = np.empty(3)
+        for prec in (B.SCS_PREC_FP64, B.SCS_PREC_MIXED):
+            B.scs_evaluate(h, np.ascontiguousarray(th), u, prec)
+            assert np.isnan(u[1]) and np.all(np.isfinite(u[[0, 2]])), (prec, u)
+        _, _, unresolved = B.scs_ctx_stats(h, reset=True)
+        assert unresolved == 2  # one particle, two evaluations
+    finally:
+        B.scs_ctx_destroy(h)
+    ms = _sparse(ds.model, 200)
+    ref = O.evaluate(ds.grid, ms, ds.d_ri, ds.psd, th, N, O.SEG_EQUAL_SNR, 16, want_bounds=True)
+    h = _ctx(ds, ms, N, G=16)
+    try:
+        u = np.empty(3)
+        B.scs_evaluate(h, np.ascontiguousarray(th), u, B.SCS_PREC_FP64)
+        _, bnd = B.scs_last_bounds(h, 3, N)
+        _, _, unresolved = B.scs_ctx_stats(h, reset=True)
+        assert unresolved == 0
+        print("unresolved per bin, sparse grid:", u, "oracle", ref["ups"])
+        PT.check_rows(ds, th, u, ref, bnd, 16, PT.TOL64, what="unresolved theta on the sparse grid", model=ms)
+    finally:
+        B.scs_ctx_destroy(h)

@@ -1,4 +1,5 @@
-"""The launch-shape autotuner and the request loop's admission limits.
+"""The launch-shape autotuners (per evaluation class and per batch) and the
+request loop's admission limits.
 
 The tuned shape changes only the order of the partial sums (chunk joins),
 so tuned results agree with the default shape to rounding and with the
@@ -48,10 +49,10 @@ def test_autotune_cache_and_results(tmp_path):
         base = {p: _eval(h1, th, p) for p in (B.SCS_PREC_FP64, B.SCS_PREC_MIXED)}
         for p in (B.SCS_PREC_FP64, B.SCS_PREC_MIXED):
             B.scs_autotune(h1, th, N, p, str(cache))
-        lines = cache.read_text().split()
-        assert len(lines) == 6, lines  # two "key waves blocks" records
-        for w, cb in zip(lines[1::3], lines[2::3]):
-            assert int(w) in (1, 2, 4) and int(cb) >= 1
+        recs = [ln.split() for ln in cache.read_text().splitlines()]
+        assert len(recs) == 2 and all(len(r) == 5 for r in recs), recs  # "key waves blocks L alt"
+        for _, w, cb, L, alt in recs:
+            assert int(w) in (1, 2, 4) and int(cb) >= 1 and int(L) in (256, 512, 1024) and int(alt) in (0, 1)
         _, bnd = B.scs_last_bounds(h1, P, N)
         for p, tol in ((B.SCS_PREC_FP64, 1e-12), (B.SCS_PREC_MIXED, 1e-5)):
             tuned = _eval(h1, th, p)
@@ -71,6 +72,63 @@ def test_autotune_cache_and_results(tmp_path):
     finally:
         B.scs_ctx_destroy(h1)
         B.scs_ctx_destroy(h2)
+
+
+def test_autotune_batch(tmp_path):
+    """The batch tuner times whole batched evaluations (launch occupancy,
+    then each item's LDS block and chunk); afterwards batched results agree
+    with the default shapes to rounding and with the oracle, and a second
+    call is answered from the cache file."""
+    ds = D.lisa_small(seed=33)
+    levels = [(64, 900, 133), (16, 300, 134), (1, 128, 135)]
+    h = _ctx(ds, 64)
+    cache = tmp_path / "tune_batch.txt"
+    try:
+        items, thetas = [], []
+        for N, P, seed in levels:
+            theta = D.lisa_particles(P, seed=seed)
+            thetas.append(theta)
+            items.append((h, N, torch.tensor(np.ascontiguousarray(theta), device="cuda"),
+                          torch.empty(P, dtype=torch.float64, device="cuda")))
+
+        def batched(prec):
+            B.scs_evaluate_batched(items, prec)
+            torch.cuda.synchronize()
+            return [it[3].cpu().numpy().copy() for it in items]
+
+        base = {p: batched(p) for p in (B.SCS_PREC_FP64, B.SCS_PREC_MIXED)}
+        for p in (B.SCS_PREC_FP64, B.SCS_PREC_MIXED):
+            B.scs_autotune_batch(items, p, str(cache))
+        recs = [ln.split() for ln in cache.read_text().splitlines()]
+        print("batch tuner records:", recs)
+        assert len(recs) == 6 and all(len(r) == 5 for r in recs)
+        # N_eff per level from a solo evaluation (its edges are the batch's)
+        neff = []
+        for (N, P, _), it in zip(levels, items):
+            B.scs_define_segmentation(h, N, B.SCS_SEG_EQUAL_SNR, 16)
+            B.scs_evaluate(h, it[2], torch.empty(P, dtype=torch.float64, device="cuda"))
+            torch.cuda.synchronize()
+            neff.append(PT.n_eff(B.scs_last_bounds(h, P, N)[1]))
+        for p, tol in ((B.SCS_PREC_FP64, 1e-12), (B.SCS_PREC_MIXED, 1e-5)):
+            tuned = batched(p)
+            for (N, P, _), a, b, ne in zip(levels, tuned, base[p], neff):
+                e = PT.floored(a, b, ne)
+                print("batch-tuned vs default shapes", p, N, e.max())
+                assert e.max() < tol, (p, N, e.max())
+        N, P, _ = levels[0]
+        B.scs_define_segmentation(h, N, B.SCS_SEG_EQUAL_SNR, 16)
+        u = torch.empty(P, dtype=torch.float64, device="cuda")
+        B.scs_evaluate(h, items[0][2], u)
+        torch.cuda.synchronize()
+        _, bnd = B.scs_last_bounds(h, P, N)
+        ref = O.evaluate(ds.grid, ds.model, ds.d_ri, ds.psd, thetas[0][:6], N, O.SEG_EQUAL_SNR, 16, want_bounds=True)
+        PT.check_rows(ds, thetas[0][:6], batched(B.SCS_PREC_FP64)[0][:6], ref, bnd[:6], 16, PT.TOL64,
+                      what="batch-tuned vs oracle")
+        mtime = cache.stat().st_mtime_ns
+        B.scs_autotune_batch(items, B.SCS_PREC_FP64, str(cache))  # every item cached: no timing, no rewrite
+        assert cache.stat().st_mtime_ns == mtime
+    finally:
+        B.scs_ctx_destroy(h)
 
 
 def test_server_budget_and_drop_on_destroy():
