@@ -222,6 +222,21 @@ int scs_data_norm(const scs_ctx* ctx, double* dd);
 int scs_loglike(scs_ctx* ctx, int64_t P, const double* stats, const double* amp, const double* phase,
                 double* logl_semi, double* logl_coh, int32_t mem_kind, void* stream);
 
+/* Absolute amplitude A of the template (the factor that makes A h the strain
+ * the data carry) for a source at luminosity distance D_L: the restricted
+ * stationary-phase amplitude of the (2,2) mode,
+ *   A = sqrt(5/24) pi^(-2/3) (G Mc / c^3)^(5/6) c / D_L,
+ * Mc the detector-frame chirp mass (theta[p][0], solar masses), D_L in Mpc
+ * (Sec 4: D_L is a 1/D_L prefactor of the waveform amplitude, cancelled by
+ * the search statistic; Sec 3.3 draws it for every walker at the hand-off to
+ * inference, whose coherent likelihood, eqn:LogL_coherent, needs it).  Feed
+ * amp to scs_loglike.  theta [P][D], dl_mpc [P], amp [P] out; NaN for Mc <= 0,
+ * D_L <= 0 or non-finite entries.  mem_kind as scs_loglike.  The amplitude
+ * matches data whose noise and PSD are in strain units (the synthetic
+ * generator's convention).  Errors: EINVAL, ESTATE, EDEVICE. */
+int scs_distance_amplitude(scs_ctx* ctx, int64_t P, const double* theta, const double* dl_mpc, double* amp,
+                           int32_t mem_kind, void* stream);
+
 /* ---- one theta against many data streams (Sec 5.1) -------------------- */
 
 /* Fill streams (DEVICE [n_chan][K][R][2], realisations innermost) with

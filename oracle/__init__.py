@@ -225,6 +225,27 @@ def likelihood_stats(grid: Grid, model: Model, d_ri, psd, theta, N, mode=SEG_EQU
             "dh": w * np.sum(Z, axis=1), "bounds": out["bounds"]}
 
 
+# IAU nominal solar mass parameter, speed of light, parsec (648000/pi au)
+_GM_SUN = 1.32712440018e20   # m^3 s^-2
+_C = 299792458.0             # m s^-1
+_MPC = 3.0856775814913673e22  # m
+
+
+def distance_amplitude(mc_msun, dl_mpc):
+    """Absolute amplitude of the template h = f^-7/6 R e^{-i Psi} (the
+    response R carrying (1 + cos^2 iota)/2 and cos iota) for a source at
+    luminosity distance D_L: the restricted stationary-phase amplitude of the
+    (2,2) mode, sqrt(5/24) pi^-2/3 (G Mc / c^3)^5/6 c / D_L, with Mc the
+    detector-frame chirp mass (Sec 4: D_L is a 1/D_L prefactor of the
+    amplitude; Sec 2.1, eqn:LogL_coherent needs the absolute amplitude)."""
+    mc = np.asarray(mc_msun, dtype=np.float64)
+    dl = np.asarray(dl_mpc, dtype=np.float64)
+    ok = (mc > 0) & (dl > 0) & np.isfinite(mc) & np.isfinite(dl)
+    tm = np.where(ok, mc, 1.0) * _GM_SUN / _C ** 3  # s
+    a = np.sqrt(5.0 / 24.0) * np.pi ** (-2.0 / 3.0) * tm ** (5.0 / 6.0) * _C / (np.where(ok, dl, 1.0) * _MPC)
+    return np.where(ok, a, np.nan)  # no physical amplitude for Mc <= 0 or D_L <= 0
+
+
 def loglike(dd, stats, amp, phase=None):
     """Log-likelihoods for templates A h e^{i phi} (A real), dropping the
     normalisation constant as the paper does:

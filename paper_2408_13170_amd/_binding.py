@@ -118,6 +118,7 @@ _SIGS = {
     "scs_theta_dim": [C.c_void_p, C.POINTER(C.c_int32)],
     "scs_peak_probe": [C.c_int32, C.POINTER(C.c_double)],
     "scs_autotune_batch": [C.POINTER(scs_batch_item), C.c_int32, C.c_int32, C.c_char_p],
+    "scs_distance_amplitude": [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p],
     "scs_ctx_info": [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                      C.POINTER(C.c_int64)],
     "scs_server_create": [C.POINTER(C.c_void_p), C.c_int32, C.c_int32, C.c_uint64, C.c_int32],
@@ -356,6 +357,24 @@ def scs_loglike(ctx, stats, amp, phase=None, logl_semi=None, logl_coh=None, stre
     if kind == SCS_MEM_DEVICE and stream is None:
         stream = current_stream()
     _check(lib().scs_loglike(ctx, P, *(p for p, _ in ptrs), kind, _stream(stream)))
+
+
+def scs_distance_amplitude(ctx, theta, dl_mpc, amp, stream=None):
+    """Absolute template amplitude A [P] for distances dl_mpc [P] (Mpc) and the
+    chirp masses of theta [P][D]; all arrays in one memory."""
+    info = scs_ctx_info(ctx)
+    need_f64(theta, "theta", (None, info["theta_dim"]))
+    P = theta.shape[0]
+    need_f64(dl_mpc, "dl_mpc", (P,))
+    need_f64(amp, "amp", (P,))
+    ptrs = [ptr(x) for x in (theta, dl_mpc, amp)]
+    kinds = {k for _, k in ptrs}
+    if len(kinds) != 1:
+        raise ValueError("theta, dl_mpc and amp must live in the same memory")
+    kind = kinds.pop()
+    if kind == SCS_MEM_DEVICE and stream is None:
+        stream = current_stream()
+    _check(lib().scs_distance_amplitude(ctx, P, *(p for p, _ in ptrs), kind, _stream(stream)))
 
 
 def scs_make_realisations(ctx, streams, seed, r0=0, scale=1.0, stream=None):

@@ -1039,6 +1039,42 @@ extern "C" int scs_data_norm(const scs_ctx* c, double* dd)
     return SCS_OK;
 }
 
+extern "C" int scs_distance_amplitude(scs_ctx* c, int64_t P, const double* theta, const double* dl_mpc, double* amp,
+                                      int32_t mem_kind, void* stream)
+{
+    int rc = check_ready(c);
+    if (rc) return rc;
+    if (P < 0) return fail(SCS_EINVAL, "P < 0");
+    if (P > 0 && (!theta || !dl_mpc || !amp)) return fail(SCS_EINVAL, "theta, dl_mpc or amp is NULL");
+    if (mem_kind != SCS_MEM_HOST && mem_kind != SCS_MEM_DEVICE) return fail(SCS_EINVAL, "bad mem_kind");
+    if (P == 0) return SCS_OK;
+    // sqrt(5/24) pi^(-2/3) (G Msun / c^3)^(5/6) c / (1 Mpc): the restricted
+    // stationary-phase amplitude of the (2,2) mode per Msun^(5/6) at 1 Mpc
+    const double gm_sun = 1.32712440018e20, c_light = 299792458.0, mpc = 3.0856775814913673e22;
+    const double k = std::sqrt(5.0 / 24.0) * std::pow(M_PI, -2.0 / 3.0) *
+                     std::pow(gm_sun / (c_light * c_light * c_light), 5.0 / 6.0) * c_light / mpc;
+    const int td = theta_dim(c);
+    DevScope ds(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    if (mem_kind == SCS_MEM_DEVICE) {
+        launch_distance_amp(P, td, theta, dl_mpc, k, amp, s);
+        hipError_t e = hipGetLastError();
+        return e == hipSuccess ? SCS_OK : fail(SCS_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    }
+    Workspace& w = c->ws[-2];
+    if ((rc = grow(&w.stage, &w.capStage, P * (td + 2)))) return rc;
+    double* dth = w.stage;
+    double* ddl = dth + P * td;
+    double* damp = ddl + P;
+    HIP_TRY(hipMemcpyAsync(dth, theta, sizeof(double) * td * P, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(ddl, dl_mpc, sizeof(double) * P, hipMemcpyHostToDevice, s));
+    launch_distance_amp(P, td, dth, ddl, k, damp, s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(amp, damp, sizeof(double) * P, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return SCS_OK;
+}
+
 extern "C" int scs_loglike(scs_ctx* c, int64_t P, const double* stats, const double* amp, const double* phase,
                            double* logl_semi, double* logl_coh, int32_t mem_kind, void* stream)
 {

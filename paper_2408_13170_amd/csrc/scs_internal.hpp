@@ -221,6 +221,8 @@ void launch_streams_final(const StreamArgs& a, hipStream_t s);  // per-stream st
 constexpr int kNormBlocks = 256;
 void launch_data_norm(const GridArgs& g, const double* d_ri, const double* psd, double* part, double* out,
                       hipStream_t s);
+void launch_distance_amp(int64_t P, int td, const double* theta, const double* dl, double k, double* amp,
+                         hipStream_t s);
 void launch_loglike(int64_t P, double dd, const double* stats, const double* amp, const double* phase, double* semi,
                     double* coh, hipStream_t s);
 void launch_bins(const GridArgs& g, const double* d_ri, const double* psd, double* b64, float* b32, double su,

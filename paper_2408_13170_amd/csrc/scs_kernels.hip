@@ -1893,6 +1893,18 @@ __global__ void k_loglike(int64_t P, double dd, const double* __restrict__ stats
     }
 }
 
+// Absolute template amplitude from the luminosity distance: k Mc^(5/6) / D_L
+// (k carries the restricted-amplitude constants and the units, Mc in solar
+// masses, D_L in Mpc); NaN for Mc <= 0, D_L <= 0 or a non-finite entry.
+__global__ void k_distance_amp(int64_t P, int td, const double* __restrict__ theta, const double* __restrict__ dl,
+                               double k, double* __restrict__ amp)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P) return;
+    const double mc = theta[i * td], d = dl[i];
+    amp[i] = (mc > 0.0 && d > 0.0 && isfinite(mc) && isfinite(d)) ? k * pow(mc, 5.0 / 6.0) / d : __builtin_nan("");
+}
+
 // ============================================================== waveform
 __global__ void k_waveform(MainArgs a, double* __restrict__ h_ri)
 {
@@ -2261,6 +2273,11 @@ void launch_data_norm(const GridArgs& g, const double* d_ri, const double* psd, 
 {
     hipLaunchKernelGGL(k_data_norm, dim3(kNormBlocks), dim3(256), 0, s, g, d_ri, psd, part);
     hipLaunchKernelGGL(k_data_norm_total, dim3(1), dim3(kNormBlocks), 0, s, part, g.df, out);
+}
+void launch_distance_amp(int64_t P, int td, const double* theta, const double* dl, double k, double* amp,
+                         hipStream_t s)
+{
+    if (P > 0) hipLaunchKernelGGL(k_distance_amp, dim3(nblk(P, 256)), dim3(256), 0, s, P, td, theta, dl, k, amp);
 }
 void launch_loglike(int64_t P, double dd, const double* stats, const double* amp, const double* phase, double* semi,
                     double* coh, hipStream_t s)

@@ -135,3 +135,59 @@ def test_noise_free_injection_loglike_zero():
             assert abs(semi[0]) < 1e-9 * dd and abs(coh[0]) < 1e-9 * dd
         finally:
             B.scs_ctx_destroy(h)
+
+
+def test_distance_amplitude_and_coherent_loglike():
+    """The coherent log-likelihood with the absolute amplitude from the
+    luminosity distance (eqn:LogL_coherent; Sec 4: D_L is a 1/D_L prefactor
+    of the amplitude): data carry the injection at its physical amplitude for
+    a distance D_L*; the device amplitudes equal the oracle's, log L at the
+    injected (theta, D_L, phase) against the oracle, and without noise log L
+    peaks at D_L* (where it is 0) along a grid of distances."""
+    base = D.lisa_small(seed=75, noise=False, snr=0.0)
+    g, m, psd = base.grid, base.model, base.psd
+    inj = base.injection
+    h = O.template(g, m, inj)
+    hh = D.inner(g, psd, h, h)
+    a1 = float(O.distance_amplitude(inj[0], 1.0))
+    dl_true = a1 * np.sqrt(hh) / 20.0  # SNR 20 at this distance
+    for noise in (False, True):
+        d = float(O.distance_amplitude(inj[0], dl_true)) * h
+        if noise:
+            d = d + synth.noise(psd, g.df, 76)
+        ds = D.Dataset(g, m, psd, d, inj, 20.0, None, None)
+        th = D.lisa_particles(6, seed=77)
+        th[0] = inj
+        dl = np.full(6, dl_true)
+        dl[1] = -1.0  # invalid distance: NaN amplitude
+        ctx = _ctx(ds, 8, G=16)
+        try:
+            amp = np.empty(6)
+            B.scs_distance_amplitude(ctx, np.ascontiguousarray(th), dl, amp)
+            ref_amp = O.distance_amplitude(th[:, 0], dl)
+            assert np.isnan(amp[1]) and np.isnan(ref_amp[1])
+            ok = np.isfinite(ref_amp)
+            assert np.all(np.abs(amp[ok] / ref_amp[ok] - 1) < 1e-14), amp / ref_amp
+            st = np.empty((6, B.SCS_NSTATS))
+            B.scs_evaluate_stats(ctx, np.ascontiguousarray(th), st)
+            dd = B.scs_data_norm(ctx)
+            semi, coh = np.empty(6), np.empty(6)
+            B.scs_loglike(ctx, st, np.nan_to_num(amp), np.zeros(6), semi, coh)
+            rs = O.likelihood_stats(g, m, ds.d_ri, psd, th, 8, O.SEG_EQUAL_SNR, 16)
+            ref_semi, ref_coh = O.loglike(O.data_norm(g, ds.d_ri, psd), rs, np.nan_to_num(ref_amp), np.zeros(6))
+            scale = dd + np.nan_to_num(ref_amp) ** 2 * rs["hh"]
+            e = np.abs(coh - ref_coh)[ok] / scale[ok]
+            print(f"noise {noise}: coherent log L at the physical amplitude, max err {e.max():.3g}; "
+                  f"log L(theta*, D_L*) = {coh[0]:.6g}")
+            assert e.max() < 1e-9
+            if not noise:
+                assert abs(coh[0]) < 1e-9 * dd
+                # log L along distances: its maximum sits at D_L*
+                grid_dl = dl_true * np.linspace(0.8, 1.2, 41)
+                a = np.empty(41)
+                B.scs_distance_amplitude(ctx, np.ascontiguousarray(np.tile(inj, (41, 1))), grid_dl, a)
+                _, c41 = np.empty(41), np.empty(41)
+                B.scs_loglike(ctx, np.ascontiguousarray(np.tile(st[0], (41, 1))), a, np.zeros(41), None, c41)
+                assert int(np.argmax(c41)) == 20, np.argmax(c41)
+        finally:
+            B.scs_ctx_destroy(ctx)
