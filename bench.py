@@ -586,17 +586,21 @@ def bench_serve(args):
            "config": {"workload": rep["workload"], **rep["server_shape"]},
            "capacity_rps": rep["fp64"]["capacity_rps"],
            "capacity_evals_per_s": rep["fp64"]["capacity_evals_per_s"], "levels": levels,
-           "mixed": rep["mixed"], "server": rep["server"]}
+           "mixed": rep["mixed"], "equal_rate": rep.get("equal_rate"), "server": rep["server"]}
     print(json.dumps(out), flush=True)
 
 
-def bench_serve_core(B, torch, dev, n_requests, loads):
+def bench_serve_core(B, torch, dev, n_requests, loads, equal_rate=0.95):
     """Eight independent searches (2^19 - 2^21 bins, A+E, GW150914-like and
     GW190521-like injections at SNR 15 - 40) behind the native request loop.
     Requests of 256 - 16384 particles (log-uniform) at a segment count from
     the ladder arrive as a Poisson process at fractions of the measured
     capacity; p50 / p99 latency (submit to result) and throughput, FP64 and
-    mixed; mixed against FP64 on the same requests (floored at 2 N_eff)."""
+    mixed; then the same requests at the same arrival times in both
+    precisions, at equal_rate x the FP64 capacity (latency at equal offered
+    traffic: each precision's loads above are fractions of its own capacity,
+    and the mixed capacity is higher); mixed against FP64 on the same
+    requests (floored at 2 N_eff)."""
     searches = []
     for w in synth.served_streams():
         ctx, _ = make_search(B, torch, w, dev)
@@ -668,6 +672,21 @@ def bench_serve_core(B, torch, dev, n_requests, loads):
             log(f"served {pname} load {load}: {len(reqs) / t:.1f} req/s, p50 {np.median(lat):.1f} ms, "
                 f"p99 {np.quantile(lat, 0.99):.1f} ms (queue p50 {np.median(queue):.1f} ms)")
         report[pname] = {"capacity_rps": capacity, "capacity_evals_per_s": ev_b / t_b, "levels": levels}
+    if equal_rate:
+        reqs = make_requests(n_requests)
+        rate = equal_rate * report["fp64"]["capacity_rps"]
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, len(reqs)))
+        eq = {"offered_rps": rate, "fraction_of_fp64_capacity": equal_rate, "requests": len(reqs)}
+        for pname, prec in (("fp64", B.SCS_PREC_FP64), ("mixed", B.SCS_PREC_MIXED)):
+            t, lat, queue, _ = run(reqs, arrivals, prec)
+            for _, ctx in searches:
+                B.scs_ctx_stats(ctx, reset=True)
+            eq[pname] = {"achieved_rps": len(reqs) / t,
+                         "latency_ms": {"p50": float(np.median(lat)), "p99": float(np.quantile(lat, 0.99))},
+                         "queue_ms": {"p50": float(np.median(queue)), "p99": float(np.quantile(queue, 0.99))}}
+            log(f"served {pname} at {rate:.1f} req/s (both precisions, same requests and arrivals): "
+                f"p50 {np.median(lat):.1f} ms, p99 {np.quantile(lat, 0.99):.1f} ms")
+        report["equal_rate"] = eq
     # mixed against FP64 on the burst's requests (each served in both precisions)
     errs = []
     for (ctx, N, th, si), a, b in zip(burst, burst_out["fp64"], burst_out["mixed"]):
