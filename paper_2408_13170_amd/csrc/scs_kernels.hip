@@ -1064,11 +1064,44 @@ struct SinCosK {
     double s3, s1, c2;
 };
 
+// What one bin adds to the running sums, kept apart from the sums so that
+// two bins can be evaluated side by side before either is added:
+// Z += (sr + i si)(cs + i sn), H += sum_alpha q_alpha w_alpha, where sr + i si
+// is the data weighted by the conjugate response, (cs, sn) the phasor and
+// w_alpha = |R_alpha|^2 (one channel: the amplitude factor).
+template <typename T, int NCH>
+struct BinTerms {
+    T sr, si, sn, cs;
+    T w[NCH], q[NCH];
+};
+__device__ __forceinline__ double fmx(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmx(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+// Keeps terms formed where they are written: without it the compiler sinks
+// the second bin's arithmetic past the first bin's event branch, where it no
+// longer interleaves with the first bin's.
+template <typename T, int NCH>
+__device__ __forceinline__ void pin_terms(BinTerms<T, NCH>& b)
+{
+    __asm__ volatile("" : "+v"(b.sr), "+v"(b.si), "+v"(b.sn), "+v"(b.cs));
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) __asm__ volatile("" : "+v"(b.w[c]), "+v"(b.q[c]));
+}
+template <typename T, int NCH>
+__device__ __forceinline__ void add_terms(const BinTerms<T, NCH>& b, T& zr, T& zi, T& hh)
+{
+    zr = fmx(b.sr, b.cs, fmx(-b.si, b.sn, zr));
+    zi = fmx(b.sr, b.sn, fmx(b.si, b.cs, zi));
+    T h = hh;
+#pragma unroll
+    for (int c = NCH - 1; c >= 0; --c) h = fmx(b.q[c], b.w[c], h);
+    hh = h;
+}
+
 template <int NCH, int D = 5>
-__device__ __forceinline__ void bin_fp64(double j, const double* __restrict__ bin, const double2* __restrict__ tab,
-                                         const SinCosK& kk, const PhasePoly& poly,
-                                         const RespPolyN<NCH == 3 ? 6 : 4>& rp, int tmask, int toff, double amp,
-                                         double& zr, double& zi, double& hh)
+__device__ __forceinline__ void bin_terms_fp64(double j, const double* __restrict__ bin,
+                                               const double2* __restrict__ tab, const SinCosK& kk,
+                                               const PhasePoly& poly, const RespPolyN<NCH == 3 ? 6 : 4>& rp,
+                                               int tmask, int toff, double amp, BinTerms<double, NCH>& o)
 {
     constexpr bool RESP = NCH >= 2;
     // the bin's data first, then the table read, so that both are in flight
@@ -1094,6 +1127,8 @@ __device__ __forceinline__ void bin_fp64(double j, const double* __restrict__ bi
     const double t = pc + kRoundShift;
     const int iq = ((int)(uint32_t)__double_as_longlong(t) & tmask) | toff;
     const double2 tt = tab[iq];
+    // the table read is issued before the response work that hides its latency
+    __builtin_amdgcn_sched_barrier(0);
     double sr, si;
     if constexpr (NCH == 3) {
         const double rar = horner<D>(rp.r[0], j), rai = horner<D>(rp.r[1], j);
@@ -1111,10 +1146,12 @@ __device__ __forceinline__ void bin_fp64(double j, const double* __restrict__ bi
         si = __builtin_fma(-uE.x, rei, si);
         si = __builtin_fma(uT.y, rtr, si);
         si = __builtin_fma(-uT.x, rti, si);
-        const double wa = __builtin_fma(rar, rar, rai * rai);
-        const double we = __builtin_fma(rer, rer, rei * rei);
-        const double wt = __builtin_fma(rtr, rtr, rti * rti);
-        hh = __builtin_fma(qq.x, wa, __builtin_fma(qq.y, we, __builtin_fma(qT.x, wt, hh)));
+        o.w[0] = __builtin_fma(rar, rar, rai * rai);
+        o.w[1] = __builtin_fma(rer, rer, rei * rei);
+        o.w[2] = __builtin_fma(rtr, rtr, rti * rti);
+        o.q[0] = qq.x;
+        o.q[1] = qq.y;
+        o.q[2] = qT.x;
     } else if constexpr (RESP) {
         const double rar = horner<D>(rp.r[0], j), rai = horner<D>(rp.r[1], j);
         const double rer = horner<D>(rp.r[2], j), rei = horner<D>(rp.r[3], j);
@@ -1126,22 +1163,34 @@ __device__ __forceinline__ void bin_fp64(double j, const double* __restrict__ bi
         si = __builtin_fma(-uA.x, rai, si);
         si = __builtin_fma(uE.y, rer, si);
         si = __builtin_fma(-uE.x, rei, si);
-        const double wa = __builtin_fma(rar, rar, rai * rai);
-        const double we = __builtin_fma(rer, rer, rei * rei);
-        hh = __builtin_fma(qq.x, wa, __builtin_fma(qq.y, we, hh));
+        o.w[0] = __builtin_fma(rar, rar, rai * rai);
+        o.w[1] = __builtin_fma(rer, rer, rei * rei);
+        o.q[0] = qq.x;
+        o.q[1] = qq.y;
     } else {
         sr = ur;
         si = ui;
-        hh = __builtin_fma(q1, amp, hh);
+        o.w[0] = amp;
+        o.q[0] = q1;
     }
     const double s = pc - (t - kRoundShift);  // exact, |s| <= 1/2
     const double z = s * s;
     const double sn = s * __builtin_fma(z, kk.s3, kk.s1);
     const double cn = __builtin_fma(z, kk.c2, 1.0);
-    const double sv = __builtin_fma(tt.y, cn, tt.x * sn);
-    const double cv = __builtin_fma(tt.x, cn, -(tt.y * sn));
-    zr = __builtin_fma(sr, cv, __builtin_fma(-si, sv, zr));
-    zi = __builtin_fma(sr, sv, __builtin_fma(si, cv, zi));
+    o.sn = __builtin_fma(tt.y, cn, tt.x * sn);
+    o.cs = __builtin_fma(tt.x, cn, -(tt.y * sn));
+    o.sr = sr;
+    o.si = si;
+}
+template <int NCH, int D = 5>
+__device__ __forceinline__ void bin_fp64(double j, const double* __restrict__ bin, const double2* __restrict__ tab,
+                                         const SinCosK& kk, const PhasePoly& poly,
+                                         const RespPolyN<NCH == 3 ? 6 : 4>& rp, int tmask, int toff, double amp,
+                                         double& zr, double& zi, double& hh)
+{
+    BinTerms<double, NCH> t;
+    bin_terms_fp64<NCH, D>(j, bin, tab, kk, poly, rp, tmask, toff, amp, t);
+    add_terms(t, zr, zi, hh);
 }
 
 // One bin of the mixed path: FP32 phase a0 + frac(a1h j) + residual(j)
@@ -1152,9 +1201,9 @@ __device__ __forceinline__ void bin_fp64(double j, const double* __restrict__ bi
 // rounded to FP32 (the sparse-grid template, whose spline intervals are too
 // long for an FP32 residual), instead of a0 + frac(a1h j) + residual.
 template <int NCH, bool PH64 = false>
-__device__ __forceinline__ void bin_mixed(float jf, const float* __restrict__ bin, const float* phf, float a1h,
-                                          const float (*rf)[kRespMixed], float amp, float& pzr, float& pzi, float& phh,
-                                          const double* ph64 = nullptr, double ud = 0.0)
+__device__ __forceinline__ void bin_terms_mixed(float jf, const float* __restrict__ bin, const float* phf, float a1h,
+                                                const float (*rf)[kRespMixed], float amp, BinTerms<float, NCH>& o,
+                                                const double* ph64 = nullptr, double ud = 0.0)
 {
     constexpr bool RESP = NCH >= 2;
     // the bin's data first, in flight while the phase and sin / cos are formed
@@ -1203,12 +1252,14 @@ __device__ __forceinline__ void bin_mixed(float jf, const float* __restrict__ bi
         si = __builtin_fmaf(-u.z, rei, si);
         si = __builtin_fmaf(tq.y, rtr, si);
         si = __builtin_fmaf(-tq.x, rti, si);
-        pzr = __builtin_fmaf(sr, cs, __builtin_fmaf(-si, sn, pzr));
-        pzi = __builtin_fmaf(sr, sn, __builtin_fmaf(si, cs, pzi));
-        const float wa = __builtin_fmaf(rar, rar, rai * rai);
-        const float we = __builtin_fmaf(rer, rer, rei * rei);
-        const float wt = __builtin_fmaf(rtr, rtr, rti * rti);
-        phh = __builtin_fmaf(tq.z, wa, __builtin_fmaf(tq.w, we, __builtin_fmaf(qt, wt, phh)));
+        o.sr = sr;
+        o.si = si;
+        o.w[0] = __builtin_fmaf(rar, rar, rai * rai);
+        o.w[1] = __builtin_fmaf(rer, rer, rei * rei);
+        o.w[2] = __builtin_fmaf(rtr, rtr, rti * rti);
+        o.q[0] = tq.z;
+        o.q[1] = tq.w;
+        o.q[2] = qt;
     } else if constexpr (RESP) {
         const float rar = horner3f(rf[0], jf), rai = horner3f(rf[1], jf);
         const float rer = horner3f(rf[2], jf), rei = horner3f(rf[3], jf);
@@ -1220,18 +1271,29 @@ __device__ __forceinline__ void bin_mixed(float jf, const float* __restrict__ bi
         si = __builtin_fmaf(-u.x, rai, si);
         si = __builtin_fmaf(u.w, rer, si);
         si = __builtin_fmaf(-u.z, rei, si);
-        pzr = __builtin_fmaf(sr, cs, __builtin_fmaf(-si, sn, pzr));
-        pzi = __builtin_fmaf(sr, sn, __builtin_fmaf(si, cs, pzi));
-        const float wa = __builtin_fmaf(rar, rar, rai * rai);
-        const float we = __builtin_fmaf(rer, rer, rei * rei);
-        phh = __builtin_fmaf(qq.x, wa, __builtin_fmaf(qq.y, we, phh));
+        o.sr = sr;
+        o.si = si;
+        o.w[0] = __builtin_fmaf(rar, rar, rai * rai);
+        o.w[1] = __builtin_fmaf(rer, rer, rei * rei);
+        o.q[0] = qq.x;
+        o.q[1] = qq.y;
     } else {
-        ur *= amp;
-        ui *= amp;
-        pzr = __builtin_fmaf(ur, cs, __builtin_fmaf(-ui, sn, pzr));
-        pzi = __builtin_fmaf(ur, sn, __builtin_fmaf(ui, cs, pzi));
-        phh = __builtin_fmaf(q1, amp, phh);
+        o.sr = ur * amp;
+        o.si = ui * amp;
+        o.w[0] = amp;
+        o.q[0] = q1;
     }
+    o.sn = sn;
+    o.cs = cs;
+}
+template <int NCH, bool PH64 = false>
+__device__ __forceinline__ void bin_mixed(float jf, const float* __restrict__ bin, const float* phf, float a1h,
+                                          const float (*rf)[kRespMixed], float amp, float& pzr, float& pzi, float& phh,
+                                          const double* ph64 = nullptr, double ud = 0.0)
+{
+    BinTerms<float, NCH> t;
+    bin_terms_mixed<NCH, PH64>(jf, bin, phf, a1h, rf, amp, t, ph64, ud);
+    add_terms(t, pzr, pzi, phh);
 }
 
 // Occupancy target (waves per SIMD), measured on MI355X: three for both
@@ -1645,34 +1707,66 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
             // no vector-memory operation of the set-up (spill reloads
             // included) is left pending, so the bin loop needs no wait for one
             __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+            // Two bins per pass: the terms of both are formed before either
+            // enters the sums (the lanes' events come between them), so the
+            // two bins' arithmetic interleaves.  A pass with one bin left
+            // forms its second terms from the first bin's data and drops them.
             if constexpr (!MIXED) {
                 double jd = (double)(s_lo - kcl);
                 const double* binp = reinterpret_cast<const double*>(smem) + (s_lo - b0) * NV;
 #pragma unroll 1
-                for (int k = s_lo; k < s_hi; ++k) {
+                for (int k = s_lo; k < s_hi; k += 2) {
+                    const bool two = k + 1 < s_hi;  // wave-uniform
+                    BinTerms<double, NCH> t0, t1;
+                    bin_terms_fp64<NCH>(jd, binp, s_trig, kk, poly, rp, tmask, toff, amp, t0);
+                    bin_terms_fp64<NCH>(jd + 1.0, two ? binp + NV : binp, s_trig, kk, poly, rp, tmask, toff, amp, t1);
+                    pin_terms(t0);
+                    pin_terms(t1);
                     if (nxt <= k) handle(k);
-                    bin_fp64<NCH>(jd, binp, s_trig, kk, poly, rp, tmask, toff, amp, zr, zi, hh);
-                    jd += 1.0;
-                    binp += NV;
+                    add_terms(t0, zr, zi, hh);
+                    if (two) {
+                        if (nxt <= k + 1) handle(k + 1);
+                        add_terms(t1, zr, zi, hh);
+                    }
+                    jd += 2.0;
+                    binp += 2 * NV;
                 }
             } else {
                 const float ampf = (float)amp;
-                float jf = (float)(s_lo - kcl);
-                const float* binp = reinterpret_cast<const float*>(smem) + (s_lo - b0) * NV;
+                const float* const sb = reinterpret_cast<const float*>(smem);
+                // runs of bins between multiples of kMixedRun, after each of
+                // which the plain FP32 sums enter the compensated ones (a
+                // position fixed by the bin index)
 #pragma unroll 1
-                for (int k = s_lo; k < s_hi; ++k) {
-                    if (nxt <= k) handle(k);
-                    bin_mixed<NCH>(jf, binp, phf, a1h, rf, ampf, qzr, qzi, qhh);
-                    jf += 1.f;
-                    binp += NV;
-                    // the plain FP32 sums enter the compensated ones at every
-                    // multiple of kMixedRun (a position fixed by the bin index)
-                    if (((k + 1) & (kMixedRun - 1)) == 0) {
+                for (int k0 = s_lo; k0 < s_hi;) {
+                    const int kr = (k0 | (kMixedRun - 1)) + 1;
+                    const int k1 = kr < s_hi ? kr : s_hi;
+                    float jf = (float)(k0 - kcl);
+                    const float* binp = sb + (k0 - b0) * NV;
+#pragma unroll 1
+                    for (int k = k0; k < k1; k += 2) {
+                        const bool two = k + 1 < k1;  // wave-uniform
+                        BinTerms<float, NCH> t0, t1;
+                        bin_terms_mixed<NCH>(jf, binp, phf, a1h, rf, ampf, t0);
+                        bin_terms_mixed<NCH>(jf + 1.f, two ? binp + NV : binp, phf, a1h, rf, ampf, t1);
+                        pin_terms(t0);
+                        pin_terms(t1);
+                        if (nxt <= k) handle(k);
+                        add_terms(t0, qzr, qzi, qhh);
+                        if (two) {
+                            if (nxt <= k + 1) handle(k + 1);
+                            add_terms(t1, qzr, qzi, qhh);
+                        }
+                        jf += 2.f;
+                        binp += 2 * NV;
+                    }
+                    if ((k1 & (kMixedRun - 1)) == 0) {
                         kahan(kzr, czr, qzr);
                         kahan(kzi, czi, qzi);
                         kahan(khh, chh, qhh);
                         qzr = qzi = qhh = 0.f;
                     }
+                    k0 = k1;
                 }
             }
         }

@@ -6,12 +6,14 @@ two-channel layout the step benchmark uses (512-bin LDS blocks, 2048-bin
 chunks, 256 particle slots per tile) and over adversarial supports and
 edges: supports that start or end on chunk and block boundaries, one-bin
 supports, runs of empty segments, edges on chunk boundaries, idle lanes and
-the last particle of the buffer.  It also covers the variant that reads each
-bin's table entry one bin ahead (the entry of bin k + 1 while bin k is
-evaluated): the table index is the bin's phase, in 1/1024 cycles, masked to
-10 bits and or-ed with the zero-entry offset, so whatever the phase, the
-index lies in [0, 1024], the 1025 entries the table holds (the zero entry
-included).  Nothing here runs on a GPU; it replays integer arithmetic."""
+the last particle of the buffer.  The bin loop takes two bins per pass and
+forms both bins' terms before either bin's events: the second bin of a pass
+that has one bin left reads the first bin's data again, and every table
+index (the bin's phase, in 1/1024 cycles, masked to 10 bits and or-ed with
+the zero-entry offset) lies in [0, 1024], the 1025 entries the table holds
+(the zero entry included), whatever the phase; the same holds for the
+variant that reads each bin's table entry one bin ahead.  Nothing here runs
+on a GPU; it replays integer arithmetic."""
 import numpy as np
 
 K_TRIG = 1024
@@ -130,18 +132,21 @@ def emulate_tile(K, L, CB, N, NV, lanes_lg, lanes_klo, lanes_khi, bounds, P_tota
                 assert 0 <= sub < lg_levels[lgl[i]], "basis-table entry out of its level"
                 have[i] = sbl[i]
                 tmask[i], toff[i] = K_TRIG - 1, 0
-            for k in range(s_lo, s_hi):
-                due = np.flatnonzero(nxt <= k)
-                for i in due:
-                    handle(i, k)
-                off = (k - b0) * NV
-                assert 0 <= off and off + NV <= nbins * NV, "bin read out of the staged block"
-                # the table entry of this bin and, read ahead, of the next one:
-                # any phase (random, huge, negative) gives an index in range
-                ph = rng.uniform(-2.0 ** 40, 2.0 ** 40, size=(2, W))
-                for q in (table_index(ph[0], tmask, toff), table_index(ph[1], tmask, toff)):
-                    assert np.all((q >= 0) & (q < TAB_ENTRIES)), "table index out of the table"
-                visited += W
+            for k in range(s_lo, s_hi, 2):
+                two = k + 1 < s_hi
+                # both bins' data and table entries first: any phase (random,
+                # huge, negative) gives a table index in range
+                for kb in (k, k + 1 if two else k):
+                    off = (kb - b0) * NV
+                    assert 0 <= off and off + NV <= nbins * NV, "bin read out of the staged block"
+                    ph = rng.uniform(-2.0 ** 40, 2.0 ** 40, size=(2, W))
+                    for q in (table_index(ph[0], tmask, toff), table_index(ph[1], tmask, toff)):
+                        assert np.all((q >= 0) & (q < TAB_ENTRIES)), "table index out of the table"
+                # then each bin's events, before its terms enter the sums
+                for kb in ((k, k + 1) if two else (k,)):
+                    for i in np.flatnonzero(nxt <= kb):
+                        handle(i, kb)
+                    visited += W
     # chunk close: the open segment's sums
     for i in np.flatnonzero(has & (n < N)):
         if nb[i] <= hi[i]:
