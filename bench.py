@@ -45,19 +45,20 @@ PEAK_FP64_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 64 lanes x 2
 # FP32 operations per in-support particle-bin of the mixed-precision
 # generate-and-reduce kernel, two channels, from its per-bin op list (same
 # counting): bin coordinate 1 add; linear phase a1h j 1 mul, its fraction
-# 1 sub; residual cubic 3 FMA and 1 add; response cubics 4 x 3 FMA; data x
+# 1 op; residual cubic 3 FMA and 1 add; response cubics 4 x 3 FMA; data x
 # conj(response) 6 FMA + 2 mul; Z rotate-and-accumulate 4 FMA; H 4 FMA +
 # 2 mul.  Total 29 FMA + 8 other = 66, plus 2 hardware transcendentals
-# (sin and cos of revolutions), counted apart.  The compensated additions
-# (12 ops per 32 bins) are left out.
+# (sin and cos of revolutions), counted apart.  The FP64 additions of the
+# FP32 partial sums (3 per 32 bins) are left out.
 FLOP_PER_EVAL_MIXED = 66
 TRANS_PER_EVAL_MIXED = 2
-# FP32 vector peak as published (256 CU x 2.4 GHz x 128 FMA lanes x 2).  On
-# gfx950 non-packed FP32 instructions reach the doubled rate too, once two
-# waves issue FP32 side by side on a SIMD (the library's peak probe measures
-# it), so this is the mixed path's reference although packed FP32
-# instructions are kept out of the code.  Transcendentals issue at a quarter
-# of the FP32 rate.
+# FP32 vector peak as published (256 CU x 2.4 GHz x 128 FMA lanes x 2), the
+# rate of packed FP32 instructions, which the code does not use.  Non-packed
+# FP32 instructions issue at up to 1.2x (three waves per SIMD) to 1.5x
+# (eight waves, eight independent chains) the single-issue rate of 64 lanes
+# per 4 cycles on gfx950; the library's peak probe measures the eight-wave
+# figure (measured_peaks in the JSON line).  Transcendentals issue at a
+# quarter of the FP32 rate.
 PEAK_FP32_TFLOPS = 157.3
 PEAK_TRANS_PER_S = 256 * 4 * 32 * 2.4e9 / 4  # 1.97e13 per second
 

@@ -58,7 +58,7 @@ extern "C" {
 #define SCS_MEM_DEVICE 1
 
 #define SCS_PREC_FP64 0  /* every step in IEEE double */
-#define SCS_PREC_MIXED 1 /* FP64 anchors + FP32 residual, FP32 Kahan sums */
+#define SCS_PREC_MIXED 1 /* FP64 anchors + FP32 residual; FP32 partial sums of at most 32 bins, FP64 segment sums */
 
 #define SCS_RESP_NONE 0       /* one channel, h = f^-7/6 e^{-i Psi} */
 #define SCS_RESP_LISA_LF_AE 1 /* two channels A, E, low-frequency LISA response */

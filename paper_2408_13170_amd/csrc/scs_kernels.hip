@@ -1196,7 +1196,7 @@ __device__ __forceinline__ void bin_fp64(double j, const double* __restrict__ bi
 // One bin of the mixed path: FP32 phase a0 + frac(a1h j) + residual(j)
 // (a1h j exact, see the block set-up), hardware sin / cos of cycles, FP32
 // response; plain FP32 partial sums over at most kMixedRun bins, which then
-// enter the FP32 segment sums through Kahan-compensated additions.
+// enter FP64 segment sums.
 // PH64: the phase is the FP64 cubic ph64 at ud (cycles), reduced and then
 // rounded to FP32 (the sparse-grid template, whose spline intervals are too
 // long for an FP32 residual), instead of a0 + frac(a1h j) + residual.
@@ -1228,7 +1228,7 @@ __device__ __forceinline__ void bin_terms_mixed(float jf, const float* __restric
         ph = (float)(pd - rint(pd));
     } else {
         const float pl = a1h * jf;
-        const float f1 = pl - rintf(pl);
+        const float f1 = __builtin_amdgcn_fractf(pl);  // [0, 1): sin and cos take revolutions
         float r = phf[3];
         r = __builtin_fmaf(r, jf, phf[2]);
         r = __builtin_fmaf(r, jf, phf[1]);
@@ -1312,7 +1312,7 @@ __host__ __device__ constexpr int main_waves_per_eu(int nch, bool mixed, bool al
     return mixed ? (alt ? 4 : SCS_WAVES_MIXED) : (nch == 3 ? 2 : (alt ? 2 : SCS_WAVES_FP64));
 }
 // Plain FP32 partial sums cover the bins between consecutive multiples of
-// this (and a lane's own segment edges) before their compensated addition.
+// this (and a lane's own segment edges) before they enter the FP64 sums.
 constexpr int kMixedRun = 32;
 
 // One work tile (chunk, particle group) of the generate-and-reduce.  Called
@@ -1375,20 +1375,17 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
     // the chunk (the sums then drop what the lane's first polynomial block
     // added before it), else the end of the current segment
     int nxt = has ? (lo > Kc ? lo : nb) : INT32_MAX;
-    double zr = 0.0, zi = 0.0, hh = 0.0;  // FP64 sums
-    // mixed: FP32 running sums with Kahan compensation (value = sum - comp)
-    float kzr = 0.f, kzi = 0.f, khh = 0.f, czr = 0.f, czi = 0.f, chh = 0.f;
+    double zr = 0.0, zi = 0.0, hh = 0.0;  // FP64 sums (mixed: of the FP32 partial sums)
     // mixed: plain FP32 sums of the bins since the last multiple of kMixedRun
     float qzr = 0.f, qzi = 0.f, qhh = 0.f;
-    auto kahan = [](float& sum, float& comp, float x) {
-        const float y = x - comp;
-        const float t = sum + y;
-        comp = (t - sum) - y;
-        sum = t;
+    auto flush32 = [&]() {  // the FP32 partial sums enter the FP64 ones
+        zr += (double)qzr;
+        zi += (double)qzi;
+        hh += (double)qhh;
+        qzr = qzi = qhh = 0.f;
     };
     auto clear_sums = [&]() {
         zr = zi = hh = 0.0;
-        kzr = kzi = khh = czr = czi = chh = 0.f;
         qzr = qzi = qhh = 0.f;
     };
     // chunk record of this slot: [0..2] head piece (Z re, Z im, H) of the
@@ -1403,9 +1400,9 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
     GLOBAL double* dst = before ? recp : zsp;
     auto store_sums = [&](GLOBAL double* dst) {
         if constexpr (MIXED) {
-            dst[0] = ((double)kzr - (double)czr + (double)qzr) * a.zscale32;
-            dst[1] = ((double)kzi - (double)czi + (double)qzi) * a.zscale32;
-            dst[2] = ((double)khh - (double)chh + (double)qhh) * a.hscale32;
+            dst[0] = (zr + (double)qzr) * a.zscale32;
+            dst[1] = (zi + (double)qzi) * a.zscale32;
+            dst[2] = (hh + (double)qhh) * a.hscale32;
         } else {
             dst[0] = zr;
             dst[1] = zi;
@@ -1573,12 +1570,7 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
                         bin_mixed<NCH, true>((float)ud, binp, phf, a1h, rf, ampf, qzr, qzi, qhh, cph, ud);
                         ud += 1.0;
                         binp += NV;
-                        if (((k + 1) & (kMixedRun - 1)) == 0) {
-                            kahan(kzr, czr, qzr);
-                            kahan(kzi, czi, qzi);
-                            kahan(khh, chh, qhh);
-                            qzr = qzi = qhh = 0.f;
-                        }
+                        if (((k + 1) & (kMixedRun - 1)) == 0) flush32();
                     }
                 }
             }
@@ -1735,8 +1727,8 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
                 const float ampf = (float)amp;
                 const float* const sb = reinterpret_cast<const float*>(smem);
                 // runs of bins between multiples of kMixedRun, after each of
-                // which the plain FP32 sums enter the compensated ones (a
-                // position fixed by the bin index)
+                // which the plain FP32 sums enter the FP64 ones (a position
+                // fixed by the bin index)
 #pragma unroll 1
                 for (int k0 = s_lo; k0 < s_hi;) {
                     const int kr = (k0 | (kMixedRun - 1)) + 1;
@@ -1760,12 +1752,7 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
                         jf += 2.f;
                         binp += 2 * NV;
                     }
-                    if ((k1 & (kMixedRun - 1)) == 0) {
-                        kahan(kzr, czr, qzr);
-                        kahan(kzi, czi, qzi);
-                        kahan(khh, chh, qhh);
-                        qzr = qzi = qhh = 0.f;
-                    }
+                    if ((k1 & (kMixedRun - 1)) == 0) flush32();
                     k0 = k1;
                 }
             }
