@@ -1398,11 +1398,15 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
     // in an earlier chunk, else zs (a pointer rather than a flag, so that the
     // bin loop carries no per-lane condition)
     GLOBAL double* dst = before ? recp : zsp;
+    // the mixed path's scales, read once: read at each segment end, the
+    // compiler reloads them from the argument record (no alias proof against
+    // the stores) and each segment end waits for the scalar load
+    const double zscale32 = a.zscale32, hscale32 = a.hscale32;
     auto store_sums = [&](GLOBAL double* dst) {
         if constexpr (MIXED) {
-            dst[0] = (zr + (double)qzr) * a.zscale32;
-            dst[1] = (zi + (double)qzi) * a.zscale32;
-            dst[2] = (hh + (double)qhh) * a.hscale32;
+            dst[0] = (zr + (double)qzr) * zscale32;
+            dst[1] = (zi + (double)qzi) * zscale32;
+            dst[2] = (hh + (double)qhh) * hscale32;
         } else {
             dst[0] = zr;
             dst[1] = zi;
