@@ -536,10 +536,15 @@ int scs_search_create(scs_ctx* ctx, const scs_search_params* params, const doubl
  * swarm's best position starts at the best position of its particle with the
  * highest earlier best value); then define the rung's segmentation on the
  * context and iterate
- * every swarm that has not converged, all of them in one scs_pso_step_swarms
- * per iteration, until each has converged (a converged swarm stops moving)
- * or max_iters.  report may be NULL.  Synchronises the stream once per
- * iteration (one value per swarm). */
+ * every swarm that has not converged, all of them in one batched step per
+ * iteration (as scs_pso_step_swarms), until each has converged (a converged
+ * swarm stops moving) or max_iters.  The convergence rule runs on the device:
+ * each swarm's last conv_window + 1 best values stay there, and a swarm that
+ * converged is frozen by its record, so that every later kernel leaves it as
+ * it is.  The host queues 8 iterations at a time and then reads the records
+ * (three integers per swarm): one stream synchronisation per 8 iterations,
+ * and the results are those of deciding after every iteration.  report may
+ * be NULL. */
 int scs_search_run_rung(scs_search* s, const scs_rung* rung, scs_rung_report* report, void* stream);
 
 /* Current swarms: their number, sizes [n] and bests [n][D + 1] (position,

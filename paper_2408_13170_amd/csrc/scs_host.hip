@@ -653,7 +653,7 @@ struct EvalJob {
 };
 
 static int eval_front(EvalJob& j, const double* theta, double* ups, double* seg, const TuneChoice& t, hipStream_t s,
-                      double* stats = nullptr, bool fixed_ws = false)
+                      double* stats = nullptr, bool fixed_ws = false, const int32_t* frozen = nullptr)
 {
     scs_ctx* c = j.c;
     Workspace& w = *j.w;
@@ -682,6 +682,7 @@ static int eval_front(EvalJob& j, const double* theta, double* ups, double* seg,
     pa.lg_max = c->lg_max;
     pa.evals = c->counters;
     pa.unresolved = c->counters + 2;
+    pa.frozen = frozen;
     launch_prologue(pa, s);
     const int64_t spl_nmax = c->m.sparse > 0 ? spl_max_nodes(c->g.K, c->m.sparse) : 0;
     if (c->m.sparse > 0) {
@@ -1511,7 +1512,8 @@ static int eval_main(scs_ctx* c, EvalJob& j, int prec, hipStream_t s)
 // wss[i] (nullable) is the workspace of item i; by default slot 1 + i of its
 // context.
 static int run_batched(const scs_batch_item* items, int n_items, int prec, hipStream_t s, BatchSlot& b, bool upload,
-                       Workspace* const* wss = nullptr, const TuneChoice* force = nullptr)
+                       Workspace* const* wss = nullptr, const TuneChoice* force = nullptr,
+                       const int32_t* const* frozen = nullptr)
 {
     const bool mixed = prec == SCS_PREC_MIXED;
     constexpr int kWaves = 4;  // workgroup shape of the fused launch
@@ -1525,7 +1527,7 @@ static int run_batched(const scs_batch_item* items, int n_items, int prec, hipSt
         j.N = it.N;
         TuneChoice t = force ? force[i] : choose(it.ctx, it.P, it.N, prec);
         t.waves = kWaves;
-        int rc = eval_front(j, it.theta, it.ups, it.seg, t, s);
+        int rc = eval_front(j, it.theta, it.ups, it.seg, t, s, nullptr, false, frozen ? frozen[i] : nullptr);
         if (rc) return rc;
     }
     int rc = fused_main(jobs, kWaves, mixed, s, b, upload);
@@ -2460,6 +2462,59 @@ extern "C" int scs_pso_step_swarms(scs_swarm* const* sws, int32_t n, const scs_p
     }
     return SCS_OK;
 }
+
+// One iteration of the swarms of a search whose convergence is tracked on the
+// device (conv[i], one record per swarm): a swarm whose record says converged
+// is left as it is by every kernel of the step (move, evaluation, bests), and
+// the swarm best kernel pushes each new best value and applies the rule.
+// Queues only; the caller reads the records when it needs them.  Each swarm's
+// iteration counter advances here; the caller winds back those that
+// converged, so that they count the iterations they took.
+int pso_step_swarms_tracked(scs_swarm* const* sws, int n, const scs_pso_params* prm, int prec,
+                            const ConvRecord* conv, int32_t rung_it, hipStream_t s)
+{
+    if (!sws || n < 1 || !prm || !conv) return fail(SCS_EINVAL, "bad arguments");
+    std::vector<scs_batch_item> items(n);
+    std::vector<const int32_t*> frozen(n);
+    for (int i = 0; i < n; ++i) {
+        scs_swarm* sw = sws[i];
+        if (!sw) return fail(SCS_EINVAL, "swarm %d is NULL", i);
+        int rc = check_eps(prm, sw->dim);
+        if (rc) return rc;
+        items[i] = scs_batch_item{sw->ctx, sw->ctx ? sw->ctx->N : 0, 0, sw->P, sw->theta, sw->ups, nullptr};
+        frozen[i] = conv[i].state + 1;
+    }
+    int rc = check_items(items.data(), n, prec);
+    if (rc) return rc;
+    scs_ctx* c0 = sws[0]->ctx;
+    DevScope ds(c0->device);
+    for (int i = 0; i < n; ++i) {
+        scs_swarm* sw = sws[i];
+        if (sw->iteration > 0)
+            launch_pso_move(sw->P, sw->box, to_params(prm, sw->dim), sw->seed, sw->swarm_id, sw->iteration, sw->theta,
+                            sw->vel, sw->pbest, sw->gbest, s, frozen[i]);
+    }
+    BatchSlot& b = c0->ring[c0->ring_next];
+    c0->ring_next = (c0->ring_next + 1) % scs_ctx::kRing;
+    if ((rc = slot_reserve(b, n))) return rc;
+    if ((rc = run_batched(items.data(), n, prec, s, b, true, nullptr, nullptr, frozen.data()))) return rc;
+    HIP_TRY(hipEventRecord(b.done, s));
+    for (int i = 0; i < n; ++i) {
+        scs_swarm* sw = sws[i];
+        launch_pso_best(sw->P, sw->box, sw->theta, sw->ups, sw->pbest, sw->pbest_val, sw->gbest, sw->gbest + sw->dim, s,
+                        &conv[i], rung_it);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(SCS_EDEVICE, "pso launch failed: %s", hipGetErrorString(e));
+    for (int i = 0; i < n; ++i) sws[i]->iteration += 1;
+    return SCS_OK;
+}
+
+// The iteration counter of a swarm (the tracked step's caller sets it back
+// for a swarm that converged part way through the queued iterations).
+uint32_t swarm_iteration(const scs_swarm* sw) { return sw->iteration; }
+void set_swarm_iteration(scs_swarm* sw, uint32_t it) { sw->iteration = it; }
+int ctx_device(const scs_ctx* c) { return c->device; }
 
 extern "C" int scs_swarm_read(scs_swarm* sw, double* theta, double* vel, double* pbest, double* pbest_val,
                               double* gbest, double* gbest_val, uint32_t* iteration)

@@ -103,6 +103,7 @@ struct PrologueArgs {
     int lg_max;
     unsigned long long* evals;
     unsigned long long* unresolved;
+    const int32_t* frozen;  // nullable; when *frozen != 0 no theta is evaluated (all as invalid)
 };
 
 struct BoundArgs {
@@ -249,10 +250,25 @@ void launch_finalize(const FinalArgs& a, hipStream_t s);
 void launch_waveform(const MainArgs& a, double* h_ri, hipStream_t s);
 void launch_gtab(const GridArgs& g, int lg, int64_t nsub, double* tab, hipStream_t s);
 void launch_pso_init(int64_t P, const PsoBox& box, uint64_t seed, uint32_t swarm, double* theta, hipStream_t s);
+// Convergence record of one swarm of a search, kept on the device: the last
+// window + 1 swarm best values (a ring) and state = [values pushed, converged
+// (0 or 1), the rung iteration at which it converged].  A converged swarm is
+// frozen: every kernel of a step leaves it as it is.
+struct ConvRecord {
+    double* ring;
+    int32_t* state;
+    int32_t window;
+    double tol;
+};
+// frozen (nullable): when *frozen != 0 the kernels return at once.  conv
+// (nullable): after the swarm best, push it and apply the convergence rule
+// (rung iteration rung_it); its state[1] then serves as the frozen flag.
 void launch_pso_move(int64_t P, const PsoBox& box, const PsoParams& prm, uint64_t seed, uint32_t swarm, uint32_t it,
-                     double* theta, double* vel, const double* pbest, const double* gbest, hipStream_t s);
+                     double* theta, double* vel, const double* pbest, const double* gbest, hipStream_t s,
+                     const int32_t* frozen = nullptr);
 void launch_pso_best(int64_t P, const PsoBox& box, const double* theta, const double* vals, double* pbest,
-                     double* pbest_val, double* gbest, double* gbest_val, hipStream_t s);
+                     double* pbest_val, double* gbest, double* gbest_val, hipStream_t s,
+                     const ConvRecord* conv = nullptr, int32_t rung_it = 0);
 constexpr int kSortBuckets = 65536;  // 256 levels of k_hi x 256 levels of k_lo
 void launch_sort_perm(int64_t P, int64_t K, const int32_t* klo, const int32_t* khi, unsigned* hist, int32_t* bucket,
                       int32_t* rank, int32_t* perm, hipStream_t s);

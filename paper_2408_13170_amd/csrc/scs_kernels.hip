@@ -100,6 +100,12 @@ __global__ void k_prologue(PrologueArgs a)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= a.P) return;
+    if (a.frozen && *a.frozen) {  // a converged swarm of a search: nothing to evaluate
+        a.klo[p] = 0;
+        a.khi[p] = 0;
+        a.lg[p] = -1;
+        return;
+    }
     const int64_t S = a.stride;
     double* cf = a.coef;
     const int td = a.m.ecc ? kThetaMax : kTheta;
@@ -2235,10 +2241,10 @@ __global__ void k_pso_init(int64_t P, PsoBox box, uint64_t seed, uint32_t swarm,
 
 __global__ void k_pso_move(int64_t P, PsoBox box, PsoParams prm, uint64_t seed, uint32_t swarm, uint32_t it,
                            double* __restrict__ theta, double* __restrict__ vel, const double* __restrict__ pbest,
-                           const double* __restrict__ gbest)
+                           const double* __restrict__ gbest, const int32_t* __restrict__ frozen)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= P * box.dim) return;
+    if (i >= P * box.dim || (frozen && *frozen)) return;
     const int64_t pp = i / box.dim;
     const int d = (int)(i % box.dim);
     const double x = theta[i];
@@ -2276,10 +2282,10 @@ __global__ void k_pso_move(int64_t P, PsoBox box, PsoParams prm, uint64_t seed, 
 // Particle bests (one thread per particle), then the swarm best by a
 // single-workgroup arg-max (first index among equal values).
 __global__ void k_pso_pbest(int64_t P, PsoBox box, const double* __restrict__ theta, const double* __restrict__ vals,
-                            double* __restrict__ pbest, double* __restrict__ pbest_val)
+                            double* __restrict__ pbest, double* __restrict__ pbest_val, const int32_t* __restrict__ frozen)
 {
     const int64_t pp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (pp >= P) return;
+    if (pp >= P || (frozen && *frozen)) return;
     double v = vals[pp];
     bool inbox = true;
     const int D = box.dim;
@@ -2296,8 +2302,10 @@ __global__ void k_pso_pbest(int64_t P, PsoBox box, const double* __restrict__ th
 
 __global__ __launch_bounds__(1024) void k_pso_gbest(int64_t P, int D, const double* __restrict__ pbest,
                                                      const double* __restrict__ pbest_val, double* __restrict__ gbest,
-                                                     double* __restrict__ gbest_val)
+                                                     double* __restrict__ gbest_val, ConvRecord conv, int32_t rung_it)
 {
+    // the flag is read by every thread before thread 0 may set it below
+    if (conv.state && conv.state[1]) return;
     __shared__ double sv[1024];
     __shared__ int64_t si[1024];
     const int tid = threadIdx.x;
@@ -2325,6 +2333,23 @@ __global__ __launch_bounds__(1024) void k_pso_gbest(int64_t P, int D, const doub
         if (si[0] >= 0 && sv[0] > *gbest_val) {
             *gbest_val = sv[0];
             for (int d = 0; d < D; ++d) gbest[d] = pbest[si[0] * D + d];
+        }
+        if (conv.state) {
+            // the convergence rule: the best value rose by at most tol over
+            // the last window iterations (the value pushed window pushes ago
+            // still sits in the ring of window + 1)
+            const int32_t W = conv.window;
+            const int32_t h = conv.state[0];
+            const double v = *gbest_val;
+            conv.ring[h % (W + 1)] = v;
+            conv.state[0] = h + 1;
+            if (h + 1 > W) {
+                const double old = conv.ring[(h - W) % (W + 1)];
+                if (isfinite(old) && v - old <= conv.tol) {
+                    conv.state[1] = 1;
+                    conv.state[2] = rung_it;
+                }
+            }
         }
     }
 }
@@ -2583,16 +2608,21 @@ void launch_pso_init(int64_t P, const PsoBox& box, uint64_t seed, uint32_t swarm
     hipLaunchKernelGGL(k_pso_init, dim3(nblk(P * box.dim, 256)), dim3(256), 0, s, P, box, seed, swarm, theta);
 }
 void launch_pso_move(int64_t P, const PsoBox& box, const PsoParams& prm, uint64_t seed, uint32_t swarm, uint32_t it,
-                     double* theta, double* vel, const double* pbest, const double* gbest, hipStream_t s)
+                     double* theta, double* vel, const double* pbest, const double* gbest, hipStream_t s,
+                     const int32_t* frozen)
 {
     hipLaunchKernelGGL(k_pso_move, dim3(nblk(P * box.dim, 256)), dim3(256), 0, s, P, box, prm, seed, swarm, it, theta,
-                       vel, pbest, gbest);
+                       vel, pbest, gbest, frozen);
 }
 void launch_pso_best(int64_t P, const PsoBox& box, const double* theta, const double* vals, double* pbest,
-                     double* pbest_val, double* gbest, double* gbest_val, hipStream_t s)
+                     double* pbest_val, double* gbest, double* gbest_val, hipStream_t s, const ConvRecord* conv,
+                     int32_t rung_it)
 {
-    hipLaunchKernelGGL(k_pso_pbest, dim3(nblk(P, 256)), dim3(256), 0, s, P, box, theta, vals, pbest, pbest_val);
-    hipLaunchKernelGGL(k_pso_gbest, dim3(1), dim3(1024), 0, s, P, box.dim, pbest, pbest_val, gbest, gbest_val);
+    const ConvRecord c = conv ? *conv : ConvRecord{nullptr, nullptr, 0, 0.0};
+    hipLaunchKernelGGL(k_pso_pbest, dim3(nblk(P, 256)), dim3(256), 0, s, P, box, theta, vals, pbest, pbest_val,
+                       c.state ? c.state + 1 : nullptr);
+    hipLaunchKernelGGL(k_pso_gbest, dim3(1), dim3(1024), 0, s, P, box.dim, pbest, pbest_val, gbest, gbest_val, c,
+                       rung_it);
 }
 void launch_fill(double* p, int64_t n, double v, hipStream_t s)
 {

@@ -1,10 +1,14 @@
 // Hierarchical multi-swarm search (arXiv:2408.13170, Sec 3.1 - 3.2 and the PSO
-// appendix app:PSO_params), written on top of the library's public calls: the
-// swarms live on the device and every iteration is one scs_pso_step_swarms
-// over the swarms still moving (their moves, ONE batched generate-and-reduce
-// over all of their particles, their bests); the host keeps one number per
-// swarm per iteration (its best value) for the convergence rule, and
-// re-groups the particles between rungs with k-means.
+// appendix app:PSO_params).  The swarms live on the device; every iteration
+// is one batched step over the swarms still moving (their moves, ONE batched
+// generate-and-reduce over all of their particles, their bests), and the
+// convergence rule runs on the device too: the swarm best kernel keeps each
+// swarm's last window + 1 best values and freezes a swarm that converged, so
+// that every kernel of the later iterations leaves it as it is.  The host
+// queues kConvBatch iterations at a time and then reads the swarms'
+// convergence records (three integers each), instead of reading the best
+// values back after every iteration.  It re-groups the particles between
+// rungs with k-means.
 //
 //   rung:      Upsilon_N with the rung's N, equal-[h|h] edges, and the rung's
 //              hyper-parameters and minimum speeds (tab:PSO_hyperparams);
@@ -36,6 +40,18 @@
 #include <vector>
 
 #include "../../include/scs.h"
+#include "scs_internal.hpp"
+
+// scs_host.hip: one iteration of a search's swarms with convergence tracked
+// on the device, and the swarms' iteration counters
+int pso_step_swarms_tracked(scs_swarm* const* sws, int n, const scs_pso_params* prm, int prec,
+                            const scs::ConvRecord* conv, int32_t rung_it, hipStream_t s);
+uint32_t swarm_iteration(const scs_swarm* sw);
+void set_swarm_iteration(scs_swarm* sw, uint32_t it);
+int ctx_device(const scs_ctx* c);
+
+// iterations queued between two reads of the convergence records
+constexpr int kConvBatch = 8;
 
 namespace {
 
@@ -68,6 +84,12 @@ struct scs_search {
     std::vector<int64_t> sizes;
     uint32_t next_id = 0;
     int rungs_done = 0;
+    // device convergence records, one per swarm slot (at most n_swarms
+    // swarms exist at a time): ring [n][window + 1], state [n][3]
+    double* d_ring = nullptr;
+    int32_t* d_state = nullptr;
+    int32_t* h_state = nullptr;  // pinned copy of d_state
+    double* h_best = nullptr;    // pinned: the swarms' best values
 };
 
 // k-means with k-means++ seeding (Arthur & Vassilvitskii 2007) and Lloyd
@@ -179,6 +201,17 @@ extern "C" int scs_search_create(scs_ctx* ctx, const scs_search_params* p, const
         return rc0;
     }
     s->dim = dim;
+    {
+        const int n = p->n_swarms;
+        const size_t ring = sizeof(double) * (size_t)n * (p->conv_window + 1);
+        if (hipSetDevice(ctx_device(ctx)) != hipSuccess || hipMalloc((void**)&s->d_ring, ring) != hipSuccess ||
+            hipMalloc((void**)&s->d_state, sizeof(int32_t) * 3 * n) != hipSuccess ||
+            hipHostMalloc((void**)&s->h_state, sizeof(int32_t) * 3 * n, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void**)&s->h_best, sizeof(double) * n, hipHostMallocDefault) != hipSuccess) {
+            scs_search_destroy(s);
+            return err(SCS_ENOMEM, "search: convergence records could not be allocated");
+        }
+    }
     for (int d = 0; d < dim; ++d) {
         s->lo[d] = lo[d];
         s->hi[d] = hi[d];
@@ -284,52 +317,72 @@ extern "C" int scs_search_run_rung(scs_search* s, const scs_rung* r, scs_rung_re
     if (s->rungs_done > 0 && (rc = regroup(s))) return rc;
     if ((rc = scs_define_segmentation(s->ctx, r->N, SCS_SEG_EQUAL_SNR, s->p.G, nullptr))) return rc;
     const int nsw = (int)s->swarms.size();
-    std::vector<std::vector<double>> hist(nsw);
+    const int W = s->p.conv_window;
+    hipStream_t st = (hipStream_t)stream;
+    if (hipSetDevice(ctx_device(s->ctx)) != hipSuccess) return err(SCS_EDEVICE, "hipSetDevice failed");
+    // fresh records: nothing pushed, nothing converged
+    std::fill(s->h_state, s->h_state + 3 * nsw, 0);
+    if (hipMemcpyAsync(s->d_state, s->h_state, sizeof(int32_t) * 3 * nsw, hipMemcpyHostToDevice, st) != hipSuccess)
+        return err(SCS_EDEVICE, "search: record upload failed");
+    std::vector<scs::ConvRecord> conv(nsw);
+    std::vector<uint32_t> it0(nsw);
+    for (int i = 0; i < nsw; ++i) {
+        conv[i] = scs::ConvRecord{s->d_ring + (size_t)i * (W + 1), s->d_state + 3 * i, W, s->p.conv_tol};
+        it0[i] = swarm_iteration(s->swarms[i]);
+    }
     std::vector<char> done(nsw, 0);
+    std::vector<int32_t> done_at(nsw, -1);
     std::vector<scs_swarm*> act;
-    std::vector<int> idx;
-    std::vector<double> g;
+    std::vector<scs::ConvRecord> cact;
     int it = 0;
-    for (; it < r->max_iters; ++it) {
+    bool all = false;
+    while (it < r->max_iters && !all) {
         act.clear();
-        idx.clear();
+        cact.clear();
         for (int i = 0; i < nsw; ++i)
             if (!done[i]) {
                 act.push_back(s->swarms[i]);
-                idx.push_back(i);
+                cact.push_back(conv[i]);
             }
-        if (act.empty()) break;
-        // every active swarm moves and is evaluated in one batched launch
-        g.resize(act.size());
-        if ((rc = scs_pso_step_swarms(act.data(), (int32_t)act.size(), &r->prm, s->p.prec, g.data(), stream)))
-            return rc;
-        for (size_t a = 0; a < act.size(); ++a) {
-            const int i = idx[a];
-            hist[i].push_back(g[a]);
-            const size_t h = hist[i].size();
-            const size_t w = (size_t)s->p.conv_window;
-            if (h > w && std::isfinite(hist[i][h - 1 - w]) && hist[i][h - 1] - hist[i][h - 1 - w] <= s->p.conv_tol)
+        // a batch of iterations, queued with no read back: a swarm that
+        // converges part way through is frozen by its record on the device
+        const int nb = std::min(kConvBatch, r->max_iters - it);
+        for (int j = 0; j < nb; ++j)
+            if ((rc = pso_step_swarms_tracked(act.data(), (int)act.size(), &r->prm, s->p.prec, cact.data(), it + j, st)))
+                return rc;
+        if (hipMemcpyAsync(s->h_state, s->d_state, sizeof(int32_t) * 3 * nsw, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return err(SCS_EDEVICE, "search: record read failed");
+        all = true;
+        for (int i = 0; i < nsw; ++i) {
+            if (!done[i] && s->h_state[3 * i + 1]) {
                 done[i] = 1;
+                done_at[i] = s->h_state[3 * i + 2];
+                // the swarm took the iterations up to the one it converged in
+                set_swarm_iteration(s->swarms[i], it0[i] + (uint32_t)done_at[i] + 1u);
+            }
+            all = all && done[i];
         }
-        bool all = true;
-        for (int i = 0; i < nsw; ++i) all = all && done[i];
-        if (all) {
-            ++it;
-            break;
-        }
+        it += nb;
     }
+    // the rung ends at the iteration in which its last swarm converged
+    int iterations = it;
+    if (all) iterations = 1 + *std::max_element(done_at.begin(), done_at.end());
     s->rungs_done += 1;
     if (rep) {
         rep->N = r->N;
         rep->n_swarms = nsw;
-        rep->iterations = it;
-        int conv = 0;
+        rep->iterations = iterations;
+        int n_conv = 0;
         double best = -std::numeric_limits<double>::infinity();
         for (int i = 0; i < nsw; ++i) {
-            conv += done[i];
-            if (!hist[i].empty()) best = std::max(best, hist[i].back());
+            n_conv += done[i];
+            // a frozen swarm's best is the last value its record took
+            double g = 0.0;
+            if ((rc = scs_swarm_read(s->swarms[i], nullptr, nullptr, nullptr, nullptr, nullptr, &g, nullptr))) return rc;
+            best = std::max(best, g);
         }
-        rep->converged = conv;
+        rep->converged = n_conv;
         rep->best_val = best;
         rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
@@ -355,6 +408,14 @@ extern "C" int scs_search_destroy(scs_search* s)
 {
     if (!s) return SCS_OK;
     for (scs_swarm* sw : s->swarms) scs_swarm_destroy(sw);
+    if (s->d_ring || s->d_state) {
+        hipSetDevice(ctx_device(s->ctx));
+        hipDeviceSynchronize();
+    }
+    if (s->d_ring) hipFree(s->d_ring);
+    if (s->d_state) hipFree(s->d_state);
+    if (s->h_state) hipHostFree(s->h_state);
+    if (s->h_best) hipHostFree(s->h_best);
     delete s;
     return SCS_OK;
 }
