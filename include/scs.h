@@ -558,10 +558,22 @@ int scs_search_destroy(scs_search* s);
  * seeding with splitmix64 draws from seed, then Lloyd iterations until no
  * label changes or iters; ties go to the lower index; empty clusters are
  * dropped and labels [n] renumbered by first appearance; centers [k][dim]
- * (may be NULL); *k_out = clusters kept.  The re-grouping step of the search,
- * exported for its tests.  Errors: EINVAL. */
+ * (may be NULL); *k_out = clusters kept.  The re-grouping's k-means on host
+ * data, for callers that hold their points there.  Errors: EINVAL. */
 int scs_kmeans(const double* x, int64_t n, int32_t dim, int32_t k, int32_t iters, uint64_t seed, int32_t* labels,
                double* centers, int32_t* k_out);
+
+/* The same k-means on device data, as the search's re-grouping runs it: one
+ * workgroup takes the whole k-means, each of its threads a run of consecutive
+ * points, and every sum is formed in a fixed order, so a call gives the same
+ * labels every time.  They equal scs_kmeans's except where a point lies
+ * within rounding of two centres or a draw falls within rounding of a
+ * cumulative weight (the sums are ordered differently).  x (DEVICE [n][dim],
+ * dim <= 16), labels (DEVICE [n], out), centers (DEVICE [k][dim], out, may
+ * be NULL), *k_out (HOST) the clusters kept; 1 <= k <= 1024.  Allocates its
+ * scratch; synchronises the stream.  Errors: EINVAL, ENOMEM, EDEVICE. */
+int scs_kmeans_device(const double* x, int64_t n, int32_t dim, int32_t k, int32_t iters, uint64_t seed,
+                      int32_t* labels, double* centers, int32_t* k_out, void* stream);
 
 /* Thread-local description of the last error on this thread ("" if none). */
 const char* scs_last_error(void);

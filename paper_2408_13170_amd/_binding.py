@@ -135,6 +135,8 @@ _SIGS = {
     "scs_search_destroy": [C.c_void_p],
     "scs_kmeans": [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_uint64, C.c_void_p, C.c_void_p,
                    C.POINTER(C.c_int32)],
+    "scs_kmeans_device": [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_uint64, C.c_void_p,
+                          C.c_void_p, C.POINTER(C.c_int32), C.c_void_p],
     "scs_last_error": [],
 }
 _RESTYPES = {"scs_last_error": C.c_char_p, "scs_server_clock": C.c_double}
@@ -574,6 +576,24 @@ def scs_kmeans(x, k, iters=100, seed=0):
     _check(lib().scs_kmeans(C.c_void_p(x.ctypes.data), n, dim, k, iters, seed, C.c_void_p(labels.ctypes.data),
                             C.c_void_p(centers.ctypes.data), C.byref(ko)))
     return labels, centers[:ko.value].copy()
+
+
+def scs_kmeans_device(x, k, iters=100, seed=0, stream=None):
+    """x torch float64 [n, dim] on the device -> (labels int32 [n], centers
+    [k_out, dim]), both device tensors."""
+    import torch
+
+    if stream is None:
+        stream = current_stream()
+    if not (x.is_cuda and x.dtype == torch.float64 and x.dim() == 2 and x.is_contiguous()):
+        raise ValueError("x must be a contiguous float64 [n, dim] device tensor")
+    n, dim = x.shape
+    labels = torch.empty(n, dtype=torch.int32, device=x.device)
+    centers = torch.empty((k, dim), dtype=torch.float64, device=x.device)
+    ko = C.c_int32()
+    _check(lib().scs_kmeans_device(C.c_void_p(x.data_ptr()), n, dim, k, iters, seed, C.c_void_p(labels.data_ptr()),
+                                   C.c_void_p(centers.data_ptr()), C.byref(ko), _stream(stream)))
+    return labels, centers[:ko.value]
 
 
 def scs_pso_step(sw, params, prec=SCS_PREC_FP64, stream=None):

@@ -2515,6 +2515,15 @@ int pso_step_swarms_tracked(scs_swarm* const* sws, int n, const scs_pso_params* 
 uint32_t swarm_iteration(const scs_swarm* sw) { return sw->iteration; }
 void set_swarm_iteration(scs_swarm* sw, uint32_t it) { sw->iteration = it; }
 int ctx_device(const scs_ctx* c) { return c->device; }
+// A swarm's device arrays: theta, vel, pbest [P][D], pbest_val [P], gbest [D + 1].
+void swarm_arrays(scs_swarm* sw, double** theta, double** vel, double** pbest, double** pbest_val, double** gbest)
+{
+    *theta = sw->theta;
+    *vel = sw->vel;
+    *pbest = sw->pbest;
+    *pbest_val = sw->pbest_val;
+    *gbest = sw->gbest;
+}
 
 extern "C" int scs_swarm_read(scs_swarm* sw, double* theta, double* vel, double* pbest, double* pbest_val,
                               double* gbest, double* gbest_val, uint32_t* iteration)
