@@ -746,6 +746,7 @@ static int eval_front(EvalJob& j, const double* theta, double* ups, double* seg,
     ma.b32 = c->b32;
     ma.gtab = c->gtab;
     for (int l = 0; l < kMaxLevel; ++l) ma.gtab_off[l] = c->gtab_off[l];
+    ma.lg_max = c->lg_max;
     ma.perm = perm;
     ma.rec = w.rec;
     ma.zs = seg ? seg : w.zs;
@@ -1180,6 +1181,7 @@ extern "C" int scs_waveform(scs_ctx* c, const double* theta, double* h_ri, int32
     ma.lg = w.lg;
     ma.gtab = c->gtab;
     for (int l = 0; l < kMaxLevel; ++l) ma.gtab_off[l] = c->gtab_off[l];
+    ma.lg_max = c->lg_max;
     if (c->m.sparse > 0) {
         SplineArgs sa{};
         sa.g = c->g;
@@ -1291,6 +1293,7 @@ extern "C" int scs_evaluate_streams(scs_ctx* c, const double* theta, int64_t R, 
     ma.lg = w.lg;
     ma.gtab = c->gtab;
     for (int l = 0; l < kMaxLevel; ++l) ma.gtab_off[l] = c->gtab_off[l];
+    ma.lg_max = c->lg_max;
     ma.spl = w.spl;  // the sparse-grid template's nodes of theta, from the evaluation above
     ma.spl_nmax = c->m.sparse > 0 ? spl_max_nodes(c->g.K, c->m.sparse) : 0;
     launch_waveform(ma, st + off_h, s);

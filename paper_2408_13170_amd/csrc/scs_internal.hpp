@@ -145,6 +145,7 @@ struct MainArgs {
     const float* b32;
     const double* gtab;            // basis tables of every level
     int64_t gtab_off[kMaxLevel];   // entry offset of level lg
+    int32_t lg_max;                // log2 of the longest polynomial block (the basis table's top level)
     const int32_t* perm;   // slot -> particle (relative to p0), or null for identity
     double* rec;           // [chunk][rec_stride][kRec], indexed by slot
     double* zs;            // [P][N][3]: (Z re, Z im, H) of segments closed inside a chunk

@@ -1320,6 +1320,15 @@ __host__ __device__ constexpr int main_waves_per_eu(int nch, bool mixed, bool al
 // Plain FP32 partial sums cover the bins between consecutive multiples of
 // this (and a lane's own segment edges) before they enter the FP64 sums.
 constexpr int kMixedRun = 32;
+// The mixed path's polynomial blocks are twice as long as the FP64 bounds
+// allow (up to the longest block).  Its response cubics drop the
+// interpolant's T4 and T5 terms; the fourth orbital harmonic, at the largest
+// amplitude the FP64 bound admits, then spans at most ~0.14 rad per half
+// block, whose T4 coefficient is below 2e-6 of |R|: Upsilon moves by at most
+// ~4e-6, within the path's 1e-5, and by ~1e-7 on the PSO workloads (the
+// harmonic is far weaker than |R|).  Set-ups halve; four times as long would
+// allow ~6e-5 at worst.
+constexpr int kMixedLgBoost = 1;
 
 // One work tile (chunk, particle group) of the generate-and-reduce.  Called
 // by every thread of the workgroup; returns early, uniformly, when no
@@ -1346,6 +1355,7 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
     int lo = 0, hi = 0, lg = -1;
     if (p < a.P_end) {
         lg = ((const GLOBAL int8_t*)a.lg)[p];
+        if (MIXED && lg >= 0 && lg < a.lg_max) lg += kMixedLgBoost;
         if (lg >= 0) {
             lo = ((const GLOBAL int32_t*)a.klo)[p];
             hi = ((const GLOBAL int32_t*)a.khi)[p];
