@@ -563,10 +563,10 @@ int scs_search_destroy(scs_search* s);
 int scs_kmeans(const double* x, int64_t n, int32_t dim, int32_t k, int32_t iters, uint64_t seed, int32_t* labels,
                double* centers, int32_t* k_out);
 
-/* The same k-means on device data, as the search's re-grouping runs it: one
- * workgroup takes the whole k-means, each of its threads a run of consecutive
- * points, and every sum is formed in a fixed order, so a call gives the same
- * labels every time.  They equal scs_kmeans's except where a point lies
+/* The same k-means on device data, as the search's re-grouping runs it: each
+ * workgroup takes a run of 256 consecutive points, every sum is formed in a
+ * fixed order (workgroups' partial sums added in workgroup order), so a call
+ * gives the same labels every time.  They equal scs_kmeans's except where a point lies
  * within rounding of two centres or a draw falls within rounding of a
  * cumulative weight (the sums are ordered differently).  x (DEVICE [n][dim],
  * dim <= 16), labels (DEVICE [n], out), centers (DEVICE [k][dim], out, may

@@ -236,8 +236,6 @@ extern "C" int scs_search_create(scs_ctx* ctx, const scs_search_params* p, const
 
 namespace {
 
-constexpr int kKmThreads = 1024;  // one workgroup runs a re-grouping's whole k-means
-constexpr int kKmWaves = kKmThreads / 64;
 constexpr int kMaxFeat = 16;  // features per particle: at most 8 dimensions, 2 each when periodic
 
 struct FeatBox {
@@ -267,29 +265,23 @@ __global__ void k_features(int64_t P, FeatBox b, int F, const double* __restrict
     }
 }
 
-struct KmArgs {
-    int64_t P;
-    int32_t F, k, iters;
-    const double* x;      // [P][F] features
-    const double* draws;  // [k] the k-means++ draws, uniform in (0, 1), in the order they are used
-    const double* pv;     // [P] (nullable) the particles' best values so far, for the top members
-    double* d2;           // [P] scratch
-    int32_t* lab;         // [P] scratch: cluster labels
-    double* cen;          // [k][F] scratch: centres
-    int32_t* inv;         // [k] scratch: old label of each kept cluster
-    int32_t* map;         // [k] scratch: new label of each old one (-1: dropped)
-    int32_t* info;        // out: [0] clusters kept kk, [1 + c] size of kept cluster c, [1 + k + c] its top member
-    int32_t* labels;      // out (nullable): [P] labels, kept clusters numbered by first appearance
-    double* centers;      // out (nullable): [kk][F] their centres
-    int32_t* order;       // out (nullable, with pv): [P] particle indices, cluster by cluster, ascending within each
-};
+// k-means (Arthur & Vassilvitskii 2007 seeding, then Lloyd iterations until
+// no label changes, at most iters) on the device, with the steps of
+// scs_kmeans and of the host re-grouping: each workgroup takes a run of
+// kKmBlock consecutive points, one per thread, and every sum is formed in a
+// fixed order (within a workgroup by wave shuffles and then the waves in
+// turn, across workgroups in workgroup order), so a call gives the same
+// result every time.  The sums are ordered differently from the host's
+// sequential ones, so labels can differ only where a point lies within
+// rounding of two centres or a draw within rounding of a cumulative weight.
+constexpr int kKmBlock = 256;
+constexpr int kKmBWaves = kKmBlock / 64;
 
-// Sums over the workgroup of v[j] for j < n (n <= kMaxFeat) and, with
-// count, of v[kMaxFeat], in a fixed order (wave shuffles, then the waves in
-// turn), so that a run gives the same totals every time; the totals land in
-// out[j] (and out[kMaxFeat]).  Every index is a constant after unrolling, so
-// v stays in registers.
-__device__ void wg_sums(const double* v, int n, bool count, double* red, double* out)
+// Workgroup sums of v[j], j < n (n <= kMaxFeat), and with count of
+// v[kMaxFeat], in a fixed order (wave shuffles, then the waves in turn); the
+// totals land in out[j] (and out[kMaxFeat]).  Every index is a constant after
+// unrolling, so v stays in registers.  red: [kKmBWaves][kMaxFeat + 1].
+__device__ void blk_sums(const double* v, int n, bool count, double* red, double* out)
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
@@ -304,232 +296,292 @@ __device__ void wg_sums(const double* v, int n, bool count, double* red, double*
     const int j = threadIdx.x;
     if (j < n || (count && j == kMaxFeat)) {
         double t = 0.0;
-        for (int q = 0; q < kKmWaves; ++q) t += red[q * (kMaxFeat + 1) + j];
+        for (int q = 0; q < kKmBWaves; ++q) t += red[q * (kMaxFeat + 1) + j];
         out[j] = t;
     }
     __syncthreads();
 }
 
-// k-means (Arthur & Vassilvitskii 2007 seeding, then Lloyd iterations until
-// no label changes, at most iters), then the kept clusters in order of first
-// appearance and the particles grouped by cluster: the steps of scs_kmeans
-// and of the host re-grouping, on the device.  Each thread takes a run of
-// consecutive particles; every sum is formed in a fixed order.
-__global__ __launch_bounds__(kKmThreads) void k_kmeans(KmArgs a)
+__device__ __forceinline__ double km_dist(const double* __restrict__ x, int64_t i, int F, const double* c)
 {
-    __shared__ double red[kKmWaves * (kMaxFeat + 1)];
+    double s = 0.0;
+    for (int j = 0; j < F; ++j) {
+        const double d = x[i * F + j] - c[j];
+        s += d * d;
+    }
+    return s;
+}
+
+__global__ void k_km_fill(int32_t* p, int64_t n, int32_t v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Seeding, round m >= 1: each point's squared distance to its nearest centre
+// so far (centre m - 1 the newest), and each workgroup's sum of them.
+__global__ __launch_bounds__(kKmBlock) void k_km_seed_d2(int64_t P, int F, const double* __restrict__ x,
+                                                          const double* __restrict__ c, int first, double* d2,
+                                                          double* bsum)
+{
+    __shared__ double red[kKmBWaves * (kMaxFeat + 1)];
     __shared__ double tot[kMaxFeat + 1];
-    __shared__ double part[kKmThreads];
-    __shared__ int32_t ipart[kKmThreads];
-    __shared__ double bvs[kKmThreads];
-    __shared__ unsigned long long s_min, s_cnt;
-    __shared__ int s_changed;
-    const int t = threadIdx.x;
-    const int64_t P = a.P;
-    const int F = a.F, k = a.k;
-    const int64_t C = (P + kKmThreads - 1) / kKmThreads;
-    const int64_t i0 = t * C < P ? t * C : P, i1 = i0 + C < P ? i0 + C : P;
-    const double* x = a.x;
-    auto dist = [&](int64_t i, const double* c) {
-        double s = 0.0;
-        for (int j = 0; j < F; ++j) {
-            const double d = x[i * F + j] - c[j];
-            s += d * d;
-        }
-        return s;
-    };
-    auto clamp_pick = [&](double u) {
-        const int64_t q = (int64_t)(u * (double)P);
-        return q < P - 1 ? q : P - 1;
-    };
-    // ---- seeding: the first centre a uniform pick, each next one a pick
-    // with probability proportional to the squared distance to the nearest
-    // centre so far
-    if (t < F) a.cen[t] = x[clamp_pick(a.draws[0]) * F + t];
-    for (int64_t i = i0; i < i1; ++i) a.d2[i] = INFINITY;
-    __syncthreads();
-    for (int m = 1; m < k; ++m) {
-        double pl = 0.0;
-        const double* c = a.cen + (int64_t)(m - 1) * F;
-        for (int64_t i = i0; i < i1; ++i) {
-            const double d = dist(i, c);
-            if (d < a.d2[i]) a.d2[i] = d;
-            pl += a.d2[i];
-        }
-        part[t] = pl;
-        double v1[kMaxFeat + 1];
+    const int64_t i = (int64_t)blockIdx.x * kKmBlock + threadIdx.x;
+    double v[kMaxFeat + 1];
 #pragma unroll
-        for (int j = 0; j < kMaxFeat + 1; ++j) v1[j] = 0.0;
-        v1[0] = pl;
-        wg_sums(v1, 1, false, red, tot);
-        const double total = tot[0];
-        int64_t pick;
-        if (total > 0.0) {
-            const double u = a.draws[m] * total;
-            if (t == 0) {  // exclusive prefix sums of the runs, in thread order
-                double acc = 0.0;
-                for (int q = 0; q < kKmThreads; ++q) {
-                    const double v = part[q];
-                    part[q] = acc;
-                    acc += v;
+    for (int j = 0; j < kMaxFeat + 1; ++j) v[j] = 0.0;
+    if (i < P) {
+        const double d = km_dist(x, i, F, c);
+        const double o = first ? INFINITY : d2[i];
+        const double n = d < o ? d : o;
+        d2[i] = n;
+        v[0] = n;
+    }
+    blk_sums(v, 1, false, red, tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot[0];
+}
+
+// Seeding, round m: the pick (round 0: uniform; else the first point whose
+// running sum of squared distances reaches draw * total, the runs taken
+// workgroup by workgroup and then point by point), copied to centre m.
+__global__ void k_km_seed_pick(int64_t P, int F, int m, int64_t nb, const double* __restrict__ x,
+                               const double* __restrict__ draws, const double* __restrict__ d2,
+                               const double* __restrict__ bsum, double* cen)
+{
+    __shared__ int64_t s_pick;
+    if (threadIdx.x == 0) {
+        const double r = draws[m];
+        int64_t pick = -1;
+        double total = 0.0;
+        if (m > 0)
+            for (int64_t b = 0; b < nb; ++b) total += bsum[b];
+        if (m > 0 && total > 0.0) {
+            const double u = r * total;
+            double acc = 0.0;
+            for (int64_t b = 0; b < nb && pick < 0; ++b) {
+                if (acc + bsum[b] >= u) {
+                    double a2 = acc;
+                    const int64_t e = (b + 1) * kKmBlock < P ? (b + 1) * kKmBlock : P;
+                    for (int64_t i = b * kKmBlock; i < e; ++i) {
+                        a2 += d2[i];
+                        if (a2 >= u) {
+                            pick = i;
+                            break;
+                        }
+                    }
                 }
-                s_min = (unsigned long long)P;
+                acc += bsum[b];
             }
-            __syncthreads();
-            // the first particle whose running sum reaches u
-            double acc = part[t];
-            for (int64_t i = i0; i < i1; ++i) {
-                acc += a.d2[i];
-                if (acc >= u) {
-                    atomicMin(&s_min, (unsigned long long)i);
-                    break;
-                }
-            }
-            __syncthreads();
-            pick = (int64_t)s_min < P ? (int64_t)s_min : P - 1;
+            if (pick < 0) pick = P - 1;
         } else {
-            pick = clamp_pick(a.draws[m]);
+            pick = (int64_t)(r * (double)P);
+            pick = pick < P - 1 ? pick : P - 1;
         }
-        if (t < F) a.cen[(int64_t)m * F + t] = x[pick * F + t];
-        __syncthreads();
-    }
-    // ---- Lloyd iterations: nearest centre (ties to the lower index), then
-    // every non-empty cluster's centre to its mean
-    for (int64_t i = i0; i < i1; ++i) a.lab[i] = -1;
-    for (int it = 0; it < a.iters; ++it) {
-        if (t == 0) s_changed = 0;
-        __syncthreads();
-        int ch = 0;
-        for (int64_t i = i0; i < i1; ++i) {
-            int best = 0;
-            double bd = dist(i, a.cen);
-            for (int m = 1; m < k; ++m) {
-                const double dm = dist(i, a.cen + (int64_t)m * F);
-                if (dm < bd) {
-                    bd = dm;
-                    best = m;
-                }
-            }
-            if (a.lab[i] != best) {
-                a.lab[i] = best;
-                ch = 1;
-            }
-        }
-        if (ch) atomicOr(&s_changed, 1);
-        __syncthreads();
-        const bool changed = s_changed != 0;
-        __syncthreads();
-        if (!changed && it > 0) break;
-        for (int m = 0; m < k; ++m) {
-            double v[kMaxFeat + 1];
-#pragma unroll
-            for (int j = 0; j < kMaxFeat + 1; ++j) v[j] = 0.0;
-            for (int64_t i = i0; i < i1; ++i)
-                if (a.lab[i] == m) {
-#pragma unroll
-                    for (int j = 0; j < kMaxFeat; ++j)
-                        if (j < F) v[j] += x[i * F + j];
-                    v[kMaxFeat] += 1.0;
-                }
-            wg_sums(v, F, true, red, tot);
-            if (tot[kMaxFeat] > 0.0 && t < F) a.cen[(int64_t)m * F + t] = tot[t] / tot[kMaxFeat];
-            __syncthreads();
-        }
-    }
-    // ---- the kept clusters in order of first appearance
-    for (int m = 0; m < k; ++m) {
-        if (t == 0) {
-            s_min = (unsigned long long)P;
-            s_cnt = 0ULL;
-        }
-        __syncthreads();
-        unsigned long long first = (unsigned long long)P, cnt = 0ULL;
-        for (int64_t i = i0; i < i1; ++i)
-            if (a.lab[i] == m) {
-                if (first == (unsigned long long)P) first = (unsigned long long)i;
-                ++cnt;
-            }
-        if (cnt) {
-            atomicMin(&s_min, first);
-            atomicAdd(&s_cnt, cnt);
-        }
-        __syncthreads();
-        if (t == 0) {
-            a.d2[m] = (double)s_min;  // d2 is free now: cluster m's first particle
-            ipart[m] = (int32_t)s_cnt;
-        }
-        __syncthreads();
-    }
-    if (t == 0) {  // non-empty clusters, by insertion, in order of their first particle
-        int kk = 0;
-        for (int m = 0; m < k; ++m)
-            if (ipart[m] > 0) {
-                int q = kk++;
-                while (q > 0 && a.d2[a.inv[q - 1]] > a.d2[m]) {
-                    a.inv[q] = a.inv[q - 1];
-                    --q;
-                }
-                a.inv[q] = m;
-            }
-        a.info[0] = kk;
-        for (int m = 0; m < k; ++m) a.map[m] = -1;
-        for (int c = 0; c < kk; ++c) {
-            a.info[1 + c] = ipart[a.inv[c]];
-            a.map[a.inv[c]] = c;
-        }
+        s_pick = pick;
     }
     __syncthreads();
-    const int kk = a.info[0];
-    if (a.labels)
-        for (int64_t i = i0; i < i1; ++i) a.labels[i] = a.map[a.lab[i]];
-    if (a.centers && t < F)
-        for (int c = 0; c < kk; ++c) a.centers[(int64_t)c * F + t] = a.cen[(int64_t)a.inv[c] * F + t];
-    if (!a.order || !a.pv) return;
-    // ---- the particles grouped by kept cluster, each cluster's top member
-    // (the highest earlier best value, the first among equals)
-    int64_t base = 0;
-    for (int c = 0; c < kk; ++c) {
-        const int m = a.inv[c];
-        // the run's count and top member: its first member, then strictly larger values
-        int32_t cnt = 0;
-        double bv = -INFINITY;
-        int64_t bi = P;
-        for (int64_t i = i0; i < i1; ++i)
-            if (a.lab[i] == m) {
-                if (bi == P || a.pv[i] > bv) {
-                    bv = a.pv[i];
-                    bi = i;
-                }
-                ++cnt;
+    for (int j = threadIdx.x; j < F; j += blockDim.x) cen[(int64_t)m * F + j] = x[s_pick * F + j];
+}
+
+// Lloyd, one iteration's first half: nearest centre of each point (ties to
+// the lower index), whether any label of the workgroup changed, and each
+// cluster's sum and count over the workgroup's points.  Nothing once the
+// iterations have stopped (state[0]).
+__global__ __launch_bounds__(kKmBlock) void k_km_assign(int64_t P, int F, int k, const double* __restrict__ x,
+                                                         const double* __restrict__ cen, int32_t* lab,
+                                                         double* part, int32_t* chg, const int32_t* state)
+{
+    __shared__ double red[kKmBWaves * (kMaxFeat + 1)];
+    __shared__ double tot[kMaxFeat + 1];
+    if (state[0]) return;
+    const int64_t i = (int64_t)blockIdx.x * kKmBlock + threadIdx.x;
+    int best = -1;
+    int changed = 0;
+    if (i < P) {
+        best = 0;
+        double bd = km_dist(x, i, F, cen);
+        for (int m = 1; m < k; ++m) {
+            const double dm = km_dist(x, i, F, cen + (int64_t)m * F);
+            if (dm < bd) {
+                bd = dm;
+                best = m;
             }
-        ipart[t] = cnt;
-        bvs[t] = bv;
-        part[t] = (double)bi;
+        }
+        if (lab[i] != best) {
+            lab[i] = best;
+            changed = 1;
+        }
+    }
+    const int any = __syncthreads_or(changed);
+    if (threadIdx.x == 0) chg[blockIdx.x] = any;
+    double* pb = part + (int64_t)blockIdx.x * k * (kMaxFeat + 1);
+    for (int m = 0; m < k; ++m) {
+        const bool mine = best == m;
+        if (!__syncthreads_or(mine)) {
+            if ((int)threadIdx.x <= F) pb[(int64_t)m * (kMaxFeat + 1) + (threadIdx.x == (unsigned)F ? kMaxFeat : threadIdx.x)] = 0.0;
+            continue;
+        }
+        double v[kMaxFeat + 1];
+#pragma unroll
+        for (int j = 0; j < kMaxFeat + 1; ++j) v[j] = 0.0;
+        if (mine) {
+#pragma unroll
+            for (int j = 0; j < kMaxFeat; ++j)
+                if (j < F) v[j] = x[i * F + j];
+            v[kMaxFeat] = 1.0;
+        }
+        blk_sums(v, F, true, red, tot);
+        if ((int)threadIdx.x < F) pb[(int64_t)m * (kMaxFeat + 1) + threadIdx.x] = tot[threadIdx.x];
+        if ((int)threadIdx.x == F) pb[(int64_t)m * (kMaxFeat + 1) + kMaxFeat] = tot[kMaxFeat];
+    }
+}
+
+// Lloyd, the second half (one workgroup): stop if no label changed (and it
+// was not the first iteration); else every non-empty cluster's centre to the
+// mean of its points, the workgroups' sums added in workgroup order.
+__global__ void k_km_update(int F, int k, int64_t nb, const double* __restrict__ part, const int32_t* __restrict__ chg,
+                            double* cen, int32_t* state)
+{
+    __shared__ int s_stop;
+    const int done = state[0], it = state[1];
+    if (done) return;
+    if (threadIdx.x == 0) {
+        int any = 0;
+        for (int64_t b = 0; b < nb; ++b) any |= chg[b];
+        s_stop = (!any && it > 0);
+    }
+    __syncthreads();
+    if (s_stop) {
+        if (threadIdx.x == 0) state[0] = 1;
+        return;
+    }
+    for (int q = threadIdx.x; q < k * F; q += blockDim.x) {
+        const int m = q / F, j = q % F;
+        double sj = 0.0, cnt = 0.0;
+        for (int64_t b = 0; b < nb; ++b) {
+            const double* pb = part + (b * k + m) * (kMaxFeat + 1);
+            sj += pb[j];
+            cnt += pb[kMaxFeat];
+        }
+        if (cnt > 0.0) cen[(int64_t)m * F + j] = sj / cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) state[1] = it + 1;
+}
+
+// Per workgroup and cluster: the count, the first point, and the top member
+// (the highest earlier best value, the first among equals; pv may be NULL).
+__global__ __launch_bounds__(kKmBlock) void k_km_blockstats(int64_t P, int k, const int32_t* __restrict__ lab,
+                                                             const double* __restrict__ pv, int32_t* bcnt,
+                                                             int32_t* bfirst, double* btv, int32_t* bti)
+{
+    __shared__ double sv[kKmBlock];
+    __shared__ int32_t si[kKmBlock];
+    const int64_t i = (int64_t)blockIdx.x * kKmBlock + threadIdx.x;
+    const int l = i < P ? lab[i] : -1;
+    for (int m = 0; m < k; ++m) {
+        const bool mine = l == m;
+        sv[threadIdx.x] = mine ? (pv ? pv[i] : 0.0) : -INFINITY;
+        si[threadIdx.x] = mine ? (int32_t)i : INT32_MAX;
         __syncthreads();
-        if (t == 0) {
-            int32_t acc = 0;
-            for (int q = 0; q < kKmThreads; ++q) {
-                const int32_t v = ipart[q];
-                ipart[q] = acc;
-                acc += v;
-            }
-            // the top over the runs: the largest value, the lowest index among equals
+        if (threadIdx.x == 0) {
+            int32_t cnt = 0, first = INT32_MAX, ti = INT32_MAX;
             double tv = -INFINITY;
-            int64_t ti = P;
-            for (int q = 0; q < kKmThreads; ++q) {
-                const int64_t qi = (int64_t)part[q];
-                if (qi < P && (ti == P || bvs[q] > tv)) {
-                    tv = bvs[q];
-                    ti = qi;
+            for (int q = 0; q < kKmBlock; ++q)
+                if (si[q] != INT32_MAX) {
+                    ++cnt;
+                    if (first == INT32_MAX) first = si[q];
+                    if (ti == INT32_MAX || sv[q] > tv) {
+                        tv = sv[q];
+                        ti = si[q];
+                    }
                 }
-            }
-            a.info[1 + k + c] = (int32_t)ti;
+            const int64_t o = (int64_t)blockIdx.x * k + m;
+            bcnt[o] = cnt;
+            bfirst[o] = first;
+            btv[o] = tv;
+            bti[o] = ti;
         }
         __syncthreads();
-        int64_t pos = base + ipart[t];
-        for (int64_t i = i0; i < i1; ++i)
-            if (a.lab[i] == m) a.order[pos++] = (int32_t)i;
-        base += a.info[1 + c];
+    }
+}
+
+// One workgroup, one thread: the kept clusters in order of their first point,
+// their sizes and top members, and where each workgroup's points of each
+// kept cluster start in the grouped order.
+__global__ void k_km_finish(int k, int64_t nb, const int32_t* __restrict__ bcnt, const int32_t* __restrict__ bfirst,
+                            const double* __restrict__ btv, const int32_t* __restrict__ bti, int32_t* inv,
+                            int32_t* map, int32_t* info, int64_t* base)
+{
+    if (threadIdx.x != 0) return;
+    // each cluster's first point (INT32_MAX: empty), held in map for now
+    for (int m = 0; m < k; ++m) {
+        int64_t cnt = 0;
+        int32_t first = INT32_MAX;
+        for (int64_t b = 0; b < nb; ++b) {
+            cnt += bcnt[b * k + m];
+            if (bfirst[b * k + m] < first) first = bfirst[b * k + m];
+        }
+        map[m] = cnt ? first : INT32_MAX;
+    }
+    int kk = 0;
+    for (int m = 0; m < k; ++m) {
+        if (map[m] == INT32_MAX) continue;
+        int q = kk++;  // insertion by first point
+        while (q > 0 && map[inv[q - 1]] > map[m]) {
+            inv[q] = inv[q - 1];
+            --q;
+        }
+        inv[q] = m;
+    }
+    for (int m = 0; m < k; ++m) map[m] = -1;
+    info[0] = kk;
+    int64_t off = 0;
+    for (int c = 0; c < kk; ++c) {
+        const int m = inv[c];
+        map[m] = c;
+        double tv = -INFINITY;
+        int32_t ti = INT32_MAX;
+        int64_t cnt = 0;
+        for (int64_t b = 0; b < nb; ++b) {
+            base[(int64_t)c * nb + b] = off + cnt;
+            cnt += bcnt[b * k + m];
+            const int32_t bi = bti[b * k + m];
+            if (bi != INT32_MAX && (ti == INT32_MAX || btv[b * k + m] > tv)) {
+                tv = btv[b * k + m];
+                ti = bi;
+            }
+        }
+        info[1 + c] = (int32_t)cnt;
+        info[1 + k + c] = ti;
+        off += cnt;
+    }
+}
+
+// Each point's new label and its place in the grouped order: its cluster's
+// start for the workgroup plus the points of that cluster before it there.
+__global__ __launch_bounds__(kKmBlock) void k_km_scatter(int64_t P, int64_t nb, const int32_t* __restrict__ lab,
+                                                          const int32_t* __restrict__ map, const int32_t* __restrict__ info,
+                                                          const int64_t* __restrict__ base, int32_t* labels,
+                                                          int32_t* order)
+{
+    __shared__ int32_t wc[kKmBWaves];
+    const int64_t i = (int64_t)blockIdx.x * kKmBlock + threadIdx.x;
+    const int c = i < P ? map[lab[i]] : -1;
+    if (labels && i < P) labels[i] = c;
+    if (!order) return;
+    const int kk = info[0];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int q = 0; q < kk; ++q) {
+        const unsigned long long mask = __ballot(c == q);
+        if (lane == 0) wc[w] = __popcll(mask);
+        __syncthreads();
+        if (c == q) {
+            int64_t pos = base[(int64_t)q * nb + blockIdx.x];
+            for (int v = 0; v < w; ++v) pos += wc[v];
+            pos += __popcll(mask & ((1ULL << lane) - 1ULL));
+            order[pos] = (int32_t)i;
+        }
         __syncthreads();
     }
 }
@@ -547,41 +599,86 @@ __global__ void k_gather_rows(int64_t n, int D, const int32_t* __restrict__ idx,
 
 }  // namespace
 
-// The k-means of KmArgs on device data x [P][F]: scratch allocated here, the
+// The k-means above on device data x [P][F]: scratch allocated here, the
 // draws from seed (splitmix64, in the order the seeding uses them); info
 // (host, 1 + 2k entries) receives the kept count, sizes and top members.
-// Queued on st; returns once info is on the host.
+// The Lloyd iterations are queued 16 at a time; after each batch the host
+// reads whether they stopped.  Queued on st; returns once info is on the host.
 static int kmeans_dev(const double* x, int64_t P, int F, int k, int iters, uint64_t seed, const double* pv,
                       int32_t* labels, double* centers, int32_t* order, std::vector<int32_t>& info, hipStream_t st)
 {
     SplitMix rng{seed};
     std::vector<double> draws(k);
     for (int m = 0; m < k; ++m) draws[m] = rng.uniform();
-    double *d2 = nullptr, *cen = nullptr, *dr = nullptr;
-    int32_t *lab = nullptr, *inv = nullptr, *map = nullptr, *dinfo = nullptr;
+    const int64_t nb = (P + kKmBlock - 1) / kKmBlock;
+    double *d2 = nullptr, *cen = nullptr, *dr = nullptr, *bsum = nullptr, *part = nullptr, *btv = nullptr;
+    int32_t *lab = nullptr, *chg = nullptr, *state = nullptr, *bcnt = nullptr, *bfirst = nullptr, *bti = nullptr,
+            *inv = nullptr, *map = nullptr, *dinfo = nullptr;
+    int64_t* base = nullptr;
     int rc = SCS_OK;
-    if (hipMalloc((void**)&d2, sizeof(double) * std::max<int64_t>(P, k)) != hipSuccess ||
-        hipMalloc((void**)&cen, sizeof(double) * (size_t)k * F) != hipSuccess ||
-        hipMalloc((void**)&dr, sizeof(double) * k) != hipSuccess ||
-        hipMalloc((void**)&lab, sizeof(int32_t) * P) != hipSuccess ||
-        hipMalloc((void**)&inv, sizeof(int32_t) * k) != hipSuccess ||
-        hipMalloc((void**)&map, sizeof(int32_t) * k) != hipSuccess ||
-        hipMalloc((void**)&dinfo, sizeof(int32_t) * (1 + 2 * k)) != hipSuccess)
+    auto al = [&](void** q, size_t bytes) { return hipMalloc(q, bytes) == hipSuccess; };
+    if (!al((void**)&d2, sizeof(double) * P) || !al((void**)&cen, sizeof(double) * (size_t)k * F) ||
+        !al((void**)&dr, sizeof(double) * k) || !al((void**)&bsum, sizeof(double) * nb) ||
+        !al((void**)&part, sizeof(double) * (size_t)nb * k * (kMaxFeat + 1)) ||
+        !al((void**)&btv, sizeof(double) * (size_t)nb * k) || !al((void**)&lab, sizeof(int32_t) * P) ||
+        !al((void**)&chg, sizeof(int32_t) * nb) || !al((void**)&state, sizeof(int32_t) * 2) ||
+        !al((void**)&bcnt, sizeof(int32_t) * (size_t)nb * k) || !al((void**)&bfirst, sizeof(int32_t) * (size_t)nb * k) ||
+        !al((void**)&bti, sizeof(int32_t) * (size_t)nb * k) || !al((void**)&inv, sizeof(int32_t) * k) ||
+        !al((void**)&map, sizeof(int32_t) * k) || !al((void**)&dinfo, sizeof(int32_t) * (1 + 2 * k)) ||
+        !al((void**)&base, sizeof(int64_t) * (size_t)k * nb))
         rc = err(SCS_ENOMEM, "k-means: device buffers could not be allocated");
     info.assign(1 + 2 * k, 0);
     if (rc == SCS_OK &&
         hipMemcpyAsync(dr, draws.data(), sizeof(double) * k, hipMemcpyHostToDevice, st) != hipSuccess)
         rc = err(SCS_EDEVICE, "k-means: upload failed");
     if (rc == SCS_OK) {
-        KmArgs ka{P, F, k, iters, x, dr, pv, d2, lab, cen, inv, map, dinfo, labels, centers, order};
-        hipLaunchKernelGGL(k_kmeans, dim3(1), dim3(kKmThreads), 0, st, ka);
-        if (hipGetLastError() != hipSuccess ||
-            hipMemcpyAsync(info.data(), dinfo, sizeof(int32_t) * (1 + 2 * k), hipMemcpyDeviceToHost, st) != hipSuccess ||
-            hipStreamSynchronize(st) != hipSuccess)
-            rc = err(SCS_EDEVICE, "k-means on the device failed");
+        const dim3 g((unsigned)nb), b(kKmBlock);
+        hipLaunchKernelGGL(k_km_fill, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, st, lab, P, -1);
+        hipLaunchKernelGGL(k_km_fill, dim3(1), dim3(256), 0, st, state, (int64_t)2, 0);
+        hipLaunchKernelGGL(k_km_seed_pick, dim3(1), dim3(64), 0, st, P, F, 0, nb, x, dr, d2, bsum, cen);
+        for (int m = 1; m < k; ++m) {
+            hipLaunchKernelGGL(k_km_seed_d2, g, b, 0, st, P, F, x, cen + (size_t)(m - 1) * F, m == 1 ? 1 : 0, d2,
+                               bsum);
+            hipLaunchKernelGGL(k_km_seed_pick, dim3(1), dim3(64), 0, st, P, F, m, nb, x, dr, d2, bsum, cen);
+        }
+        int32_t hstate[2] = {0, 0};
+        for (int it = 0; it < iters && rc == SCS_OK;) {
+            const int n = std::min(16, iters - it);
+            for (int q = 0; q < n; ++q) {
+                hipLaunchKernelGGL(k_km_assign, g, b, 0, st, P, F, k, x, cen, lab, part, chg, state);
+                hipLaunchKernelGGL(k_km_update, dim3(1), dim3(256), 0, st, F, k, nb, part, chg, cen, state);
+            }
+            it += n;
+            if (hipGetLastError() != hipSuccess ||
+                hipMemcpyAsync(hstate, state, sizeof(hstate), hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess)
+                rc = err(SCS_EDEVICE, "k-means on the device failed");
+            if (hstate[0]) break;
+        }
+        if (rc == SCS_OK) {
+            hipLaunchKernelGGL(k_km_blockstats, g, b, 0, st, P, k, lab, pv, bcnt, bfirst, btv, bti);
+            hipLaunchKernelGGL(k_km_finish, dim3(1), dim3(64), 0, st, k, nb, bcnt, bfirst, btv, bti, inv, map, dinfo,
+                               base);
+            hipLaunchKernelGGL(k_km_scatter, g, b, 0, st, P, nb, lab, map, dinfo, base, labels, order);
+            if (hipGetLastError() != hipSuccess ||
+                hipMemcpyAsync(info.data(), dinfo, sizeof(int32_t) * (1 + 2 * k), hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess)
+                rc = err(SCS_EDEVICE, "k-means on the device failed");
+        }
+        if (rc == SCS_OK && centers) {
+            std::vector<int32_t> hinv(k);
+            if (hipMemcpy(hinv.data(), inv, sizeof(int32_t) * k, hipMemcpyDeviceToHost) != hipSuccess)
+                rc = err(SCS_EDEVICE, "k-means: read failed");
+            for (int c = 0; c < info[0] && rc == SCS_OK; ++c)
+                if (hipMemcpyAsync(centers + (size_t)c * F, cen + (size_t)hinv[c] * F, sizeof(double) * F,
+                                   hipMemcpyDeviceToDevice, st) != hipSuccess)
+                    rc = err(SCS_EDEVICE, "k-means: centre copy failed");
+        }
     }
     hipStreamSynchronize(st);
-    for (void* q : {(void*)d2, (void*)cen, (void*)dr, (void*)lab, (void*)inv, (void*)map, (void*)dinfo})
+    for (void* q : {(void*)d2, (void*)cen, (void*)dr, (void*)bsum, (void*)part, (void*)btv, (void*)lab, (void*)chg,
+                    (void*)state, (void*)bcnt, (void*)bfirst, (void*)bti, (void*)inv, (void*)map, (void*)dinfo,
+                    (void*)base})
         if (q) hipFree(q);
     return rc;
 }
