@@ -318,7 +318,7 @@ __global__ void k_km_fill(int32_t* p, int64_t n, int32_t v)
     if (i < n) p[i] = v;
 }
 
-// Seeding, round m >= 1: each point's squared distance to its nearest centre
+// Seeding, centre m >= 1: each point's squared distance to its nearest centre
 // so far (centre m - 1 the newest), and each workgroup's sum of them.
 __global__ __launch_bounds__(kKmBlock) void k_km_seed_d2(int64_t P, int F, const double* __restrict__ x,
                                                           const double* __restrict__ c, int first, double* d2,
@@ -341,7 +341,7 @@ __global__ __launch_bounds__(kKmBlock) void k_km_seed_d2(int64_t P, int F, const
     if (threadIdx.x == 0) bsum[blockIdx.x] = tot[0];
 }
 
-// Seeding, round m: the pick (round 0: uniform; else the first point whose
+// Seeding, centre m: the pick (centre 0: uniform; else the first point whose
 // running sum of squared distances reaches draw * total, the runs taken
 // workgroup by workgroup and then point by point), copied to centre m.
 __global__ void k_km_seed_pick(int64_t P, int F, int m, int64_t nb, const double* __restrict__ x,
