@@ -96,6 +96,10 @@ __device__ inline double dphase_pn(const double* cf, double f)
     return s;
 }
 
+static_assert(C_COUNT <= kCoefStride, "the coefficient record holds every field");
+// a bin index beyond any grid: no block length change ahead
+constexpr double kNoBin = 0x1p40;
+
 __global__ void k_prologue(PrologueArgs a)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -211,33 +215,52 @@ __global__ void k_prologue(PrologueArgs a)
     //      whose Taylor / Chebyshev remainders stay below 1e-12 cycles
     //      (phase) and 1e-11 relative (response), using the Newtonian scaling
     //      at the fastest-chirping point of the support, its start.
-    int lg = -2;
-    if (khi > klo) {
-        const double fs = (a.g.k0 + (double)klo) * a.g.df;
+    // Both remainders fall as f rises (the chirp slows), so a length that
+    // holds at one bin holds at every later one; blocks that start at or
+    // after bin kup[i] may be 2^(i+1) times the support start's length.
+    auto block_ok = [&](double fs, int l) {
         double taus = -dphase_pn(b, fs);
         taus = taus > 0.0 ? taus : 0.0;
+        const double h = (double)(1 << (l - 1));
+        const double r = h * a.g.df / fs;
+        const double r2 = r * r, r6 = r2 * r2 * r2;
+        // the eccentric term's sixth Taylor coefficient is ~17 times the
+        // Newtonian one per unit size, and its size is <= 1.61 e0^2 of it
+        const double ephi = 2.4 * taus * fs * r6 * (1.0 + 27.0 * e0 * e0);
+        bool good = ephi <= 1e-12;
+        if (a.m.response != 0) {
+            // fourth orbital harmonic; the full response's arm-length
+            // terms add harmonics of small amplitude only (its
+            // interpolation error at the block's worst point is within
+            // a few percent of the low-frequency response's)
+            const double th_h = 4.0 * kTwoPi * kInvYear * (8.0 / 3.0) * (taus / fs) * a.g.df * h;
+            const double t2 = th_h * th_h;
+            good = good && (t2 * t2 * t2 / 11520.0) <= 1e-11;
+        }
+        return good;
+    };
+    int lg = -2;
+    double kup[2] = {kNoBin, kNoBin};
+    if (khi > klo) {
+        const double fs = (a.g.k0 + (double)klo) * a.g.df;
         for (int l = a.lg_max; l >= 3; --l) {
-            const double h = (double)(1 << (l - 1));
-            const double r = h * a.g.df / fs;
-            const double r2 = r * r, r6 = r2 * r2 * r2;
-            // the eccentric term's sixth Taylor coefficient is ~17 times the
-            // Newtonian one per unit size, and its size is <= 1.61 e0^2 of it
-            const double ephi = 2.4 * taus * fs * r6 * (1.0 + 27.0 * e0 * e0);
-            bool good = ephi <= 1e-12;
-            if (a.m.response != 0) {
-                // fourth orbital harmonic; the full response's arm-length
-                // terms add harmonics of small amplitude only (its
-                // interpolation error at the block's worst point is within
-                // a few percent of the low-frequency response's)
-                const double th_h = 4.0 * kTwoPi * kInvYear * (8.0 / 3.0) * (taus / fs) * a.g.df * h;
-                const double t2 = th_h * th_h;
-                good = good && (t2 * t2 * t2 / 11520.0) <= 1e-11;
-            }
-            if (good) { lg = l; break; }
+            if (block_ok(fs, l)) { lg = l; break; }
         }
         // the sparse-grid template expands nothing in blocks: every theta resolves
         if (lg < 0 && a.m.sparse > 0) lg = a.lg_max;
         if (lg < 0) atomicAdd(a.unresolved, 1ULL);
+        if (lg >= 3 && a.m.sparse == 0) {
+            for (int i = 0; i < 2 && lg + 1 + i <= a.lg_max; ++i) {
+                const int l = lg + 1 + i;
+                int64_t lo = klo, hi = khi;  // first bin of [klo, khi) where l holds, or khi
+                while (lo < hi) {
+                    const int64_t mid = lo + (hi - lo) / 2;
+                    if (block_ok((a.g.k0 + (double)mid) * a.g.df, l)) hi = mid; else lo = mid + 1;
+                }
+                if (lo >= khi) break;
+                kup[i] = (double)lo;
+            }
+        }
     } else {
         lg = a.lg_max;  // empty support: nothing to resolve
     }
@@ -302,6 +325,8 @@ __global__ void k_prologue(PrologueArgs a)
     cf[p * kCoefStride + C_TAUL] = tau.lo;
     cf[p * kCoefStride + C_TC] = tcs;
     cf[p * kCoefStride + C_TCL] = tc.lo - (tcs - tc.hi);
+    cf[p * kCoefStride + C_LGUP] = kup[0];
+    cf[p * kCoefStride + C_LGUP + 1] = kup[1];
     a.klo[p] = (int32_t)klo;
     a.khi[p] = (int32_t)khi;
     a.lg[p] = (int8_t)lg;
@@ -1352,18 +1377,40 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
     const int cbins = a.L * a.CB;
     const int Kc = (int)chunk * cbins;
     const int Ke = (Kc + cbins < K) ? Kc + cbins : K;
-    int lo = 0, hi = 0, lg = -1;
+    // Block level (log2 of the polynomial block length) of the lane at a bin:
+    // the prologue's level lgb at the support start, one more from the first
+    // super-block (2^lg_max bins, aligned) that starts at or after the bin
+    // from which twice the length meets the same bounds (up0), two more from
+    // up1 (the chirp slows as f rises).  Levels change only at super-block
+    // starts, so every block lies inside one super-block, and the choice
+    // does not depend on how the band is cut into chunks.  The mixed path
+    // then doubles the length (below lg_max).
+    int lo = 0, hi = 0, lgb = -1;
+    int up0 = INT32_MAX, up1 = INT32_MAX;
     if (p < a.P_end) {
-        lg = ((const GLOBAL int8_t*)a.lg)[p];
-        if (MIXED && lg >= 0 && lg < a.lg_max) lg += kMixedLgBoost;
-        if (lg >= 0) {
+        lgb = ((const GLOBAL int8_t*)a.lg)[p];
+        if (TM == 0 && lgb >= 3 && lgb < a.lg_max) {
+            const GLOBAL double* cfp = (const GLOBAL double*)a.coef + p * kCoefStride + C_LGUP;
+            const double sup = (double)(1 << a.lg_max);
+            const double u0 = ceil(cfp[0] / sup) * sup, u1 = ceil(cfp[1] / sup) * sup;
+            up0 = u0 < 2147483647.0 ? (int)u0 : INT32_MAX;
+            up1 = (lgb + 2 <= a.lg_max && u1 < 2147483647.0) ? (int)u1 : INT32_MAX;
+        }
+        if (lgb >= 0) {
             lo = ((const GLOBAL int32_t*)a.klo)[p];
             hi = ((const GLOBAL int32_t*)a.khi)[p];
         }
     }
+    auto level_at = [&](int k) {
+        int l = lgb + (k >= up0 ? 1 : 0) + (k >= up1 ? 1 : 0);
+        if (MIXED && l >= 0 && l < a.lg_max) l += kMixedLgBoost;
+        return l;
+    };
     const int plo = lo, phi = hi;  // the whole support (the sparse-grid template's nodes)
     lo = lo > Kc ? lo : Kc;
     hi = hi < Ke ? hi : Ke;
+    // the lane's level at its first bin in the chunk, the lowest in the chunk
+    const int lg = level_at(lo);
     const bool has = lo < hi;
     if (!__syncthreads_or(has)) return;
     const int64_t S = a.stride;
@@ -1498,14 +1545,12 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
         }
     }
     // Each lane builds its polynomials on the sub-blocks of its own length
-    // 2^lgl (aligned; the wave steps through the shortest in the wave, whose
-    // boundaries are boundaries of every lane's), so a particle's arithmetic
-    // does not depend on the particles that share its wave.  have: first bin
-    // of the lane's current sub-block (-1: none yet); kcl its centre.  After
-    // its support a lane keeps its last polynomials: what they add is never
-    // read.
-    const int lgl = has ? lg : lgw;
-    const GLOBAL double* __restrict__ gtl = (const GLOBAL double*)gtab + a.gtab_off[lgl] * kGStride;
+    // 2^lgl (aligned; the wave steps through the shortest in the wave at the
+    // chunk start, whose boundaries are boundaries of every lane's blocks in
+    // the chunk), so a particle's arithmetic does not depend on the particles
+    // that share its wave.  have: first bin of the lane's current sub-block
+    // (-1: none yet); kcl its centre.  After its support a lane keeps its
+    // last polynomials: what they add is never read.
     const GLOBAL double* __restrict__ coef = (const GLOBAL double*)a.coef;
     int have = -1, kcl = 0;
     // Sparse-grid template: bins are taken in pieces between multiples of
@@ -1644,11 +1689,13 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
             const int s_lo = sb0 > wlo ? sb0 : wlo;
             const int s_hi = (sb0 + Lp < whi) ? sb0 + Lp : whi;
             const bool sact = act && llo < sb0 + Lp && lhi > sb0;
+            const int lgl = has ? level_at(sb0) : lgw;
             const int sbl = (sb0 >> lgl) << lgl;
             if (sact && have != sbl) {
                 have = sbl;
                 kcl = sbl + (1 << (lgl - 1));
                 const double inv_h = 1.0 / (double)(1 << (lgl - 1));
+                const GLOBAL double* __restrict__ gtl = (const GLOBAL double*)gtab + a.gtab_off[lgl] * kGStride;
                 block_setup<RM, NR>(coef, S, p, a.g.k0 + (double)kcl, lgl, gtl + (int64_t)(sbl >> lgl) * kGStride,
                                   a.g, a.m, poly, rp);
                 if constexpr (MIXED) {

@@ -25,7 +25,7 @@ constexpr double kEulerGamma = 0.57721566490153286060651209;
 constexpr int kTheta = 7;     // theta entries of a circular model
 constexpr int kThetaMax = 8;  // with the eccentricity e0
 
-// coefficient-buffer field indices (field-major SoA, stride = particle capacity)
+// coefficient-buffer field indices (one record of kCoefStride doubles per particle)
 enum Coef : int {
     C_C0H = 0, C_C0L,      // Newtonian coefficient of f^-5/3, double-double
     C_B1, C_B2, C_B3, C_B4, C_B5, C_B6, C_B7,  // coefficients of f^-1, f^-2/3, f^-1/3, ln f, f^1/3, f^1/3 ln f, f^2/3
@@ -37,7 +37,9 @@ enum Coef : int {
     C_RESP,                // 36 response trig-polynomial coefficients: R_A re, R_A im, R_E re, R_E im
                            // (full response: the source record FdSlot instead)
     C_TCL = C_RESP + 36,   // low part of t_c in double-double: t_c = C_TC + C_TCL
-    C_COUNT
+    C_LGUP,                // first bins from which blocks of 2 and 4 times the
+                           // support start's length meet the same bounds (2 slots)
+    C_COUNT = C_LGUP + 2
 };
 
 // Source record of the full response, at C_RESP: direction to the source,

@@ -6,7 +6,9 @@ two-channel layout the step benchmark uses (512-bin LDS blocks, 2048-bin
 chunks, 256 particle slots per tile) and over adversarial supports and
 edges: supports that start or end on chunk and block boundaries, one-bin
 supports, runs of empty segments, edges on chunk boundaries, idle lanes and
-the last particle of the buffer.  The bin loop takes two bins per pass and
+the last particle of the buffer, with each lane's block level picked as the
+tile picks it (the prologue's level, raised from the super-blocks where
+longer blocks meet the same bounds; the mixed path's doubled lengths too).  The bin loop takes two bins per pass and
 forms both bins' terms before either bin's events: the second bin of a pass
 that has one bin left reads the first bin's data again, and every table
 index (the bin's phase, in 1/1024 cycles, masked to 10 bits and or-ed with
@@ -30,13 +32,15 @@ def table_index(phase_units, tmask, toff):
 
 
 def emulate_tile(K, L, CB, N, NV, lanes_lg, lanes_klo, lanes_khi, bounds, P_total, slot0, chunk, n_chunks,
-                 lg_levels):
+                 lg_levels, lanes_up=None, lg_max=11, mixed=False):
     """Replay the offsets of one tile (chunk, group of len(lanes) slots);
     bounds is the whole [P_total][N+1] edge array plus two spare entries, the
     lanes are particles slot0 .. slot0 + len - 1.  Returns the number of
     lane-bins visited.  Raises AssertionError at the first offset out of its
     buffer."""
     W = len(lanes_lg)
+    if lanes_up is None:
+        lanes_up = np.full((W, 2), INT32_MAX, dtype=np.int64)
     cbins = L * CB
     Kc = chunk * cbins
     Ke = min(Kc + cbins, K)
@@ -46,12 +50,17 @@ def emulate_tile(K, L, CB, N, NV, lanes_lg, lanes_klo, lanes_khi, bounds, P_tota
     lds_doubles = L * NV
     p = slot0 + np.arange(W)
     live = p < P_total
-    lg = np.where(live, lanes_lg, -1)
-    lo = np.where(lg >= 0, lanes_klo, 0)
-    hi = np.where(lg >= 0, lanes_khi, 0)
+    lgb = np.where(live, lanes_lg, -1)
+    lo = np.where(lgb >= 0, lanes_klo, 0)
+    hi = np.where(lgb >= 0, lanes_khi, 0)
     lo = np.maximum(lo, Kc)
     hi = np.minimum(hi, Ke)
     has = lo < hi
+
+    def lev(i, k):
+        return level_at(lgb[i], lanes_up[i], k, lg_max, mixed)
+
+    lg = np.array([lev(i, lo[i]) for i in range(W)])
     if not has.any():
         return 0
     prow = np.where(live, p, slot0) * (N + 1)
@@ -105,7 +114,6 @@ def emulate_tile(K, L, CB, N, NV, lanes_lg, lanes_klo, lanes_khi, bounds, P_tota
             dst_zs[i] = zsp[i]
         nxt[i] = nb[i]
 
-    lgl = np.where(has, lg, lgw)
     have = np.full(W, -1, dtype=np.int64)
     tmask = np.zeros(W, dtype=np.int64)
     toff = np.full(W, K_TRIG, dtype=np.int64)
@@ -125,11 +133,16 @@ def emulate_tile(K, L, CB, N, NV, lanes_lg, lanes_klo, lanes_khi, bounds, P_tota
         for sb0 in range((wlo >> lgw) << lgw, whi, Lp):
             s_lo, s_hi = max(sb0, wlo), min(sb0 + Lp, whi)
             sact = act & (llo < sb0 + Lp) & (lhi > sb0)
+            lgl = np.array([lev(i, sb0) if has[i] else lgw for i in range(W)])
+            assert np.all(lgl[sact] >= lgw) and np.all(lgl <= lg_max), "a lane's level below the wave's step"
             sbl = (sb0 >> lgl) << lgl
             setup = sact & (have != sbl)
             for i in np.flatnonzero(setup):
                 sub = sbl[i] >> lgl[i]
                 assert 0 <= sub < lg_levels[lgl[i]], "basis-table entry out of its level"
+                # the block lies inside one super-block, at one level throughout
+                assert sbl[i] >> lg_max == (sbl[i] + (1 << lgl[i]) - 1) >> lg_max
+                assert lev(i, sbl[i]) == lgl[i] == lev(i, sbl[i] + (1 << lgl[i]) - 1)
                 have[i] = sbl[i]
                 tmask[i], toff[i] = K_TRIG - 1, 0
             for k in range(s_lo, s_hi, 2):
@@ -155,6 +168,32 @@ def emulate_tile(K, L, CB, N, NV, lanes_lg, lanes_klo, lanes_khi, bounds, P_tota
             off = rec_base[i] + (0 if dst_rec[i] else 3)
             assert off + 2 < n_rec
     return visited
+
+
+NO_BIN = 2.0 ** 40
+INT32_MAX = 2 ** 31 - 1
+
+
+def super_ups(lgb, kup, lg_max):
+    """The tile's thresholds for one lane (the kernel's rule): the first
+    super-block start (a multiple of 2^lg_max) at or after each bin from which
+    two and four times the prologue's block length meet the bounds, or
+    INT32_MAX."""
+    ups = [INT32_MAX, INT32_MAX]
+    if 3 <= lgb < lg_max:
+        sup = float(1 << lg_max)
+        u = [np.ceil(kup[0] / sup) * sup, np.ceil(kup[1] / sup) * sup]
+        ups[0] = int(u[0]) if u[0] < INT32_MAX else INT32_MAX
+        ups[1] = int(u[1]) if (lgb + 2 <= lg_max and u[1] < INT32_MAX) else INT32_MAX
+    return ups
+
+
+def level_at(lgb, ups, k, lg_max, mixed=False):
+    """The lane's block level at bin k (the kernel's rule)."""
+    lev = lgb + (k >= ups[0]) + (k >= ups[1])
+    if mixed and 0 <= lev < lg_max:
+        lev += 1
+    return int(lev)
 
 
 def _edges(rng, klo, khi, N, kind):
@@ -186,6 +225,14 @@ def test_tile_offsets_stay_in_their_buffers():
     klo[:8] = [0, 2048, 2047, 512, K - 1, K - 2048, 4096, 0]
     khi[:8] = [2048, 4096, 2049, 1024, K, K, 4097, K]
     lg[8], khi[9] = -1, klo[9]
+    # bins from which two and four times the prologue's length hold: inside
+    # the support, at its start, or never
+    u0 = klo + rng.integers(0, np.maximum(khi - klo, 1))
+    u1 = u0 + rng.integers(0, np.maximum(khi - u0, 1))
+    kup = np.stack([u0, u1], axis=1).astype(np.float64)
+    kup[rng.random(P_total) < 0.25] = NO_BIN
+    kup[rng.random(P_total) < 0.1, 1] = NO_BIN
+    kup[10:14, 0] = klo[10:14]
     kinds = ["equal", "runs", "boundary"]
     bounds = np.concatenate([np.concatenate([_edges(rng, klo[i], khi[i], N, kinds[i % 3]) if khi[i] > klo[i]
                                              else np.full(N + 1, klo[i]) for i in range(P_total)]),
@@ -196,13 +243,46 @@ def test_tile_offsets_stay_in_their_buffers():
     for g0 in range(0, P_total, W):
         sl = slice(g0, min(g0 + W, P_total))
         pad = W - (sl.stop - sl.start)
-        lgs = np.concatenate([lg[sl], np.full(pad, -1)])
         kl = np.concatenate([klo[sl], np.zeros(pad, dtype=np.int64)])
         kh = np.concatenate([khi[sl], np.zeros(pad, dtype=np.int64)])
+        lgs = np.concatenate([lg[sl], np.full(pad, -1)])
+        ups = np.array([super_ups(lg[i], kup[i], 11) for i in range(sl.start, sl.stop)] +
+                       [[INT32_MAX, INT32_MAX]] * pad, dtype=np.int64)
         for c in chunks:
-            total += emulate_tile(K, L, CB, N, NV, lgs, kl, kh, bounds, P_total, g0, c, n_chunks, lg_levels)
+            for mixed in (False, True):
+                total += emulate_tile(K, L, CB, N, NV, lgs, kl, kh, bounds, P_total, g0, c, n_chunks, lg_levels,
+                                      ups, 11, mixed)
     print(f"lane-bins replayed: {total}")
     assert total > 0
+
+
+def test_block_level_rule():
+    """Every block of a raised level starts at or after the bin from which
+    that level meets the bounds; the level never falls below the prologue's,
+    never rises above lg_max, never falls as the bin rises, and changes only
+    at super-block starts, so it does not depend on the chunk length."""
+    rng = np.random.default_rng(13170)
+    K, lg_max = 1 << 20, 11
+    for _ in range(2000):
+        lgb = int(rng.integers(3, lg_max + 1))
+        u0 = float(rng.integers(0, K))
+        u1 = u0 + float(rng.integers(0, K))
+        kup = [np.array([u0, u1]), np.array([u0, NO_BIN]), np.array([NO_BIN, NO_BIN])][int(rng.integers(0, 3))]
+        ups = super_ups(lgb, kup, lg_max)
+        ks = np.sort(rng.integers(0, K, size=64))
+        prev = -1
+        for k in ks:
+            k = int(k)
+            lev = level_at(lgb, ups, k, lg_max)
+            assert lgb <= lev <= lg_max and lev >= prev
+            prev = lev
+            first = (k >> lev) << lev  # the start of the block holding bin k
+            for i in range(lev - lgb):
+                assert first >= kup[i]
+            s0 = (k >> lg_max) << lg_max
+            assert level_at(lgb, ups, s0, lg_max) == lev == level_at(lgb, ups, s0 + (1 << lg_max) - 1, lg_max)
+            mix = level_at(lgb, ups, k, lg_max, mixed=True)
+            assert mix == min(lev + 1, lg_max)
 
 
 def test_table_index_range_for_any_phase():
