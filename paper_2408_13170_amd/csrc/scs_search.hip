@@ -26,9 +26,9 @@
 //              The swarm's best position starts at the best position of its
 //              particle with the highest earlier best value.
 //
-// The re-grouping runs on the device too (k_features, k_kmeans: one
-// workgroup runs the whole k-means, every sum in a fixed order); the host
-// reads back the cluster count, sizes and top members.  scs_kmeans, the same
+// The re-grouping runs on the device too (k_features, then the k_km_*
+// kernels: k-means over many workgroups, every sum in a fixed order); the
+// host reads back the cluster count, sizes and top members.  scs_kmeans, the same
 // k-means on host data, stays available to callers.
 #include <hip/hip_runtime.h>
 
@@ -699,7 +699,7 @@ extern "C" int scs_kmeans_device(const double* x, int64_t n, int32_t dim, int32_
 
 // Re-group all particles into k-means clusters of their positions, on the
 // device: the swarms' arrays are gathered into one set, k_features and
-// k_kmeans cluster them, and every kept cluster becomes a new swarm whose
+// the k_km_* kernels cluster them, and every kept cluster becomes a new swarm whose
 // rows are gathered from the set (positions, velocities and best positions
 // carry over; best values restart at -inf, the first step of the rung only
 // evaluates; the swarm's best position starts at the best position of its
