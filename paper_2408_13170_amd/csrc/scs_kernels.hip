@@ -257,7 +257,9 @@ __global__ void k_prologue(PrologueArgs a)
                     const int64_t mid = lo + (hi - lo) / 2;
                     if (block_ok((a.g.k0 + (double)mid) * a.g.df, l)) hi = mid; else lo = mid + 1;
                 }
-                if (lo >= khi) break;
+                // the bisection takes the bound as falling with f; where it
+                // does not also hold at the support's end, keep the length
+                if (lo >= khi || !block_ok((a.g.k0 + (double)(khi - 1)) * a.g.df, l)) break;
                 kup[i] = (double)lo;
             }
         }
@@ -1663,6 +1665,10 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
             const int cnt = nbins * NV;
             for (int i = tid; i < cnt; i += nthreads) dst[i] = src[i];
         }
+        if (tid < NV) {  // the spare bin after the staged ones
+            if constexpr (MIXED) reinterpret_cast<float*>(smem)[nbins * NV + tid] = 0.f;
+            else reinterpret_cast<double*>(smem)[nbins * NV + tid] = 0.0;
+        }
         __syncthreads();
         const int llo = lo > b0 ? lo : b0;
         const int lhi = hi < b1 ? hi : b1;
@@ -1769,7 +1775,8 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
             // Two bins per pass: the terms of both are formed before either
             // enters the sums (the lanes' events come between them), so the
             // two bins' arithmetic interleaves.  A pass with one bin left
-            // forms its second terms from the first bin's data and drops them.
+            // forms its second terms from the next staged bin (at the block's
+            // end the spare bin, zero) and drops them.
             if constexpr (!MIXED) {
                 double jd = (double)(s_lo - kcl);
                 const double* binp = reinterpret_cast<const double*>(smem) + (s_lo - b0) * NV;
@@ -1778,7 +1785,7 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
                     const bool two = k + 1 < s_hi;  // wave-uniform
                     BinTerms<double, NCH> t0, t1;
                     bin_terms_fp64<NCH>(jd, binp, s_trig, kk, poly, rp, tmask, toff, amp, t0);
-                    bin_terms_fp64<NCH>(jd + 1.0, two ? binp + NV : binp, s_trig, kk, poly, rp, tmask, toff, amp, t1);
+                    bin_terms_fp64<NCH>(jd + 1.0, binp + NV, s_trig, kk, poly, rp, tmask, toff, amp, t1);
                     pin_terms(t0);
                     pin_terms(t1);
                     if (nxt <= k) handle(k);
@@ -1807,7 +1814,7 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
                         const bool two = k + 1 < k1;  // wave-uniform
                         BinTerms<float, NCH> t0, t1;
                         bin_terms_mixed<NCH>(jf, binp, phf, a1h, rf, ampf, t0);
-                        bin_terms_mixed<NCH>(jf + 1.f, two ? binp + NV : binp, phf, a1h, rf, ampf, t1);
+                        bin_terms_mixed<NCH>(jf + 1.f, binp + NV, phf, a1h, rf, ampf, t1);
                         pin_terms(t0);
                         pin_terms(t1);
                         if (nxt <= k) handle(k);
@@ -2493,7 +2500,9 @@ void launch_bounds(const BoundArgs& a, hipStream_t s)
         hipLaunchKernelGGL(k_bounds_simple, dim3(nblk(a.P * (a.N + 1), 256)), dim3(256), 0, s, a);
     }
 }
-size_t main_lds_bytes(int nch, int L, bool mixed) { return (size_t)L * bin_stride(nch) * (mixed ? 4 : 8); }
+// L staged bins and one spare bin after them (read by a two-bin pass that
+// has one bin left, whose second terms are dropped)
+size_t main_lds_bytes(int nch, int L, bool mixed) { return (size_t)(L + 1) * bin_stride(nch) * (mixed ? 4 : 8); }
 // The generate-and-reduce instantiation of a kernel variant (variant_of) and
 // precision.
 typedef void (*MainKernel)(const MainArgs*, const int64_t*, int, unsigned long long*);

@@ -10,7 +10,8 @@ the last particle of the buffer, with each lane's block level picked as the
 tile picks it (the prologue's level, raised from the super-blocks where
 longer blocks meet the same bounds; the mixed path's doubled lengths too).  The bin loop takes two bins per pass and
 forms both bins' terms before either bin's events: the second bin of a pass
-that has one bin left reads the first bin's data again, and every table
+that has one bin left reads the next bin, at the block's end the spare bin
+the LDS holds after the staged ones, and every table
 index (the bin's phase, in 1/1024 cycles, masked to 10 bits and or-ed with
 the zero-entry offset) lies in [0, 1024], the 1025 entries the table holds
 (the zero entry included), whatever the phase; the same holds for the
@@ -47,7 +48,7 @@ def emulate_tile(K, L, CB, N, NV, lanes_lg, lanes_klo, lanes_khi, bounds, P_tota
     n_bounds = P_total * (N + 1) + 2
     n_zs = P_total * N * 3
     n_rec = n_chunks * P_total * K_REC
-    lds_doubles = L * NV
+    lds_doubles = (L + 1) * NV  # L staged bins and the spare one after them
     p = slot0 + np.arange(W)
     live = p < P_total
     lgb = np.where(live, lanes_lg, -1)
@@ -122,7 +123,8 @@ def emulate_tile(K, L, CB, N, NV, lanes_lg, lanes_klo, lanes_khi, bounds, P_tota
     for b0 in range(Kc, Ke, L):
         b1 = min(b0 + L, Ke)
         nbins = b1 - b0
-        assert b1 * NV <= K * NV and nbins * NV <= lds_doubles, "staging out of the bin table or the LDS block"
+        # the staged bins, then the zeroed spare bin after them
+        assert b1 * NV <= K * NV and (nbins + 1) * NV <= lds_doubles, "staging out of the bin table or the LDS block"
         llo = np.maximum(lo, b0)
         lhi = np.minimum(hi, b1)
         act = llo < lhi
@@ -149,9 +151,11 @@ def emulate_tile(K, L, CB, N, NV, lanes_lg, lanes_klo, lanes_khi, bounds, P_tota
                 two = k + 1 < s_hi
                 # both bins' data and table entries first: any phase (random,
                 # huge, negative) gives a table index in range
-                for kb in (k, k + 1 if two else k):
+                for kb in (k, k + 1):
                     off = (kb - b0) * NV
-                    assert 0 <= off and off + NV <= nbins * NV, "bin read out of the staged block"
+                    # a pass with one bin left reads the next bin, at most the
+                    # spare one after the staged block
+                    assert 0 <= off and off + NV <= (nbins + 1) * NV <= lds_doubles, "bin read out of the staged block"
                     ph = rng.uniform(-2.0 ** 40, 2.0 ** 40, size=(2, W))
                     for q in (table_index(ph[0], tmask, toff), table_index(ph[1], tmask, toff)):
                         assert np.all((q >= 0) & (q < TAB_ENTRIES)), "table index out of the table"
