@@ -1618,6 +1618,7 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
                 }
                 __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): nothing of the set-up pending in the bin loop
                 if constexpr (!MIXED) {
+                    // one bin at a time: two per pass measured no faster here
                     double jd = (double)(s_lo - xl);
                     const double* binp = reinterpret_cast<const double*>(smem) + (s_lo - b0) * NV;
 #pragma unroll 1
@@ -1628,16 +1629,36 @@ __device__ __forceinline__ void main_tile(const MainArgs& a, const double* __res
                         binp += NV;
                     }
                 } else {
+                    // two bins per pass, as in the block polynomials' loop below
+                    // (the same arithmetic per bin, sums and events in bin order)
                     const float ampf = (float)amp;
-                    double ud = (double)(s_lo - xl);
-                    const float* binp = reinterpret_cast<const float*>(smem) + (s_lo - b0) * NV;
+                    const float* const sb = reinterpret_cast<const float*>(smem);
 #pragma unroll 1
-                    for (int k = s_lo; k < s_hi; ++k) {
-                        if (nxt <= k) handle(k);
-                        bin_mixed<NCH, true>((float)ud, binp, phf, a1h, rf, ampf, qzr, qzi, qhh, cph, ud);
-                        ud += 1.0;
-                        binp += NV;
-                        if (((k + 1) & (kMixedRun - 1)) == 0) flush32();
+                    for (int k0 = s_lo; k0 < s_hi;) {
+                        const int kr = (k0 | (kMixedRun - 1)) + 1;
+                        const int k1 = kr < s_hi ? kr : s_hi;
+                        double ud = (double)(k0 - xl);
+                        const float* binp = sb + (k0 - b0) * NV;
+#pragma unroll 1
+                        for (int k = k0; k < k1; k += 2) {
+                            const bool two = k + 1 < k1;  // wave-uniform
+                            BinTerms<float, NCH> t0, t1;
+                            bin_terms_mixed<NCH, true>((float)ud, binp, phf, a1h, rf, ampf, t0, cph, ud);
+                            bin_terms_mixed<NCH, true>((float)(ud + 1.0), binp + NV, phf, a1h, rf, ampf, t1, cph,
+                                                       ud + 1.0);
+                            pin_terms(t0);
+                            pin_terms(t1);
+                            if (nxt <= k) handle(k);
+                            add_terms(t0, qzr, qzi, qhh);
+                            if (two) {
+                                if (nxt <= k + 1) handle(k + 1);
+                                add_terms(t1, qzr, qzi, qhh);
+                            }
+                            ud += 2.0;
+                            binp += 2 * NV;
+                        }
+                        if ((k1 & (kMixedRun - 1)) == 0) flush32();
+                        k0 = k1;
                     }
                 }
             }
