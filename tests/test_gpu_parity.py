@@ -7,6 +7,8 @@ are integers and must match exactly; an equal-[h|h] edge may differ only at a
 rounding tie of the oracle's cumulative, and such a row is then compared with
 the oracle on the GPU's edges (tests/parity.py).
 """
+import functools
+
 import numpy as np
 import pytest
 
@@ -208,6 +210,7 @@ def test_maximum_segment_count():
         c.close()
 
 
+@functools.lru_cache(maxsize=1)
 def _lisa1m_dataset():
     w = synth.workload("lisa1m")
     g = O.Grid(w.grid.K, w.grid.k0, w.grid.df, 2)
@@ -244,3 +247,35 @@ def test_upsilon_lisa1m_full_size_sampled():
         assert eall.max() < TOLMIX
     finally:
         c.close()
+
+
+def test_growing_block_lengths_lisa1m():
+    """Blocks that grow along the support (up to 2048 bins) against blocks
+    capped at 512 bins (about the length this prior box's support starts
+    allow, so they can hardly grow): both expand the template within the same
+    bounds, so over all 10^4 particles of the 2^20-bin workload the two agree
+    far inside the FP64 tolerance, and the mixed path within its own."""
+    w, ds = _lisa1m_dataset()
+    theta = synth.workload_particles(w)
+    N = w.N
+    c1 = Ctx(ds, N, B.SCS_SEG_EQUAL_SNR, w.G)
+    c2 = Ctx(ds, N, B.SCS_SEG_EQUAL_SNR, w.G, block_len=512)
+    try:
+        g1, _ = c1.eval(theta)
+        g2, _ = c2.eval(theta)
+        _, bnd = B.scs_last_bounds(c1.h, theta.shape[0], N)
+        _, bnd2 = B.scs_last_bounds(c2.h, theta.shape[0], N)
+        assert np.array_equal(bnd, bnd2)
+        assert np.all(np.isfinite(g1)) and np.all(np.isfinite(g2))
+        e = PT.floored(g1, g2, PT.n_eff(bnd))
+        print("fp64, growing vs 512-bin blocks: median", np.median(e), "max", e.max())
+        assert e.max() < 1e-11
+        m1, _ = c1.eval(theta, prec=B.SCS_PREC_MIXED)
+        m2, _ = c2.eval(theta, prec=B.SCS_PREC_MIXED)
+        em = PT.floored(m1, g2, PT.n_eff(bnd))
+        print("mixed with growing blocks vs fp64 with 512-bin blocks: max", em.max(),
+              "; mixed with 512-bin blocks:", PT.floored(m2, g2, PT.n_eff(bnd)).max())
+        assert em.max() < TOLMIX
+    finally:
+        c1.close()
+        c2.close()
