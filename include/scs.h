@@ -87,7 +87,11 @@ typedef struct scs_model {
     int32_t pn_order;        /* highest PN power of v in the phase, 0..7 (4 = 2PN, 7 = 3.5PN) */
     int32_t response;        /* SCS_RESP_* ; NONE needs 1 channel, LISA_LF_AE 2, LISA_FD_AE 2 or 3 */
     int32_t support;         /* SCS_SUPPORT_* */
-    int32_t block_len;       /* longest polynomial block in bins (power of 2, 16..2048); 0 = 2048 */
+    int32_t block_len;       /* longest polynomial block in bins (power of 2, 16..2048); 0 = 2048.
+                              * A particle's blocks start at the longest length whose remainder
+                              * bounds hold at its support start and double (twice at most, up
+                              * to block_len) from the first block_len-aligned run of bins
+                              * where the longer length meets the same bounds. */
     double t_obs;            /* observation time [s]; 0 = 1/df */
     double orbit_phase0;     /* orbital angle of the constellation centre at t = 0 [rad] */
     double cartwheel_phase0; /* in-plane angle of spacecraft 0 at t = 0 [rad] */
