@@ -231,6 +231,13 @@ struct scs_ctx {
     static constexpr int kRing = 4;
     BatchSlot ring[kRing];
     int ring_next = 0;
+    // side streams (default priority) on which a batch's per-item kernels
+    // before and after the fused launch run side by side, forked from and
+    // joined back to the caller's stream by events (null: one stream)
+    static constexpr int kSide = 3;
+    hipStream_t side[kSide] = {};
+    hipEvent_t fork_ev = nullptr;
+    hipEvent_t join_ev[kSide] = {};
 };
 
 static int build_gtab(scs_ctx* c);
@@ -320,6 +327,21 @@ extern "C" int scs_ctx_create(scs_ctx** out, int device)
         return fail(SCS_ENOMEM, "counter allocation failed");
     }
     launch_fill_u64(c->counters, 3, 0ULL, nullptr);
+    bool side_ok = hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; i < scs_ctx::kSide && side_ok; ++i)
+        side_ok = hipStreamCreateWithFlags(&c->side[i], hipStreamNonBlocking) == hipSuccess &&
+                  hipEventCreateWithFlags(&c->join_ev[i], hipEventDisableTiming) == hipSuccess;
+    if (!side_ok) {  // the batched form then stays on the caller's stream
+        for (int i = 0; i < scs_ctx::kSide; ++i) {
+            if (c->side[i]) hipStreamDestroy(c->side[i]);
+            if (c->join_ev[i]) hipEventDestroy(c->join_ev[i]);
+            c->side[i] = nullptr;
+            c->join_ev[i] = nullptr;
+        }
+        if (c->fork_ev) hipEventDestroy(c->fork_ev);
+        c->fork_ev = nullptr;
+        (void)hipGetLastError();
+    }
     if (hipDeviceSynchronize() != hipSuccess) {
         hipFree(c->counters);
         delete c;
@@ -340,6 +362,11 @@ extern "C" int scs_ctx_destroy(scs_ctx* c)
         hipEventDestroy(e.first);
         hipEventDestroy(e.second);
     }
+    for (int i = 0; i < scs_ctx::kSide; ++i) {
+        if (c->side[i]) hipStreamDestroy(c->side[i]);
+        if (c->join_ev[i]) hipEventDestroy(c->join_ev[i]);
+    }
+    if (c->fork_ev) hipEventDestroy(c->fork_ev);
     hipFree(c->b64);
     hipFree(c->b32);
     hipFree(c->d_dev);
@@ -1520,8 +1547,33 @@ static int run_batched(const scs_batch_item* items, int n_items, int prec, hipSt
 {
     const bool mixed = prec == SCS_PREC_MIXED;
     constexpr int kWaves = 4;  // workgroup shape of the fused launch
+    // The items' prologues, sorts and edges (and afterwards their
+    // finalizes) are independent: item i runs on the caller's stream or on
+    // side stream (i - 1) mod kSide of the first item's context, forked from
+    // the caller's stream and joined back before the fused launch (and
+    // before the call returns), so that small items do not wait for large
+    // ones.  Graph capture records the fork and join as dependencies.
+    scs_ctx* c0 = items[0].ctx;
+    const int n_side = (n_items > 1 && c0->fork_ev) ? std::min(n_items - 1, scs_ctx::kSide) : 0;
+    auto stream_of = [&](int i) { return i == 0 || n_side == 0 ? s : c0->side[(i - 1) % n_side]; };
+    auto fork = [&]() -> hipError_t {
+        hipError_t e = n_side ? hipEventRecord(c0->fork_ev, s) : hipSuccess;
+        for (int k = 0; k < n_side && e == hipSuccess; ++k) e = hipStreamWaitEvent(c0->side[k], c0->fork_ev, 0);
+        return e;
+    };
+    auto join = [&]() -> hipError_t {
+        hipError_t e = hipSuccess;
+        for (int k = 0; k < n_side && e == hipSuccess; ++k) {
+            e = hipEventRecord(c0->join_ev[k], c0->side[k]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s, c0->join_ev[k], 0);
+        }
+        return e;
+    };
     std::vector<EvalJob> jobs(n_items);
-    for (int i = 0; i < n_items; ++i) {
+    hipError_t e = fork();
+    if (e != hipSuccess) return fail(SCS_EDEVICE, "stream fork failed: %s", hipGetErrorString(e));
+    int rc = SCS_OK;
+    for (int i = 0; i < n_items && rc == SCS_OK; ++i) {
         const scs_batch_item& it = items[i];
         EvalJob& j = jobs[i];
         j.c = it.ctx;
@@ -1530,14 +1582,20 @@ static int run_batched(const scs_batch_item* items, int n_items, int prec, hipSt
         j.N = it.N;
         TuneChoice t = force ? force[i] : choose(it.ctx, it.P, it.N, prec);
         t.waves = kWaves;
-        int rc = eval_front(j, it.theta, it.ups, it.seg, t, s, nullptr, false, frozen ? frozen[i] : nullptr);
-        if (rc) return rc;
+        rc = eval_front(j, it.theta, it.ups, it.seg, t, stream_of(i), nullptr, false, frozen ? frozen[i] : nullptr);
     }
-    int rc = fused_main(jobs, kWaves, mixed, s, b, upload);
+    // joined even after a failed item, so that no side stream is left
+    // waiting apart from the caller's (a capture needs every branch joined)
+    e = join();
     if (rc) return rc;
+    if (e != hipSuccess) return fail(SCS_EDEVICE, "stream join failed: %s", hipGetErrorString(e));
+    rc = fused_main(jobs, kWaves, mixed, s, b, upload);
+    if (rc) return rc;
+    if ((e = fork()) != hipSuccess) return fail(SCS_EDEVICE, "stream fork failed: %s", hipGetErrorString(e));
     for (int i = 0; i < n_items; ++i)
-        if (jobs[i].P > 0) launch_finalize(jobs[i].fa, s);
-    hipError_t e = hipGetLastError();
+        if (jobs[i].P > 0) launch_finalize(jobs[i].fa, stream_of(i));
+    if ((e = join()) != hipSuccess) return fail(SCS_EDEVICE, "stream join failed: %s", hipGetErrorString(e));
+    e = hipGetLastError();
     if (e != hipSuccess) return fail(SCS_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     for (int i = 0; i < n_items; ++i) items[i].ctx->last_stream = s;
     return SCS_OK;
